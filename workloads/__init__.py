@@ -1,0 +1,205 @@
+"""Seeded synthetic inputs for finite-element assembly: meshes, coefficient fields, sources.
+
+This module holds no finite-element arithmetic. It lays out the node and element
+numbering of structured Q1 meshes, draws seeded random numbers and samples smooth
+random fields. The HIP path's tests, the oracle's tests and the benchmark all take
+their inputs from here, so both sides of every parity check see identical arrays.
+
+Conventions (the paper leaves local node order and numbering open, Sec. 2.2 B-1):
+  * node id      = i + (nx+1) * (j + (ny+1) * k)
+  * element id   = ex + nx * (ey + ny * ez)
+  * local node a = ax + 2*ay + 4*az  maps to node (ex+ax, ey+ay, ez+az)
+  * arrays are structure-of-arrays: coords [dim][n_nodes] float64,
+    conn [nen][n_elems] int32, nodal fields [n_fields][n_nodes].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "Mesh", "structured_mesh", "permute_mesh", "lognormal_elem", "uniform_nodal",
+    "fourier_velocity", "grf_lognormal_elem", "boundary_node_mask", "dof_mask",
+    "batch_problem_sizes",
+]
+
+
+class Mesh:
+    """A Q1 mesh in structure-of-arrays form."""
+
+    def __init__(self, coords: np.ndarray, conn: np.ndarray, shape=None):
+        self.coords = np.ascontiguousarray(coords, dtype=np.float64)
+        self.conn = np.ascontiguousarray(conn, dtype=np.int32)
+        self.shape = tuple(shape) if shape is not None else None
+
+    @property
+    def dim(self) -> int:
+        return self.coords.shape[0]
+
+    @property
+    def n_nodes(self) -> int:
+        return self.coords.shape[1]
+
+    @property
+    def n_elems(self) -> int:
+        return self.conn.shape[1]
+
+    @property
+    def nen(self) -> int:
+        return self.conn.shape[0]
+
+
+def structured_mesh(n, jitter: float = 0.0, seed=None, lengths=None) -> Mesh:
+    """Structured Q1 mesh of the box [0,L_0]x...x[0,L_{dim-1}] with n[d] elements per axis.
+
+    jitter > 0 moves every interior node by an independent U[-jitter*h_d, +jitter*h_d]
+    in each coordinate d (boundary nodes stay put, so the domain keeps its volume).
+    """
+    n = tuple(int(v) for v in n)
+    dim = len(n)
+    if dim not in (2, 3):
+        raise ValueError("dim must be 2 or 3")
+    L = np.ones(dim) if lengths is None else np.asarray(lengths, dtype=np.float64)
+    npts = [v + 1 for v in n]
+    axes = [np.linspace(0.0, L[d], npts[d]) for d in range(dim)]
+    # node id = i + (nx+1)(j + (ny+1)k)  ->  meshgrid with 'ij' and Fortran-order ravel
+    grids = np.meshgrid(*axes, indexing="ij")
+    coords = np.stack([g.ravel(order="F") for g in grids]).astype(np.float64)
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        idx = np.stack(np.meshgrid(*[np.arange(p) for p in npts], indexing="ij"))
+        idx = idx.reshape(dim, -1, order="F")
+        interior = np.all((idx > 0) & (idx < np.asarray(n)[:, None]), axis=0)
+        h = L / np.asarray(n)
+        delta = rng.uniform(-1.0, 1.0, size=coords.shape) * (jitter * h)[:, None]
+        coords = coords + delta * interior[None, :]
+    # element connectivity
+    eidx = np.stack(np.meshgrid(*[np.arange(v) for v in n], indexing="ij"))
+    eidx = eidx.reshape(dim, -1, order="F")  # element id = ex + nx(ey + ny ez)
+    nen = 1 << dim
+    conn = np.empty((nen, eidx.shape[1]), dtype=np.int64)
+    for a in range(nen):
+        bits = [(a >> d) & 1 for d in range(dim)]
+        node = np.zeros(eidx.shape[1], dtype=np.int64)
+        stride = 1
+        for d in range(dim):
+            node += (eidx[d] + bits[d]) * stride
+            stride *= npts[d]
+        conn[a] = node
+    return Mesh(coords, conn.astype(np.int32), shape=n)
+
+
+def permute_mesh(mesh: Mesh, seed) -> tuple[Mesh, np.ndarray, np.ndarray]:
+    """Relabel nodes and elements at random (topology and geometry unchanged).
+
+    Returns (new_mesh, node_perm, elem_perm) with new node id = node_perm[old id] and
+    new element e' holding old element elem_perm[e'].  The local node order inside each
+    element is kept, so every element keeps its orientation.
+    """
+    rng = np.random.default_rng(seed)
+    node_perm = rng.permutation(mesh.n_nodes)
+    elem_perm = rng.permutation(mesh.n_elems)
+    coords = np.empty_like(mesh.coords)
+    coords[:, node_perm] = mesh.coords
+    conn = node_perm[mesh.conn[:, elem_perm]].astype(np.int32)
+    return Mesh(coords, conn, shape=None), node_perm, elem_perm
+
+
+def lognormal_elem(n_elems: int, sigma: float, seed) -> np.ndarray:
+    """Per-element coefficient exp(N(0, sigma^2))."""
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.normal(0.0, sigma, size=n_elems)).astype(np.float64)
+
+
+def uniform_nodal(n_fields: int, n_nodes: int, lo: float, hi: float, seed) -> np.ndarray:
+    """Nodal field [n_fields][n_nodes] with entries U[lo, hi]."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=(n_fields, n_nodes)).astype(np.float64)
+
+
+def fourier_velocity(coords: np.ndarray, seed, modes: int = 8, kmax: int = 3) -> np.ndarray:
+    """Smooth random vector field sampled at the nodes: sum of `modes` Fourier modes.
+
+    a(x) = sum_m A_m sin(2 pi k_m . x + phi_m), k_m integer in {-kmax..kmax}^dim minus 0,
+    A_m ~ U[-1,1]^dim, phi_m ~ U[0, 2 pi); then scaled so max over nodes of |a|_2 is 1.
+    """
+    rng = np.random.default_rng(seed)
+    dim = coords.shape[0]
+    out = np.zeros_like(coords)
+    for _ in range(modes):
+        while True:
+            k = rng.integers(-kmax, kmax + 1, size=dim)
+            if np.any(k != 0):
+                break
+        A = rng.uniform(-1.0, 1.0, size=dim)
+        phi = rng.uniform(0.0, 2.0 * np.pi)
+        s = np.sin(2.0 * np.pi * (k @ coords) + phi)
+        out += A[:, None] * s[None, :]
+    scale = np.max(np.sqrt(np.sum(out * out, axis=0)))
+    return out / scale
+
+
+def grf_lognormal_elem(n, sigma: float, ell: float, seed) -> np.ndarray:
+    """Lognormal per-element field exp(sigma * g) on a structured unit-box mesh.
+
+    g is a zero-mean, unit-variance Gaussian random field with covariance
+    exp(-r^2 / (2 ell^2)), sampled at element centroids by circulant embedding on a
+    grid padded to twice the mesh in every axis.  Element order follows the structured
+    element numbering (x fastest).
+    """
+    n = tuple(int(v) for v in n)
+    dim = len(n)
+    rng = np.random.default_rng(seed)
+    h = 1.0 / np.asarray(n, dtype=np.float64)
+    m = [2 * v for v in n]
+    # periodic distances on the padded grid
+    dist2 = np.zeros(m)
+    for d in range(dim):
+        r = np.arange(m[d])
+        r = np.minimum(r, m[d] - r) * h[d]
+        shape = [1] * dim
+        shape[d] = m[d]
+        dist2 = dist2 + (r ** 2).reshape(shape)
+    cov = np.exp(-dist2 / (2.0 * ell * ell))
+    lam = np.real(np.fft.fftn(cov))
+    lam = np.maximum(lam, 0.0)
+    noise = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    field = np.fft.ifftn(np.sqrt(lam) * noise) * np.sqrt(np.prod(m))
+    g = np.real(field)[tuple(slice(0, v) for v in n)]
+    # element id = ex + nx(ey + ny ez): index [ex, ey, ez] raveled in Fortran order
+    return np.exp(sigma * g.ravel(order="F")).astype(np.float64)
+
+
+def boundary_node_mask(n) -> np.ndarray:
+    """uint8 [n_nodes]: 1 for nodes on the boundary of a structured mesh."""
+    n = tuple(int(v) for v in n)
+    npts = [v + 1 for v in n]
+    idx = np.stack(np.meshgrid(*[np.arange(p) for p in npts], indexing="ij"))
+    idx = idx.reshape(len(n), -1, order="F")
+    on = np.any((idx == 0) | (idx == np.asarray(n)[:, None]), axis=0)
+    return on.astype(np.uint8)
+
+
+def dof_mask(node_mask: np.ndarray, n_fields: int, field_major: bool,
+             fields=None) -> np.ndarray:
+    """Expand a node mask to a DOF mask for the given numbering.
+
+    node-major dof(a, i) = n_fields * a + i;  field-major dof(a, i) = i * n_nodes + a.
+    `fields` restricts the constraint to a subset of field indices (default: all).
+    """
+    nn = node_mask.shape[0]
+    fields = range(n_fields) if fields is None else fields
+    m = np.zeros((n_fields, nn), dtype=np.uint8)
+    for i in fields:
+        m[i] = node_mask
+    if field_major:
+        return m.reshape(-1).copy()
+    return m.T.reshape(-1).copy()
+
+
+def batch_problem_sizes(n_problems: int, lo: int, hi: int, base_seed: int = 6):
+    """Per-problem element counts per axis, each drawn U{lo..hi} with seed base_seed + p."""
+    sizes = []
+    for p in range(n_problems):
+        rng = np.random.default_rng(base_seed + p)
+        sizes.append(tuple(int(v) for v in rng.integers(lo, hi + 1, size=3)))
+    return sizes
