@@ -1,0 +1,169 @@
+/*
+ * mf.h - C ABI of the MI355X finite-element assembly library (libmf.so).
+ *
+ * The library assembles the sparse linear system K x = d of a weak form on a Q1 mesh
+ * (MetaFEM, arXiv 2111.03541).  Sec. 1 of the paper states that K x = d is fixed by
+ * six inputs: the weak forms, their linearisation, the element type and order, the
+ * quadrature, the time scheme and the numbering of the unknowns.  These become the
+ * arguments below.  The time scheme is steady here, so the time coefficient of the
+ * stiffness assembly (Sec. 2.2 D-3) is 1.
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers unless marked (host).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Calls are asynchronous on `stream` unless marked (sync).
+ *   - Every call returns an mf_status.  A message for the last failure on the
+ *     calling thread is available from mf_last_error().
+ *   - Nothing throws across the ABI.  A handle must not be used from two host
+ *     threads at once.
+ *   - The caller owns every array it passes: conn, coords, fields, K values, d and
+ *     vectors.  The library owns the arrays of a pattern handle.  Views returned by
+ *     mf_pattern_info stay valid until mf_pattern_destroy.
+ *   - Structure-of-arrays layouts:
+ *       conn    [nen][n_elems] int32, with the local node order of the reference
+ *               element, a = ax + 2 ay + 4 az
+ *       coords  [dim][n_nodes] FP64
+ *       fields  [n_fields][n_nodes]
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MF_OK = 0,
+    MF_ERR_ARG = 1,           /* invalid argument (message says which)                  */
+    MF_ERR_UNSUPPORTED = 2,   /* valid but not implemented (element, order, quadrature) */
+    MF_ERR_OVERFLOW = 3,      /* an index exceeds its type: nnz >= 2^31, valence > 255  */
+    MF_ERR_HIP = 4,           /* a HIP runtime call failed                              */
+    MF_ERR_BAD_JACOBIAN = 5,  /* det J <= 0 at an integration point (mf_status_poll)    */
+    MF_ERR_NONFINITE = 6,     /* non-finite value produced                              */
+    MF_ERR_NOT_CONVERGED = 7, /* iterative solver hit its iteration limit               */
+    MF_ERR_OOM = 8,           /* device allocation failed                               */
+    MF_ERR_BAD_MESH = 9       /* connectivity references a node outside [0, n_nodes)    */
+} mf_status;
+
+typedef enum { MF_QUAD4 = 1, MF_HEX8 = 2 } mf_elem_type;           /* Lagrange order 1 */
+/* DOF numbering.  Field-major is the paper's map (Sec. 2.2 B-3): dof = field*n_nodes + node.
+   Node-major interleaves the fields of a node: dof = n_fields*node + field. */
+typedef enum { MF_NODE_MAJOR = 0, MF_FIELD_MAJOR = 1 } mf_numbering;
+typedef enum {
+    MF_FORM_MASS = 0,       /* K_ab = int c N_a N_b,                    d = M f           */
+    MF_FORM_POISSON = 1,    /* thermal conduction, Sec. 4.1 (steady): K_ab = int k dN_a.dN_b,
+                               d = M f                                                    */
+    MF_FORM_ELASTICITY = 2, /* linear elasticity, Sec. 4.2: K = int eps(N_a):sigma(N_b),
+                               d = int N_a b (nodal body force b, interpolated)           */
+    MF_FORM_NS_SUPG = 3     /* steady incompressible Navier-Stokes with SUPG/PSPG/LSIC,
+                               Sec. 4.3: Newton tangent K = dR/dU and d = -R at the state U0 */
+} mf_form_kind;
+typedef enum { MF_F64 = 0, MF_F32 = 1 } mf_precision;
+
+typedef struct {
+    int32_t dim;           /* 2 (MF_QUAD4) or 3 (MF_HEX8) */
+    int64_t n_nodes;
+    int64_t n_elems;
+    const int32_t* conn;   /* [nen][n_elems] (device) */
+} mf_mesh;
+
+typedef struct {
+    int32_t n_fields;          /* 1..4 */
+    const uint8_t* coupling;   /* (host) [n_fields*n_fields], 1 = block (i,j) present; NULL = all */
+    mf_numbering numbering;
+} mf_dofs;
+
+typedef struct mf_pattern_s mf_pattern_t;   /* opaque, library-owned */
+
+/*
+ * mf_pattern - sparsity pattern of K (Sec. 2.2 Block B: B-1 element-to-node map and node
+ * pairs, B-3 DOF map, B-4 sparse layout, here CSR instead of COO).
+ *   N(v) = sorted set of nodes sharing an element with node v (v included).
+ *   Row dof(v,i) holds columns dof(w,j) for w in N(v) and coupling(i,j), ascending.
+ *   rank[(a*nen+b)*n_elems + e] = position of conn[b][e] in N(conn[a][e]).
+ * order must be 1.  Runs on `stream` and synchronises it (sync); allocates the
+ * pattern's device arrays.  Errors: MF_ERR_ARG, MF_ERR_BAD_MESH (node id out of
+ * range), MF_ERR_OVERFLOW (nnz or nen*n_elems >= 2^31, or more than 255 neighbours of
+ * one node), MF_ERR_OOM, MF_ERR_HIP.  *out is NULL on error.
+ */
+mf_status mf_pattern(const mf_mesh* mesh, mf_elem_type type, int32_t order, const mf_dofs* dofs,
+                     void* stream, mf_pattern_t** out);
+
+/* (sync) sizes and device views: row_ptr int32 [n_rows+1], col_idx int32 [nnz],
+   rank uint8 [nen*nen][n_elems].  Any output pointer may be NULL. */
+mf_status mf_pattern_info(const mf_pattern_t* pat, int64_t* n_rows, int64_t* nnz,
+                          const int32_t** row_ptr, const int32_t** col_idx, const uint8_t** rank);
+
+/* (sync) 1 when the connectivity is a structured lexicographic grid (node id
+   i + (nx+1)(j + (ny+1)k), element id ex + nx(ey + ny ez)), with its element counts. */
+mf_status mf_pattern_grid(const mf_pattern_t* pat, int32_t* is_grid, int64_t* nx, int64_t* ny,
+                          int64_t* nz);
+
+void mf_pattern_destroy(mf_pattern_t* pat);
+
+/* Scalar parameters of a form.
+   coef: MASS density c, POISSON conductivity k, ELASTICITY Young's modulus E; each is
+         multiplied by elem_param[e] when that array is given.
+   nu:   ELASTICITY Poisson's ratio (Lame parameters as in Sec. 4.2).
+   rho, mu, tau_m, tau_c: NS_SUPG density, dynamic viscosity, stabilisation constants. */
+typedef struct {
+    mf_form_kind kind;
+    double coef, nu, rho, mu, tau_m, tau_c;
+} mf_form;
+
+/* Per-mesh inputs; precision-typed arrays are double (MF_F64) or float (MF_F32). */
+typedef struct {
+    const void* elem_param;   /* [n_elems] or NULL (= 1) */
+    const void* nodal_src;    /* MASS/POISSON: f [1][n_nodes]; ELASTICITY: b [dim][n_nodes];
+                                 NULL = 0 */
+    const void* lin_state;    /* NS_SUPG: U0 [dim+1][n_nodes] = (u_1..u_dim, p); NULL = 0 */
+    const uint8_t* dirichlet; /* [n_rows] constrained-DOF mask or NULL; a constrained row
+                                 becomes a unit row with d = 0, its column is zeroed
+                                 elsewhere (homogeneous elimination, structure kept) */
+} mf_fields;
+
+typedef struct { int32_t points_per_axis; } mf_quadrature;   /* Gauss-Legendre; 2 supported */
+
+/* Assembly strategies.  AUTO picks the owner-computes gather for structured grids and
+   element-parallel atomics otherwise. */
+typedef enum { MF_SCATTER_AUTO = 0, MF_SCATTER_ATOMIC = 1, MF_SCATTER_GATHER = 2 } mf_scatter;
+
+/*
+ * mf_assemble - fill K (CSR values on the pattern) and d (Sec. 2.2 D-2 residual and
+ * D-3 stiffness assembly, Sec. 2.1 numerical integration).
+ *   K = dR/dU and d = -R(U0), where R is the weak form with the sign that makes the
+ *   diffusion term positive (thermal and elastic forms times -1, the flow form as
+ *   written).  Each integration point uses the geometry Jacobian J = sum_a x_a (x)
+ *   dN_a/dxi, with det J > 0 required, g_a = J^-T dN_a/dxi and weight w_q det J.
+ * precision MF_F64: everything in FP64.  MF_F32: geometry (J, det J, J^-1, g, weights)
+ *   in FP64, rounded to FP32; coefficients, contractions and accumulation in FP32;
+ *   K, d, elem_param, nodal_src and lin_state are float.  coords are FP64 always.
+ * K_values [nnz] and d [n_rows] are overwritten entirely (no prior clear needed).
+ * Async on `stream`.  A device-side det J <= 0 is reported by mf_status_poll.
+ * The pattern's n_fields must match the form (1, 1, dim, dim+1).
+ */
+mf_status mf_assemble(const mf_pattern_t* pat, const mf_form* form, const double* coords,
+                      const mf_fields* fields, const mf_quadrature* quad, mf_precision precision,
+                      void* K_values, void* d, void* stream);
+
+/* Same as mf_assemble with an explicit strategy (for tests and tuning). */
+mf_status mf_assemble_ex(const mf_pattern_t* pat, const mf_form* form, const double* coords,
+                         const mf_fields* fields, const mf_quadrature* quad, mf_precision precision,
+                         mf_scatter scatter, void* K_values, void* d, void* stream);
+
+/* (sync) Reads the device status word of the last assembly on this pattern: MF_OK, or
+   MF_ERR_BAD_JACOBIAN with the smallest offending element id in *first_bad_elem. */
+mf_status mf_status_poll(const mf_pattern_t* pat, int64_t* first_bad_elem);
+
+/* Thread-local message for the last failing call ("" if none). */
+const char* mf_last_error(void);
+
+/* Library version string. */
+const char* mf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MF_H */

@@ -1,0 +1,236 @@
+"""Python binding of libmf.so, the MI355X finite-element assembly library (include/mf.h).
+
+Argument marshalling only: torch tensors supply device memory and the HIP stream, and
+every step of the path runs in the library's kernels.  There is no fallback: if the
+library is missing or fails to load, every call raises.
+
+    import paper_2111_03541_amd as mf
+    pat = mf.Pattern(conn, n_nodes, dim=3, n_fields=3)          # conn: int32 cuda [nen][n_el]
+    K, d = pat.assemble(mf.Form(mf.ELASTICITY, coef=1.0, nu=0.3), coords, precision=mf.F64,
+                        elem_param=E, nodal_src=b)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmf.so")
+
+# enums of mf.h
+OK, ERR_ARG, ERR_UNSUPPORTED, ERR_OVERFLOW, ERR_HIP, ERR_BAD_JACOBIAN, ERR_NONFINITE, \
+    ERR_NOT_CONVERGED, ERR_OOM, ERR_BAD_MESH = range(10)
+QUAD4, HEX8 = 1, 2
+NODE_MAJOR, FIELD_MAJOR = 0, 1
+MASS, POISSON, ELASTICITY, NS_SUPG = 0, 1, 2, 3
+F64, F32 = 0, 1
+SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_GATHER = 0, 1, 2
+
+_STATUS_NAMES = {
+    0: "MF_OK", 1: "MF_ERR_ARG", 2: "MF_ERR_UNSUPPORTED", 3: "MF_ERR_OVERFLOW", 4: "MF_ERR_HIP",
+    5: "MF_ERR_BAD_JACOBIAN", 6: "MF_ERR_NONFINITE", 7: "MF_ERR_NOT_CONVERGED", 8: "MF_ERR_OOM",
+    9: "MF_ERR_BAD_MESH",
+}
+
+
+class MFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_nodes", C.c_int64), ("n_elems", C.c_int64),
+                ("conn", C.c_void_p)]
+
+
+class _Dofs(C.Structure):
+    _fields_ = [("n_fields", C.c_int32), ("coupling", C.c_void_p), ("numbering", C.c_int)]
+
+
+class _Form(C.Structure):
+    _fields_ = [("kind", C.c_int), ("coef", C.c_double), ("nu", C.c_double), ("rho", C.c_double),
+                ("mu", C.c_double), ("tau_m", C.c_double), ("tau_c", C.c_double)]
+
+
+class _Fields(C.Structure):
+    _fields_ = [("elem_param", C.c_void_p), ("nodal_src", C.c_void_p), ("lin_state", C.c_void_p),
+                ("dirichlet", C.c_void_p)]
+
+
+class _Quad(C.Structure):
+    _fields_ = [("points_per_axis", C.c_int32)]
+
+
+_lib = None
+
+# every symbol declared in include/mf.h (checked by the ABI test)
+EXPORTS = [
+    "mf_pattern", "mf_pattern_info", "mf_pattern_grid", "mf_pattern_destroy", "mf_assemble",
+    "mf_assemble_ex", "mf_status_poll", "mf_last_error", "mf_version",
+]
+
+
+def load():
+    """Load libmf.so (built in-tree by paper_2111_03541_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2111_03541_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+    lib.mf_pattern.argtypes = [C.POINTER(_Mesh), C.c_int, i32, C.POINTER(_Dofs), P, C.POINTER(P)]
+    lib.mf_pattern_info.argtypes = [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(P), C.POINTER(P), C.POINTER(P)]
+    lib.mf_pattern_grid.argtypes = [P, C.POINTER(i32), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    lib.mf_pattern_destroy.argtypes = [P]
+    lib.mf_pattern_destroy.restype = None
+    lib.mf_assemble.argtypes = [P, C.POINTER(_Form), P, C.POINTER(_Fields), C.POINTER(_Quad), C.c_int, P, P, P]
+    lib.mf_assemble_ex.argtypes = [P, C.POINTER(_Form), P, C.POINTER(_Fields), C.POINTER(_Quad), C.c_int,
+                                   C.c_int, P, P, P]
+    lib.mf_status_poll.argtypes = [P, C.POINTER(i64)]
+    lib.mf_last_error.restype = C.c_char_p
+    lib.mf_version.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != OK:
+        raise MFError(status, load().mf_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def form_fields(kind: int, dim: int) -> int:
+    return {MASS: 1, POISSON: 1, ELASTICITY: dim, NS_SUPG: dim + 1}[kind]
+
+
+class Form:
+    def __init__(self, kind: int, coef=1.0, nu=0.0, rho=0.0, mu=0.0, tau_m=0.0, tau_c=0.0):
+        self.kind = kind
+        self.c = _Form(kind, coef, nu, rho, mu, tau_m, tau_c)
+
+
+class Pattern:
+    """mf_pattern handle.  conn: int32 CUDA tensor [nen][n_elems] (contiguous)."""
+
+    def __init__(self, conn, n_nodes: int, dim: int, n_fields: int, coupling=None,
+                 numbering: int = NODE_MAJOR, stream=None):
+        import torch
+        lib = load()
+        assert conn.is_cuda and conn.dtype == torch.int32 and conn.is_contiguous()
+        self.dim, self.n_fields, self.numbering = dim, n_fields, numbering
+        self.n_nodes, self.n_elems = int(n_nodes), int(conn.shape[1])
+        self._conn = conn
+        mesh = _Mesh(dim, self.n_nodes, self.n_elems, conn.data_ptr())
+        cpl = None
+        if coupling is not None:
+            cpl = (C.c_uint8 * (n_fields * n_fields))(*[int(bool(v)) for v in
+                                                        __import__("numpy").asarray(coupling).reshape(-1)])
+        dofs = _Dofs(n_fields, C.cast(cpl, C.c_void_p) if cpl is not None else None, numbering)
+        h = C.c_void_p()
+        check(lib.mf_pattern(C.byref(mesh), HEX8 if dim == 3 else QUAD4, 1, C.byref(dofs), _stream(stream),
+                             C.byref(h)))
+        self._h = h
+        n_rows, nnz = C.c_int64(), C.c_int64()
+        check(lib.mf_pattern_info(h, C.byref(n_rows), C.byref(nnz), None, None, None))
+        self.n_rows, self.nnz = n_rows.value, nnz.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.mf_pattern_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def grid(self):
+        g = C.c_int32()
+        nx, ny, nz = C.c_int64(), C.c_int64(), C.c_int64()
+        check(load().mf_pattern_grid(self._h, C.byref(g), C.byref(nx), C.byref(ny), C.byref(nz)))
+        return bool(g.value), (nx.value, ny.value, nz.value)
+
+    def arrays(self):
+        """(row_ptr, col_idx, rank) copied to host numpy arrays (sync)."""
+        import numpy as np
+        import torch
+        lib = load()
+        rp, ci, rk = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        check(lib.mf_pattern_info(self._h, None, None, C.byref(rp), C.byref(ci), C.byref(rk)))
+        torch.cuda.synchronize()
+        nen = 1 << self.dim
+        out = []
+        for ptr, n, dt in ((rp, self.n_rows + 1, np.int32), (ci, self.nnz, np.int32),
+                           (rk, nen * nen * self.n_elems, np.uint8)):
+            host = np.zeros(max(n, 1), dtype=dt)
+            if n > 0:
+                _memcpy_d2h(host.ctypes.data, ptr.value, n * host.itemsize)
+            out.append(host[:n])
+        out[2] = out[2].reshape(nen * nen, self.n_elems)
+        return tuple(out)
+
+    def device_arrays(self):
+        """Raw device pointers (row_ptr, col_idx, rank), valid while the pattern lives."""
+        rp, ci, rk = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        check(load().mf_pattern_info(self._h, None, None, C.byref(rp), C.byref(ci), C.byref(rk)))
+        return rp.value, ci.value, rk.value
+
+    def assemble(self, form: Form, coords, precision: int = F64, elem_param=None, nodal_src=None,
+                 lin_state=None, dirichlet=None, K=None, d=None, scatter: int = SCATTER_AUTO,
+                 points_per_axis: int = 2, stream=None):
+        """Fill K [nnz] and d [n_rows] (allocated here when not given) on the stream."""
+        import torch
+        lib = load()
+        dt = torch.float64 if precision == F64 else torch.float32
+        dev = coords.device
+        if K is None:
+            K = torch.empty(self.nnz, dtype=dt, device=dev)
+        if d is None:
+            d = torch.empty(self.n_rows, dtype=dt, device=dev)
+        for name, t in (("elem_param", elem_param), ("nodal_src", nodal_src), ("lin_state", lin_state)):
+            if t is not None:
+                assert t.is_cuda and t.dtype == dt and t.is_contiguous(), f"{name} must be contiguous {dt} on cuda"
+        assert coords.dtype == torch.float64 and coords.is_contiguous()
+        if dirichlet is not None:
+            assert dirichlet.dtype == torch.uint8 and dirichlet.is_cuda
+        f = _Fields(_ptr(elem_param), _ptr(nodal_src), _ptr(lin_state), _ptr(dirichlet))
+        q = _Quad(points_per_axis)
+        check(lib.mf_assemble_ex(self._h, C.byref(form.c), _ptr(coords), C.byref(f), C.byref(q), precision,
+                                 scatter, _ptr(K), _ptr(d), _stream(stream)))
+        return K, d
+
+    def status(self):
+        """(status, first bad element or -1) of the last assembly (sync)."""
+        bad = C.c_int64()
+        st = load().mf_status_poll(self._h, C.byref(bad))
+        return st, bad.value
+
+
+_hip = None
+
+
+def _memcpy_d2h(dst: int, src: int, nbytes: int):
+    """Synchronous device-to-host copy of library-owned arrays (HIP runtime, as loaded by torch)."""
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+    rc = _hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(src), nbytes, 2)  # hipMemcpyDeviceToHost
+    if rc != 0:
+        raise MFError(ERR_HIP, f"hipMemcpy failed with {rc}")
+
+
+def version() -> str:
+    return load().mf_version().decode()

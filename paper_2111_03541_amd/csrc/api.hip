@@ -1,0 +1,223 @@
+// Host side of the C ABI declared in include/mf.h: argument validation, handle
+// lifetime, strategy dispatch and error reporting.  No device arithmetic here.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "mf_internal.h"
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+namespace mf {
+
+mf_status set_error(mf_status s, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+mf_status hip_error(hipError_t e, const char* what)
+{
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return set_error(MF_ERR_OOM, "%s: %s", what, hipGetErrorString(e));
+    return set_error(MF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace mf
+
+using namespace mf;
+
+static void free_pattern(mf_pattern_s* P)
+{
+    if (!P) return;
+    (void)hipFree(P->conn);
+    (void)hipFree(P->nbr_ptr);
+    (void)hipFree(P->nbr);
+    (void)hipFree(P->row_ptr);
+    (void)hipFree(P->col_idx);
+    (void)hipFree(P->rank);
+    (void)hipFree(P->status);
+    delete P;
+}
+
+extern "C" {
+
+const char* mf_last_error(void) { return g_err; }
+
+const char* mf_version(void) { return "metafem-mi 0.1 (gfx950)"; }
+
+mf_status mf_pattern(const mf_mesh* mesh, mf_elem_type type, int32_t order, const mf_dofs* dofs,
+                     void* stream, mf_pattern_t** out)
+{
+    g_err[0] = 0;
+    if (!out) return set_error(MF_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!mesh || !dofs) return set_error(MF_ERR_ARG, "mesh or dofs is NULL");
+    if (type != MF_QUAD4 && type != MF_HEX8) return set_error(MF_ERR_UNSUPPORTED, "element type %d", (int)type);
+    if (order != 1) return set_error(MF_ERR_UNSUPPORTED, "element order %d (only 1)", (int)order);
+    const int dim = type == MF_QUAD4 ? 2 : 3;
+    if (mesh->dim != dim) return set_error(MF_ERR_ARG, "mesh dim %d does not match the element", (int)mesh->dim);
+    if (mesh->n_nodes < 0 || mesh->n_elems < 0) return set_error(MF_ERR_ARG, "negative mesh size");
+    if (mesh->n_elems > 0 && !mesh->conn) return set_error(MF_ERR_ARG, "conn is NULL");
+    if (dofs->n_fields < 1 || dofs->n_fields > 4) return set_error(MF_ERR_ARG, "n_fields %d not in 1..4", (int)dofs->n_fields);
+    if (dofs->numbering != MF_NODE_MAJOR && dofs->numbering != MF_FIELD_MAJOR)
+        return set_error(MF_ERR_ARG, "unknown numbering %d", (int)dofs->numbering);
+    const int nen = 1 << dim;
+    if ((int64_t)nen * nen * mesh->n_elems >= ((int64_t)1 << 31) || mesh->n_nodes * dofs->n_fields >= ((int64_t)1 << 31))
+        return set_error(MF_ERR_OVERFLOW, "mesh too large for int32 indices");
+
+    mf_pattern_s* P = new (std::nothrow) mf_pattern_s();
+    if (!P) return set_error(MF_ERR_OOM, "host allocation failed");
+    P->dim = dim;
+    P->nen = nen;
+    P->nf = dofs->n_fields;
+    P->numbering = dofs->numbering;
+    P->n_nodes = mesh->n_nodes;
+    P->n_elems = mesh->n_elems;
+    P->n_rows = mesh->n_nodes * dofs->n_fields;
+    bool full = true;
+    for (int k = 0; k < P->nf * P->nf; ++k) {
+        P->coupling[k] = dofs->coupling ? (dofs->coupling[k] ? 1 : 0) : 1;
+        full = full && P->coupling[k];
+    }
+    for (int i = 0; i < P->nf; ++i) {
+        bool any = false;
+        for (int j = 0; j < P->nf; ++j) any = any || P->coupling[i * P->nf + j];
+        if (!any) {
+            delete P;
+            return set_error(MF_ERR_ARG, "coupling row %d is empty", i);
+        }
+    }
+    P->full_coupling = full;
+    hipStream_t s = (hipStream_t)stream;
+    mf_status st = build_pattern(P, mesh->conn, s);
+    if (st != MF_OK) {
+        (void)hipStreamSynchronize(s);
+        free_pattern(P);
+        return st;
+    }
+    st = reset_status(P, s);
+    if (st == MF_OK) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_error(e, "hipStreamSynchronize");
+    }
+    if (st != MF_OK) {
+        free_pattern(P);
+        return st;
+    }
+    *out = P;
+    return MF_OK;
+}
+
+mf_status mf_pattern_info(const mf_pattern_t* P, int64_t* n_rows, int64_t* nnz, const int32_t** row_ptr,
+                          const int32_t** col_idx, const uint8_t** rank)
+{
+    if (!P) return set_error(MF_ERR_ARG, "pattern is NULL");
+    if (n_rows) *n_rows = P->n_rows;
+    if (nnz) *nnz = P->nnz;
+    if (row_ptr) *row_ptr = P->row_ptr;
+    if (col_idx) *col_idx = P->col_idx;
+    if (rank) *rank = P->rank;
+    return MF_OK;
+}
+
+mf_status mf_pattern_grid(const mf_pattern_t* P, int32_t* is_grid, int64_t* nx, int64_t* ny, int64_t* nz)
+{
+    if (!P) return set_error(MF_ERR_ARG, "pattern is NULL");
+    if (is_grid) *is_grid = P->is_grid;
+    if (nx) *nx = P->gx;
+    if (ny) *ny = P->gy;
+    if (nz) *nz = P->gz;
+    return MF_OK;
+}
+
+void mf_pattern_destroy(mf_pattern_t* P)
+{
+    if (!P) return;
+    if (P->last_stream) (void)hipStreamSynchronize(P->last_stream);
+    free_pattern(P);
+}
+
+mf_status mf_assemble_ex(const mf_pattern_t* P, const mf_form* form, const double* coords,
+                         const mf_fields* fields, const mf_quadrature* quad, mf_precision prec,
+                         mf_scatter scatter, void* K, void* d, void* stream)
+{
+    g_err[0] = 0;
+    if (!P || !form || !quad) return set_error(MF_ERR_ARG, "pattern, form or quadrature is NULL");
+    if (quad->points_per_axis != 2)
+        return set_error(MF_ERR_UNSUPPORTED, "%d Gauss points per axis (only 2)", (int)quad->points_per_axis);
+    if (prec != MF_F64 && prec != MF_F32) return set_error(MF_ERR_ARG, "unknown precision %d", (int)prec);
+    int nf_form;
+    switch (form->kind) {
+        case MF_FORM_MASS:
+        case MF_FORM_POISSON: nf_form = 1; break;
+        case MF_FORM_ELASTICITY: nf_form = P->dim; break;
+        case MF_FORM_NS_SUPG: nf_form = P->dim + 1; break;
+        default: return set_error(MF_ERR_ARG, "unknown form kind %d", (int)form->kind);
+    }
+    if (nf_form != P->nf)
+        return set_error(MF_ERR_ARG, "form needs %d fields, pattern has %d", nf_form, P->nf);
+    if (!P->full_coupling)
+        return set_error(MF_ERR_ARG, "the form couples every field pair; the pattern's coupling is partial");
+    if (form->kind == MF_FORM_ELASTICITY && !(form->nu > -1.0 && form->nu < 0.5))
+        return set_error(MF_ERR_ARG, "Poisson's ratio %g outside (-1, 0.5)", form->nu);
+    if (P->n_elems > 0 && !coords) return set_error(MF_ERR_ARG, "coords is NULL");
+    if ((P->nnz > 0 && !K) || (P->n_rows > 0 && !d)) return set_error(MF_ERR_ARG, "K or d is NULL");
+    if (scatter != MF_SCATTER_AUTO && scatter != MF_SCATTER_ATOMIC && scatter != MF_SCATTER_GATHER)
+        return set_error(MF_ERR_ARG, "unknown scatter strategy %d", (int)scatter);
+
+    AssembleArgs A{};
+    A.P = P;
+    A.form = form;
+    A.coords = coords;
+    mf_fields none{};
+    const mf_fields* F = fields ? fields : &none;
+    A.elem_param = F->elem_param;
+    A.nodal_src = F->nodal_src;
+    A.lin_state = F->lin_state;
+    A.dirichlet = F->dirichlet;
+    A.prec = prec;
+    A.K = K;
+    A.d = d;
+    A.stream = (hipStream_t)stream;
+    const_cast<mf_pattern_s*>(P)->last_stream = A.stream;
+
+    mf_status st = reset_status(P, A.stream);
+    if (st != MF_OK) return st;
+    if (scatter == MF_SCATTER_AUTO) scatter = P->is_grid ? MF_SCATTER_GATHER : MF_SCATTER_ATOMIC;
+    if (scatter == MF_SCATTER_GATHER) {
+        st = assemble_gather(A);
+        if (st == MF_ERR_UNSUPPORTED) st = assemble_atomic(A);  // e.g. a form without a gather kernel
+    } else {
+        st = assemble_atomic(A);
+    }
+    if (st != MF_OK) return st;
+    return apply_dirichlet(A);
+}
+
+mf_status mf_assemble(const mf_pattern_t* P, const mf_form* form, const double* coords, const mf_fields* fields,
+                      const mf_quadrature* quad, mf_precision prec, void* K, void* d, void* stream)
+{
+    return mf_assemble_ex(P, form, coords, fields, quad, prec, MF_SCATTER_AUTO, K, d, stream);
+}
+
+mf_status mf_status_poll(const mf_pattern_t* P, int64_t* first_bad_elem)
+{
+    if (!P) return set_error(MF_ERR_ARG, "pattern is NULL");
+    unsigned long long v = 0;
+    if (P->last_stream) MF_HIP(hipStreamSynchronize(P->last_stream));
+    MF_HIP(hipMemcpy(&v, P->status, sizeof(v), hipMemcpyDeviceToHost));
+    if (first_bad_elem) *first_bad_elem = v == ~0ull ? -1 : (int64_t)v;
+    if (v != ~0ull) return set_error(MF_ERR_BAD_JACOBIAN, "det J <= 0 in element %lld", (long long)v);
+    return MF_OK;
+}
+
+}  // extern "C"

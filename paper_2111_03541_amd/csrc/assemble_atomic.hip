@@ -1,0 +1,204 @@
+// Element-parallel assembly with atomic scatter (Sec. 2.2 D-2 and D-3): the paper's own
+// scheme, kept as the strategy for meshes of any topology.
+//
+// One thread per (element e, local row (a, i)).  The thread computes the FP64 geometry
+// at every Gauss point of e, accumulates row (a, i) of the element tangent and the
+// element residual in precision T, and adds them into K and d with hardware atomics,
+// locating each entry through the element-to-nonzero rank map.  K and d are cleared by
+// fill kernels first, so the call overwrites them entirely.
+#include <hip/hip_runtime.h>
+
+#include "element.h"
+#include "mf_internal.h"
+
+namespace mf {
+namespace {
+
+constexpr int kThreads = 256;
+
+struct AtomicParams {
+    mf_form form;
+    int64_t n_el, n_nodes;
+    const int32_t* conn;
+    const double* coords;
+    const int32_t* row_ptr;
+    const int32_t* nbr_ptr;
+    const uint8_t* rank;
+    const void* elem_param;
+    const void* src;  // nodal sources (MASS/POISSON/ELASTICITY) or state (NS)
+    int field_major;
+    void* K;
+    void* d;
+    unsigned long long* status;
+};
+
+template <typename T>
+__global__ void k_fill(T* p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = T(0);
+}
+
+template <int FORM, int DIM, typename T>
+__global__ void __launch_bounds__(kThreads) k_assemble_atomic(AtomicParams p)
+{
+    constexpr int NEN = 1 << DIM;
+    constexpr int NF = FormTraits<FORM, DIM>::NF;
+    constexpr int NSRC = FormTraits<FORM, DIM>::NSRC;
+    const int64_t n_el = p.n_el;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_el * NEN * NF) return;
+    const int64_t e = t % n_el;
+    const int ai = (int)(t / n_el);
+    const int a = ai / NF, i = ai % NF;
+
+    int32_t node[NEN];
+    double x[NEN][DIM];
+    T U[NEN][NSRC];
+    const T* src = (const T*)p.src;
+#pragma unroll
+    for (int b = 0; b < NEN; ++b) {
+        node[b] = p.conn[(int64_t)b * n_el + e];
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) x[b][m] = p.coords[(int64_t)m * p.n_nodes + node[b]];
+#pragma unroll
+        for (int s = 0; s < NSRC; ++s) U[b][s] = src ? src[(int64_t)s * p.n_nodes + node[b]] : T(0);
+    }
+    const double ep = p.elem_param ? (double)((const T*)p.elem_param)[e] : 1.0;
+    const Coef<T> C = make_coef<T>(FORM, p.form, ep);
+
+    T krow[NEN * NF];
+#pragma unroll
+    for (int k = 0; k < NEN * NF; ++k) krow[k] = T(0);
+    T rrow = T(0);
+#pragma unroll
+    for (int q = 0; q < NEN; ++q) {  // 2^DIM Gauss points, unit weights
+        double gd[NEN][DIM];
+        const double det = geometry_at<DIM>(x, q, gd);
+        if (!(det > 0.0)) {
+            atomicMin(p.status, (unsigned long long)e);
+            return;
+        }
+        T N[NEN], g[NEN][DIM];
+#pragma unroll
+        for (int b = 0; b < NEN; ++b) {
+            N[b] = (T)ref_N<DIM>(b, q);
+#pragma unroll
+            for (int m = 0; m < DIM; ++m) g[b][m] = (T)gd[b][m];
+        }
+        row_update<FORM, DIM, T>(a, i, C, N, g, (T)det, U, krow, rrow);
+    }
+
+    const int64_t va = node[a];
+    const int64_t row = p.field_major ? (int64_t)i * p.n_nodes + va : (int64_t)NF * va + i;
+    const int64_t rs = p.row_ptr[row];
+    const int64_t deg = p.nbr_ptr[va + 1] - p.nbr_ptr[va];
+    T* K = (T*)p.K;
+    T* d = (T*)p.d;
+#pragma unroll
+    for (int b = 0; b < NEN; ++b) {
+        const int64_t rk = p.rank[(int64_t)(a * NEN + b) * n_el + e];
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            const int64_t pos = p.field_major ? rs + j * deg + rk : rs + rk * NF + j;
+            unsafeAtomicAdd(K + pos, krow[b * NF + j]);
+        }
+    }
+    unsafeAtomicAdd(d + row, -rrow);
+}
+
+template <typename T>
+__global__ void k_dirichlet(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                            const uint8_t* __restrict__ mask, int64_t n_rows, T* __restrict__ K,
+                            T* __restrict__ d)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    const int64_t k0 = row_ptr[r], k1 = row_ptr[r + 1];
+    if (mask[r]) {
+        for (int64_t k = k0; k < k1; ++k) K[k] = (col_idx[k] == r) ? T(1) : T(0);
+        d[r] = T(0);
+    } else {
+        for (int64_t k = k0; k < k1; ++k)
+            if (mask[col_idx[k]]) K[k] = T(0);
+    }
+}
+
+__global__ void k_reset_status(unsigned long long* s) { *s = ~0ull; }
+
+template <int FORM, int DIM, typename T>
+mf_status launch_atomic(const AssembleArgs& A)
+{
+    constexpr int NEN = 1 << DIM;
+    constexpr int NF = FormTraits<FORM, DIM>::NF;
+    const mf_pattern_s* P = A.P;
+    AtomicParams p{};
+    p.form = *A.form;
+    p.n_el = P->n_elems;
+    p.n_nodes = P->n_nodes;
+    p.conn = P->conn;
+    p.coords = A.coords;
+    p.row_ptr = P->row_ptr;
+    p.nbr_ptr = P->nbr_ptr;
+    p.rank = P->rank;
+    p.elem_param = A.elem_param;
+    p.src = FORM == MF_FORM_NS_SUPG ? A.lin_state : A.nodal_src;
+    p.field_major = P->numbering == MF_FIELD_MAJOR;
+    p.K = A.K;
+    p.d = A.d;
+    p.status = P->status;
+    if (P->nnz > 0) k_fill<T><<<blocks_for(P->nnz, kThreads), kThreads, 0, A.stream>>>((T*)A.K, P->nnz);
+    if (P->n_rows > 0) k_fill<T><<<blocks_for(P->n_rows, kThreads), kThreads, 0, A.stream>>>((T*)A.d, P->n_rows);
+    const int64_t n = P->n_elems * NEN * NF;
+    if (n > 0) k_assemble_atomic<FORM, DIM, T><<<blocks_for(n, kThreads), kThreads, 0, A.stream>>>(p);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+template <typename T>
+mf_status dispatch_atomic(const AssembleArgs& A)
+{
+    const int dim = A.P->dim;
+    switch (A.form->kind) {
+        case MF_FORM_MASS:
+            return dim == 2 ? launch_atomic<MF_FORM_MASS, 2, T>(A) : launch_atomic<MF_FORM_MASS, 3, T>(A);
+        case MF_FORM_POISSON:
+            return dim == 2 ? launch_atomic<MF_FORM_POISSON, 2, T>(A) : launch_atomic<MF_FORM_POISSON, 3, T>(A);
+        case MF_FORM_ELASTICITY:
+            return dim == 2 ? launch_atomic<MF_FORM_ELASTICITY, 2, T>(A)
+                            : launch_atomic<MF_FORM_ELASTICITY, 3, T>(A);
+        case MF_FORM_NS_SUPG:
+            return dim == 2 ? launch_atomic<MF_FORM_NS_SUPG, 2, T>(A) : launch_atomic<MF_FORM_NS_SUPG, 3, T>(A);
+    }
+    return set_error(MF_ERR_ARG, "unknown form kind %d", (int)A.form->kind);
+}
+
+}  // namespace
+
+mf_status assemble_atomic(const AssembleArgs& A)
+{
+    return A.prec == MF_F64 ? dispatch_atomic<double>(A) : dispatch_atomic<float>(A);
+}
+
+mf_status apply_dirichlet(const AssembleArgs& A)
+{
+    const mf_pattern_s* P = A.P;
+    if (!A.dirichlet || P->n_rows == 0) return MF_OK;
+    if (A.prec == MF_F64)
+        k_dirichlet<double><<<blocks_for(P->n_rows, kThreads), kThreads, 0, A.stream>>>(
+            P->row_ptr, P->col_idx, A.dirichlet, P->n_rows, (double*)A.K, (double*)A.d);
+    else
+        k_dirichlet<float><<<blocks_for(P->n_rows, kThreads), kThreads, 0, A.stream>>>(
+            P->row_ptr, P->col_idx, A.dirichlet, P->n_rows, (float*)A.K, (float*)A.d);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+mf_status reset_status(const mf_pattern_s* P, hipStream_t s)
+{
+    k_reset_status<<<1, 1, 0, s>>>(P->status);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+}  // namespace mf

@@ -1,0 +1,69 @@
+// Internal declarations shared by the host API and the HIP kernels of libmf.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "mf.h"
+
+// Library-owned state of one pattern (Sec. 2.2 Block B).
+struct mf_pattern_s {
+    int dim = 0, nen = 0, nf = 0;
+    mf_numbering numbering = MF_NODE_MAJOR;
+    int64_t n_nodes = 0, n_elems = 0, n_rows = 0, nnz = 0, n_pairs = 0;
+    uint8_t coupling[16] = {0};
+    bool full_coupling = false;
+    // device arrays, all owned
+    int32_t* conn = nullptr;     // [nen][n_elems] copy of the caller's connectivity
+    int32_t* nbr_ptr = nullptr;  // [n_nodes+1] node graph offsets
+    int32_t* nbr = nullptr;      // [n_pairs] sorted neighbours N(v)
+    int32_t* row_ptr = nullptr;  // [n_rows+1]
+    int32_t* col_idx = nullptr;  // [nnz]
+    uint8_t* rank = nullptr;     // [nen*nen][n_elems]
+    unsigned long long* status = nullptr;  // [1] first element with det J <= 0 (or ~0)
+    // structured lexicographic grid detection
+    int is_grid = 0;
+    int64_t gx = 0, gy = 0, gz = 0;
+    hipStream_t last_stream = nullptr;
+};
+
+namespace mf {
+
+mf_status set_error(mf_status s, const char* fmt, ...);
+mf_status hip_error(hipError_t e, const char* what);
+
+#define MF_HIP(call)                                            \
+    do {                                                        \
+        hipError_t e_ = (call);                                 \
+        if (e_ != hipSuccess) return ::mf::hip_error(e_, #call); \
+    } while (0)
+
+// pattern.hip
+mf_status build_pattern(mf_pattern_s* P, const int32_t* conn_in, hipStream_t s);
+
+// assemble.hip
+struct AssembleArgs {
+    const mf_pattern_s* P;
+    const mf_form* form;
+    const double* coords;
+    const void* elem_param;
+    const void* nodal_src;
+    const void* lin_state;
+    const uint8_t* dirichlet;
+    mf_precision prec;
+    void* K;
+    void* d;
+    hipStream_t stream;
+};
+mf_status assemble_atomic(const AssembleArgs& a);
+mf_status assemble_gather(const AssembleArgs& a);
+mf_status apply_dirichlet(const AssembleArgs& a);
+mf_status reset_status(const mf_pattern_s* P, hipStream_t s);
+
+inline unsigned blocks_for(int64_t n, int threads) {
+    return (unsigned)((n + threads - 1) / threads);
+}
+
+}  // namespace mf

@@ -1,0 +1,262 @@
+"""GPU parity of mf_pattern / mf_assemble against the oracle (through the C ABI).
+
+Pattern: bit-exact.  K and d: row-scaled relative error <= 1e-12 (FP64) or 1e-5 (FP32).
+In FP32 mode the oracle receives the same float-rounded inputs as the GPU (coordinates
+stay FP64), so the comparison measures the arithmetic only.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from helpers import TOL, oracle_rows, rowscaled_error, vec_error
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def cuda(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def gpu_pattern(mf, mesh, nf, coupling=None, numbering=0):
+    return mf.Pattern(cuda(mesh.conn), mesh.n_nodes, mesh.dim, nf, coupling=coupling, numbering=numbering)
+
+
+# ------------------------------------------------------------------ pattern
+
+PATTERN_CASES = [
+    ("quad3x2", lambda: W.structured_mesh((3, 2)), 1, None, 0),
+    ("quad7x5_fm", lambda: W.structured_mesh((7, 5)), 2, [[1, 0], [1, 1]], 1),
+    ("hex1", lambda: W.structured_mesh((1, 1, 1)), 3, None, 0),
+    ("hex9x7x6", lambda: W.structured_mesh((9, 7, 6)), 3, None, 0),
+    ("hex9x7x6_fm", lambda: W.structured_mesh((9, 7, 6)), 4, None, 1),
+    ("hex_perm", lambda: W.permute_mesh(W.structured_mesh((5, 4, 3)), 7)[0], 4,
+     [[1, 1, 0, 1], [1, 1, 0, 1], [0, 0, 1, 1], [1, 1, 1, 1]], 0),
+    ("hex_perm_fm", lambda: W.permute_mesh(W.structured_mesh((5, 4, 3)), 8)[0], 3, None, 1),
+]
+
+
+@pytest.mark.parametrize("name,make,nf,cpl,numbering", PATTERN_CASES, ids=[c[0] for c in PATTERN_CASES])
+def test_pattern_bit_exact(mf, name, make, nf, cpl, numbering):
+    say("pattern", name)
+    mesh = make()
+    cpl_arr = None if cpl is None else np.array(cpl, np.uint8)
+    ref = O.Pattern(mesh, nf, cpl_arr, numbering)
+    pat = gpu_pattern(mf, mesh, nf, cpl_arr, numbering)
+    rp, ci, rk = pat.arrays()
+    assert pat.n_rows == ref.n_rows and pat.nnz == ref.nnz
+    assert np.array_equal(rp.astype(np.int64), ref.row_ptr)
+    assert np.array_equal(ci, ref.col_idx)
+    assert np.array_equal(rk, ref.rank)
+
+
+def test_grid_detection(mf):
+    say("grid detection")
+    m = W.structured_mesh((6, 5, 4), jitter=0.1, seed=1)
+    g, n = gpu_pattern(mf, m, 1).grid()
+    assert g and n == (6, 5, 4)
+    g2, n2 = gpu_pattern(mf, W.structured_mesh((6, 5)), 1).grid()
+    assert g2 and n2[:2] == (6, 5)
+    gp, _ = gpu_pattern(mf, W.permute_mesh(m, 3)[0], 1).grid()
+    assert not gp
+
+
+def test_bad_node_id_is_reported(mf):
+    say("bad node id")
+    m = W.structured_mesh((2, 2, 2))
+    conn = m.conn.copy()
+    conn[3, 2] = m.n_nodes  # out of range
+    with pytest.raises(mf.MFError) as ei:
+        mf.Pattern(cuda(conn), m.n_nodes, 3, 1)
+    assert ei.value.status == mf.ERR_BAD_MESH
+
+
+# ------------------------------------------------------------------ assembly
+
+def make_inputs(kind, mesh, seed=0):
+    dim = mesh.dim
+    ep, src, state = None, None, None
+    params = {}
+    if kind == O.MASS:
+        params = {"coef": 1.7}
+        ep = W.lognormal_elem(mesh.n_elems, 0.3, seed + 1)
+        src = W.uniform_nodal(1, mesh.n_nodes, 0, 1, seed + 2)
+    elif kind == O.POISSON:
+        params = {"coef": 1.3}
+        ep = W.lognormal_elem(mesh.n_elems, 0.5, seed + 1)
+        src = W.uniform_nodal(1, mesh.n_nodes, 0, 1, seed + 2)
+    elif kind == O.ELASTICITY:
+        params = {"coef": 1.0, "nu": 0.3}
+        ep = W.lognormal_elem(mesh.n_elems, 0.5, seed + 1)
+        src = W.uniform_nodal(dim, mesh.n_nodes, -1, 1, seed + 2)
+    else:
+        params = {"rho": 1.0, "mu": 0.01, "tau_m": 3.417e-3, "tau_c": 1.059e-2}
+        state = np.zeros((dim + 1, mesh.n_nodes))
+        state[:dim] = W.fourier_velocity(mesh.coords, seed + 5)
+        state[dim] = W.uniform_nodal(1, mesh.n_nodes, -0.5, 0.5, seed + 3)[0]
+    return params, ep, src, state
+
+
+def run_gpu(mf, pat, kind, params, mesh, prec, ep, src, state, mask=None, scatter=0):
+    dt = torch.float64 if prec == mf.F64 else torch.float32
+    form = mf.Form(kind, **params)
+    K, d = pat.assemble(form, cuda(mesh.coords), precision=prec,
+                        elem_param=None if ep is None else cuda(ep, dt),
+                        nodal_src=None if src is None else cuda(src, dt),
+                        lin_state=None if state is None else cuda(state, dt),
+                        dirichlet=None if mask is None else cuda(mask),
+                        scatter=scatter)
+    torch.cuda.synchronize()
+    st, bad = pat.status()
+    assert st == mf.OK, (st, bad)
+    return K.double().cpu().numpy(), d.double().cpu().numpy()
+
+
+def rounded(a, prec):
+    if a is None or prec == 0:
+        return a
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+FORMS = [("mass", O.MASS), ("poisson", O.POISSON), ("elasticity", O.ELASTICITY), ("ns", O.NS_SUPG)]
+MESHES = [
+    ("hex9x7x6_jit", lambda: W.structured_mesh((9, 7, 6), jitter=0.15, seed=2)),
+    ("hex_perm", lambda: W.permute_mesh(W.structured_mesh((6, 5, 4), jitter=0.2, seed=3), 4)[0]),
+    ("quad11x6_jit", lambda: W.structured_mesh((11, 6), jitter=0.2, seed=5)),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("fname,kind", FORMS, ids=[f[0] for f in FORMS])
+@pytest.mark.parametrize("mname,make", MESHES, ids=[m[0] for m in MESHES])
+@pytest.mark.parametrize("scatter", [0, 1], ids=["auto", "atomic"])
+def test_assembly_parity(mf, prec, fname, kind, mname, make, scatter):
+    say("assemble", fname, mname, "f32" if prec else "f64", "scatter", scatter)
+    mesh = make()
+    nf = O.form_nf(kind, mesh.dim)
+    params, ep, src, state = make_inputs(kind, mesh)
+    ref_pat = O.Pattern(mesh, nf)
+    Kr, dr = O.assemble(ref_pat, kind, params, elem_param=rounded(ep, prec), nodal_src=rounded(src, prec),
+                        state=rounded(state, prec))
+    pat = gpu_pattern(mf, mesh, nf)
+    K, d = run_gpu(mf, pat, kind, params, mesh, prec, ep, src, state, scatter=scatter)
+    ek, ed = rowscaled_error(ref_pat, K, Kr), vec_error(d, dr)
+    say(f"  K err {ek:.3e}  d err {ed:.3e}")
+    assert ek <= TOL[prec] and ed <= TOL[prec]
+
+
+@pytest.mark.parametrize("numbering", [0, 1], ids=["node_major", "field_major"])
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_elasticity_dirichlet_and_numbering(mf, numbering, prec):
+    say("elasticity dirichlet numbering", numbering, prec)
+    mesh = W.structured_mesh((8, 6, 5), jitter=0.15, seed=9)
+    params, ep, src, _ = make_inputs(O.ELASTICITY, mesh, seed=3)
+    mask = W.dof_mask(W.boundary_node_mask(mesh.shape), 3, field_major=bool(numbering), fields=[0, 2])
+    ref_pat = O.Pattern(mesh, 3, numbering=numbering)
+    Kr, dr = O.assemble(ref_pat, O.ELASTICITY, params, elem_param=rounded(ep, prec),
+                        nodal_src=rounded(src, prec), dirichlet=mask)
+    pat = gpu_pattern(mf, mesh, 3, numbering=numbering)
+    K, d = run_gpu(mf, pat, O.ELASTICITY, params, mesh, prec, ep, src, None, mask=mask)
+    assert rowscaled_error(ref_pat, K, Kr) <= TOL[prec]
+    assert vec_error(d, dr) <= TOL[prec]
+
+
+def test_poisson_2d_32x32_dirichlet_f64(mf):
+    """Thermal conduction on the unit square, 32x32 Q1, k = 1, f ~ U[0,1] (seed 1),
+    u = 0 on the boundary: the whole system against the oracle."""
+    say("poisson 2d 32x32")
+    mesh = W.structured_mesh((32, 32))
+    f = W.uniform_nodal(1, mesh.n_nodes, 0, 1, 1)
+    mask = W.boundary_node_mask(mesh.shape)
+    ref_pat = O.Pattern(mesh, 1)
+    Kr, dr = O.assemble(ref_pat, O.POISSON, {"coef": 1.0}, nodal_src=f, dirichlet=mask)
+    pat = gpu_pattern(mf, mesh, 1)
+    K, d = run_gpu(mf, pat, O.POISSON, {"coef": 1.0}, mesh, 0, None, f, None, mask=mask)
+    assert rowscaled_error(ref_pat, K, Kr) <= 1e-12
+    assert vec_error(d, dr) <= 1e-12
+    assert int(mask.sum()) == 128
+
+
+def sampled_nodes(shape, n_random, seed):
+    rng = np.random.default_rng(seed)
+    npts = [v + 1 for v in shape]
+    nn = int(np.prod(npts))
+    picks = set(rng.integers(0, nn, n_random).tolist())
+    for corner in range(8):  # corners and a few edge/face nodes
+        ijk = [(npts[d] - 1) if (corner >> d) & 1 else 0 for d in range(3)]
+        picks.add(ijk[0] + npts[0] * (ijk[1] + npts[1] * ijk[2]))
+    picks.add(npts[0] // 2)                      # edge
+    picks.add(npts[0] * (npts[1] // 2))          # face
+    return sorted(picks)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_elasticity_64cubed_sampled_rows(mf, prec):
+    """Full-size 3D elasticity, 64^3 Q1, +-15% jitter, lognormal E, nu = 0.3, body force
+    U[-1,1]: sampled rows against the oracle on the elements around each sampled node."""
+    say("elasticity 64^3 sampled", prec)
+    mesh = W.structured_mesh((64, 64, 64), jitter=0.15, seed=2)
+    E = W.lognormal_elem(mesh.n_elems, 0.5, 3)
+    b = W.uniform_nodal(3, mesh.n_nodes, -1, 1, 4)
+    params = {"coef": 1.0, "nu": 0.3}
+    pat = gpu_pattern(mf, mesh, 3)
+    K, d = run_gpu(mf, pat, O.ELASTICITY, params, mesh, prec, E, b, None)
+    rp, ci, _ = pat.arrays()
+    nodes = sampled_nodes(mesh.shape, 120, 11)
+    ref = oracle_rows(mesh, nodes, O.ELASTICITY, 3, params, elem_param=rounded(E, prec),
+                      nodal_src=rounded(b, prec))
+    worst_k = worst_d = 0.0
+    for v, (cols, Krows, dref) in ref.items():
+        for i in range(3):
+            r = 3 * v + i
+            sl = slice(rp[r], rp[r + 1])
+            assert np.array_equal(ci[sl], cols)
+            scale = np.max(np.abs(Krows[i]))
+            worst_k = max(worst_k, np.max(np.abs(K[sl] - Krows[i])) / scale)
+        worst_d = max(worst_d, np.max(np.abs(d[3 * v:3 * v + 3] - dref)) / max(np.max(np.abs(dref)), 1e-300))
+    say(f"  sampled K err {worst_k:.3e} d err {worst_d:.3e}")
+    assert worst_k <= TOL[prec]
+    assert worst_d <= (TOL[prec] * 10 if prec else TOL[prec])
+
+
+def test_inverted_element_sets_status(mf):
+    say("inverted element")
+    mesh = W.structured_mesh((3, 3, 3))
+    conn = mesh.conn.copy()
+    conn[[0, 1], 13] = conn[[1, 0], 13]
+    bad = W.Mesh(mesh.coords, conn)
+    pat = gpu_pattern(mf, bad, 1)
+    form = mf.Form(mf.POISSON, coef=1.0)
+    pat.assemble(form, cuda(bad.coords))
+    st, e = pat.status()
+    assert st == mf.ERR_BAD_JACOBIAN and e == 13
+    # a good assembly on the same pattern clears the status
+    pat2 = gpu_pattern(mf, mesh, 1)
+    pat2.assemble(form, cuda(mesh.coords))
+    assert pat2.status() == (mf.OK, -1)
+
+
+def test_argument_errors(mf):
+    say("argument errors")
+    mesh = W.structured_mesh((2, 2, 2))
+    pat = gpu_pattern(mf, mesh, 1)
+    with pytest.raises(mf.MFError) as ei:
+        pat.assemble(mf.Form(mf.ELASTICITY, coef=1.0, nu=0.3), cuda(mesh.coords))
+    assert ei.value.status == mf.ERR_ARG
+    with pytest.raises(mf.MFError) as ei:
+        pat.assemble(mf.Form(mf.POISSON), cuda(mesh.coords), points_per_axis=3)
+    assert ei.value.status == mf.ERR_UNSUPPORTED
+    pat4 = gpu_pattern(mf, mesh, 4, coupling=np.tril(np.ones((4, 4))))
+    with pytest.raises(mf.MFError):
+        pat4.assemble(mf.Form(mf.NS_SUPG, rho=1.0), cuda(mesh.coords))
