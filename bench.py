@@ -147,6 +147,22 @@ def main():
                      "frac": achieved / HBM_PEAK, "traffic": None,
                      "alg_bytes_per_launch": B, "avg_launch_us": avg * 1e6},
     }
+    # secondary: the same workload in FP32 (geometry FP64, contractions FP32)
+    K32 = torch.empty(pat.nnz, dtype=torch.float32, device=dev)
+    d32 = torch.empty(pat.n_rows, dtype=torch.float32, device=dev)
+    E32, b32 = Et.float(), bt.float()
+
+    def step32():
+        pat.assemble(form, coords, precision=mf.F32, elem_param=E32, nodal_src=b32, K=K32, d=d32)
+
+    _, per32 = time_launches(step32, args.steps, args.warmup, stream)
+    avg32 = float(np.mean(per32))
+    B32 = alg_bytes_elasticity(mesh, pat.nnz, pat.n_rows, 4)
+    log(f"[bench] FP32 assemble avg {avg32 * 1e6:.1f} us ({B32 / avg32 / 1e9:.0f} GB/s algorithmic)")
+    record["secondary"] = {
+        "elasticity_64_f32": {"avg_launch_us": avg32 * 1e6, "elems_per_s": mesh.n_elems / avg32,
+                              "alg_bytes": B32, "hbm_frac": B32 / avg32 / HBM_PEAK},
+    }
     if not args.no_cpu:
         log("[bench] timing the oracle on the host")
         record["cpu_baseline"] = cpu_baseline(mesh, E, b)

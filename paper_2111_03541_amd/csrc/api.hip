@@ -193,14 +193,16 @@ mf_status mf_assemble_ex(const mf_pattern_t* P, const mf_form* form, const doubl
     mf_status st = reset_status(P, A.stream);
     if (st != MF_OK) return st;
     if (scatter == MF_SCATTER_AUTO) scatter = P->is_grid ? MF_SCATTER_GATHER : MF_SCATTER_ATOMIC;
+    bool gathered = false;
     if (scatter == MF_SCATTER_GATHER) {
-        st = assemble_gather(A);
+        st = assemble_gather(A);  // applies the Dirichlet elimination while writing K
+        gathered = st == MF_OK;
         if (st == MF_ERR_UNSUPPORTED) st = assemble_atomic(A);  // e.g. a form without a gather kernel
     } else {
         st = assemble_atomic(A);
     }
     if (st != MF_OK) return st;
-    return apply_dirichlet(A);
+    return gathered ? MF_OK : apply_dirichlet(A);
 }
 
 mf_status mf_assemble(const mf_pattern_t* P, const mf_form* form, const double* coords, const mf_fields* fields,

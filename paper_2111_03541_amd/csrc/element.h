@@ -21,7 +21,7 @@ constexpr double kGaussPt = 0.57735026918962576450914878050196;
 // s_{a,d} = +1 if bit d of a is set, else -1.  Integration point q uses the same bit
 // layout: xi_d = +1/sqrt(3) if bit d of q is set, else -1/sqrt(3).
 template <int DIM>
-__device__ __forceinline__ constexpr double ref_N(int a, int q)
+__host__ __device__ __forceinline__ constexpr double ref_N(int a, int q)
 {
     double v = 1.0;
     for (int d = 0; d < DIM; ++d) {
@@ -33,7 +33,7 @@ __device__ __forceinline__ constexpr double ref_N(int a, int q)
 }
 
 template <int DIM>
-__device__ __forceinline__ constexpr double ref_dN(int a, int q, int d)
+__host__ __device__ __forceinline__ constexpr double ref_dN(int a, int q, int d)
 {
     double v = ((a >> d) & 1) ? 0.5 : -0.5;
     for (int k = 0; k < DIM; ++k) {
@@ -43,6 +43,63 @@ __device__ __forceinline__ constexpr double ref_dN(int a, int q, int d)
         v *= 0.5 * (1.0 + s * xi);
     }
     return v;
+}
+
+// Reference basis at the 8 Gauss points of the hexahedron, for loops over q that are
+// not unrolled (q is uniform across a wavefront, so the reads are scalar loads).
+struct RefTablesHex {
+    double N[8][8];      // [q][a]
+    double dN[8][8][3];  // [q][a][d]
+    constexpr RefTablesHex() : N{}, dN{}
+    {
+        for (int q = 0; q < 8; ++q)
+            for (int a = 0; a < 8; ++a) {
+                N[q][a] = ref_N<3>(a, q);
+                for (int d = 0; d < 3; ++d) dN[q][a][d] = ref_dN<3>(a, q, d);
+            }
+    }
+};
+__constant__ constexpr RefTablesHex kRefHex{};
+
+// Hexahedron geometry at a runtime integration point q (tables above); same arithmetic
+// as geometry_at<3>.
+__device__ __forceinline__ double geometry_hex_rt(const double (&x)[8][3], int q, double (&g)[8][3])
+{
+    double J[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < 8; ++a) s = fma(x[a][i], kRefHex.dN[q][a][j], s);
+            J[i][j] = s;
+        }
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double r = 1.0 / det;
+    double Ji[3][3];
+    Ji[0][0] = c00 * r;
+    Ji[1][0] = c01 * r;
+    Ji[2][0] = c02 * r;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) s = fma(kRefHex.dN[q][a][j], Ji[j][m], s);
+            g[a][m] = s;
+        }
+    return det;
 }
 
 // Geometry at integration point q (FP64): J_ij = sum_a x_{a,i} dN_a/dxi_j, inverse by

@@ -260,3 +260,28 @@ def test_argument_errors(mf):
     pat4 = gpu_pattern(mf, mesh, 4, coupling=np.tril(np.ones((4, 4))))
     with pytest.raises(mf.MFError):
         pat4.assemble(mf.Form(mf.NS_SUPG, rho=1.0), cuda(mesh.coords))
+
+
+GATHER_MESHES = [(1, 1, 1), (2, 1, 1), (3, 5, 2), (7, 7, 3), (4, 4, 4), (5, 3, 11)]
+
+
+@pytest.mark.parametrize("n", GATHER_MESHES, ids=["x".join(map(str, n)) for n in GATHER_MESHES])
+@pytest.mark.parametrize("fname,kind", FORMS[:3], ids=[f[0] for f in FORMS[:3]])
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_gather_on_small_and_ragged_grids(mf, n, fname, kind, prec):
+    """The owner-computes path on grids whose node counts are and are not multiples of
+    the 4x4x4 brick, with Dirichlet rows on one face; against the oracle."""
+    say("gather", n, fname, prec)
+    mesh = W.structured_mesh(n, jitter=0.1, seed=sum(n))
+    nf = O.form_nf(kind, 3)
+    params, ep, src, state = make_inputs(kind, mesh, seed=7)
+    nm = W.boundary_node_mask(mesh.shape) * (mesh.coords[0] == 0.0)
+    mask = W.dof_mask(nm.astype(np.uint8), nf, field_major=False)
+    ref_pat = O.Pattern(mesh, nf)
+    Kr, dr = O.assemble(ref_pat, kind, params, elem_param=rounded(ep, prec), nodal_src=rounded(src, prec),
+                        dirichlet=mask)
+    pat = gpu_pattern(mf, mesh, nf)
+    assert pat.grid()[0]
+    K, d = run_gpu(mf, pat, kind, params, mesh, prec, ep, src, state, mask=mask, scatter=mf.SCATTER_GATHER)
+    assert rowscaled_error(ref_pat, K, Kr) <= TOL[prec]
+    assert vec_error(d, dr) <= TOL[prec]
