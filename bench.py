@@ -66,6 +66,49 @@ def time_launches(fn, steps, warmup, stream):
     return wall, per
 
 
+def poisson96_system(dev, seed=10000, n=96):
+    """3D Poisson on 96^3 Q1 hexes: lognormal k from a Gaussian field (sigma ~ U[1,2] drawn
+    from the seed, correlation length 0.1), f ~ U[0,1], u = 0 on the boundary."""
+    import torch
+    import workloads as W
+    import paper_2111_03541_amd as mf
+    rng = np.random.default_rng(seed)
+    sigma = float(rng.uniform(1.0, 2.0))
+    mesh = W.structured_mesh((n, n, n))
+    k = W.grf_lognormal_elem((n, n, n), sigma, 0.1, seed + 1)
+    f = W.uniform_nodal(1, mesh.n_nodes, 0, 1, seed + 2)
+    mask = W.boundary_node_mask(mesh.shape)
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 1)
+    args = dict(elem_param=torch.from_numpy(k).to(dev), nodal_src=torch.from_numpy(f).to(dev),
+                dirichlet=torch.from_numpy(mask).to(dev))
+    return mesh, pat, torch.from_numpy(mesh.coords).to(dev), args, sigma
+
+
+def bench_pcg(dev, steps=3):
+    import torch
+    import paper_2111_03541_amd as mf
+    mesh, pat, coords, args, sigma = poisson96_system(dev)
+    form = mf.Form(mf.POISSON, coef=1.0)
+    K, d = pat.assemble(form, coords, precision=mf.F64, **args)
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream(dev)
+    rp, ci, _ = pat.device_arrays()
+    times, res = [], None
+    x = torch.empty_like(d)
+    for _ in range(steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, res = mf.pcg(rp, ci, K, d, x=x, tol=1e-8, maxit=20000, precond=mf.PRECOND_JACOBI,
+                        check_every=16, use_graph=True, stream=stream)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times[1:]))
+    log(f"[bench] PCG 96^3 Jacobi: {res['iterations']} it, {t * 1e3:.1f} ms, relres {res['true_relres']:.2e}")
+    return {"n_dofs": pat.n_rows, "nnz": pat.nnz, "sigma": sigma, "iterations": res["iterations"],
+            "time_to_1e-8_ms": t * 1e3, "ms_per_iteration": t * 1e3 / max(res["iterations"], 1),
+            "true_relres": res["true_relres"], "converged": res["converged"]}
+
+
 def cpu_baseline(mesh, E, b):
     import oracle as O
     t0 = time.perf_counter()
@@ -163,6 +206,7 @@ def main():
         "elasticity_64_f32": {"avg_launch_us": avg32 * 1e6, "elems_per_s": mesh.n_elems / avg32,
                               "alg_bytes": B32, "hbm_frac": B32 / avg32 / HBM_PEAK},
     }
+    record["secondary"]["poisson_96_jacobi_pcg"] = bench_pcg(dev)
     if not args.no_cpu:
         log("[bench] timing the oracle on the host")
         record["cpu_baseline"] = cpu_baseline(mesh, E, b)

@@ -160,6 +160,53 @@ mf_status mf_status_poll(const mf_pattern_t* pat, int64_t* first_bad_elem);
 /* Thread-local message for the last failing call ("" if none). */
 const char* mf_last_error(void);
 
+/* ------------------------------------------------------------------------------------
+ * Linear solve of the assembled system (Sec. 2.2 D-4 leaves the solver open): FP64
+ * preconditioned conjugate gradients for symmetric positive definite K.
+ * ------------------------------------------------------------------------------------ */
+typedef enum {
+    MF_PRECOND_NONE = 0,    /* plain CG                                                 */
+    MF_PRECOND_JACOBI = 1,  /* z = r / diag(K)                                          */
+    MF_PRECOND_NN = 2       /* learned network (mf_nn_t), flexible CG; an iteration whose
+                               z.r <= 0 or non-finite z falls back to the Jacobi z      */
+} mf_precond_kind;
+
+typedef struct mf_nn_s mf_nn_t;   /* opaque learned preconditioner, see below */
+
+typedef struct {
+    int64_t n_rows;
+    const int32_t* row_ptr;   /* [n_rows+1] (device) */
+    const int32_t* col_idx;   /* [nnz] (device) */
+    const double* values;     /* [nnz] (device), FP64 */
+} mf_csr;
+
+typedef struct {
+    double tol;               /* stop when |b - K x|_2 / |b|_2 <= tol (true residual)      */
+    int32_t maxit;
+    int32_t check_every;      /* iterations between host convergence checks (0 = 8)       */
+    int32_t use_graph;        /* 1: replay each chunk of iterations as a HIP graph (needs a
+                                 non-default stream; silently off otherwise)              */
+    mf_precond_kind precond;
+    const mf_nn_t* net;       /* MF_PRECOND_NN only */
+} mf_pcg_opts;
+
+typedef struct {
+    int32_t iterations;       /* iterations run (a multiple of check_every unless maxit)  */
+    int32_t converged;        /* 1 when the true residual met tol                         */
+    int32_t fallbacks;        /* MF_PRECOND_NN: iterations that used the Jacobi z         */
+    double true_relres;       /* |b - K x|_2 / |b|_2 at exit                              */
+} mf_pcg_result;
+
+/*
+ * mf_pcg - solve K x = b from x0 = 0.  x [n_rows] is overwritten.  (sync: returns when
+ * the solve is done.)  Scalars stay on the device; the host reads the recurrence
+ * residual every check_every iterations and accepts only a true residual <= tol.
+ * Errors: MF_ERR_ARG, MF_ERR_NOT_CONVERGED (maxit reached; x and res hold the last
+ * iterate), MF_ERR_NONFINITE (breakdown: p.Kp <= 0 or r.z <= 0), MF_ERR_OOM, MF_ERR_HIP.
+ */
+mf_status mf_pcg(const mf_csr* A, const double* b, double* x, const mf_pcg_opts* opts,
+                 mf_pcg_result* res, void* stream);
+
 /* Library version string. */
 const char* mf_version(void);
 

@@ -62,12 +62,29 @@ class _Quad(C.Structure):
     _fields_ = [("points_per_axis", C.c_int32)]
 
 
+class _CSR(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("values", C.c_void_p)]
+
+
+class _PcgOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
+                ("precond", C.c_int), ("net", C.c_void_p)]
+
+
+class _PcgResult(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("fallbacks", C.c_int32),
+                ("true_relres", C.c_double)]
+
+
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_NN = 0, 1, 2
+
+
 _lib = None
 
 # every symbol declared in include/mf.h (checked by the ABI test)
 EXPORTS = [
     "mf_pattern", "mf_pattern_info", "mf_pattern_grid", "mf_pattern_destroy", "mf_assemble",
-    "mf_assemble_ex", "mf_status_poll", "mf_last_error", "mf_version",
+    "mf_assemble_ex", "mf_status_poll", "mf_last_error", "mf_version", "mf_pcg",
 ]
 
 
@@ -89,6 +106,7 @@ def load():
     lib.mf_assemble_ex.argtypes = [P, C.POINTER(_Form), P, C.POINTER(_Fields), C.POINTER(_Quad), C.c_int,
                                    C.c_int, P, P, P]
     lib.mf_status_poll.argtypes = [P, C.POINTER(i64)]
+    lib.mf_pcg.argtypes = [C.POINTER(_CSR), P, P, C.POINTER(_PcgOpts), C.POINTER(_PcgResult), P]
     lib.mf_last_error.restype = C.c_char_p
     lib.mf_version.restype = C.c_char_p
     _lib = lib
@@ -230,6 +248,36 @@ def _memcpy_d2h(dst: int, src: int, nbytes: int):
     rc = _hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(src), nbytes, 2)  # hipMemcpyDeviceToHost
     if rc != 0:
         raise MFError(ERR_HIP, f"hipMemcpy failed with {rc}")
+
+
+def pcg(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PRECOND_JACOBI, net=None,
+        check_every=8, use_graph=True, stream=None, raise_on_fail=True):
+    """Solve K x = b (FP64 CSR on the device; row_ptr/col_idx int32) by PCG from x0 = 0.
+
+    Returns (x, result dict).  use_graph needs a non-default stream; with the default
+    stream the iterations run eagerly."""
+    import torch
+    lib = load()
+    n = int(b.shape[0])
+    if x is None:
+        x = torch.empty(n, dtype=torch.float64, device=b.device)
+    A = _CSR(n, _ptr_any(row_ptr), _ptr_any(col_idx), _ptr(values))
+    opts = _PcgOpts(tol, maxit, check_every, int(bool(use_graph)), precond,
+                    None if net is None else net.handle)
+    res = _PcgResult()
+    st = lib.mf_pcg(C.byref(A), _ptr(b), _ptr(x), C.byref(opts), C.byref(res), _stream(stream))
+    out = {"iterations": res.iterations, "converged": bool(res.converged), "fallbacks": res.fallbacks,
+           "true_relres": res.true_relres, "status": st}
+    if st != OK and raise_on_fail:
+        raise MFError(st, lib.mf_last_error().decode())
+    return x, out
+
+
+def _ptr_any(t):
+    """A torch tensor or a raw device address (int)."""
+    if t is None:
+        return None
+    return C.c_void_p(t if isinstance(t, int) else t.data_ptr())
 
 
 def version() -> str:

@@ -43,6 +43,9 @@ mf_status hip_error(hipError_t e, const char* what);
 // pattern.hip
 mf_status build_pattern(mf_pattern_s* P, const int32_t* conn_in, hipStream_t s);
 
+struct PcgArgs;
+mf_status nn_bind_pcg(const mf_nn_t* net, int64_t n_rows, PcgArgs* a);
+
 // assemble.hip
 struct AssembleArgs {
     const mf_pattern_s* P;

@@ -1,0 +1,37 @@
+// Internal interface of the PCG driver (pcg.hip) used by the C ABI and by the learned
+// preconditioner.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mf.h"
+
+namespace mf {
+
+enum PcgPrecond { MF_PRECOND_INTERNAL_NONE = 0 };
+constexpr int MF_PRECOND_EXTERNAL = 100;  // z = apply(r) supplied by the caller
+
+// Writes z from r on the stream (no synchronisation).
+typedef mf_status (*PcgApply)(void* ctx, const double* r, double* z, hipStream_t s);
+
+struct PcgArgs {
+    int64_t n;
+    const int32_t* row_ptr;
+    const int32_t* col_idx;
+    const double* values;
+    const double* b;
+    double* x;
+    double tol;
+    int maxit;
+    int check_every;
+    int use_graph;
+    int precond;  // MF_PRECOND_NONE, MF_PRECOND_JACOBI or MF_PRECOND_EXTERNAL
+    PcgApply apply;
+    void* apply_ctx;
+    int apply_graph_safe;
+    hipStream_t stream;
+};
+
+mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res);
+
+}  // namespace mf

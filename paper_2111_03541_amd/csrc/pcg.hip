@@ -1,0 +1,441 @@
+// Preconditioned conjugate gradients on an assembled K (the linear solve of Sec. 2.2 D-4,
+// which the paper leaves open).  FP64 throughout.
+//
+// One iteration, all scalars kept on the device:
+//   k_spmv_dot   q = K p, partial sums of p.q
+//   k_reduce     alpha = (r.z) / (p.q)
+//   k_update     x += alpha p, r -= alpha q, z = M r, partial sums of r.z, r.r (and of
+//                z.r_old for the flexible variant)
+//   k_reduce     beta = (r.z)_new / (r.z) (flexible: (z.(r - r_old)) / (r.z)_old)
+//   k_dir        p = z + beta p
+// Partial sums use fixed block order, so a run is bit-reproducible.  Chunks of
+// iterations are captured once into a HIP graph and replayed; between chunks the host
+// reads the recurrence residual, and a candidate solution is accepted only when the
+// true residual |b - K x| / |b| meets the tolerance.
+//
+// Preconditioners: Jacobi (z = r / diag K), none, or an external apply (the learned
+// network) that writes z from r; for the external one the flexible beta is used and
+// any iteration with z.r <= 0 or a non-finite z falls back to the Jacobi z.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "mf_internal.h"
+#include "pcg.h"
+
+namespace mf {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRowsPerWave = 4;  // 16 lanes per row
+constexpr int kLanesPerRow = 64 / kRowsPerWave;
+constexpr int kMaxBlocks = 2048;  // partial-sum slots per reduction
+
+__device__ __forceinline__ double warp_sum_lanes16(double v)
+{
+#pragma unroll
+    for (int off = kLanesPerRow / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kLanesPerRow);
+    return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x / 64); ++k) s += sh[k];
+    __syncthreads();
+    return s;  // valid in thread 0
+}
+
+// y = A x (CSR), partial[block] = sum over the block's rows of w[row] * y[row] (w may be null)
+__global__ void __launch_bounds__(kThreads) k_spmv_dot(int n, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci,
+                                                       const double* __restrict__ v,
+                                                       const double* __restrict__ x, double* __restrict__ y,
+                                                       const double* __restrict__ w, double* __restrict__ partial,
+                                                       int rows_per_block_iter)
+{
+    __shared__ double sh[kThreads / 64];
+    const int lane = threadIdx.x % kLanesPerRow;
+    const int sub = threadIdx.x / kLanesPerRow;  // row slot within the block
+    constexpr int kSlots = kThreads / kLanesPerRow;
+    double acc_dot = 0.0;
+    for (int base = blockIdx.x * kSlots; base < n; base += gridDim.x * kSlots) {
+        const int row = base + sub;
+        double s = 0.0;
+        if (row < n) {
+            const int k1 = rp[row + 1];
+            for (int k = rp[row] + lane; k < k1; k += kLanesPerRow) s = fma(v[k], x[ci[k]], s);
+        }
+        s = warp_sum_lanes16(s);
+        if (row < n && lane == 0) {
+            y[row] = s;
+            if (w) acc_dot = fma(w[row], s, acc_dot);
+        }
+    }
+    (void)rows_per_block_iter;
+    const double t = block_sum(acc_dot, sh);
+    if (threadIdx.x == 0 && partial) partial[blockIdx.x] = t;
+}
+
+// Scalars (device): s[0] = rz, s[1] = pq, s[2] = alpha, s[3] = beta, s[4] = rr, s[5] = rz_new,
+// s[6] = zdr (flexible numerator), s[7] = fallback count, s[8] = breakdown flag
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RZNEW, S_ZDR, S_FALLBACK, S_BREAK, S_COUNT };
+
+__global__ void k_reduce_alpha(const double* __restrict__ partial, int nb, double* __restrict__ s)
+{
+    __shared__ double sh[kThreads / 64];
+    double v = 0.0;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) v += partial[k];
+    const double pq = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+        s[S_PQ] = pq;
+        const bool ok = pq > 0.0 && isfinite(pq);
+        if (!ok) s[S_BREAK] = 1.0;
+        s[S_ALPHA] = ok ? s[S_RZ] / pq : 0.0;
+    }
+}
+
+// x += alpha p; r -= alpha q; z = precond(r) (Jacobi here; external apply overwrites z
+// afterwards); partials: [0..nb) r.z, [nb..2nb) r.r, [2nb..3nb) z.r_old
+__global__ void __launch_bounds__(kThreads) k_update(int n, const double* __restrict__ s,
+                                                     double* __restrict__ x, double* __restrict__ r,
+                                                     double* __restrict__ r_old, const double* __restrict__ p,
+                                                     const double* __restrict__ q, const double* __restrict__ dinv,
+                                                     double* __restrict__ z, int jacobi, int keep_old)
+{
+    const double alpha = s[S_ALPHA];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        x[i] = fma(alpha, p[i], x[i]);
+        const double ri = fma(-alpha, q[i], r[i]);
+        if (keep_old) r_old[i] = r[i];
+        r[i] = ri;
+        if (jacobi >= 0) z[i] = jacobi ? dinv[i] * ri : ri;
+    }
+}
+
+// partial dots after z is known: r.z, r.r, z.r_old
+__global__ void __launch_bounds__(kThreads) k_dots(int n, const double* __restrict__ r, const double* __restrict__ z,
+                                                   const double* __restrict__ r_old, double* __restrict__ partial,
+                                                   int nb)
+{
+    __shared__ double sh[kThreads / 64];
+    double rz = 0.0, rr = 0.0, zro = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double ri = r[i], zi = z[i];
+        rz = fma(ri, zi, rz);
+        rr = fma(ri, ri, rr);
+        if (r_old) zro = fma(zi, r_old[i], zro);
+    }
+    const double a = block_sum(rz, sh);
+    const double b = block_sum(rr, sh);
+    const double c = block_sum(zro, sh);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = a;
+        partial[nb + blockIdx.x] = b;
+        partial[2 * nb + blockIdx.x] = c;
+    }
+}
+
+// beta from the partials; flexible: beta = (z.r - z.r_old) / rz_old
+__global__ void k_reduce_beta(const double* __restrict__ partial, int nb, double* __restrict__ s, int flexible)
+{
+    __shared__ double sh[kThreads / 64];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        a += partial[k];
+        b += partial[nb + k];
+        c += partial[2 * nb + k];
+    }
+    const double rz = block_sum(a, sh);
+    const double rr = block_sum(b, sh);
+    const double zro = block_sum(c, sh);
+    if (threadIdx.x == 0) {
+        const double rz_old = s[S_RZ];
+        const double num = flexible ? rz - zro : rz;
+        s[S_BETA] = rz_old != 0.0 ? num / rz_old : 0.0;
+        s[S_RZNEW] = rz;
+        s[S_RZ] = rz;
+        s[S_RR] = rr;
+        if (!(rz > 0.0) || !isfinite(rz)) s[S_BREAK] = 1.0;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_dir(int n, const double* __restrict__ s, const double* __restrict__ z,
+                                                  double* __restrict__ p)
+{
+    const double beta = s[S_BETA];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = fma(beta, p[i], z[i]);
+}
+
+// diag inverse, x = 0, r = b, z = M b, p = z
+__global__ void __launch_bounds__(kThreads) k_init(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                   const double* __restrict__ v, const double* __restrict__ b,
+                                                   double* __restrict__ dinv, double* __restrict__ x,
+                                                   double* __restrict__ r, double* __restrict__ z,
+                                                   double* __restrict__ p, int jacobi)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double di = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] == i) di = v[k];
+        dinv[i] = di != 0.0 ? 1.0 / di : 1.0;
+        x[i] = 0.0;
+        r[i] = b[i];
+        if (jacobi >= 0) {
+            z[i] = jacobi ? dinv[i] * b[i] : b[i];
+            p[i] = z[i];
+        }
+    }
+}
+
+// true residual partial sums: |b - A x|^2 and |b|^2
+__global__ void __launch_bounds__(kThreads) k_true_res(int n, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                                       const double* __restrict__ x, const double* __restrict__ b,
+                                                       double* __restrict__ partial, int nb)
+{
+    __shared__ double sh[kThreads / 64];
+    const int lane = threadIdx.x % kLanesPerRow;
+    const int sub = threadIdx.x / kLanesPerRow;
+    constexpr int kSlots = kThreads / kLanesPerRow;
+    double e2 = 0.0, b2 = 0.0;
+    for (int base = blockIdx.x * kSlots; base < n; base += gridDim.x * kSlots) {
+        const int row = base + sub;
+        double sacc = 0.0;
+        if (row < n)
+            for (int k = rp[row] + lane; k < rp[row + 1]; k += kLanesPerRow) sacc = fma(v[k], x[ci[k]], sacc);
+        sacc = warp_sum_lanes16(sacc);
+        if (row < n && lane == 0) {
+            const double e = b[row] - sacc;
+            e2 = fma(e, e, e2);
+            b2 = fma(b[row], b[row], b2);
+        }
+    }
+    const double a = block_sum(e2, sh);
+    const double c = block_sum(b2, sh);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = a;
+        partial[nb + blockIdx.x] = c;
+    }
+}
+
+__global__ void k_reduce2(const double* __restrict__ partial, int nb, double* __restrict__ out)
+{
+    __shared__ double sh[kThreads / 64];
+    double a = 0.0, c = 0.0;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        a += partial[k];
+        c += partial[nb + k];
+    }
+    const double A = block_sum(a, sh);
+    const double Cc = block_sum(c, sh);
+    if (threadIdx.x == 0) {
+        out[0] = A;
+        out[1] = Cc;
+    }
+}
+
+// z := Jacobi z where the external preconditioner failed (z.r <= 0 or non-finite z)
+__global__ void k_check_external(const double* __restrict__ partial_rz, int nb, double* __restrict__ s, int* flag)
+{
+    __shared__ double sh[kThreads / 64];
+    double a = 0.0;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) a += partial_rz[k];
+    const double rz = block_sum(a, sh);
+    if (threadIdx.x == 0) {
+        const int bad = !(rz > 0.0) || !isfinite(rz);
+        *flag = bad;
+        if (bad) s[S_FALLBACK] += 1.0;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_jacobi_if(int n, const int* __restrict__ flag,
+                                                        const double* __restrict__ dinv,
+                                                        const double* __restrict__ r, double* __restrict__ z)
+{
+    if (!*flag) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) z[i] = dinv[i] * r[i];
+}
+
+__global__ void k_set(double* p, int n, double v)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
+{
+    const int n = (int)a.n;
+    hipStream_t s = a.stream;
+    res->iterations = 0;
+    res->true_relres = 0.0;
+    res->fallbacks = 0;
+    res->converged = 0;
+    if (n == 0) {
+        res->converged = 1;
+        return MF_OK;
+    }
+    const int vec_blocks = (int)std::min<int64_t>(kMaxBlocks, (n + kThreads - 1) / kThreads);
+    const int spmv_blocks = (int)std::min<int64_t>(kMaxBlocks, (n + (kThreads / kLanesPerRow) - 1) / (kThreads / kLanesPerRow));
+    const int nb = std::max(vec_blocks, spmv_blocks);
+
+    // workspace: dinv r r_old z p q | partial[3 nb] | scalars | flag
+    std::vector<void*> owned;
+    auto dalloc = [&](size_t bytes) -> void* {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        owned.push_back(p);
+        return p;
+    };
+    struct Free {
+        std::vector<void*>* v;
+        ~Free() { for (void* p : *v) (void)hipFree(p); }
+    } fr{&owned};
+    double* dinv = (double*)dalloc(sizeof(double) * n);
+    double* r = (double*)dalloc(sizeof(double) * n);
+    double* r_old = (double*)dalloc(sizeof(double) * n);
+    double* z = (double*)dalloc(sizeof(double) * n);
+    double* p = (double*)dalloc(sizeof(double) * n);
+    double* q = (double*)dalloc(sizeof(double) * n);
+    double* partial = (double*)dalloc(sizeof(double) * 3 * nb);
+    double* sc = (double*)dalloc(sizeof(double) * (S_COUNT + 2));
+    int* flag = (int*)dalloc(sizeof(int));
+    if (!dinv || !r || !r_old || !z || !p || !q || !partial || !sc || !flag)
+        return set_error(MF_ERR_OOM, "PCG workspace allocation failed");
+
+    const bool external = a.precond == MF_PRECOND_EXTERNAL;
+    const int jac = a.precond == MF_PRECOND_JACOBI ? 1 : (a.precond == MF_PRECOND_NONE ? 0 : -1);
+    const int flexible = external ? 1 : 0;
+
+    k_set<<<1, 64, 0, s>>>(sc, S_COUNT + 2, 0.0);
+    k_init<<<vec_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, a.b, dinv, a.x, r, z, p, external ? 1 : jac);
+    if (external) {
+        mf_status st = a.apply(a.apply_ctx, r, z, s);
+        if (st != MF_OK) return st;
+        k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, nullptr, partial, vec_blocks);
+        k_check_external<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, flag);
+        k_jacobi_if<<<vec_blocks, kThreads, 0, s>>>(n, flag, dinv, r, z);
+        MF_HIP(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    }
+    k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, nullptr, partial, vec_blocks);
+    k_reduce_beta<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, 0);
+    MF_HIP(hipGetLastError());
+
+    // |b|
+    double hb2[2] = {0, 0};
+    k_true_res<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, a.x, a.b, partial, spmv_blocks);
+    k_reduce2<<<1, kThreads, 0, s>>>(partial, spmv_blocks, sc + S_COUNT);
+    MF_HIP(hipMemcpyAsync(hb2, sc + S_COUNT, sizeof(hb2), hipMemcpyDeviceToHost, s));
+    MF_HIP(hipStreamSynchronize(s));
+    const double bnorm = std::sqrt(hb2[1]);
+    if (bnorm == 0.0) {
+        res->converged = 1;
+        return MF_OK;
+    }
+
+    auto iteration = [&]() -> mf_status {
+        k_spmv_dot<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, p, q, p, partial, 0);
+        k_reduce_alpha<<<1, kThreads, 0, s>>>(partial, spmv_blocks, sc);
+        k_update<<<vec_blocks, kThreads, 0, s>>>(n, sc, a.x, r, r_old, p, q, dinv, z, external ? -1 : jac,
+                                                 flexible);
+        if (external) {
+            mf_status st = a.apply(a.apply_ctx, r, z, s);
+            if (st != MF_OK) return st;
+            k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, nullptr, partial, vec_blocks);
+            k_check_external<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, flag);
+            k_jacobi_if<<<vec_blocks, kThreads, 0, s>>>(n, flag, dinv, r, z);
+        }
+        k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, flexible ? r_old : nullptr, partial, vec_blocks);
+        k_reduce_beta<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, flexible);
+        k_dir<<<vec_blocks, kThreads, 0, s>>>(n, sc, z, p);
+        return MF_OK;
+    };
+
+    const int chunk = a.check_every > 0 ? a.check_every : 8;
+    // capture one chunk of iterations as a graph when the preconditioner allows it
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    bool use_graph = a.use_graph && (!external || a.apply_graph_safe);
+    if (use_graph) {
+        hipStreamCaptureMode mode = hipStreamCaptureModeThreadLocal;
+        if (hipStreamBeginCapture(s, mode) == hipSuccess) {
+            mf_status st = MF_OK;
+            for (int k = 0; k < chunk && st == MF_OK; ++k) st = iteration();
+            hipError_t e = hipStreamEndCapture(s, &graph);
+            if (st != MF_OK) return st;
+            if (e != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                use_graph = false;
+                (void)hipGetLastError();
+            }
+        } else {
+            use_graph = false;
+            (void)hipGetLastError();
+        }
+    }
+    struct GraphFree {
+        hipGraphExec_t* e;
+        hipGraph_t* g;
+        ~GraphFree() {
+            if (*e) (void)hipGraphExecDestroy(*e);
+            if (*g) (void)hipGraphDestroy(*g);
+        }
+    } gf{&exec, &graph};
+
+    double h[S_COUNT];
+    int it = 0;
+    const double tol = a.tol;
+    while (it < a.maxit) {
+        const int todo = std::min(chunk, a.maxit - it);
+        if (use_graph && todo == chunk) {
+            MF_HIP(hipGraphLaunch(exec, s));
+        } else {
+            for (int k = 0; k < todo; ++k) {
+                mf_status st = iteration();
+                if (st != MF_OK) return st;
+            }
+        }
+        MF_HIP(hipGetLastError());
+        it += todo;
+        MF_HIP(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s));
+        MF_HIP(hipStreamSynchronize(s));
+        res->fallbacks = (int)h[S_FALLBACK];
+        if (h[S_BREAK] != 0.0 || !std::isfinite(h[S_RR])) {
+            res->iterations = it;
+            return set_error(MF_ERR_NONFINITE, "PCG breakdown (p.Kp <= 0 or r.z <= 0) near iteration %d", it);
+        }
+        if (std::sqrt(h[S_RR]) / bnorm <= tol) {
+            // true residual as judge
+            k_true_res<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, a.x, a.b, partial,
+                                                        spmv_blocks);
+            k_reduce2<<<1, kThreads, 0, s>>>(partial, spmv_blocks, sc + S_COUNT);
+            MF_HIP(hipMemcpyAsync(hb2, sc + S_COUNT, sizeof(hb2), hipMemcpyDeviceToHost, s));
+            MF_HIP(hipStreamSynchronize(s));
+            res->true_relres = std::sqrt(hb2[0]) / bnorm;
+            if (res->true_relres <= tol) {
+                res->iterations = it;
+                res->converged = 1;
+                return MF_OK;
+            }
+        }
+    }
+    k_true_res<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, a.x, a.b, partial, spmv_blocks);
+    k_reduce2<<<1, kThreads, 0, s>>>(partial, spmv_blocks, sc + S_COUNT);
+    MF_HIP(hipMemcpyAsync(hb2, sc + S_COUNT, sizeof(hb2), hipMemcpyDeviceToHost, s));
+    MF_HIP(hipStreamSynchronize(s));
+    res->true_relres = std::sqrt(hb2[0]) / bnorm;
+    res->iterations = it;
+    return set_error(MF_ERR_NOT_CONVERGED, "PCG reached maxit = %d (true relative residual %.3e)", a.maxit,
+                     res->true_relres);
+}
+
+}  // namespace mf

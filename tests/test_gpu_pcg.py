@@ -1,0 +1,84 @@
+"""GPU Jacobi-PCG (mf_pcg) against the oracle's CPU PCG and a direct solve."""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def poisson_system(n, sigma, seed):
+    mesh = W.structured_mesh(n)
+    k = W.grf_lognormal_elem(n, sigma, 0.1, seed)
+    f = W.uniform_nodal(1, mesh.n_nodes, 0, 1, seed + 1)
+    mask = W.boundary_node_mask(mesh.shape)
+    pat = O.Pattern(mesh, 1)
+    K, d = O.assemble(pat, O.POISSON, {"coef": 1.0}, elem_param=k, nodal_src=f, dirichlet=mask)
+    return pat, K, d
+
+
+def to_dev(pat, K, d):
+    return (torch.from_numpy(pat.row_ptr.astype(np.int32)).cuda(), torch.from_numpy(pat.col_idx).cuda(),
+            torch.from_numpy(K).cuda(), torch.from_numpy(d).cuda())
+
+
+@pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
+def test_jacobi_pcg_matches_oracle(mf, graph):
+    say("pcg 16^3 lognormal", graph)
+    pat, K, d = poisson_system((16, 16, 16), 1.5, 3)
+    x_ref, it_ref, rel_ref = O.pcg_jacobi(pat.row_ptr, pat.col_idx, K, d, tol=1e-8)
+    rp, ci, v, b = to_dev(pat, K, d)
+    stream = torch.cuda.Stream() if graph else None
+    with torch.cuda.stream(stream) if stream is not None else torch.cuda.stream(torch.cuda.current_stream()):
+        x, res = mf.pcg(rp, ci, v, b, tol=1e-8, check_every=1 if not graph else 8, use_graph=graph,
+                        stream=stream)
+        torch.cuda.synchronize()
+    xh = x.cpu().numpy()
+    say("  gpu", res, "cpu iterations", it_ref)
+    assert res["converged"] and res["true_relres"] <= 1e-8
+    # recompute the true residual on the host
+    S = pat.to_scipy(K)
+    assert np.linalg.norm(d - S @ xh) / np.linalg.norm(d) <= 1e-8
+    direct = spla.spsolve(S.tocsc(), d)
+    assert np.max(np.abs(xh - direct)) <= 1e-7 * np.max(np.abs(direct))
+    if not graph:
+        # same recurrence, different summation order: iteration counts agree closely
+        assert abs(res["iterations"] - it_ref) <= max(2, 0.02 * it_ref)
+    else:
+        assert res["iterations"] >= it_ref - 1 and res["iterations"] <= it_ref + 8
+
+
+def test_pcg_2d_32x32(mf):
+    say("pcg 2d")
+    mesh = W.structured_mesh((32, 32))
+    f = W.uniform_nodal(1, mesh.n_nodes, 0, 1, 1)
+    mask = W.boundary_node_mask(mesh.shape)
+    pat = O.Pattern(mesh, 1)
+    K, d = O.assemble(pat, O.POISSON, {"coef": 1.0}, nodal_src=f, dirichlet=mask)
+    rp, ci, v, b = to_dev(pat, K, d)
+    x, res = mf.pcg(rp, ci, v, b, tol=1e-10, check_every=1)
+    direct = spla.spsolve(pat.to_scipy(K).tocsc(), d)
+    assert np.max(np.abs(x.cpu().numpy() - direct)) <= 1e-9 * np.max(np.abs(direct))
+
+
+def test_pcg_maxit_and_plain_cg(mf):
+    say("pcg maxit")
+    pat, K, d = poisson_system((8, 8, 8), 1.0, 5)
+    rp, ci, v, b = to_dev(pat, K, d)
+    x, res = mf.pcg(rp, ci, v, b, tol=1e-12, maxit=3, check_every=1, raise_on_fail=False)
+    assert res["status"] == mf.ERR_NOT_CONVERGED and not res["converged"] and res["iterations"] == 3
+    x2, res2 = mf.pcg(rp, ci, v, b, tol=1e-8, precond=mf.PRECOND_NONE, check_every=1)
+    assert res2["converged"]
+    _, it_ref, _ = O.pcg_jacobi(pat.row_ptr, pat.col_idx, K, d, tol=1e-8)
+    assert res2["iterations"] >= it_ref - 2  # plain CG never needs fewer here by much
+    with pytest.raises(mf.MFError):
+        mf.pcg(rp, ci, v, b, precond=mf.PRECOND_NN)
