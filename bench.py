@@ -109,6 +109,51 @@ def bench_pcg(dev, steps=3):
             "true_relres": res["true_relres"], "converged": res["converged"]}
 
 
+def bench_batch(dev, steps=10, warmup=3):
+    """256 independent problems, n_x, n_y, n_z ~ U{8..48} (seed 6+p), +-20% jitter; even p
+    Poisson (lognormal k, f ~ U[0,1]), odd p elasticity (lognormal E, nu 0.3, b ~ U[-1,1]);
+    FP32 with FP64 geometry, one persistent launch replayed as a HIP graph, autotuned."""
+    import torch
+    import workloads as W
+    import paper_2111_03541_amd as mf
+    sizes = W.batch_problem_sizes(256, 8, 48, base_seed=6)
+    probs, B_alg, n_el = [], 0, 0
+    for p, n in enumerate(sizes):
+        mesh = W.structured_mesh(n, jitter=0.2, seed=6 + p)
+        elastic = p % 2 == 1
+        nf = 3 if elastic else 1
+        ep = W.lognormal_elem(mesh.n_elems, 0.5, 10_000 + p)
+        src = W.uniform_nodal(nf, mesh.n_nodes, -1.0 if elastic else 0.0, 1.0, 20_000 + p)
+        pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, nf)
+        form = mf.Form(mf.ELASTICITY, coef=1.0, nu=0.3) if elastic else mf.Form(mf.POISSON, coef=1.0)
+        probs.append({"pattern": pat, "form": form, "coords": torch.from_numpy(mesh.coords).to(dev),
+                      "elem_param": torch.from_numpy(ep).float().to(dev),
+                      "nodal_src": torch.from_numpy(src).float().to(dev)})
+        n_el += mesh.n_elems
+        B_alg += (pat.nnz * 4 + pat.n_rows * 4 + 24 * mesh.n_nodes + 32 * mesh.n_elems + 4 * mesh.n_elems +
+                  4 * nf * mesh.n_nodes)
+    batch = mf.Batch(probs, precision=mf.F32)
+    stream = torch.cuda.Stream(dev)
+    info = batch.tune(os.environ.get("MF_TUNE_CACHE"), stream)
+    for _ in range(warmup):
+        batch.run(stream)
+    stream.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        batch.run(stream)
+        b.record(stream)
+    stream.synchronize()
+    t = float(np.median([a.elapsed_time(b) * 1e-3 for a, b in ev]))
+    for pr in probs:
+        assert pr["pattern"].status()[0] == mf.OK
+    info = batch.info()
+    log(f"[bench] batch 256 problems: {n_el} elements, {t * 1e6:.0f} us, {n_el / t / 1e9:.2f} G el/s, "
+        f"{B_alg / t / 1e9:.0f} GB/s algorithmic, tuned {info}")
+    return {"n_problems": 256, "n_elems": n_el, "launch_us": t * 1e6, "elems_per_s": n_el / t,
+            "alg_bytes": B_alg, "hbm_frac": B_alg / t / HBM_PEAK, "tuned": info}
+
+
 def cpu_baseline(mesh, E, b):
     import oracle as O
     t0 = time.perf_counter()
@@ -207,6 +252,7 @@ def main():
                               "alg_bytes": B32, "hbm_frac": B32 / avg32 / HBM_PEAK},
     }
     record["secondary"]["poisson_96_jacobi_pcg"] = bench_pcg(dev)
+    record["secondary"]["batched_256_f32"] = bench_batch(dev)
     if not args.no_cpu:
         log("[bench] timing the oracle on the host")
         record["cpu_baseline"] = cpu_baseline(mesh, E, b)

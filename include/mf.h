@@ -161,6 +161,46 @@ mf_status mf_status_poll(const mf_pattern_t* pat, int64_t* first_bad_elem);
 const char* mf_last_error(void);
 
 /* ------------------------------------------------------------------------------------
+ * Batched assembly: many independent structured problems (each with its own pattern,
+ * the paper's "workpieces", Sec. 2.2 A-1 and B-2) assembled by ONE persistent launch
+ * that work-steals (problem, brick) items, replayed as a HIP graph.  Problems must be
+ * structured 3D grids (mf_pattern_grid) with MASS, POISSON or ELASTICITY forms.
+ * ------------------------------------------------------------------------------------ */
+typedef struct mf_batch_s mf_batch_t;
+
+typedef struct {
+    const mf_pattern_t* pattern;
+    mf_form form;
+    const double* coords;     /* [3][n_nodes] FP64 (device) */
+    mf_fields fields;         /* lin_state unused */
+    void* K;                  /* [nnz] of this problem (device, precision-typed) */
+    void* d;                  /* [n_rows] (device) */
+} mf_batch_problem;
+
+/* (sync) Copies the problem descriptors to the device; the arrays they point to must
+   stay valid while the batch is used.  Default launch: round-robin items, one (FP64) or
+   two (FP32) workgroups per CU. */
+mf_status mf_batch_create(const mf_batch_problem* problems /* (host) [n] */, int32_t n,
+                          mf_precision precision, mf_batch_t** out);
+
+/* (sync) Autotuner: times each candidate launch shape (work-item order: problem-major,
+   round-robin, elasticity-first; workgroups per CU: 1, 2, 4) on the batch itself and
+   keeps the fastest.  cache_path (host string, may be NULL) is a text file of tuned
+   choices keyed by device, precision, problem mix and size bucket: a hit skips timing. */
+mf_status mf_batch_tune(mf_batch_t* batch, const char* cache_path, void* stream);
+
+/* One persistent launch assembling every problem (K and d overwritten; device status
+   words of all patterns reset first).  On a non-default stream the launch is captured
+   once as a HIP graph and replayed on later calls.  Async. */
+mf_status mf_batch_run(mf_batch_t* batch, void* stream);
+
+/* (sync) Work items, workgroups, item order, whether a graph exists, tuned time (us). */
+mf_status mf_batch_info(const mf_batch_t* batch, int64_t* n_items, int32_t* n_workgroups, int32_t* order,
+                        int32_t* graphed, double* tuned_us);
+
+void mf_batch_destroy(mf_batch_t* batch);
+
+/* ------------------------------------------------------------------------------------
  * Linear solve of the assembled system (Sec. 2.2 D-4 leaves the solver open): FP64
  * preconditioned conjugate gradients for symmetric positive definite K.
  * ------------------------------------------------------------------------------------ */

@@ -79,12 +79,18 @@ class _PcgResult(C.Structure):
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_NN = 0, 1, 2
 
 
+class _BatchProblem(C.Structure):
+    _fields_ = [("pattern", C.c_void_p), ("form", _Form), ("coords", C.c_void_p), ("fields", _Fields),
+                ("K", C.c_void_p), ("d", C.c_void_p)]
+
+
 _lib = None
 
 # every symbol declared in include/mf.h (checked by the ABI test)
 EXPORTS = [
     "mf_pattern", "mf_pattern_info", "mf_pattern_grid", "mf_pattern_destroy", "mf_assemble",
     "mf_assemble_ex", "mf_status_poll", "mf_last_error", "mf_version", "mf_pcg",
+    "mf_batch_create", "mf_batch_tune", "mf_batch_run", "mf_batch_info", "mf_batch_destroy",
 ]
 
 
@@ -107,6 +113,13 @@ def load():
                                    C.c_int, P, P, P]
     lib.mf_status_poll.argtypes = [P, C.POINTER(i64)]
     lib.mf_pcg.argtypes = [C.POINTER(_CSR), P, P, C.POINTER(_PcgOpts), C.POINTER(_PcgResult), P]
+    lib.mf_batch_create.argtypes = [C.POINTER(_BatchProblem), i32, C.c_int, C.POINTER(P)]
+    lib.mf_batch_tune.argtypes = [P, C.c_char_p, P]
+    lib.mf_batch_run.argtypes = [P, P]
+    lib.mf_batch_info.argtypes = [P, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                  C.POINTER(C.c_double)]
+    lib.mf_batch_destroy.argtypes = [P]
+    lib.mf_batch_destroy.restype = None
     lib.mf_last_error.restype = C.c_char_p
     lib.mf_version.restype = C.c_char_p
     _lib = lib
@@ -248,6 +261,61 @@ def _memcpy_d2h(dst: int, src: int, nbytes: int):
     rc = _hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(src), nbytes, 2)  # hipMemcpyDeviceToHost
     if rc != 0:
         raise MFError(ERR_HIP, f"hipMemcpy failed with {rc}")
+
+
+class Batch:
+    """mf_batch handle: many structured problems assembled by one persistent launch.
+
+    problems: list of dicts with keys pattern (Pattern), form (Form), coords, and optional
+    elem_param, nodal_src, dirichlet; K and d are allocated here unless given."""
+
+    def __init__(self, problems, precision: int = F32):
+        import torch
+        lib = load()
+        dt = torch.float64 if precision == F64 else torch.float32
+        self.problems = []
+        arr = (_BatchProblem * len(problems))()
+        for k, pr in enumerate(problems):
+            pat = pr["pattern"]
+            K = pr.get("K")
+            d = pr.get("d")
+            dev = pr["coords"].device
+            if K is None:
+                K = torch.empty(pat.nnz, dtype=dt, device=dev)
+            if d is None:
+                d = torch.empty(pat.n_rows, dtype=dt, device=dev)
+            keep = dict(pr, K=K, d=d)
+            self.problems.append(keep)
+            arr[k].pattern = pat.handle
+            arr[k].form = pr["form"].c
+            arr[k].coords = pr["coords"].data_ptr()
+            arr[k].fields = _Fields(_ptr(pr.get("elem_param")), _ptr(pr.get("nodal_src")), None,
+                                    _ptr(pr.get("dirichlet")))
+            arr[k].K = K.data_ptr()
+            arr[k].d = d.data_ptr()
+        h = C.c_void_p()
+        check(lib.mf_batch_create(arr, len(problems), precision, C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.mf_batch_destroy(h)
+            self._h = None
+
+    def tune(self, cache_path=None, stream=None):
+        check(load().mf_batch_tune(self._h, None if cache_path is None else cache_path.encode(), _stream(stream)))
+        return self.info()
+
+    def run(self, stream=None):
+        check(load().mf_batch_run(self._h, _stream(stream)))
+
+    def info(self):
+        n, wg, order, graphed, us = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        check(load().mf_batch_info(self._h, C.byref(n), C.byref(wg), C.byref(order), C.byref(graphed),
+                                   C.byref(us)))
+        return {"items": n.value, "workgroups": wg.value, "order": order.value, "graphed": bool(graphed.value),
+                "tuned_us": us.value}
 
 
 def pcg(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PRECOND_JACOBI, net=None,

@@ -17,6 +17,8 @@
 // carry weight 1/2.  Geometry is FP64 in both precisions (rounded to T afterwards).
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "element.h"
 #include "mf_internal.h"
 
@@ -68,8 +70,11 @@ struct GatherShape {
     static constexpr int kMinBlocks = sizeof(T) == 8 && FORM == MF_FORM_ELASTICITY ? 1 : 2;
 };
 
+// One brick of one problem; called by the single-problem kernel and by the persistent
+// batched kernel.  accK/accD/nodeInfo are the workgroup's LDS arrays.
 template <int FORM, typename T>
-__global__ void __launch_bounds__(kThreads, (GatherShape<FORM, T>::kMinBlocks)) k_gather_brick(GatherParams p)
+__device__ __forceinline__ void gather_brick_body(const GatherParams& p, int b, T* __restrict__ accK,
+                                                  T* __restrict__ accD, int (*nodeInfo)[4])
 {
     constexpr int NF = FormTraits<FORM, 3>::NF;
     constexpr int NSRC = FormTraits<FORM, 3>::NSRC;
@@ -77,15 +82,11 @@ __global__ void __launch_bounds__(kThreads, (GatherShape<FORM, T>::kMinBlocks)) 
     constexpr int ROWVALS = 27 * NB;            // values of one owned node's rows
     constexpr int NV = FORM == MF_FORM_ELASTICITY ? 9 : 1;
     constexpr int PASSES = GatherShape<FORM, T>::kPasses, PER = GatherShape<FORM, T>::kPerPass;
-    __shared__ T accK[kOwned * ROWVALS];
-    __shared__ T accD[kOwned * NF];
-    __shared__ int nodeInfo[kOwned][4];         // node id, first pair offset, degree, boundary bits
 
     const int tid = threadIdx.x;
     const int nx = (int)p.nx, ny = (int)p.ny, nz = (int)p.nz;
     const int NX = nx + 1, NY = ny + 1, NZ = nz + 1;  // nodes per axis
     const int nbx = (NX + BX - 1) / BX, nby = (NY + BY - 1) / BY;
-    const int b = blockIdx.x;
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     const int i0 = bx * BX, j0 = by * BY, k0 = bz * BZ;
 
@@ -300,7 +301,61 @@ __global__ void __launch_bounds__(kThreads, (GatherShape<FORM, T>::kMinBlocks)) 
 }
 
 template <int FORM, typename T>
-mf_status launch_gather(const AssembleArgs& A)
+__global__ void __launch_bounds__(kThreads, (GatherShape<FORM, T>::kMinBlocks)) k_gather_brick(GatherParams p)
+{
+    constexpr int NF = FormTraits<FORM, 3>::NF;
+    __shared__ T accK[kOwned * 27 * NF * NF];
+    __shared__ T accD[kOwned * NF];
+    __shared__ int nodeInfo[kOwned][4];  // node id, first pair offset, degree, boundary bits
+    gather_brick_body<FORM, T>(p, blockIdx.x, accK, accD, nodeInfo);
+}
+
+
+// ------------------------------------------------------------------------------------
+// Batched persistent launch: many structured problems in one kernel.  Work items are
+// (problem, brick) pairs in an order chosen on the host; each workgroup pops the next
+// item from a device counter until the list is exhausted (every wave reaches the exit).
+// ------------------------------------------------------------------------------------
+struct BatchProblemDev {
+    GatherParams gp;
+    int kind;
+};
+
+__global__ void k_batch_reset(int* counter, unsigned long long* const* status, int n_status)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *counter = 0;
+    if (i < n_status) *status[i] = ~0ull;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 ? 1 : 2))
+    k_batch_persistent(const BatchProblemDev* __restrict__ probs, const int2* __restrict__ items, int n_items,
+                       int* __restrict__ counter)
+{
+    __shared__ T accK[kOwned * 27 * 9];
+    __shared__ T accD[kOwned * 3];
+    __shared__ int nodeInfo[kOwned][4];
+    __shared__ int sItem;
+    while (true) {
+        __syncthreads();  // the previous item's write-out is done with the LDS
+        if (threadIdx.x == 0) sItem = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = sItem;
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        const GatherParams gp = probs[w.x].gp;
+        const int kind = probs[w.x].kind;
+        if (kind == MF_FORM_ELASTICITY)
+            gather_brick_body<MF_FORM_ELASTICITY, T>(gp, w.y, accK, accD, nodeInfo);
+        else if (kind == MF_FORM_POISSON)
+            gather_brick_body<MF_FORM_POISSON, T>(gp, w.y, accK, accD, nodeInfo);
+        else
+            gather_brick_body<MF_FORM_MASS, T>(gp, w.y, accK, accD, nodeInfo);
+    }
+}
+
+GatherParams make_params(const AssembleArgs& A)
 {
     const mf_pattern_s* P = A.P;
     GatherParams p{};
@@ -319,7 +374,19 @@ mf_status launch_gather(const AssembleArgs& A)
     p.K = A.K;
     p.d = A.d;
     p.status = P->status;
-    const int64_t nb = ((p.nx + 1 + BX - 1) / BX) * ((p.ny + 1 + BY - 1) / BY) * ((p.nz + 1 + BZ - 1) / BZ);
+    return p;
+}
+
+int64_t brick_count(const mf_pattern_s* P)
+{
+    return ((P->gx + 1 + BX - 1) / BX) * ((P->gy + 1 + BY - 1) / BY) * ((P->gz + 1 + BZ - 1) / BZ);
+}
+
+template <int FORM, typename T>
+mf_status launch_gather(const AssembleArgs& A)
+{
+    const GatherParams p = make_params(A);
+    const int64_t nb = brick_count(A.P);
     k_gather_brick<FORM, T><<<(unsigned)nb, kThreads, 0, A.stream>>>(p);
     MF_HIP(hipGetLastError());
     return MF_OK;
@@ -337,6 +404,49 @@ mf_status dispatch(const AssembleArgs& A)
 }
 
 }  // namespace
+
+
+// ---------------- batched launch: host side ----------------
+
+int64_t brick_count_of(const mf_pattern_s* P) { return brick_count(P); }
+
+mf_status batch_check(const AssembleArgs& A)
+{
+    const mf_pattern_s* P = A.P;
+    if (!P->is_grid || P->dim != 3 || !P->full_coupling || P->n_elems == 0)
+        return set_error(MF_ERR_UNSUPPORTED, "batched problems must be non-empty structured 3D grids with full coupling");
+    if (A.form->kind == MF_FORM_NS_SUPG) return set_error(MF_ERR_UNSUPPORTED, "batched launch covers mass, Poisson and elasticity");
+    return MF_OK;
+}
+
+mf_status batch_upload(const std::vector<AssembleArgs>& probs, void** dev_probs, void** dev_status)
+{
+    std::vector<BatchProblemDev> h(probs.size());
+    std::vector<unsigned long long*> st(probs.size());
+    for (size_t k = 0; k < probs.size(); ++k) {
+        h[k].gp = make_params(probs[k]);
+        h[k].kind = probs[k].form->kind;
+        st[k] = probs[k].P->status;
+    }
+    MF_HIP(hipMalloc(dev_probs, sizeof(BatchProblemDev) * (h.size() > 0 ? h.size() : 1)));
+    MF_HIP(hipMemcpy(*dev_probs, h.data(), sizeof(BatchProblemDev) * h.size(), hipMemcpyHostToDevice));
+    MF_HIP(hipMalloc(dev_status, sizeof(void*) * (st.size() > 0 ? st.size() : 1)));
+    MF_HIP(hipMemcpy(*dev_status, st.data(), sizeof(void*) * st.size(), hipMemcpyHostToDevice));
+    return MF_OK;
+}
+
+mf_status batch_launch(const void* dev_probs, void* dev_status, int n_probs, const int2* items, int n_items,
+                       int* counter, int n_wg, mf_precision prec, hipStream_t s)
+{
+    k_batch_reset<<<(n_probs + 255) / 256 > 0 ? (n_probs + 255) / 256 : 1, 256, 0, s>>>(
+        counter, (unsigned long long* const*)dev_status, n_probs);
+    if (prec == MF_F64)
+        k_batch_persistent<double><<<n_wg, kThreads, 0, s>>>((const BatchProblemDev*)dev_probs, items, n_items, counter);
+    else
+        k_batch_persistent<float><<<n_wg, kThreads, 0, s>>>((const BatchProblemDev*)dev_probs, items, n_items, counter);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
 
 // Returns MF_ERR_UNSUPPORTED (without launching) when the gather path does not cover
 // the case: unstructured meshes, 2D, partial coupling, or the flow form.

@@ -1,0 +1,337 @@
+// Batched assembly of many structured problems in one persistent launch, replayed as a
+// HIP graph, with a small autotuner for the launch shape (workgroup count and work-item
+// order).  The per-problem offsets play the role of the paper's workpiece offsets
+// n_dense / n_sp (Sec. 2.2 B-2): every problem keeps its own CSR and vector, located by
+// the pointers in its descriptor.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "mf_internal.h"
+
+struct mf_batch_s {
+    std::vector<mf::AssembleArgs> probs;
+    std::vector<mf_form> forms;
+    std::vector<int64_t> bricks;
+    mf_precision prec = MF_F64;
+    void* dprobs = nullptr;
+    void* dstatus = nullptr;
+    int* counter = nullptr;
+    int2* items = nullptr;
+    int n_items = 0;
+    int n_wg = 0;
+    int order = 1;
+    int num_cus = 256;
+    double tuned_us = 0.0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+};
+
+namespace {
+
+using namespace mf;
+
+void drop_graph(mf_batch_s* B)
+{
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    B->graph_stream = nullptr;
+}
+
+// order 0: problem-major; 1: round-robin over problems; 2: elasticity problems first,
+// then round-robin (costlier items early, so the tail is short)
+std::vector<int2> build_items(const mf_batch_s* B, int order)
+{
+    std::vector<int2> it;
+    const int np = (int)B->probs.size();
+    if (order == 0) {
+        for (int p = 0; p < np; ++p)
+            for (int64_t b = 0; b < B->bricks[p]; ++b) it.push_back(make_int2(p, (int)b));
+        return it;
+    }
+    std::vector<int> sel;
+    if (order == 2) {
+        for (int p = 0; p < np; ++p)
+            if (B->forms[p].kind == MF_FORM_ELASTICITY) sel.push_back(p);
+        for (int p = 0; p < np; ++p)
+            if (B->forms[p].kind != MF_FORM_ELASTICITY) sel.push_back(p);
+        // two groups, each round-robin
+        std::vector<int> a, b;
+        for (int p : sel) (B->forms[p].kind == MF_FORM_ELASTICITY ? a : b).push_back(p);
+        for (auto* grp : {&a, &b}) {
+            int64_t mx = 0;
+            for (int p : *grp) mx = std::max(mx, B->bricks[p]);
+            for (int64_t k = 0; k < mx; ++k)
+                for (int p : *grp)
+                    if (k < B->bricks[p]) it.push_back(make_int2(p, (int)k));
+        }
+        return it;
+    }
+    int64_t mx = 0;
+    for (int p = 0; p < np; ++p) mx = std::max(mx, B->bricks[p]);
+    for (int64_t k = 0; k < mx; ++k)
+        for (int p = 0; p < np; ++p)
+            if (k < B->bricks[p]) it.push_back(make_int2(p, (int)k));
+    return it;
+}
+
+mf_status upload_items(mf_batch_s* B, int order)
+{
+    std::vector<int2> it = build_items(B, order);
+    if (!B->items) MF_HIP(hipMalloc(&B->items, sizeof(int2) * (it.size() > 0 ? it.size() : 1)));
+    MF_HIP(hipMemcpy(B->items, it.data(), sizeof(int2) * it.size(), hipMemcpyHostToDevice));
+    B->n_items = (int)it.size();
+    B->order = order;
+    drop_graph(B);
+    return MF_OK;
+}
+
+std::string tune_key(const mf_batch_s* B)
+{
+    int n_el = 0;
+    for (auto& f : B->forms) n_el += f.kind == MF_FORM_ELASTICITY;
+    // bucket the item count to two significant digits
+    double lg = std::floor(std::log10(std::max(1, B->n_items)));
+    long bucket = (long)(std::round(B->n_items / std::pow(10.0, lg - 1)) * std::pow(10.0, lg - 1));
+    std::ostringstream os;
+    os << "gfx950|prec=" << (B->prec == MF_F64 ? "f64" : "f32") << "|problems=" << B->probs.size()
+       << "|elasticity=" << n_el << "|items~" << bucket;
+    return os.str();
+}
+
+bool cache_lookup(const char* path, const std::string& key, int* order, int* mult, double* us)
+{
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string k;
+        int o, m;
+        double u;
+        if (is >> k >> o >> m >> u && k == key) {
+            *order = o;
+            *mult = m;
+            *us = u;
+            return true;
+        }
+    }
+    return false;
+}
+
+void cache_store(const char* path, const std::string& key, int order, int mult, double us)
+{
+    if (!path) return;
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (std::getline(f, line))
+            if (line.compare(0, key.size() + 1, key + " ") != 0) keep.push_back(line);
+    }
+    std::ofstream f(path, std::ios::trunc);
+    for (auto& l : keep) f << l << "\n";
+    f << key << " " << order << " " << mult << " " << us << "\n";
+}
+
+mf_status launch(mf_batch_s* B, hipStream_t s)
+{
+    return batch_launch(B->dprobs, B->dstatus, (int)B->probs.size(), B->items, B->n_items, B->counter, B->n_wg,
+                        B->prec, s);
+}
+
+mf_status time_config(mf_batch_s* B, hipStream_t s, double* us)
+{
+    hipEvent_t e0, e1;
+    MF_HIP(hipEventCreate(&e0));
+    MF_HIP(hipEventCreate(&e1));
+    for (int w = 0; w < 2; ++w) {
+        mf_status st = launch(B, s);
+        if (st != MF_OK) return st;
+    }
+    std::vector<float> t;
+    for (int r = 0; r < 5; ++r) {
+        MF_HIP(hipEventRecord(e0, s));
+        mf_status st = launch(B, s);
+        if (st != MF_OK) return st;
+        MF_HIP(hipEventRecord(e1, s));
+        MF_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        MF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        t.push_back(ms);
+    }
+    std::sort(t.begin(), t.end());
+    *us = t[t.size() / 2] * 1e3;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return MF_OK;
+}
+
+void free_batch(mf_batch_s* B)
+{
+    if (!B) return;
+    drop_graph(B);
+    (void)hipFree(B->dprobs);
+    (void)hipFree(B->dstatus);
+    (void)hipFree(B->counter);
+    (void)hipFree(B->items);
+    delete B;
+}
+
+}  // namespace
+
+extern "C" {
+
+mf_status mf_batch_create(const mf_batch_problem* problems, int32_t n, mf_precision prec, mf_batch_t** out)
+{
+    if (!out) return set_error(MF_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!problems || n <= 0) return set_error(MF_ERR_ARG, "need at least one problem");
+    if (prec != MF_F64 && prec != MF_F32) return set_error(MF_ERR_ARG, "unknown precision");
+    mf_batch_s* B = new mf_batch_s();
+    B->prec = prec;
+    B->forms.resize(n);
+    for (int k = 0; k < n; ++k) {
+        const mf_batch_problem& q = problems[k];
+        if (!q.pattern || !q.coords || !q.K || !q.d) {
+            free_batch(B);
+            return set_error(MF_ERR_ARG, "problem %d: NULL pattern, coords, K or d", k);
+        }
+        B->forms[k] = q.form;
+        const int nf_form = q.form.kind == MF_FORM_ELASTICITY ? 3 : 1;
+        if (q.pattern->nf != nf_form) {
+            free_batch(B);
+            return set_error(MF_ERR_ARG, "problem %d: form needs %d fields, pattern has %d", k, nf_form,
+                             q.pattern->nf);
+        }
+    }
+    for (int k = 0; k < n; ++k) {
+        const mf_batch_problem& q = problems[k];
+        AssembleArgs a{};
+        a.P = q.pattern;
+        a.form = &B->forms[k];
+        a.coords = q.coords;
+        a.elem_param = q.fields.elem_param;
+        a.nodal_src = q.fields.nodal_src;
+        a.lin_state = nullptr;
+        a.dirichlet = q.fields.dirichlet;
+        a.prec = prec;
+        a.K = q.K;
+        a.d = q.d;
+        mf_status st = batch_check(a);
+        if (st != MF_OK) {
+            free_batch(B);
+            return st;
+        }
+        B->probs.push_back(a);
+        B->bricks.push_back(brick_count_of(q.pattern));
+    }
+    mf_status st = batch_upload(B->probs, &B->dprobs, &B->dstatus);
+    if (st == MF_OK && hipMalloc(&B->counter, sizeof(int)) != hipSuccess) st = set_error(MF_ERR_OOM, "counter");
+    int dev = 0, cus = 256;
+    if (st == MF_OK && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+        B->num_cus = cus;
+    B->n_wg = B->num_cus * (prec == MF_F64 ? 1 : 2);
+    if (st == MF_OK) st = upload_items(B, 1);
+    if (st != MF_OK) {
+        free_batch(B);
+        return st;
+    }
+    *out = B;
+    return MF_OK;
+}
+
+mf_status mf_batch_tune(mf_batch_t* B, const char* cache_path, void* stream)
+{
+    if (!B) return set_error(MF_ERR_ARG, "batch is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const std::string key = tune_key(B);
+    int order = 1, mult = 1;
+    double us = 0;
+    if (cache_lookup(cache_path, key, &order, &mult, &us)) {
+        mf_status st = upload_items(B, order);
+        if (st != MF_OK) return st;
+        B->n_wg = B->num_cus * mult;
+        B->tuned_us = us;
+        return MF_OK;
+    }
+    double best = 1e300;
+    int best_order = 1, best_mult = 1;
+    const int max_mult = B->prec == MF_F64 ? 2 : 4;
+    for (int o = 0; o < 3; ++o) {
+        mf_status st = upload_items(B, o);
+        if (st != MF_OK) return st;
+        for (int m = 1; m <= max_mult; m *= 2) {
+            B->n_wg = B->num_cus * m;
+            double t = 0;
+            st = time_config(B, s, &t);
+            if (st != MF_OK) return st;
+            if (t < best) {
+                best = t;
+                best_order = o;
+                best_mult = m;
+            }
+        }
+    }
+    mf_status st = upload_items(B, best_order);
+    if (st != MF_OK) return st;
+    B->n_wg = B->num_cus * best_mult;
+    B->tuned_us = best;
+    cache_store(cache_path, key, best_order, best_mult, best);
+    return MF_OK;
+}
+
+mf_status mf_batch_run(mf_batch_t* B, void* stream)
+{
+    if (!B) return set_error(MF_ERR_ARG, "batch is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    for (auto& a : B->probs) const_cast<mf_pattern_s*>(a.P)->last_stream = s;
+    if (!s) return launch(B, s);  // the default stream cannot be captured
+    if (!B->exec || B->graph_stream != s) {
+        drop_graph(B);
+        MF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        mf_status st = launch(B, s);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (st != MF_OK) return st;
+        if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+        B->graph = g;
+        MF_HIP(hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0));
+        B->graph_stream = s;
+    }
+    MF_HIP(hipGraphLaunch(B->exec, s));
+    return MF_OK;
+}
+
+mf_status mf_batch_info(const mf_batch_t* B, int64_t* n_items, int32_t* n_workgroups, int32_t* order,
+                        int32_t* graphed, double* tuned_us)
+{
+    if (!B) return set_error(MF_ERR_ARG, "batch is NULL");
+    if (n_items) *n_items = B->n_items;
+    if (n_workgroups) *n_workgroups = B->n_wg;
+    if (order) *order = B->order;
+    if (graphed) *graphed = B->exec != nullptr;
+    if (tuned_us) *tuned_us = B->tuned_us;
+    return MF_OK;
+}
+
+void mf_batch_destroy(mf_batch_t* B)
+{
+    if (!B) return;
+    if (B->graph_stream) (void)hipStreamSynchronize(B->graph_stream);
+    free_batch(B);
+}
+
+}  // extern "C"

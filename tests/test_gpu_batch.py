@@ -1,0 +1,98 @@
+"""Batched persistent launch (mf_batch_*) against the oracle and the single-problem path."""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from helpers import TOL, rowscaled_error, vec_error
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def make_problems(mf, sizes, prec, seed0=100):
+    dt = torch.float64 if prec == mf.F64 else torch.float32
+    out, host = [], []
+    for p, n in enumerate(sizes):
+        mesh = W.structured_mesh(n, jitter=0.2, seed=seed0 + p)
+        elastic = p % 2 == 1
+        nf = 3 if elastic else 1
+        ep = W.lognormal_elem(mesh.n_elems, 0.5, seed0 + 1000 + p)
+        src = W.uniform_nodal(nf, mesh.n_nodes, -1 if elastic else 0, 1, seed0 + 2000 + p)
+        mask = None
+        if p % 3 == 0:
+            mask = W.dof_mask(W.boundary_node_mask(mesh.shape), nf, field_major=False)
+        pat = mf.Pattern(torch.from_numpy(mesh.conn).cuda(), mesh.n_nodes, 3, nf)
+        form = mf.Form(mf.ELASTICITY, coef=1.0, nu=0.3) if elastic else mf.Form(mf.POISSON, coef=1.0)
+        out.append({"pattern": pat, "form": form, "coords": torch.from_numpy(mesh.coords).cuda(),
+                    "elem_param": torch.from_numpy(ep).to(dt).cuda(),
+                    "nodal_src": torch.from_numpy(src).to(dt).cuda(),
+                    "dirichlet": None if mask is None else torch.from_numpy(mask).cuda()})
+        host.append((mesh, elastic, ep, src, mask))
+    return out, host
+
+
+def rounded(a, prec):
+    return a if prec == 0 else np.asarray(a, np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_batch_matches_oracle(mf, prec):
+    sizes = [(3, 2, 2), (5, 4, 3), (2, 7, 3), (9, 3, 4), (1, 1, 1), (6, 6, 5), (4, 9, 2), (3, 3, 8)]
+    say("batch", prec, sizes)
+    probs, host = make_problems(mf, sizes, prec)
+    batch = mf.Batch(probs, precision=prec)
+    stream = torch.cuda.Stream()
+    batch.run(stream)
+    stream.synchronize()
+    for pr, (mesh, elastic, ep, src, mask) in zip(batch.problems, host):
+        st, bad = pr["pattern"].status()
+        assert st == mf.OK
+        kind = O.ELASTICITY if elastic else O.POISSON
+        params = {"coef": 1.0, "nu": 0.3} if elastic else {"coef": 1.0}
+        ref = O.Pattern(mesh, 3 if elastic else 1)
+        Kr, dr = O.assemble(ref, kind, params, elem_param=rounded(ep, prec), nodal_src=rounded(src, prec),
+                            dirichlet=mask)
+        K = pr["K"].double().cpu().numpy()
+        d = pr["d"].double().cpu().numpy()
+        assert rowscaled_error(ref, K, Kr) <= TOL[prec]
+        assert vec_error(d, dr) <= TOL[prec]
+
+
+def test_batch_graph_replays_and_tuner_cache(mf):
+    sizes = [tuple(int(v) for v in s) for s in W.batch_problem_sizes(12, 2, 7, base_seed=40)]
+    say("batch replay", sizes)
+    probs, _ = make_problems(mf, sizes, 1, seed0=300)
+    batch = mf.Batch(probs, precision=mf.F32)
+    stream = torch.cuda.Stream()
+    with tempfile.TemporaryDirectory() as tmp:
+        cache = os.path.join(tmp, "tune.txt")
+        info = batch.tune(cache, stream)
+        assert info["tuned_us"] > 0 and os.path.exists(cache)
+        batch2 = mf.Batch(probs, precision=mf.F32)
+        info2 = batch2.tune(cache, stream)  # cache hit: same choice, no timing
+        assert info2["order"] == info["order"] and info2["workgroups"] == info["workgroups"]
+        assert info2["tuned_us"] == pytest.approx(info["tuned_us"], rel=1e-6)
+    batch.run(stream)
+    stream.synchronize()
+    first = [(p["K"].clone(), p["d"].clone()) for p in batch.problems]
+    assert batch.info()["graphed"]
+    for rep in range(3):
+        # eager work between replays: wipe the outputs
+        for p in batch.problems:
+            p["K"].fill_(123.0)
+            p["d"].zero_()
+        torch.cuda.synchronize()
+        batch.run(stream)
+        stream.synchronize()
+        for (K0, d0), p in zip(first, batch.problems):
+            assert torch.allclose(p["K"], K0, rtol=1e-5, atol=1e-6 * float(K0.abs().max()))
+            assert torch.allclose(p["d"], d0, rtol=1e-5, atol=1e-6 * float(d0.abs().max() + 1e-30))
