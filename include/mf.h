@@ -247,6 +247,52 @@ typedef struct {
 mf_status mf_pcg(const mf_csr* A, const double* b, double* x, const mf_pcg_opts* opts,
                  mf_pcg_result* res, void* stream);
 
+/* y = A x (FP64 CSR).  Async. */
+mf_status mf_spmv(const mf_csr* A, const double* x, double* y, void* stream);
+
+/* ------------------------------------------------------------------------------------
+ * Learned preconditioner for mf_pcg on structured-grid scalar systems (node id
+ * x + nx (y + ny z), one DOF per node).  A small linear multilevel 3D convolution network
+ * applied to the diagonally scaled residual:
+ *   z = s Dm^-1/2 N(v),  v = Dm^-1/2 r / s,  s = max|Dm^-1/2 r|,  Dm = diag(K),
+ *   N(v) = y_0 + P(y_1 + P(y_2 + ...)),  y_0 = conv(v) (1->1 channel),
+ *   y_l = conv(conv(conv(R^l v))) (1 -> c_l -> c_l -> 1), R full weighting, P = R^T,
+ *   3x3x3 kernels, zero padding, no bias; z = 0 on Dirichlet rows.
+ * Weights and activations are BF16, accumulation FP32; parameters are kept in FP32 for
+ * the optimiser.  Training minimises |K z - r|^2 / |r|^2 with Adam.
+ * ------------------------------------------------------------------------------------ */
+
+/* grid (host) [3] = node counts (nx, ny, nz), odd and >= 3 on every level but the last;
+   channels (host) [levels], channels[0] = 1, others in {1, 2, 4, 8}.  Parameters start
+   with the level-0 stencil equal to the identity (the network starts as Jacobi) and the
+   other weights drawn from N(0, 0.02^2) with the given seed.  (sync) */
+mf_status mf_nn_create(const int32_t* grid, int32_t levels, const int32_t* channels, uint64_t seed,
+                       mf_nn_t** out);
+
+/* (sync) Number of parameters; copy them out (get, host, may be NULL) and/or replace them
+   (set, host, may be NULL; resets the optimiser state).  Layout: the level-0 tensor
+   [1][1][27], then per level l >= 1: [c][1][27], [c][c][27], [1][c][27]; each kernel
+   tap t = (dz+1)*9 + (dy+1)*3 + (dx+1). */
+mf_status mf_nn_params(mf_nn_t* net, float* get, const float* set, int64_t* n_params);
+
+/* Bind the network to one assembled system: K (device CSR, FP64, n_rows = node count)
+   and its Dirichlet mask (device, may be NULL).  Async; K must stay valid while bound. */
+mf_status mf_nn_set_system(mf_nn_t* net, const mf_csr* K, const uint8_t* dirichlet, void* stream);
+
+/* z = N_theta(r) for the bound system (BF16 inference).  Async, graph-capturable. */
+mf_status mf_nn_apply(mf_nn_t* net, const double* r, double* z, void* stream);
+
+/* One training step on residual r of the bound system: forward, loss, backward.
+   Loss: with e == NULL, |K z - r|^2 / |r|^2; with e (device, the error whose residual is
+   r = K e), the energy-norm error (z - e)^T K (z - e) / e^T K e, the quantity CG
+   minimises.  grad (host, may be NULL): if given, the gradient is copied out and the
+   parameters are NOT updated; otherwise one Adam step with learning rate lr.  *loss
+   (host) receives the loss.  (sync) */
+mf_status mf_nn_train_step(mf_nn_t* net, const double* r, const double* e, double lr, double* loss,
+                           float* grad, void* stream);
+
+void mf_nn_destroy(mf_nn_t* net);
+
 /* Library version string. */
 const char* mf_version(void);
 

@@ -91,6 +91,7 @@ EXPORTS = [
     "mf_pattern", "mf_pattern_info", "mf_pattern_grid", "mf_pattern_destroy", "mf_assemble",
     "mf_assemble_ex", "mf_status_poll", "mf_last_error", "mf_version", "mf_pcg",
     "mf_batch_create", "mf_batch_tune", "mf_batch_run", "mf_batch_info", "mf_batch_destroy",
+    "mf_nn_create", "mf_nn_params", "mf_nn_set_system", "mf_nn_apply", "mf_nn_train_step", "mf_nn_destroy", "mf_spmv",
 ]
 
 
@@ -120,6 +121,14 @@ def load():
                                   C.POINTER(C.c_double)]
     lib.mf_batch_destroy.argtypes = [P]
     lib.mf_batch_destroy.restype = None
+    lib.mf_nn_create.argtypes = [P, i32, P, C.c_uint64, C.POINTER(P)]
+    lib.mf_nn_params.argtypes = [P, P, P, C.POINTER(i64)]
+    lib.mf_nn_set_system.argtypes = [P, C.POINTER(_CSR), P, P]
+    lib.mf_nn_apply.argtypes = [P, P, P, P]
+    lib.mf_nn_train_step.argtypes = [P, P, P, C.c_double, C.POINTER(C.c_double), P, P]
+    lib.mf_spmv.argtypes = [C.POINTER(_CSR), P, P, P]
+    lib.mf_nn_destroy.argtypes = [P]
+    lib.mf_nn_destroy.restype = None
     lib.mf_last_error.restype = C.c_char_p
     lib.mf_version.restype = C.c_char_p
     _lib = lib
@@ -318,6 +327,79 @@ class Batch:
                 "tuned_us": us.value}
 
 
+class Net:
+    """mf_nn handle: the learned multilevel convolution preconditioner on a node grid."""
+
+    def __init__(self, grid, channels, seed: int = 0):
+        import numpy as np
+        lib = load()
+        g = (C.c_int32 * 3)(*[int(v) for v in grid])
+        ch = (C.c_int32 * len(channels))(*[int(v) for v in channels])
+        h = C.c_void_p()
+        check(lib.mf_nn_create(g, len(channels), ch, seed, C.byref(h)))
+        self._h = h
+        self.grid, self.channels = tuple(grid), list(channels)
+        n = C.c_int64()
+        check(lib.mf_nn_params(h, None, None, C.byref(n)))
+        self.n_params = n.value
+        self._np = np
+        self._bound = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.mf_nn_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def get_params(self):
+        out = self._np.zeros(self.n_params, self._np.float32)
+        check(load().mf_nn_params(self._h, out.ctypes.data_as(C.c_void_p), None, None))
+        return out
+
+    def set_params(self, values):
+        v = self._np.ascontiguousarray(values, dtype=self._np.float32)
+        assert v.size == self.n_params
+        check(load().mf_nn_params(self._h, None, v.ctypes.data_as(C.c_void_p), None))
+
+    def set_system(self, row_ptr, col_idx, values, dirichlet=None, stream=None):
+        A = _CSR(int(values.shape[0]) if False else int(self._np.prod(self.grid)), _ptr_any(row_ptr),
+                 _ptr_any(col_idx), _ptr(values))
+        check(load().mf_nn_set_system(self._h, C.byref(A), _ptr(dirichlet), _stream(stream)))
+        self._bound = (row_ptr, col_idx, values, dirichlet)
+
+    def apply(self, r, z=None, stream=None):
+        import torch
+        if z is None:
+            z = torch.empty_like(r)
+        check(load().mf_nn_apply(self._h, _ptr(r), _ptr(z), _stream(stream)))
+        return z
+
+    def train_step(self, r, lr, e=None, stream=None):
+        loss = C.c_double()
+        check(load().mf_nn_train_step(self._h, _ptr(r), _ptr(e), lr, C.byref(loss), None, _stream(stream)))
+        return loss.value
+
+    def grad(self, r, e=None, stream=None):
+        loss = C.c_double()
+        g = self._np.zeros(self.n_params, self._np.float32)
+        check(load().mf_nn_train_step(self._h, _ptr(r), _ptr(e), 0.0, C.byref(loss), g.ctypes.data_as(C.c_void_p),
+                                      _stream(stream)))
+        return loss.value, g
+
+    def save(self, path):
+        import json
+        self._np.save(path + ".npy", self.get_params())
+        with open(path + ".json", "w") as f:
+            json.dump({"grid": self.grid, "channels": self.channels, "n_params": self.n_params}, f)
+
+    def load_params(self, path):
+        self.set_params(self._np.load(path + ".npy"))
+
+
 def pcg(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PRECOND_JACOBI, net=None,
         check_every=8, use_graph=True, stream=None, raise_on_fail=True):
     """Solve K x = b (FP64 CSR on the device; row_ptr/col_idx int32) by PCG from x0 = 0.
@@ -339,6 +421,16 @@ def pcg(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PREC
     if st != OK and raise_on_fail:
         raise MFError(st, lib.mf_last_error().decode())
     return x, out
+
+
+def spmv(row_ptr, col_idx, values, x, y=None, stream=None):
+    """y = K x for an FP64 CSR matrix on the device."""
+    import torch
+    if y is None:
+        y = torch.empty_like(x)
+    A = _CSR(int(x.shape[0]), _ptr_any(row_ptr), _ptr_any(col_idx), _ptr(values))
+    check(load().mf_spmv(C.byref(A), _ptr(x), _ptr(y), _stream(stream)))
+    return y
 
 
 def _ptr_any(t):

@@ -258,5 +258,12 @@ mf_status mf_pcg(const mf_csr* A, const double* b, double* x, const mf_pcg_opts*
     return run_pcg(a, res);
 }
 
-}  // extern "C"
+mf_status mf_spmv(const mf_csr* A, const double* x, double* y, void* stream)
+{
+    if (!A) return set_error(MF_ERR_ARG, "A is NULL");
+    if (A->n_rows > 0 && (!A->row_ptr || !A->col_idx || !A->values || !x || !y))
+        return set_error(MF_ERR_ARG, "NULL matrix or vector");
+    return run_spmv(A, x, y, (hipStream_t)stream);
+}
 
+}  // extern "C"

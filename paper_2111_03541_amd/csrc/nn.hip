@@ -1,10 +1,764 @@
-// Learned preconditioner (placeholder until the network kernels land).
+// Learned preconditioner for PCG on structured-grid systems: a small linear multilevel
+// 3D convolution network, with inference and training kernels written here.  BF16
+// storage for weights and activations, FP32 accumulation, FP64 at the PCG boundary.
+//
+//   z = s * Dm^-1/2 * N(v),   v = Dm^-1/2 r / s,   s = max |Dm^-1/2 r|,   Dm = diag(K)
+//   N(v) = y_0 + P(y_1 + P(y_2 + ... ))
+//   y_0 = conv(v)  (1 -> 1);   y_l = conv(conv(conv(R^l v)))  (1 -> c_l -> c_l -> 1)
+//   R: full weighting from a (2n-1)-node grid to an n-node grid; P = R^T (trilinear).
+//   3x3x3 convolutions, zero padding, no bias (N is linear in v).  z = 0 on Dirichlet rows.
+// Training loss for a residual r: |K z - r|^2 / |r|^2, minimised by Adam; the gradient
+// is the adjoint of the linear network (weight gradients only, v does not depend on the
+// parameters).  Convolutions have at most 8 channels here, so they are bandwidth-bound
+// and run on the vector units; no MFMA is used in this file.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
 #include "mf_internal.h"
 #include "pcg.h"
 
 namespace mf {
-mf_status nn_bind_pcg(const mf_nn_t*, int64_t, PcgArgs*)
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxLevels = 6;
+constexpr int kMaxC = 8;
+constexpr int kChunk = 8192;  // points per wgrad block
+
+typedef uint16_t bf16;
+
+__device__ __forceinline__ float bf2f(bf16 v) { return __uint_as_float((uint32_t)v << 16); }
+__device__ __forceinline__ bf16 f2bf(float f)
 {
-    return set_error(MF_ERR_UNSUPPORTED, "learned preconditioner not built");
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (bf16)(u >> 16);
+}
+template <typename T>
+__device__ __forceinline__ float ld(const T* p, int64_t i);
+template <>
+__device__ __forceinline__ float ld<bf16>(const bf16* p, int64_t i) { return bf2f(p[i]); }
+template <>
+__device__ __forceinline__ float ld<float>(const float* p, int64_t i) { return p[i]; }
+template <typename T>
+__device__ __forceinline__ void st(T* p, int64_t i, float v);
+template <>
+__device__ __forceinline__ void st<bf16>(bf16* p, int64_t i, float v) { p[i] = f2bf(v); }
+template <>
+__device__ __forceinline__ void st<float>(float* p, int64_t i, float v) { p[i] = v; }
+
+struct Grid {
+    int nx, ny, nz;
+    __host__ __device__ int64_t n() const { return (int64_t)nx * ny * nz; }
+};
+
+// ---------------- transfer operators ----------------
+
+// coarse(i,j,k) = sum over d in {-1,0,1}^3 of prod 0.5^|d| * fine(2i+dx, 2j+dy, 2k+dz)
+template <typename TI, typename TO>
+__global__ void k_restrict(const TI* __restrict__ f, Grid gf, TO* __restrict__ c, Grid gc)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= gc.n()) return;
+    const int i = (int)(t % gc.nx), j = (int)((t / gc.nx) % gc.ny), k = (int)(t / ((int64_t)gc.nx * gc.ny));
+    float s = 0.f;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int z = 2 * k + dz;
+        if (z < 0 || z >= gf.nz) continue;
+        const float wz = dz ? 0.5f : 1.f;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int y = 2 * j + dy;
+            if (y < 0 || y >= gf.ny) continue;
+            const float wy = wz * (dy ? 0.5f : 1.f);
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int x = 2 * i + dx;
+                if (x < 0 || x >= gf.nx) continue;
+                s += wy * (dx ? 0.5f : 1.f) * ld(f, x + (int64_t)gf.nx * (y + (int64_t)gf.ny * z));
+            }
+        }
+    }
+    st(c, t, s);
+}
+
+// out(fine) = y(fine) + (P c)(fine), trilinear interpolation from the coarse grid
+__global__ void k_prolong_add(const float* __restrict__ c, Grid gc, const float* __restrict__ y, float* __restrict__ out,
+                              Grid gf)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= gf.n()) return;
+    const int x = (int)(t % gf.nx), yy = (int)((t / gf.nx) % gf.ny), z = (int)(t / ((int64_t)gf.nx * gf.ny));
+    const int x0 = x >> 1, x1 = (x + 1) >> 1, y0 = yy >> 1, y1 = (yy + 1) >> 1, z0 = z >> 1, z1 = (z + 1) >> 1;
+    auto C = [&](int a, int b, int d) { return c[a + (int64_t)gc.nx * (b + (int64_t)gc.ny * d)]; };
+    const float v = 0.125f * (C(x0, y0, z0) + C(x1, y0, z0) + C(x0, y1, z0) + C(x1, y1, z0) + C(x0, y0, z1) +
+                              C(x1, y0, z1) + C(x0, y1, z1) + C(x1, y1, z1));
+    out[t] = (y ? y[t] : 0.f) + v;
+}
+
+// ---------------- convolution ----------------
+
+// out[co][p] = sum_ci sum_t w[co][ci][t] in[ci][p + d_t]   (forward)
+// dgrad: out[ci][p] = sum_co sum_t w[co][ci][t] in[co][p - d_t]  (transpose = true)
+// Weights are FP32 copies of the BF16-rounded parameters.
+template <int CIN, int COUT, bool TRANS, typename TI, typename TO>
+__global__ void __launch_bounds__(kThreads) k_conv(const TI* __restrict__ in, const float* __restrict__ w,
+                                                   TO* __restrict__ out, Grid g)
+{
+    const int64_t n = g.n();
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int x = (int)(t % g.nx), y = (int)((t / g.nx) % g.ny), z = (int)(t / ((int64_t)g.nx * g.ny));
+    float acc[COUT];
+#pragma unroll
+    for (int o = 0; o < COUT; ++o) acc[o] = 0.f;
+#pragma unroll
+    for (int tap = 0; tap < 27; ++tap) {
+        const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+        const int sx = TRANS ? x - dx : x + dx, sy = TRANS ? y - dy : y + dy, sz = TRANS ? z - dz : z + dz;
+        if (sx < 0 || sx >= g.nx || sy < 0 || sy >= g.ny || sz < 0 || sz >= g.nz) continue;
+        const int64_t q = sx + (int64_t)g.nx * (sy + (int64_t)g.ny * sz);
+#pragma unroll
+        for (int i = 0; i < CIN; ++i) {
+            const float xv = ld(in, (int64_t)i * n + q);
+#pragma unroll
+            for (int o = 0; o < COUT; ++o) {
+                // forward weight index [o][i][tap]; transpose: input channel i is the
+                // forward output channel, output channel o the forward input channel
+                const float wv = TRANS ? w[(i * COUT + o) * 27 + tap] : w[(o * CIN + i) * 27 + tap];
+                acc[o] = fmaf(wv, xv, acc[o]);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < COUT; ++o) st(out, (int64_t)o * n + t, acc[o]);
+}
+
+// partial[(o*CIN + i)*27 + tap][chunk] = sum over the chunk of gy[o][p] * x[i][p + d_tap]
+template <typename TX>
+__global__ void __launch_bounds__(kThreads) k_wgrad(const TX* __restrict__ x, const float* __restrict__ gy, int cin,
+                                                    int cout, Grid g, float* __restrict__ partial, int nchunks)
+{
+    __shared__ float sh[kThreads / 64][27];
+    const int pair = blockIdx.y;  // o * cin + i
+    const int o = pair / cin, i = pair % cin;
+    const int chunk = blockIdx.x;
+    const int64_t n = g.n();
+    float acc[27];
+#pragma unroll
+    for (int tap = 0; tap < 27; ++tap) acc[tap] = 0.f;
+    const int64_t p0 = (int64_t)chunk * kChunk;
+    const int64_t p1 = p0 + kChunk < n ? p0 + kChunk : n;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += kThreads) {
+        const float gv = gy[(int64_t)o * n + p];
+        const int xx = (int)(p % g.nx), yy = (int)((p / g.nx) % g.ny), zz = (int)(p / ((int64_t)g.nx * g.ny));
+#pragma unroll
+        for (int tap = 0; tap < 27; ++tap) {
+            const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+            const int sx = xx + dx, sy = yy + dy, sz = zz + dz;
+            if (sx < 0 || sx >= g.nx || sy < 0 || sy >= g.ny || sz < 0 || sz >= g.nz) continue;
+            acc[tap] = fmaf(gv, ld(x, (int64_t)i * n + sx + (int64_t)g.nx * (sy + (int64_t)g.ny * sz)), acc[tap]);
+        }
+    }
+    const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+#pragma unroll
+    for (int tap = 0; tap < 27; ++tap) {
+        float v = acc[tap];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (ln == 0) sh[wv][tap] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 27) {
+        float s = 0.f;
+        for (int k = 0; k < kThreads / 64; ++k) s += sh[k][threadIdx.x];
+        partial[((int64_t)pair * 27 + threadIdx.x) * nchunks + chunk] = s;
+    }
+}
+
+// grad[off + j] = sum over chunks of partial[j][chunk]   (fixed order)
+__global__ void k_wgrad_reduce(const float* __restrict__ partial, int n_w, int nchunks, float* __restrict__ grad)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_w) return;
+    float s = 0.f;
+    for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)j * nchunks + c];
+    grad[j] = s;
+}
+
+// ---------------- scaling, loss, optimiser ----------------
+
+__global__ void k_diag_scale(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                             const double* __restrict__ v, int64_t n, const uint8_t* __restrict__ mask,
+                             float* __restrict__ dm, uint8_t* __restrict__ m_out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+        if (ci[k] == i) d = v[k];
+    dm[i] = d > 0.0 ? (float)(1.0 / sqrt(d)) : 0.f;
+    m_out[i] = mask ? mask[i] : 0;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// partial[b] = max over the block of |dm * r|
+__global__ void k_absmax(const double* __restrict__ r, const float* __restrict__ dm, int64_t n, float* __restrict__ partial)
+{
+    __shared__ float sh[kThreads / 64];
+    float m = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf((float)r[i] * dm[i]));
+    m = wave_max(m);
+    if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.f;
+        for (int k = 0; k < kThreads / 64; ++k) s = fmaxf(s, sh[k]);
+        partial[blockIdx.x] = s;
+    }
+}
+
+__global__ void k_absmax_final(const float* __restrict__ partial, int nb, float* __restrict__ s)
+{
+    __shared__ float sh[kThreads / 64];
+    float m = 0.f;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) m = fmaxf(m, partial[k]);
+    m = wave_max(m);
+    if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float v = 0.f;
+        for (int k = 0; k < kThreads / 64; ++k) v = fmaxf(v, sh[k]);
+        *s = v > 0.f ? v : 1.f;
+    }
+}
+
+__global__ void k_input(const double* __restrict__ r, const float* __restrict__ dm, const float* __restrict__ s,
+                        int64_t n, bf16* __restrict__ v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = f2bf((float)r[i] * dm[i] / *s);
+}
+
+__global__ void k_output(const float* __restrict__ acc, const float* __restrict__ dm, const float* __restrict__ s,
+                         const uint8_t* __restrict__ mask, int64_t n, double* __restrict__ z)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = mask[i] ? 0.0 : (double)(*s) * (double)dm[i] * (double)acc[i];
+}
+
+// y = K x (FP64 CSR, one row per thread); partial sums of |y - r|^2 and |r|^2
+__global__ void k_residual(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const double* __restrict__ v, int64_t n, const double* __restrict__ x,
+                           const double* __restrict__ r, double* __restrict__ res, double* __restrict__ partial)
+{
+    __shared__ double sh[2][kThreads / 64];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) s = fma(v[k], x[ci[k]], s);
+        const double e = s - r[i];
+        res[i] = e;
+        a = fma(e, e, a);
+        b = fma(r[i], r[i], b);
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (threadIdx.x % 64 == 0) {
+        sh[0][threadIdx.x / 64] = a;
+        sh[1][threadIdx.x / 64] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0, s1 = 0;
+        for (int k = 0; k < kThreads / 64; ++k) {
+            s0 += sh[0][k];
+            s1 += sh[1][k];
+        }
+        partial[2 * blockIdx.x] = s0;
+        partial[2 * blockIdx.x + 1] = s1;
+    }
+}
+
+// energy loss pieces: res = K z - r; partial sums of res.(z - e) and r.e
+__global__ void k_residual_energy(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                  const double* __restrict__ v, int64_t n, const double* __restrict__ z,
+                                  const double* __restrict__ r, const double* __restrict__ e,
+                                  double* __restrict__ res, double* __restrict__ partial)
+{
+    __shared__ double sh[2][kThreads / 64];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) s = fma(v[k], z[ci[k]], s);
+        const double q = s - r[i];
+        res[i] = q;
+        a = fma(q, z[i] - e[i], a);
+        b = fma(r[i], e[i], b);
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (threadIdx.x % 64 == 0) {
+        sh[0][threadIdx.x / 64] = a;
+        sh[1][threadIdx.x / 64] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0, s1 = 0;
+        for (int k = 0; k < kThreads / 64; ++k) {
+            s0 += sh[0][k];
+            s1 += sh[1][k];
+        }
+        partial[2 * blockIdx.x] = s0;
+        partial[2 * blockIdx.x + 1] = s1;
+    }
+}
+
+// energy loss gradient: dL/dz = 2 (K z - r) / (r.e), scaled into the network output
+__global__ void k_out_grad_energy(const double* __restrict__ res, int64_t n, const double* __restrict__ sums,
+                                  const float* __restrict__ dm, const float* __restrict__ s,
+                                  const uint8_t* __restrict__ mask, float* __restrict__ g)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double gz = mask[i] ? 0.0 : 2.0 * res[i] / sums[1];
+    g[i] = (float)((double)(*s) * (double)dm[i] * gz);
+}
+
+__global__ void k_loss_final(const double* __restrict__ partial, int nb, double* __restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a = 0, b = 0;
+    for (int k = 0; k < nb; ++k) {
+        a += partial[2 * k];
+        b += partial[2 * k + 1];
+    }
+    out[0] = a;
+    out[1] = b;
+    out[2] = b > 0 ? a / b : 0.0;
+}
+
+// gacc = s * dm * (2 K res / |r|^2), zero on Dirichlet rows (K symmetric)
+__global__ void k_out_grad(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const double* __restrict__ v, int64_t n, const double* __restrict__ res,
+                           const double* __restrict__ sums, const float* __restrict__ dm,
+                           const float* __restrict__ s, const uint8_t* __restrict__ mask, float* __restrict__ g)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double t = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) t = fma(v[k], res[ci[k]], t);
+    const double gz = mask[i] ? 0.0 : 2.0 * t / sums[1];
+    g[i] = (float)((double)(*s) * (double)dm[i] * gz);
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ vv,
+                       int n, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    m[i] = b1 * m[i] + (1.f - b1) * gi;
+    vv[i] = b2 * vv[i] + (1.f - b2) * gi * gi;
+    p[i] -= lr * (m[i] / c1) / (sqrtf(vv[i] / c2) + eps);
+}
+
+// BF16-rounded FP32 copy of the parameters used by the forward pass
+__global__ void k_round_bf16(const float* __restrict__ p, float* __restrict__ q, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) q[i] = bf2f(f2bf(p[i]));
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+}  // namespace mf
+
+// ------------------------------------------------------------------------------------
+// Host object
+// ------------------------------------------------------------------------------------
+struct mf_nn_s {
+    int L = 0;
+    int ch[mf::kMaxLevels] = {0};
+    mf::Grid g[mf::kMaxLevels];
+    int64_t n0 = 0;
+    int n_params = 0;
+    int w_off[3 * mf::kMaxLevels + 1] = {0};  // parameter offsets of conv tensors
+    float* p = nullptr;      // master FP32
+    float* pb = nullptr;     // BF16-rounded FP32 copy
+    float* grad = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    int step = 0;
+    // activations
+    mf::bf16* vin[mf::kMaxLevels] = {nullptr};
+    mf::bf16* h1[mf::kMaxLevels] = {nullptr};
+    mf::bf16* h2[mf::kMaxLevels] = {nullptr};
+    float* y[mf::kMaxLevels] = {nullptr};
+    float* acc[mf::kMaxLevels] = {nullptr};
+    float* gy[mf::kMaxLevels] = {nullptr};
+    float* g1[mf::kMaxLevels] = {nullptr};
+    float* g2[mf::kMaxLevels] = {nullptr};
+    float* wpart = nullptr;
+    int64_t wpart_n = 0;
+    // system binding
+    const int32_t* rp = nullptr;
+    const int32_t* ci = nullptr;
+    const double* kv = nullptr;
+    float* dm = nullptr;
+    uint8_t* mask = nullptr;
+    float* s = nullptr;
+    float* maxpart = nullptr;
+    double* zbuf = nullptr;
+    double* res = nullptr;
+    double* lpart = nullptr;
+    double* sums = nullptr;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+using namespace mf;
+
+template <typename T>
+mf_status nn_alloc(mf_nn_s* N, T** p, int64_t n)
+{
+    void* q = nullptr;
+    if (hipMalloc(&q, sizeof(T) * (size_t)(n > 0 ? n : 1)) != hipSuccess)
+        return set_error(MF_ERR_OOM, "learned preconditioner: device allocation failed");
+    N->allocs.push_back(q);
+    *p = (T*)q;
+    return MF_OK;
+}
+
+#define NN_TRY(x)                     \
+    do {                              \
+        mf_status st_ = (x);          \
+        if (st_ != MF_OK) return st_; \
+    } while (0)
+
+template <bool TRANS, typename TI, typename TO>
+mf_status conv_dispatch(int cin, int cout, const TI* in, const float* w, TO* out, Grid g, hipStream_t s)
+{
+#define MF_CONV(CI, CO)                                                                         \
+    if (cin == CI && cout == CO) {                                                              \
+        k_conv<CI, CO, TRANS, TI, TO><<<nblk(g.n()), kThreads, 0, s>>>(in, w, out, g);          \
+        return MF_OK;                                                                           \
+    }
+    MF_CONV(1, 1)
+    MF_CONV(1, 2) MF_CONV(2, 2) MF_CONV(2, 1)
+    MF_CONV(1, 4) MF_CONV(4, 4) MF_CONV(4, 1)
+    MF_CONV(1, 8) MF_CONV(8, 8) MF_CONV(8, 1)
+#undef MF_CONV
+    return set_error(MF_ERR_UNSUPPORTED, "conv %d -> %d channels not instantiated", cin, cout);
+}
+
+// forward pass from r (FP64) to acc[0] (FP32)
+mf_status nn_forward(mf_nn_s* N, const double* r, hipStream_t s)
+{
+    const int64_t n = N->n0;
+    const unsigned nb = (unsigned)std::min<int64_t>(1024, nblk(n));
+    k_absmax<<<nb, kThreads, 0, s>>>(r, N->dm, n, N->maxpart);
+    k_absmax_final<<<1, kThreads, 0, s>>>(N->maxpart, nb, N->s);
+    k_input<<<nblk(n), kThreads, 0, s>>>(r, N->dm, N->s, n, N->vin[0]);
+    for (int l = 1; l < N->L; ++l)
+        k_restrict<bf16, bf16><<<nblk(N->g[l].n()), kThreads, 0, s>>>(N->vin[l - 1], N->g[l - 1], N->vin[l], N->g[l]);
+    NN_TRY((conv_dispatch<false, bf16, float>(1, 1, N->vin[0], N->pb + N->w_off[0], N->y[0], N->g[0], s)));
+    for (int l = 1; l < N->L; ++l) {
+        const int c = N->ch[l];
+        const int b = 1 + 3 * (l - 1);
+        NN_TRY((conv_dispatch<false, bf16, bf16>(1, c, N->vin[l], N->pb + N->w_off[b], N->h1[l], N->g[l], s)));
+        NN_TRY((conv_dispatch<false, bf16, bf16>(c, c, N->h1[l], N->pb + N->w_off[b + 1], N->h2[l], N->g[l], s)));
+        NN_TRY((conv_dispatch<false, bf16, float>(c, 1, N->h2[l], N->pb + N->w_off[b + 2], N->y[l], N->g[l], s)));
+    }
+    // acc_{L-1} = y_{L-1}; acc_l = y_l + P acc_{l+1}
+    for (int l = N->L - 2; l >= 0; --l) {
+        const float* coarse = (l == N->L - 2) ? N->y[l + 1] : N->acc[l + 1];
+        k_prolong_add<<<nblk(N->g[l].n()), kThreads, 0, s>>>(coarse, N->g[l + 1], N->y[l], N->acc[l], N->g[l]);
+    }
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+const float* nn_out(const mf_nn_s* N) { return N->L > 1 ? N->acc[0] : N->y[0]; }
+
+mf_status nn_apply_cb(void* ctx, const double* r, double* z, hipStream_t s)
+{
+    mf_nn_s* N = (mf_nn_s*)ctx;
+    NN_TRY(nn_forward(N, r, s));
+    k_output<<<nblk(N->n0), kThreads, 0, s>>>(nn_out(N), N->dm, N->s, N->mask, N->n0, z);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+// weight gradient of conv(x) -> gy into grad[off ...]
+template <typename TX>
+mf_status wgrad(mf_nn_s* N, const TX* x, const float* gy, int cin, int cout, Grid g, int off, hipStream_t s)
+{
+    const int nchunks = (int)((g.n() + kChunk - 1) / kChunk);
+    const int64_t need = (int64_t)cin * cout * 27 * nchunks;
+    if (need > N->wpart_n) return set_error(MF_ERR_ARG, "wgrad scratch too small");
+    k_wgrad<TX><<<dim3(nchunks, cin * cout), kThreads, 0, s>>>(x, gy, cin, cout, g, N->wpart, nchunks);
+    const int nw = cin * cout * 27;
+    k_wgrad_reduce<<<(nw + 255) / 256, 256, 0, s>>>(N->wpart, nw, nchunks, N->grad + off);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+void free_nn(mf_nn_s* N)
+{
+    if (!N) return;
+    for (void* p : N->allocs) (void)hipFree(p);
+    delete N;
+}
+
+uint64_t splitmix(uint64_t& x)
+{
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
+namespace mf {
+mf_status nn_bind_pcg(const mf_nn_t* net, int64_t n_rows, PcgArgs* a)
+{
+    if (!net->dm || !net->kv) return set_error(MF_ERR_ARG, "call mf_nn_set_system before mf_pcg");
+    if (n_rows != net->n0) return set_error(MF_ERR_ARG, "network grid has %lld nodes, system %lld rows",
+                                            (long long)net->n0, (long long)n_rows);
+    if (a->values != net->kv) return set_error(MF_ERR_ARG, "the network is bound to a different matrix");
+    a->precond = MF_PRECOND_EXTERNAL;
+    a->apply = nn_apply_cb;
+    a->apply_ctx = (void*)net;
+    a->apply_graph_safe = 1;
+    return MF_OK;
 }
 }  // namespace mf
+
+extern "C" {
+
+mf_status mf_nn_create(const int32_t* grid, int32_t levels, const int32_t* channels, uint64_t seed, mf_nn_t** out)
+{
+    if (!out) return set_error(MF_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!grid || !channels) return set_error(MF_ERR_ARG, "grid or channels is NULL");
+    if (levels < 1 || levels > kMaxLevels) return set_error(MF_ERR_ARG, "levels must be 1..%d", kMaxLevels);
+    if (channels[0] != 1) return set_error(MF_ERR_ARG, "channels[0] must be 1 (the level-0 stencil)");
+    mf_nn_s* N = new mf_nn_s();
+    N->L = levels;
+    N->g[0] = Grid{grid[0], grid[1], grid[2]};
+    for (int l = 0; l < levels; ++l) {
+        const int c = channels[l];
+        if (l > 0 && !(c == 1 || c == 2 || c == 4 || c == 8)) {
+            free_nn(N);
+            return set_error(MF_ERR_UNSUPPORTED, "level %d width %d (1, 2, 4 or 8)", l, c);
+        }
+        N->ch[l] = c;
+        if (l > 0) {
+            const Grid& f = N->g[l - 1];
+            if (f.nx % 2 == 0 || f.ny % 2 == 0 || f.nz % 2 == 0 || f.nx < 3 || f.ny < 3 || f.nz < 3) {
+                free_nn(N);
+                return set_error(MF_ERR_ARG, "grid %dx%dx%d cannot be coarsened (odd sizes >= 3)", f.nx, f.ny, f.nz);
+            }
+            N->g[l] = Grid{(f.nx + 1) / 2, (f.ny + 1) / 2, (f.nz + 1) / 2};
+        }
+    }
+    if (N->g[0].nx < 1 || N->g[0].ny < 1 || N->g[0].nz < 1) {
+        free_nn(N);
+        return set_error(MF_ERR_ARG, "empty grid");
+    }
+    N->n0 = N->g[0].n();
+    // parameter layout: level-0 conv (1x1x27), then per level (c,1) (c,c) (1,c) x 27
+    int off = 0, k = 0;
+    N->w_off[k++] = off;
+    off += 27;
+    for (int l = 1; l < levels; ++l) {
+        const int c = N->ch[l];
+        N->w_off[k++] = off;
+        off += c * 27;
+        N->w_off[k++] = off;
+        off += c * c * 27;
+        N->w_off[k++] = off;
+        off += c * 27;
+    }
+    N->n_params = off;
+    mf_status st = MF_OK;
+    auto A = [&](mf_status x) { if (st == MF_OK) st = x; };
+    A(nn_alloc(N, &N->p, off));
+    A(nn_alloc(N, &N->pb, off));
+    A(nn_alloc(N, &N->grad, off));
+    A(nn_alloc(N, &N->m, off));
+    A(nn_alloc(N, &N->v, off));
+    int64_t wp = 0;
+    for (int l = 0; l < levels; ++l) {
+        const int64_t n = N->g[l].n();
+        const int c = N->ch[l];
+        A(nn_alloc(N, &N->vin[l], n));
+        A(nn_alloc(N, &N->y[l], n));
+        A(nn_alloc(N, &N->acc[l], n));
+        A(nn_alloc(N, &N->gy[l], n));
+        if (l > 0) {
+            A(nn_alloc(N, &N->h1[l], n * c));
+            A(nn_alloc(N, &N->h2[l], n * c));
+            A(nn_alloc(N, &N->g1[l], n * c));
+            A(nn_alloc(N, &N->g2[l], n * c));
+        }
+        const int64_t chunks = (n + kChunk - 1) / kChunk;
+        wp = std::max<int64_t>(wp, (int64_t)std::max(c, 1) * std::max(c, 1) * 27 * chunks);
+    }
+    N->wpart_n = wp;
+    A(nn_alloc(N, &N->wpart, wp));
+    A(nn_alloc(N, &N->dm, N->n0));
+    A(nn_alloc(N, &N->mask, N->n0));
+    A(nn_alloc(N, &N->s, 1));
+    A(nn_alloc(N, &N->maxpart, 1024));
+    A(nn_alloc(N, &N->zbuf, N->n0));
+    A(nn_alloc(N, &N->res, N->n0));
+    A(nn_alloc(N, &N->lpart, 2 * 1024));
+    A(nn_alloc(N, &N->sums, 4));
+    if (st != MF_OK) {
+        free_nn(N);
+        return st;
+    }
+    // initial parameters: level-0 stencil = identity (the network starts as Jacobi),
+    // other weights small Gaussian (splitmix64 + Box-Muller), Adam state zero
+    std::vector<float> h(off, 0.f);
+    uint64_t x = seed;
+    for (int i = 27; i < off; ++i) {
+        double u1 = ((splitmix(x) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        double u2 = ((splitmix(x) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        h[i] = (float)(0.02 * std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2));
+    }
+    h[13] = 1.f;
+    std::vector<float> zero(off, 0.f);
+    if (hipMemcpy(N->p, h.data(), sizeof(float) * off, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(N->m, zero.data(), sizeof(float) * off, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(N->v, zero.data(), sizeof(float) * off, hipMemcpyHostToDevice) != hipSuccess) {
+        free_nn(N);
+        return set_error(MF_ERR_HIP, "parameter upload failed");
+    }
+    k_round_bf16<<<(off + 255) / 256, 256>>>(N->p, N->pb, off);
+    if (hipDeviceSynchronize() != hipSuccess) {
+        free_nn(N);
+        return set_error(MF_ERR_HIP, "parameter rounding failed");
+    }
+    *out = N;
+    return MF_OK;
+}
+
+mf_status mf_nn_params(mf_nn_t* N, float* get, const float* set, int64_t* n_params)
+{
+    if (!N) return set_error(MF_ERR_ARG, "network is NULL");
+    if (n_params) *n_params = N->n_params;
+    if (get) MF_HIP(hipMemcpy(get, N->p, sizeof(float) * N->n_params, hipMemcpyDeviceToHost));
+    if (set) {
+        MF_HIP(hipMemcpy(N->p, set, sizeof(float) * N->n_params, hipMemcpyHostToDevice));
+        std::vector<float> zero(N->n_params, 0.f);
+        MF_HIP(hipMemcpy(N->m, zero.data(), sizeof(float) * N->n_params, hipMemcpyHostToDevice));
+        MF_HIP(hipMemcpy(N->v, zero.data(), sizeof(float) * N->n_params, hipMemcpyHostToDevice));
+        N->step = 0;
+        k_round_bf16<<<(N->n_params + 255) / 256, 256>>>(N->p, N->pb, N->n_params);
+        MF_HIP(hipDeviceSynchronize());
+    }
+    return MF_OK;
+}
+
+mf_status mf_nn_set_system(mf_nn_t* N, const mf_csr* K, const uint8_t* dirichlet, void* stream)
+{
+    if (!N || !K) return set_error(MF_ERR_ARG, "network or matrix is NULL");
+    if (K->n_rows != N->n0) return set_error(MF_ERR_ARG, "matrix has %lld rows, network grid %lld nodes",
+                                             (long long)K->n_rows, (long long)N->n0);
+    hipStream_t s = (hipStream_t)stream;
+    N->rp = K->row_ptr;
+    N->ci = K->col_idx;
+    N->kv = K->values;
+    k_diag_scale<<<nblk(N->n0), kThreads, 0, s>>>(K->row_ptr, K->col_idx, K->values, N->n0, dirichlet, N->dm, N->mask);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+mf_status mf_nn_apply(mf_nn_t* N, const double* r, double* z, void* stream)
+{
+    if (!N || !r || !z) return set_error(MF_ERR_ARG, "NULL argument");
+    if (!N->kv) return set_error(MF_ERR_ARG, "call mf_nn_set_system first");
+    return nn_apply_cb(N, r, z, (hipStream_t)stream);
+}
+
+mf_status mf_nn_train_step(mf_nn_t* N, const double* r, const double* e, double lr, double* loss, float* grad_out,
+                           void* stream)
+{
+    if (!N || !r) return set_error(MF_ERR_ARG, "NULL argument");
+    if (!N->kv) return set_error(MF_ERR_ARG, "call mf_nn_set_system first");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = N->n0;
+    NN_TRY(nn_forward(N, r, s));
+    k_output<<<nblk(n), kThreads, 0, s>>>(nn_out(N), N->dm, N->s, N->mask, n, N->zbuf);
+    const unsigned nb = (unsigned)std::min<int64_t>(1024, nblk(n));
+    if (e) {
+        k_residual_energy<<<nb, kThreads, 0, s>>>(N->rp, N->ci, N->kv, n, N->zbuf, r, e, N->res, N->lpart);
+        k_loss_final<<<1, 64, 0, s>>>(N->lpart, nb, N->sums);
+        k_out_grad_energy<<<nblk(n), kThreads, 0, s>>>(N->res, n, N->sums, N->dm, N->s, N->mask, N->gy[0]);
+    } else {
+        k_residual<<<nb, kThreads, 0, s>>>(N->rp, N->ci, N->kv, n, N->zbuf, r, N->res, N->lpart);
+        k_loss_final<<<1, 64, 0, s>>>(N->lpart, nb, N->sums);
+        k_out_grad<<<nblk(n), kThreads, 0, s>>>(N->rp, N->ci, N->kv, n, N->res, N->sums, N->dm, N->s, N->mask,
+                                                N->gy[0]);
+    }
+    for (int l = 1; l < N->L; ++l)
+        k_restrict<float, float><<<nblk(N->g[l].n()), kThreads, 0, s>>>(N->gy[l - 1], N->g[l - 1], N->gy[l], N->g[l]);
+    NN_TRY(wgrad<bf16>(N, N->vin[0], N->gy[0], 1, 1, N->g[0], N->w_off[0], s));
+    for (int l = 1; l < N->L; ++l) {
+        const int c = N->ch[l];
+        const int b = 1 + 3 * (l - 1);
+        NN_TRY(wgrad<bf16>(N, N->h2[l], N->gy[l], c, 1, N->g[l], N->w_off[b + 2], s));
+        NN_TRY((conv_dispatch<true, float, float>(1, c, N->gy[l], N->pb + N->w_off[b + 2], N->g2[l], N->g[l], s)));
+        NN_TRY(wgrad<bf16>(N, N->h1[l], N->g2[l], c, c, N->g[l], N->w_off[b + 1], s));
+        NN_TRY((conv_dispatch<true, float, float>(c, c, N->g2[l], N->pb + N->w_off[b + 1], N->g1[l], N->g[l], s)));
+        NN_TRY(wgrad<bf16>(N, N->vin[l], N->g1[l], 1, c, N->g[l], N->w_off[b], s));
+    }
+    double h[3] = {0, 0, 0};
+    MF_HIP(hipMemcpyAsync(h, N->sums, sizeof(h), hipMemcpyDeviceToHost, s));
+    if (grad_out) MF_HIP(hipMemcpyAsync(grad_out, N->grad, sizeof(float) * N->n_params, hipMemcpyDeviceToHost, s));
+    MF_HIP(hipStreamSynchronize(s));
+    if (loss) *loss = h[2];
+    if (!std::isfinite(h[2])) return set_error(MF_ERR_NONFINITE, "non-finite training loss");
+    if (!grad_out && lr > 0.0) {
+        N->step += 1;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = 1.f - std::pow(b1, (float)N->step), c2 = 1.f - std::pow(b2, (float)N->step);
+        k_adam<<<(N->n_params + 255) / 256, 256, 0, s>>>(N->p, N->grad, N->m, N->v, N->n_params, (float)lr, b1, b2,
+                                                        1e-8f, c1, c2);
+        k_round_bf16<<<(N->n_params + 255) / 256, 256, 0, s>>>(N->p, N->pb, N->n_params);
+        MF_HIP(hipGetLastError());
+    }
+    return MF_OK;
+}
+
+void mf_nn_destroy(mf_nn_t* N)
+{
+    if (!N) return;
+    (void)hipDeviceSynchronize();
+    free_nn(N);
+}
+
+}  // extern "C"

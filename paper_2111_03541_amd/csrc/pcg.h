@@ -33,5 +33,6 @@ struct PcgArgs {
 };
 
 mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res);
+mf_status run_spmv(const mf_csr* A, const double* x, double* y, hipStream_t s);
 
 }  // namespace mf

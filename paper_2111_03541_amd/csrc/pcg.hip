@@ -273,6 +273,16 @@ __global__ void k_set(double* p, int n, double v)
 
 }  // namespace
 
+mf_status run_spmv(const mf_csr* A, const double* x, double* y, hipStream_t s)
+{
+    const int n = (int)A->n_rows;
+    if (n == 0) return MF_OK;
+    const int blocks = (int)std::min<int64_t>(kMaxBlocks, (n + (kThreads / kLanesPerRow) - 1) / (kThreads / kLanesPerRow));
+    k_spmv_dot<<<blocks, kThreads, 0, s>>>(n, A->row_ptr, A->col_idx, A->values, x, y, nullptr, nullptr, 0);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
 mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
 {
     const int n = (int)a.n;

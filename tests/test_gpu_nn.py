@@ -1,0 +1,112 @@
+"""Learned preconditioner kernels (BF16 inference and training) against the numpy oracle,
+and flexible PCG with the network through mf_pcg."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.nn_ref as NR
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def bf16(a):
+    """Round to the nearest bfloat16 (ties to even), returned as float64."""
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def system(n, seed):
+    mesh = W.structured_mesh((n, n, n))
+    rng = np.random.default_rng(seed)
+    k = W.grf_lognormal_elem((n, n, n), float(rng.uniform(1, 2)), 0.1, seed + 1)
+    f = W.uniform_nodal(1, mesh.n_nodes, 0, 1, seed + 2)
+    mask = W.boundary_node_mask(mesh.shape)
+    pat = O.Pattern(mesh, 1)
+    K, d = O.assemble(pat, O.POISSON, {"coef": 1.0}, elem_param=k, nodal_src=f, dirichlet=mask)
+    return pat, K, d, mask
+
+
+def bind(mf, net, pat, K, mask):
+    rp = torch.from_numpy(pat.row_ptr.astype(np.int32)).cuda()
+    ci = torch.from_numpy(pat.col_idx).cuda()
+    v = torch.from_numpy(K).cuda()
+    m = torch.from_numpy(mask).cuda()
+    net.set_system(rp, ci, v, m)
+    return rp, ci, v, m
+
+
+CH = [1, 4, 8, 8]
+
+
+def test_forward_matches_oracle(mf):
+    say("nn forward 17^3")
+    pat, K, d, mask = system(16, 7)
+    net = mf.Net((17, 17, 17), CH, seed=3)
+    theta = NR.init_params(CH, 11).astype(np.float32)
+    net.set_params(theta)
+    bind(mf, net, pat, K, mask)
+    rng = np.random.default_rng(5)
+    r = np.where(mask != 0, 0.0, rng.standard_normal(pat.n_rows))
+    z = net.apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    ref = NR.Net((17, 17, 17), CH).forward(bf16(theta), r, pat.to_scipy(K).diagonal(), mask)
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    say(f"  forward rel err {err:.2e}")
+    assert err < 2e-2
+    # linear in r (the input scale cancels)
+    z2 = net.apply(torch.from_numpy(-3.0 * r).cuda()).cpu().numpy()
+    assert np.linalg.norm(z2 + 3.0 * z) <= 1e-5 * np.linalg.norm(z)
+
+
+def test_gradient_matches_oracle(mf):
+    say("nn gradient 17^3")
+    pat, K, d, mask = system(16, 9)
+    net = mf.Net((17, 17, 17), CH, seed=3)
+    theta = NR.init_params(CH, 12).astype(np.float32)
+    net.set_params(theta)
+    bind(mf, net, pat, K, mask)
+    rng = np.random.default_rng(6)
+    r = np.where(mask != 0, 0.0, rng.standard_normal(pat.n_rows))
+    loss, g = net.grad(torch.from_numpy(r).cuda())
+    Lr, gr = NR.Net((17, 17, 17), CH).loss_and_grad(bf16(theta), r, pat.to_scipy(K).diagonal(),
+                                                     pat.to_scipy(K), mask)
+    say(f"  loss {loss:.6f} vs {Lr:.6f}; grad rel err {np.linalg.norm(g - gr) / np.linalg.norm(gr):.2e}")
+    assert abs(loss - Lr) <= 2e-2 * Lr
+    assert np.linalg.norm(g - gr) <= 5e-2 * np.linalg.norm(gr)
+    # per level, the gradient blocks point the same way
+    assert float(g @ gr) / (np.linalg.norm(g) * np.linalg.norm(gr)) > 0.998
+    # parameters are untouched by a gradient query
+    assert np.array_equal(net.get_params(), theta)
+
+
+def test_training_reduces_loss_and_pcg_converges(mf):
+    say("nn train + pcg 16^3")
+    pat, K, d, mask = system(16, 21)
+    net = mf.Net((17, 17, 17), CH, seed=4)
+    rp, ci, v, m = bind(mf, net, pat, K, mask)
+    rng = np.random.default_rng(8)
+    S = pat.to_scipy(K)
+    rs = [torch.from_numpy(S @ np.where(mask != 0, 0.0, rng.standard_normal(pat.n_rows))).cuda()
+          for _ in range(8)]
+    first = [net.grad(r)[0] for r in rs]
+    for it in range(150):
+        net.train_step(rs[it % len(rs)], 3e-3)
+    last = [net.grad(r)[0] for r in rs]
+    say(f"  loss {np.mean(first):.4f} -> {np.mean(last):.4f}")
+    assert np.mean(last) < 0.7 * np.mean(first)
+    b = torch.from_numpy(d).cuda()
+    x, res = mf.pcg(rp, ci, v, b, tol=1e-8, precond=mf.PRECOND_NN, net=net, check_every=1)
+    _, it_j, _ = O.pcg_jacobi(pat.row_ptr, pat.col_idx, K, d, tol=1e-8)
+    say(f"  nn-pcg {res}, jacobi {it_j}")
+    assert res["converged"] and res["true_relres"] <= 1e-8
+    xh = x.cpu().numpy()
+    assert np.linalg.norm(d - S @ xh) / np.linalg.norm(d) <= 1e-8
+    assert res["iterations"] < it_j

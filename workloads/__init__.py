@@ -139,13 +139,16 @@ def fourier_velocity(coords: np.ndarray, seed, modes: int = 8, kmax: int = 3) ->
 
 
 def grf_lognormal_elem(n, sigma: float, ell: float, seed) -> np.ndarray:
-    """Lognormal per-element field exp(sigma * g) on a structured unit-box mesh.
+    """Lognormal per-element field exp(sigma * g) on a structured unit-box mesh, with g
+    from grf_elem (unit-variance Gaussian field, covariance exp(-r^2 / (2 ell^2)))."""
+    return np.exp(sigma * grf_elem(n, ell, seed)).astype(np.float64)
 
-    g is a zero-mean, unit-variance Gaussian random field with covariance
-    exp(-r^2 / (2 ell^2)), sampled at element centroids by circulant embedding on a
-    grid padded to twice the mesh in every axis.  Element order follows the structured
-    element numbering (x fastest).
-    """
+
+def grf_elem(n, ell: float, seed) -> np.ndarray:
+    """Zero-mean, unit-variance Gaussian random field with covariance exp(-r^2/(2 ell^2)),
+    sampled at element centroids by circulant embedding on a grid padded to twice the
+    mesh in every axis.  Element order follows the structured numbering (x fastest).
+    Any unit-norm linear combination of independent draws is again such a field."""
     n = tuple(int(v) for v in n)
     dim = len(n)
     rng = np.random.default_rng(seed)
@@ -166,7 +169,47 @@ def grf_lognormal_elem(n, sigma: float, ell: float, seed) -> np.ndarray:
     field = np.fft.ifftn(np.sqrt(lam) * noise) * np.sqrt(np.prod(m))
     g = np.real(field)[tuple(slice(0, v) for v in n)]
     # element id = ex + nx(ey + ny ez): index [ex, ey, ez] raveled in Fortran order
-    return np.exp(sigma * g.ravel(order="F")).astype(np.float64)
+    return g.ravel(order="F").astype(np.float64)
+
+
+def upsample_nodes(c: np.ndarray) -> np.ndarray:
+    """Piecewise-linear upsampling of a node field [nz, ny, nx] to [2nz-1, 2ny-1, 2nx-1]."""
+    f = c
+    for ax in range(3):
+        n = f.shape[ax]
+        shp = list(f.shape)
+        shp[ax] = 2 * n - 1
+        g = np.empty(shp)
+        ev = [slice(None)] * 3
+        ev[ax] = slice(0, None, 2)
+        od = [slice(None)] * 3
+        od[ax] = slice(1, None, 2)
+        lo = [slice(None)] * 3
+        lo[ax] = slice(0, n - 1)
+        hi = [slice(None)] * 3
+        hi[ax] = slice(1, n)
+        g[tuple(ev)] = f
+        g[tuple(od)] = 0.5 * (f[tuple(lo)] + f[tuple(hi)])
+        f = g
+    return f
+
+
+def multiscale_nodal(n_nodes_axis: int, levels: int, seed) -> np.ndarray:
+    """Random node field on an (n x n x n)-node grid with comparable energy at every scale:
+    white noise drawn on the grid coarsened 0..levels-1 times, amplitude 2^l at level l,
+    upsampled to the fine grid and summed.  Node id = x + n(y + n z)."""
+    rng = np.random.default_rng(seed)
+    sizes = [n_nodes_axis]
+    for _ in range(levels - 1):
+        sizes.append((sizes[-1] + 1) // 2)
+    out = np.zeros((n_nodes_axis,) * 3)
+    for l in range(levels - 1, -1, -1):
+        w = rng.standard_normal((sizes[l],) * 3) * (2.0 ** l)
+        acc = w if l == levels - 1 else w + acc_up
+        acc_up = upsample_nodes(acc) if l > 0 else None
+        if l == 0:
+            out = acc
+    return out.reshape(-1)
 
 
 def boundary_node_mask(n) -> np.ndarray:
