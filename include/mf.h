@@ -254,7 +254,7 @@ mf_status mf_spmv(const mf_csr* A, const double* x, double* y, void* stream);
  * Learned preconditioner for mf_pcg on structured-grid scalar systems (node id
  * x + nx (y + ny z), one DOF per node).  A small linear multilevel 3D convolution network
  * applied to the diagonally scaled residual:
- *   z = s Dm^-1/2 N(v),  v = Dm^-1/2 r / s,  s = max|Dm^-1/2 r|,  Dm = diag(K),
+ *   z = Dm^-1/2 N(v),  v = Dm^-1/2 r,  Dm = diag(K),
  *   N(v) = y_0 + P(y_1 + P(y_2 + ...)),  y_0 = conv(v) (1->1 channel),
  *   y_l = conv(conv(conv(R^l v))) (1 -> c_l -> c_l -> 1), R full weighting, P = R^T,
  *   3x3x3 kernels, zero padding, no bias; z = 0 on Dirichlet rows.

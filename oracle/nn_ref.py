@@ -7,7 +7,7 @@ this module; the HIP library never does, and the two share no code.
 The paper leaves the linear solver open (Sec. 2.2 D-4).  The preconditioner is a small
 linear multilevel 3D convolution network on the node grid of a structured mesh:
 
-    z = s * Dm^-1/2 * N(v),      v = Dm^-1/2 r / s,    s = max|Dm^-1/2 r|
+    z = Dm^-1/2 * N(v),      v = Dm^-1/2 r
     N(v) = y_0 + P(y_1 + P(y_2 + ... P(y_{L-1})))
     y_0 = conv_0(v)                                  (1 -> 1 channel)
     y_l = conv_{l,3}(conv_{l,2}(conv_{l,1}(R^l v)))  (1 -> c_l -> c_l -> 1), l >= 1
@@ -17,7 +17,8 @@ P = R^T is trilinear prolongation, and every conv is 3x3x3 with zero padding and
 bias.  z is set to 0 on constrained (Dirichlet) rows.  N is linear in v, so the
 preconditioner is a fixed linear operator for each system.
 
-Training loss for one residual r:  L = |K z - r|_2^2 / |r|_2^2.
+Training losses for one residual r:  L = |K z - r|_2^2 / |r|_2^2, or, given the error e
+with r = K e, the energy-norm error L = (z - e)^T K (z - e) / e^T K e.
 """
 from __future__ import annotations
 
@@ -155,9 +156,7 @@ class Net:
         ws = unpack(theta, self.channels)
         dm = 1.0 / np.sqrt(diag)
         v0 = (dm * r).reshape(self.shape)[None]
-        s = np.max(np.abs(v0))
-        s = s if s > 0 else 1.0
-        v0 = v0 / s
+        s = 1.0
         vs, ys, acts = [v0], [], []
         for l in range(1, self.levels):
             vs.append(restrict(vs[-1]))
@@ -205,6 +204,31 @@ class Net:
             g1 = conv_dgrad(g2, w2)
             grads[b] = conv_wgrad(v, g1)
         return L, np.concatenate([g.reshape(-1) for g in grads])
+
+
+def energy_loss_and_grad(net, theta, e, diag, Kmat, mask=None):
+    """L = (z - e)^T K (z - e) / (e^T K e) for r = K e, and dL/dtheta."""
+    r = Kmat @ e
+    ws = unpack(theta, net.channels)
+    z, (s, dm, acts) = net.forward(theta, r, diag, mask, keep=True)
+    den = float(e @ r)
+    L = float((z - e) @ (Kmat @ (z - e))) / den
+    gz = 2.0 * (Kmat @ (z - e)) / den
+    if mask is not None:
+        gz = np.where(mask != 0, 0.0, gz)
+    gy = [(s * dm * gz).reshape(net.shape)[None]]
+    for l in range(1, net.levels):
+        gy.append(restrict(gy[-1]))
+    grads = [conv_wgrad(acts[0][0], gy[0])]
+    for l in range(1, net.levels):
+        w1, w2, w3 = ws[1 + 3 * (l - 1): 4 + 3 * (l - 1)]
+        v, h1, h2 = acts[l]
+        g3 = conv_wgrad(h2, gy[l])
+        g2 = conv_dgrad(gy[l], w3)
+        gw2 = conv_wgrad(h1, g2)
+        g1 = conv_dgrad(g2, w2)
+        grads += [conv_wgrad(v, g1), gw2, g3]
+    return L, r, np.concatenate([g.reshape(-1) for g in grads])
 
 
 def init_params(channels, seed):

@@ -2,7 +2,8 @@
 // 3D convolution network, with inference and training kernels written here.  BF16
 // storage for weights and activations, FP32 accumulation, FP64 at the PCG boundary.
 //
-//   z = s * Dm^-1/2 * N(v),   v = Dm^-1/2 r / s,   s = max |Dm^-1/2 r|,   Dm = diag(K)
+//   z = Dm^-1/2 * N(v),   v = Dm^-1/2 r,   Dm = diag(K)   (BF16 has the exponent range of
+//   FP32 and N is linear, so the residual needs no rescaling)
 //   N(v) = y_0 + P(y_1 + P(y_2 + ... ))
 //   y_0 = conv(v)  (1 -> 1);   y_l = conv(conv(conv(R^l v)))  (1 -> c_l -> c_l -> 1)
 //   R: full weighting from a (2n-1)-node grid to an n-node grid; P = R^T (trilinear).
@@ -205,12 +206,6 @@ __global__ void k_diag_scale(const int32_t* __restrict__ rp, const int32_t* __re
     m_out[i] = mask ? mask[i] : 0;
 }
 
-__device__ __forceinline__ float wave_max(float v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-    return v;
-}
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -218,50 +213,38 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// partial[b] = max over the block of |dm * r|
-__global__ void k_absmax(const double* __restrict__ r, const float* __restrict__ dm, int64_t n, float* __restrict__ partial)
-{
-    __shared__ float sh[kThreads / 64];
-    float m = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        m = fmaxf(m, fabsf((float)r[i] * dm[i]));
-    m = wave_max(m);
-    if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float s = 0.f;
-        for (int k = 0; k < kThreads / 64; ++k) s = fmaxf(s, sh[k]);
-        partial[blockIdx.x] = s;
-    }
-}
-
-__global__ void k_absmax_final(const float* __restrict__ partial, int nb, float* __restrict__ s)
-{
-    __shared__ float sh[kThreads / 64];
-    float m = 0.f;
-    for (int k = threadIdx.x; k < nb; k += blockDim.x) m = fmaxf(m, partial[k]);
-    m = wave_max(m);
-    if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float v = 0.f;
-        for (int k = 0; k < kThreads / 64; ++k) v = fmaxf(v, sh[k]);
-        *s = v > 0.f ? v : 1.f;
-    }
-}
-
-__global__ void k_input(const double* __restrict__ r, const float* __restrict__ dm, const float* __restrict__ s,
-                        int64_t n, bf16* __restrict__ v)
+__global__ void k_input(const double* __restrict__ r, const float* __restrict__ dm, int64_t n, bf16* __restrict__ v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) v[i] = f2bf((float)r[i] * dm[i] / *s);
+    if (i < n) v[i] = f2bf((float)r[i] * dm[i]);
 }
 
-__global__ void k_output(const float* __restrict__ acc, const float* __restrict__ dm, const float* __restrict__ s,
-                         const uint8_t* __restrict__ mask, int64_t n, double* __restrict__ z)
+// z = Dm^-1/2 (conv_0(v0) + P acc_1), 0 on Dirichlet rows: the level-0 convolution, the
+// last prolongation and the output scaling in one pass.  acc1 == nullptr for one level.
+// Also stores the level-0 output sum in y0 when y0 != nullptr (training).
+__global__ void __launch_bounds__(kThreads) k_final(const bf16* __restrict__ v0, const float* __restrict__ w0,
+                                                    const float* __restrict__ acc1, Grid gc, Grid g,
+                                                    const float* __restrict__ dm, const uint8_t* __restrict__ mask,
+                                                    double* __restrict__ z, float* __restrict__ y0)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) z[i] = mask[i] ? 0.0 : (double)(*s) * (double)dm[i] * (double)acc[i];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.n()) return;
+    const int x = (int)(t % g.nx), y = (int)((t / g.nx) % g.ny), zz = (int)(t / ((int64_t)g.nx * g.ny));
+    float acc = 0.f;
+#pragma unroll
+    for (int tap = 0; tap < 27; ++tap) {
+        const int sx = x + tap % 3 - 1, sy = y + (tap / 3) % 3 - 1, sz = zz + tap / 9 - 1;
+        if (sx < 0 || sx >= g.nx || sy < 0 || sy >= g.ny || sz < 0 || sz >= g.nz) continue;
+        acc = fmaf(w0[tap], bf2f(v0[sx + (int64_t)g.nx * (sy + (int64_t)g.ny * sz)]), acc);
+    }
+    if (acc1) {
+        const int x0 = x >> 1, x1 = (x + 1) >> 1, y0i = y >> 1, y1 = (y + 1) >> 1, z0 = zz >> 1, z1 = (zz + 1) >> 1;
+        auto C = [&](int a, int b, int d) { return acc1[a + (int64_t)gc.nx * (b + (int64_t)gc.ny * d)]; };
+        acc += 0.125f * (C(x0, y0i, z0) + C(x1, y0i, z0) + C(x0, y1, z0) + C(x1, y1, z0) + C(x0, y0i, z1) +
+                         C(x1, y0i, z1) + C(x0, y1, z1) + C(x1, y1, z1));
+    }
+    if (y0) y0[t] = acc;
+    z[t] = mask[t] ? 0.0 : (double)dm[t] * (double)acc;
 }
 
 // y = K x (FP64 CSR, one row per thread); partial sums of |y - r|^2 and |r|^2
@@ -333,13 +316,13 @@ __global__ void k_residual_energy(const int32_t* __restrict__ rp, const int32_t*
 
 // energy loss gradient: dL/dz = 2 (K z - r) / (r.e), scaled into the network output
 __global__ void k_out_grad_energy(const double* __restrict__ res, int64_t n, const double* __restrict__ sums,
-                                  const float* __restrict__ dm, const float* __restrict__ s,
-                                  const uint8_t* __restrict__ mask, float* __restrict__ g)
+                                  const float* __restrict__ dm, const uint8_t* __restrict__ mask,
+                                  float* __restrict__ g)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double gz = mask[i] ? 0.0 : 2.0 * res[i] / sums[1];
-    g[i] = (float)((double)(*s) * (double)dm[i] * gz);
+    g[i] = (float)((double)dm[i] * gz);
 }
 
 __global__ void k_loss_final(const double* __restrict__ partial, int nb, double* __restrict__ out)
@@ -359,14 +342,14 @@ __global__ void k_loss_final(const double* __restrict__ partial, int nb, double*
 __global__ void k_out_grad(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                            const double* __restrict__ v, int64_t n, const double* __restrict__ res,
                            const double* __restrict__ sums, const float* __restrict__ dm,
-                           const float* __restrict__ s, const uint8_t* __restrict__ mask, float* __restrict__ g)
+                           const uint8_t* __restrict__ mask, float* __restrict__ g)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double t = 0.0;
     for (int k = rp[i]; k < rp[i + 1]; ++k) t = fma(v[k], res[ci[k]], t);
     const double gz = mask[i] ? 0.0 : 2.0 * t / sums[1];
-    g[i] = (float)((double)(*s) * (double)dm[i] * gz);
+    g[i] = (float)((double)dm[i] * gz);
 }
 
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ vv,
@@ -425,8 +408,6 @@ struct mf_nn_s {
     const double* kv = nullptr;
     float* dm = nullptr;
     uint8_t* mask = nullptr;
-    float* s = nullptr;
-    float* maxpart = nullptr;
     double* zbuf = nullptr;
     double* res = nullptr;
     double* lpart = nullptr;
@@ -471,17 +452,13 @@ mf_status conv_dispatch(int cin, int cout, const TI* in, const float* w, TO* out
     return set_error(MF_ERR_UNSUPPORTED, "conv %d -> %d channels not instantiated", cin, cout);
 }
 
-// forward pass from r (FP64) to acc[0] (FP32)
-mf_status nn_forward(mf_nn_s* N, const double* r, hipStream_t s)
+// forward pass: z (FP64) from r; y0 != nullptr keeps the level-0 output (training)
+mf_status nn_forward(mf_nn_s* N, const double* r, double* z, float* y0, hipStream_t s)
 {
     const int64_t n = N->n0;
-    const unsigned nb = (unsigned)std::min<int64_t>(1024, nblk(n));
-    k_absmax<<<nb, kThreads, 0, s>>>(r, N->dm, n, N->maxpart);
-    k_absmax_final<<<1, kThreads, 0, s>>>(N->maxpart, nb, N->s);
-    k_input<<<nblk(n), kThreads, 0, s>>>(r, N->dm, N->s, n, N->vin[0]);
+    k_input<<<nblk(n), kThreads, 0, s>>>(r, N->dm, n, N->vin[0]);
     for (int l = 1; l < N->L; ++l)
         k_restrict<bf16, bf16><<<nblk(N->g[l].n()), kThreads, 0, s>>>(N->vin[l - 1], N->g[l - 1], N->vin[l], N->g[l]);
-    NN_TRY((conv_dispatch<false, bf16, float>(1, 1, N->vin[0], N->pb + N->w_off[0], N->y[0], N->g[0], s)));
     for (int l = 1; l < N->L; ++l) {
         const int c = N->ch[l];
         const int b = 1 + 3 * (l - 1);
@@ -489,24 +466,21 @@ mf_status nn_forward(mf_nn_s* N, const double* r, hipStream_t s)
         NN_TRY((conv_dispatch<false, bf16, bf16>(c, c, N->h1[l], N->pb + N->w_off[b + 1], N->h2[l], N->g[l], s)));
         NN_TRY((conv_dispatch<false, bf16, float>(c, 1, N->h2[l], N->pb + N->w_off[b + 2], N->y[l], N->g[l], s)));
     }
-    // acc_{L-1} = y_{L-1}; acc_l = y_l + P acc_{l+1}
-    for (int l = N->L - 2; l >= 0; --l) {
+    // acc_{L-1} = y_{L-1}; acc_l = y_l + P acc_{l+1} for l >= 1; level 0 fused in k_final
+    for (int l = N->L - 2; l >= 1; --l) {
         const float* coarse = (l == N->L - 2) ? N->y[l + 1] : N->acc[l + 1];
         k_prolong_add<<<nblk(N->g[l].n()), kThreads, 0, s>>>(coarse, N->g[l + 1], N->y[l], N->acc[l], N->g[l]);
     }
+    const float* acc1 = N->L > 2 ? N->acc[1] : (N->L == 2 ? N->y[1] : nullptr);
+    k_final<<<nblk(n), kThreads, 0, s>>>(N->vin[0], N->pb + N->w_off[0], acc1, N->L > 1 ? N->g[1] : N->g[0], N->g[0],
+                                         N->dm, N->mask, z, y0);
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
 
-const float* nn_out(const mf_nn_s* N) { return N->L > 1 ? N->acc[0] : N->y[0]; }
-
 mf_status nn_apply_cb(void* ctx, const double* r, double* z, hipStream_t s)
 {
-    mf_nn_s* N = (mf_nn_s*)ctx;
-    NN_TRY(nn_forward(N, r, s));
-    k_output<<<nblk(N->n0), kThreads, 0, s>>>(nn_out(N), N->dm, N->s, N->mask, N->n0, z);
-    MF_HIP(hipGetLastError());
-    return MF_OK;
+    return nn_forward((mf_nn_s*)ctx, r, z, nullptr, s);
 }
 
 // weight gradient of conv(x) -> gy into grad[off ...]
@@ -630,8 +604,6 @@ mf_status mf_nn_create(const int32_t* grid, int32_t levels, const int32_t* chann
     A(nn_alloc(N, &N->wpart, wp));
     A(nn_alloc(N, &N->dm, N->n0));
     A(nn_alloc(N, &N->mask, N->n0));
-    A(nn_alloc(N, &N->s, 1));
-    A(nn_alloc(N, &N->maxpart, 1024));
     A(nn_alloc(N, &N->zbuf, N->n0));
     A(nn_alloc(N, &N->res, N->n0));
     A(nn_alloc(N, &N->lpart, 2 * 1024));
@@ -711,18 +683,16 @@ mf_status mf_nn_train_step(mf_nn_t* N, const double* r, const double* e, double 
     if (!N->kv) return set_error(MF_ERR_ARG, "call mf_nn_set_system first");
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = N->n0;
-    NN_TRY(nn_forward(N, r, s));
-    k_output<<<nblk(n), kThreads, 0, s>>>(nn_out(N), N->dm, N->s, N->mask, n, N->zbuf);
+    NN_TRY(nn_forward(N, r, N->zbuf, nullptr, s));
     const unsigned nb = (unsigned)std::min<int64_t>(1024, nblk(n));
     if (e) {
         k_residual_energy<<<nb, kThreads, 0, s>>>(N->rp, N->ci, N->kv, n, N->zbuf, r, e, N->res, N->lpart);
         k_loss_final<<<1, 64, 0, s>>>(N->lpart, nb, N->sums);
-        k_out_grad_energy<<<nblk(n), kThreads, 0, s>>>(N->res, n, N->sums, N->dm, N->s, N->mask, N->gy[0]);
+        k_out_grad_energy<<<nblk(n), kThreads, 0, s>>>(N->res, n, N->sums, N->dm, N->mask, N->gy[0]);
     } else {
         k_residual<<<nb, kThreads, 0, s>>>(N->rp, N->ci, N->kv, n, N->zbuf, r, N->res, N->lpart);
         k_loss_final<<<1, 64, 0, s>>>(N->lpart, nb, N->sums);
-        k_out_grad<<<nblk(n), kThreads, 0, s>>>(N->rp, N->ci, N->kv, n, N->res, N->sums, N->dm, N->s, N->mask,
-                                                N->gy[0]);
+        k_out_grad<<<nblk(n), kThreads, 0, s>>>(N->rp, N->ci, N->kv, n, N->res, N->sums, N->dm, N->mask, N->gy[0]);
     }
     for (int l = 1; l < N->L; ++l)
         k_restrict<float, float><<<nblk(N->g[l].n()), kThreads, 0, s>>>(N->gy[l - 1], N->g[l - 1], N->gy[l], N->g[l]);

@@ -90,3 +90,26 @@ def test_network_is_linear_and_identity_start_is_jacobi():
     th[27:] = 0.0
     zj = net.forward(th, a, diag, mask)
     assert np.max(np.abs(zj - np.where(mask != 0, 0.0, a / diag))) < 1e-14
+
+
+def test_energy_gradient_matches_central_differences():
+    S, d, diag, mask = small_system(8, seed=6)
+    net = N.Net((9, 9, 9), [1, 2, 2])
+    theta = N.init_params(net.channels, 9)
+    rng = np.random.default_rng(3)
+    e = np.where(mask != 0, 0.0, rng.standard_normal(d.shape))
+    L, r, g = N.energy_loss_and_grad(net, theta, e, diag, S, mask)
+    # at the Jacobi start with coarse levels off the loss is that of z = D^-1 r
+    th = theta.copy()
+    th[27:] = 0.0
+    zj = np.where(mask != 0, 0.0, r / diag)
+    Lj = (zj - e) @ (S @ (zj - e)) / (e @ r)
+    assert abs(N.energy_loss_and_grad(net, th, e, diag, S, mask)[0] - Lj) < 1e-12
+    eps = 1e-6
+    for i in rng.choice(theta.size, 30, replace=False):
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += eps
+        tm[i] -= eps
+        fd = (N.energy_loss_and_grad(net, tp, e, diag, S, mask)[0] -
+              N.energy_loss_and_grad(net, tm, e, diag, S, mask)[0]) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i]))
