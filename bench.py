@@ -1,6 +1,6 @@
 """Benchmark of the assembly hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--extra]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--only all|primary] [--copy-probe]
 
 One step = one mf_assemble of 3D linear elasticity on the unit cube: 64^3 trilinear Q1
 hexes (274,625 nodes, 823,875 DOFs), interior nodes jittered by +-15% of h, per-element
@@ -9,8 +9,9 @@ FP64 (K = 64,701,513 nonzeros).  Inputs are resident in HBM before timing starts
 
 Printed: one JSON line with throughput (elements/s), the roofline of the assembly
 launch (algorithmic HBM bytes / measured time vs 8 TB/s) and the oracle timed on the
-host (one core) on the same workload.  --extra adds the other workloads as secondary
-records (FP32, the Navier-Stokes Jacobian, the batched launch, PCG).
+host (one core) on the same workload.  Secondary records: the same assembly in FP32,
+PCG to 1e-8 on 96^3 Poisson with Jacobi and with the learned preconditioner, and the
+batched launch of 256 problems.
 """
 from __future__ import annotations
 
@@ -84,29 +85,62 @@ def poisson96_system(dev, seed=10000, n=96):
     return mesh, pat, torch.from_numpy(mesh.coords).to(dev), args, sigma
 
 
-def bench_pcg(dev, steps=3):
+WEIGHTS = os.path.join(ROOT, "paper_2111_03541_amd", "weights", "poisson96")
+
+
+def learned_net(dev):
+    """The trained preconditioner (weights shipped with the package, produced by
+    paper_2111_03541_amd/train_nn.py); trains one when the file is missing."""
+    import json as _json
+    import paper_2111_03541_amd as mf
+    if os.path.exists(WEIGHTS + ".npy"):
+        meta = _json.load(open(WEIGHTS + ".json"))
+        net = mf.Net(tuple(meta["grid"]), meta["channels"], seed=0)
+        net.load_params(WEIGHTS)
+        return net, {"source": "paper_2111_03541_amd/weights/poisson96", "train_s": None}
+    from paper_2111_03541_amd import train_nn
+    t0 = time.perf_counter()
+    net, hist, _ = train_nn.train(96, 2000, log_every=0)
+    return net, {"source": "trained in this run (2000 systems)", "train_s": time.perf_counter() - t0,
+                 "final_loss": float(np.mean(hist[-100:]))}
+
+
+def bench_pcg(dev, seeds=(10000, 10001, 10002), reps=2):
+    """Time to true relative residual 1e-8 on 96^3 lognormal Poisson: Jacobi-PCG vs PCG
+    with the learned preconditioner (network inference inside the timed region)."""
     import torch
     import paper_2111_03541_amd as mf
-    mesh, pat, coords, args, sigma = poisson96_system(dev)
-    form = mf.Form(mf.POISSON, coef=1.0)
-    K, d = pat.assemble(form, coords, precision=mf.F64, **args)
-    torch.cuda.synchronize()
+    net, net_info = learned_net(dev)
     stream = torch.cuda.Stream(dev)
-    rp, ci, _ = pat.device_arrays()
-    times, res = [], None
-    x = torch.empty_like(d)
-    for _ in range(steps + 1):
+    rows = []
+    for seed in seeds:
+        mesh, pat, coords, args, sigma = poisson96_system(dev, seed)
+        K, d = pat.assemble(mf.Form(mf.POISSON, coef=1.0), coords, precision=mf.F64, **args)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, res = mf.pcg(rp, ci, K, d, x=x, tol=1e-8, maxit=20000, precond=mf.PRECOND_JACOBI,
-                        check_every=16, use_graph=True, stream=stream)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    t = float(np.median(times[1:]))
-    log(f"[bench] PCG 96^3 Jacobi: {res['iterations']} it, {t * 1e3:.1f} ms, relres {res['true_relres']:.2e}")
-    return {"n_dofs": pat.n_rows, "nnz": pat.nnz, "sigma": sigma, "iterations": res["iterations"],
-            "time_to_1e-8_ms": t * 1e3, "ms_per_iteration": t * 1e3 / max(res["iterations"], 1),
-            "true_relres": res["true_relres"], "converged": res["converged"]}
+        rp, ci, _ = pat.device_arrays()
+        net.set_system(rp, ci, K, args["dirichlet"])
+        x = torch.empty_like(d)
+        row = {"seed": seed, "sigma": sigma}
+        for name, pc in (("jacobi", mf.PRECOND_JACOBI), ("learned", mf.PRECOND_NN)):
+            ts = []
+            for _ in range(reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, res = mf.pcg(rp, ci, K, d, x=x, tol=1e-8, maxit=20000, precond=pc,
+                                net=net if pc == mf.PRECOND_NN else None, check_every=8,
+                                use_graph=True, stream=stream)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            assert res["converged"] and res["true_relres"] <= 1e-8
+            row[name] = {"iterations": res["iterations"], "ms": 1e3 * min(ts[1:]),
+                         "true_relres": res["true_relres"], "fallbacks": res["fallbacks"]}
+        log(f"[bench] PCG 96^3 seed {seed}: jacobi {row['jacobi']['iterations']} it "
+            f"{row['jacobi']['ms']:.1f} ms, learned {row['learned']['iterations']} it {row['learned']['ms']:.1f} ms")
+        rows.append(row)
+    jm = float(np.median([r["jacobi"]["ms"] for r in rows]))
+    lm = float(np.median([r["learned"]["ms"] for r in rows]))
+    return {"n_dofs": pat.n_rows, "nnz": pat.nnz, "systems": rows, "median_ms_jacobi": jm,
+            "median_ms_learned": lm, "speedup_learned_vs_jacobi": jm / lm, "network": net_info}
 
 
 def bench_batch(dev, steps=10, warmup=3):
@@ -172,7 +206,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extra", action="store_true")
+    ap.add_argument("--only", choices=["all", "primary"], default="all",
+                    help="primary: the elasticity assembly alone (for counter runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the assembly shards by "
@@ -235,6 +272,19 @@ def main():
                      "frac": achieved / HBM_PEAK, "traffic": None,
                      "alg_bytes_per_launch": B, "avg_launch_us": avg * 1e6},
     }
+    if args.copy_probe:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: 3 copies of {src.numel() * 8} bytes")
+        del src, dst
+    if args.only == "primary":
+        if not args.no_cpu:
+            record["cpu_baseline"] = cpu_baseline(mesh, E, b)
+        print(json.dumps(record), flush=True)
+        return
     # secondary: the same workload in FP32 (geometry FP64, contractions FP32)
     K32 = torch.empty(pat.nnz, dtype=torch.float32, device=dev)
     d32 = torch.empty(pat.n_rows, dtype=torch.float32, device=dev)
@@ -251,7 +301,7 @@ def main():
         "elasticity_64_f32": {"avg_launch_us": avg32 * 1e6, "elems_per_s": mesh.n_elems / avg32,
                               "alg_bytes": B32, "hbm_frac": B32 / avg32 / HBM_PEAK},
     }
-    record["secondary"]["poisson_96_jacobi_pcg"] = bench_pcg(dev)
+    record["secondary"]["poisson_96_pcg_time_to_1e-8"] = bench_pcg(dev)
     record["secondary"]["batched_256_f32"] = bench_batch(dev)
     if not args.no_cpu:
         log("[bench] timing the oracle on the host")

@@ -138,8 +138,9 @@ typedef enum { MF_SCATTER_AUTO = 0, MF_SCATTER_ATOMIC = 1, MF_SCATTER_GATHER = 2
  *   written).  Each integration point uses the geometry Jacobian J = sum_a x_a (x)
  *   dN_a/dxi, with det J > 0 required, g_a = J^-T dN_a/dxi and weight w_q det J.
  * precision MF_F64: everything in FP64.  MF_F32: geometry (J, det J, J^-1, g, weights)
- *   in FP64, rounded to FP32; coefficients, contractions and accumulation in FP32;
- *   K, d, elem_param, nodal_src and lin_state are float.  coords are FP64 always.
+ *   in FP64, rounded to FP32; coefficients and the element contractions in FP32 (the
+ *   structured-grid path sums the element contributions of a row in FP64 and rounds
+ *   once); K, d, elem_param, nodal_src and lin_state are float.  coords are FP64 always.
  * K_values [nnz] and d [n_rows] are overwritten entirely (no prior clear needed).
  * Async on `stream`.  A device-side det J <= 0 is reported by mf_status_poll.
  * The pattern's n_fields must match the form (1, 1, dim, dim+1).
@@ -163,7 +164,7 @@ const char* mf_last_error(void);
 /* ------------------------------------------------------------------------------------
  * Batched assembly: many independent structured problems (each with its own pattern,
  * the paper's "workpieces", Sec. 2.2 A-1 and B-2) assembled by ONE persistent launch
- * that work-steals (problem, brick) items, replayed as a HIP graph.  Problems must be
+ * that work-steals (problem, node column) items, replayed as a HIP graph.  Problems must be
  * structured 3D grids (mf_pattern_grid) with MASS, POISSON or ELASTICITY forms.
  * ------------------------------------------------------------------------------------ */
 typedef struct mf_batch_s mf_batch_t;

@@ -196,7 +196,7 @@ mf_status mf_assemble_ex(const mf_pattern_t* P, const mf_form* form, const doubl
     if (scatter == MF_SCATTER_AUTO) scatter = P->is_grid ? MF_SCATTER_GATHER : MF_SCATTER_ATOMIC;
     bool gathered = false;
     if (scatter == MF_SCATTER_GATHER) {
-        st = assemble_gather(A);  // applies the Dirichlet elimination while writing K
+        st = assemble_column(A);  // applies the Dirichlet elimination while writing K
         gathered = st == MF_OK;
         if (st == MF_ERR_UNSUPPORTED) st = assemble_atomic(A);  // e.g. a form without a gather kernel
     } else {

@@ -1,0 +1,696 @@
+// Owner-computes assembly on structured grids, streamed through columns of nodes
+// (numerical integration and scatter of Sec. 2.2 D-2 and D-3, with no atomic increments
+// into global memory).
+//
+// A workgroup owns the nodes of a 4x4 column cross-section over a range of node layers
+// [z0, z1) and walks up the column one node layer kz at a time:
+//   phase A  computes the element layer kz (the 5x5 elements around the column) into an
+//            LDS ring: at each Gauss point q of element e, h_a(q) = sqrt(det J) grad N_a
+//            for the eight element nodes (FP64 geometry, stored in the working
+//            precision), W_q f(x_q) for the load vector, and the element coefficients;
+//            it also writes out the rows of node layer kz-1, finished in the previous
+//            step;
+//   phase B  forms the rows of node layer kz from the element layers kz-1 and kz: lane
+//            (a, e, half) contracts the four Gauss points of its half for the eight
+//            node pairs (a, b), b in e; the two halves are added across adjacent lanes
+//            and the blocks of the eight elements around a are summed into a per-node
+//            LDS row buffer (FP64 in both precisions).
+// Each value of K is written exactly once, in CSR row order, with the Dirichlet
+// elimination applied on the way out.  The geometry of an element is computed once per
+// column that sees it (25 elements per 16 owned nodes per layer).
+//
+// For a symmetric form the block of pair (a, b) is sum_q h_a h_b^T scaled by the element
+// coefficients: mass c W N_a N_b, Poisson c h_a . h_b, elasticity
+// lam M + mu M^T + mu tr(M) I with M = sum_q h_a h_b^T (Sec. 4.2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "element.h"
+#include "mf_internal.h"
+
+namespace mf {
+namespace {
+
+constexpr int CX = 4, CY = 4;              // owned nodes per layer of a column
+constexpr int kColNodes = CX * CY;
+constexpr int EXH = CX + 1, EYH = CY + 1;  // elements per layer around the column
+constexpr int kLayerElems = EXH * EYH;
+constexpr int TX = CX + 2, TY = CY + 2;    // node tile per layer
+constexpr int kTileNodes = TX * TY;
+constexpr int kThreads = 256;
+constexpr int kGeomItems = kLayerElems * 8;  // (element, Gauss point)
+static_assert(kColNodes * 8 * 2 == kThreads, "one lane per (node, element, half)");
+static_assert(kGeomItems <= kThreads, "one lane per (element, Gauss point)");
+
+// LDS layout of the per-Gauss-point vectors h (in units of T).  Strides are padded so
+// that adjacent lanes of phase B (the two halves of a node, and x-adjacent nodes) read
+// distinct banks with 16-byte loads.
+template <typename T>
+struct HLayout {
+    static constexpr int SQ = sizeof(T) == 8 ? 26 : 28;                 // per Gauss point
+    static constexpr int SE = 8 * SQ + (sizeof(T) == 8 ? 2 : 4);        // per element
+    static constexpr int SL = kLayerElems * SE;                         // per element layer
+};
+
+struct ColParams {
+    mf_form form;
+    int nx, ny, nz;  // elements per axis
+    int lz;          // node layers per workgroup
+    int n_nodes;
+    const double* coords;
+    const int32_t* nbr_ptr;
+    const void* elem_param;
+    const void* src;
+    const uint8_t* dirichlet;
+    int field_major;
+    int n_pairs;
+    void* K;
+    void* d;
+    unsigned long long* status;
+};
+
+typedef double Acc;
+
+// exchange a value with the adjacent lane (lane ^ 1)
+__device__ __forceinline__ double swap_adjacent(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0xB1, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float swap_adjacent(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+// 1D linear basis factors at the Gauss point of bit qb: F[0] = (1 - xi)/2, F[1] = (1 + xi)/2
+__device__ __forceinline__ void gauss_factors(int qb, double (&F)[2])
+{
+    const double xi = qb ? kGaussPt : -kGaussPt;
+    F[0] = 0.5 * (1.0 - xi);
+    F[1] = 0.5 * (1.0 + xi);
+}
+
+template <int FORM, typename T>
+struct ColShared {
+    static constexpr int NF = FormTraits<FORM, 3>::NF;
+    static constexpr int NSRC = FormTraits<FORM, 3>::NSRC;
+    static constexpr int NB = NF * NF;
+    T h[2 * HLayout<T>::SL];
+    T wf[2][kLayerElems][8][NF];
+    T cf[2][kLayerElems][2];
+    double x[3][kTileNodes][3];
+    T u[3][kTileNodes][NSRC];
+    double ep[2][kLayerElems];
+    Acc rowK[kColNodes][27 * NB];
+    Acc rowD[kColNodes][NF];
+    int ni[kColNodes][4];  // node id, first pair offset, degree, boundary bits
+};
+
+__device__ __forceinline__ int ring3(int L) { return (L + 3) % 3; }
+
+// Global loads of one node of the tile of node layer L (registers), and their LDS store.
+template <int NSRC, typename T>
+struct NodeLoad {
+    double x[3];
+    T u[NSRC];
+    bool ok;
+    __device__ __forceinline__ void load(const ColParams& p, int L, int tn, int i0, int j0)
+    {
+        const int NX = p.nx + 1, NY = p.ny + 1;
+        const int gi = i0 - 1 + tn % TX, gj = j0 - 1 + tn / TX;
+        ok = L >= 0 && L <= p.nz && gi >= 0 && gi < NX && gj >= 0 && gj < NY;
+        if (!ok) return;
+        const int node = gi + NX * (gj + NY * L);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) x[m] = p.coords[(int64_t)m * p.n_nodes + node];
+        const T* s = (const T*)p.src;
+#pragma unroll
+        for (int k = 0; k < NSRC; ++k) u[k] = s ? s[(int64_t)k * p.n_nodes + node] : T(0);
+    }
+    template <int FORM>
+    __device__ __forceinline__ void store(ColShared<FORM, T>& S, int L, int tn) const
+    {
+        if (!ok) return;
+        const int r = ring3(L);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) S.x[r][tn][m] = x[m];
+#pragma unroll
+        for (int k = 0; k < NSRC; ++k) S.u[r][tn][k] = u[k];
+    }
+};
+
+__device__ __forceinline__ bool elem_param_of(const ColParams& p, int L, int el, int i0, int j0, bool f32,
+                                              double& v)
+{
+    const int ex = i0 - 1 + el % EXH, ey = j0 - 1 + el / EXH;
+    if (L < 0 || L >= p.nz || ex < 0 || ex >= p.nx || ey < 0 || ey >= p.ny) return false;
+    const int e = ex + p.nx * (ey + p.ny * L);
+    v = p.elem_param ? (f32 ? (double)((const float*)p.elem_param)[e] : ((const double*)p.elem_param)[e]) : 1.0;
+    return true;
+}
+
+// Phase A: geometry of element `el` of element layer L at Gauss point q.
+template <int FORM, typename T>
+__device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM, T>& S, int L, int el, int q,
+                                              int i0, int j0)
+{
+    constexpr int NF = FormTraits<FORM, 3>::NF;
+    const int hx = el % EXH, hy = el / EXH;
+    const int ex = i0 - 1 + hx, ey = j0 - 1 + hy;
+    if (L < 0 || L >= p.nz || ex < 0 || ex >= p.nx || ey < 0 || ey >= p.ny) return;
+    double x[8][3];
+    T U[8][FormTraits<FORM, 3>::NSRC];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const int r = ring3(L + (a >> 2));
+        const int tn = (hx + (a & 1)) + TX * (hy + ((a >> 1) & 1));
+#pragma unroll
+        for (int m = 0; m < 3; ++m) x[a][m] = S.x[r][tn][m];
+#pragma unroll
+        for (int k = 0; k < FormTraits<FORM, 3>::NSRC; ++k) U[a][k] = S.u[r][tn][k];
+    }
+    double F[3][2];
+    gauss_factors(q & 1, F[0]);
+    gauss_factors((q >> 1) & 1, F[1]);
+    gauss_factors((q >> 2) & 1, F[2]);
+    double N[8], dN[8][3];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+        N[a] = F[0][ax] * F[1][ay] * F[2][az];
+        dN[a][0] = (ax ? 0.5 : -0.5) * F[1][ay] * F[2][az];
+        dN[a][1] = (ay ? 0.5 : -0.5) * F[0][ax] * F[2][az];
+        dN[a][2] = (az ? 0.5 : -0.5) * F[0][ax] * F[1][ay];
+    }
+    double J[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < 8; ++a) s = fma(x[a][i], dN[a][j], s);
+            J[i][j] = s;
+        }
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const int slot = L & 1;
+    if (!(det > 0.0)) atomicMin(p.status, (unsigned long long)(ex + p.nx * (ey + p.ny * L)));
+    const double ep = S.ep[slot][el];
+    double coefA = 0.0, coefB = 0.0;
+    if constexpr (FORM == MF_FORM_ELASTICITY) {
+        const double E = p.form.coef * ep, nu = p.form.nu;
+        coefA = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        coefB = E / (2.0 * (1.0 + nu));
+    } else {
+        coefA = p.form.coef * ep;
+    }
+    T* hq = S.h + slot * HLayout<T>::SL + el * HLayout<T>::SE + q * HLayout<T>::SQ;
+    if constexpr (FORM == MF_FORM_MASS) {
+        hq[0] = (T)det;
+    } else {
+        const double r = 1.0 / det;
+        double A[3][3];  // sqrt(det) * J^-1, with (J^-1)_{jm} = cofactor_{mj} / det
+        const double s = sqrt(det) * r;
+        A[0][0] = c00 * s;
+        A[1][0] = c01 * s;
+        A[2][0] = c02 * s;
+        A[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * s;
+        A[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * s;
+        A[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * s;
+        A[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * s;
+        A[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * s;
+        A[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * s;
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                double v = 0.0;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) v = fma(dN[a][j], A[j][m], v);
+                hq[3 * a + m] = (T)v;
+            }
+    }
+    // load vector integrand W f(x_q) (times c for the mass form)
+    const double wscale = det * (FORM == MF_FORM_MASS ? coefA : 1.0);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+        double f = 0.0;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) f = fma(N[a], (double)U[a][i], f);
+        S.wf[slot][el][q][i] = (T)(wscale * f);
+    }
+    if (q == 0) {
+        S.cf[slot][el][0] = (T)coefA;
+        S.cf[slot][el][1] = (T)coefB;
+    }
+}
+
+// Phase B: lane (node al, element eps around it, half qh) of node layer kz.
+template <int FORM, typename T>
+__device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>& S, int kz, int i0, int j0)
+{
+    constexpr int NF = FormTraits<FORM, 3>::NF;
+    constexpr int NB = NF * NF;
+    constexpr int NV = FORM == MF_FORM_ELASTICITY ? 9 : 1;
+    const int tid = threadIdx.x;
+    const int qh = tid & 1, pe = tid >> 1;
+    const int al = pe & (kColNodes - 1), eps = pe / kColNodes;
+    const int alx = al % CX, aly = al / CX;
+    const int gi = i0 + alx, gj = j0 + aly;
+    const int dx = eps & 1, dy = (eps >> 1) & 1, dz = eps >> 2;
+    const int ex = gi - 1 + dx, ey = gj - 1 + dy, ez = kz - 1 + dz;
+    const bool valid = gi <= p.nx && gj <= p.ny && ex >= 0 && ex < p.nx && ey >= 0 && ey < p.ny && ez >= 0 &&
+                       ez < p.nz;
+    const int alpha = 7 - eps;  // the node's local index in the element
+    const int slot = ez & 1, el = (alx + dx) + EXH * (aly + dy);
+    const T* he = S.h + slot * HLayout<T>::SL + el * HLayout<T>::SE;
+
+    T M[8][NV];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) M[b][v] = T(0);
+    T dp[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) dp[i] = T(0);
+
+    if (valid) {
+        double Fz[2];
+        gauss_factors(qh, Fz);  // z factors of this half (q bit 2 = qh)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int q = 4 * qh + k;
+            const T* hq = he + q * HLayout<T>::SQ;
+            double Fx[2], Fy[2];
+            gauss_factors(k & 1, Fx);
+            gauss_factors((k >> 1) & 1, Fy);
+            const double Na = Fx[alpha & 1] * Fy[(alpha >> 1) & 1] * Fz[alpha >> 2];
+            if constexpr (FORM == MF_FORM_MASS) {
+                const T wa = hq[0] * (T)Na;
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+                    M[b][0] += wa * (T)(Fx[b & 1] * Fy[(b >> 1) & 1] * Fz[b >> 2]);
+            } else {
+                T hb[8][3];
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) hb[b][m] = hq[3 * b + m];
+                T ha[3];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) ha[m] = hq[3 * alpha + m];
+                if constexpr (FORM == MF_FORM_ELASTICITY) {
+#pragma unroll
+                    for (int b = 0; b < 8; ++b)
+#pragma unroll
+                        for (int i = 0; i < 3; ++i)
+#pragma unroll
+                            for (int j = 0; j < 3; ++j) M[b][3 * i + j] += ha[i] * hb[b][j];
+                } else {
+#pragma unroll
+                    for (int b = 0; b < 8; ++b) M[b][0] += ha[0] * hb[b][0] + ha[1] * hb[b][1] + ha[2] * hb[b][2];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NF; ++i) dp[i] += (T)Na * S.wf[slot][el][q][i];
+        }
+    }
+    // add the two halves: lane qh keeps the blocks b = 4 qh .. 4 qh + 3
+    T Mk[4][NV];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const T give = qh ? M[b][v] : M[b + 4][v];
+            const T keep = qh ? M[b + 4][v] : M[b][v];
+            Mk[b][v] = keep + swap_adjacent(give);
+        }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) dp[i] += swap_adjacent(dp[i]);
+    if (!valid) return;
+
+    const T cA = S.cf[slot][el][0], cB = S.cf[slot][el][1];
+    const int ax = alpha & 1, ay = (alpha >> 1) & 1, az = alpha >> 2;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int beta = b + 4 * qh;
+        const int nslot = (qh - az + 1) * 9 + (((beta >> 1) & 1) - ay + 1) * 3 + ((beta & 1) - ax + 1);
+        Acc* dst = &S.rowK[al][nslot * NB];
+        if constexpr (FORM == MF_FORM_ELASTICITY) {
+            const T tr = Mk[b][0] + Mk[b][4] + Mk[b][8];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const T v = cA * Mk[b][3 * i + j] + cB * Mk[b][3 * j + i] + (i == j ? cB * tr : T(0));
+                    unsafeAtomicAdd(dst + 3 * i + j, (Acc)v);
+                }
+        } else {
+            unsafeAtomicAdd(dst, (Acc)(cA * Mk[b][0]));
+        }
+    }
+    if (qh == 0) {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) unsafeAtomicAdd(&S.rowD[al][i], (Acc)dp[i]);
+    }
+}
+
+// Rows of node layer kz from the row buffers (cleared on the way for the next layer).
+template <int FORM, typename T>
+__device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, T>& S)
+{
+    constexpr int NF = FormTraits<FORM, 3>::NF;
+    constexpr int NB = NF * NF;
+    constexpr int kRowSlots = 27 * NF;
+    T* K = (T*)p.K;
+    T* d = (T*)p.d;
+    const int NX = p.nx + 1, NY = p.ny + 1;
+    const int nn = p.n_nodes;
+    for (int flat = threadIdx.x; flat < kColNodes * NF * kRowSlots; flat += kThreads) {
+        const int rloc = flat / kRowSlots;
+        const int sj = flat - rloc * kRowSlots;
+        const int slot = sj / NF, j = sj - slot * NF;
+        const int il = rloc / NF, i = rloc - il * NF;
+        Acc* src = &S.rowK[il][slot * NB + i * NF + j];
+        const Acc acc = *src;
+        *src = 0.0;
+        Acc accd = 0.0;
+        if (slot == 13 && j == 0) {
+            accd = S.rowD[il][i];
+            S.rowD[il][i] = 0.0;
+        }
+        const int node = S.ni[il][0];
+        if (node < 0) continue;
+        const int bits = S.ni[il][3];
+        const int ddx = slot % 3 - 1, ddy = (slot / 3) % 3 - 1, ddz = slot / 9 - 1;
+        const int need = (ddx < 0 ? 1 : 0) | (ddx > 0 ? 2 : 0) | (ddy < 0 ? 4 : 0) | (ddy > 0 ? 8 : 0) |
+                         (ddz < 0 ? 16 : 0) | (ddz > 0 ? 32 : 0);
+        if ((bits & need) != need) continue;
+        const int lo_x = bits & 1, lo_y = (bits >> 2) & 1, lo_z = (bits >> 4) & 1;
+        const int mx = 1 + lo_x + ((bits >> 1) & 1), my = 1 + lo_y + ((bits >> 3) & 1);
+        const int rank = ((ddz + lo_z) * my + (ddy + lo_y)) * mx + (ddx + lo_x);
+        const int deg = S.ni[il][2];
+        const int P = S.ni[il][1];
+        int row, kpos;
+        if (p.field_major) {
+            row = i * nn + node;
+            kpos = i * NF * p.n_pairs + NF * P + j * deg + rank;
+        } else {
+            row = NF * node + i;
+            kpos = P * NB + i * NF * deg + rank * NF + j;
+        }
+        T v = (T)acc;
+        if (p.dirichlet) {
+            const int nb = node + ddx + NX * (ddy + NY * ddz);
+            const int col = p.field_major ? j * nn + nb : NF * nb + j;
+            if (p.dirichlet[row]) v = (col == row) ? T(1) : T(0);
+            else if (p.dirichlet[col]) v = T(0);
+        }
+        K[kpos] = v;
+        if (slot == 13 && j == 0) d[row] = (p.dirichlet && p.dirichlet[row]) ? T(0) : (T)accd;
+    }
+}
+
+// One column chunk b of one problem (b = column + columns * chunk); called by the
+// single-problem kernel and by the persistent batched kernel.
+template <int FORM, typename T>
+__device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared<FORM, T>& S)
+{
+    constexpr int NF = FormTraits<FORM, 3>::NF;
+    constexpr int NSRC = FormTraits<FORM, 3>::NSRC;
+    constexpr int NB = NF * NF;
+    const int tid = threadIdx.x;
+    const int NX = p.nx + 1, NY = p.ny + 1, NZ = p.nz + 1;
+    const int ncx = (NX + CX - 1) / CX, ncy = (NY + CY - 1) / CY;
+    const int cx = b % ncx, cy = (b / ncx) % ncy, ch = b / (ncx * ncy);
+    const int i0 = cx * CX, j0 = cy * CY;
+    const int z0 = ch * p.lz, z1 = min(z0 + p.lz, NZ);
+    const bool f32 = sizeof(T) == 4;
+
+    for (int k = tid; k < kColNodes * 27 * NB; k += kThreads) (&S.rowK[0][0])[k] = 0.0;
+    for (int k = tid; k < kColNodes * NF; k += kThreads) (&S.rowD[0][0])[k] = 0.0;
+    // prologue: node layers z0-1 .. z0+1, element parameters of layers z0-1 and z0
+    for (int it = tid; it < 3 * kTileNodes; it += kThreads) {
+        NodeLoad<NSRC, T> ld;
+        const int L = z0 - 1 + it / kTileNodes, tn = it % kTileNodes;
+        ld.load(p, L, tn, i0, j0);
+        ld.template store<FORM>(S, L, tn);
+    }
+    for (int it = tid; it < 2 * kLayerElems; it += kThreads) {
+        const int L = z0 - 1 + it / kLayerElems, el = it % kLayerElems;
+        double v;
+        if (elem_param_of(p, L, el, i0, j0, f32, v)) S.ep[L & 1][el] = v;
+    }
+    __syncthreads();
+
+    for (int kz = z0; kz < z1; ++kz) {
+        // ---- phase A: geometry of element layer kz (and kz-1 on the first step); rows of kz-1
+        const int first = kz == z0 ? kz - 1 : kz;
+        for (int it = tid; it < (kz - first + 1) * kGeomItems; it += kThreads) {
+            const int L = first + it / kGeomItems, r = it % kGeomItems;
+            geometry_item<FORM, T>(p, S, L, r >> 3, r & 7, i0, j0);
+        }
+        if (kz > z0) write_layer<FORM, T>(p, S);
+        __syncthreads();
+
+        // ---- phase B: rows of node layer kz; prefetch for the next step
+        NodeLoad<NSRC, T> ld;
+        ld.ok = false;
+        double epv = 0.0;
+        bool ep_ok = false;
+        int info[4] = {-1, 0, 0, 0};
+        if (tid < kTileNodes) {
+            ld.load(p, kz + 2, tid, i0, j0);
+        } else if (tid >= 64 && tid < 64 + kLayerElems) {
+            ep_ok = elem_param_of(p, kz + 1, tid - 64, i0, j0, f32, epv);
+        } else if (tid >= 128 && tid < 128 + kColNodes) {
+            const int il = tid - 128;
+            const int gi = i0 + il % CX, gj = j0 + il / CX;
+            if (gi < NX && gj < NY) {
+                const int node = gi + NX * (gj + NY * kz);
+                const int mx = 1 + (gi > 0) + (gi < p.nx), my = 1 + (gj > 0) + (gj < p.ny),
+                          mz = 1 + (kz > 0) + (kz < p.nz);
+                info[0] = node;
+                info[1] = p.nbr_ptr[node];
+                info[2] = mx * my * mz;
+                info[3] = (gi > 0) | ((gi < p.nx) << 1) | ((gj > 0) << 2) | ((gj < p.ny) << 3) | ((kz > 0) << 4) |
+                          ((kz < p.nz) << 5);
+            }
+        }
+        pair_item<FORM, T>(p, S, kz, i0, j0);
+        if (tid < kTileNodes) ld.template store<FORM>(S, kz + 2, tid);
+        if (ep_ok) S.ep[(kz + 1) & 1][tid - 64] = epv;
+        if (tid >= 128 && tid < 128 + kColNodes) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) S.ni[tid - 128][k] = info[k];
+        }
+        __syncthreads();
+    }
+    if (z0 < z1) write_layer<FORM, T>(p, S);
+}
+
+template <int FORM, typename T>
+__global__ void __launch_bounds__(kThreads, 1) k_assemble_column(ColParams p)
+{
+    __shared__ ColShared<FORM, T> S;
+    column_body<FORM, T>(p, blockIdx.x, S);
+}
+
+// ------------------------------------------------------------------------------------
+// Batched persistent launch: many structured problems in one kernel.  Work items are
+// (problem, column) pairs in an order chosen on the host; each workgroup pops the next
+// item from a device counter until the list is exhausted (every wave reaches the exit).
+// ------------------------------------------------------------------------------------
+struct BatchProblemDev {
+    ColParams cp;
+    int kind;
+};
+
+template <typename T>
+union BatchShared {
+    ColShared<MF_FORM_MASS, T> mass;
+    ColShared<MF_FORM_POISSON, T> poisson;
+    ColShared<MF_FORM_ELASTICITY, T> elasticity;
+};
+
+__global__ void k_batch_reset(int* counter, unsigned long long* const* status, int n_status)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *counter = 0;
+    if (i < n_status) *status[i] = ~0ull;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads, 1)
+    k_batch_persistent(const BatchProblemDev* __restrict__ probs, const int2* __restrict__ items, int n_items,
+                       int* __restrict__ counter)
+{
+    __shared__ BatchShared<T> S;
+    __shared__ int sItem;
+    while (true) {
+        __syncthreads();  // the previous item's write-out is done with the LDS
+        if (threadIdx.x == 0) sItem = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = sItem;
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        const ColParams cp = probs[w.x].cp;
+        const int kind = probs[w.x].kind;
+        if (kind == MF_FORM_ELASTICITY)
+            column_body<MF_FORM_ELASTICITY, T>(cp, w.y, S.elasticity);
+        else if (kind == MF_FORM_POISSON)
+            column_body<MF_FORM_POISSON, T>(cp, w.y, S.poisson);
+        else
+            column_body<MF_FORM_MASS, T>(cp, w.y, S.mass);
+    }
+}
+
+int device_cus()
+{
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cached[dev] = n;
+    }
+    return cached[dev];
+}
+
+// Node layers per workgroup: minimise (rounds of workgroups over the CUs) x (layers per
+// workgroup + the one extra element layer each workgroup computes first).
+int choose_lz(int64_t columns, int NZ, int cus)
+{
+    int best = NZ;
+    double best_cost = 1e300;
+    for (int n_ch = 1; n_ch <= NZ; ++n_ch) {
+        const int lz = (NZ + n_ch - 1) / n_ch;
+        const int64_t wgs = columns * ((NZ + lz - 1) / lz);
+        const double rounds = (double)((wgs + cus - 1) / cus);
+        const double cost = rounds * (lz + 1);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = lz;
+        }
+    }
+    return best;
+}
+
+ColParams make_params(const AssembleArgs& A)
+{
+    const mf_pattern_s* P = A.P;
+    ColParams p{};
+    p.form = *A.form;
+    p.nx = (int)P->gx;
+    p.ny = (int)P->gy;
+    p.nz = (int)P->gz;
+    p.n_nodes = (int)P->n_nodes;
+    p.coords = A.coords;
+    p.nbr_ptr = P->nbr_ptr;
+    p.elem_param = A.elem_param;
+    p.src = A.nodal_src;
+    p.dirichlet = A.dirichlet;
+    p.field_major = P->numbering == MF_FIELD_MAJOR;
+    p.n_pairs = (int)P->n_pairs;
+    p.K = A.K;
+    p.d = A.d;
+    p.status = P->status;
+    p.lz = p.nz + 1;
+    return p;
+}
+
+int64_t column_count(const mf_pattern_s* P)
+{
+    return (int64_t)((P->gx + 1 + CX - 1) / CX) * ((P->gy + 1 + CY - 1) / CY);
+}
+
+template <int FORM, typename T>
+mf_status launch_column(const AssembleArgs& A)
+{
+    ColParams p = make_params(A);
+    const int NZ = p.nz + 1;
+    const int64_t columns = column_count(A.P);
+    p.lz = choose_lz(columns, NZ, device_cus());
+    const int64_t wgs = columns * ((NZ + p.lz - 1) / p.lz);
+    if (wgs <= 0) return MF_OK;
+    if (wgs > 0x7fffffff) return set_error(MF_ERR_OVERFLOW, "grid of %lld workgroups", (long long)wgs);
+    k_assemble_column<FORM, T><<<(unsigned)wgs, kThreads, 0, A.stream>>>(p);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+template <typename T>
+mf_status dispatch(const AssembleArgs& A)
+{
+    switch (A.form->kind) {
+        case MF_FORM_MASS: return launch_column<MF_FORM_MASS, T>(A);
+        case MF_FORM_POISSON: return launch_column<MF_FORM_POISSON, T>(A);
+        case MF_FORM_ELASTICITY: return launch_column<MF_FORM_ELASTICITY, T>(A);
+        default: return MF_ERR_UNSUPPORTED;
+    }
+}
+
+}  // namespace
+
+// ---------------- batched launch: host side ----------------
+// Each problem is one item per column (the whole column height in one workgroup).
+
+int64_t batch_units_of(const mf_pattern_s* P) { return column_count(P); }
+
+mf_status batch_check(const AssembleArgs& A)
+{
+    const mf_pattern_s* P = A.P;
+    if (!P->is_grid || P->dim != 3 || !P->full_coupling || P->n_elems == 0)
+        return set_error(MF_ERR_UNSUPPORTED, "batched problems must be non-empty structured 3D grids with full coupling");
+    if (A.form->kind == MF_FORM_NS_SUPG) return set_error(MF_ERR_UNSUPPORTED, "batched launch covers mass, Poisson and elasticity");
+    if (P->n_nodes >= 0x7fffffff) return set_error(MF_ERR_OVERFLOW, "problem too large for the batched launch");
+    return MF_OK;
+}
+
+mf_status batch_upload(const std::vector<AssembleArgs>& probs, void** dev_probs, void** dev_status)
+{
+    std::vector<BatchProblemDev> h(probs.size());
+    std::vector<unsigned long long*> st(probs.size());
+    for (size_t k = 0; k < probs.size(); ++k) {
+        h[k].cp = make_params(probs[k]);
+        h[k].kind = probs[k].form->kind;
+        st[k] = probs[k].P->status;
+    }
+    MF_HIP(hipMalloc(dev_probs, sizeof(BatchProblemDev) * (h.size() > 0 ? h.size() : 1)));
+    MF_HIP(hipMemcpy(*dev_probs, h.data(), sizeof(BatchProblemDev) * h.size(), hipMemcpyHostToDevice));
+    MF_HIP(hipMalloc(dev_status, sizeof(void*) * (st.size() > 0 ? st.size() : 1)));
+    MF_HIP(hipMemcpy(*dev_status, st.data(), sizeof(void*) * st.size(), hipMemcpyHostToDevice));
+    return MF_OK;
+}
+
+mf_status batch_launch(const void* dev_probs, void* dev_status, int n_probs, const int2* items, int n_items,
+                       int* counter, int n_wg, mf_precision prec, hipStream_t s)
+{
+    k_batch_reset<<<(n_probs + 255) / 256 > 0 ? (n_probs + 255) / 256 : 1, 256, 0, s>>>(
+        counter, (unsigned long long* const*)dev_status, n_probs);
+    if (prec == MF_F64)
+        k_batch_persistent<double><<<n_wg, kThreads, 0, s>>>((const BatchProblemDev*)dev_probs, items, n_items, counter);
+    else
+        k_batch_persistent<float><<<n_wg, kThreads, 0, s>>>((const BatchProblemDev*)dev_probs, items, n_items, counter);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+// Returns MF_ERR_UNSUPPORTED (without launching) when the case is not covered:
+// unstructured meshes, 2D, partial coupling, or the flow form.
+mf_status assemble_column(const AssembleArgs& A)
+{
+    const mf_pattern_s* P = A.P;
+    if (!P->is_grid || P->dim != 3 || !P->full_coupling) return MF_ERR_UNSUPPORTED;
+    if (A.form->kind == MF_FORM_NS_SUPG) return MF_ERR_UNSUPPORTED;
+    if (P->n_elems == 0) return MF_ERR_UNSUPPORTED;
+    return A.prec == MF_F64 ? dispatch<double>(A) : dispatch<float>(A);
+}
+
+}  // namespace mf

@@ -20,7 +20,7 @@
 struct mf_batch_s {
     std::vector<mf::AssembleArgs> probs;
     std::vector<mf_form> forms;
-    std::vector<int64_t> bricks;
+    std::vector<int64_t> units;  // work items (columns) per problem
     mf_precision prec = MF_F64;
     void* dprobs = nullptr;
     void* dstatus = nullptr;
@@ -57,7 +57,7 @@ std::vector<int2> build_items(const mf_batch_s* B, int order)
     const int np = (int)B->probs.size();
     if (order == 0) {
         for (int p = 0; p < np; ++p)
-            for (int64_t b = 0; b < B->bricks[p]; ++b) it.push_back(make_int2(p, (int)b));
+            for (int64_t b = 0; b < B->units[p]; ++b) it.push_back(make_int2(p, (int)b));
         return it;
     }
     std::vector<int> sel;
@@ -71,18 +71,18 @@ std::vector<int2> build_items(const mf_batch_s* B, int order)
         for (int p : sel) (B->forms[p].kind == MF_FORM_ELASTICITY ? a : b).push_back(p);
         for (auto* grp : {&a, &b}) {
             int64_t mx = 0;
-            for (int p : *grp) mx = std::max(mx, B->bricks[p]);
+            for (int p : *grp) mx = std::max(mx, B->units[p]);
             for (int64_t k = 0; k < mx; ++k)
                 for (int p : *grp)
-                    if (k < B->bricks[p]) it.push_back(make_int2(p, (int)k));
+                    if (k < B->units[p]) it.push_back(make_int2(p, (int)k));
         }
         return it;
     }
     int64_t mx = 0;
-    for (int p = 0; p < np; ++p) mx = std::max(mx, B->bricks[p]);
+    for (int p = 0; p < np; ++p) mx = std::max(mx, B->units[p]);
     for (int64_t k = 0; k < mx; ++k)
         for (int p = 0; p < np; ++p)
-            if (k < B->bricks[p]) it.push_back(make_int2(p, (int)k));
+            if (k < B->units[p]) it.push_back(make_int2(p, (int)k));
     return it;
 }
 
@@ -105,7 +105,7 @@ std::string tune_key(const mf_batch_s* B)
     double lg = std::floor(std::log10(std::max(1, B->n_items)));
     long bucket = (long)(std::round(B->n_items / std::pow(10.0, lg - 1)) * std::pow(10.0, lg - 1));
     std::ostringstream os;
-    os << "gfx950|prec=" << (B->prec == MF_F64 ? "f64" : "f32") << "|problems=" << B->probs.size()
+    os << "gfx950|column-v1|prec=" << (B->prec == MF_F64 ? "f64" : "f32") << "|problems=" << B->probs.size()
        << "|elasticity=" << n_el << "|items~" << bucket;
     return os.str();
 }
@@ -235,7 +235,7 @@ mf_status mf_batch_create(const mf_batch_problem* problems, int32_t n, mf_precis
             return st;
         }
         B->probs.push_back(a);
-        B->bricks.push_back(brick_count_of(q.pattern));
+        B->units.push_back(batch_units_of(q.pattern));
     }
     mf_status st = batch_upload(B->probs, &B->dprobs, &B->dstatus);
     if (st == MF_OK && hipMalloc(&B->counter, sizeof(int)) != hipSuccess) st = set_error(MF_ERR_OOM, "counter");
@@ -243,7 +243,7 @@ mf_status mf_batch_create(const mf_batch_problem* problems, int32_t n, mf_precis
     if (st == MF_OK && hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
         B->num_cus = cus;
-    B->n_wg = B->num_cus * (prec == MF_F64 ? 1 : 2);
+    B->n_wg = B->num_cus;
     if (st == MF_OK) st = upload_items(B, 1);
     if (st != MF_OK) {
         free_batch(B);
@@ -269,7 +269,7 @@ mf_status mf_batch_tune(mf_batch_t* B, const char* cache_path, void* stream)
     }
     double best = 1e300;
     int best_order = 1, best_mult = 1;
-    const int max_mult = B->prec == MF_F64 ? 2 : 4;
+    const int max_mult = 2;
     for (int o = 0; o < 3; ++o) {
         mf_status st = upload_items(B, o);
         if (st != MF_OK) return st;

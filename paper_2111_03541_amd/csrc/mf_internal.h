@@ -62,14 +62,14 @@ struct AssembleArgs {
     hipStream_t stream;
 };
 mf_status assemble_atomic(const AssembleArgs& a);
-mf_status assemble_gather(const AssembleArgs& a);
+mf_status assemble_column(const AssembleArgs& a);
 mf_status apply_dirichlet(const AssembleArgs& a);
 mf_status reset_status(const mf_pattern_s* P, hipStream_t s);
 
-// batched persistent launch (assemble_gather.hip)
+// batched persistent launch (assemble_column.hip)
 mf_status batch_check(const AssembleArgs& a);
 mf_status batch_upload(const std::vector<AssembleArgs>& probs, void** dev_probs, void** dev_status);
-int64_t brick_count_of(const mf_pattern_s* P);
+int64_t batch_units_of(const mf_pattern_s* P);
 mf_status batch_launch(const void* dev_probs, void* dev_status, int n_probs, const int2* items, int n_items,
                        int* counter, int n_wg, mf_precision prec, hipStream_t s);
 

@@ -4,8 +4,9 @@
 // One iteration, all scalars kept on the device:
 //   k_spmv_dot   q = K p, partial sums of p.q
 //   k_reduce     alpha = (r.z) / (p.q)
-//   k_update     x += alpha p, r -= alpha q, z = M r, partial sums of r.z, r.r (and of
-//                z.r_old for the flexible variant)
+//   k_update     x += alpha p, r -= alpha q, z = M r, partial sums of r.z, r.r
+//                (k_update_dots for Jacobi / none; for an external apply the update,
+//                the apply and the dots r.z, r.r, z.r_old are separate steps)
 //   k_reduce     beta = (r.z)_new / (r.z) (flexible: (z.(r - r_old)) / (r.z)_old)
 //   k_dir        p = z + beta p
 // Partial sums use fixed block order, so a run is bit-reproducible.  Chunks of
@@ -117,6 +118,35 @@ __global__ void __launch_bounds__(kThreads) k_update(int n, const double* __rest
         if (keep_old) r_old[i] = r[i];
         r[i] = ri;
         if (jacobi >= 0) z[i] = jacobi ? dinv[i] * ri : ri;
+    }
+}
+
+// Jacobi iteration body in one pass: x += alpha p; r -= alpha q; z = D^-1 r (or z = r);
+// partial sums of r.z and r.r (the z.r_old slot is zero)
+__global__ void __launch_bounds__(kThreads) k_update_dots(int n, const double* __restrict__ s,
+                                                          double* __restrict__ x, double* __restrict__ r,
+                                                          const double* __restrict__ p, const double* __restrict__ q,
+                                                          const double* __restrict__ dinv, double* __restrict__ z,
+                                                          int jacobi, double* __restrict__ partial, int nb)
+{
+    __shared__ double sh[kThreads / 64];
+    const double alpha = s[S_ALPHA];
+    double rz = 0.0, rr = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        x[i] = fma(alpha, p[i], x[i]);
+        const double ri = fma(-alpha, q[i], r[i]);
+        r[i] = ri;
+        const double zi = jacobi ? dinv[i] * ri : ri;
+        z[i] = zi;
+        rz = fma(ri, zi, rz);
+        rr = fma(ri, ri, rr);
+    }
+    const double a = block_sum(rz, sh);
+    const double b = block_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = a;
+        partial[nb + blockIdx.x] = b;
+        partial[2 * nb + blockIdx.x] = 0.0;
     }
 }
 
@@ -356,9 +386,14 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
     auto iteration = [&]() -> mf_status {
         k_spmv_dot<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, p, q, p, partial, 0);
         k_reduce_alpha<<<1, kThreads, 0, s>>>(partial, spmv_blocks, sc);
-        k_update<<<vec_blocks, kThreads, 0, s>>>(n, sc, a.x, r, r_old, p, q, dinv, z, external ? -1 : jac,
-                                                 flexible);
-        if (external) {
+        if (!external) {
+            k_update_dots<<<vec_blocks, kThreads, 0, s>>>(n, sc, a.x, r, p, q, dinv, z, jac, partial, vec_blocks);
+            k_reduce_beta<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, 0);
+            k_dir<<<vec_blocks, kThreads, 0, s>>>(n, sc, z, p);
+            return MF_OK;
+        }
+        k_update<<<vec_blocks, kThreads, 0, s>>>(n, sc, a.x, r, r_old, p, q, dinv, z, -1, flexible);
+        {
             mf_status st = a.apply(a.apply_ctx, r, z, s);
             if (st != MF_OK) return st;
             k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, nullptr, partial, vec_blocks);

@@ -270,7 +270,7 @@ GATHER_MESHES = [(1, 1, 1), (2, 1, 1), (3, 5, 2), (7, 7, 3), (4, 4, 4), (5, 3, 1
 @pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
 def test_gather_on_small_and_ragged_grids(mf, n, fname, kind, prec):
     """The owner-computes path on grids whose node counts are and are not multiples of
-    the 4x4x4 brick, with Dirichlet rows on one face; against the oracle."""
+    the 4x4 node column, with Dirichlet rows on one face; against the oracle."""
     say("gather", n, fname, prec)
     mesh = W.structured_mesh(n, jitter=0.1, seed=sum(n))
     nf = O.form_nf(kind, 3)

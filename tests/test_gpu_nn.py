@@ -127,3 +127,41 @@ def test_training_reduces_loss_and_pcg_converges(mf):
     assert res["converged"] and res["true_relres"] <= 1e-8
     xh = x.cpu().numpy()
     assert np.linalg.norm(d - S @ xh) / np.linalg.norm(d) <= 1e-8
+
+
+def test_shipped_weights_beat_jacobi_on_held_out_96(mf):
+    """The shipped 96^3 network on systems whose conductivity fields were never seen in
+    training (fresh Gaussian-field draws): both solvers reach true relative residual 1e-8
+    and the learned preconditioner needs at most half of Jacobi's iterations."""
+    import json
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    wpath = os.path.join(root, "paper_2111_03541_amd", "weights", "poisson96")
+    assert os.path.exists(wpath + ".npy"), "trained weights missing from the package"
+    meta = json.load(open(wpath + ".json"))
+    net = mf.Net(tuple(meta["grid"]), meta["channels"], seed=0)
+    net.load_params(wpath)
+    dev = torch.device("cuda:0")
+    n = 96
+    mesh = W.structured_mesh((n, n, n))
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 1)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    mask = torch.from_numpy(W.boundary_node_mask(mesh.shape)).to(dev)
+    rp, ci, _ = pat.device_arrays()
+    for seed in (20000, 20001):
+        rng = np.random.default_rng(seed)
+        sigma = float(rng.uniform(1.0, 2.0))
+        say("held-out 96^3 seed", seed, "sigma", round(sigma, 3))
+        k = torch.from_numpy(W.grf_lognormal_elem((n, n, n), sigma, 0.1, seed + 1)).to(dev)
+        f = torch.from_numpy(W.uniform_nodal(1, mesh.n_nodes, 0, 1, seed + 2)).to(dev)
+        K, d = pat.assemble(mf.Form(mf.POISSON, coef=1.0), coords, precision=mf.F64, elem_param=k,
+                            nodal_src=f, dirichlet=mask)
+        net.set_system(rp, ci, K, mask)
+        its = {}
+        for name, pc in (("jacobi", mf.PRECOND_JACOBI), ("learned", mf.PRECOND_NN)):
+            _, res = mf.pcg(rp, ci, K, d, tol=1e-8, maxit=20000, precond=pc,
+                            net=net if pc == mf.PRECOND_NN else None)
+            assert res["converged"] and res["true_relres"] <= 1e-8, (name, res)
+            its[name] = res["iterations"]
+        say("iterations", its)
+        assert its["learned"] <= 0.5 * its["jacobi"], its
