@@ -10,8 +10,10 @@
 //   3x3x3 convolutions, zero padding, no bias (N is linear in v).  z = 0 on Dirichlet rows.
 // Training loss for a residual r: |K z - r|^2 / |r|^2, minimised by Adam; the gradient
 // is the adjoint of the linear network (weight gradients only, v does not depend on the
-// parameters).  Convolutions have at most 8 channels here, so they are bandwidth-bound
-// and run on the vector units; no MFMA is used in this file.
+// parameters).  Convolutions have at most 8 channels here, so they are bandwidth- and
+// latency-bound and run on the vector units; no MFMA is used in this file.  Inference
+// fuses the three convolutions and the prolongation of each level into one kernel over
+// LDS tiles; training keeps them separate because the weight gradients need h1 and h2.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -137,6 +139,98 @@ __global__ void __launch_bounds__(kThreads) k_conv(const TI* __restrict__ in, co
     }
 #pragma unroll
     for (int o = 0; o < COUT; ++o) st(out, (int64_t)o * n + t, acc[o]);
+}
+
+// Inference for one level l >= 1, fused over a T^3 tile of output points: the input v_l
+// with a three-point halo, h1 = conv_1(v) and h2 = conv_2(h1) on the shrinking halos (BF16
+// in LDS, zero outside the grid, as the unfused kernels store them), y = conv_3(h2), and
+// out = y + P coarse (coarse == nullptr on the coarsest level).  The arithmetic order per
+// point is that of k_conv and k_prolong_add.
+template <int C, int T>
+__global__ void __launch_bounds__(kThreads) k_level_fused(const bf16* __restrict__ v, Grid g,
+                                                          const float* __restrict__ w1, const float* __restrict__ w2,
+                                                          const float* __restrict__ w3,
+                                                          const float* __restrict__ coarse, Grid gc,
+                                                          float* __restrict__ out)
+{
+    constexpr int A = T + 6, B = T + 4, D = T + 2;  // tile edges of v, h1, h2
+    __shared__ float sv[A * A * A];
+    __shared__ bf16 sh1[C][B * B * B];
+    __shared__ bf16 sh2[C][D * D * D];
+    const int tid = threadIdx.x;
+    const int ntx = (g.nx + T - 1) / T, nty = (g.ny + T - 1) / T;
+    const int bt = blockIdx.x;
+    const int x0 = (bt % ntx) * T, y0 = ((bt / ntx) % nty) * T, z0 = (bt / (ntx * nty)) * T;
+    auto inside = [&](int x, int y, int z) {
+        return x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+    };
+    for (int i = tid; i < A * A * A; i += kThreads) {
+        const int lx = i % A, ly = (i / A) % A, lz = i / (A * A);
+        const int x = x0 - 3 + lx, y = y0 - 3 + ly, z = z0 - 3 + lz;
+        sv[i] = inside(x, y, z) ? bf2f(v[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)]) : 0.f;
+    }
+    __syncthreads();
+    for (int i = tid; i < B * B * B; i += kThreads) {
+        const int lx = i % B, ly = (i / B) % B, lz = i / (B * B);
+        float a[C];
+#pragma unroll
+        for (int o = 0; o < C; ++o) a[o] = 0.f;
+        if (inside(x0 - 2 + lx, y0 - 2 + ly, z0 - 2 + lz)) {
+#pragma unroll
+            for (int tap = 0; tap < 27; ++tap) {
+                const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+                const float xv = sv[(lx + 1 + dx) + A * ((ly + 1 + dy) + A * (lz + 1 + dz))];
+#pragma unroll
+                for (int o = 0; o < C; ++o) a[o] = fmaf(w1[o * 27 + tap], xv, a[o]);
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < C; ++o) sh1[o][i] = f2bf(a[o]);
+    }
+    __syncthreads();
+    for (int i = tid; i < D * D * D; i += kThreads) {
+        const int lx = i % D, ly = (i / D) % D, lz = i / (D * D);
+        float a[C];
+#pragma unroll
+        for (int o = 0; o < C; ++o) a[o] = 0.f;
+        if (inside(x0 - 1 + lx, y0 - 1 + ly, z0 - 1 + lz)) {
+#pragma unroll
+            for (int tap = 0; tap < 27; ++tap) {
+                const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+                const int q = (lx + 1 + dx) + B * ((ly + 1 + dy) + B * (lz + 1 + dz));
+#pragma unroll
+                for (int ci = 0; ci < C; ++ci) {
+                    const float xv = bf2f(sh1[ci][q]);
+#pragma unroll
+                    for (int o = 0; o < C; ++o) a[o] = fmaf(w2[(o * C + ci) * 27 + tap], xv, a[o]);
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < C; ++o) sh2[o][i] = f2bf(a[o]);
+    }
+    __syncthreads();
+    for (int i = tid; i < T * T * T; i += kThreads) {
+        const int lx = i % T, ly = (i / T) % T, lz = i / (T * T);
+        const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+        if (!inside(x, y, z)) continue;
+        float a = 0.f;
+#pragma unroll
+        for (int tap = 0; tap < 27; ++tap) {
+            const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+            const int q = (lx + 1 + dx) + D * ((ly + 1 + dy) + D * (lz + 1 + dz));
+#pragma unroll
+            for (int ci = 0; ci < C; ++ci) a = fmaf(w3[ci * 27 + tap], bf2f(sh2[ci][q]), a);
+        }
+        float p = 0.f;
+        if (coarse) {
+            const int xa = x >> 1, xb = (x + 1) >> 1, ya = y >> 1, yb = (y + 1) >> 1, za = z >> 1, zb = (z + 1) >> 1;
+            auto Cv = [&](int aa, int bb, int dd) { return coarse[aa + (int64_t)gc.nx * (bb + (int64_t)gc.ny * dd)]; };
+            p = 0.125f * (Cv(xa, ya, za) + Cv(xb, ya, za) + Cv(xa, yb, za) + Cv(xb, yb, za) + Cv(xa, ya, zb) +
+                          Cv(xb, ya, zb) + Cv(xa, yb, zb) + Cv(xb, yb, zb));
+        }
+        out[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = a + p;
+    }
 }
 
 // partial[(o*CIN + i)*27 + tap][chunk] = sum over the chunk of gy[o][p] * x[i][p + d_tap]
@@ -478,9 +572,52 @@ mf_status nn_forward(mf_nn_s* N, const double* r, double* z, float* y0, hipStrea
     return MF_OK;
 }
 
+template <int T>
+mf_status level_fused_dispatch(int c, const bf16* v, Grid g, const float* w1, const float* w2, const float* w3,
+                               const float* coarse, Grid gc, float* out, hipStream_t s)
+{
+    const int64_t tiles = (int64_t)((g.nx + T - 1) / T) * ((g.ny + T - 1) / T) * ((g.nz + T - 1) / T);
+#define MF_LEVEL(CC)                                                                                        \
+    if (c == CC) {                                                                                          \
+        k_level_fused<CC, T><<<(unsigned)tiles, kThreads, 0, s>>>(v, g, w1, w2, w3, coarse, gc, out);     \
+        return MF_OK;                                                                                       \
+    }
+    MF_LEVEL(1) MF_LEVEL(2) MF_LEVEL(4) MF_LEVEL(8)
+#undef MF_LEVEL
+    return set_error(MF_ERR_UNSUPPORTED, "fused level with %d channels not instantiated", c);
+}
+
+// Inference: the restriction chain, then one fused kernel per level from the coarsest
+// up (each adds the prolongation of the level below it), then the level-0 pass.
+mf_status nn_infer(mf_nn_s* N, const double* r, double* z, hipStream_t s)
+{
+    const int64_t n = N->n0;
+    k_input<<<nblk(n), kThreads, 0, s>>>(r, N->dm, n, N->vin[0]);
+    for (int l = 1; l < N->L; ++l)
+        k_restrict<bf16, bf16><<<nblk(N->g[l].n()), kThreads, 0, s>>>(N->vin[l - 1], N->g[l - 1], N->vin[l], N->g[l]);
+    for (int l = N->L - 1; l >= 1; --l) {
+        const int b = 1 + 3 * (l - 1);
+        const float* coarse = l == N->L - 1 ? nullptr : (l + 1 == N->L - 1 ? N->y[l + 1] : N->acc[l + 1]);
+        float* out = l == N->L - 1 ? N->y[l] : N->acc[l];
+        const Grid gc = l + 1 < N->L ? N->g[l + 1] : N->g[l];
+        const float* w1 = N->pb + N->w_off[b];
+        const float* w2 = N->pb + N->w_off[b + 1];
+        const float* w3 = N->pb + N->w_off[b + 2];
+        if (N->g[l].n() > 50000)
+            NN_TRY(level_fused_dispatch<8>(N->ch[l], N->vin[l], N->g[l], w1, w2, w3, coarse, gc, out, s));
+        else
+            NN_TRY(level_fused_dispatch<4>(N->ch[l], N->vin[l], N->g[l], w1, w2, w3, coarse, gc, out, s));
+    }
+    const float* acc1 = N->L > 2 ? N->acc[1] : (N->L == 2 ? N->y[1] : nullptr);
+    k_final<<<nblk(n), kThreads, 0, s>>>(N->vin[0], N->pb + N->w_off[0], acc1, N->L > 1 ? N->g[1] : N->g[0], N->g[0],
+                                         N->dm, N->mask, z, nullptr);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
 mf_status nn_apply_cb(void* ctx, const double* r, double* z, hipStream_t s)
 {
-    return nn_forward((mf_nn_s*)ctx, r, z, nullptr, s);
+    return nn_infer((mf_nn_s*)ctx, r, z, s);
 }
 
 // weight gradient of conv(x) -> gy into grad[off ...]

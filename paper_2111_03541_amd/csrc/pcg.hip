@@ -2,12 +2,12 @@
 // which the paper leaves open).  FP64 throughout.
 //
 // One iteration, all scalars kept on the device:
-//   k_spmv_dot   q = K p, partial sums of p.q
-//   k_reduce     alpha = (r.z) / (p.q)
-//   k_update     x += alpha p, r -= alpha q, z = M r, partial sums of r.z, r.r
-//                (k_update_dots for Jacobi / none; for an external apply the update,
-//                the apply and the dots r.z, r.r, z.r_old are separate steps)
-//   k_reduce     beta = (r.z)_new / (r.z) (flexible: (z.(r - r_old)) / (r.z)_old)
+//   k_spmv_dot   q = K p, partial sums of p.q; the last block to finish sums the
+//                partials (fixed order) into alpha = (r.z) / (p.q)
+//   k_update_dots  x += alpha p, r -= alpha q, z = M r, partial sums of r.z, r.r; its
+//                last block forms beta = (r.z)_new / (r.z).  For an external apply the
+//                update (k_update), the apply and the dots (k_dots: r.z, r.r, z.r_old,
+//                flexible beta = (z.(r - r_old)) / (r.z)_old) are separate steps.
 //   k_dir        p = z + beta p
 // Partial sums use fixed block order, so a run is bit-reproducible.  Chunks of
 // iterations are captured once into a HIP graph and replayed; between chunks the host
@@ -54,13 +54,75 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
     return s;  // valid in thread 0
 }
 
+// True in every thread of the block that finishes last among the grid's blocks.  Each
+// block's thread 0 has written its partial sums before the call; the release fence and
+// the counter make them visible to the last block, which re-arms the counter.
+__device__ __forceinline__ bool last_block(unsigned int* cnt)
+{
+    __shared__ int is_last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        is_last = atomicAdd(cnt, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (is_last) __threadfence();
+    return is_last;
+}
+
+// Scalars (device): s[0] = rz, s[1] = pq, s[2] = alpha, s[3] = beta, s[4] = rr, s[5] = rz_new,
+// s[6] = zdr (flexible numerator), s[7] = fallback count, s[8] = breakdown flag
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RZNEW, S_ZDR, S_FALLBACK, S_BREAK, S_COUNT };
+
+// alpha = (r.z) / (p.q) from nb block partials of p.q, summed in a fixed order by one
+// block (all its threads call this); cnt (if any) is re-armed.
+__device__ __forceinline__ void finish_alpha(const double* partial, int nb, double* s, double* sh,
+                                             unsigned int* cnt)
+{
+    double v = 0.0;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) v += partial[k];
+    const double pq = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+        s[S_PQ] = pq;
+        const bool ok = pq > 0.0 && isfinite(pq);
+        if (!ok) s[S_BREAK] = 1.0;
+        s[S_ALPHA] = ok ? s[S_RZ] / pq : 0.0;
+        if (cnt) *cnt = 0u;
+    }
+}
+
+// beta from the partials [0..nb) r.z, [nb..2nb) r.r, [2nb..3nb) z.r_old;
+// flexible: beta = (z.r - z.r_old) / rz_old
+__device__ __forceinline__ void finish_beta(const double* partial, int nb, double* s, int flexible, double* sh,
+                                            unsigned int* cnt)
+{
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        a += partial[k];
+        b += partial[nb + k];
+        c += partial[2 * nb + k];
+    }
+    const double rz = block_sum(a, sh);
+    const double rr = block_sum(b, sh);
+    const double zro = block_sum(c, sh);
+    if (threadIdx.x == 0) {
+        const double rz_old = s[S_RZ];
+        const double num = flexible ? rz - zro : rz;
+        s[S_BETA] = rz_old != 0.0 ? num / rz_old : 0.0;
+        s[S_RZNEW] = rz;
+        s[S_RZ] = rz;
+        s[S_RR] = rr;
+        if (!(rz > 0.0) || !isfinite(rz)) s[S_BREAK] = 1.0;
+        if (cnt) *cnt = 0u;
+    }
+}
+
 // y = A x (CSR), partial[block] = sum over the block's rows of w[row] * y[row] (w may be null)
 __global__ void __launch_bounds__(kThreads) k_spmv_dot(int n, const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci,
                                                        const double* __restrict__ v,
                                                        const double* __restrict__ x, double* __restrict__ y,
-                                                       const double* __restrict__ w, double* __restrict__ partial,
-                                                       int rows_per_block_iter)
+                                                       const double* __restrict__ w, double* partial,
+                                                       unsigned int* cnt, double* s)
 {
     __shared__ double sh[kThreads / 64];
     const int lane = threadIdx.x % kLanesPerRow;
@@ -80,28 +142,11 @@ __global__ void __launch_bounds__(kThreads) k_spmv_dot(int n, const int32_t* __r
             if (w) acc_dot = fma(w[row], s, acc_dot);
         }
     }
-    (void)rows_per_block_iter;
     const double t = block_sum(acc_dot, sh);
     if (threadIdx.x == 0 && partial) partial[blockIdx.x] = t;
+    if (cnt && last_block(cnt)) finish_alpha(partial, gridDim.x, s, sh, cnt);
 }
 
-// Scalars (device): s[0] = rz, s[1] = pq, s[2] = alpha, s[3] = beta, s[4] = rr, s[5] = rz_new,
-// s[6] = zdr (flexible numerator), s[7] = fallback count, s[8] = breakdown flag
-enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_RZNEW, S_ZDR, S_FALLBACK, S_BREAK, S_COUNT };
-
-__global__ void k_reduce_alpha(const double* __restrict__ partial, int nb, double* __restrict__ s)
-{
-    __shared__ double sh[kThreads / 64];
-    double v = 0.0;
-    for (int k = threadIdx.x; k < nb; k += blockDim.x) v += partial[k];
-    const double pq = block_sum(v, sh);
-    if (threadIdx.x == 0) {
-        s[S_PQ] = pq;
-        const bool ok = pq > 0.0 && isfinite(pq);
-        if (!ok) s[S_BREAK] = 1.0;
-        s[S_ALPHA] = ok ? s[S_RZ] / pq : 0.0;
-    }
-}
 
 // x += alpha p; r -= alpha q; z = precond(r) (Jacobi here; external apply overwrites z
 // afterwards); partials: [0..nb) r.z, [nb..2nb) r.r, [2nb..3nb) z.r_old
@@ -123,11 +168,11 @@ __global__ void __launch_bounds__(kThreads) k_update(int n, const double* __rest
 
 // Jacobi iteration body in one pass: x += alpha p; r -= alpha q; z = D^-1 r (or z = r);
 // partial sums of r.z and r.r (the z.r_old slot is zero)
-__global__ void __launch_bounds__(kThreads) k_update_dots(int n, const double* __restrict__ s,
-                                                          double* __restrict__ x, double* __restrict__ r,
-                                                          const double* __restrict__ p, const double* __restrict__ q,
+__global__ void __launch_bounds__(kThreads) k_update_dots(int n, double* s, double* __restrict__ x,
+                                                          double* __restrict__ r, const double* __restrict__ p,
+                                                          const double* __restrict__ q,
                                                           const double* __restrict__ dinv, double* __restrict__ z,
-                                                          int jacobi, double* __restrict__ partial, int nb)
+                                                          int jacobi, double* partial, int nb, unsigned int* cnt)
 {
     __shared__ double sh[kThreads / 64];
     const double alpha = s[S_ALPHA];
@@ -148,12 +193,13 @@ __global__ void __launch_bounds__(kThreads) k_update_dots(int n, const double* _
         partial[nb + blockIdx.x] = b;
         partial[2 * nb + blockIdx.x] = 0.0;
     }
+    if (last_block(cnt)) finish_beta(partial, nb, s, 0, sh, cnt);
 }
 
 // partial dots after z is known: r.z, r.r, z.r_old
 __global__ void __launch_bounds__(kThreads) k_dots(int n, const double* __restrict__ r, const double* __restrict__ z,
-                                                   const double* __restrict__ r_old, double* __restrict__ partial,
-                                                   int nb)
+                                                   const double* __restrict__ r_old, double* partial, int nb,
+                                                   unsigned int* cnt, double* s, int flexible)
 {
     __shared__ double sh[kThreads / 64];
     double rz = 0.0, rr = 0.0, zro = 0.0;
@@ -171,30 +217,13 @@ __global__ void __launch_bounds__(kThreads) k_dots(int n, const double* __restri
         partial[nb + blockIdx.x] = b;
         partial[2 * nb + blockIdx.x] = c;
     }
+    if (cnt && last_block(cnt)) finish_beta(partial, nb, s, flexible, sh, cnt);
 }
 
-// beta from the partials; flexible: beta = (z.r - z.r_old) / rz_old
-__global__ void k_reduce_beta(const double* __restrict__ partial, int nb, double* __restrict__ s, int flexible)
+__global__ void k_reduce_beta(const double* partial, int nb, double* s, int flexible)
 {
     __shared__ double sh[kThreads / 64];
-    double a = 0.0, b = 0.0, c = 0.0;
-    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-        a += partial[k];
-        b += partial[nb + k];
-        c += partial[2 * nb + k];
-    }
-    const double rz = block_sum(a, sh);
-    const double rr = block_sum(b, sh);
-    const double zro = block_sum(c, sh);
-    if (threadIdx.x == 0) {
-        const double rz_old = s[S_RZ];
-        const double num = flexible ? rz - zro : rz;
-        s[S_BETA] = rz_old != 0.0 ? num / rz_old : 0.0;
-        s[S_RZNEW] = rz;
-        s[S_RZ] = rz;
-        s[S_RR] = rr;
-        if (!(rz > 0.0) || !isfinite(rz)) s[S_BREAK] = 1.0;
-    }
+    finish_beta(partial, nb, s, flexible, sh, nullptr);
 }
 
 __global__ void __launch_bounds__(kThreads) k_dir(int n, const double* __restrict__ s, const double* __restrict__ z,
@@ -308,7 +337,8 @@ mf_status run_spmv(const mf_csr* A, const double* x, double* y, hipStream_t s)
     const int n = (int)A->n_rows;
     if (n == 0) return MF_OK;
     const int blocks = (int)std::min<int64_t>(kMaxBlocks, (n + (kThreads / kLanesPerRow) - 1) / (kThreads / kLanesPerRow));
-    k_spmv_dot<<<blocks, kThreads, 0, s>>>(n, A->row_ptr, A->col_idx, A->values, x, y, nullptr, nullptr, 0);
+    k_spmv_dot<<<blocks, kThreads, 0, s>>>(n, A->row_ptr, A->col_idx, A->values, x, y, nullptr, nullptr, nullptr,
+                                           nullptr);
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
@@ -350,7 +380,8 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
     double* partial = (double*)dalloc(sizeof(double) * 3 * nb);
     double* sc = (double*)dalloc(sizeof(double) * (S_COUNT + 2));
     int* flag = (int*)dalloc(sizeof(int));
-    if (!dinv || !r || !r_old || !z || !p || !q || !partial || !sc || !flag)
+    unsigned int* cnt = (unsigned int*)dalloc(sizeof(unsigned int) * 2);
+    if (!dinv || !r || !r_old || !z || !p || !q || !partial || !sc || !flag || !cnt)
         return set_error(MF_ERR_OOM, "PCG workspace allocation failed");
 
     const bool external = a.precond == MF_PRECOND_EXTERNAL;
@@ -358,16 +389,17 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
     const int flexible = external ? 1 : 0;
 
     k_set<<<1, 64, 0, s>>>(sc, S_COUNT + 2, 0.0);
+    MF_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned int) * 2, s));
     k_init<<<vec_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, a.b, dinv, a.x, r, z, p, external ? 1 : jac);
     if (external) {
         mf_status st = a.apply(a.apply_ctx, r, z, s);
         if (st != MF_OK) return st;
-        k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, nullptr, partial, vec_blocks);
+        k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, nullptr, partial, vec_blocks, nullptr, nullptr, 0);
         k_check_external<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, flag);
         k_jacobi_if<<<vec_blocks, kThreads, 0, s>>>(n, flag, dinv, r, z);
         MF_HIP(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     }
-    k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, nullptr, partial, vec_blocks);
+    k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, nullptr, partial, vec_blocks, nullptr, nullptr, 0);
     k_reduce_beta<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, 0);
     MF_HIP(hipGetLastError());
 
@@ -384,11 +416,10 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
     }
 
     auto iteration = [&]() -> mf_status {
-        k_spmv_dot<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, p, q, p, partial, 0);
-        k_reduce_alpha<<<1, kThreads, 0, s>>>(partial, spmv_blocks, sc);
+        k_spmv_dot<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, p, q, p, partial, cnt, sc);
         if (!external) {
-            k_update_dots<<<vec_blocks, kThreads, 0, s>>>(n, sc, a.x, r, p, q, dinv, z, jac, partial, vec_blocks);
-            k_reduce_beta<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, 0);
+            k_update_dots<<<vec_blocks, kThreads, 0, s>>>(n, sc, a.x, r, p, q, dinv, z, jac, partial, vec_blocks,
+                                                          cnt + 1);
             k_dir<<<vec_blocks, kThreads, 0, s>>>(n, sc, z, p);
             return MF_OK;
         }
@@ -396,12 +427,12 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
         {
             mf_status st = a.apply(a.apply_ctx, r, z, s);
             if (st != MF_OK) return st;
-            k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, nullptr, partial, vec_blocks);
+            k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, nullptr, partial, vec_blocks, nullptr, nullptr, 0);
             k_check_external<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, flag);
             k_jacobi_if<<<vec_blocks, kThreads, 0, s>>>(n, flag, dinv, r, z);
         }
-        k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, flexible ? r_old : nullptr, partial, vec_blocks);
-        k_reduce_beta<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, flexible);
+        k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, flexible ? r_old : nullptr, partial, vec_blocks, cnt + 1, sc,
+                                               flexible);
         k_dir<<<vec_blocks, kThreads, 0, s>>>(n, sc, z, p);
         return MF_OK;
     };

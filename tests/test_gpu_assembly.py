@@ -230,6 +230,68 @@ def test_elasticity_64cubed_sampled_rows(mf, prec):
     assert worst_d <= (TOL[prec] * 10 if prec else TOL[prec])
 
 
+def check_sampled(K, d, rp, ci, ref, nf, mask=None):
+    """Worst row-scaled K error and d error of sampled rows against oracle rows; with a
+    mask the oracle rows get the homogeneous Dirichlet elimination applied here."""
+    worst_k = worst_d = 0.0
+    for v, (cols, Krows, dref) in ref.items():
+        dref = dref.copy()
+        for i in range(nf):
+            r = nf * v + i
+            sl = slice(rp[r], rp[r + 1])
+            assert np.array_equal(ci[sl], cols)
+            want = Krows[i].copy()
+            if mask is not None:
+                if mask[r]:
+                    want = (cols == r).astype(np.float64)
+                    dref[i] = 0.0
+                else:
+                    want[mask[cols] != 0] = 0.0
+            scale = np.max(np.abs(want))
+            worst_k = max(worst_k, np.max(np.abs(K[sl] - want)) / scale)
+        worst_d = max(worst_d, np.max(np.abs(d[nf * v:nf * v + nf] - dref)) / max(np.max(np.abs(dref)), 1e-300))
+    return worst_k, worst_d
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_ns_48cubed_sampled_rows(mf, prec):
+    """Full-size SUPG Navier-Stokes Jacobian, 48^3 Q1 on the unit cube, rho 1, mu 0.01,
+    smooth random velocity, pressure U[-0.5,0.5]: sampled rows against the oracle."""
+    say("ns 48^3 sampled", prec)
+    mesh = W.structured_mesh((48, 48, 48))
+    params, _, _, state = make_inputs(O.NS_SUPG, mesh, seed=5)
+    pat = gpu_pattern(mf, mesh, 4)
+    K, d = run_gpu(mf, pat, O.NS_SUPG, params, mesh, prec, None, None, state)
+    rp, ci, _ = pat.arrays()
+    nodes = sampled_nodes(mesh.shape, 80, 13)
+    ref = oracle_rows(mesh, nodes, O.NS_SUPG, 4, params, state=rounded(state, prec))
+    wk, wd = check_sampled(K, d, rp, ci, ref, 4)
+    say(f"  sampled K err {wk:.3e} d err {wd:.3e}")
+    assert wk <= TOL[prec]
+    assert wd <= TOL[prec] * (10 if prec else 1)
+
+
+def test_poisson_96cubed_sampled_rows_dirichlet(mf):
+    """Full-size 3D Poisson, 96^3 Q1, lognormal Gaussian-field conductivity, f ~ U[0,1],
+    u = 0 on the boundary (55,298 constrained rows), FP64: sampled rows against the
+    oracle with the elimination applied."""
+    say("poisson 96^3 sampled")
+    n = (96, 96, 96)
+    mesh = W.structured_mesh(n)
+    k = W.grf_lognormal_elem(n, 1.5, 0.1, 10001)
+    f = W.uniform_nodal(1, mesh.n_nodes, 0, 1, 10002)
+    mask = W.boundary_node_mask(n)
+    assert int(mask.sum()) == 55298
+    pat = gpu_pattern(mf, mesh, 1)
+    K, d = run_gpu(mf, pat, O.POISSON, {"coef": 1.0}, mesh, 0, k, f, None, mask=mask)
+    rp, ci, _ = pat.arrays()
+    nodes = sampled_nodes(n, 100, 17)
+    ref = oracle_rows(mesh, nodes, O.POISSON, 1, {"coef": 1.0}, elem_param=k, nodal_src=f)
+    wk, wd = check_sampled(K, d, rp, ci, ref, 1, mask=mask)
+    say(f"  sampled K err {wk:.3e} d err {wd:.3e}")
+    assert wk <= TOL[0] and wd <= TOL[0]
+
+
 def test_inverted_element_sets_status(mf):
     say("inverted element")
     mesh = W.structured_mesh((3, 3, 3))

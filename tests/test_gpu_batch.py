@@ -96,3 +96,48 @@ def test_batch_graph_replays_and_tuner_cache(mf):
         for (K0, d0), p in zip(first, batch.problems):
             assert torch.allclose(p["K"], K0, rtol=1e-5, atol=1e-6 * float(K0.abs().max()))
             assert torch.allclose(p["d"], d0, rtol=1e-5, atol=1e-6 * float(d0.abs().max() + 1e-30))
+
+
+def test_batch_256_problems_sampled_against_oracle(mf):
+    """The full batched workload: 256 problems with n_x, n_y, n_z ~ U{8..48} (seed 6+p),
+    +-20% jitter, even p Poisson (lognormal k, f ~ U[0,1]), odd p elasticity (lognormal
+    E, nu 0.3, b ~ U[-1,1]), FP32, one persistent launch.  Whole systems of six problems
+    (the largest of each form, the first two, two drawn at random) against the oracle."""
+    sizes = W.batch_problem_sizes(256, 8, 48, base_seed=6)
+    say("batch 256, sizes drawn")
+    probs, host = [], []
+    for p, n in enumerate(sizes):
+        mesh = W.structured_mesh(n, jitter=0.2, seed=6 + p)
+        elastic = p % 2 == 1
+        nf = 3 if elastic else 1
+        ep = W.lognormal_elem(mesh.n_elems, 0.5, 10_000 + p)
+        src = W.uniform_nodal(nf, mesh.n_nodes, -1.0 if elastic else 0.0, 1.0, 20_000 + p)
+        pat = mf.Pattern(torch.from_numpy(mesh.conn).cuda(), mesh.n_nodes, 3, nf)
+        form = mf.Form(mf.ELASTICITY, coef=1.0, nu=0.3) if elastic else mf.Form(mf.POISSON, coef=1.0)
+        probs.append({"pattern": pat, "form": form, "coords": torch.from_numpy(mesh.coords).cuda(),
+                      "elem_param": torch.from_numpy(ep).float().cuda(),
+                      "nodal_src": torch.from_numpy(src).float().cuda()})
+        host.append((mesh, elastic, ep, src))
+    batch = mf.Batch(probs, precision=mf.F32)
+    stream = torch.cuda.Stream()
+    batch.run(stream)
+    stream.synchronize()
+    el = [p for p in range(256) if p % 2 == 1]
+    po = [p for p in range(256) if p % 2 == 0]
+    big_e = max(el, key=lambda p: host[p][0].n_elems)
+    big_p = max(po, key=lambda p: host[p][0].n_elems)
+    rng = np.random.default_rng(0)
+    pick = sorted({0, 1, big_e, big_p, *rng.choice(256, 2, replace=False).tolist()})
+    for p in pick:
+        mesh, elastic, ep, src = host[p]
+        say("  problem", p, sizes[p], "elasticity" if elastic else "poisson")
+        pr = batch.problems[p]
+        assert pr["pattern"].status()[0] == mf.OK
+        kind = O.ELASTICITY if elastic else O.POISSON
+        params = {"coef": 1.0, "nu": 0.3} if elastic else {"coef": 1.0}
+        ref = O.Pattern(mesh, 3 if elastic else 1)
+        Kr, dr = O.assemble(ref, kind, params, elem_param=rounded(ep, 1), nodal_src=rounded(src, 1))
+        K = pr["K"].double().cpu().numpy()
+        d = pr["d"].double().cpu().numpy()
+        assert rowscaled_error(ref, K, Kr) <= TOL[1]
+        assert vec_error(d, dr) <= TOL[1]

@@ -66,6 +66,25 @@ def test_forward_matches_oracle(mf):
     assert np.linalg.norm(z2 + 4.0 * z) <= 1e-6 * np.linalg.norm(z)
 
 
+def test_forward_large_tiles_matches_oracle(mf):
+    """Inference at a size whose first coarse level (37^3 nodes) runs the 8^3-tile fused
+    kernel, with ragged tiles on every level; against the oracle."""
+    say("nn forward 73^3")
+    ch = [1, 4, 8]
+    pat, K, d, mask = system(72, 21)
+    net = mf.Net((73, 73, 73), ch, seed=3)
+    theta = NR.init_params(ch, 13).astype(np.float32)
+    net.set_params(theta)
+    bind(mf, net, pat, K, mask)
+    rng = np.random.default_rng(8)
+    r = np.where(mask != 0, 0.0, rng.standard_normal(pat.n_rows))
+    z = net.apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    ref = NR.Net((73, 73, 73), ch).forward(bf16(theta), r, pat.to_scipy(K).diagonal(), mask)
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    say(f"  forward rel err {err:.2e}")
+    assert err < 2e-2
+
+
 def test_gradient_matches_oracle(mf):
     say("nn gradient 17^3")
     pat, K, d, mask = system(16, 9)
