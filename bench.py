@@ -10,8 +10,8 @@ FP64 (K = 64,701,513 nonzeros).  Inputs are resident in HBM before timing starts
 Printed: one JSON line with throughput (elements/s), the roofline of the assembly
 launch (algorithmic HBM bytes / measured time vs 8 TB/s) and the oracle timed on the
 host (one core) on the same workload.  Secondary records: the same assembly in FP32,
-PCG to 1e-8 on 96^3 Poisson with Jacobi and with the learned preconditioner, and the
-batched launch of 256 problems.
+PCG to 1e-8 on 96^3 Poisson with Jacobi and with the learned preconditioner, the
+batched launch of 256 problems, and the 48^3 Navier-Stokes Jacobian in FP32.
 """
 from __future__ import annotations
 
@@ -188,6 +188,36 @@ def bench_batch(dev, steps=10, warmup=3):
             "alg_bytes": B_alg, "hbm_frac": B_alg / t / HBM_PEAK, "tuned": info}
 
 
+def bench_ns(dev, steps=10, warmup=3, n=48):
+    """SUPG Navier-Stokes Jacobian on 48^3 Q1 hexes of the unit cube (4 fields per node),
+    rho 1, mu 0.01, smooth random velocity (8 Fourier modes, max |u| = 1), pressure
+    U[-0.5,0.5]; FP32 contractions on FP64 geometry."""
+    import torch
+    import workloads as W
+    import paper_2111_03541_amd as mf
+    mesh = W.structured_mesh((n, n, n))
+    state = np.zeros((4, mesh.n_nodes))
+    state[:3] = W.fourier_velocity(mesh.coords, 5)
+    state[3] = W.uniform_nodal(1, mesh.n_nodes, -0.5, 0.5, 3)[0]
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 4)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    st = torch.from_numpy(state).float().to(dev)
+    K = torch.empty(pat.nnz, dtype=torch.float32, device=dev)
+    d = torch.empty(pat.n_rows, dtype=torch.float32, device=dev)
+    form = mf.Form(mf.NS_SUPG, rho=1.0, mu=0.01, tau_m=3.417e-3, tau_c=1.059e-2)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        pat.assemble(form, coords, precision=mf.F32, lin_state=st, K=K, d=d)
+
+    _, per = time_launches(step, steps, warmup, stream)
+    avg = float(np.mean(per))
+    B = pat.nnz * 4 + pat.n_rows * 4 + 3 * mesh.n_nodes * 8 + 4 * mesh.n_nodes * 4
+    log(f"[bench] NS 48^3 FP32 avg {avg * 1e6:.1f} us ({mesh.n_elems / avg / 1e6:.1f} M el/s)")
+    return {"avg_us": avg * 1e6, "elems_per_s": mesh.n_elems / avg, "n_elems": mesh.n_elems, "nnz": pat.nnz,
+            "alg_bytes": B, "hbm_frac": B / avg / HBM_PEAK}
+
+
 def cpu_baseline(mesh, E, b):
     import oracle as O
     t0 = time.perf_counter()
@@ -303,6 +333,7 @@ def main():
     }
     record["secondary"]["poisson_96_pcg_time_to_1e-8"] = bench_pcg(dev)
     record["secondary"]["batched_256_f32"] = bench_batch(dev)
+    record["secondary"]["ns_48_f32"] = bench_ns(dev)
     if not args.no_cpu:
         log("[bench] timing the oracle on the host")
         record["cpu_baseline"] = cpu_baseline(mesh, E, b)

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "element.h"
 #include "mf_internal.h"
@@ -43,15 +44,21 @@ constexpr int kGeomItems = kLayerElems * 8;  // (element, Gauss point)
 static_assert(kColNodes * 8 * 2 == kThreads, "one lane per (node, element, half)");
 static_assert(kGeomItems <= kThreads, "one lane per (element, Gauss point)");
 
-// LDS layout of the per-Gauss-point vectors h (in units of T).  Strides are padded so
+// LDS layout of the per-Gauss-point records (in units of T).  Symmetric forms store h
+// (24 values); the flow form stores h, sqrt(W) N, sqrt(W) u.grad N, the state terms
+// u, grad u, Rm, sqrt(W), p and div u (58 values, NsRec below).  Strides are padded so
 // that adjacent lanes of phase B (the two halves of a node, and x-adjacent nodes) read
 // distinct banks with 16-byte loads.
-template <typename T>
+template <int FORM, typename T>
 struct HLayout {
-    static constexpr int SQ = sizeof(T) == 8 ? 26 : 28;                 // per Gauss point
-    static constexpr int SE = 8 * SQ + (sizeof(T) == 8 ? 2 : 4);        // per element
-    static constexpr int SL = kLayerElems * SE;                         // per element layer
+    static constexpr bool NS = FORM == MF_FORM_NS_SUPG;
+    static constexpr int SQ = NS ? 60 : (sizeof(T) == 8 ? 26 : 28);           // per Gauss point
+    static constexpr int SE = 8 * SQ + (sizeof(T) == 8 ? 2 : 4);              // per element
+    static constexpr int SL = kLayerElems * SE;                               // per element layer
 };
+
+// Offsets inside one flow-form record.
+enum NsRec { R_H = 0, R_N = 24, R_ADV = 32, R_U = 40, R_GU = 43, R_RM = 52, R_S = 55, R_P = 56, R_DIV = 57 };
 
 struct ColParams {
     mf_form form;
@@ -70,7 +77,10 @@ struct ColParams {
     unsigned long long* status;
 };
 
-typedef double Acc;
+// Row-buffer accumulators: FP64 for the symmetric forms in both precisions, FP32 for the
+// flow form (its 16-value blocks would not fit the LDS in FP64 next to the ring).
+template <int FORM>
+using AccT = typename std::conditional<FORM == MF_FORM_NS_SUPG, float, double>::type;
 
 // exchange a value with the adjacent lane (lane ^ 1)
 __device__ __forceinline__ double swap_adjacent(double v)
@@ -97,14 +107,15 @@ struct ColShared {
     static constexpr int NF = FormTraits<FORM, 3>::NF;
     static constexpr int NSRC = FormTraits<FORM, 3>::NSRC;
     static constexpr int NB = NF * NF;
-    T h[2 * HLayout<T>::SL];
-    T wf[2][kLayerElems][8][NF];
+    static constexpr bool NS = FORM == MF_FORM_NS_SUPG;
+    T h[2 * HLayout<FORM, T>::SL];
+    T wf[2][kLayerElems][NS ? 1 : 8][NF];
     T cf[2][kLayerElems][2];
     double x[3][kTileNodes][3];
     T u[3][kTileNodes][NSRC];
     double ep[2][kLayerElems];
-    Acc rowK[kColNodes][27 * NB];
-    Acc rowD[kColNodes][NF];
+    AccT<FORM> rowK[kColNodes][27 * NB];
+    AccT<FORM> rowD[kColNodes][NF];
     int ni[kColNodes][4];  // node id, first pair offset, degree, boundary bits
 };
 
@@ -200,7 +211,7 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
     const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
     const int slot = L & 1;
     if (!(det > 0.0)) atomicMin(p.status, (unsigned long long)(ex + p.nx * (ey + p.ny * L)));
-    const double ep = S.ep[slot][el];
+    const double ep = FORM == MF_FORM_NS_SUPG ? 1.0 : S.ep[slot][el];
     double coefA = 0.0, coefB = 0.0;
     if constexpr (FORM == MF_FORM_ELASTICITY) {
         const double E = p.form.coef * ep, nu = p.form.nu;
@@ -209,8 +220,74 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
     } else {
         coefA = p.form.coef * ep;
     }
-    T* hq = S.h + slot * HLayout<T>::SL + el * HLayout<T>::SE + q * HLayout<T>::SQ;
-    if constexpr (FORM == MF_FORM_MASS) {
+    T* hq = S.h + slot * HLayout<FORM, T>::SL + el * HLayout<FORM, T>::SE + q * HLayout<FORM, T>::SQ;
+    if constexpr (FORM == MF_FORM_NS_SUPG) {
+        // g = J^-T grad_xi N (FP64); state at the point: u, grad u, p, grad p, Rm, div u
+        const double r = 1.0 / det;
+        double Ji[3][3];
+        Ji[0][0] = c00 * r;
+        Ji[1][0] = c01 * r;
+        Ji[2][0] = c02 * r;
+        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+        double g[8][3];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                double v = 0.0;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) v = fma(dN[a][j], Ji[j][m], v);
+                g[a][m] = v;
+            }
+        double u[3] = {0, 0, 0}, gu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, pr = 0.0, gp[3] = {0, 0, 0};
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const double Ub = (double)U[b][m];
+                u[m] = fma(N[b], Ub, u[m]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) gu[m][k] = fma(g[b][k], Ub, gu[m][k]);  // du_m/dx_k
+            }
+            const double Pb = (double)U[b][3];
+            pr = fma(N[b], Pb, pr);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) gp[k] = fma(g[b][k], Pb, gp[k]);
+        }
+        const double rho = p.form.rho;
+        const double sw = sqrt(det);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            double adv = 0.0;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                hq[R_H + 3 * a + m] = (T)(sw * g[a][m]);
+                adv = fma(u[m], g[a][m], adv);
+            }
+            hq[R_N + a] = (T)(sw * N[a]);
+            hq[R_ADV + a] = (T)(sw * adv);
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            hq[R_U + m] = (T)u[m];
+            double c = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                hq[R_GU + 3 * m + k] = (T)gu[m][k];
+                c = fma(u[k], gu[m][k], c);
+            }
+            hq[R_RM + m] = (T)(rho * c + gp[m]);
+        }
+        hq[R_S] = (T)sw;
+        hq[R_P] = (T)pr;
+        hq[R_DIV] = (T)(gu[0][0] + gu[1][1] + gu[2][2]);
+        return;
+    } else if constexpr (FORM == MF_FORM_MASS) {
         hq[0] = (T)det;
     } else {
         const double r = 1.0 / det;
@@ -235,18 +312,20 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
                 hq[3 * a + m] = (T)v;
             }
     }
-    // load vector integrand W f(x_q) (times c for the mass form)
-    const double wscale = det * (FORM == MF_FORM_MASS ? coefA : 1.0);
+    if constexpr (FORM != MF_FORM_NS_SUPG) {
+        // load vector integrand W f(x_q) (times c for the mass form)
+        const double wscale = det * (FORM == MF_FORM_MASS ? coefA : 1.0);
 #pragma unroll
-    for (int i = 0; i < NF; ++i) {
-        double f = 0.0;
+        for (int i = 0; i < NF; ++i) {
+            double f = 0.0;
 #pragma unroll
-        for (int a = 0; a < 8; ++a) f = fma(N[a], (double)U[a][i], f);
-        S.wf[slot][el][q][i] = (T)(wscale * f);
-    }
-    if (q == 0) {
-        S.cf[slot][el][0] = (T)coefA;
-        S.cf[slot][el][1] = (T)coefB;
+            for (int a = 0; a < 8; ++a) f = fma(N[a], (double)U[a][i], f);
+            S.wf[slot][el][q][i] = (T)(wscale * f);
+        }
+        if (q == 0) {
+            S.cf[slot][el][0] = (T)coefA;
+            S.cf[slot][el][1] = (T)coefB;
+        }
     }
 }
 
@@ -256,7 +335,8 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
 {
     constexpr int NF = FormTraits<FORM, 3>::NF;
     constexpr int NB = NF * NF;
-    constexpr int NV = FORM == MF_FORM_ELASTICITY ? 9 : 1;
+    using Acc = AccT<FORM>;
+    constexpr int NV = FORM == MF_FORM_ELASTICITY ? 9 : (FORM == MF_FORM_NS_SUPG ? 16 : 1);
     const int tid = threadIdx.x;
     const int qh = tid & 1, pe = tid >> 1;
     const int al = pe & (kColNodes - 1), eps = pe / kColNodes;
@@ -268,7 +348,7 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
                        ez < p.nz;
     const int alpha = 7 - eps;  // the node's local index in the element
     const int slot = ez & 1, el = (alx + dx) + EXH * (aly + dy);
-    const T* he = S.h + slot * HLayout<T>::SL + el * HLayout<T>::SE;
+    const T* he = S.h + slot * HLayout<FORM, T>::SL + el * HLayout<FORM, T>::SE;
 
     T M[8][NV];
 #pragma unroll
@@ -285,12 +365,60 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int q = 4 * qh + k;
-            const T* hq = he + q * HLayout<T>::SQ;
+            const T* hq = he + q * HLayout<FORM, T>::SQ;
             double Fx[2], Fy[2];
             gauss_factors(k & 1, Fx);
             gauss_factors((k >> 1) & 1, Fy);
             const double Na = Fx[alpha & 1] * Fy[(alpha >> 1) & 1] * Fz[alpha >> 2];
-            if constexpr (FORM == MF_FORM_MASS) {
+            if constexpr (FORM == MF_FORM_NS_SUPG) {
+                // block (a, b) = sum over the point of (a-side term) x (b-side term) x (state
+                // coefficient); every product below carries W through the sqrt(W) factors
+                const T rho = (T)p.form.rho, mu = (T)p.form.mu, tm = (T)p.form.tau_m, tc = (T)p.form.tau_c;
+                T ha[3], u[3], gu[3][3], Rm[3];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    ha[m] = hq[R_H + 3 * alpha + m];
+                    u[m] = hq[R_U + m];
+                    Rm[m] = hq[R_RM + m];
+#pragma unroll
+                    for (int k2 = 0; k2 < 3; ++k2) gu[m][k2] = hq[R_GU + 3 * m + k2];
+                }
+                const T Nta = hq[R_N + alpha], aa = hq[R_ADV + alpha];
+                const T sw = hq[R_S], pr = hq[R_P], div = hq[R_DIV];
+                T cN[3][3], cH[3], sgu[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const T ci = -rho * u[i] + tm * rho * Rm[i];
+#pragma unroll
+                    for (int l = 0; l < 3; ++l) cN[i][l] = ci * ha[l] + tm * rho * rho * aa * gu[i][l];
+                    cH[i] = tc * ha[i];
+                    sgu[i] = ha[0] * gu[0][i] + ha[1] * gu[1][i] + ha[2] * gu[2][i];
+                }
+                const T d1 = -rho * aa, d3 = tm * rho * rho * aa, pa = tm * rho * aa;
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const T hb[3] = {hq[R_H + 3 * b], hq[R_H + 3 * b + 1], hq[R_H + 3 * b + 2]};
+                    const T Nb = hq[R_N + b], ab = hq[R_ADV + b];
+                    const T hab = ha[0] * hb[0] + ha[1] * hb[1] + ha[2] * hb[2];
+                    const T dg = d1 * Nb + mu * hab + d3 * ab;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+                        for (int l = 0; l < 3; ++l)
+                            M[b][4 * i + l] += cN[i][l] * Nb + cH[i] * hb[l] + (i == l ? dg : T(0));
+                        M[b][4 * i + 3] += -ha[i] * Nb + pa * hb[i];
+                        M[b][12 + i] += Nta * hb[i] + tm * rho * (sgu[i] * Nb + ha[i] * ab);
+                    }
+                    M[b][15] += tm * hab;
+                }
+                // d = -R at this point
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const T visc = ha[0] * gu[i][0] + ha[1] * gu[i][1] + ha[2] * gu[i][2];
+                    dp[i] -= sw * (-rho * aa * u[i] - ha[i] * pr + mu * visc + tm * rho * aa * Rm[i] + tc * ha[i] * div);
+                }
+                dp[3] -= sw * (Nta * div + tm * (ha[0] * Rm[0] + ha[1] * Rm[1] + ha[2] * Rm[2]));
+            } else if constexpr (FORM == MF_FORM_MASS) {
                 const T wa = hq[0] * (T)Na;
 #pragma unroll
                 for (int b = 0; b < 8; ++b)
@@ -316,8 +444,10 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
                     for (int b = 0; b < 8; ++b) M[b][0] += ha[0] * hb[b][0] + ha[1] * hb[b][1] + ha[2] * hb[b][2];
                 }
             }
+            if constexpr (FORM != MF_FORM_NS_SUPG) {
 #pragma unroll
-            for (int i = 0; i < NF; ++i) dp[i] += (T)Na * S.wf[slot][el][q][i];
+                for (int i = 0; i < NF; ++i) dp[i] += (T)Na * S.wf[slot][el][q][i];
+            }
         }
     }
     // add the two halves: lane qh keeps the blocks b = 4 qh .. 4 qh + 3
@@ -334,14 +464,18 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
     for (int i = 0; i < NF; ++i) dp[i] += swap_adjacent(dp[i]);
     if (!valid) return;
 
-    const T cA = S.cf[slot][el][0], cB = S.cf[slot][el][1];
+    const T cA = FORM == MF_FORM_NS_SUPG ? T(0) : S.cf[slot][el][0];
+    const T cB = FORM == MF_FORM_NS_SUPG ? T(0) : S.cf[slot][el][1];
     const int ax = alpha & 1, ay = (alpha >> 1) & 1, az = alpha >> 2;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int beta = b + 4 * qh;
         const int nslot = (qh - az + 1) * 9 + (((beta >> 1) & 1) - ay + 1) * 3 + ((beta & 1) - ax + 1);
         Acc* dst = &S.rowK[al][nslot * NB];
-        if constexpr (FORM == MF_FORM_ELASTICITY) {
+        if constexpr (FORM == MF_FORM_NS_SUPG) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) unsafeAtomicAdd(dst + v, (Acc)Mk[b][v]);
+        } else if constexpr (FORM == MF_FORM_ELASTICITY) {
             const T tr = Mk[b][0] + Mk[b][4] + Mk[b][8];
 #pragma unroll
             for (int i = 0; i < 3; ++i)
@@ -367,6 +501,7 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
     constexpr int NF = FormTraits<FORM, 3>::NF;
     constexpr int NB = NF * NF;
     constexpr int kRowSlots = 27 * NF;
+    using Acc = AccT<FORM>;
     T* K = (T*)p.K;
     T* d = (T*)p.d;
     const int NX = p.nx + 1, NY = p.ny + 1;
@@ -594,7 +729,7 @@ ColParams make_params(const AssembleArgs& A)
     p.coords = A.coords;
     p.nbr_ptr = P->nbr_ptr;
     p.elem_param = A.elem_param;
-    p.src = A.nodal_src;
+    p.src = A.form->kind == MF_FORM_NS_SUPG ? A.lin_state : A.nodal_src;
     p.dirichlet = A.dirichlet;
     p.field_major = P->numbering == MF_FIELD_MAJOR;
     p.n_pairs = (int)P->n_pairs;
@@ -632,6 +767,9 @@ mf_status dispatch(const AssembleArgs& A)
         case MF_FORM_MASS: return launch_column<MF_FORM_MASS, T>(A);
         case MF_FORM_POISSON: return launch_column<MF_FORM_POISSON, T>(A);
         case MF_FORM_ELASTICITY: return launch_column<MF_FORM_ELASTICITY, T>(A);
+        case MF_FORM_NS_SUPG:
+            if constexpr (sizeof(T) == 4) return launch_column<MF_FORM_NS_SUPG, T>(A);
+            return MF_ERR_UNSUPPORTED;
         default: return MF_ERR_UNSUPPORTED;
     }
 }
@@ -683,12 +821,11 @@ mf_status batch_launch(const void* dev_probs, void* dev_status, int n_probs, con
 }
 
 // Returns MF_ERR_UNSUPPORTED (without launching) when the case is not covered:
-// unstructured meshes, 2D, partial coupling, or the flow form.
+// unstructured meshes, 2D, partial coupling, or the flow form in FP64.
 mf_status assemble_column(const AssembleArgs& A)
 {
     const mf_pattern_s* P = A.P;
     if (!P->is_grid || P->dim != 3 || !P->full_coupling) return MF_ERR_UNSUPPORTED;
-    if (A.form->kind == MF_FORM_NS_SUPG) return MF_ERR_UNSUPPORTED;
     if (P->n_elems == 0) return MF_ERR_UNSUPPORTED;
     return A.prec == MF_F64 ? dispatch<double>(A) : dispatch<float>(A);
 }

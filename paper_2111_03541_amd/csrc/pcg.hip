@@ -2,13 +2,13 @@
 // which the paper leaves open).  FP64 throughout.
 //
 // One iteration, all scalars kept on the device:
-//   k_spmv_dot   q = K p, partial sums of p.q; the last block to finish sums the
-//                partials (fixed order) into alpha = (r.z) / (p.q)
+//   k_spmv_dir_dot  p = z + beta p (double-buffered) and q = K p in one pass, partial
+//                sums of p.q; the last block to finish sums the partials (fixed order)
+//                into alpha = (r.z) / (p.q)
 //   k_update_dots  x += alpha p, r -= alpha q, z = M r, partial sums of r.z, r.r; its
 //                last block forms beta = (r.z)_new / (r.z).  For an external apply the
 //                update (k_update), the apply and the dots (k_dots: r.z, r.r, z.r_old,
 //                flexible beta = (z.(r - r_old)) / (r.z)_old) are separate steps.
-//   k_dir        p = z + beta p
 // Partial sums use fixed block order, so a run is bit-reproducible.  Chunks of
 // iterations are captured once into a HIP graph and replayed; between chunks the host
 // reads the recurrence residual, and a candidate solution is accepted only when the
@@ -148,6 +148,46 @@ __global__ void __launch_bounds__(kThreads) k_spmv_dot(int n, const int32_t* __r
 }
 
 
+// p_new = z + beta p_old and q = K p_new in one pass (the direction update of the previous
+// iteration folded into the SpMV: each column value is formed on the fly, bit-identical
+// to the stored p_new); partial sums of p_new.q, finished into alpha by the last block.
+__global__ void __launch_bounds__(kThreads) k_spmv_dir_dot(int n, const int32_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ ci,
+                                                           const double* __restrict__ v,
+                                                           const double* __restrict__ z,
+                                                           const double* __restrict__ p_old,
+                                                           double* __restrict__ p_new, double* __restrict__ q,
+                                                           double* s, double* partial, unsigned int* cnt)
+{
+    __shared__ double sh[kThreads / 64];
+    const double beta = s[S_BETA];
+    const int lane = threadIdx.x % kLanesPerRow;
+    const int sub = threadIdx.x / kLanesPerRow;
+    constexpr int kSlots = kThreads / kLanesPerRow;
+    double acc_dot = 0.0;
+    for (int base = blockIdx.x * kSlots; base < n; base += gridDim.x * kSlots) {
+        const int row = base + sub;
+        double sum = 0.0;
+        if (row < n) {
+            const int k1 = rp[row + 1];
+            for (int k = rp[row] + lane; k < k1; k += kLanesPerRow) {
+                const int c = ci[k];
+                sum = fma(v[k], fma(beta, p_old[c], z[c]), sum);
+            }
+        }
+        sum = warp_sum_lanes16(sum);
+        if (row < n && lane == 0) {
+            const double pn = fma(beta, p_old[row], z[row]);
+            p_new[row] = pn;
+            q[row] = sum;
+            acc_dot = fma(pn, sum, acc_dot);
+        }
+    }
+    const double t = block_sum(acc_dot, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+    if (last_block(cnt)) finish_alpha(partial, gridDim.x, s, sh, cnt);
+}
+
 // x += alpha p; r -= alpha q; z = precond(r) (Jacobi here; external apply overwrites z
 // afterwards); partials: [0..nb) r.z, [nb..2nb) r.r, [2nb..3nb) z.r_old
 __global__ void __launch_bounds__(kThreads) k_update(int n, const double* __restrict__ s,
@@ -224,14 +264,6 @@ __global__ void k_reduce_beta(const double* partial, int nb, double* s, int flex
 {
     __shared__ double sh[kThreads / 64];
     finish_beta(partial, nb, s, flexible, sh, nullptr);
-}
-
-__global__ void __launch_bounds__(kThreads) k_dir(int n, const double* __restrict__ s, const double* __restrict__ z,
-                                                  double* __restrict__ p)
-{
-    const double beta = s[S_BETA];
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        p[i] = fma(beta, p[i], z[i]);
 }
 
 // diag inverse, x = 0, r = b, z = M b, p = z
@@ -376,12 +408,13 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
     double* r_old = (double*)dalloc(sizeof(double) * n);
     double* z = (double*)dalloc(sizeof(double) * n);
     double* p = (double*)dalloc(sizeof(double) * n);
+    double* p2 = (double*)dalloc(sizeof(double) * n);
     double* q = (double*)dalloc(sizeof(double) * n);
     double* partial = (double*)dalloc(sizeof(double) * 3 * nb);
     double* sc = (double*)dalloc(sizeof(double) * (S_COUNT + 2));
     int* flag = (int*)dalloc(sizeof(int));
     unsigned int* cnt = (unsigned int*)dalloc(sizeof(unsigned int) * 2);
-    if (!dinv || !r || !r_old || !z || !p || !q || !partial || !sc || !flag || !cnt)
+    if (!dinv || !r || !r_old || !z || !p || !p2 || !q || !partial || !sc || !flag || !cnt)
         return set_error(MF_ERR_OOM, "PCG workspace allocation failed");
 
     const bool external = a.precond == MF_PRECOND_EXTERNAL;
@@ -415,15 +448,20 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
         return MF_OK;
     }
 
-    auto iteration = [&]() -> mf_status {
-        k_spmv_dot<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, p, q, p, partial, cnt, sc);
+    // the direction alternates between two buffers: iteration k reads p_old = pb[k & 1]
+    // and writes p_new = pb[(k + 1) & 1]
+    double* pb[2] = {p, p2};
+    auto iteration = [&](int k) -> mf_status {
+        double* p_old = pb[k & 1];
+        double* p_new = pb[(k + 1) & 1];
+        k_spmv_dir_dot<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, z, p_old, p_new, q, sc,
+                                                        partial, cnt);
         if (!external) {
-            k_update_dots<<<vec_blocks, kThreads, 0, s>>>(n, sc, a.x, r, p, q, dinv, z, jac, partial, vec_blocks,
+            k_update_dots<<<vec_blocks, kThreads, 0, s>>>(n, sc, a.x, r, p_new, q, dinv, z, jac, partial, vec_blocks,
                                                           cnt + 1);
-            k_dir<<<vec_blocks, kThreads, 0, s>>>(n, sc, z, p);
             return MF_OK;
         }
-        k_update<<<vec_blocks, kThreads, 0, s>>>(n, sc, a.x, r, r_old, p, q, dinv, z, -1, flexible);
+        k_update<<<vec_blocks, kThreads, 0, s>>>(n, sc, a.x, r, r_old, p_new, q, dinv, z, -1, flexible);
         {
             mf_status st = a.apply(a.apply_ctx, r, z, s);
             if (st != MF_OK) return st;
@@ -433,20 +471,21 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
         }
         k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, flexible ? r_old : nullptr, partial, vec_blocks, cnt + 1, sc,
                                                flexible);
-        k_dir<<<vec_blocks, kThreads, 0, s>>>(n, sc, z, p);
         return MF_OK;
     };
 
-    const int chunk = a.check_every > 0 ? a.check_every : 8;
-    // capture one chunk of iterations as a graph when the preconditioner allows it
+    int chunk = a.check_every > 0 ? a.check_every : 8;
+    // capture one chunk of iterations as a graph when the preconditioner allows it; a
+    // graphed chunk is even so that the direction buffers are in step across replays
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     bool use_graph = a.use_graph && (!external || a.apply_graph_safe);
+    if (use_graph) chunk += chunk & 1;
     if (use_graph) {
         hipStreamCaptureMode mode = hipStreamCaptureModeThreadLocal;
         if (hipStreamBeginCapture(s, mode) == hipSuccess) {
             mf_status st = MF_OK;
-            for (int k = 0; k < chunk && st == MF_OK; ++k) st = iteration();
+            for (int k = 0; k < chunk && st == MF_OK; ++k) st = iteration(k);
             hipError_t e = hipStreamEndCapture(s, &graph);
             if (st != MF_OK) return st;
             if (e != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -476,7 +515,7 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
             MF_HIP(hipGraphLaunch(exec, s));
         } else {
             for (int k = 0; k < todo; ++k) {
-                mf_status st = iteration();
+                mf_status st = iteration(it + k);
                 if (st != MF_OK) return st;
             }
         }
