@@ -224,8 +224,7 @@ typedef struct {
 typedef struct {
     double tol;               /* stop when |b - K x|_2 / |b|_2 <= tol (true residual)      */
     int32_t maxit;
-    int32_t check_every;      /* iterations between host convergence checks (0 = 8; with
-                                 use_graph an odd value is rounded up to even)          */
+    int32_t check_every;      /* iterations between host convergence checks (0 = 8)       */
     int32_t use_graph;        /* 1: replay each chunk of iterations as a HIP graph (needs a
                                  non-default stream; silently off otherwise)              */
     mf_precond_kind precond;

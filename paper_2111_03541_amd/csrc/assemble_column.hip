@@ -39,10 +39,11 @@ constexpr int EXH = CX + 1, EYH = CY + 1;  // elements per layer around the colu
 constexpr int kLayerElems = EXH * EYH;
 constexpr int TX = CX + 2, TY = CY + 2;    // node tile per layer
 constexpr int kTileNodes = TX * TY;
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;  // two waves per SIMD with one workgroup per CU
+constexpr int kGeomThreads = 256;  // phase A: geometry on waves 0-3, write-out on waves 4-7
 constexpr int kGeomItems = kLayerElems * 8;  // (element, Gauss point)
-static_assert(kColNodes * 8 * 2 == kThreads, "one lane per (node, element, half)");
-static_assert(kGeomItems <= kThreads, "one lane per (element, Gauss point)");
+static_assert(kColNodes * 8 * 4 == kThreads, "one lane per (node, element, quarter)");
+static_assert(kGeomItems <= kGeomThreads, "one lane per (element, Gauss point)");
 
 // LDS layout of the per-Gauss-point records (in units of T).  Symmetric forms store h
 // (24 values); the flow form stores h, sqrt(W) N, sqrt(W) u.grad N, the state terms
@@ -82,16 +83,26 @@ struct ColParams {
 template <int FORM>
 using AccT = typename std::conditional<FORM == MF_FORM_NS_SUPG, float, double>::type;
 
-// exchange a value with the adjacent lane (lane ^ 1)
-__device__ __forceinline__ double swap_adjacent(double v)
+// value of the lane (lane ^ 1) or (lane ^ 2) of the same quad: DPP quad_perm [1,0,3,2]
+// (0xB1) and [2,3,0,1] (0x4E)
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0xB1, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0xB1, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ float swap_adjacent(float v)
+template <int CTRL>
+__device__ __forceinline__ float quad_swap(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+// sum over the four lanes of a quad, in every lane of it
+template <typename T>
+__device__ __forceinline__ T quad_sum(T v)
+{
+    v += quad_swap<0xB1>(v);
+    return v + quad_swap<0x4E>(v);
 }
 
 // 1D linear basis factors at the Gauss point of bit qb: F[0] = (1 - xi)/2, F[1] = (1 + xi)/2
@@ -329,7 +340,10 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
     }
 }
 
-// Phase B: lane (node al, element eps around it, half qh) of node layer kz.
+// Phase B: lane (node al, element eps around it, quarter bq) of node layer kz: the pair
+// blocks (a, b) for the two element nodes b = 2 bq, 2 bq + 1, over all eight Gauss
+// points.  The element's load-vector share of a is split by Gauss-point pairs between
+// the four lanes of (al, eps) and added across them.
 template <int FORM, typename T>
 __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>& S, int kz, int i0, int j0)
 {
@@ -338,7 +352,7 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
     using Acc = AccT<FORM>;
     constexpr int NV = FORM == MF_FORM_ELASTICITY ? 9 : (FORM == MF_FORM_NS_SUPG ? 16 : 1);
     const int tid = threadIdx.x;
-    const int qh = tid & 1, pe = tid >> 1;
+    const int bq = tid & 3, pe = tid >> 2;
     const int al = pe & (kColNodes - 1), eps = pe / kColNodes;
     const int alx = al % CX, aly = al / CX;
     const int gi = i0 + alx, gj = j0 + aly;
@@ -350,9 +364,9 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
     const int slot = ez & 1, el = (alx + dx) + EXH * (aly + dy);
     const T* he = S.h + slot * HLayout<FORM, T>::SL + el * HLayout<FORM, T>::SE;
 
-    T M[8][NV];
+    T M[2][NV];
 #pragma unroll
-    for (int b = 0; b < 8; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int v = 0; v < NV; ++v) M[b][v] = T(0);
     T dp[NF];
@@ -360,16 +374,10 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
     for (int i = 0; i < NF; ++i) dp[i] = T(0);
 
     if (valid) {
-        double Fz[2];
-        gauss_factors(qh, Fz);  // z factors of this half (q bit 2 = qh)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int q = 4 * qh + k;
+        const int fb = 2 * bq;  // first element node of this lane's pair
+#pragma unroll 2
+        for (int q = 0; q < 8; ++q) {
             const T* hq = he + q * HLayout<FORM, T>::SQ;
-            double Fx[2], Fy[2];
-            gauss_factors(k & 1, Fx);
-            gauss_factors((k >> 1) & 1, Fy);
-            const double Na = Fx[alpha & 1] * Fy[(alpha >> 1) & 1] * Fz[alpha >> 2];
             if constexpr (FORM == MF_FORM_NS_SUPG) {
                 // block (a, b) = sum over the point of (a-side term) x (b-side term) x (state
                 // coefficient); every product below carries W through the sqrt(W) factors
@@ -384,7 +392,6 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
                     for (int k2 = 0; k2 < 3; ++k2) gu[m][k2] = hq[R_GU + 3 * m + k2];
                 }
                 const T Nta = hq[R_N + alpha], aa = hq[R_ADV + alpha];
-                const T sw = hq[R_S], pr = hq[R_P], div = hq[R_DIV];
                 T cN[3][3], cH[3], sgu[3];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
@@ -396,9 +403,10 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
                 }
                 const T d1 = -rho * aa, d3 = tm * rho * rho * aa, pa = tm * rho * aa;
 #pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    const T hb[3] = {hq[R_H + 3 * b], hq[R_H + 3 * b + 1], hq[R_H + 3 * b + 2]};
-                    const T Nb = hq[R_N + b], ab = hq[R_ADV + b];
+                for (int b = 0; b < 2; ++b) {
+                    const int B = fb + b;
+                    const T hb[3] = {hq[R_H + 3 * B], hq[R_H + 3 * B + 1], hq[R_H + 3 * B + 2]};
+                    const T Nb = hq[R_N + B], ab = hq[R_ADV + B];
                     const T hab = ha[0] * hb[0] + ha[1] * hb[1] + ha[2] * hb[2];
                     const T dg = d1 * Nb + mu * hab + d3 * ab;
 #pragma unroll
@@ -411,117 +419,138 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
                     }
                     M[b][15] += tm * hab;
                 }
-                // d = -R at this point
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const T visc = ha[0] * gu[i][0] + ha[1] * gu[i][1] + ha[2] * gu[i][2];
-                    dp[i] -= sw * (-rho * aa * u[i] - ha[i] * pr + mu * visc + tm * rho * aa * Rm[i] + tc * ha[i] * div);
-                }
-                dp[3] -= sw * (Nta * div + tm * (ha[0] * Rm[0] + ha[1] * Rm[1] + ha[2] * Rm[2]));
             } else if constexpr (FORM == MF_FORM_MASS) {
+                double Fx[2], Fy[2], Fz[2];
+                gauss_factors(q & 1, Fx);
+                gauss_factors((q >> 1) & 1, Fy);
+                gauss_factors(q >> 2, Fz);
+                const double Na = Fx[alpha & 1] * Fy[(alpha >> 1) & 1] * Fz[alpha >> 2];
                 const T wa = hq[0] * (T)Na;
 #pragma unroll
-                for (int b = 0; b < 8; ++b)
-                    M[b][0] += wa * (T)(Fx[b & 1] * Fy[(b >> 1) & 1] * Fz[b >> 2]);
+                for (int b = 0; b < 2; ++b) M[b][0] += wa * (T)(Fx[b] * Fy[bq & 1] * Fz[bq >> 1]);
             } else {
-                T hb[8][3];
+                T hb[2][3];
 #pragma unroll
-                for (int b = 0; b < 8; ++b)
+                for (int b = 0; b < 2; ++b)
 #pragma unroll
-                    for (int m = 0; m < 3; ++m) hb[b][m] = hq[3 * b + m];
+                    for (int m = 0; m < 3; ++m) hb[b][m] = hq[3 * (fb + b) + m];
                 T ha[3];
 #pragma unroll
                 for (int m = 0; m < 3; ++m) ha[m] = hq[3 * alpha + m];
                 if constexpr (FORM == MF_FORM_ELASTICITY) {
 #pragma unroll
-                    for (int b = 0; b < 8; ++b)
+                    for (int b = 0; b < 2; ++b)
 #pragma unroll
                         for (int i = 0; i < 3; ++i)
 #pragma unroll
                             for (int j = 0; j < 3; ++j) M[b][3 * i + j] += ha[i] * hb[b][j];
                 } else {
 #pragma unroll
-                    for (int b = 0; b < 8; ++b) M[b][0] += ha[0] * hb[b][0] + ha[1] * hb[b][1] + ha[2] * hb[b][2];
+                    for (int b = 0; b < 2; ++b) M[b][0] += ha[0] * hb[b][0] + ha[1] * hb[b][1] + ha[2] * hb[b][2];
                 }
             }
-            if constexpr (FORM != MF_FORM_NS_SUPG) {
+        }
+        // load vector (d = -R for the flow form) over this lane's two points
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int q = 2 * bq + k;
+            const T* hq = he + q * HLayout<FORM, T>::SQ;
+            if constexpr (FORM == MF_FORM_NS_SUPG) {
+                const T rho = (T)p.form.rho, mu = (T)p.form.mu, tm = (T)p.form.tau_m, tc = (T)p.form.tau_c;
+                T ha[3], u[3], Rm[3];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    ha[m] = hq[R_H + 3 * alpha + m];
+                    u[m] = hq[R_U + m];
+                    Rm[m] = hq[R_RM + m];
+                }
+                const T Nta = hq[R_N + alpha], aa = hq[R_ADV + alpha];
+                const T sw = hq[R_S], pr = hq[R_P], div = hq[R_DIV];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const T visc = ha[0] * hq[R_GU + 3 * i] + ha[1] * hq[R_GU + 3 * i + 1] + ha[2] * hq[R_GU + 3 * i + 2];
+                    dp[i] -= sw * (-rho * aa * u[i] - ha[i] * pr + mu * visc + tm * rho * aa * Rm[i] + tc * ha[i] * div);
+                }
+                dp[3] -= sw * (Nta * div + tm * (ha[0] * Rm[0] + ha[1] * Rm[1] + ha[2] * Rm[2]));
+            } else {
+                double Fx[2], Fy[2], Fz[2];
+                gauss_factors(k, Fx);
+                gauss_factors(bq & 1, Fy);
+                gauss_factors(bq >> 1, Fz);
+                const double Na = Fx[alpha & 1] * Fy[(alpha >> 1) & 1] * Fz[alpha >> 2];
 #pragma unroll
                 for (int i = 0; i < NF; ++i) dp[i] += (T)Na * S.wf[slot][el][q][i];
             }
         }
     }
-    // add the two halves: lane qh keeps the blocks b = 4 qh .. 4 qh + 3
-    T Mk[4][NV];
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const T give = qh ? M[b][v] : M[b + 4][v];
-            const T keep = qh ? M[b + 4][v] : M[b][v];
-            Mk[b][v] = keep + swap_adjacent(give);
-        }
-#pragma unroll
-    for (int i = 0; i < NF; ++i) dp[i] += swap_adjacent(dp[i]);
+    for (int i = 0; i < NF; ++i) dp[i] = quad_sum(dp[i]);
     if (!valid) return;
 
     const T cA = FORM == MF_FORM_NS_SUPG ? T(0) : S.cf[slot][el][0];
     const T cB = FORM == MF_FORM_NS_SUPG ? T(0) : S.cf[slot][el][1];
     const int ax = alpha & 1, ay = (alpha >> 1) & 1, az = alpha >> 2;
+    Acc* row = &S.rowK[al][0];  // K order: [(i * 27 + slot) * NF + j]
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int beta = b + 4 * qh;
-        const int nslot = (qh - az + 1) * 9 + (((beta >> 1) & 1) - ay + 1) * 3 + ((beta & 1) - ax + 1);
-        Acc* dst = &S.rowK[al][nslot * NB];
+    for (int b = 0; b < 2; ++b) {
+        const int nslot = ((bq >> 1) - az + 1) * 9 + ((bq & 1) - ay + 1) * 3 + (b - ax + 1);
         if constexpr (FORM == MF_FORM_NS_SUPG) {
 #pragma unroll
-            for (int v = 0; v < 16; ++v) unsafeAtomicAdd(dst + v, (Acc)Mk[b][v]);
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int l = 0; l < 4; ++l) unsafeAtomicAdd(row + (i * 27 + nslot) * 4 + l, (Acc)M[b][4 * i + l]);
         } else if constexpr (FORM == MF_FORM_ELASTICITY) {
-            const T tr = Mk[b][0] + Mk[b][4] + Mk[b][8];
+            const T tr = M[b][0] + M[b][4] + M[b][8];
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    const T v = cA * Mk[b][3 * i + j] + cB * Mk[b][3 * j + i] + (i == j ? cB * tr : T(0));
-                    unsafeAtomicAdd(dst + 3 * i + j, (Acc)v);
+                    const T v = cA * M[b][3 * i + j] + cB * M[b][3 * j + i] + (i == j ? cB * tr : T(0));
+                    unsafeAtomicAdd(row + (i * 27 + nslot) * 3 + j, (Acc)v);
                 }
         } else {
-            unsafeAtomicAdd(dst, (Acc)(cA * Mk[b][0]));
+            unsafeAtomicAdd(row + nslot, (Acc)(cA * M[b][0]));
         }
     }
-    if (qh == 0) {
+    if (bq == 0) {
 #pragma unroll
         for (int i = 0; i < NF; ++i) unsafeAtomicAdd(&S.rowD[al][i], (Acc)dp[i]);
     }
 }
 
 // Rows of node layer kz from the row buffers (cleared on the way for the next layer).
+// The buffer is in the order of a node-major CSR row block, so an interior node's rows
+// are one contiguous copy; boundary nodes, field-major numbering and Dirichlet masks take
+// the general mapping.
 template <int FORM, typename T>
-__device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, T>& S)
+__device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, T>& S, int wid, int nw)
 {
     constexpr int NF = FormTraits<FORM, 3>::NF;
     constexpr int NB = NF * NF;
-    constexpr int kRowSlots = 27 * NF;
+    constexpr int kNodeVals = 27 * NB;
     using Acc = AccT<FORM>;
     T* K = (T*)p.K;
     T* d = (T*)p.d;
     const int NX = p.nx + 1, NY = p.ny + 1;
     const int nn = p.n_nodes;
-    for (int flat = threadIdx.x; flat < kColNodes * NF * kRowSlots; flat += kThreads) {
-        const int rloc = flat / kRowSlots;
-        const int sj = flat - rloc * kRowSlots;
-        const int slot = sj / NF, j = sj - slot * NF;
-        const int il = rloc / NF, i = rloc - il * NF;
-        Acc* src = &S.rowK[il][slot * NB + i * NF + j];
+    const bool plain = !p.field_major && !p.dirichlet;
+    for (int flat = wid; flat < kColNodes * kNodeVals; flat += nw) {
+        const int il = flat / kNodeVals;
+        const int o = flat - il * kNodeVals;  // (i * 27 + slot) * NF + j
+        Acc* src = &S.rowK[il][o];
         const Acc acc = *src;
-        *src = 0.0;
-        Acc accd = 0.0;
-        if (slot == 13 && j == 0) {
-            accd = S.rowD[il][i];
-            S.rowD[il][i] = 0.0;
-        }
+        *src = Acc(0);
         const int node = S.ni[il][0];
         if (node < 0) continue;
         const int bits = S.ni[il][3];
+        const int P = S.ni[il][1];
+        if (plain && bits == 63) {
+            K[P * NB + o] = (T)acc;
+            continue;
+        }
+        const int i = o / (27 * NF);
+        const int rem = o - i * (27 * NF);
+        const int slot = rem / NF, j = rem - slot * NF;
         const int ddx = slot % 3 - 1, ddy = (slot / 3) % 3 - 1, ddz = slot / 9 - 1;
         const int need = (ddx < 0 ? 1 : 0) | (ddx > 0 ? 2 : 0) | (ddy < 0 ? 4 : 0) | (ddy > 0 ? 8 : 0) |
                          (ddz < 0 ? 16 : 0) | (ddz > 0 ? 32 : 0);
@@ -530,7 +559,6 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
         const int mx = 1 + lo_x + ((bits >> 1) & 1), my = 1 + lo_y + ((bits >> 3) & 1);
         const int rank = ((ddz + lo_z) * my + (ddy + lo_y)) * mx + (ddx + lo_x);
         const int deg = S.ni[il][2];
-        const int P = S.ni[il][1];
         int row, kpos;
         if (p.field_major) {
             row = i * nn + node;
@@ -547,7 +575,16 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
             else if (p.dirichlet[col]) v = T(0);
         }
         K[kpos] = v;
-        if (slot == 13 && j == 0) d[row] = (p.dirichlet && p.dirichlet[row]) ? T(0) : (T)accd;
+    }
+    if (wid < kColNodes * NF) {
+        const int il = wid / NF, i = wid - il * NF;
+        const Acc acc = S.rowD[il][i];
+        S.rowD[il][i] = Acc(0);
+        const int node = S.ni[il][0];
+        if (node >= 0) {
+            const int row = p.field_major ? i * nn + node : NF * node + i;
+            d[row] = (p.dirichlet && p.dirichlet[row]) ? T(0) : (T)acc;
+        }
     }
 }
 
@@ -586,11 +623,14 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
     for (int kz = z0; kz < z1; ++kz) {
         // ---- phase A: geometry of element layer kz (and kz-1 on the first step); rows of kz-1
         const int first = kz == z0 ? kz - 1 : kz;
-        for (int it = tid; it < (kz - first + 1) * kGeomItems; it += kThreads) {
-            const int L = first + it / kGeomItems, r = it % kGeomItems;
-            geometry_item<FORM, T>(p, S, L, r >> 3, r & 7, i0, j0);
+        if (tid < kGeomThreads) {
+            for (int it = tid; it < (kz - first + 1) * kGeomItems; it += kGeomThreads) {
+                const int L = first + it / kGeomItems, r = it % kGeomItems;
+                geometry_item<FORM, T>(p, S, L, r >> 3, r & 7, i0, j0);
+            }
+        } else if (kz > z0) {
+            write_layer<FORM, T>(p, S, tid - kGeomThreads, kThreads - kGeomThreads);
         }
-        if (kz > z0) write_layer<FORM, T>(p, S);
         __syncthreads();
 
         // ---- phase B: rows of node layer kz; prefetch for the next step
@@ -626,7 +666,7 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
         }
         __syncthreads();
     }
-    if (z0 < z1) write_layer<FORM, T>(p, S);
+    if (z0 < z1) write_layer<FORM, T>(p, S, tid, kThreads);
 }
 
 template <int FORM, typename T>

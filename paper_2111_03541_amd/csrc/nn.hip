@@ -157,7 +157,21 @@ __global__ void __launch_bounds__(kThreads) k_level_fused(const bf16* __restrict
     __shared__ float sv[A * A * A];
     __shared__ bf16 sh1[C][B * B * B];
     __shared__ bf16 sh2[C][D * D * D];
+    // weights, tap-major so that the C weights of one (tap, input channel) are adjacent
+    // (read with uniform addresses, i.e. LDS broadcasts)
+    __shared__ float sw1[27][C];
+    __shared__ float sw2[27][C][C];
+    __shared__ float sw3[27][C];
     const int tid = threadIdx.x;
+    for (int k = tid; k < 27 * C; k += kThreads) {
+        const int tap = k / C, o = k % C;
+        sw1[tap][o] = w1[o * 27 + tap];
+        sw3[tap][o] = w3[o * 27 + tap];
+    }
+    for (int k = tid; k < 27 * C * C; k += kThreads) {
+        const int tap = k / (C * C), ci = (k / C) % C, o = k % C;
+        sw2[tap][ci][o] = w2[(o * C + ci) * 27 + tap];
+    }
     const int ntx = (g.nx + T - 1) / T, nty = (g.ny + T - 1) / T;
     const int bt = blockIdx.x;
     const int x0 = (bt % ntx) * T, y0 = ((bt / ntx) % nty) * T, z0 = (bt / (ntx * nty)) * T;
@@ -181,7 +195,7 @@ __global__ void __launch_bounds__(kThreads) k_level_fused(const bf16* __restrict
                 const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
                 const float xv = sv[(lx + 1 + dx) + A * ((ly + 1 + dy) + A * (lz + 1 + dz))];
 #pragma unroll
-                for (int o = 0; o < C; ++o) a[o] = fmaf(w1[o * 27 + tap], xv, a[o]);
+                for (int o = 0; o < C; ++o) a[o] = fmaf(sw1[tap][o], xv, a[o]);
             }
         }
 #pragma unroll
@@ -194,7 +208,7 @@ __global__ void __launch_bounds__(kThreads) k_level_fused(const bf16* __restrict
 #pragma unroll
         for (int o = 0; o < C; ++o) a[o] = 0.f;
         if (inside(x0 - 1 + lx, y0 - 1 + ly, z0 - 1 + lz)) {
-#pragma unroll
+#pragma unroll 1
             for (int tap = 0; tap < 27; ++tap) {
                 const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
                 const int q = (lx + 1 + dx) + B * ((ly + 1 + dy) + B * (lz + 1 + dz));
@@ -202,7 +216,7 @@ __global__ void __launch_bounds__(kThreads) k_level_fused(const bf16* __restrict
                 for (int ci = 0; ci < C; ++ci) {
                     const float xv = bf2f(sh1[ci][q]);
 #pragma unroll
-                    for (int o = 0; o < C; ++o) a[o] = fmaf(w2[(o * C + ci) * 27 + tap], xv, a[o]);
+                    for (int o = 0; o < C; ++o) a[o] = fmaf(sw2[tap][ci][o], xv, a[o]);
                 }
             }
         }
@@ -220,7 +234,7 @@ __global__ void __launch_bounds__(kThreads) k_level_fused(const bf16* __restrict
             const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
             const int q = (lx + 1 + dx) + D * ((ly + 1 + dy) + D * (lz + 1 + dz));
 #pragma unroll
-            for (int ci = 0; ci < C; ++ci) a = fmaf(w3[ci * 27 + tap], bf2f(sh2[ci][q]), a);
+            for (int ci = 0; ci < C; ++ci) a = fmaf(sw3[tap][ci], bf2f(sh2[ci][q]), a);
         }
         float p = 0.f;
         if (coarse) {
