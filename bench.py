@@ -27,6 +27,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
+# HBM bytes per launch of the 64^3 FP64 elasticity assembly measured with rocprofv3
+# FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a 1 GiB copy (summary in
+# profiles/assemble_column_elasticity64_f64_counters.md); used only while the library
+# reports the kernel revision it was measured on.
+MEASURED_TRAFFIC = {"revision": "assembly column-512 r1", "bytes": 631.4e6}
 FP64_PEAK = 78.6e12        # flop/s, vector and matrix
 FP32_PEAK = 157.3e12       # flop/s, matrix (vector without packed math: half)
 
@@ -299,7 +304,9 @@ def main():
                    "n_elems": mesh.n_elems, "n_dofs": pat.n_rows, "nnz": pat.nnz,
                    "pattern_ms": pattern_s * 1e3},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK, "traffic": None,
+                     "frac": achieved / HBM_PEAK,
+                     "traffic": (MEASURED_TRAFFIC["bytes"] if MEASURED_TRAFFIC["revision"] in mf.version()
+                                 else None),
                      "alg_bytes_per_launch": B, "avg_launch_us": avg * 1e6},
     }
     if args.copy_probe:
