@@ -2,9 +2,9 @@
 // (numerical integration and scatter of Sec. 2.2 D-2 and D-3, with no atomic increments
 // into global memory).
 //
-// A workgroup owns the nodes of a 4x4 column cross-section over a range of node layers
+// A workgroup owns the nodes of a 4x2 column cross-section over a range of node layers
 // [z0, z1) and walks up the column one node layer kz at a time:
-//   phase A  computes the element layer kz (the 5x5 elements around the column) into an
+//   phase A  computes the element layer kz (the 5x3 elements around the column) into an
 //            LDS ring: at each Gauss point q of element e, h_a(q) = sqrt(det J) grad N_a
 //            for the eight element nodes (FP64 geometry, stored in the working
 //            precision), W_q f(x_q) for the load vector, and the element coefficients;
@@ -17,7 +17,9 @@
 //            LDS row buffer (FP64 in both precisions).
 // Each value of K is written exactly once, in CSR row order, with the Dirichlet
 // elimination applied on the way out.  The geometry of an element is computed once per
-// column that sees it (25 elements per 16 owned nodes per layer).
+// column that sees it (15 elements per 8 owned nodes per layer); the small cross-section
+// keeps the LDS of the FP64 elasticity case under half a CU, so two workgroups share
+// each CU and overlap their phases.
 //
 // For a symmetric form the block of pair (a, b) is sum_q h_a h_b^T scaled by the element
 // coefficients: mass c W N_a N_b, Poisson c h_a . h_b, elasticity
@@ -33,17 +35,21 @@
 namespace mf {
 namespace {
 
-constexpr int CX = 4, CY = 4;              // owned nodes per layer of a column
+constexpr int CX = 4, CY = 2;              // owned nodes per layer of a column
 constexpr int kColNodes = CX * CY;
 constexpr int EXH = CX + 1, EYH = CY + 1;  // elements per layer around the column
 constexpr int kLayerElems = EXH * EYH;
 constexpr int TX = CX + 2, TY = CY + 2;    // node tile per layer
 constexpr int kTileNodes = TX * TY;
-constexpr int kThreads = 512;  // two waves per SIMD with one workgroup per CU
-constexpr int kGeomThreads = 256;  // phase A: geometry on waves 0-3, write-out on waves 4-7
+constexpr int kThreads = kColNodes * 8 * 4;  // phase B: one lane per (node, element, quarter)
+constexpr int kGeomThreads = 128;            // phase A: geometry on these, write-out on the rest
+constexpr int kMinBlocks = 2;                // workgroups per CU the LDS budget allows (FP64)
 constexpr int kGeomItems = kLayerElems * 8;  // (element, Gauss point)
-static_assert(kColNodes * 8 * 4 == kThreads, "one lane per (node, element, quarter)");
-static_assert(kGeomItems <= kGeomThreads, "one lane per (element, Gauss point)");
+constexpr int kPfElemT0 = 64, kPfInfoT0 = 96;  // phase B prefetch roles: [0, tile), [64, ..), [96, ..)
+static_assert(kGeomItems <= kGeomThreads && kGeomThreads < kThreads, "one lane per (element, Gauss point)");
+static_assert(kGeomThreads % 64 == 0 && kThreads % 64 == 0, "the write-out works in whole waves");
+static_assert(kTileNodes <= kPfElemT0 && kPfElemT0 + kLayerElems <= kPfInfoT0 && kPfInfoT0 + kColNodes <= kThreads,
+              "prefetch roles");
 
 // LDS layout of the per-Gauss-point records (in units of T).  Symmetric forms store h
 // (24 values); the flow form stores h, sqrt(W) N, sqrt(W) u.grad N, the state terms
@@ -518,63 +524,83 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
     }
 }
 
-// Rows of node layer kz from the row buffers (cleared on the way for the next layer).
-// The buffer is in the order of a node-major CSR row block, so an interior node's rows
-// are one contiguous copy; boundary nodes, field-major numbering and Dirichlet masks take
-// the general mapping.
+// Rows of node layer kz from the row buffers (cleared on the way for the next layer),
+// by the workers wid in [0, nw) (whole waves).  Each wave takes whole nodes: their
+// values are loaded from LDS in 64-lane chunks before any store, and the buffer is in
+// the order of a node-major CSR row block, so an interior node's rows are one contiguous
+// copy; boundary nodes, field-major numbering and Dirichlet masks take the general
+// mapping.
 template <int FORM, typename T>
 __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, T>& S, int wid, int nw)
 {
     constexpr int NF = FormTraits<FORM, 3>::NF;
     constexpr int NB = NF * NF;
     constexpr int kNodeVals = 27 * NB;
+    constexpr int NCH = (kNodeVals + 63) / 64;
     using Acc = AccT<FORM>;
     T* K = (T*)p.K;
     T* d = (T*)p.d;
     const int NX = p.nx + 1, NY = p.ny + 1;
     const int nn = p.n_nodes;
     const bool plain = !p.field_major && !p.dirichlet;
-    for (int flat = wid; flat < kColNodes * kNodeVals; flat += nw) {
-        const int il = flat / kNodeVals;
-        const int o = flat - il * kNodeVals;  // (i * 27 + slot) * NF + j
-        Acc* src = &S.rowK[il][o];
-        const Acc acc = *src;
-        *src = Acc(0);
+    const int lane = wid & 63, wv = wid >> 6, nwv = nw >> 6;
+    for (int il = wv; il < kColNodes; il += nwv) {
+        Acc vals[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int o = lane + 64 * c;
+            vals[c] = o < kNodeVals ? S.rowK[il][o] : Acc(0);
+        }
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int o = lane + 64 * c;
+            if (o < kNodeVals) S.rowK[il][o] = Acc(0);
+        }
         const int node = S.ni[il][0];
         if (node < 0) continue;
         const int bits = S.ni[il][3];
         const int P = S.ni[il][1];
         if (plain && bits == 63) {
-            K[P * NB + o] = (T)acc;
+            T* dst = K + (int64_t)P * NB;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int o = lane + 64 * c;
+                if (o < kNodeVals) dst[o] = (T)vals[c];
+            }
             continue;
         }
-        const int i = o / (27 * NF);
-        const int rem = o - i * (27 * NF);
-        const int slot = rem / NF, j = rem - slot * NF;
-        const int ddx = slot % 3 - 1, ddy = (slot / 3) % 3 - 1, ddz = slot / 9 - 1;
-        const int need = (ddx < 0 ? 1 : 0) | (ddx > 0 ? 2 : 0) | (ddy < 0 ? 4 : 0) | (ddy > 0 ? 8 : 0) |
-                         (ddz < 0 ? 16 : 0) | (ddz > 0 ? 32 : 0);
-        if ((bits & need) != need) continue;
+        const int deg = S.ni[il][2];
         const int lo_x = bits & 1, lo_y = (bits >> 2) & 1, lo_z = (bits >> 4) & 1;
         const int mx = 1 + lo_x + ((bits >> 1) & 1), my = 1 + lo_y + ((bits >> 3) & 1);
-        const int rank = ((ddz + lo_z) * my + (ddy + lo_y)) * mx + (ddx + lo_x);
-        const int deg = S.ni[il][2];
-        int row, kpos;
-        if (p.field_major) {
-            row = i * nn + node;
-            kpos = i * NF * p.n_pairs + NF * P + j * deg + rank;
-        } else {
-            row = NF * node + i;
-            kpos = P * NB + i * NF * deg + rank * NF + j;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int o = lane + 64 * c;  // (i * 27 + slot) * NF + j
+            if (o >= kNodeVals) continue;
+            const int i = o / (27 * NF);
+            const int rem = o - i * (27 * NF);
+            const int slot = rem / NF, j = rem - slot * NF;
+            const int ddx = slot % 3 - 1, ddy = (slot / 3) % 3 - 1, ddz = slot / 9 - 1;
+            const int need = (ddx < 0 ? 1 : 0) | (ddx > 0 ? 2 : 0) | (ddy < 0 ? 4 : 0) | (ddy > 0 ? 8 : 0) |
+                             (ddz < 0 ? 16 : 0) | (ddz > 0 ? 32 : 0);
+            if ((bits & need) != need) continue;
+            const int rank = ((ddz + lo_z) * my + (ddy + lo_y)) * mx + (ddx + lo_x);
+            int row, kpos;
+            if (p.field_major) {
+                row = i * nn + node;
+                kpos = i * NF * p.n_pairs + NF * P + j * deg + rank;
+            } else {
+                row = NF * node + i;
+                kpos = P * NB + i * NF * deg + rank * NF + j;
+            }
+            T v = (T)vals[c];
+            if (p.dirichlet) {
+                const int nb = node + ddx + NX * (ddy + NY * ddz);
+                const int col = p.field_major ? j * nn + nb : NF * nb + j;
+                if (p.dirichlet[row]) v = (col == row) ? T(1) : T(0);
+                else if (p.dirichlet[col]) v = T(0);
+            }
+            K[kpos] = v;
         }
-        T v = (T)acc;
-        if (p.dirichlet) {
-            const int nb = node + ddx + NX * (ddy + NY * ddz);
-            const int col = p.field_major ? j * nn + nb : NF * nb + j;
-            if (p.dirichlet[row]) v = (col == row) ? T(1) : T(0);
-            else if (p.dirichlet[col]) v = T(0);
-        }
-        K[kpos] = v;
     }
     if (wid < kColNodes * NF) {
         const int il = wid / NF, i = wid - il * NF;
@@ -641,10 +667,10 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
         int info[4] = {-1, 0, 0, 0};
         if (tid < kTileNodes) {
             ld.load(p, kz + 2, tid, i0, j0);
-        } else if (tid >= 64 && tid < 64 + kLayerElems) {
-            ep_ok = elem_param_of(p, kz + 1, tid - 64, i0, j0, f32, epv);
-        } else if (tid >= 128 && tid < 128 + kColNodes) {
-            const int il = tid - 128;
+        } else if (tid >= kPfElemT0 && tid < kPfElemT0 + kLayerElems) {
+            ep_ok = elem_param_of(p, kz + 1, tid - kPfElemT0, i0, j0, f32, epv);
+        } else if (tid >= kPfInfoT0 && tid < kPfInfoT0 + kColNodes) {
+            const int il = tid - kPfInfoT0;
             const int gi = i0 + il % CX, gj = j0 + il / CX;
             if (gi < NX && gj < NY) {
                 const int node = gi + NX * (gj + NY * kz);
@@ -659,10 +685,10 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
         }
         pair_item<FORM, T>(p, S, kz, i0, j0);
         if (tid < kTileNodes) ld.template store<FORM>(S, kz + 2, tid);
-        if (ep_ok) S.ep[(kz + 1) & 1][tid - 64] = epv;
-        if (tid >= 128 && tid < 128 + kColNodes) {
+        if (ep_ok) S.ep[(kz + 1) & 1][tid - kPfElemT0] = epv;
+        if (tid >= kPfInfoT0 && tid < kPfInfoT0 + kColNodes) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) S.ni[tid - 128][k] = info[k];
+            for (int k = 0; k < 4; ++k) S.ni[tid - kPfInfoT0][k] = info[k];
         }
         __syncthreads();
     }
@@ -670,7 +696,7 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
 }
 
 template <int FORM, typename T>
-__global__ void __launch_bounds__(kThreads, 1) k_assemble_column(ColParams p)
+__global__ void __launch_bounds__(kThreads, kMinBlocks) k_assemble_column(ColParams p)
 {
     __shared__ ColShared<FORM, T> S;
     column_body<FORM, T>(p, blockIdx.x, S);
@@ -701,7 +727,7 @@ __global__ void k_batch_reset(int* counter, unsigned long long* const* status, i
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kThreads, 1)
+__global__ void __launch_bounds__(kThreads, kMinBlocks)
     k_batch_persistent(const BatchProblemDev* __restrict__ probs, const int2* __restrict__ items, int n_items,
                        int* __restrict__ counter)
 {
@@ -791,7 +817,7 @@ mf_status launch_column(const AssembleArgs& A)
     ColParams p = make_params(A);
     const int NZ = p.nz + 1;
     const int64_t columns = column_count(A.P);
-    p.lz = choose_lz(columns, NZ, device_cus());
+    p.lz = choose_lz(columns, NZ, device_cus() * kMinBlocks);
     const int64_t wgs = columns * ((NZ + p.lz - 1) / p.lz);
     if (wgs <= 0) return MF_OK;
     if (wgs > 0x7fffffff) return set_error(MF_ERR_OVERFLOW, "grid of %lld workgroups", (long long)wgs);
