@@ -43,7 +43,13 @@ constexpr int TX = CX + 2, TY = CY + 2;    // node tile per layer
 constexpr int kTileNodes = TX * TY;
 constexpr int kThreads = kColNodes * 8 * 4;  // phase B: one lane per (node, element, quarter)
 constexpr int kGeomThreads = 128;            // phase A: geometry on these, write-out on the rest
-constexpr int kMinBlocks = 2;                // workgroups per CU the LDS budget allows (FP64)
+// workgroups per CU that the LDS of each case allows (FP64 and the flow form: 2; FP32
+// symmetric forms: 3)
+template <int FORM, typename T>
+struct MinBlocks {
+    static constexpr int value = (sizeof(T) == 4 && FORM != MF_FORM_NS_SUPG) ? 3 : 2;
+};
+constexpr int kMinBlocks = 2;                // the batched kernel (largest case)
 constexpr int kGeomItems = kLayerElems * 8;  // (element, Gauss point)
 constexpr int kPfElemT0 = 64, kPfInfoT0 = 96;  // phase B prefetch roles: [0, tile), [64, ..), [96, ..)
 static_assert(kGeomItems <= kGeomThreads && kGeomThreads < kThreads, "one lane per (element, Gauss point)");
@@ -188,40 +194,58 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
     const int hx = el % EXH, hy = el / EXH;
     const int ex = i0 - 1 + hx, ey = j0 - 1 + hy;
     if (L < 0 || L >= p.nz || ex < 0 || ex >= p.nx || ey < 0 || ey >= p.ny) return;
-    double x[8][3];
-    T U[8][FormTraits<FORM, 3>::NSRC];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        const int r = ring3(L + (a >> 2));
-        const int tn = (hx + (a & 1)) + TX * (hy + ((a >> 1) & 1));
-#pragma unroll
-        for (int m = 0; m < 3; ++m) x[a][m] = S.x[r][tn][m];
-#pragma unroll
-        for (int k = 0; k < FormTraits<FORM, 3>::NSRC; ++k) U[a][k] = S.u[r][tn][k];
-    }
+    // nodes are streamed from the LDS tile and the basis at the point is rebuilt from the
+    // 1D factors where it is used, to keep few values live
     double F[3][2];
     gauss_factors(q & 1, F[0]);
     gauss_factors((q >> 1) & 1, F[1]);
     gauss_factors((q >> 2) & 1, F[2]);
-    double N[8], dN[8][3];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
+    auto node_slot = [&](int a, int& r, int& tn) {
+        r = ring3(L + (a >> 2));
+        tn = (hx + (a & 1)) + TX * (hy + ((a >> 1) & 1));
+    };
+    auto N_of = [&](int a) { return F[0][a & 1] * F[1][(a >> 1) & 1] * F[2][a >> 2]; };
+    auto dN_of = [&](int a, double (&d)[3]) {
         const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
-        N[a] = F[0][ax] * F[1][ay] * F[2][az];
-        dN[a][0] = (ax ? 0.5 : -0.5) * F[1][ay] * F[2][az];
-        dN[a][1] = (ay ? 0.5 : -0.5) * F[0][ax] * F[2][az];
-        dN[a][2] = (az ? 0.5 : -0.5) * F[0][ax] * F[1][ay];
-    }
-    double J[3][3];
+        d[0] = (ax ? 0.5 : -0.5) * F[1][ay] * F[2][az];
+        d[1] = (ay ? 0.5 : -0.5) * F[0][ax] * F[2][az];
+        d[2] = (az ? 0.5 : -0.5) * F[0][ax] * F[1][ay];
+    };
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    if constexpr (sizeof(T) == 8) {
+        // FP64 kernels are bounded by LDS, not registers: load the eight nodes first
+        double x[8][3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+        for (int a = 0; a < 8; ++a) {
+            int r, tn;
+            node_slot(a, r, tn);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            double s = 0.0;
-#pragma unroll
-            for (int a = 0; a < 8; ++a) s = fma(x[a][i], dN[a][j], s);
-            J[i][j] = s;
+            for (int i = 0; i < 3; ++i) x[a][i] = S.x[r][tn][i];
         }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            double d[3];
+            dN_of(a, d);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) J[i][j] = fma(x[a][i], d[j], J[i][j]);
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            int r, tn;
+            node_slot(a, r, tn);
+            double d[3];
+            dN_of(a, d);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double xa = S.x[r][tn][i];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) J[i][j] = fma(xa, d[j], J[i][j]);
+            }
+        }
+    }
     const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
     const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
     const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
@@ -251,42 +275,45 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
         Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
         Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
         Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
-        double g[8][3];
+        auto g_of = [&](int a, double (&g)[3]) {
+            double d[3];
+            dN_of(a, d);
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                double v = 0.0;
-#pragma unroll
-                for (int j = 0; j < 3; ++j) v = fma(dN[a][j], Ji[j][m], v);
-                g[a][m] = v;
-            }
+            for (int m = 0; m < 3; ++m) g[m] = fma(d[0], Ji[0][m], fma(d[1], Ji[1][m], d[2] * Ji[2][m]));
+        };
         double u[3] = {0, 0, 0}, gu[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, pr = 0.0, gp[3] = {0, 0, 0};
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
+            int r, tn;
+            node_slot(b, r, tn);
+            double g[3];
+            g_of(b, g);
+            const double Nb = N_of(b);
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                const double Ub = (double)U[b][m];
-                u[m] = fma(N[b], Ub, u[m]);
+                const double Ub = (double)S.u[r][tn][m];
+                u[m] = fma(Nb, Ub, u[m]);
 #pragma unroll
-                for (int k = 0; k < 3; ++k) gu[m][k] = fma(g[b][k], Ub, gu[m][k]);  // du_m/dx_k
+                for (int k = 0; k < 3; ++k) gu[m][k] = fma(g[k], Ub, gu[m][k]);  // du_m/dx_k
             }
-            const double Pb = (double)U[b][3];
-            pr = fma(N[b], Pb, pr);
+            const double Pb = (double)S.u[r][tn][3];
+            pr = fma(Nb, Pb, pr);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) gp[k] = fma(g[b][k], Pb, gp[k]);
+            for (int k = 0; k < 3; ++k) gp[k] = fma(g[k], Pb, gp[k]);
         }
         const double rho = p.form.rho;
         const double sw = sqrt(det);
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
+            double g[3];
+            g_of(a, g);
             double adv = 0.0;
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                hq[R_H + 3 * a + m] = (T)(sw * g[a][m]);
-                adv = fma(u[m], g[a][m], adv);
+                hq[R_H + 3 * a + m] = (T)(sw * g[m]);
+                adv = fma(u[m], g[m], adv);
             }
-            hq[R_N + a] = (T)(sw * N[a]);
+            hq[R_N + a] = (T)(sw * N_of(a));
             hq[R_ADV + a] = (T)(sw * adv);
         }
 #pragma unroll
@@ -320,25 +347,29 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
         A[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * s;
         A[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * s;
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
+        for (int a = 0; a < 8; ++a) {
+            double d[3];
+            dN_of(a, d);
 #pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                double v = 0.0;
-#pragma unroll
-                for (int j = 0; j < 3; ++j) v = fma(dN[a][j], A[j][m], v);
-                hq[3 * a + m] = (T)v;
-            }
+            for (int m = 0; m < 3; ++m) hq[3 * a + m] = (T)fma(d[0], A[0][m], fma(d[1], A[1][m], d[2] * A[2][m]));
+        }
     }
     if constexpr (FORM != MF_FORM_NS_SUPG) {
         // load vector integrand W f(x_q) (times c for the mass form)
         const double wscale = det * (FORM == MF_FORM_MASS ? coefA : 1.0);
+        double f[NF];
 #pragma unroll
-        for (int i = 0; i < NF; ++i) {
-            double f = 0.0;
+        for (int i = 0; i < NF; ++i) f[i] = 0.0;
 #pragma unroll
-            for (int a = 0; a < 8; ++a) f = fma(N[a], (double)U[a][i], f);
-            S.wf[slot][el][q][i] = (T)(wscale * f);
+        for (int a = 0; a < 8; ++a) {
+            int r, tn;
+            node_slot(a, r, tn);
+            const double Na = N_of(a);
+#pragma unroll
+            for (int i = 0; i < NF; ++i) f[i] = fma(Na, (double)S.u[r][tn][i], f[i]);
         }
+#pragma unroll
+        for (int i = 0; i < NF; ++i) S.wf[slot][el][q][i] = (T)(wscale * f[i]);
         if (q == 0) {
             S.cf[slot][el][0] = (T)coefA;
             S.cf[slot][el][1] = (T)coefB;
@@ -696,7 +727,7 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
 }
 
 template <int FORM, typename T>
-__global__ void __launch_bounds__(kThreads, kMinBlocks) k_assemble_column(ColParams p)
+__global__ void __launch_bounds__(kThreads, (MinBlocks<FORM, T>::value)) k_assemble_column(ColParams p)
 {
     __shared__ ColShared<FORM, T> S;
     column_body<FORM, T>(p, blockIdx.x, S);
@@ -817,7 +848,7 @@ mf_status launch_column(const AssembleArgs& A)
     ColParams p = make_params(A);
     const int NZ = p.nz + 1;
     const int64_t columns = column_count(A.P);
-    p.lz = choose_lz(columns, NZ, device_cus() * kMinBlocks);
+    p.lz = choose_lz(columns, NZ, device_cus() * MinBlocks<FORM, T>::value);
     const int64_t wgs = columns * ((NZ + p.lz - 1) / p.lz);
     if (wgs <= 0) return MF_OK;
     if (wgs > 0x7fffffff) return set_error(MF_ERR_OVERFLOW, "grid of %lld workgroups", (long long)wgs);
