@@ -147,21 +147,31 @@ __global__ void __launch_bounds__(kThreads) k_conv(const TI* __restrict__ in, co
 // out = y + P coarse (coarse == nullptr on the coarsest level).  The arithmetic order per
 // point is that of k_conv and k_prolong_add.
 template <int C, int T>
-__global__ void __launch_bounds__(kThreads) k_level_fused(const bf16* __restrict__ v, Grid g,
-                                                          const float* __restrict__ w1, const float* __restrict__ w2,
-                                                          const float* __restrict__ w3,
-                                                          const float* __restrict__ coarse, Grid gc,
-                                                          float* __restrict__ out)
-{
-    constexpr int A = T + 6, B = T + 4, D = T + 2;  // tile edges of v, h1, h2
-    __shared__ float sv[A * A * A];
-    __shared__ bf16 sh1[C][B * B * B];
-    __shared__ bf16 sh2[C][D * D * D];
+struct LevelSmem {
+    static constexpr int A = T + 6, B = T + 4, D = T + 2;  // tile edges of v, h1, h2
+    float sv[A * A * A];
+    bf16 sh1[C][B * B * B];
+    bf16 sh2[C][D * D * D];
     // weights, tap-major so that the C weights of one (tap, input channel) are adjacent
     // (read with uniform addresses, i.e. LDS broadcasts)
-    __shared__ float sw1[27][C];
-    __shared__ float sw2[27][C][C];
-    __shared__ float sw3[27][C];
+    float sw1[27][C];
+    float sw2[27][C][C];
+    float sw3[27][C];
+};
+
+template <int C, int T>
+__device__ __forceinline__ void level_tile(const bf16* __restrict__ v, Grid g, const float* __restrict__ w1,
+                                           const float* __restrict__ w2, const float* __restrict__ w3,
+                                           const float* __restrict__ coarse, Grid gc, float* __restrict__ out,
+                                           int bt, LevelSmem<C, T>& S)
+{
+    constexpr int A = T + 6, B = T + 4, D = T + 2;
+    float* sv = S.sv;
+    auto& sh1 = S.sh1;
+    auto& sh2 = S.sh2;
+    auto& sw1 = S.sw1;
+    auto& sw2 = S.sw2;
+    auto& sw3 = S.sw3;
     const int tid = threadIdx.x;
     for (int k = tid; k < 27 * C; k += kThreads) {
         const int tap = k / C, o = k % C;
@@ -173,7 +183,6 @@ __global__ void __launch_bounds__(kThreads) k_level_fused(const bf16* __restrict
         sw2[tap][ci][o] = w2[(o * C + ci) * 27 + tap];
     }
     const int ntx = (g.nx + T - 1) / T, nty = (g.ny + T - 1) / T;
-    const int bt = blockIdx.x;
     const int x0 = (bt % ntx) * T, y0 = ((bt / ntx) % nty) * T, z0 = (bt / (ntx * nty)) * T;
     auto inside = [&](int x, int y, int z) {
         return x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
@@ -245,6 +254,54 @@ __global__ void __launch_bounds__(kThreads) k_level_fused(const bf16* __restrict
         }
         out[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = a + p;
     }
+}
+
+
+template <int C, int T>
+__global__ void __launch_bounds__(kThreads) k_level_fused(const bf16* __restrict__ v, Grid g,
+                                                          const float* __restrict__ w1, const float* __restrict__ w2,
+                                                          const float* __restrict__ w3,
+                                                          const float* __restrict__ coarse, Grid gc,
+                                                          float* __restrict__ out)
+{
+    __shared__ LevelSmem<C, T> S;
+    level_tile<C, T>(v, g, w1, w2, w3, coarse, gc, out, blockIdx.x, S);
+}
+
+// The convolution chains of several levels in one launch (they are independent; the
+// prolongation chain runs after): level 1 with <C1, T1> tiles, the coarser levels with
+// <C2, T2> tiles; workgroup b takes tile b of the first level whose tile range holds it.
+struct LevelJob {
+    const bf16* v;
+    Grid g;
+    const float* w1;
+    const float* w2;
+    const float* w3;
+    float* out;
+    int tiles;
+};
+struct LevelJobs {
+    LevelJob j[kMaxLevels];
+    int n;
+};
+
+template <int C1, int T1, int C2, int T2>
+__global__ void __launch_bounds__(kThreads) k_levels(LevelJobs J)
+{
+    __shared__ union {
+        LevelSmem<C1, T1> a;
+        LevelSmem<C2, T2> b;
+    } U;
+    int b = blockIdx.x, l = 0;
+    while (l < J.n - 1 && b >= J.j[l].tiles) {
+        b -= J.j[l].tiles;
+        ++l;
+    }
+    const LevelJob& q = J.j[l];
+    if (l == 0)
+        level_tile<C1, T1>(q.v, q.g, q.w1, q.w2, q.w3, nullptr, q.g, q.out, b, U.a);
+    else
+        level_tile<C2, T2>(q.v, q.g, q.w1, q.w2, q.w3, nullptr, q.g, q.out, b, U.b);
 }
 
 // partial[(o*CIN + i)*27 + tap][chunk] = sum over the chunk of gy[o][p] * x[i][p + d_tap]
@@ -353,6 +410,100 @@ __global__ void __launch_bounds__(kThreads) k_final(const bf16* __restrict__ v0,
     }
     if (y0) y0[t] = acc;
     z[t] = mask[t] ? 0.0 : (double)dm[t] * (double)acc;
+}
+
+// v0 = bf16(Dm^-1/2 r) on the fine grid (threads [0, n0)) and v1 = R v0 on the first coarse
+// grid (threads [n0, n0 + n1)), v1 recomputing the rounded v0 values it needs; the same
+// arithmetic as k_input followed by k_restrict.
+__global__ void __launch_bounds__(kThreads) k_input_restrict(const double* __restrict__ r,
+                                                             const float* __restrict__ dm, Grid gf,
+                                                             bf16* __restrict__ v0, Grid gc, bf16* __restrict__ v1)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n0 = gf.n();
+    if (t < n0) {
+        v0[t] = f2bf((float)r[t] * dm[t]);
+        return;
+    }
+    const int64_t c = t - n0;
+    if (c >= gc.n()) return;
+    const int i = (int)(c % gc.nx), j = (int)((c / gc.nx) % gc.ny), k = (int)(c / ((int64_t)gc.nx * gc.ny));
+    float s = 0.f;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int z = 2 * k + dz;
+        if (z < 0 || z >= gf.nz) continue;
+        const float wz = dz ? 0.5f : 1.f;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int y = 2 * j + dy;
+            if (y < 0 || y >= gf.ny) continue;
+            const float wy = wz * (dy ? 0.5f : 1.f);
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int x = 2 * i + dx;
+                if (x < 0 || x >= gf.nx) continue;
+                const int64_t f = x + (int64_t)gf.nx * (y + (int64_t)gf.ny * z);
+                s += wy * (dx ? 0.5f : 1.f) * bf2f(f2bf((float)r[f] * dm[f]));
+            }
+        }
+    }
+    v1[c] = f2bf(s);
+}
+
+// Inference form of k_final over 8^3 tiles: the level-0 input with a one-point halo and
+// the 5^3 coarse values the tile interpolates from are staged in LDS first; same
+// arithmetic order per point as k_final.
+__global__ void __launch_bounds__(kThreads) k_final_tiled(const bf16* __restrict__ v0, const float* __restrict__ w0,
+                                                          const float* __restrict__ acc1, Grid gc, Grid g,
+                                                          const float* __restrict__ dm,
+                                                          const uint8_t* __restrict__ mask, double* __restrict__ z)
+{
+    constexpr int T = 8, A = T + 2, CT = T / 2 + 1;
+    __shared__ float sv[A * A * A];
+    __shared__ float sc[CT * CT * CT];
+    __shared__ float sw[27];
+    const int tid = threadIdx.x;
+    const int ntx = (g.nx + T - 1) / T, nty = (g.ny + T - 1) / T;
+    const int bt = blockIdx.x;
+    const int x0 = (bt % ntx) * T, y0 = ((bt / ntx) % nty) * T, z0 = (bt / (ntx * nty)) * T;
+    if (tid < 27) sw[tid] = w0[tid];
+    for (int i = tid; i < A * A * A; i += kThreads) {
+        const int x = x0 - 1 + i % A, y = y0 - 1 + (i / A) % A, zz = z0 - 1 + i / (A * A);
+        const bool in = x >= 0 && x < g.nx && y >= 0 && y < g.ny && zz >= 0 && zz < g.nz;
+        sv[i] = in ? bf2f(v0[x + (int64_t)g.nx * (y + (int64_t)g.ny * zz)]) : 0.f;
+    }
+    if (acc1) {
+        for (int i = tid; i < CT * CT * CT; i += kThreads) {
+            const int cx = x0 / 2 + i % CT, cy = y0 / 2 + (i / CT) % CT, cz = z0 / 2 + i / (CT * CT);
+            const bool in = cx < gc.nx && cy < gc.ny && cz < gc.nz;
+            sc[i] = in ? acc1[cx + (int64_t)gc.nx * (cy + (int64_t)gc.ny * cz)] : 0.f;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < T * T * T; i += kThreads) {
+        const int lx = i % T, ly = (i / T) % T, lz = i / (T * T);
+        const int x = x0 + lx, y = y0 + ly, zz = z0 + lz;
+        if (x >= g.nx || y >= g.ny || zz >= g.nz) continue;
+        float acc = 0.f;
+#pragma unroll
+        for (int tap = 0; tap < 27; ++tap) {
+            const int sx = x + tap % 3 - 1, sy = y + (tap / 3) % 3 - 1, sz = zz + tap / 9 - 1;
+            if (sx < 0 || sx >= g.nx || sy < 0 || sy >= g.ny || sz < 0 || sz >= g.nz) continue;
+            acc = fmaf(sw[tap], sv[(lx + tap % 3) + A * ((ly + (tap / 3) % 3) + A * (lz + tap / 9))], acc);
+        }
+        if (acc1) {
+            // coarse corners relative to the tile's first coarse point
+            const int ax = (x >> 1) - x0 / 2, bx = ((x + 1) >> 1) - x0 / 2;
+            const int ay = (y >> 1) - y0 / 2, by = ((y + 1) >> 1) - y0 / 2;
+            const int az = (zz >> 1) - z0 / 2, bz = ((zz + 1) >> 1) - z0 / 2;
+            auto C = [&](int a, int b, int d) { return sc[a + CT * (b + CT * d)]; };
+            acc += 0.125f * (C(ax, ay, az) + C(bx, ay, az) + C(ax, by, az) + C(bx, by, az) + C(ax, ay, bz) +
+                             C(bx, ay, bz) + C(ax, by, bz) + C(bx, by, bz));
+        }
+        const int64_t t = x + (int64_t)g.nx * (y + (int64_t)g.ny * zz);
+        z[t] = mask[t] ? 0.0 : (double)dm[t] * (double)acc;
+    }
 }
 
 // y = K x (FP64 CSR, one row per thread); partial sums of |y - r|^2 and |r|^2
@@ -601,30 +752,70 @@ mf_status level_fused_dispatch(int c, const bf16* v, Grid g, const float* w1, co
     return set_error(MF_ERR_UNSUPPORTED, "fused level with %d channels not instantiated", c);
 }
 
-// Inference: the restriction chain, then one fused kernel per level from the coarsest
-// up (each adds the prolongation of the level below it), then the level-0 pass.
+// Inference.  For the shipped shape (level 1 with 4 channels on 8^3 tiles, coarser levels
+// with 8 channels on 4^3 tiles): the fine input and first restriction in one kernel, the
+// other restrictions, the convolution chains of all levels in one launch (they are
+// independent), then the prolongation chain acc_l = y_l + P acc_{l+1} and the level-0
+// pass.  Any other shape runs one fused kernel per level from the coarsest up, each
+// adding the prolongation of the level below it.
 mf_status nn_infer(mf_nn_s* N, const double* r, double* z, hipStream_t s)
 {
     const int64_t n = N->n0;
-    k_input<<<nblk(n), kThreads, 0, s>>>(r, N->dm, n, N->vin[0]);
-    for (int l = 1; l < N->L; ++l)
-        k_restrict<bf16, bf16><<<nblk(N->g[l].n()), kThreads, 0, s>>>(N->vin[l - 1], N->g[l - 1], N->vin[l], N->g[l]);
-    for (int l = N->L - 1; l >= 1; --l) {
-        const int b = 1 + 3 * (l - 1);
-        const float* coarse = l == N->L - 1 ? nullptr : (l + 1 == N->L - 1 ? N->y[l + 1] : N->acc[l + 1]);
-        float* out = l == N->L - 1 ? N->y[l] : N->acc[l];
-        const Grid gc = l + 1 < N->L ? N->g[l + 1] : N->g[l];
-        const float* w1 = N->pb + N->w_off[b];
-        const float* w2 = N->pb + N->w_off[b + 1];
-        const float* w3 = N->pb + N->w_off[b + 2];
-        if (N->g[l].n() > 50000)
-            NN_TRY(level_fused_dispatch<8>(N->ch[l], N->vin[l], N->g[l], w1, w2, w3, coarse, gc, out, s));
-        else
-            NN_TRY(level_fused_dispatch<4>(N->ch[l], N->vin[l], N->g[l], w1, w2, w3, coarse, gc, out, s));
+    const int L = N->L;
+    bool fast = L >= 3 && N->ch[1] == 4 && N->g[1].n() > 50000;
+    for (int l = 2; l < L; ++l) fast = fast && N->ch[l] == 8 && N->g[l].n() <= 50000;
+    if (fast) {
+        k_input_restrict<<<nblk(n + N->g[1].n()), kThreads, 0, s>>>(r, N->dm, N->g[0], N->vin[0], N->g[1],
+                                                                     N->vin[1]);
+        for (int l = 2; l < L; ++l)
+            k_restrict<bf16, bf16><<<nblk(N->g[l].n()), kThreads, 0, s>>>(N->vin[l - 1], N->g[l - 1], N->vin[l],
+                                                                         N->g[l]);
+        LevelJobs J{};
+        int total = 0;
+        for (int l = 1; l < L; ++l) {
+            const int T = l == 1 ? 8 : 4;
+            const Grid g = N->g[l];
+            const int b = 1 + 3 * (l - 1);
+            LevelJob& q = J.j[l - 1];
+            q.v = N->vin[l];
+            q.g = g;
+            q.w1 = N->pb + N->w_off[b];
+            q.w2 = N->pb + N->w_off[b + 1];
+            q.w3 = N->pb + N->w_off[b + 2];
+            q.out = N->y[l];
+            q.tiles = ((g.nx + T - 1) / T) * ((g.ny + T - 1) / T) * ((g.nz + T - 1) / T);
+            total += q.tiles;
+        }
+        J.n = L - 1;
+        k_levels<4, 8, 8, 4><<<(unsigned)total, kThreads, 0, s>>>(J);
+        for (int l = L - 2; l >= 1; --l) {
+            const float* coarse = (l == L - 2) ? N->y[l + 1] : N->acc[l + 1];
+            k_prolong_add<<<nblk(N->g[l].n()), kThreads, 0, s>>>(coarse, N->g[l + 1], N->y[l], N->acc[l], N->g[l]);
+        }
+    } else {
+        k_input<<<nblk(n), kThreads, 0, s>>>(r, N->dm, n, N->vin[0]);
+        for (int l = 1; l < L; ++l)
+            k_restrict<bf16, bf16><<<nblk(N->g[l].n()), kThreads, 0, s>>>(N->vin[l - 1], N->g[l - 1], N->vin[l],
+                                                                         N->g[l]);
+        for (int l = L - 1; l >= 1; --l) {
+            const int b = 1 + 3 * (l - 1);
+            const float* coarse = l == L - 1 ? nullptr : (l + 1 == L - 1 ? N->y[l + 1] : N->acc[l + 1]);
+            float* out = l == L - 1 ? N->y[l] : N->acc[l];
+            const Grid gc = l + 1 < L ? N->g[l + 1] : N->g[l];
+            const float* w1 = N->pb + N->w_off[b];
+            const float* w2 = N->pb + N->w_off[b + 1];
+            const float* w3 = N->pb + N->w_off[b + 2];
+            if (N->g[l].n() > 50000)
+                NN_TRY(level_fused_dispatch<8>(N->ch[l], N->vin[l], N->g[l], w1, w2, w3, coarse, gc, out, s));
+            else
+                NN_TRY(level_fused_dispatch<4>(N->ch[l], N->vin[l], N->g[l], w1, w2, w3, coarse, gc, out, s));
+        }
     }
-    const float* acc1 = N->L > 2 ? N->acc[1] : (N->L == 2 ? N->y[1] : nullptr);
-    k_final<<<nblk(n), kThreads, 0, s>>>(N->vin[0], N->pb + N->w_off[0], acc1, N->L > 1 ? N->g[1] : N->g[0], N->g[0],
-                                         N->dm, N->mask, z, nullptr);
+    const float* acc1 = L > 2 ? N->acc[1] : (L == 2 ? N->y[1] : nullptr);
+    const Grid g0 = N->g[0];
+    const unsigned tiles = (unsigned)(((g0.nx + 7) / 8) * ((g0.ny + 7) / 8) * ((g0.nz + 7) / 8));
+    k_final_tiled<<<tiles, kThreads, 0, s>>>(N->vin[0], N->pb + N->w_off[0], acc1, L > 1 ? N->g[1] : N->g[0],
+                                             g0, N->dm, N->mask, z);
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
@@ -763,6 +954,7 @@ mf_status mf_nn_create(const int32_t* grid, int32_t levels, const int32_t* chann
         free_nn(N);
         return st;
     }
+
     // initial parameters: level-0 stencil = identity (the network starts as Jacobi),
     // other weights small Gaussian (splitmix64 + Box-Muller), Adam state zero
     std::vector<float> h(off, 0.f);
