@@ -59,14 +59,15 @@ static_assert(kTileNodes <= kPfElemT0 && kPfElemT0 + kLayerElems <= kPfInfoT0 &&
 
 // LDS layout of the per-Gauss-point records (in units of T).  Symmetric forms store h
 // (24 values); the flow form stores h, sqrt(W) N, sqrt(W) u.grad N, the state terms
-// u, grad u, Rm, sqrt(W), p and div u (58 values, NsRec below).  Strides are padded so
-// that adjacent lanes of phase B (the two halves of a node, and x-adjacent nodes) read
-// distinct banks with 16-byte loads.
+// u, grad u, Rm, sqrt(W), p and div u (58 values, NsRec below).  The strides spread the
+// phase-B reads of one wave (eight nodes x two elements x four quarters) over the LDS
+// banks: with an odd FP64 element stride the ten elements a wave reads start on distinct
+// banks, which cuts the conflict degree of the h_b reads from 5 to 3 (32 banks).
 template <int FORM, typename T>
 struct HLayout {
     static constexpr bool NS = FORM == MF_FORM_NS_SUPG;
     static constexpr int SQ = NS ? 60 : (sizeof(T) == 8 ? 26 : 28);           // per Gauss point
-    static constexpr int SE = 8 * SQ + (sizeof(T) == 8 ? 2 : 4);              // per element
+    static constexpr int SE = 8 * SQ + (sizeof(T) == 8 ? 1 : 4);              // per element
     static constexpr int SL = kLayerElems * SE;                               // per element layer
 };
 
