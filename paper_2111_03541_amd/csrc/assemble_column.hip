@@ -561,7 +561,7 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
 // values are loaded from LDS in 64-lane chunks before any store, and the buffer is in
 // the order of a node-major CSR row block, so an interior node's rows are one contiguous
 // copy; boundary nodes, field-major numbering and Dirichlet masks take the general
-// mapping.
+// mapping.  K is written once and is far larger than the caches: non-temporal stores.
 template <int FORM, typename T>
 __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, T>& S, int wid, int nw)
 {
@@ -597,7 +597,7 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int o = lane + 64 * c;
-                if (o < kNodeVals) dst[o] = (T)vals[c];
+                if (o < kNodeVals) __builtin_nontemporal_store((T)vals[c], &dst[o]);
             }
             continue;
         }
@@ -631,7 +631,7 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
                 if (p.dirichlet[row]) v = (col == row) ? T(1) : T(0);
                 else if (p.dirichlet[col]) v = T(0);
             }
-            K[kpos] = v;
+            __builtin_nontemporal_store(v, &K[kpos]);
         }
     }
     if (wid < kColNodes * NF) {
