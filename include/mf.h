@@ -251,6 +251,64 @@ mf_status mf_pcg(const mf_csr* A, const double* b, double* x, const mf_pcg_opts*
 /* y = A x (FP64 CSR).  Async. */
 mf_status mf_spmv(const mf_csr* A, const double* x, double* y, void* stream);
 
+/*
+ * mf_bicgstab - solve K x = b for a non-symmetric K (the Newton tangent of the flow form
+ * of Sec. 4.3; Sec. 2.2 D-4 leaves the solver open) by BiCGStab from x0 = 0 with shadow
+ * residual b, right-preconditioned by Jacobi (opts->precond MF_PRECOND_JACOBI) or
+ * unpreconditioned (MF_PRECOND_NONE).  Options, result and synchronisation as mf_pcg
+ * (opts->net is ignored, res->fallbacks is 0); the true residual |b - K x|_2 / |b|_2
+ * decides convergence.  On a breakdown (rh.r, rh.Kp or t.t exactly 0 or non-finite), or
+ * when the recurrence residual meets tol but the true residual does not, the method
+ * restarts from the current x with rh = r = b - K x (at most 64 restarts).
+ * x [n_rows] is overwritten.  (sync)
+ * Errors: MF_ERR_ARG (including MF_PRECOND_NN), MF_ERR_NOT_CONVERGED (maxit reached; x and
+ * res hold the last iterate), MF_ERR_NONFINITE (a non-finite true residual, or breakdown
+ * after 64 restarts), MF_ERR_OOM, MF_ERR_HIP.
+ */
+mf_status mf_bicgstab(const mf_csr* A, const double* b, double* x, const mf_pcg_opts* opts,
+                      mf_pcg_result* res, void* stream);
+
+/* ------------------------------------------------------------------------------------
+ * Newton iteration for the steady flow form (Sec. 2.1: the update solves K dU = -R(U)
+ * with K = dR/dU, repeated until the residual vanishes; form of Sec. 4.3).  Each step
+ * assembles K and d = -R(U) in FP64 at the current state with the Dirichlet elimination
+ * (d is 0 on constrained rows, so the update keeps their values), solves K dU = d with
+ * mf_bicgstab (Jacobi) and adds dU to the state.
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+    double rtol;            /* converged when |d|_2 <= rtol |d_0|_2 ...                     */
+    double atol;            /* ... or |d|_2 <= atol (d_0: the residual of the initial state) */
+    int32_t max_steps;      /* updates at most                                              */
+    double lin_tol;         /* relative true-residual tolerance of each linear solve         */
+    int32_t lin_maxit;
+    int32_t check_every;    /* linear solve: iterations between host checks (0 = 8)          */
+    int32_t use_graph;      /* linear solve: replay chunks as a HIP graph (non-default stream) */
+} mf_newton_opts;
+
+#define MF_NEWTON_MAX_HISTORY 64
+typedef struct {
+    int32_t steps;          /* updates applied                                              */
+    int32_t converged;      /* 1 when the residual test passed                              */
+    int32_t lin_iterations; /* BiCGStab iterations over all steps                           */
+    double res_norm[MF_NEWTON_MAX_HISTORY];  /* |d|_2 at the state before update k, k <= steps
+                                                (the first min(steps+1, 64) entries)        */
+} mf_newton_result;
+
+/*
+ * mf_ns_newton - state [4][n_nodes] (device, FP64: u1, u2, u3, p per node) is the initial
+ * guess and carries the Dirichlet values of the constrained DOFs; it is overwritten with
+ * the last iterate.  P is a pattern of the 3D flow form (4 fields, full coupling) in
+ * either numbering; dirichlet [n_rows] (device, may be NULL) marks constrained rows; the
+ * form must be MF_FORM_NS_SUPG.  Workspace for K, d and dU is allocated and freed inside
+ * the call.  (sync)
+ * Errors: those of mf_assemble and mf_bicgstab (a linear solve that stops short of lin_tol
+ * but lowers the residual still gives its update); MF_ERR_NOT_CONVERGED when max_steps is
+ * reached (state and res hold the last iterate).
+ */
+mf_status mf_ns_newton(const mf_pattern_t* P, const mf_form* form, const double* coords, double* state,
+                       const uint8_t* dirichlet, const mf_quadrature* quad, const mf_newton_opts* opts,
+                       mf_newton_result* res, void* stream);
+
 /* ------------------------------------------------------------------------------------
  * Learned preconditioner for mf_pcg on structured-grid scalar systems (node id
  * x + nx (y + ny z), one DOF per node).  A small linear multilevel 3D convolution network

@@ -78,6 +78,18 @@ class _PcgResult(C.Structure):
 
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_NN = 0, 1, 2
 
+NEWTON_MAX_HISTORY = 64
+
+
+class _NewtonOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int32), ("lin_tol", C.c_double),
+                ("lin_maxit", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class _NewtonResult(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("converged", C.c_int32), ("lin_iterations", C.c_int32),
+                ("res_norm", C.c_double * NEWTON_MAX_HISTORY)]
+
 
 class _BatchProblem(C.Structure):
     _fields_ = [("pattern", C.c_void_p), ("form", _Form), ("coords", C.c_void_p), ("fields", _Fields),
@@ -92,6 +104,7 @@ EXPORTS = [
     "mf_assemble_ex", "mf_status_poll", "mf_last_error", "mf_version", "mf_pcg",
     "mf_batch_create", "mf_batch_tune", "mf_batch_run", "mf_batch_info", "mf_batch_destroy",
     "mf_nn_create", "mf_nn_params", "mf_nn_set_system", "mf_nn_apply", "mf_nn_train_step", "mf_nn_destroy", "mf_spmv",
+    "mf_bicgstab", "mf_ns_newton",
 ]
 
 
@@ -127,6 +140,9 @@ def load():
     lib.mf_nn_apply.argtypes = [P, P, P, P]
     lib.mf_nn_train_step.argtypes = [P, P, P, C.c_double, C.POINTER(C.c_double), P, P]
     lib.mf_spmv.argtypes = [C.POINTER(_CSR), P, P, P]
+    lib.mf_bicgstab.argtypes = [C.POINTER(_CSR), P, P, C.POINTER(_PcgOpts), C.POINTER(_PcgResult), P]
+    lib.mf_ns_newton.argtypes = [P, C.POINTER(_Form), P, P, P, C.POINTER(_Quad), C.POINTER(_NewtonOpts),
+                                 C.POINTER(_NewtonResult), P]
     lib.mf_nn_destroy.argtypes = [P]
     lib.mf_nn_destroy.restype = None
     lib.mf_last_error.restype = C.c_char_p
@@ -421,6 +437,49 @@ def pcg(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PREC
     if st != OK and raise_on_fail:
         raise MFError(st, lib.mf_last_error().decode())
     return x, out
+
+
+def bicgstab(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PRECOND_JACOBI,
+             check_every=8, use_graph=True, stream=None, raise_on_fail=True):
+    """Solve K x = b for a non-symmetric FP64 CSR K on the device by BiCGStab from x0 = 0.
+
+    Returns (x, result dict) like pcg."""
+    import torch
+    lib = load()
+    n = int(b.shape[0])
+    if x is None:
+        x = torch.empty(n, dtype=torch.float64, device=b.device)
+    A = _CSR(n, _ptr_any(row_ptr), _ptr_any(col_idx), _ptr(values))
+    opts = _PcgOpts(tol, maxit, check_every, int(bool(use_graph)), precond, None)
+    res = _PcgResult()
+    st = lib.mf_bicgstab(C.byref(A), _ptr(b), _ptr(x), C.byref(opts), C.byref(res), _stream(stream))
+    out = {"iterations": res.iterations, "converged": bool(res.converged), "true_relres": res.true_relres,
+           "status": st}
+    if st != OK and raise_on_fail:
+        raise MFError(st, lib.mf_last_error().decode())
+    return x, out
+
+
+def ns_newton(pattern, form, coords, state, dirichlet=None, rtol=1e-10, atol=0.0, max_steps=20, lin_tol=1e-10,
+              lin_maxit=20000, check_every=8, use_graph=True, points_per_axis=2, stream=None, raise_on_fail=True):
+    """Newton iteration for the steady flow form; state [4][n_nodes] FP64 (cuda) is updated
+    in place.  Returns the result dict (steps, converged, lin_iterations, res_norm list)."""
+    import torch
+    lib = load()
+    assert state.dtype == torch.float64 and state.is_cuda and state.is_contiguous()
+    assert coords.dtype == torch.float64 and coords.is_contiguous()
+    if dirichlet is not None:
+        assert dirichlet.dtype == torch.uint8 and dirichlet.is_cuda
+    opts = _NewtonOpts(rtol, atol, max_steps, lin_tol, lin_maxit, check_every, int(bool(use_graph)))
+    res = _NewtonResult()
+    q = _Quad(points_per_axis)
+    st = lib.mf_ns_newton(pattern.handle, C.byref(form.c), _ptr(coords), _ptr(state), _ptr(dirichlet), C.byref(q),
+                          C.byref(opts), C.byref(res), _stream(stream))
+    out = {"steps": res.steps, "converged": bool(res.converged), "lin_iterations": res.lin_iterations,
+           "res_norm": [res.res_norm[k] for k in range(min(res.steps + 1, NEWTON_MAX_HISTORY))], "status": st}
+    if st != OK and raise_on_fail:
+        raise MFError(st, lib.mf_last_error().decode())
+    return out
 
 
 def spmv(row_ptr, col_idx, values, x, y=None, stream=None):

@@ -260,6 +260,34 @@ mf_status mf_pcg(const mf_csr* A, const double* b, double* x, const mf_pcg_opts*
     return run_pcg(a, res);
 }
 
+mf_status mf_bicgstab(const mf_csr* A, const double* b, double* x, const mf_pcg_opts* opts, mf_pcg_result* res,
+                      void* stream)
+{
+    g_err[0] = 0;
+    if (!A || !opts || !res) return set_error(MF_ERR_ARG, "A, opts or res is NULL");
+    if (A->n_rows < 0 || A->n_rows >= ((int64_t)1 << 31)) return set_error(MF_ERR_ARG, "n_rows out of range");
+    if (A->n_rows > 0 && (!A->row_ptr || !A->col_idx || !A->values || !b || !x))
+        return set_error(MF_ERR_ARG, "NULL matrix or vector");
+    if (!(opts->tol > 0.0) || opts->maxit < 0) return set_error(MF_ERR_ARG, "tol must be > 0 and maxit >= 0");
+    if (opts->precond != MF_PRECOND_NONE && opts->precond != MF_PRECOND_JACOBI)
+        return set_error(MF_ERR_ARG, "BiCGStab takes MF_PRECOND_NONE or MF_PRECOND_JACOBI, not %d",
+                         (int)opts->precond);
+    PcgArgs a{};
+    a.n = A->n_rows;
+    a.row_ptr = A->row_ptr;
+    a.col_idx = A->col_idx;
+    a.values = A->values;
+    a.b = b;
+    a.x = x;
+    a.tol = opts->tol;
+    a.maxit = opts->maxit;
+    a.check_every = opts->check_every;
+    a.use_graph = opts->use_graph && stream != nullptr;
+    a.stream = (hipStream_t)stream;
+    a.precond = opts->precond;
+    return run_bicgstab(a, res);
+}
+
 mf_status mf_spmv(const mf_csr* A, const double* x, double* y, void* stream)
 {
     if (!A) return set_error(MF_ERR_ARG, "A is NULL");

@@ -33,6 +33,8 @@ struct PcgArgs {
 };
 
 mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res);
+// BiCGStab with Jacobi or no preconditioner (precond MF_PRECOND_JACOBI / MF_PRECOND_NONE)
+mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res);
 mf_status run_spmv(const mf_csr* A, const double* x, double* y, hipStream_t s);
 
 }  // namespace mf

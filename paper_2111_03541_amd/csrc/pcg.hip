@@ -382,6 +382,189 @@ __global__ void k_set(double* p, int n, double v)
     if (i < n) p[i] = v;
 }
 
+// ------------------------------------------------------------------------------------
+// BiCGStab for non-symmetric K (the Newton tangent of the flow form), right-preconditioned
+// by Jacobi (M = diag K), from x0 = 0 with the shadow residual rh = b, all scalars on
+// the device.  One iteration:
+//   k_bcg_dir              p = r + beta (p - omega v),  ph = M^-1 p
+//   SpMV                   v = K ph, partials rh.v
+//   k_bcg_alpha (1 block)  alpha = rho / rh.v
+//   k_bcg_s                s = r - alpha v (in r),  sh = M^-1 s
+//   SpMV                   t = K sh
+//   k_bcg_dots2            partials t.s and t.t
+//   k_bcg_omega (1 block)  omega = t.s / t.t
+//   k_bcg_update           x += alpha ph + omega sh,  r = s - omega t, partials rh.r, r.r
+//   k_bcg_beta  (1 block)  rho = rh.r, r.r; beta = (rho / rho_old)(alpha / omega)
+// A zero or non-finite rh.v, t.t, t.s or rho sets the breakdown flag (alpha or omega is
+// then 0, so x stays finite) and the host judges the true residual.
+// ------------------------------------------------------------------------------------
+enum { B_RHO = 0, B_ALPHA, B_OMEGA, B_BETA, B_RR, B_BREAK, B_COUNT };
+
+__global__ void k_bcg_beta(const double* __restrict__ partial, int nb, double* s, int init)
+{
+    __shared__ double sh[kThreads / 64];
+    const double rho = sum_partials(partial, nb, sh);
+    const double rr = sum_partials(partial + nb, nb, sh);
+    if (threadIdx.x == 0) {
+        const double rho_old = s[B_RHO], alpha = s[B_ALPHA], omega = s[B_OMEGA];
+        double beta = 0.0;
+        if (init) s[B_BREAK] = 0.0;  // a (re)start clears the breakdown flag
+        if (!init) {
+            if (rho_old != 0.0 && omega != 0.0) beta = (rho / rho_old) * (alpha / omega);
+            else s[B_BREAK] = 1.0;
+        }
+        if (!isfinite(rho) || rho == 0.0) s[B_BREAK] = 1.0;
+        s[B_BETA] = beta;
+        s[B_RHO] = rho;
+        s[B_RR] = rr;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_bcg_dir(int n, const double* __restrict__ s,
+                                                      const double* __restrict__ r, const double* __restrict__ v,
+                                                      const double* __restrict__ dinv, double* __restrict__ p,
+                                                      double* __restrict__ ph)
+{
+    const double beta = s[B_BETA], omega = s[B_OMEGA];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double pi = fma(beta, fma(-omega, v[i], p[i]), r[i]);
+        p[i] = pi;
+        ph[i] = dinv[i] * pi;
+    }
+}
+
+__global__ void k_bcg_alpha(const double* __restrict__ part, int nb, double* s)
+{
+    __shared__ double sh[kThreads / 64];
+    const double rv = sum_partials(part, nb, sh);
+    if (threadIdx.x == 0) {
+        const bool ok = rv != 0.0 && isfinite(rv);
+        s[B_ALPHA] = ok ? s[B_RHO] / rv : 0.0;
+        if (!ok) s[B_BREAK] = 1.0;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_bcg_s(int n, const double* __restrict__ s, double* __restrict__ r,
+                                                    const double* __restrict__ v, const double* __restrict__ dinv,
+                                                    double* __restrict__ shat)
+{
+    const double alpha = s[B_ALPHA];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double si = fma(-alpha, v[i], r[i]);
+        r[i] = si;
+        shat[i] = dinv[i] * si;
+    }
+}
+
+// partials [0..nb) t.s, [nb..2nb) t.t
+__global__ void __launch_bounds__(kThreads) k_bcg_dots2(int n, const double* __restrict__ t,
+                                                        const double* __restrict__ sv, double* __restrict__ partial)
+{
+    __shared__ double sh[kThreads / 64];
+    double ts = 0.0, tt = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double ti = t[i];
+        ts = fma(ti, sv[i], ts);
+        tt = fma(ti, ti, tt);
+    }
+    const double a = block_sum_all(ts, sh);
+    const double b = block_sum_all(tt, sh);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = a;
+        partial[gridDim.x + blockIdx.x] = b;
+    }
+}
+
+__global__ void k_bcg_omega(const double* __restrict__ partial, int nb, double* s)
+{
+    __shared__ double sh[kThreads / 64];
+    const double ts = sum_partials(partial, nb, sh);
+    const double tt = sum_partials(partial + nb, nb, sh);
+    if (threadIdx.x == 0) {
+        const bool ok = tt > 0.0 && isfinite(tt) && isfinite(ts);
+        s[B_OMEGA] = ok ? ts / tt : 0.0;
+        if (!ok || ts == 0.0) s[B_BREAK] = 1.0;
+    }
+}
+
+// x += alpha ph + omega sh; r = s - omega t (s is in r); partials [0..nb) rh.r, [nb..2nb) r.r
+__global__ void __launch_bounds__(kThreads) k_bcg_update(int n, const double* __restrict__ s, double* __restrict__ x,
+                                                         double* __restrict__ r, const double* __restrict__ t,
+                                                         const double* __restrict__ ph,
+                                                         const double* __restrict__ shat,
+                                                         const double* __restrict__ rh, double* __restrict__ partial)
+{
+    __shared__ double sh[kThreads / 64];
+    const double alpha = s[B_ALPHA], omega = s[B_OMEGA];
+    double a = 0.0, b = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        x[i] = fma(omega, shat[i], fma(alpha, ph[i], x[i]));
+        const double ri = fma(-omega, t[i], r[i]);
+        r[i] = ri;
+        a = fma(rh[i], ri, a);
+        b = fma(ri, ri, b);
+    }
+    const double A = block_sum_all(a, sh);
+    const double B = block_sum_all(b, sh);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = A;
+        partial[gridDim.x + blockIdx.x] = B;
+    }
+}
+
+// restart from the current x: r = rh = b - Ax (Ax given), p = v = 0; partials rh.r, r.r
+__global__ void __launch_bounds__(kThreads) k_bcg_restart(int n, const double* __restrict__ b,
+                                                          const double* __restrict__ ax, double* __restrict__ r,
+                                                          double* __restrict__ rh, double* __restrict__ p,
+                                                          double* __restrict__ vv, double* __restrict__ partial)
+{
+    __shared__ double sh[kThreads / 64];
+    double a = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double ri = b[i] - ax[i];
+        r[i] = ri;
+        rh[i] = ri;
+        p[i] = 0.0;
+        vv[i] = 0.0;
+        a = fma(ri, ri, a);
+    }
+    const double A = block_sum_all(a, sh);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = A;
+        partial[gridDim.x + blockIdx.x] = A;
+    }
+}
+
+// diag inverse (Jacobi or identity), x = 0, r = rh = b, p = v = 0; partials rh.r, r.r
+__global__ void __launch_bounds__(kThreads) k_bcg_init(int n, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                                       const double* __restrict__ b, double* __restrict__ dinv,
+                                                       double* __restrict__ x, double* __restrict__ r,
+                                                       double* __restrict__ rh, double* __restrict__ p,
+                                                       double* __restrict__ vv, int jacobi, double* __restrict__ partial)
+{
+    __shared__ double sh[kThreads / 64];
+    double a = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double di = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] == i) di = v[k];
+        dinv[i] = (jacobi && di != 0.0) ? 1.0 / di : 1.0;
+        x[i] = 0.0;
+        const double bi = b[i];
+        r[i] = bi;
+        rh[i] = bi;
+        p[i] = 0.0;
+        vv[i] = 0.0;
+        a = fma(bi, bi, a);
+    }
+    const double A = block_sum_all(a, sh);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = A;
+        partial[gridDim.x + blockIdx.x] = A;
+    }
+}
+
 int spmv_blocks_for(int n)
 {
     const int want = (n + kSlots - 1) / kSlots;
@@ -594,6 +777,192 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
     res->true_relres = std::sqrt(hb2[0]) / bnorm;
     res->iterations = it;
     return set_error(MF_ERR_NOT_CONVERGED, "PCG reached maxit = %d (true relative residual %.3e)", a.maxit,
+                     res->true_relres);
+}
+
+
+mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
+{
+    const int n = (int)a.n;
+    hipStream_t s = a.stream;
+    res->iterations = 0;
+    res->true_relres = 0.0;
+    res->fallbacks = 0;
+    res->converged = 0;
+    if (n == 0) {
+        res->converged = 1;
+        return MF_OK;
+    }
+    const int vec_blocks = (int)std::min<int64_t>(kVecBlocks, (n + kThreads - 1) / kThreads);
+    const int spmv_blocks = spmv_blocks_for(n);
+    const int nb = std::max(vec_blocks, spmv_blocks);
+
+    std::vector<void*> owned;
+    auto dalloc = [&](size_t bytes) -> void* {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        owned.push_back(p);
+        return p;
+    };
+    struct Free {
+        std::vector<void*>* v;
+        ~Free() { for (void* p : *v) (void)hipFree(p); }
+    } fr{&owned};
+    double* dinv = (double*)dalloc(sizeof(double) * n);
+    double* r = (double*)dalloc(sizeof(double) * n);
+    double* rh = (double*)dalloc(sizeof(double) * n);
+    double* p = (double*)dalloc(sizeof(double) * n);
+    double* ph = (double*)dalloc(sizeof(double) * n);
+    double* v = (double*)dalloc(sizeof(double) * n);
+    double* sh = (double*)dalloc(sizeof(double) * n);
+    double* t = (double*)dalloc(sizeof(double) * n);
+    double* rv_part = (double*)dalloc(sizeof(double) * spmv_blocks);
+    double* partial = (double*)dalloc(sizeof(double) * 2 * nb);
+    double* sc = (double*)dalloc(sizeof(double) * (B_COUNT + 2));
+    if (!dinv || !r || !rh || !p || !ph || !v || !sh || !t || !rv_part || !partial || !sc)
+        return set_error(MF_ERR_OOM, "BiCGStab workspace allocation failed");
+    const int jac = a.precond == MF_PRECOND_JACOBI ? 1 : 0;
+
+    // ELL copy of K when the padding stays small (as in run_pcg)
+    int width = 0, nnz32 = 0;
+    {
+        int* dmax = (int*)dalloc(sizeof(int));
+        if (!dmax) return set_error(MF_ERR_OOM, "BiCGStab workspace allocation failed");
+        MF_HIP(hipMemsetAsync(dmax, 0, sizeof(int), s));
+        k_max_row<<<vec_blocks, kThreads, 0, s>>>(n, a.row_ptr, dmax);
+        MF_HIP(hipMemcpyAsync(&width, dmax, sizeof(int), hipMemcpyDeviceToHost, s));
+        MF_HIP(hipMemcpyAsync(&nnz32, a.row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        MF_HIP(hipStreamSynchronize(s));
+    }
+    int32_t* ecol = nullptr;
+    double* eval = nullptr;
+    if (width > 0 && (int64_t)width * n <= (int64_t)nnz32 + nnz32 / 2) {
+        ecol = (int32_t*)dalloc(sizeof(int32_t) * (size_t)width * n);
+        eval = (double*)dalloc(sizeof(double) * (size_t)width * n);
+        if (ecol && eval) {
+            k_to_ell<<<vec_blocks, kThreads, 0, s>>>(n, width, a.row_ptr, a.col_idx, a.values, ecol, eval);
+        } else {
+            (void)hipGetLastError();
+            ecol = nullptr;
+            eval = nullptr;
+        }
+    }
+    auto spmv = [&](const double* x_in, double* y, const double* w, double* part) {
+        if (ecol)
+            k_spmv_ell_dot<<<spmv_blocks, kThreads, 0, s>>>(n, width, ecol, eval, x_in, y, w, part);
+        else
+            k_spmv_dot<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, x_in, y, w, part);
+    };
+
+    k_set<<<1, 64, 0, s>>>(sc, B_COUNT + 2, 0.0);
+    k_bcg_init<<<vec_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, a.b, dinv, a.x, r, rh, p, v, jac,
+                                               partial);
+    k_bcg_beta<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, 1);
+    double h[B_COUNT];
+    MF_HIP(hipGetLastError());
+    MF_HIP(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s));
+    MF_HIP(hipStreamSynchronize(s));
+    const double bnorm = std::sqrt(h[B_RR]);
+    if (bnorm == 0.0) {
+        res->converged = 1;
+        return MF_OK;
+    }
+
+    // each iteration ends with the reduction of rh.r and r.r (rho and beta for the next
+    // one), so the scalars hold the newest residual norm when a chunk ends
+    auto iteration = [&]() {
+        k_bcg_dir<<<vec_blocks, kThreads, 0, s>>>(n, sc, r, v, dinv, p, ph);
+        spmv(ph, v, rh, rv_part);
+        k_bcg_alpha<<<1, kThreads, 0, s>>>(rv_part, spmv_blocks, sc);
+        k_bcg_s<<<vec_blocks, kThreads, 0, s>>>(n, sc, r, v, dinv, sh);
+        spmv(sh, t, nullptr, nullptr);
+        k_bcg_dots2<<<vec_blocks, kThreads, 0, s>>>(n, t, r, partial);
+        k_bcg_omega<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc);
+        k_bcg_update<<<vec_blocks, kThreads, 0, s>>>(n, sc, a.x, r, t, ph, sh, rh, partial);
+        k_bcg_beta<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, 0);
+    };
+
+    const int chunk = a.check_every > 0 ? a.check_every : 8;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    bool use_graph = a.use_graph != 0;
+    if (use_graph) {
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            for (int k = 0; k < chunk; ++k) iteration();
+            hipError_t e = hipStreamEndCapture(s, &graph);
+            if (e != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                use_graph = false;
+                (void)hipGetLastError();
+            }
+        } else {
+            use_graph = false;
+            (void)hipGetLastError();
+        }
+    }
+    struct GraphFree {
+        hipGraphExec_t* e;
+        hipGraph_t* g;
+        ~GraphFree() {
+            if (*e) (void)hipGraphExecDestroy(*e);
+            if (*g) (void)hipGraphDestroy(*g);
+        }
+    } gf{&exec, &graph};
+
+    double hb2[2] = {0, 0};
+    auto true_relres = [&]() -> mf_status {
+        k_true_res<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, a.x, a.b, partial);
+        k_reduce2<<<1, kThreads, 0, s>>>(partial, spmv_blocks, sc + B_COUNT);
+        MF_HIP(hipMemcpyAsync(hb2, sc + B_COUNT, sizeof(hb2), hipMemcpyDeviceToHost, s));
+        MF_HIP(hipStreamSynchronize(s));
+        res->true_relres = std::sqrt(hb2[0]) / bnorm;
+        return MF_OK;
+    };
+    // When the recurrence claims convergence that the true residual denies (rounding
+    // after large intermediate residuals separates the two), or on a breakdown, the
+    // method restarts from the current x with r = rh = b - Kx.
+    constexpr int kMaxRestarts = 64;
+    int restarts = 0;
+    int it = 0;
+    while (it < a.maxit) {
+        const int todo = std::min(chunk, a.maxit - it);
+        if (use_graph && todo == chunk) {
+            MF_HIP(hipGraphLaunch(exec, s));
+        } else {
+            for (int k = 0; k < todo; ++k) iteration();
+        }
+        MF_HIP(hipGetLastError());
+        it += todo;
+        MF_HIP(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s));
+        MF_HIP(hipStreamSynchronize(s));
+        const bool broke = h[B_BREAK] != 0.0 || !std::isfinite(h[B_RR]);
+        if (std::sqrt(h[B_RR]) / bnorm <= a.tol || broke) {
+            mf_status st = true_relres();
+            if (st != MF_OK) return st;
+            if (res->true_relres <= a.tol) {
+                res->iterations = it;
+                res->converged = 1;
+                return MF_OK;
+            }
+            if (!std::isfinite(res->true_relres) || ++restarts > kMaxRestarts) {
+                res->iterations = it;
+                return set_error(MF_ERR_NONFINITE,
+                                 "BiCGStab breakdown near iteration %d after %d restarts (true relative residual %.3e)",
+                                 it, restarts - 1, res->true_relres);
+            }
+            spmv(a.x, t, nullptr, nullptr);
+            k_bcg_restart<<<vec_blocks, kThreads, 0, s>>>(n, a.b, t, r, rh, p, v, partial);
+            k_bcg_beta<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, 1);
+            MF_HIP(hipGetLastError());
+        }
+    }
+    mf_status st = true_relres();
+    if (st != MF_OK) return st;
+    res->iterations = it;
+    if (res->true_relres <= a.tol) {
+        res->converged = 1;
+        return MF_OK;
+    }
+    return set_error(MF_ERR_NOT_CONVERGED, "BiCGStab reached maxit = %d (true relative residual %.3e)", a.maxit,
                      res->true_relres);
 }
 

@@ -1,0 +1,162 @@
+"""BiCGStab (mf_bicgstab) and the Newton driver of the flow form (mf_ns_newton) on the
+GPU, against the oracle: scipy's direct solve of the oracle's systems and the oracle's
+own Newton iteration (oracle/newton.py)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.newton as ON
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def taus(n, U=1.0, nu=0.01):
+    h = 1.0 / n
+    tm = ((2 * U / h) ** 2 + 9 * (4 * nu / h ** 2) ** 2) ** -0.5
+    return tm, h * h / (12 * tm)
+
+
+def prm(n, rho=1.0, mu=0.01):
+    tm, tc = taus(n)
+    return dict(rho=rho, mu=mu, tau_m=tm, tau_c=tc)
+
+
+def ns_tangent(n, seed, numbering=O.NODE_MAJOR):
+    """Oracle tangent and residual of a cavity at a random interior state (non-symmetric K)."""
+    mesh = W.structured_mesh((n, n, n))
+    pat = O.Pattern(mesh, 4, numbering=numbering)
+    st, mask = W.flow_boundary(mesh, "cavity", field_major=numbering == O.FIELD_MAJOR)
+    rng = np.random.default_rng(seed)
+    node_mask = mask.reshape(-1, 4).T if numbering == O.NODE_MAJOR else mask.reshape(4, -1)
+    st = np.where(node_mask != 0, st, 0.3 * rng.standard_normal(st.shape))
+    K, d = O.assemble(pat, O.NS_SUPG, prm(n), state=st, dirichlet=mask)
+    return pat, K, d
+
+
+def dev_csr(pat, K):
+    return (torch.from_numpy(pat.row_ptr.astype(np.int32)).cuda(), torch.from_numpy(pat.col_idx).cuda(),
+            torch.from_numpy(K).cuda())
+
+
+def test_bicgstab_solves_the_flow_tangent(mf):
+    say("bicgstab flow tangent 6^3")
+    pat, K, d = ns_tangent(6, 3)
+    S = pat.to_scipy(K)
+    assert abs(S - S.T).max() > 1e-3  # the tangent is not symmetric
+    import scipy.sparse.linalg as spla
+    x_ref = spla.spsolve(S.tocsc(), d)
+    rp, ci, v = dev_csr(pat, K)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        x, res = mf.bicgstab(rp, ci, v, torch.from_numpy(d).cuda(), tol=1e-12, check_every=4, stream=s)
+    s.synchronize()
+    say(f"  {res}")
+    assert res["converged"] and res["true_relres"] <= 1e-12
+    xh = x.cpu().numpy()
+    assert np.linalg.norm(d - S @ xh) <= 1e-12 * np.linalg.norm(d)
+    assert np.linalg.norm(xh - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+
+
+def test_bicgstab_on_spd_matches_pcg(mf):
+    say("bicgstab poisson 10^3")
+    n = 10
+    mesh = W.structured_mesh((n, n, n), jitter=0.15, seed=4)
+    pat = O.Pattern(mesh, 1)
+    k = W.lognormal_elem(mesh.n_elems, 0.5, 5)
+    f = W.uniform_nodal(1, mesh.n_nodes, 0, 1, 6)
+    K, d = O.assemble(pat, O.POISSON, {"coef": 1.0}, elem_param=k, nodal_src=f,
+                      dirichlet=W.boundary_node_mask(mesh.shape))
+    x_ref, it, rel = O.pcg_jacobi(pat.row_ptr, pat.col_idx, K, d, tol=1e-12)
+    rp, ci, v = dev_csr(pat, K)
+    x, res = mf.bicgstab(rp, ci, v, torch.from_numpy(d).cuda(), tol=1e-12, use_graph=False)
+    say(f"  {res}, pcg {it}")
+    assert res["converged"]
+    assert np.linalg.norm(x.cpu().numpy() - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+
+
+def test_bicgstab_edge_cases(mf):
+    say("bicgstab edge cases")
+    pat, K, d = ns_tangent(3, 5)
+    rp, ci, v = dev_csr(pat, K)
+    # zero right-hand side: x = 0, converged at once
+    x, res = mf.bicgstab(rp, ci, v, torch.zeros(pat.n_rows, dtype=torch.float64, device="cuda"), tol=1e-10)
+    assert res["converged"] and res["iterations"] == 0 and float(x.abs().max()) == 0.0
+    # maxit = 0: not converged, x = 0, true residual 1
+    x, res = mf.bicgstab(rp, ci, v, torch.from_numpy(d).cuda(), tol=1e-10, maxit=0, raise_on_fail=False)
+    assert res["status"] == mf.ERR_NOT_CONVERGED and abs(res["true_relres"] - 1.0) < 1e-12
+    # the learned preconditioner is for SPD systems only
+    with pytest.raises(mf.MFError):
+        mf.bicgstab(rp, ci, v, torch.from_numpy(d).cuda(), precond=mf.PRECOND_NN)
+    # no preconditioner still converges
+    x, res = mf.bicgstab(rp, ci, v, torch.from_numpy(d).cuda(), tol=1e-10, precond=mf.PRECOND_NONE)
+    assert res["converged"]
+
+
+def run_gpu_newton(mf, mesh, kind, p, numbering=0, **kw):
+    dev = torch.device("cuda:0")
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 4, numbering=numbering)
+    st0, mask = W.flow_boundary(mesh, kind, field_major=numbering == 1)
+    state = torch.from_numpy(st0).to(dev).contiguous()
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    form = mf.Form(mf.NS_SUPG, rho=p["rho"], mu=p["mu"], tau_m=p["tau_m"], tau_c=p["tau_c"])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        res = mf.ns_newton(pat, form, coords, state, dirichlet=torch.from_numpy(mask).to(dev), stream=s, **kw)
+    s.synchronize()
+    return state.cpu().numpy(), res, st0, mask
+
+
+@pytest.mark.parametrize("numbering", [0, 1])
+def test_newton_reaches_couette_exactly(mf, numbering):
+    say("newton couette 6^3 numbering", numbering)
+    n = 6
+    mesh = W.structured_mesh((n, n, n))
+    st, res, st0, mask = run_gpu_newton(mf, mesh, "couette", prm(n), numbering, rtol=1e-13, lin_tol=1e-12)
+    say(f"  steps {res['steps']} lin {res['lin_iterations']} res {['%.2e' % r for r in res['res_norm']]}")
+    exact = np.zeros_like(st)
+    exact[0] = mesh.coords[2]
+    assert res["converged"]
+    assert np.abs(st - exact).max() < 1e-10
+
+
+def test_newton_cavity_matches_oracle(mf):
+    say("newton cavity 8^3 vs oracle")
+    n = 8
+    mesh = W.structured_mesh((n, n, n))
+    p = prm(n)
+    st, res, st0, mask = run_gpu_newton(mf, mesh, "cavity", p, rtol=1e-12, lin_tol=1e-12)
+    pat = O.Pattern(mesh, 4)
+    st_ref, hist, ok = ON.ns_newton(pat, p, st0, mask, rtol=1e-12, max_steps=20)
+    say(f"  gpu {['%.2e' % r for r in res['res_norm']]} lin {res['lin_iterations']}")
+    say(f"  oracle {['%.2e' % r for r in hist]}")
+    assert res["converged"] and ok
+    # the first residual is the same assembly on both sides
+    assert abs(res["res_norm"][0] - hist[0]) <= 1e-12 * hist[0]
+    # quadratic convergence gives the same number of steps
+    assert abs(res["steps"] - (len(hist) - 1)) <= 1
+    scale = np.abs(st_ref).max()
+    assert np.abs(st - st_ref).max() <= 1e-9 * scale
+
+
+def test_newton_max_steps_and_converged_start(mf):
+    say("newton max_steps / converged start")
+    n = 4
+    mesh = W.structured_mesh((n, n, n))
+    p = prm(n)
+    st, res, st0, mask = run_gpu_newton(mf, mesh, "cavity", p, max_steps=0, raise_on_fail=False)
+    assert res["status"] == mf.ERR_NOT_CONVERGED and res["steps"] == 0
+    assert np.array_equal(st, st0)
+    pat = O.Pattern(mesh, 4)
+    _, d = O.assemble(pat, O.NS_SUPG, p, state=st0, dirichlet=mask)
+    assert abs(res["res_norm"][0] - np.linalg.norm(d)) <= 1e-12 * np.linalg.norm(d)
+    # a state that already satisfies the test takes no step
+    st, res, st0, mask = run_gpu_newton(mf, mesh, "cavity", p, atol=1e3)
+    assert res["converged"] and res["steps"] == 0 and np.array_equal(st, st0)

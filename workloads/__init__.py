@@ -239,6 +239,30 @@ def dof_mask(node_mask: np.ndarray, n_fields: int, field_major: bool,
     return m.T.reshape(-1).copy()
 
 
+def flow_boundary(mesh: Mesh, kind: str, field_major: bool = False, lid_speed: float = 1.0):
+    """Initial state and Dirichlet rows of an enclosed 3D flow on a structured box mesh.
+
+    kind "couette": u = (z, 0, 0) on every boundary node; "cavity": u = (lid_speed, 0, 0)
+    on the nodes of the top face z = max (edges included), u = 0 on the rest of the
+    boundary.  Velocity is constrained on all boundary nodes and the pressure at node 0.
+    Interior values start at 0.  Returns (state [4][n_nodes] float64, DOF mask uint8).
+    """
+    coords = mesh.coords
+    nn = mesh.n_nodes
+    on = boundary_node_mask(mesh.shape)
+    state = np.zeros((4, nn))
+    if kind == "couette":
+        state[0] = np.where(on != 0, coords[2], 0.0)
+    elif kind == "cavity":
+        top = np.isclose(coords[2], coords[2].max())
+        state[0] = np.where(top, lid_speed, 0.0)
+    else:
+        raise ValueError(kind)
+    mask = dof_mask(on, 4, field_major, fields=(0, 1, 2))
+    mask[3 * nn if field_major else 3] = 1  # pressure of node 0
+    return state, mask
+
+
 def batch_problem_sizes(n_problems: int, lo: int, hi: int, base_seed: int = 6):
     """Per-problem element counts per axis, each drawn U{lo..hi} with seed base_seed + p."""
     sizes = []
