@@ -223,6 +223,68 @@ def bench_ns(dev, steps=10, warmup=3, n=48):
             "alg_bytes": B, "hbm_frac": B / avg / HBM_PEAK}
 
 
+def ns_taus(n, U=1.0, nu=0.01):
+    """Stabilisation constants from the element size h = 1/n (U = 1, nu = 0.01)."""
+    h = 1.0 / n
+    tm = ((2 * U / h) ** 2 + 9 * (4 * nu / h ** 2) ** 2) ** -0.5
+    return tm, h * h / (12 * tm)
+
+
+def run_newton(dev, n, rtol=1e-10):
+    """Lid-driven cavity on n^3 Q1 hexes (rho 1, mu 0.01): mf_ns_newton from a zero interior."""
+    import torch
+    import workloads as W
+    import paper_2111_03541_amd as mf
+    mesh = W.structured_mesh((n, n, n))
+    st0, mask = W.flow_boundary(mesh, "cavity")
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 4)
+    tm, tc = ns_taus(n)
+    form = mf.Form(mf.NS_SUPG, rho=1.0, mu=0.01, tau_m=tm, tau_c=tc)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    state = torch.from_numpy(st0).to(dev).contiguous()
+    m = torch.from_numpy(mask).to(dev)
+    s = torch.cuda.Stream(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        res = mf.ns_newton(pat, form, coords, state, dirichlet=m, rtol=rtol, lin_tol=1e-10, stream=s)
+    s.synchronize()
+    wall = time.perf_counter() - t0
+    return mesh, pat, res, wall
+
+
+def bench_newton(dev, n=32, cpu=True, n_cpu=16):
+    """Newton for the steady flow form (lid-driven cavity, 4 fields per node): FP64 tangent
+    and residual assembled at every step, BiCGStab (Jacobi) to 1e-10, until |R| falls by
+    1e-10.  The oracle (scipy LU for each step) is timed on a smaller mesh beside the
+    GPU at the same size.  Jacobi-BiCGStab stops scaling past about 32^3 on this system
+    (40^3: 24k linear iterations; 48^3 does not converge), hence 32^3."""
+    run_newton(dev, 6)  # warm-up
+    mesh, pat, res, wall = run_newton(dev, n)
+    log(f"[bench] Newton cavity {n}^3: {res['steps']} steps, {res['lin_iterations']} BiCGStab iterations, "
+        f"{wall * 1e3:.1f} ms, |R| {['%.1e' % r for r in res['res_norm']]}")
+    out = {"n": n, "n_dofs": pat.n_rows, "nnz": pat.nnz, "steps": res["steps"], "converged": res["converged"],
+           "lin_iterations": res["lin_iterations"], "ms": wall * 1e3, "res_norm": res["res_norm"]}
+    _, pat_s, res_s, wall_s = run_newton(dev, n_cpu)
+    out["gpu_small"] = {"n": n_cpu, "steps": res_s["steps"], "lin_iterations": res_s["lin_iterations"],
+                        "ms": wall_s * 1e3}
+    if cpu:
+        import oracle as O
+        import oracle.newton as ON
+        import workloads as W
+        m = W.structured_mesh((n_cpu, n_cpu, n_cpu))
+        st0, mask = W.flow_boundary(m, "cavity")
+        tm, tc = ns_taus(n_cpu)
+        t0 = time.perf_counter()
+        _, hist, ok = ON.ns_newton(O.Pattern(m, 4), dict(rho=1.0, mu=0.01, tau_m=tm, tau_c=tc), st0, mask,
+                                   rtol=1e-10)
+        t = time.perf_counter() - t0
+        out["cpu_oracle_small"] = {"n": n_cpu, "steps": len(hist) - 1, "converged": ok, "ms": t * 1e3,
+                                   "kind": "oracle (FP64 assembly, scipy sparse LU per step)", "cores": 1}
+        log(f"[bench] oracle Newton {n_cpu}^3: {len(hist) - 1} steps in {t:.1f} s; GPU {wall_s * 1e3:.1f} ms")
+    return out
+
+
 def cpu_baseline(mesh, E, b):
     import oracle as O
     t0 = time.perf_counter()
@@ -341,6 +403,7 @@ def main():
     record["secondary"]["poisson_96_pcg_time_to_1e-8"] = bench_pcg(dev)
     record["secondary"]["batched_256_f32"] = bench_batch(dev)
     record["secondary"]["ns_48_f32"] = bench_ns(dev)
+    record["secondary"]["ns_newton_cavity_32"] = bench_newton(dev, cpu=not args.no_cpu)
     if not args.no_cpu:
         log("[bench] timing the oracle on the host")
         record["cpu_baseline"] = cpu_baseline(mesh, E, b)

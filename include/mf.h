@@ -279,7 +279,8 @@ typedef struct {
     double rtol;            /* converged when |d|_2 <= rtol |d_0|_2 ...                     */
     double atol;            /* ... or |d|_2 <= atol (d_0: the residual of the initial state) */
     int32_t max_steps;      /* updates at most                                              */
-    double lin_tol;         /* relative true-residual tolerance of each linear solve         */
+    double lin_tol;         /* floor of the linear solves' relative true-residual tolerance:
+                               step k asks for max(lin_tol, min(0.1, |d_k|_2 / |d_0|_2))   */
     int32_t lin_maxit;
     int32_t check_every;    /* linear solve: iterations between host checks (0 = 8)          */
     int32_t use_graph;      /* linear solve: replay chunks as a HIP graph (non-default stream) */
@@ -301,9 +302,10 @@ typedef struct {
  * either numbering; dirichlet [n_rows] (device, may be NULL) marks constrained rows; the
  * form must be MF_FORM_NS_SUPG.  Workspace for K, d and dU is allocated and freed inside
  * the call.  (sync)
- * Errors: those of mf_assemble and mf_bicgstab (a linear solve that stops short of lin_tol
- * but lowers the residual still gives its update); MF_ERR_NOT_CONVERGED when max_steps is
- * reached (state and res hold the last iterate).
+ * Errors: those of mf_assemble, and of mf_bicgstab unless the solve lowered the residual
+ * (a solve that stops short of its tolerance, by the iteration limit or a breakdown, still
+ * gives its update); MF_ERR_NOT_CONVERGED when max_steps is reached (state and res hold
+ * the last iterate).
  */
 mf_status mf_ns_newton(const mf_pattern_t* P, const mf_form* form, const double* coords, double* state,
                        const uint8_t* dirichlet, const mf_quadrature* quad, const mf_newton_opts* opts,

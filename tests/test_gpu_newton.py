@@ -140,8 +140,9 @@ def test_newton_cavity_matches_oracle(mf):
     assert res["converged"] and ok
     # the first residual is the same assembly on both sides
     assert abs(res["res_norm"][0] - hist[0]) <= 1e-12 * hist[0]
-    # quadratic convergence gives the same number of steps
-    assert abs(res["steps"] - (len(hist) - 1)) <= 1
+    # the inexact linear solves (tolerance tied to the Newton residual) cost at most a few
+    # more steps than the oracle's exact ones
+    assert res["steps"] <= len(hist) + 2
     scale = np.abs(st_ref).max()
     assert np.abs(st - st_ref).max() <= 1e-9 * scale
 
