@@ -202,6 +202,52 @@ mf_status mf_batch_info(const mf_batch_t* batch, int64_t* n_items, int32_t* n_wo
 void mf_batch_destroy(mf_batch_t* batch);
 
 /* ------------------------------------------------------------------------------------
+ * Boundary forms: the physics one dimension lower (Sec. 2.2, opening of the algorithm),
+ * integrated over element faces with the 2x2 Gauss rule of the face and added into an
+ * assembled K and d.  Forms of Sec. 4.1 (thermal) and Sec. 4.2 (elasticity), with the
+ * sign reading of the domain forms (R = -d_paper, K = dR/dU, d = -R(U)):
+ *   MF_BFORM_PENALTY     R_(a,i) = int coef N_a (u_i - g_i)          fix (1 or 3 fields)
+ *   MF_BFORM_CONVECTION  R_a     = int coef N_a (T - T_env)           coef = h   (1 field)
+ *   MF_BFORM_RADIATION   R_a     = int coef N_a (T^4 - T_env^4)       coef = e_m sigma^b
+ *   MF_BFORM_FLUX        R_a     = - int coef N_a n . grad T          coef = k: the flux
+ *                        term of the thermal fix condition (grad T of the face's element)
+ *   MF_BFORM_TRACTION    R_(a,i) = - int N_a sigma^l_ij n_j           load (3 fields)
+ * g / T_env come from `target` ([nf][n_nodes] nodal values, interpolated) when given,
+ * else from value[0..nf); sigma^l is value[0..9) row-major; n is the outward unit normal.
+ * ------------------------------------------------------------------------------------ */
+typedef enum {
+    MF_BFORM_PENALTY = 0,
+    MF_BFORM_CONVECTION = 1,
+    MF_BFORM_RADIATION = 2,
+    MF_BFORM_FLUX = 3,
+    MF_BFORM_TRACTION = 4
+} mf_bform_kind;
+
+typedef struct {
+    mf_bform_kind kind;
+    double coef;
+    double value[9];
+} mf_bform;
+
+/*
+ * mf_assemble_boundary - adds the face integrals of `form` into K [nnz] and d [n_rows]
+ * (precision prec, the layout of mf_assemble), so call it after mf_assemble, without a
+ * Dirichlet mask there (boundary forms replace the elimination).  Faces: face_elem
+ * [n_faces] element ids and face_id [n_faces] local faces 2 * axis + side (side 1: the
+ * face at xi_axis = +1), device arrays.  state [nf][n_nodes] (device, precision prec, or
+ * NULL = 0) is the linearisation point of the radiation, flux and penalty residuals.
+ * P must be a 3D hex pattern with full coupling.  Validates the face list on the host
+ * (sync), then runs async on the stream.  A degenerate face (zero area) or element
+ * (det J <= 0, flux form) is reported by mf_status_poll.
+ * Errors: MF_ERR_ARG (including a face list out of range or a form/field-count mismatch),
+ * MF_ERR_UNSUPPORTED (not a 3D hex pattern), MF_ERR_HIP.
+ */
+mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform* form, const double* coords,
+                               int64_t n_faces, const int32_t* face_elem, const uint8_t* face_id,
+                               const void* state, const void* target, mf_precision prec, void* K,
+                               void* d, void* stream);
+
+/* ------------------------------------------------------------------------------------
  * Linear solve of the assembled system (Sec. 2.2 D-4 leaves the solver open): FP64
  * preconditioned conjugate gradients for symmetric positive definite K.
  * ------------------------------------------------------------------------------------ */

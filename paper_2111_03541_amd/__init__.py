@@ -80,6 +80,12 @@ PRECOND_NONE, PRECOND_JACOBI, PRECOND_NN = 0, 1, 2
 
 NEWTON_MAX_HISTORY = 64
 
+BFORM_PENALTY, BFORM_CONVECTION, BFORM_RADIATION, BFORM_FLUX, BFORM_TRACTION = range(5)
+
+
+class _BForm(C.Structure):
+    _fields_ = [("kind", C.c_int), ("coef", C.c_double), ("value", C.c_double * 9)]
+
 
 class _NewtonOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int32), ("lin_tol", C.c_double),
@@ -104,7 +110,7 @@ EXPORTS = [
     "mf_assemble_ex", "mf_status_poll", "mf_last_error", "mf_version", "mf_pcg",
     "mf_batch_create", "mf_batch_tune", "mf_batch_run", "mf_batch_info", "mf_batch_destroy",
     "mf_nn_create", "mf_nn_params", "mf_nn_set_system", "mf_nn_apply", "mf_nn_train_step", "mf_nn_destroy", "mf_spmv",
-    "mf_bicgstab", "mf_ns_newton",
+    "mf_bicgstab", "mf_ns_newton", "mf_assemble_boundary",
 ]
 
 
@@ -140,6 +146,7 @@ def load():
     lib.mf_nn_apply.argtypes = [P, P, P, P]
     lib.mf_nn_train_step.argtypes = [P, P, P, C.c_double, C.POINTER(C.c_double), P, P]
     lib.mf_spmv.argtypes = [C.POINTER(_CSR), P, P, P]
+    lib.mf_assemble_boundary.argtypes = [P, C.POINTER(_BForm), P, i64, P, P, P, P, C.c_int, P, P, P]
     lib.mf_bicgstab.argtypes = [C.POINTER(_CSR), P, P, C.POINTER(_PcgOpts), C.POINTER(_PcgResult), P]
     lib.mf_ns_newton.argtypes = [P, C.POINTER(_Form), P, P, P, C.POINTER(_Quad), C.POINTER(_NewtonOpts),
                                  C.POINTER(_NewtonResult), P]
@@ -264,6 +271,31 @@ class Pattern:
         q = _Quad(points_per_axis)
         check(lib.mf_assemble_ex(self._h, C.byref(form.c), _ptr(coords), C.byref(f), C.byref(q), precision,
                                  scatter, _ptr(K), _ptr(d), _stream(stream)))
+        return K, d
+
+    def assemble_boundary(self, kind: int, coords, face_elem, face_id, coef=1.0, value=(), state=None,
+                          target=None, K=None, d=None, precision: int = F64, stream=None):
+        """Add the face integrals of a boundary form into K and d (zeros when not given).
+
+        face_elem int32 / face_id uint8 CUDA tensors; value: up to 9 constants (g, T_env or
+        the load stress sigma^l row-major)."""
+        import torch
+        lib = load()
+        dt = torch.float64 if precision == F64 else torch.float32
+        dev = coords.device
+        if K is None:
+            K = torch.zeros(self.nnz, dtype=dt, device=dev)
+        if d is None:
+            d = torch.zeros(self.n_rows, dtype=dt, device=dev)
+        for name, t in (("state", state), ("target", target)):
+            if t is not None:
+                assert t.is_cuda and t.dtype == dt and t.is_contiguous(), f"{name} must be contiguous {dt} on cuda"
+        assert face_elem.dtype == torch.int32 and face_id.dtype == torch.uint8
+        vals = list(value) + [0.0] * (9 - len(value))
+        f = _BForm(kind, coef, (C.c_double * 9)(*vals))
+        check(lib.mf_assemble_boundary(self._h, C.byref(f), _ptr(coords), int(face_elem.shape[0]), _ptr(face_elem),
+                                       _ptr(face_id), _ptr(state), _ptr(target), precision, _ptr(K), _ptr(d),
+                                       _stream(stream)))
         return K, d
 
     def status(self):

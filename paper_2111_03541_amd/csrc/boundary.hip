@@ -1,0 +1,282 @@
+// Boundary forms: the physics one dimension lower (Sec. 2.2 opening of the algorithm),
+// integrated over element faces and added into an assembled K and d.  The forms are the
+// ones of Sec. 4.1 (convection, radiation, penalty fix with its flux term) and Sec. 4.2
+// (load traction, penalty fix), with the sign reading of the domain forms: R = -d_paper
+// for the thermal and elastic physics, K = dR/dU, exported d = -R(U).
+//
+// One thread per (face f, face node k, field i): the thread gathers the 8 nodes of the
+// face's element, evaluates the 2x2 Gauss rule on the face (xi_axis = -1 or +1) with the
+// element's trilinear map in FP64 (surface measure |t_u x t_v|, outward unit normal, and
+// for the flux term the volume gradients J^-T grad_xi N_b), accumulates row (a, i) of the
+// face tangent and residual, and adds them into K and d with atomics through the
+// element-to-nonzero rank map.  Boundary work is a surface's worth, so the simple
+// per-row scatter is enough.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "element.h"
+#include "mf_internal.h"
+
+namespace mf {
+namespace {
+
+constexpr int kThreads = 256;
+
+struct BParams {
+    mf_bform form;
+    int64_t n_el, n_nodes, n_faces;
+    const int32_t* conn;
+    const double* coords;
+    const int32_t* row_ptr;
+    const int32_t* nbr_ptr;
+    const uint8_t* rank;
+    const int32_t* face_elem;
+    const uint8_t* face_id;
+    const void* state;   // [nf][n_nodes] or null (zero)
+    const void* target;  // [nf][n_nodes] or null (the constant form->value)
+    int field_major;
+    void* K;
+    void* d;
+    unsigned long long* status;
+};
+
+__device__ __forceinline__ double lin1(int s, double xi) { return 0.5 * (1.0 + (s ? xi : -xi)); }
+
+template <int NF, typename T>
+__global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p.n_faces * 4 * NF) return;
+    const int64_t f = t % p.n_faces;
+    const int ki = (int)(t / p.n_faces);
+    const int kf = ki / NF, i = ki % NF;
+    const int64_t e = p.face_elem[f];
+    const int fid = p.face_id[f];
+    const int axis = fid >> 1, side = fid & 1;
+    const int u = (axis + 1) % 3, v = (axis + 2) % 3;
+    // element-local node of face node k: bit axis = side, bits u, v from k
+    auto fnode = [&](int k) { return (side << axis) | ((k & 1) << u) | ((k >> 1) << v); };
+    const int a = fnode(kf);
+
+    int32_t node[8];
+    double x[8][3];
+    double U[8][NF], G[8][NF];
+    const T* st = (const T*)p.state;
+    const T* tg = (const T*)p.target;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        node[b] = p.conn[(int64_t)b * p.n_el + e];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) x[b][m] = p.coords[(int64_t)m * p.n_nodes + node[b]];
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            U[b][j] = st ? (double)st[(int64_t)j * p.n_nodes + node[b]] : 0.0;
+            G[b][j] = tg ? (double)tg[(int64_t)j * p.n_nodes + node[b]] : p.form.value[j];
+        }
+    }
+    const mf_bform_kind kind = p.form.kind;
+    const double c = p.form.coef;
+    double krow[8][NF];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) krow[b][j] = 0.0;
+    double rrow = 0.0;
+
+    for (int q = 0; q < 4; ++q) {
+        double xi[3];
+        xi[axis] = side ? 1.0 : -1.0;
+        xi[u] = (q & 1) ? kGaussPt : -kGaussPt;
+        xi[v] = (q >> 1) ? kGaussPt : -kGaussPt;
+        double N[8], dN[8][3];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+            const double Fx = lin1(bx, xi[0]), Fy = lin1(by, xi[1]), Fz = lin1(bz, xi[2]);
+            N[b] = Fx * Fy * Fz;
+            dN[b][0] = (bx ? 0.5 : -0.5) * Fy * Fz;
+            dN[b][1] = (by ? 0.5 : -0.5) * Fx * Fz;
+            dN[b][2] = (bz ? 0.5 : -0.5) * Fx * Fy;
+        }
+        double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // J[m][n] = dx_m / dxi_n
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+#pragma unroll
+                for (int n = 0; n < 3; ++n) J[m][n] = fma(x[b][m], dN[b][n], J[m][n]);
+        const double tu[3] = {J[0][u], J[1][u], J[2][u]}, tv[3] = {J[0][v], J[1][v], J[2][v]};
+        const double sg = side ? 1.0 : -1.0;
+        double nr[3] = {sg * (tu[1] * tv[2] - tu[2] * tv[1]), sg * (tu[2] * tv[0] - tu[0] * tv[2]),
+                        sg * (tu[0] * tv[1] - tu[1] * tv[0])};
+        const double dS = sqrt(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
+        if (!(dS > 0.0)) {
+            atomicMin(p.status, (unsigned long long)e);
+            return;
+        }
+        const double nv[3] = {nr[0] / dS, nr[1] / dS, nr[2] / dS};
+        const double w = dS;  // unit Gauss weights on [-1, 1]^2
+        const double Na = N[a];
+        double uq[NF], gq[NF];
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            uq[j] = 0.0;
+            gq[j] = 0.0;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                uq[j] = fma(N[b], U[b][j], uq[j]);
+                gq[j] = fma(N[b], G[b][j], gq[j]);
+            }
+        }
+        if (kind == MF_BFORM_PENALTY || kind == MF_BFORM_CONVECTION) {
+            // R = int c N_a (u_i - g_i)
+#pragma unroll
+            for (int b = 0; b < 8; ++b) krow[b][i] += c * w * Na * N[b];
+            rrow += c * w * Na * (uq[i] - gq[i]);
+        } else if (kind == MF_BFORM_RADIATION) {
+            // R = int c N_a (T^4 - T_env^4), c = e_m sigma
+            const double T1 = uq[0], Te = gq[0];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) krow[b][0] += c * w * Na * 4.0 * T1 * T1 * T1 * N[b];
+            rrow += c * w * Na * (T1 * T1 * T1 * T1 - Te * Te * Te * Te);
+        } else if (kind == MF_BFORM_TRACTION) {
+            // R = -int N_a sigma^l_ij n_j
+            const double* S = p.form.value;
+            const double ti = S[3 * i] * nv[0] + S[3 * i + 1] * nv[1] + S[3 * i + 2] * nv[2];
+            rrow -= w * Na * ti;
+        } else {  // MF_BFORM_FLUX: R = -int c N_a n . grad T
+            const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+            const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+            const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+            const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+            if (!(det > 0.0)) {
+                atomicMin(p.status, (unsigned long long)e);
+                return;
+            }
+            double Ji[3][3];  // (J^-1)[n][m] = dxi_n / dx_m
+            const double r = 1.0 / det;
+            Ji[0][0] = c00 * r;
+            Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+            Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+            Ji[1][0] = c01 * r;
+            Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+            Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+            Ji[2][0] = c02 * r;
+            Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+            Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+            double ngT = 0.0;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                double ng = 0.0;  // n . grad N_b,  grad N_b = J^-T grad_xi N_b
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    ng += nv[m] * (Ji[0][m] * dN[b][0] + Ji[1][m] * dN[b][1] + Ji[2][m] * dN[b][2]);
+                krow[b][0] -= c * w * Na * ng;
+                ngT = fma(ng, U[b][0], ngT);
+            }
+            rrow -= c * w * Na * ngT;
+        }
+    }
+
+    const int64_t va = node[a];
+    const int64_t row = p.field_major ? (int64_t)i * p.n_nodes + va : (int64_t)NF * va + i;
+    const int64_t rs = p.row_ptr[row];
+    const int64_t deg = p.nbr_ptr[va + 1] - p.nbr_ptr[va];
+    T* K = (T*)p.K;
+    T* d = (T*)p.d;
+    for (int b = 0; b < 8; ++b) {
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < NF; ++j) any = any || krow[b][j] != 0.0;
+        if (!any) continue;
+        const int64_t rk = p.rank[(int64_t)(a * 8 + b) * p.n_el + e];
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            if (krow[b][j] == 0.0) continue;
+            const int64_t pos = p.field_major ? rs + j * deg + rk : rs + rk * NF + j;
+            unsafeAtomicAdd(K + pos, (T)krow[b][j]);
+        }
+    }
+    if (rrow != 0.0) unsafeAtomicAdd(d + row, (T)(-rrow));
+}
+
+template <int NF, typename T>
+mf_status launch_boundary(const BParams& p, hipStream_t s)
+{
+    const int64_t n = p.n_faces * 4 * NF;
+    if (n == 0) return MF_OK;
+    k_boundary<NF, T><<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(p);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+}  // namespace
+}  // namespace mf
+
+using namespace mf;
+
+extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform* form, const double* coords,
+                                          int64_t n_faces, const int32_t* face_elem, const uint8_t* face_id,
+                                          const void* state, const void* target, mf_precision prec, void* K,
+                                          void* d, void* stream)
+{
+    if (!P || !form) return set_error(MF_ERR_ARG, "pattern or form is NULL");
+    if (P->dim != 3 || P->nen != 8) return set_error(MF_ERR_UNSUPPORTED, "boundary forms need a 3D hex pattern");
+    if (prec != MF_F64 && prec != MF_F32) return set_error(MF_ERR_ARG, "unknown precision %d", (int)prec);
+    if (n_faces < 0 || n_faces > ((int64_t)1 << 28)) return set_error(MF_ERR_ARG, "n_faces out of range");
+    if (n_faces > 0 && (!face_elem || !face_id || !coords || !K || !d))
+        return set_error(MF_ERR_ARG, "NULL faces, coords, K or d");
+    if (!P->full_coupling) return set_error(MF_ERR_ARG, "boundary forms need a fully coupled pattern");
+    const int nf = P->nf;
+    switch (form->kind) {
+        case MF_BFORM_PENALTY:
+            if (nf != 1 && nf != 3) return set_error(MF_ERR_ARG, "penalty needs 1 or 3 fields, pattern has %d", nf);
+            break;
+        case MF_BFORM_CONVECTION:
+        case MF_BFORM_RADIATION:
+        case MF_BFORM_FLUX:
+            if (nf != 1) return set_error(MF_ERR_ARG, "this boundary form is scalar; pattern has %d fields", nf);
+            break;
+        case MF_BFORM_TRACTION:
+            if (nf != 3) return set_error(MF_ERR_ARG, "traction needs 3 fields, pattern has %d", nf);
+            if (target) return set_error(MF_ERR_ARG, "traction takes its load from form->value, not a target");
+            break;
+        default: return set_error(MF_ERR_ARG, "unknown boundary form %d", (int)form->kind);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (n_faces > 0) {
+        // the kernel indexes elements and faces directly: check the list on the host first
+        std::vector<int32_t> fe((size_t)n_faces);
+        std::vector<uint8_t> fi((size_t)n_faces);
+        MF_HIP(hipMemcpyAsync(fe.data(), face_elem, sizeof(int32_t) * n_faces, hipMemcpyDeviceToHost, s));
+        MF_HIP(hipMemcpyAsync(fi.data(), face_id, n_faces, hipMemcpyDeviceToHost, s));
+        MF_HIP(hipStreamSynchronize(s));
+        for (int64_t k = 0; k < n_faces; ++k)
+            if (fe[k] < 0 || fe[k] >= P->n_elems || fi[k] > 5)
+                return set_error(MF_ERR_ARG, "face %lld: element %d / local face %d out of range", (long long)k,
+                                 (int)fe[k], (int)fi[k]);
+    }
+    BParams p{};
+    p.form = *form;
+    p.n_el = P->n_elems;
+    p.n_nodes = P->n_nodes;
+    p.n_faces = n_faces;
+    p.conn = P->conn;
+    p.coords = coords;
+    p.row_ptr = P->row_ptr;
+    p.nbr_ptr = P->nbr_ptr;
+    p.rank = P->rank;
+    p.face_elem = face_elem;
+    p.face_id = face_id;
+    p.state = state;
+    p.target = target;
+    p.field_major = P->numbering == MF_FIELD_MAJOR;
+    p.K = K;
+    p.d = d;
+    p.status = P->status;
+    const_cast<mf_pattern_s*>(P)->last_stream = s;
+    if (prec == MF_F64) return nf == 1 ? launch_boundary<1, double>(p, s) : launch_boundary<3, double>(p, s);
+    return nf == 1 ? launch_boundary<1, float>(p, s) : launch_boundary<3, float>(p, s);
+}

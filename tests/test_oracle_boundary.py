@@ -1,0 +1,112 @@
+"""Oracle pins for the boundary forms (Sec. 2.2: the physics one dimension lower; forms of
+Sec. 4.1 and Sec. 4.2), computed by oracle/boundary.py."""
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.boundary as OB
+import workloads as W
+
+
+def box(n, jitter=0.0, lengths=None, seed=1):
+    mesh = W.structured_mesh(n, jitter=jitter, seed=seed, lengths=lengths)
+    return mesh
+
+
+def test_face_mass_sums_to_area_and_matches_flat_face():
+    mesh = box((3, 2, 4), jitter=0.2, lengths=[2.0, 3.0, 5.0])
+    pat = O.Pattern(mesh, 1)
+    fe, fi = W.box_faces((3, 2, 4))
+    K, d = OB.assemble_boundary(pat, OB.PENALTY, 1.0, [0.0], fe, fi)
+    area = 2 * (2 * 3 + 3 * 5 + 2 * 5)
+    assert abs(K.sum() - area) < 1e-12 * area
+    assert np.abs(d).max() == 0.0
+    # one face of the top side: (h_x h_y / 36) [4, 2, 2, 1] between its corners
+    pat3 = O.Pattern(mesh, 3)
+    fe, fi = W.box_faces((3, 2, 4), sides=[5])
+    K1, _ = OB.assemble_boundary(pat, OB.PENALTY, 1.0, [0.0], fe[:1], fi[:1])
+    hx, hy = 2.0 / 3, 3.0 / 2
+    nodes = mesh.conn[4:, fe[0]]  # top face nodes of the element
+    B = K1.toarray()[np.ix_(nodes, nodes)]
+    ref = hx * hy / 36 * np.array([[4, 2, 2, 1], [2, 4, 1, 2], [2, 1, 4, 2], [1, 2, 2, 4]])
+    assert np.abs(B - ref).max() < 1e-15
+    # vector form: the same block on each field, no coupling between fields
+    K3, _ = OB.assemble_boundary(pat3, OB.PENALTY, 2.0, [0, 0, 0], *W.box_faces((3, 2, 4)))
+    assert abs(K3.sum() - 3 * 2.0 * area) < 1e-12 * area
+    rows, cols = K3.nonzero()
+    assert np.all(rows % 3 == cols % 3)
+
+
+def test_traction_integrates_to_load_times_area():
+    n = (3, 3, 2)
+    mesh = box(n, jitter=0.15, lengths=[1.0, 2.0, 0.5])
+    pat = O.Pattern(mesh, 3)
+    S = np.array([[0.3, -0.2, 0.7], [0.1, 0.5, -0.4], [0.6, 0.2, -1.1]])
+    # closed surface: sum of n dS vanishes, so a uniform stress load sums to zero
+    _, d = OB.assemble_boundary(pat, OB.TRACTION, 1.0, S.reshape(-1), *W.box_faces(n))
+    assert np.abs(d.reshape(-1, 3).sum(axis=0)).max() < 1e-14
+    # the top face alone (n = +z, area 1 x 2): the load is sigma^l e_z times the area
+    _, d = OB.assemble_boundary(pat, OB.TRACTION, 1.0, S.reshape(-1), *W.box_faces(n, sides=[5]))
+    assert np.abs(d.reshape(-1, 3).sum(axis=0) - S[:, 2] * 2.0).max() < 1e-14
+    # the left face (n = -x, area 2 x 0.5)
+    _, d = OB.assemble_boundary(pat, OB.TRACTION, 1.0, S.reshape(-1), *W.box_faces(n, sides=[0]))
+    assert np.abs(d.reshape(-1, 3).sum(axis=0) + S[:, 0] * 1.0).max() < 1e-14
+
+
+def test_convection_and_penalty_target_loads():
+    n = (2, 3, 2)
+    mesh = box(n, jitter=0.2)
+    pat = O.Pattern(mesh, 1)
+    _, d = OB.assemble_boundary(pat, OB.CONVECTION, 3.0, [2.5], *W.box_faces(n))
+    assert abs(d.sum() - 3.0 * 2.5 * 6.0) < 1e-12
+    # penalty towards g = z: the top face (z = 1) loads beta * area, the bottom nothing
+    g = mesh.coords[2][None, :].copy()
+    _, d = OB.assemble_boundary(pat, OB.PENALTY, 4.0, [0.0], *W.box_faces(n, sides=[5]), target=g)
+    assert abs(d.sum() - 4.0) < 1e-12
+    _, d = OB.assemble_boundary(pat, OB.PENALTY, 4.0, [0.0], *W.box_faces(n, sides=[4]), target=g)
+    assert np.abs(d).max() < 1e-15
+
+
+@pytest.mark.parametrize("numbering", [O.NODE_MAJOR, O.FIELD_MAJOR])
+def test_flux_term_makes_linear_fields_exact(numbering):
+    """Divergence theorem: int grad N_a . grad T = int_boundary N_a n . grad T for linear T,
+    exactly under the Gauss rules on trilinear maps; so (domain + flux) T_lin = 0, and with
+    the penalty towards T_lin the linear field solves the fix problem for any penalty."""
+    n = (3, 2, 3)
+    mesh = box(n, jitter=0.2, lengths=[1.5, 1.0, 2.0], seed=3)
+    pat = O.Pattern(mesh, 1, numbering=numbering)
+    k = 1.7
+    Kd, _ = O.assemble(pat, O.POISSON, {"coef": k})
+    Kd = pat.to_scipy(Kd)
+    Kf, _ = OB.assemble_boundary(pat, OB.FLUX, k, [0.0], *W.box_faces(n))
+    T = 0.3 * mesh.coords[0] - 1.2 * mesh.coords[1] + 0.7 * mesh.coords[2] + 0.4
+    assert np.abs((Kd + Kf) @ T).max() < 1e-13 * np.abs(Kd @ T).max()
+    # the flux residual at a state is linear: d = -K T
+    _, dflux = OB.assemble_boundary(pat, OB.FLUX, k, [0.0], *W.box_faces(n), state=T[None, :])
+    assert np.abs(dflux + Kf @ T).max() < 1e-14
+    # fix problem: domain + flux + penalty towards T: T is the exact discrete solution
+    Kp, dp = OB.assemble_boundary(pat, OB.PENALTY, 1e3, [0.0], *W.box_faces(n), target=T[None, :])
+    assert np.abs((Kd + Kf + Kp) @ T - dp).max() < 1e-11 * np.abs(dp).max()
+
+
+def test_radiation_tangent_by_central_differences():
+    n = (2, 2, 2)
+    mesh = box(n, jitter=0.2, seed=5)
+    pat = O.Pattern(mesh, 1)
+    fe, fi = W.box_faces(n)
+    rng = np.random.default_rng(2)
+    T = 1.0 + rng.random(mesh.n_nodes)
+    c, Te = 0.8, 1.3
+    K, d = OB.assemble_boundary(pat, OB.RADIATION, c, [Te], fe, fi, state=T[None, :])
+    K = K.toarray()
+    eps = 1e-5
+    for j in rng.choice(mesh.n_nodes, 6, replace=False):
+        e = np.zeros(mesh.n_nodes)
+        e[j] = eps
+        _, dp = OB.assemble_boundary(pat, OB.RADIATION, c, [Te], fe, fi, state=(T + e)[None, :])
+        _, dm = OB.assemble_boundary(pat, OB.RADIATION, c, [Te], fe, fi, state=(T - e)[None, :])
+        fd = -(dp - dm) / (2 * eps)  # d = -R
+        assert np.abs(fd - K[:, j]).max() < 1e-8 * np.abs(K).max()
+    # at T = T_env the residual vanishes
+    _, d0 = OB.assemble_boundary(pat, OB.RADIATION, c, [Te], fe, fi, state=np.full((1, mesh.n_nodes), Te))
+    assert np.abs(d0).max() < 1e-14

@@ -239,6 +239,26 @@ def dof_mask(node_mask: np.ndarray, n_fields: int, field_major: bool,
     return m.T.reshape(-1).copy()
 
 
+def box_faces(n, sides=None):
+    """Element faces on the sides of a structured 3D box mesh of n = (nx, ny, nz) elements.
+
+    sides: local face ids 2 * axis + side (side 1: the face at the upper end of the axis);
+    default all six.  Returns (element ids int32, local face ids uint8), side by side."""
+    nx, ny, nz = (int(v) for v in n)
+    sides = range(6) if sides is None else sides
+    ex, ey, ez = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    eid = (ex + nx * (ey + ny * ez)).astype(np.int64)
+    idx = (ex, ey, ez)
+    elems, fids = [], []
+    for f in sides:
+        axis, side = f >> 1, f & 1
+        sel = idx[axis] == ((n[axis] - 1) if side else 0)
+        e = np.sort(eid[sel])
+        elems.append(e)
+        fids.append(np.full(e.shape, f))
+    return np.concatenate(elems).astype(np.int32), np.concatenate(fids).astype(np.uint8)
+
+
 def flow_boundary(mesh: Mesh, kind: str, field_major: bool = False, lid_speed: float = 1.0):
     """Initial state and Dirichlet rows of an enclosed 3D flow on a structured box mesh.
 
