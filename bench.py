@@ -285,6 +285,39 @@ def bench_newton(dev, n=32, cpu=True, n_cpu=16):
     return out
 
 
+def bench_boundary(dev, mesh, pat, coords, K, d, cpu=True, steps=10, warmup=3):
+    """Boundary forms on the 64^3 elasticity mesh: penalty fix (3 fields) on all six sides
+    (24,576 faces), added into the assembled K and d.  The oracle's face loops are timed on
+    the faces of one side of an 8^3 mesh."""
+    import torch
+    import workloads as W
+    import paper_2111_03541_amd as mf
+    fe_h, fi_h = W.box_faces(mesh.shape)
+    fe, fi = torch.from_numpy(fe_h).to(dev), torch.from_numpy(fi_h).to(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        pat.assemble_boundary(mf.BFORM_PENALTY, coords, fe, fi, coef=1e4, value=[0.0, 0.0, 0.0], K=K, d=d)
+
+    _, per = time_launches(step, steps, warmup, stream)
+    avg = float(np.mean(per))
+    n_faces = int(fe_h.shape[0])
+    log(f"[bench] boundary penalty, {n_faces} faces: {avg * 1e6:.1f} us ({n_faces / avg / 1e6:.1f} M faces/s)")
+    out = {"n_faces": n_faces, "avg_us": avg * 1e6, "faces_per_s": n_faces / avg}
+    if cpu:
+        import oracle as O
+        import oracle.boundary as OB
+        m = W.structured_mesh((8, 8, 8))
+        opat = O.Pattern(m, 3)
+        ofe, ofi = W.box_faces((8, 8, 8), sides=[5])
+        t0 = time.perf_counter()
+        OB.assemble_boundary(opat, OB.PENALTY, 1e4, [0.0, 0.0, 0.0], ofe, ofi)
+        t = time.perf_counter() - t0
+        out["cpu_oracle"] = {"faces_per_s": ofe.shape[0] / t, "sample": f"{ofe.shape[0]} faces (top side of 8^3)",
+                             "kind": "oracle (numpy face loops)", "cores": 1}
+    return out
+
+
 def cpu_baseline(mesh, E, b):
     import oracle as O
     t0 = time.perf_counter()
@@ -400,6 +433,7 @@ def main():
         "elasticity_64_f32": {"avg_launch_us": avg32 * 1e6, "elems_per_s": mesh.n_elems / avg32,
                               "alg_bytes": B32, "hbm_frac": B32 / avg32 / HBM_PEAK},
     }
+    record["secondary"]["boundary_64_f64"] = bench_boundary(dev, mesh, pat, coords, K, d, cpu=not args.no_cpu)
     record["secondary"]["poisson_96_pcg_time_to_1e-8"] = bench_pcg(dev)
     record["secondary"]["batched_256_f32"] = bench_batch(dev)
     record["secondary"]["ns_48_f32"] = bench_ns(dev)

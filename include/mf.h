@@ -154,8 +154,10 @@ mf_status mf_assemble_ex(const mf_pattern_t* pat, const mf_form* form, const dou
                          const mf_fields* fields, const mf_quadrature* quad, mf_precision precision,
                          mf_scatter scatter, void* K_values, void* d, void* stream);
 
-/* (sync) Reads the device status word of the last assembly on this pattern: MF_OK, or
-   MF_ERR_BAD_JACOBIAN with the smallest offending element id in *first_bad_elem. */
+/* (sync) Reads the device status words of the assemblies on this pattern since the last
+   mf_assemble (which clears them): MF_OK; MF_ERR_ARG when mf_assemble_boundary skipped a
+   face out of range (the message names the first); else MF_ERR_BAD_JACOBIAN with the
+   smallest offending element id in *first_bad_elem. */
 mf_status mf_status_poll(const mf_pattern_t* pat, int64_t* first_bad_elem);
 
 /* Thread-local message for the last failing call ("" if none). */
@@ -236,11 +238,12 @@ typedef struct {
  * [n_faces] element ids and face_id [n_faces] local faces 2 * axis + side (side 1: the
  * face at xi_axis = +1), device arrays.  state [nf][n_nodes] (device, precision prec, or
  * NULL = 0) is the linearisation point of the radiation, flux and penalty residuals.
- * P must be a 3D hex pattern with full coupling.  Validates the face list on the host
- * (sync), then runs async on the stream.  A degenerate face (zero area) or element
- * (det J <= 0, flux form) is reported by mf_status_poll.
- * Errors: MF_ERR_ARG (including a face list out of range or a form/field-count mismatch),
- * MF_ERR_UNSUPPORTED (not a 3D hex pattern), MF_ERR_HIP.
+ * P must be a 3D hex pattern with full coupling.  Async on the stream.  Reported by
+ * mf_status_poll (until the next mf_assemble clears the status): a face whose element id
+ * or local face is out of range (skipped; MF_ERR_ARG with the first such face), and a
+ * degenerate face (zero area) or element (det J <= 0, flux form; MF_ERR_BAD_JACOBIAN).
+ * Errors: MF_ERR_ARG (a form/field-count mismatch or bad arguments), MF_ERR_UNSUPPORTED
+ * (not a 3D hex pattern), MF_ERR_HIP.
  */
 mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform* form, const double* coords,
                                int64_t n_faces, const int32_t* face_elem, const uint8_t* face_id,

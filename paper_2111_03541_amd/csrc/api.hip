@@ -217,11 +217,14 @@ mf_status mf_assemble(const mf_pattern_t* P, const mf_form* form, const double* 
 mf_status mf_status_poll(const mf_pattern_t* P, int64_t* first_bad_elem)
 {
     if (!P) return set_error(MF_ERR_ARG, "pattern is NULL");
-    unsigned long long v = 0;
+    unsigned long long v[2] = {0, 0};
     if (P->last_stream) MF_HIP(hipStreamSynchronize(P->last_stream));
-    MF_HIP(hipMemcpy(&v, P->status, sizeof(v), hipMemcpyDeviceToHost));
-    if (first_bad_elem) *first_bad_elem = v == ~0ull ? -1 : (int64_t)v;
-    if (v != ~0ull) return set_error(MF_ERR_BAD_JACOBIAN, "det J <= 0 in element %lld", (long long)v);
+    MF_HIP(hipMemcpy(v, P->status, sizeof(v), hipMemcpyDeviceToHost));
+    if (first_bad_elem) *first_bad_elem = v[0] == ~0ull ? -1 : (int64_t)v[0];
+    if (v[1] != ~0ull)
+        return set_error(MF_ERR_ARG, "boundary face %lld: element id or local face out of range (skipped)",
+                         (long long)v[1]);
+    if (v[0] != ~0ull) return set_error(MF_ERR_BAD_JACOBIAN, "det J <= 0 in element %lld", (long long)v[0]);
     return MF_OK;
 }
 

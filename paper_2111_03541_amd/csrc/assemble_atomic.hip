@@ -124,7 +124,11 @@ __global__ void k_dirichlet(const int32_t* __restrict__ row_ptr, const int32_t* 
     }
 }
 
-__global__ void k_reset_status(unsigned long long* s) { *s = ~0ull; }
+__global__ void k_reset_status(unsigned long long* s)
+{
+    s[0] = ~0ull;
+    s[1] = ~0ull;
+}
 
 template <int FORM, int DIM, typename T>
 mf_status launch_atomic(const AssembleArgs& A)

@@ -755,7 +755,10 @@ __global__ void k_batch_reset(int* counter, unsigned long long* const* status, i
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *counter = 0;
-    if (i < n_status) *status[i] = ~0ull;
+    if (i < n_status) {
+        status[i][0] = ~0ull;
+        status[i][1] = ~0ull;
+    }
 }
 
 template <typename T>

@@ -10,11 +10,11 @@
 // for the flux term the volume gradients J^-T grad_xi N_b), accumulates row (a, i) of the
 // face tangent and residual, and adds them into K and d with atomics through the
 // element-to-nonzero rank map.  Boundary work is a surface's worth, so the simple
-// per-row scatter is enough.
+// per-row scatter is enough.  A face whose element id or local face is out of range is
+// skipped and its index recorded in the pattern's second status word.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
-#include <vector>
 
 #include "element.h"
 #include "mf_internal.h"
@@ -54,6 +54,10 @@ __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
     const int kf = ki / NF, i = ki % NF;
     const int64_t e = p.face_elem[f];
     const int fid = p.face_id[f];
+    if (e < 0 || e >= p.n_el || fid > 5) {  // skipped, and reported by mf_status_poll
+        if (ki == 0) atomicMin(p.status + 1, (unsigned long long)f);
+        return;
+    }
     const int axis = fid >> 1, side = fid & 1;
     const int u = (axis + 1) % 3, v = (axis + 2) % 3;
     // element-local node of face node k: bit axis = side, bits u, v from k
@@ -246,18 +250,6 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
         default: return set_error(MF_ERR_ARG, "unknown boundary form %d", (int)form->kind);
     }
     hipStream_t s = (hipStream_t)stream;
-    if (n_faces > 0) {
-        // the kernel indexes elements and faces directly: check the list on the host first
-        std::vector<int32_t> fe((size_t)n_faces);
-        std::vector<uint8_t> fi((size_t)n_faces);
-        MF_HIP(hipMemcpyAsync(fe.data(), face_elem, sizeof(int32_t) * n_faces, hipMemcpyDeviceToHost, s));
-        MF_HIP(hipMemcpyAsync(fi.data(), face_id, n_faces, hipMemcpyDeviceToHost, s));
-        MF_HIP(hipStreamSynchronize(s));
-        for (int64_t k = 0; k < n_faces; ++k)
-            if (fe[k] < 0 || fe[k] >= P->n_elems || fi[k] > 5)
-                return set_error(MF_ERR_ARG, "face %lld: element %d / local face %d out of range", (long long)k,
-                                 (int)fe[k], (int)fi[k]);
-    }
     BParams p{};
     p.form = *form;
     p.n_el = P->n_elems;

@@ -371,7 +371,7 @@ mf_status build_pattern(mf_pattern_s* P, const int32_t* conn_in, hipStream_t s)
     MF_HIP(hipMalloc(&P->row_ptr, sizeof(int32_t) * (size_t)(P->n_rows + 1)));
     MF_HIP(hipMalloc(&P->col_idx, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1)));
     MF_HIP(hipMalloc(&P->rank, (size_t)(nen * nen * (n_el > 0 ? n_el : 1))));
-    MF_HIP(hipMalloc(&P->status, sizeof(unsigned long long)));
+    MF_HIP(hipMalloc(&P->status, 2 * sizeof(unsigned long long)));  // [0] bad element, [1] bad face
 
     k_i64_to_i32<<<blocks_for(n_nodes + 1, kThreads), kThreads, 0, s>>>(nbr_ptr64, n_nodes + 1, P->nbr_ptr);
     if (n_nodes > 0)

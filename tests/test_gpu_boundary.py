@@ -97,11 +97,18 @@ def test_boundary_argument_errors(mf):
     pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 1)
     coords = torch.from_numpy(mesh.coords).to(dev)
     fe = torch.tensor([0, 7], dtype=torch.int32, device=dev)
-    with pytest.raises(mf.MFError):  # local face 6
-        pat.assemble_boundary(mf.BFORM_PENALTY, coords, fe, torch.tensor([0, 6], dtype=torch.uint8, device=dev))
-    with pytest.raises(mf.MFError):  # element 8 of 8
-        pat.assemble_boundary(mf.BFORM_PENALTY, coords, torch.tensor([0, 8], dtype=torch.int32, device=dev),
-                              torch.tensor([0, 1], dtype=torch.uint8, device=dev))
+    # faces out of range are skipped on the device and reported by the status poll
+    pat.assemble(mf.Form(mf.POISSON), coords)  # clears the status
+    K, d = pat.assemble_boundary(mf.BFORM_PENALTY, coords, fe, torch.tensor([0, 6], dtype=torch.uint8, device=dev))
+    assert pat.status()[0] == mf.ERR_ARG  # local face 6
+    Kr, dr = pat.assemble_boundary(mf.BFORM_PENALTY, coords, fe[:1], torch.tensor([0], dtype=torch.uint8, device=dev))
+    assert torch.equal(K, Kr) and torch.equal(d, dr)  # only the valid face was added
+    pat.assemble(mf.Form(mf.POISSON), coords)
+    assert pat.status()[0] == mf.OK
+    pat.assemble_boundary(mf.BFORM_PENALTY, coords, torch.tensor([0, 8], dtype=torch.int32, device=dev),
+                          torch.tensor([0, 1], dtype=torch.uint8, device=dev))
+    assert pat.status()[0] == mf.ERR_ARG  # element 8 of 8
+    pat.assemble(mf.Form(mf.POISSON), coords)
     with pytest.raises(mf.MFError):  # traction needs 3 fields
         pat.assemble_boundary(mf.BFORM_TRACTION, coords, fe, torch.tensor([0, 1], dtype=torch.uint8, device=dev))
     # an empty face list adds nothing
