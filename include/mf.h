@@ -204,6 +204,48 @@ mf_status mf_batch_info(const mf_batch_t* batch, int64_t* n_items, int32_t* n_wo
 void mf_batch_destroy(mf_batch_t* batch);
 
 /* ------------------------------------------------------------------------------------
+ * Transient thermal conduction (the domain form of Sec. 4.1 with its capacity term,
+ * C dT/dt - div(k grad T) = s) stepped by the generalized-alpha scheme of Sec. 2.1 (its
+ * dynamic extension of the Newton-Raphson update).  With u = dT/dt, each step links the
+ * increments by dT = dt (u0 + b1 du), evaluates the residual at T~ = T0 + c1 dT and
+ * u~ = u0 + c2 du, and solves the linear effective system
+ *   (c1 K + c2 / (b1 dt) M) dT = F - K T0 - (1 - c2 / b1) M u0,
+ * then T1 = T0 + dT, u1 = u0 + (dT / dt - u0) / b1.  The parameters follow from the
+ * spectral radius at infinity rho: c2 = (3 - rho) / (2 (1 + rho)), c1 = 1 / (1 + rho),
+ * b1 = 1/2 + c2 - c1 (second order, unconditionally stable).
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+    double dt;              /* time step                                                    */
+    double rho_inf;         /* spectral radius at infinity, in [0, 1]                        */
+    int32_t n_steps;        /* steps to take (0: only the optional initial rate)             */
+    int32_t init_rate;      /* 1: first set Tdot from M Tdot = F - K T (0 on fixed rows)      */
+    double lin_tol;         /* relative true-residual tolerance of each PCG solve             */
+    int32_t lin_maxit;
+} mf_transient_opts;
+
+typedef struct {
+    int32_t steps;          /* steps taken                                                  */
+    int32_t lin_iterations; /* PCG iterations over all solves                               */
+    double max_lin_relres;  /* largest true relative residual of the solves                 */
+} mf_transient_result;
+
+/*
+ * mf_heat_transient - P is a scalar pattern (1 field, 2D or 3D).  K_ab = int k_e grad N_a .
+ * grad N_b with k_e = conductivity * elem_k[e] (elem_k [n_elems] device FP64, or NULL = 1),
+ * M_ab = int capacity N_a N_b, F_a = int N_a s with s the nodal source [n_nodes] (device
+ * FP64, or NULL = 0).  T and Tdot [n_nodes] (device FP64) hold the state at the start and
+ * are overwritten with the state after n_steps.  dirichlet [n_rows] (device, or NULL)
+ * keeps T fixed on marked rows (their Tdot should be 0).  M and K are assembled once per
+ * call; workspace is allocated and freed inside.  (sync)
+ * Errors: MF_ERR_ARG, those of mf_assemble and mf_pcg (a solve that misses lin_tol stops
+ * the run with MF_ERR_NOT_CONVERGED; res->steps counts the finished steps), MF_ERR_OOM.
+ */
+mf_status mf_heat_transient(const mf_pattern_t* P, double capacity, double conductivity, const double* coords,
+                            const double* elem_k, const double* source, const uint8_t* dirichlet,
+                            const mf_quadrature* quad, const mf_transient_opts* opts, double* T, double* Tdot,
+                            mf_transient_result* res, void* stream);
+
+/* ------------------------------------------------------------------------------------
  * Boundary forms: the physics one dimension lower (Sec. 2.2, opening of the algorithm),
  * integrated over element faces with the 2x2 Gauss rule of the face and added into an
  * assembled K and d.  Forms of Sec. 4.1 (thermal) and Sec. 4.2 (elasticity), with the

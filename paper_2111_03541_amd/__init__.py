@@ -83,6 +83,15 @@ NEWTON_MAX_HISTORY = 64
 BFORM_PENALTY, BFORM_CONVECTION, BFORM_RADIATION, BFORM_FLUX, BFORM_TRACTION = range(5)
 
 
+class _TransientOpts(C.Structure):
+    _fields_ = [("dt", C.c_double), ("rho_inf", C.c_double), ("n_steps", C.c_int32), ("init_rate", C.c_int32),
+                ("lin_tol", C.c_double), ("lin_maxit", C.c_int32)]
+
+
+class _TransientResult(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("lin_iterations", C.c_int32), ("max_lin_relres", C.c_double)]
+
+
 class _BForm(C.Structure):
     _fields_ = [("kind", C.c_int), ("coef", C.c_double), ("value", C.c_double * 9)]
 
@@ -110,7 +119,7 @@ EXPORTS = [
     "mf_assemble_ex", "mf_status_poll", "mf_last_error", "mf_version", "mf_pcg",
     "mf_batch_create", "mf_batch_tune", "mf_batch_run", "mf_batch_info", "mf_batch_destroy",
     "mf_nn_create", "mf_nn_params", "mf_nn_set_system", "mf_nn_apply", "mf_nn_train_step", "mf_nn_destroy", "mf_spmv",
-    "mf_bicgstab", "mf_ns_newton", "mf_assemble_boundary",
+    "mf_bicgstab", "mf_ns_newton", "mf_assemble_boundary", "mf_heat_transient",
 ]
 
 
@@ -146,6 +155,8 @@ def load():
     lib.mf_nn_apply.argtypes = [P, P, P, P]
     lib.mf_nn_train_step.argtypes = [P, P, P, C.c_double, C.POINTER(C.c_double), P, P]
     lib.mf_spmv.argtypes = [C.POINTER(_CSR), P, P, P]
+    lib.mf_heat_transient.argtypes = [P, C.c_double, C.c_double, P, P, P, P, C.POINTER(_Quad),
+                                      C.POINTER(_TransientOpts), P, P, C.POINTER(_TransientResult), P]
     lib.mf_assemble_boundary.argtypes = [P, C.POINTER(_BForm), P, i64, P, P, P, P, C.c_int, P, P, P]
     lib.mf_bicgstab.argtypes = [C.POINTER(_CSR), P, P, C.POINTER(_PcgOpts), C.POINTER(_PcgResult), P]
     lib.mf_ns_newton.argtypes = [P, C.POINTER(_Form), P, P, P, C.POINTER(_Quad), C.POINTER(_NewtonOpts),
@@ -512,6 +523,25 @@ def ns_newton(pattern, form, coords, state, dirichlet=None, rtol=1e-10, atol=0.0
     if st != OK and raise_on_fail:
         raise MFError(st, lib.mf_last_error().decode())
     return out
+
+
+def heat_transient(pattern, coords, T, Tdot, dt, n_steps, capacity=1.0, conductivity=1.0, elem_k=None, source=None,
+                   dirichlet=None, rho_inf=0.5, init_rate=False, lin_tol=1e-12, lin_maxit=20000,
+                   points_per_axis=2, stream=None):
+    """Generalized-alpha steps of C dT/dt - div(k grad T) = s; T and Tdot (FP64 cuda,
+    [n_nodes]) are updated in place.  Returns the result dict."""
+    import torch
+    lib = load()
+    for name, t in (("T", T), ("Tdot", Tdot), ("elem_k", elem_k), ("source", source)):
+        if t is not None:
+            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), f"{name}: contiguous float64 cuda"
+    opts = _TransientOpts(dt, rho_inf, n_steps, int(bool(init_rate)), lin_tol, lin_maxit)
+    res = _TransientResult()
+    q = _Quad(points_per_axis)
+    check(lib.mf_heat_transient(pattern.handle, capacity, conductivity, _ptr(coords), _ptr(elem_k), _ptr(source),
+                                _ptr(dirichlet), C.byref(q), C.byref(opts), _ptr(T), _ptr(Tdot), C.byref(res),
+                                _stream(stream)))
+    return {"steps": res.steps, "lin_iterations": res.lin_iterations, "max_lin_relres": res.max_lin_relres}
 
 
 def spmv(row_ptr, col_idx, values, x, y=None, stream=None):
