@@ -318,6 +318,62 @@ def bench_boundary(dev, mesh, pat, coords, K, d, cpu=True, steps=10, warmup=3):
     return out
 
 
+def bench_transient(dev, n=96, steps=20, cpu=True, n_cpu=24):
+    """Transient conduction on the 96^3 lognormal-conductivity cube of the learned
+    preconditioner's workload (seed 10000), capacity 1, unit source, T = 0 on the boundary:
+    20 generalized-alpha steps (rho_inf 0.5, dt 1e-4, about the diffusion time h^2 C / k of
+    one cell at k = 1), each solved by Jacobi-PCG to 1e-10.  The oracle (scipy LU per
+    step) is timed on a 24^3 mesh."""
+    import torch
+    import workloads as W
+    import paper_2111_03541_amd as mf
+    mesh = W.structured_mesh((n, n, n))
+    rng = np.random.default_rng(10000)
+    k = W.grf_lognormal_elem((n, n, n), float(rng.uniform(1.0, 2.0)), 0.1, 10001)
+    mask = W.boundary_node_mask(mesh.shape)
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 1)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    kt = torch.from_numpy(k).to(dev)
+    src = torch.ones(mesh.n_nodes, dtype=torch.float64, device=dev)
+    m = torch.from_numpy(mask).to(dev)
+    s = torch.cuda.Stream(dev)
+
+    def run(nsteps):
+        T = torch.zeros(mesh.n_nodes, dtype=torch.float64, device=dev)
+        U = torch.zeros(mesh.n_nodes, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(s):
+            res = mf.heat_transient(pat, coords, T, U, 1e-4, nsteps, elem_k=kt, source=src, dirichlet=m,
+                                    rho_inf=0.5, init_rate=True, lin_tol=1e-10, stream=s)
+        s.synchronize()
+        return res, time.perf_counter() - t0
+
+    run(1)  # warm-up
+    res0, w0 = run(0)
+    res, wall = run(steps)
+    per_step = (wall - w0) / steps
+    log(f"[bench] transient {n}^3: {steps} steps in {wall * 1e3:.1f} ms ({per_step * 1e3:.2f} ms/step beyond "
+        f"assembly and initial rate), {res['lin_iterations']} PCG iterations")
+    out = {"n": n, "n_dofs": pat.n_rows, "steps": steps, "ms": wall * 1e3, "ms_per_step": per_step * 1e3,
+           "setup_ms": w0 * 1e3, "lin_iterations": res["lin_iterations"] - res0["lin_iterations"]}
+    if cpu:
+        import oracle as O
+        import oracle.transient as OT
+        mc = W.structured_mesh((n_cpu, n_cpu, n_cpu))
+        kc = W.grf_lognormal_elem((n_cpu, n_cpu, n_cpu), 1.5, 0.1, 10001)
+        mk = W.boundary_node_mask(mc.shape)
+        t0 = time.perf_counter()
+        K, M, F = OT.operators(O.Pattern(mc, 1), 1.0, 1.0, elem_k=kc, source=np.ones(mc.n_nodes))
+        z = np.zeros(mc.n_nodes)
+        OT.heat_transient(K, M, F, z, z, 1e-4, steps, rho=0.5, mask=mk, init_rate=True)
+        t = time.perf_counter() - t0
+        out["cpu_oracle_small"] = {"n": n_cpu, "steps": steps, "ms": t * 1e3, "cores": 1,
+                                   "kind": "oracle (FP64 assembly, scipy sparse LU)"}
+        log(f"[bench] oracle transient {n_cpu}^3: {steps} steps in {t:.1f} s")
+    return out
+
+
 def cpu_baseline(mesh, E, b):
     import oracle as O
     t0 = time.perf_counter()
@@ -438,6 +494,7 @@ def main():
     record["secondary"]["batched_256_f32"] = bench_batch(dev)
     record["secondary"]["ns_48_f32"] = bench_ns(dev)
     record["secondary"]["ns_newton_cavity_32"] = bench_newton(dev, cpu=not args.no_cpu)
+    record["secondary"]["transient_96"] = bench_transient(dev, cpu=not args.no_cpu)
     if not args.no_cpu:
         log("[bench] timing the oracle on the host")
         record["cpu_baseline"] = cpu_baseline(mesh, E, b)
