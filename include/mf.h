@@ -47,7 +47,14 @@ typedef enum {
     MF_ERR_BAD_MESH = 9       /* connectivity references a node outside [0, n_nodes)    */
 } mf_status;
 
-typedef enum { MF_QUAD4 = 1, MF_HEX8 = 2 } mf_elem_type;           /* Lagrange order 1 */
+typedef enum {
+    MF_QUAD4 = 1,   /* 4-node quadrilateral, order 1                                        */
+    MF_HEX8 = 2,    /* 8-node hexahedron, order 1 (corners a = ax + 2 ay + 4 az)             */
+    MF_HEX20 = 3    /* 20-node serendipity hexahedron, order 2: corners as MF_HEX8, then the
+                       midpoints of the x-, y- and z-directed edges, four each, ordered by
+                       the bits of the two other axes; mass, conduction and elasticity forms
+                       with 3 Gauss points per axis (element-parallel, atomic scatter)     */
+} mf_elem_type;
 /* DOF numbering.  Field-major is the paper's map (Sec. 2.2 B-3): dof = field*n_nodes + node.
    Node-major interleaves the fields of a node: dof = n_fields*node + field. */
 typedef enum { MF_NODE_MAJOR = 0, MF_FIELD_MAJOR = 1 } mf_numbering;
@@ -63,7 +70,7 @@ typedef enum {
 typedef enum { MF_F64 = 0, MF_F32 = 1 } mf_precision;
 
 typedef struct {
-    int32_t dim;           /* 2 (MF_QUAD4) or 3 (MF_HEX8) */
+    int32_t dim;           /* 2 (MF_QUAD4) or 3 (MF_HEX8, MF_HEX20) */
     int64_t n_nodes;
     int64_t n_elems;
     const int32_t* conn;   /* [nen][n_elems] (device) */
@@ -124,7 +131,8 @@ typedef struct {
                                  elsewhere (homogeneous elimination, structure kept) */
 } mf_fields;
 
-typedef struct { int32_t points_per_axis; } mf_quadrature;   /* Gauss-Legendre; 2 supported */
+typedef struct { int32_t points_per_axis; } mf_quadrature;   /* Gauss-Legendre: 2 for order 1,
+                                                                  3 for MF_HEX20         */
 
 /* Assembly strategies.  AUTO picks the owner-computes gather for structured grids and
    element-parallel atomics otherwise. */

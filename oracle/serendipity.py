@@ -1,0 +1,156 @@
+"""Oracle: 20-node serendipity hexahedra (quadratic elements) in plain numpy.
+
+TEST INFRASTRUCTURE ONLY.  Only `tests/`, the smoke check and the benchmark's CPU
+baseline leg may import this module; the product library never does.
+
+The paper's experiments use quadratic serendipity elements (Sec. 4); the element order is
+one of the six inputs of the problem statement (Sec. 1).  Reference cube [-1, 1]^3,
+local nodes as workloads.serendipity_mesh numbers them (corners a = ax + 2 ay + 4 az,
+then the x-, y- and z-edge midpoints).  Shape functions, with s the corner signs:
+  corner   N = (1/8)(1 + s_x x)(1 + s_y y)(1 + s_z z)(s_x x + s_y y + s_z z - 2)
+  x-edge   N = (1/4)(1 - x^2)(1 + s_y y)(1 + s_z z)       (and cyclically for y, z)
+Quadrature: 3 Gauss points per axis, +-sqrt(3/5) and 0 with weights 5/9 and 8/9.
+Forms as the Q1 oracle defines them at the zero state (Sec. 4.1, 4.2; K = dR/dU, d = -R):
+  mass        K = int c N_a N_b,                        d = int c N_a f
+  conduction  K = int c grad N_a . grad N_b,            d = int N_a f
+  elasticity  K = int lam g_ai g_bj + mu g_aj g_bi + mu delta_ij g_a . g_b,  d = int N_a b_i
+with c = coef * elem_param and lam, mu from E = coef * elem_param and nu.  The pattern
+is built by brute force: N(v) = sorted nodes sharing an element with v.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import ELASTICITY, MASS, NODE_MAJOR, POISSON
+
+CORNER = np.array([[1.0 if (a >> d) & 1 else -1.0 for d in range(3)] for a in range(8)])
+# edge nodes: (axis along the edge, signs of the two other axes in cyclic order)
+EDGES = [(ax, ((m & 1) * 2 - 1.0, (m >> 1) * 2 - 1.0)) for ax in range(3) for m in range(4)]
+
+
+def basis20(xi):
+    """N [20], dN [20][3] at the reference point xi."""
+    x = np.asarray(xi, dtype=np.float64)
+    N = np.zeros(20)
+    dN = np.zeros((20, 3))
+    for a in range(8):
+        s = CORNER[a]
+        f = 1.0 + s * x
+        t = s @ x - 2.0
+        N[a] = 0.125 * f[0] * f[1] * f[2] * t
+        for d in range(3):
+            o = [k for k in range(3) if k != d]
+            dN[a, d] = 0.125 * (s[d] * f[o[0]] * f[o[1]] * t + f[0] * f[1] * f[2] * s[d])
+    for m, (ax, (s1, s2)) in enumerate(EDGES):
+        o1, o2 = (ax + 1) % 3, (ax + 2) % 3
+        # edge along ax: the other two axes carry the signs in the order (y, z), (x, z), (x, y)
+        oth = sorted((o1, o2))
+        sg = {oth[0]: s1, oth[1]: s2}
+        g0 = 1.0 - x[ax] ** 2
+        h1, h2 = 1.0 + sg[oth[0]] * x[oth[0]], 1.0 + sg[oth[1]] * x[oth[1]]
+        N[8 + m] = 0.25 * g0 * h1 * h2
+        dN[8 + m, ax] = 0.25 * (-2.0 * x[ax]) * h1 * h2
+        dN[8 + m, oth[0]] = 0.25 * g0 * sg[oth[0]] * h2
+        dN[8 + m, oth[1]] = 0.25 * g0 * h1 * sg[oth[1]]
+    return N, dN
+
+
+def gauss3():
+    p = np.sqrt(3.0 / 5.0)
+    pts, wts = np.array([-p, 0.0, p]), np.array([5.0, 8.0, 5.0]) / 9.0
+    xi = np.array([[pts[i], pts[j], pts[k]] for k in range(3) for j in range(3) for i in range(3)])
+    w = np.array([wts[i] * wts[j] * wts[k] for k in range(3) for j in range(3) for i in range(3)])
+    return xi, w
+
+
+class Pattern20:
+    """CSR pattern of K on a 20-node hex mesh, brute force."""
+
+    def __init__(self, mesh, nf: int, numbering: int = NODE_MAJOR):
+        self.mesh, self.nf, self.numbering = mesh, nf, numbering
+        nn = mesh.n_nodes
+        nbr = [set() for _ in range(nn)]
+        for e in range(mesh.n_elems):
+            nodes = mesh.conn[:, e]
+            for v in nodes:
+                nbr[v].update(int(u) for u in nodes)
+        self.nbr = [np.array(sorted(s), dtype=np.int64) for s in nbr]
+        self.n_rows = nn * nf
+        rows = []
+        for r in range(self.n_rows):
+            v, i = (r // nf, r % nf) if numbering == NODE_MAJOR else (r % nn, r // nn)
+            if numbering == NODE_MAJOR:
+                cols = (nf * self.nbr[v][:, None] + np.arange(nf)[None, :]).reshape(-1)
+            else:
+                cols = (np.arange(nf)[:, None] * nn + self.nbr[v][None, :]).reshape(-1)
+            rows.append(cols)
+        self.row_ptr = np.zeros(self.n_rows + 1, np.int64)
+        self.row_ptr[1:] = np.cumsum([len(c) for c in rows])
+        self.col_idx = np.concatenate(rows).astype(np.int32)
+        self.nnz = int(self.row_ptr[-1])
+
+    def dof(self, v, i):
+        return self.nf * v + i if self.numbering == NODE_MAJOR else i * self.mesh.n_nodes + v
+
+    def to_scipy(self, values):
+        import scipy.sparse as sp
+        return sp.csr_matrix((values, self.col_idx, self.row_ptr), shape=(self.n_rows, self.n_rows))
+
+
+def assemble20(pat: Pattern20, kind, params=None, elem_param=None, nodal_src=None):
+    """(K values [nnz] in the pattern's order, d [n_rows])."""
+    import scipy.sparse as sp
+    prm = dict(coef=1.0, nu=0.0)
+    prm.update(params or {})
+    mesh, nf = pat.mesh, pat.nf
+    xi, w = gauss3()
+    tables = [basis20(x) for x in xi]
+    rows, cols, vals = [], [], []
+    d = np.zeros(pat.n_rows)
+    for e in range(mesh.n_elems):
+        nodes = mesh.conn[:, e]
+        X = mesh.coords[:, nodes].T  # [20][3]
+        ep = 1.0 if elem_param is None else float(elem_param[e])
+        src = np.zeros((20, nf)) if nodal_src is None else np.asarray(nodal_src)[:, nodes].T
+        Ke = np.zeros((20, nf, 20, nf))
+        De = np.zeros((20, nf))
+        for (N, dN), wq in zip(tables, w):
+            J = X.T @ dN  # J[m][n] = dx_m / dxi_n
+            det = np.linalg.det(J)
+            if not det > 0.0:
+                raise FloatingPointError(f"det J <= 0 in element {e}")
+            g = np.linalg.solve(J.T, dN.T).T  # [20][3] physical gradients
+            W = wq * det
+            fq = N @ src
+            if kind == MASS:
+                c = prm["coef"] * ep
+                Ke[:, 0, :, 0] += W * c * np.outer(N, N)
+                De[:, 0] += W * c * N * fq[0]
+            elif kind == POISSON:
+                c = prm["coef"] * ep
+                Ke[:, 0, :, 0] += W * c * (g @ g.T)
+                De[:, 0] += W * N * fq[0]
+            elif kind == ELASTICITY:
+                E, nu = prm["coef"] * ep, prm["nu"]
+                lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+                mu = E / (2 * (1 + nu))
+                gg = g @ g.T
+                Ke += W * (lam * np.einsum("ai,bj->aibj", g, g) + mu * np.einsum("aj,bi->aibj", g, g)
+                           + mu * np.einsum("ab,ij->aibj", gg, np.eye(3)))
+                De += W * np.outer(N, fq)
+            else:
+                raise ValueError(kind)
+        for a in range(20):
+            for i in range(nf):
+                r = pat.dof(nodes[a], i)
+                d[r] += De[a, i]
+                for b in range(20):
+                    for j in range(nf):
+                        rows.append(r)
+                        cols.append(pat.dof(nodes[b], j))
+                        vals.append(Ke[a, i, b, j])
+    S = sp.coo_matrix((vals, (rows, cols)), shape=(pat.n_rows, pat.n_rows)).tocsr()
+    S.sum_duplicates()
+    rr = np.repeat(np.arange(pat.n_rows), np.diff(pat.row_ptr))
+    K = np.asarray(S[rr, pat.col_idx]).ravel()
+    return K, d

@@ -1,0 +1,269 @@
+// Assembly on 20-node serendipity hexahedra (quadratic elements, used by every experiment
+// of Sec. 4; element order is an input of the problem statement, Sec. 1), with the
+// 3-point Gauss rule per axis and the mass, conduction and elasticity forms of the linear
+// kernel (Sec. 4.1, 4.2; K = dR/dU, d = -R at the zero state).
+//
+// One wave per element, four elements per 256-thread workgroup:
+//   1. lanes load the element's 20 node coordinates and sources into LDS;
+//   2. lanes 0..26, one per Gauss point, build J = sum_b x_b (x) grad_xi N_b in FP64, its
+//      determinant and inverse, and store g_b = J^-T grad_xi N_b for the 20 nodes, the
+//      weight W = w det J and the interpolated source in LDS;
+//   3. lanes 0..20 nf - 1, one per element row (a, i), sum the 20 nf row entries over
+//      the 27 points and add them into K with atomics through the element-to-nonzero
+//      rank map (and d_(a,i) into d).
+// Local node order: corners a = ax + 2 ay + 4 az, then the midpoints of the x-, y- and
+// z-directed edges, four each, ordered by the bits of the two other axes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "mf_internal.h"
+
+namespace mf {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kElemsPerBlock = kThreads / 64;
+constexpr int kNQ = 27;
+
+__device__ __forceinline__ double bit_sign(int b) { return b ? 1.0 : -1.0; }
+
+// Shape functions and reference gradients of node a at xi.
+__device__ __forceinline__ void shape20(int a, const double (&x)[3], double& N, double (&dN)[3])
+{
+    if (a < 8) {
+        const double s[3] = {bit_sign(a & 1), bit_sign((a >> 1) & 1), bit_sign(a >> 2)};
+        const double f[3] = {1.0 + s[0] * x[0], 1.0 + s[1] * x[1], 1.0 + s[2] * x[2]};
+        const double t = s[0] * x[0] + s[1] * x[1] + s[2] * x[2] - 2.0;
+        N = 0.125 * f[0] * f[1] * f[2] * t;
+        dN[0] = 0.125 * s[0] * f[1] * f[2] * (t + f[0]);
+        dN[1] = 0.125 * s[1] * f[0] * f[2] * (t + f[1]);
+        dN[2] = 0.125 * s[2] * f[0] * f[1] * (t + f[2]);
+        return;
+    }
+    const int m = a - 8, ax = m >> 2, k = m & 3;
+    // the two other axes in ascending order carry the signs of bits 0 and 1 of k
+    const int o0 = ax == 0 ? 1 : 0, o1 = ax == 2 ? 1 : 2;
+    const double s0 = bit_sign(k & 1), s1 = bit_sign(k >> 1);
+    const double g = 1.0 - x[ax] * x[ax], h0 = 1.0 + s0 * x[o0], h1 = 1.0 + s1 * x[o1];
+    N = 0.25 * g * h0 * h1;
+    dN[ax] = -0.5 * x[ax] * h0 * h1;
+    dN[o0] = 0.25 * g * s0 * h1;
+    dN[o1] = 0.25 * g * h0 * s1;
+}
+
+__device__ __forceinline__ void gauss_point(int q, double (&x)[3], double& w)
+{
+    const double p = 0.7745966692414834;  // sqrt(3/5)
+    const double pts[3] = {-p, 0.0, p};
+    const double wts[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+    const int i = q % 3, j = (q / 3) % 3, k = q / 9;
+    x[0] = pts[i];
+    x[1] = pts[j];
+    x[2] = pts[k];
+    w = wts[i] * wts[j] * wts[k];
+}
+
+struct Q2Params {
+    mf_form form;
+    int64_t n_el, n_nodes;
+    const int32_t* conn;
+    const double* coords;
+    const int32_t* row_ptr;
+    const int32_t* nbr_ptr;
+    const uint8_t* rank;
+    const void* elem_param;
+    const void* src;
+    int field_major;
+    void* K;
+    void* d;
+    unsigned long long* status;
+};
+
+template <int NF>
+struct Q2Shared {
+    double x[20][3];
+    double src[20][NF];
+    double g[kNQ][20][3];
+    double N[kNQ][20];
+    double W[kNQ];
+    double f[kNQ][NF];
+    int bad;
+};
+
+template <typename T>
+__global__ void k_fill(T* p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = T(0);
+}
+
+template <int FORM, typename T>
+__global__ void __launch_bounds__(kThreads) k_assemble_hex20(Q2Params p)
+{
+    constexpr int NF = FORM == MF_FORM_ELASTICITY ? 3 : 1;
+    __shared__ Q2Shared<NF> SH[kElemsPerBlock];
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int64_t e = (int64_t)blockIdx.x * kElemsPerBlock + wv;
+    const bool live = e < p.n_el;  // uniform across the wave
+    Q2Shared<NF>& S = SH[wv];
+    if (live) {
+        if (lane < 60) {
+            const int b = lane / 3, m = lane % 3;
+            const int32_t v = p.conn[(int64_t)b * p.n_el + e];
+            S.x[b][m] = p.coords[(int64_t)m * p.n_nodes + v];
+        }
+        if (lane < 20 * NF) {
+            const int b = lane / NF, j = lane % NF;
+            const int32_t v = p.conn[(int64_t)b * p.n_el + e];
+            S.src[b][j] = p.src ? (double)((const T*)p.src)[(int64_t)j * p.n_nodes + v] : 0.0;
+        }
+        if (lane == 0) S.bad = 0;
+    }
+    __syncthreads();
+    if (live && lane < kNQ) {
+        double xi[3], w;
+        gauss_point(lane, xi, w);
+        double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int b = 0; b < 20; ++b) {
+            double Nb, dN[3];
+            shape20(b, xi, Nb, dN);
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+#pragma unroll
+                for (int n = 0; n < 3; ++n) J[m][n] = fma(S.x[b][m], dN[n], J[m][n]);
+        }
+        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        if (!(det > 0.0)) {
+            atomicMin(p.status, (unsigned long long)e);
+            S.bad = 1;
+        }
+        const double r = det > 0.0 ? 1.0 / det : 0.0;
+        double Ji[3][3];  // (J^-1)[n][m]
+        Ji[0][0] = c00 * r;
+        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+        Ji[1][0] = c01 * r;
+        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+        Ji[2][0] = c02 * r;
+        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+        double f[NF];
+#pragma unroll
+        for (int j = 0; j < NF; ++j) f[j] = 0.0;
+        for (int b = 0; b < 20; ++b) {
+            double Nb, dN[3];
+            shape20(b, xi, Nb, dN);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) S.g[lane][b][m] = Ji[0][m] * dN[0] + Ji[1][m] * dN[1] + Ji[2][m] * dN[2];
+            S.N[lane][b] = Nb;
+#pragma unroll
+            for (int j = 0; j < NF; ++j) f[j] = fma(Nb, S.src[b][j], f[j]);
+        }
+        S.W[lane] = w * det;
+#pragma unroll
+        for (int j = 0; j < NF; ++j) S.f[lane][j] = f[j];
+    }
+    __syncthreads();
+    if (!live || S.bad || lane >= 20 * NF) return;
+
+    const int a = lane / NF, i = lane % NF;
+    const double ep = p.elem_param ? (double)((const T*)p.elem_param)[e] : 1.0;
+    const double coef = p.form.coef * ep;
+    double lam = 0.0, mu = 0.0;
+    if constexpr (FORM == MF_FORM_ELASTICITY) {
+        const double nu = p.form.nu;
+        lam = coef * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        mu = coef / (2.0 * (1.0 + nu));
+    }
+    const int32_t va = p.conn[(int64_t)a * p.n_el + e];
+    const int64_t row = p.field_major ? (int64_t)i * p.n_nodes + va : (int64_t)NF * va + i;
+    const int64_t rs = p.row_ptr[row];
+    const int64_t deg = p.nbr_ptr[va + 1] - p.nbr_ptr[va];
+    T* K = (T*)p.K;
+    for (int b = 0; b < 20; ++b) {
+        double acc[NF];
+#pragma unroll
+        for (int j = 0; j < NF; ++j) acc[j] = 0.0;
+        for (int q = 0; q < kNQ; ++q) {
+            const double W = S.W[q];
+            if constexpr (FORM == MF_FORM_MASS) {
+                acc[0] = fma(W * coef * S.N[q][a], S.N[q][b], acc[0]);
+            } else {
+                const double ga[3] = {S.g[q][a][0], S.g[q][a][1], S.g[q][a][2]};
+                const double gb[3] = {S.g[q][b][0], S.g[q][b][1], S.g[q][b][2]};
+                const double gg = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+                if constexpr (FORM == MF_FORM_POISSON) {
+                    acc[0] = fma(W * coef, gg, acc[0]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < NF; ++j)
+                        acc[j] += W * (lam * ga[i] * gb[j] + mu * ga[j] * gb[i] + (i == j ? mu * gg : 0.0));
+                }
+            }
+        }
+        const int64_t rk = p.rank[(int64_t)(a * 20 + b) * p.n_el + e];
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            const int64_t pos = p.field_major ? rs + j * deg + rk : rs + rk * NF + j;
+            unsafeAtomicAdd(K + pos, (T)acc[j]);
+        }
+    }
+    double dv = 0.0;
+    const double cd = FORM == MF_FORM_MASS ? coef : 1.0;
+    for (int q = 0; q < kNQ; ++q) dv = fma(S.W[q] * cd * S.N[q][a], S.f[q][i], dv);
+    unsafeAtomicAdd((T*)p.d + row, (T)dv);
+}
+
+int blocks_for(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }
+
+template <int FORM, typename T>
+mf_status launch(const AssembleArgs& A)
+{
+    const mf_pattern_s* P = A.P;
+    Q2Params p{};
+    p.form = *A.form;
+    p.n_el = P->n_elems;
+    p.n_nodes = P->n_nodes;
+    p.conn = P->conn;
+    p.coords = A.coords;
+    p.row_ptr = P->row_ptr;
+    p.nbr_ptr = P->nbr_ptr;
+    p.rank = P->rank;
+    p.elem_param = A.elem_param;
+    p.src = A.nodal_src;
+    p.field_major = P->numbering == MF_FIELD_MAJOR;
+    p.K = A.K;
+    p.d = A.d;
+    p.status = P->status;
+    if (P->nnz > 0) k_fill<T><<<blocks_for(P->nnz), kThreads, 0, A.stream>>>((T*)A.K, P->nnz);
+    if (P->n_rows > 0) k_fill<T><<<blocks_for(P->n_rows), kThreads, 0, A.stream>>>((T*)A.d, P->n_rows);
+    const int64_t nb = (P->n_elems + kElemsPerBlock - 1) / kElemsPerBlock;
+    if (nb > 0) k_assemble_hex20<FORM, T><<<(unsigned)nb, kThreads, 0, A.stream>>>(p);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+template <typename T>
+mf_status dispatch(const AssembleArgs& A)
+{
+    switch (A.form->kind) {
+        case MF_FORM_MASS: return launch<MF_FORM_MASS, T>(A);
+        case MF_FORM_POISSON: return launch<MF_FORM_POISSON, T>(A);
+        case MF_FORM_ELASTICITY: return launch<MF_FORM_ELASTICITY, T>(A);
+        default: return set_error(MF_ERR_UNSUPPORTED, "form %d on 20-node hexahedra", (int)A.form->kind);
+    }
+}
+
+}  // namespace
+
+mf_status assemble_hex20(const AssembleArgs& A)
+{
+    return A.prec == MF_F64 ? dispatch<double>(A) : dispatch<float>(A);
+}
+
+}  // namespace mf

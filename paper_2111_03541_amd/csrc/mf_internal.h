@@ -62,6 +62,7 @@ struct AssembleArgs {
     hipStream_t stream;
 };
 mf_status assemble_atomic(const AssembleArgs& a);
+mf_status assemble_hex20(const AssembleArgs& a);
 mf_status assemble_column(const AssembleArgs& a);
 mf_status apply_dirichlet(const AssembleArgs& a);
 mf_status reset_status(const mf_pattern_s* P, hipStream_t s);

@@ -393,7 +393,7 @@ mf_status build_pattern(mf_pattern_s* P, const int32_t* conn_in, hipStream_t s)
 
     // structured-grid detection from the first element's nodes
     P->is_grid = 0;
-    if (n_el > 0) {
+    if (n_el > 0 && nen == (1 << P->dim)) {  // lexicographic Q1 grids only
         std::vector<int32_t> first(nen);
         for (int a = 0; a < nen; ++a)
             MF_HIP(hipMemcpyAsync(&first[a], conn + (int64_t)a * n_el, sizeof(int32_t),

@@ -1,0 +1,123 @@
+"""20-node serendipity hexahedra on the GPU against the numpy oracle (oracle/serendipity.py):
+pattern bit-exact, K and d within tolerance, and an end-to-end solve."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.serendipity as S
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def gpu_pattern(mf, mesh, nf, numbering=0):
+    dev = torch.device("cuda:0")
+    return mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, nf, numbering=numbering)
+
+
+@pytest.mark.parametrize("numbering", [0, 1])
+@pytest.mark.parametrize("nf", [1, 3])
+def test_pattern_bit_exact(mf, nf, numbering):
+    say("hex20 pattern nf", nf, "numbering", numbering)
+    mesh = W.serendipity_mesh((3, 2, 3), jitter=0.2, seed=1)
+    pat = gpu_pattern(mf, mesh, nf, numbering)
+    ref = S.Pattern20(mesh, nf, numbering)
+    rp, ci, rk = pat.arrays()
+    assert pat.grid()[0] is False
+    assert np.array_equal(rp.astype(np.int64), ref.row_ptr) and np.array_equal(ci, ref.col_idx)
+    # rank[a*20+b][e] is the position of node b in the sorted neighbours of node a
+    for e in (0, mesh.n_elems - 1):
+        for a in (0, 7, 8, 19):
+            va = mesh.conn[a, e]
+            nb = ref.nbr[va]
+            for b in range(20):
+                assert nb[rk[a * 20 + b, e]] == mesh.conn[b, e]
+
+
+CASES = [  # (name, kind, nf, params, elem_param, source)
+    ("mass", O.MASS, 1, {"coef": 1.7}, False, True),
+    ("poisson", O.POISSON, 1, {"coef": 1.3}, True, True),
+    ("elasticity", O.ELASTICITY, 3, {"coef": 2.0, "nu": 0.3}, True, True),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("numbering", [0, 1])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_assembly_matches_oracle(mf, case, numbering, prec):
+    name, kind, nf, prm, use_ep, use_src = case
+    say("hex20", name, "numbering", numbering, "prec", prec)
+    mesh = W.serendipity_mesh((3, 2, 3), jitter=0.2, seed=2, lengths=[1.0, 0.7, 1.2])
+    ep = W.lognormal_elem(mesh.n_elems, 0.4, 3) if use_ep else None
+    src = W.uniform_nodal(nf, mesh.n_nodes, -1, 1, 4) if use_src else None
+    fdt = np.float64 if prec == 0 else np.float32
+    if prec == 1:  # the oracle takes the same float-rounded inputs
+        ep = None if ep is None else ep.astype(np.float32).astype(np.float64)
+        src = None if src is None else src.astype(np.float32).astype(np.float64)
+    ref = S.Pattern20(mesh, nf, numbering)
+    Kr, dr = S.assemble20(ref, kind, prm, elem_param=ep, nodal_src=src)
+    dev = torch.device("cuda:0")
+    pat = gpu_pattern(mf, mesh, nf, numbering)
+    tt = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=fdt)).to(dev)
+    form = mf.Form(kind, coef=prm["coef"], nu=prm.get("nu", 0.0))
+    K, d = pat.assemble(form, torch.from_numpy(mesh.coords).to(dev), precision=prec, elem_param=tt(ep),
+                        nodal_src=tt(src))
+    assert pat.status()[0] == mf.OK
+    Kg, dg = K.double().cpu().numpy(), d.double().cpu().numpy()
+    tol = 1e-12 if prec == 0 else 1e-5
+    # row-scaled error, as for the order-1 forms
+    Sr, Sg = ref.to_scipy(Kr), ref.to_scipy(Kg)
+    rowmax = np.maximum(abs(Sr).max(axis=1).toarray().ravel(), 1e-300)
+    err = abs(Sg - Sr).max(axis=1).toarray().ravel() / rowmax
+    assert err.max() <= tol, err.max()
+    assert np.abs(dg - dr).max() <= tol * max(np.abs(dr).max(), 1e-300)
+
+
+def test_quadratic_solution_is_exact(mf):
+    """u = x^2 + y z - z^2 / 2 has lap u = 1 and lies in the serendipity space; on an
+    affine box with u on the boundary and f = -1, the discrete solution is u itself."""
+    say("hex20 quadratic solve")
+    n = (4, 3, 5)
+    L = [1.0, 0.8, 1.3]
+    mesh = W.serendipity_mesh(n, lengths=L)
+    c = mesh.coords
+    u = c[0] ** 2 + c[1] * c[2] - 0.5 * c[2] ** 2
+    hi = np.array(L)[:, None]
+    mask = np.any((np.abs(c) < 1e-12) | (np.abs(c - hi) < 1e-12), axis=0).astype(np.uint8)
+    dev = torch.device("cuda:0")
+    pat = gpu_pattern(mf, mesh, 1)
+    K, d = pat.assemble(mf.Form(mf.POISSON, coef=1.0), torch.from_numpy(c).to(dev),
+                        nodal_src=torch.full((1, mesh.n_nodes), -1.0, dtype=torch.float64, device=dev))
+    # lift the boundary values: solve K w = d - K u_b on the free rows, then u = w + u_b
+    ub = np.where(mask != 0, u, 0.0)
+    Kub = mf.spmv(*pat.device_arrays()[:2], K, torch.from_numpy(ub).to(dev)).cpu().numpy()
+    rhs = np.where(mask != 0, 0.0, d.cpu().numpy() - Kub)
+    K2, _ = pat.assemble(mf.Form(mf.POISSON, coef=1.0), torch.from_numpy(c).to(dev),
+                         dirichlet=torch.from_numpy(mask).to(dev))
+    rp, ci, _ = pat.device_arrays()
+    w, res = mf.pcg(rp, ci, K2, torch.from_numpy(rhs).to(dev), tol=1e-13)
+    say(f"  {res}")
+    assert np.abs(w.cpu().numpy() + ub - u).max() < 1e-9 * np.abs(u).max()
+
+
+def test_hex20_argument_errors(mf):
+    say("hex20 argument errors")
+    mesh = W.serendipity_mesh((1, 1, 1))
+    dev = torch.device("cuda:0")
+    pat = gpu_pattern(mf, mesh, 1)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    with pytest.raises(mf.MFError):  # the quadratic element takes 3 points per axis
+        pat.assemble(mf.Form(mf.POISSON), coords, points_per_axis=2)
+    pat4 = gpu_pattern(mf, mesh, 4)
+    st = torch.zeros((4, mesh.n_nodes), dtype=torch.float64, device=dev)
+    with pytest.raises(mf.MFError):  # no flow form on this element
+        pat4.assemble(mf.Form(mf.NS_SUPG, rho=1.0, mu=0.01), coords, lin_state=st)
+    with pytest.raises(mf.MFError):  # unknown element type
+        mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 1, elem=7)

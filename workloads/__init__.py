@@ -239,6 +239,55 @@ def dof_mask(node_mask: np.ndarray, n_fields: int, field_major: bool,
     return m.T.reshape(-1).copy()
 
 
+def serendipity_mesh(n, jitter: float = 0.0, seed=None, lengths=None) -> Mesh:
+    """Structured box of 20-node serendipity hexahedra, n = (nx, ny, nz) elements.
+
+    Nodes: the (nx+1)(ny+1)(nz+1) corner lattice (lexicographic, as structured_mesh), then
+    the midpoints of the x-, y- and z-directed edges, each set lexicographic.  Local
+    nodes: 0..7 the corners a = ax + 2 ay + 4 az; 8..11 the x-edges at (y, z) bits
+    (0,0), (1,0), (0,1), (1,1); 12..15 the y-edges at (x, z) bits; 16..19 the z-edges at
+    (x, y) bits.  Jitter moves interior corners only; every edge midpoint is the midpoint
+    of its two corners, so edges stay straight.  Returns a Mesh with nen = 20."""
+    nx, ny, nz = (int(v) for v in n)
+    base = structured_mesh((nx, ny, nz), jitter=jitter, seed=seed, lengths=lengths)
+    X = base.coords
+    NX, NY, NZ = nx + 1, ny + 1, nz + 1
+    cid = lambda i, j, k: i + NX * (j + NY * k)
+    n_c = NX * NY * NZ
+    n_ex, n_ey = nx * NY * NZ, NX * ny * NZ
+    ex_id = lambda i, j, k: n_c + i + nx * (j + NY * k)
+    ey_id = lambda i, j, k: n_c + n_ex + i + NX * (j + ny * k)
+    ez_id = lambda i, j, k: n_c + n_ex + n_ey + i + NX * (j + NY * k)
+    n_ez = NX * NY * nz
+    coords = np.zeros((3, n_c + n_ex + n_ey + n_ez))
+    coords[:, :n_c] = X
+    for k in range(NZ):
+        for j in range(NY):
+            for i in range(nx):
+                coords[:, ex_id(i, j, k)] = 0.5 * (X[:, cid(i, j, k)] + X[:, cid(i + 1, j, k)])
+    for k in range(NZ):
+        for j in range(ny):
+            for i in range(NX):
+                coords[:, ey_id(i, j, k)] = 0.5 * (X[:, cid(i, j, k)] + X[:, cid(i, j + 1, k)])
+    for k in range(nz):
+        for j in range(NY):
+            for i in range(NX):
+                coords[:, ez_id(i, j, k)] = 0.5 * (X[:, cid(i, j, k)] + X[:, cid(i, j, k + 1)])
+    conn = np.zeros((20, nx * ny * nz), dtype=np.int32)
+    for ez in range(nz):
+        for ey in range(ny):
+            for ex in range(nx):
+                e = ex + nx * (ey + ny * ez)
+                for a in range(8):
+                    conn[a, e] = cid(ex + (a & 1), ey + ((a >> 1) & 1), ez + (a >> 2))
+                for m in range(4):
+                    b0, b1 = m & 1, m >> 1
+                    conn[8 + m, e] = ex_id(ex, ey + b0, ez + b1)
+                    conn[12 + m, e] = ey_id(ex + b0, ey, ez + b1)
+                    conn[16 + m, e] = ez_id(ex + b0, ey + b1, ez)
+    return Mesh(coords, conn)
+
+
 def box_faces(n, sides=None):
     """Element faces on the sides of a structured 3D box mesh of n = (nx, ny, nz) elements.
 
