@@ -374,6 +374,48 @@ def bench_transient(dev, n=96, steps=20, cpu=True, n_cpu=24):
     return out
 
 
+def bench_hex20(dev, n=24, steps=10, warmup=3, cpu=True):
+    """Elasticity on 24^3 quadratic 20-node serendipity hexahedra (+-15% corner jitter,
+    lognormal E sigma 0.5, nu 0.3, body force U[-1,1]; 27 Gauss points), FP64 and FP32.
+    The oracle (numpy element loop) is timed on a 2^3 sample."""
+    import torch
+    import workloads as W
+    import paper_2111_03541_amd as mf
+    mesh = W.serendipity_mesh((n, n, n), jitter=0.15, seed=2)
+    E = W.lognormal_elem(mesh.n_elems, 0.5, 3)
+    b = W.uniform_nodal(3, mesh.n_nodes, -1, 1, 4)
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 3)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    form = mf.Form(mf.ELASTICITY, coef=1.0, nu=0.3)
+    out = {"n": n, "n_elems": mesh.n_elems, "nnz": pat.nnz}
+    for prec, dt, key in ((mf.F64, torch.float64, "f64"), (mf.F32, torch.float32, "f32")):
+        Et = torch.from_numpy(E).to(dt).to(dev)
+        bt = torch.from_numpy(b).to(dt).to(dev)
+        K = torch.empty(pat.nnz, dtype=dt, device=dev)
+        d = torch.empty(pat.n_rows, dtype=dt, device=dev)
+
+        def step():
+            pat.assemble(form, coords, precision=prec, elem_param=Et, nodal_src=bt, K=K, d=d)
+
+        _, per = time_launches(step, steps, warmup, stream)
+        avg = float(np.mean(per))
+        out[key] = {"avg_us": avg * 1e6, "elems_per_s": mesh.n_elems / avg}
+        log(f"[bench] hex20 elasticity {n}^3 {key}: {avg * 1e6:.1f} us ({mesh.n_elems / avg / 1e6:.2f} M el/s)")
+        del K, d
+    if cpu:
+        import oracle as O
+        import oracle.serendipity as S
+        m = W.serendipity_mesh((2, 2, 2), jitter=0.15, seed=2)
+        t0 = time.perf_counter()
+        S.assemble20(S.Pattern20(m, 3), O.ELASTICITY, {"coef": 1.0, "nu": 0.3},
+                     elem_param=W.lognormal_elem(m.n_elems, 0.5, 3), nodal_src=W.uniform_nodal(3, m.n_nodes, -1, 1, 4))
+        t = time.perf_counter() - t0
+        out["cpu_oracle"] = {"elems_per_s": m.n_elems / t, "sample": "2^3 elements", "cores": 1,
+                             "kind": "oracle (numpy element loop)"}
+    return out
+
+
 def cpu_baseline(mesh, E, b):
     import oracle as O
     t0 = time.perf_counter()
@@ -495,6 +537,7 @@ def main():
     record["secondary"]["ns_48_f32"] = bench_ns(dev)
     record["secondary"]["ns_newton_cavity_32"] = bench_newton(dev, cpu=not args.no_cpu)
     record["secondary"]["transient_96"] = bench_transient(dev, cpu=not args.no_cpu)
+    record["secondary"]["hex20_elasticity_24"] = bench_hex20(dev, cpu=not args.no_cpu)
     if not args.no_cpu:
         log("[bench] timing the oracle on the host")
         record["cpu_baseline"] = cpu_baseline(mesh, E, b)
