@@ -46,6 +46,7 @@ static void free_pattern(mf_pattern_s* P)
     (void)hipFree(P->col_idx);
     (void)hipFree(P->rank);
     (void)hipFree(P->status);
+    (void)hipFree(P->color_elems);
     delete P;
 }
 

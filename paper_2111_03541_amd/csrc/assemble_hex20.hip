@@ -3,14 +3,17 @@
 // 3-point Gauss rule per axis and the mass, conduction and elasticity forms of the linear
 // kernel (Sec. 4.1, 4.2; K = dR/dU, d = -R at the zero state).
 //
-// One wave per element, four elements per 256-thread workgroup:
+// One 256-thread workgroup per element:
 //   1. lanes load the element's 20 node coordinates and sources into LDS;
 //   2. lanes 0..26, one per Gauss point, build J = sum_b x_b (x) grad_xi N_b in FP64, its
 //      determinant and inverse, and store g_b = J^-T grad_xi N_b for the 20 nodes, the
 //      weight W = w det J and the interpolated source in LDS;
-//   3. lanes 0..20 nf - 1, one per element row (a, i), sum the 20 nf row entries over
-//      the 27 points and add them into K with atomics through the element-to-nonzero
-//      rank map (and d_(a,i) into d).
+//   3. lane (row (a, i), quarter) sums the entries of row (a, i) for the five column
+//      nodes b of its quarter over the 27 points and adds them into K through the
+//      element-to-nonzero rank map (quarter 0 also adds d_(a,i) into d).
+// Elements go colour by colour (no two elements of one colour share a node), one launch
+// per colour, so the adds are plain read-modify-writes: every entry of K and d has one
+// writer per launch, and the stream orders the launches.
 // Local node order: corners a = ax + 2 ay + 4 az, then the midpoints of the x-, y- and
 // z-directed edges, four each, ordered by the bits of the two other axes.
 #include <hip/hip_runtime.h>
@@ -23,8 +26,8 @@ namespace mf {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kElemsPerBlock = kThreads / 64;
 constexpr int kNQ = 27;
+constexpr int kQuarters = 4;  // column nodes b split in four groups of five
 
 __device__ __forceinline__ double bit_sign(int b) { return b ? 1.0 : -1.0; }
 
@@ -67,6 +70,8 @@ __device__ __forceinline__ void gauss_point(int q, double (&x)[3], double& w)
 struct Q2Params {
     mf_form form;
     int64_t n_el, n_nodes;
+    const int32_t* elems;  // the elements of one colour
+    int64_t n_list;
     const int32_t* conn;
     const double* coords;
     const int32_t* row_ptr;
@@ -102,11 +107,11 @@ template <int FORM, typename T>
 __global__ void __launch_bounds__(kThreads) k_assemble_hex20(Q2Params p)
 {
     constexpr int NF = FORM == MF_FORM_ELASTICITY ? 3 : 1;
-    __shared__ Q2Shared<NF> SH[kElemsPerBlock];
-    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int64_t e = (int64_t)blockIdx.x * kElemsPerBlock + wv;
-    const bool live = e < p.n_el;  // uniform across the wave
-    Q2Shared<NF>& S = SH[wv];
+    __shared__ Q2Shared<NF> S;
+    const int lane = threadIdx.x;
+    const int64_t li = blockIdx.x;
+    const bool live = li < p.n_list;  // uniform across the workgroup
+    const int64_t e = live ? p.elems[li] : 0;
     if (live) {
         if (lane < 60) {
             const int b = lane / 3, m = lane % 3;
@@ -169,9 +174,10 @@ __global__ void __launch_bounds__(kThreads) k_assemble_hex20(Q2Params p)
         for (int j = 0; j < NF; ++j) S.f[lane][j] = f[j];
     }
     __syncthreads();
-    if (!live || S.bad || lane >= 20 * NF) return;
+    if (!live || S.bad || lane >= 20 * NF * kQuarters) return;
 
-    const int a = lane / NF, i = lane % NF;
+    const int rowl = lane % (20 * NF), quarter = lane / (20 * NF);
+    const int a = rowl / NF, i = rowl % NF;
     const double ep = p.elem_param ? (double)((const T*)p.elem_param)[e] : 1.0;
     const double coef = p.form.coef * ep;
     double lam = 0.0, mu = 0.0;
@@ -185,7 +191,7 @@ __global__ void __launch_bounds__(kThreads) k_assemble_hex20(Q2Params p)
     const int64_t rs = p.row_ptr[row];
     const int64_t deg = p.nbr_ptr[va + 1] - p.nbr_ptr[va];
     T* K = (T*)p.K;
-    for (int b = 0; b < 20; ++b) {
+    for (int b = 5 * quarter; b < 5 * quarter + 5; ++b) {
         double acc[NF];
 #pragma unroll
         for (int j = 0; j < NF; ++j) acc[j] = 0.0;
@@ -210,13 +216,14 @@ __global__ void __launch_bounds__(kThreads) k_assemble_hex20(Q2Params p)
 #pragma unroll
         for (int j = 0; j < NF; ++j) {
             const int64_t pos = p.field_major ? rs + j * deg + rk : rs + rk * NF + j;
-            unsafeAtomicAdd(K + pos, (T)acc[j]);
+            K[pos] += (T)acc[j];
         }
     }
+    if (quarter != 0) return;
     double dv = 0.0;
     const double cd = FORM == MF_FORM_MASS ? coef : 1.0;
     for (int q = 0; q < kNQ; ++q) dv = fma(S.W[q] * cd * S.N[q][a], S.f[q][i], dv);
-    unsafeAtomicAdd((T*)p.d + row, (T)dv);
+    ((T*)p.d)[row] += (T)dv;
 }
 
 int blocks_for(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }
@@ -242,8 +249,15 @@ mf_status launch(const AssembleArgs& A)
     p.status = P->status;
     if (P->nnz > 0) k_fill<T><<<blocks_for(P->nnz), kThreads, 0, A.stream>>>((T*)A.K, P->nnz);
     if (P->n_rows > 0) k_fill<T><<<blocks_for(P->n_rows), kThreads, 0, A.stream>>>((T*)A.d, P->n_rows);
-    const int64_t nb = (P->n_elems + kElemsPerBlock - 1) / kElemsPerBlock;
-    if (nb > 0) k_assemble_hex20<FORM, T><<<(unsigned)nb, kThreads, 0, A.stream>>>(p);
+    MF_HIP(hipGetLastError());
+    if (P->n_elems == 0) return MF_OK;
+    mf_status st = ensure_coloring(P, A.stream);
+    if (st != MF_OK) return st;
+    for (size_t c = 0; c + 1 < P->color_ptr.size(); ++c) {
+        p.elems = P->color_elems + P->color_ptr[c];
+        p.n_list = P->color_ptr[c + 1] - P->color_ptr[c];
+        if (p.n_list > 0) k_assemble_hex20<FORM, T><<<(unsigned)p.n_list, kThreads, 0, A.stream>>>(p);
+    }
     MF_HIP(hipGetLastError());
     return MF_OK;
 }

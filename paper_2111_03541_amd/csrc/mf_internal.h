@@ -23,7 +23,11 @@ struct mf_pattern_s {
     int32_t* row_ptr = nullptr;  // [n_rows+1]
     int32_t* col_idx = nullptr;  // [nnz]
     uint8_t* rank = nullptr;     // [nen*nen][n_elems]
-    unsigned long long* status = nullptr;  // [1] first element with det J <= 0 (or ~0)
+    unsigned long long* status = nullptr;  // [2] first element with det J <= 0, first bad face (or ~0)
+    // element colouring (no two elements of one colour share a node), made on first use:
+    // the elements of colour c are color_elems[color_ptr[c] .. color_ptr[c+1])
+    int32_t* color_elems = nullptr;  // device [n_elems]
+    std::vector<int64_t> color_ptr;
     // structured lexicographic grid detection
     int is_grid = 0;
     int64_t gx = 0, gy = 0, gz = 0;
@@ -43,6 +47,8 @@ mf_status hip_error(hipError_t e, const char* what);
 
 // pattern.hip
 mf_status build_pattern(mf_pattern_s* P, const int32_t* conn_in, hipStream_t s);
+// greedy element colouring, cached in the pattern (sync on first call)
+mf_status ensure_coloring(const mf_pattern_s* P, hipStream_t s);
 
 struct PcgArgs;
 mf_status nn_bind_pcg(const mf_nn_t* net, int64_t n_rows, PcgArgs* a);

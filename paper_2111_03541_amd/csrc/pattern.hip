@@ -11,6 +11,7 @@
 // in which atomics fill the incidence lists).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <vector>
 
@@ -427,6 +428,63 @@ mf_status build_pattern(mf_pattern_s* P, const int32_t* conn_in, hipStream_t s)
         }
     }
     MF_HIP(hipStreamSynchronize(s));
+    return MF_OK;
+}
+
+// Greedy colouring of the elements in id order: each element takes the smallest colour
+// not used by an element that shares one of its nodes.  Host work over the node-element
+// incidence, once per pattern; elements are then listed colour by colour on the device.
+mf_status ensure_coloring(const mf_pattern_s* Pc, hipStream_t s)
+{
+    mf_pattern_s* P = const_cast<mf_pattern_s*>(Pc);
+    if (P->color_elems || P->n_elems == 0) return MF_OK;
+    const int64_t n_el = P->n_elems, nn = P->n_nodes;
+    const int nen = P->nen;
+    std::vector<int32_t> conn((size_t)(n_el * nen));
+    MF_HIP(hipMemcpyAsync(conn.data(), P->conn, sizeof(int32_t) * conn.size(), hipMemcpyDeviceToHost, s));
+    MF_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> inc_ptr((size_t)nn + 1, 0);
+    for (int64_t k = 0; k < n_el * nen; ++k) ++inc_ptr[(size_t)conn[(size_t)k] + 1];
+    for (int64_t v = 0; v < nn; ++v) inc_ptr[(size_t)v + 1] += inc_ptr[(size_t)v];
+    std::vector<int32_t> inc((size_t)(n_el * nen));
+    std::vector<int64_t> cur(inc_ptr.begin(), inc_ptr.end() - 1);
+    for (int64_t e = 0; e < n_el; ++e)
+        for (int a = 0; a < nen; ++a) inc[(size_t)cur[(size_t)conn[(size_t)(a * n_el + e)]]++] = (int32_t)e;
+    std::vector<int32_t> color((size_t)n_el, -1);
+    std::vector<int64_t> seen_at(64, -1);  // colour -> last element that saw it taken
+    int n_colors = 0;
+    for (int64_t e = 0; e < n_el; ++e) {
+        for (int a = 0; a < nen; ++a) {
+            const int32_t v = conn[(size_t)(a * n_el + e)];
+            for (int64_t k = inc_ptr[(size_t)v]; k < inc_ptr[(size_t)v + 1]; ++k) {
+                const int32_t c = color[(size_t)inc[(size_t)k]];
+                if (c >= 0) {
+                    if ((size_t)c >= seen_at.size()) seen_at.resize((size_t)c + 1, -1);
+                    seen_at[(size_t)c] = e;
+                }
+            }
+        }
+        int c = 0;
+        while ((size_t)c < seen_at.size() && seen_at[(size_t)c] == e) ++c;
+        color[(size_t)e] = c;
+        n_colors = std::max(n_colors, c + 1);
+    }
+    P->color_ptr.assign((size_t)n_colors + 1, 0);
+    for (int64_t e = 0; e < n_el; ++e) ++P->color_ptr[(size_t)color[(size_t)e] + 1];
+    for (int c = 0; c < n_colors; ++c) P->color_ptr[(size_t)c + 1] += P->color_ptr[(size_t)c];
+    std::vector<int32_t> order((size_t)n_el);
+    std::vector<int64_t> at(P->color_ptr.begin(), P->color_ptr.end() - 1);
+    for (int64_t e = 0; e < n_el; ++e) order[(size_t)at[(size_t)color[(size_t)e]]++] = (int32_t)e;
+    int32_t* dev = nullptr;
+    MF_HIP(hipMalloc(&dev, sizeof(int32_t) * (size_t)n_el));
+    hipError_t err = hipMemcpyAsync(dev, order.data(), sizeof(int32_t) * (size_t)n_el, hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err != hipSuccess) {
+        (void)hipFree(dev);
+        P->color_ptr.clear();
+        return hip_error(err, "colour upload");
+    }
+    P->color_elems = dev;
     return MF_OK;
 }
 
