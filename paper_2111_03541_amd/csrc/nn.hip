@@ -152,11 +152,8 @@ struct LevelSmem {
     float sv[A * A * A];
     bf16 sh1[C][B * B * B];
     bf16 sh2[C][D * D * D];
-    // weights, tap-major so that the C weights of one (tap, input channel) are adjacent
-    // (read with uniform addresses, i.e. LDS broadcasts)
-    float sw1[27][C];
-    float sw2[27][C][C];
-    float sw3[27][C];
+    // The weights are not staged: every weight index below is uniform across the wave,
+    // so they are scalar loads (SGPR operands of the FMAs) and cost no LDS issue slots.
 };
 
 template <int C, int T>
@@ -169,19 +166,7 @@ __device__ __forceinline__ void level_tile(const bf16* __restrict__ v, Grid g, c
     float* sv = S.sv;
     auto& sh1 = S.sh1;
     auto& sh2 = S.sh2;
-    auto& sw1 = S.sw1;
-    auto& sw2 = S.sw2;
-    auto& sw3 = S.sw3;
     const int tid = threadIdx.x;
-    for (int k = tid; k < 27 * C; k += kThreads) {
-        const int tap = k / C, o = k % C;
-        sw1[tap][o] = w1[o * 27 + tap];
-        sw3[tap][o] = w3[o * 27 + tap];
-    }
-    for (int k = tid; k < 27 * C * C; k += kThreads) {
-        const int tap = k / (C * C), ci = (k / C) % C, o = k % C;
-        sw2[tap][ci][o] = w2[(o * C + ci) * 27 + tap];
-    }
     const int ntx = (g.nx + T - 1) / T, nty = (g.ny + T - 1) / T;
     const int x0 = (bt % ntx) * T, y0 = ((bt / ntx) % nty) * T, z0 = (bt / (ntx * nty)) * T;
     auto inside = [&](int x, int y, int z) {
@@ -204,7 +189,7 @@ __device__ __forceinline__ void level_tile(const bf16* __restrict__ v, Grid g, c
                 const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
                 const float xv = sv[(lx + 1 + dx) + A * ((ly + 1 + dy) + A * (lz + 1 + dz))];
 #pragma unroll
-                for (int o = 0; o < C; ++o) a[o] = fmaf(sw1[tap][o], xv, a[o]);
+                for (int o = 0; o < C; ++o) a[o] = fmaf(w1[o * 27 + tap], xv, a[o]);
             }
         }
 #pragma unroll
@@ -225,7 +210,7 @@ __device__ __forceinline__ void level_tile(const bf16* __restrict__ v, Grid g, c
                 for (int ci = 0; ci < C; ++ci) {
                     const float xv = bf2f(sh1[ci][q]);
 #pragma unroll
-                    for (int o = 0; o < C; ++o) a[o] = fmaf(sw2[tap][ci][o], xv, a[o]);
+                    for (int o = 0; o < C; ++o) a[o] = fmaf(w2[(o * C + ci) * 27 + tap], xv, a[o]);
                 }
             }
         }
@@ -243,7 +228,7 @@ __device__ __forceinline__ void level_tile(const bf16* __restrict__ v, Grid g, c
             const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
             const int q = (lx + 1 + dx) + D * ((ly + 1 + dy) + D * (lz + 1 + dz));
 #pragma unroll
-            for (int ci = 0; ci < C; ++ci) a = fmaf(sw3[tap][ci], bf2f(sh2[ci][q]), a);
+            for (int ci = 0; ci < C; ++ci) a = fmaf(w3[ci * 27 + tap], bf2f(sh2[ci][q]), a);
         }
         float p = 0.f;
         if (coarse) {
@@ -462,12 +447,10 @@ __global__ void __launch_bounds__(kThreads) k_final_tiled(const bf16* __restrict
     constexpr int T = 8, A = T + 2, CT = T / 2 + 1;
     __shared__ float sv[A * A * A];
     __shared__ float sc[CT * CT * CT];
-    __shared__ float sw[27];
     const int tid = threadIdx.x;
     const int ntx = (g.nx + T - 1) / T, nty = (g.ny + T - 1) / T;
     const int bt = blockIdx.x;
     const int x0 = (bt % ntx) * T, y0 = ((bt / ntx) % nty) * T, z0 = (bt / (ntx * nty)) * T;
-    if (tid < 27) sw[tid] = w0[tid];
     for (int i = tid; i < A * A * A; i += kThreads) {
         const int x = x0 - 1 + i % A, y = y0 - 1 + (i / A) % A, zz = z0 - 1 + i / (A * A);
         const bool in = x >= 0 && x < g.nx && y >= 0 && y < g.ny && zz >= 0 && zz < g.nz;
@@ -490,7 +473,7 @@ __global__ void __launch_bounds__(kThreads) k_final_tiled(const bf16* __restrict
         for (int tap = 0; tap < 27; ++tap) {
             const int sx = x + tap % 3 - 1, sy = y + (tap / 3) % 3 - 1, sz = zz + tap / 9 - 1;
             if (sx < 0 || sx >= g.nx || sy < 0 || sy >= g.ny || sz < 0 || sz >= g.nz) continue;
-            acc = fmaf(sw[tap], sv[(lx + tap % 3) + A * ((ly + (tap / 3) % 3) + A * (lz + tap / 9))], acc);
+            acc = fmaf(w0[tap], sv[(lx + tap % 3) + A * ((ly + (tap / 3) % 3) + A * (lz + tap / 9))], acc);
         }
         if (acc1) {
             // coarse corners relative to the tile's first coarse point
