@@ -150,8 +150,9 @@ template <int C, int T>
 struct LevelSmem {
     static constexpr int A = T + 6, B = T + 4, D = T + 2;  // tile edges of v, h1, h2
     float sv[A * A * A];
-    bf16 sh1[C][B * B * B];
-    bf16 sh2[C][D * D * D];
+    // channel-minor, so that the C channels of one point are one 8- or 16-byte read
+    bf16 sh1[B * B * B][C];
+    bf16 sh2[D * D * D][C];
     // The weights are not staged: every weight index below is uniform across the wave,
     // so they are scalar loads (SGPR operands of the FMAs) and cost no LDS issue slots.
 };
@@ -193,7 +194,7 @@ __device__ __forceinline__ void level_tile(const bf16* __restrict__ v, Grid g, c
             }
         }
 #pragma unroll
-        for (int o = 0; o < C; ++o) sh1[o][i] = f2bf(a[o]);
+        for (int o = 0; o < C; ++o) sh1[i][o] = f2bf(a[o]);
     }
     __syncthreads();
     for (int i = tid; i < D * D * D; i += kThreads) {
@@ -208,14 +209,14 @@ __device__ __forceinline__ void level_tile(const bf16* __restrict__ v, Grid g, c
                 const int q = (lx + 1 + dx) + B * ((ly + 1 + dy) + B * (lz + 1 + dz));
 #pragma unroll
                 for (int ci = 0; ci < C; ++ci) {
-                    const float xv = bf2f(sh1[ci][q]);
+                    const float xv = bf2f(sh1[q][ci]);
 #pragma unroll
                     for (int o = 0; o < C; ++o) a[o] = fmaf(w2[(o * C + ci) * 27 + tap], xv, a[o]);
                 }
             }
         }
 #pragma unroll
-        for (int o = 0; o < C; ++o) sh2[o][i] = f2bf(a[o]);
+        for (int o = 0; o < C; ++o) sh2[i][o] = f2bf(a[o]);
     }
     __syncthreads();
     for (int i = tid; i < T * T * T; i += kThreads) {
@@ -228,7 +229,7 @@ __device__ __forceinline__ void level_tile(const bf16* __restrict__ v, Grid g, c
             const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
             const int q = (lx + 1 + dx) + D * ((ly + 1 + dy) + D * (lz + 1 + dz));
 #pragma unroll
-            for (int ci = 0; ci < C; ++ci) a = fmaf(w3[ci * 27 + tap], bf2f(sh2[ci][q]), a);
+            for (int ci = 0; ci < C; ++ci) a = fmaf(w3[ci * 27 + tap], bf2f(sh2[q][ci]), a);
         }
         float p = 0.f;
         if (coarse) {
