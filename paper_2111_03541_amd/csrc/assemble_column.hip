@@ -141,15 +141,20 @@ struct ColShared {
     AccT<FORM> rowK[kColNodes][27 * NB];
     AccT<FORM> rowD[kColNodes][NF];
     int ni[kColNodes][4];  // node id, first pair offset, degree, boundary bits
+    // Dirichlet flags of the tile's DOFs for node layers L = kz-2 .. kz+1 (slot L & 3): the
+    // write-out of layer kz-1 reads its rows' and its neighbours' flags here, so no global
+    // load follows its stores (a load would wait for every store in flight)
+    uint8_t msk[4][kTileNodes][NF];
 };
 
 __device__ __forceinline__ int ring3(int L) { return (L + 3) % 3; }
 
 // Global loads of one node of the tile of node layer L (registers), and their LDS store.
-template <int NSRC, typename T>
+template <int NSRC, int NF, bool MASK, typename T>
 struct NodeLoad {
     double x[3];
     T u[NSRC];
+    int m;  // Dirichlet flag of field k in bit k
     bool ok;
     __device__ __forceinline__ void load(const ColParams& p, int L, int tn, int i0, int j0)
     {
@@ -159,10 +164,16 @@ struct NodeLoad {
         if (!ok) return;
         const int node = gi + NX * (gj + NY * L);
 #pragma unroll
-        for (int m = 0; m < 3; ++m) x[m] = p.coords[(int64_t)m * p.n_nodes + node];
+        for (int c = 0; c < 3; ++c) x[c] = p.coords[(int64_t)c * p.n_nodes + node];
         const T* s = (const T*)p.src;
 #pragma unroll
         for (int k = 0; k < NSRC; ++k) u[k] = s ? s[(int64_t)k * p.n_nodes + node] : T(0);
+        m = 0;
+        if (MASK && p.dirichlet) {
+#pragma unroll
+            for (int k = 0; k < NF; ++k)
+                m |= (p.dirichlet[p.field_major ? (int64_t)k * p.n_nodes + node : (int64_t)NF * node + k] != 0) << k;
+        }
     }
     template <int FORM>
     __device__ __forceinline__ void store(ColShared<FORM, T>& S, int L, int tn) const
@@ -170,9 +181,13 @@ struct NodeLoad {
         if (!ok) return;
         const int r = ring3(L);
 #pragma unroll
-        for (int m = 0; m < 3; ++m) S.x[r][tn][m] = x[m];
+        for (int c = 0; c < 3; ++c) S.x[r][tn][c] = x[c];
 #pragma unroll
         for (int k = 0; k < NSRC; ++k) S.u[r][tn][k] = u[k];
+        if constexpr (MASK) {
+#pragma unroll
+            for (int k = 0; k < NF; ++k) S.msk[L & 3][tn][k] = (uint8_t)((m >> k) & 1);
+        }
     }
 };
 
@@ -386,7 +401,6 @@ template <int FORM, typename T>
 __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>& S, int kz, int i0, int j0)
 {
     constexpr int NF = FormTraits<FORM, 3>::NF;
-    constexpr int NB = NF * NF;
     using Acc = AccT<FORM>;
     constexpr int NV = FORM == MF_FORM_ELASTICITY ? 9 : (FORM == MF_FORM_NS_SUPG ? 16 : 1);
     const int tid = threadIdx.x;
@@ -562,8 +576,8 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
 // the order of a node-major CSR row block, so an interior node's rows are one contiguous
 // copy; boundary nodes, field-major numbering and Dirichlet masks take the general
 // mapping.  K is written once and is far larger than the caches: non-temporal stores.
-template <int FORM, typename T>
-__device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, T>& S, int wid, int nw)
+template <int FORM, bool MASK, typename T>
+__device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, T>& S, int L, int wid, int nw)
 {
     constexpr int NF = FormTraits<FORM, 3>::NF;
     constexpr int NB = NF * NF;
@@ -572,9 +586,9 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
     using Acc = AccT<FORM>;
     T* K = (T*)p.K;
     T* d = (T*)p.d;
-    const int NX = p.nx + 1, NY = p.ny + 1;
     const int nn = p.n_nodes;
-    const bool plain = !p.field_major && !p.dirichlet;
+    const bool masked = MASK && p.dirichlet;
+    const bool plain = !p.field_major && !masked;
     const int lane = wid & 63, wv = wid >> 6, nwv = nw >> 6;
     for (int il = wv; il < kColNodes; il += nwv) {
         Acc vals[NCH];
@@ -616,20 +630,13 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
                              (ddz < 0 ? 16 : 0) | (ddz > 0 ? 32 : 0);
             if ((bits & need) != need) continue;
             const int rank = ((ddz + lo_z) * my + (ddy + lo_y)) * mx + (ddx + lo_x);
-            int row, kpos;
-            if (p.field_major) {
-                row = i * nn + node;
-                kpos = i * NF * p.n_pairs + NF * P + j * deg + rank;
-            } else {
-                row = NF * node + i;
-                kpos = P * NB + i * NF * deg + rank * NF + j;
-            }
+            const int kpos = p.field_major ? i * NF * p.n_pairs + NF * P + j * deg + rank
+                                           : P * NB + i * NF * deg + rank * NF + j;
             T v = (T)vals[c];
-            if (p.dirichlet) {
-                const int nb = node + ddx + NX * (ddy + NY * ddz);
-                const int col = p.field_major ? j * nn + nb : NF * nb + j;
-                if (p.dirichlet[row]) v = (col == row) ? T(1) : T(0);
-                else if (p.dirichlet[col]) v = T(0);
+            if (masked) {
+                const int tn = il % CX + 1 + TX * (il / CX + 1);  // the node in the tile
+                if (S.msk[L & 3][tn][i]) v = (slot == 13 && j == i) ? T(1) : T(0);
+                else if (S.msk[(L + ddz) & 3][tn + ddx + TX * ddy][j]) v = T(0);
             }
             __builtin_nontemporal_store(v, &K[kpos]);
         }
@@ -641,14 +648,14 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
         const int node = S.ni[il][0];
         if (node >= 0) {
             const int row = p.field_major ? i * nn + node : NF * node + i;
-            d[row] = (p.dirichlet && p.dirichlet[row]) ? T(0) : (T)acc;
+            d[row] = (masked && S.msk[L & 3][il % CX + 1 + TX * (il / CX + 1)][i]) ? T(0) : (T)acc;
         }
     }
 }
 
 // One column chunk b of one problem (b = column + columns * chunk); called by the
 // single-problem kernel and by the persistent batched kernel.
-template <int FORM, typename T>
+template <int FORM, bool MASK, typename T>
 __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared<FORM, T>& S)
 {
     constexpr int NF = FormTraits<FORM, 3>::NF;
@@ -666,7 +673,7 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
     for (int k = tid; k < kColNodes * NF; k += kThreads) (&S.rowD[0][0])[k] = 0.0;
     // prologue: node layers z0-1 .. z0+1, element parameters of layers z0-1 and z0
     for (int it = tid; it < 3 * kTileNodes; it += kThreads) {
-        NodeLoad<NSRC, T> ld;
+        NodeLoad<NSRC, NF, MASK, T> ld;
         const int L = z0 - 1 + it / kTileNodes, tn = it % kTileNodes;
         ld.load(p, L, tn, i0, j0);
         ld.template store<FORM>(S, L, tn);
@@ -687,12 +694,12 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
                 geometry_item<FORM, T>(p, S, L, r >> 3, r & 7, i0, j0);
             }
         } else if (kz > z0) {
-            write_layer<FORM, T>(p, S, tid - kGeomThreads, kThreads - kGeomThreads);
+            write_layer<FORM, MASK, T>(p, S, kz - 1, tid - kGeomThreads, kThreads - kGeomThreads);
         }
         __syncthreads();
 
         // ---- phase B: rows of node layer kz; prefetch for the next step
-        NodeLoad<NSRC, T> ld;
+        NodeLoad<NSRC, NF, MASK, T> ld;
         ld.ok = false;
         double epv = 0.0;
         bool ep_ok = false;
@@ -724,14 +731,16 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
         }
         __syncthreads();
     }
-    if (z0 < z1) write_layer<FORM, T>(p, S, tid, kThreads);
+    if (z0 < z1) write_layer<FORM, MASK, T>(p, S, z1 - 1, tid, kThreads);
 }
 
-template <int FORM, typename T>
+// MASK: the problem has Dirichlet flags (the unmasked instantiation carries none of their
+// loads or registers)
+template <int FORM, bool MASK, typename T>
 __global__ void __launch_bounds__(kThreads, (MinBlocks<FORM, T>::value)) k_assemble_column(ColParams p)
 {
     __shared__ ColShared<FORM, T> S;
-    column_body<FORM, T>(p, blockIdx.x, S);
+    column_body<FORM, MASK, T>(p, blockIdx.x, S);
 }
 
 // ------------------------------------------------------------------------------------
@@ -778,11 +787,11 @@ __global__ void __launch_bounds__(kThreads, kMinBlocks)
         const ColParams cp = probs[w.x].cp;
         const int kind = probs[w.x].kind;
         if (kind == MF_FORM_ELASTICITY)
-            column_body<MF_FORM_ELASTICITY, T>(cp, w.y, S.elasticity);
+            column_body<MF_FORM_ELASTICITY, true, T>(cp, w.y, S.elasticity);
         else if (kind == MF_FORM_POISSON)
-            column_body<MF_FORM_POISSON, T>(cp, w.y, S.poisson);
+            column_body<MF_FORM_POISSON, true, T>(cp, w.y, S.poisson);
         else
-            column_body<MF_FORM_MASS, T>(cp, w.y, S.mass);
+            column_body<MF_FORM_MASS, true, T>(cp, w.y, S.mass);
     }
 }
 
@@ -856,7 +865,10 @@ mf_status launch_column(const AssembleArgs& A)
     const int64_t wgs = columns * ((NZ + p.lz - 1) / p.lz);
     if (wgs <= 0) return MF_OK;
     if (wgs > 0x7fffffff) return set_error(MF_ERR_OVERFLOW, "grid of %lld workgroups", (long long)wgs);
-    k_assemble_column<FORM, T><<<(unsigned)wgs, kThreads, 0, A.stream>>>(p);
+    if (p.dirichlet)
+        k_assemble_column<FORM, true, T><<<(unsigned)wgs, kThreads, 0, A.stream>>>(p);
+    else
+        k_assemble_column<FORM, false, T><<<(unsigned)wgs, kThreads, 0, A.stream>>>(p);
     MF_HIP(hipGetLastError());
     return MF_OK;
 }

@@ -332,7 +332,7 @@ GATHER_MESHES = [(1, 1, 1), (2, 1, 1), (3, 5, 2), (7, 7, 3), (4, 4, 4), (5, 3, 1
 @pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
 def test_gather_on_small_and_ragged_grids(mf, n, fname, kind, prec):
     """The owner-computes path on grids whose node counts are and are not multiples of
-    the 4x4 node column, with Dirichlet rows on one face; against the oracle."""
+    the 4x2 node column, with Dirichlet rows on one face; against the oracle."""
     say("gather", n, fname, prec)
     mesh = W.structured_mesh(n, jitter=0.1, seed=sum(n))
     nf = O.form_nf(kind, 3)
@@ -347,3 +347,23 @@ def test_gather_on_small_and_ragged_grids(mf, n, fname, kind, prec):
     K, d = run_gpu(mf, pat, kind, params, mesh, prec, ep, src, state, mask=mask, scatter=mf.SCATTER_GATHER)
     assert rowscaled_error(ref_pat, K, Kr) <= TOL[prec]
     assert vec_error(d, dr) <= TOL[prec]
+
+
+@pytest.mark.parametrize("numbering", [0, 1], ids=["node_major", "field_major"])
+@pytest.mark.parametrize("fname,kind", [FORMS[1], FORMS[2]], ids=["poisson", "elasticity"])
+def test_gather_scattered_dirichlet(mf, fname, kind, numbering):
+    """Dirichlet flags on random DOFs inside the grid (not only on faces), so every
+    neighbour offset of the write-out's flag lookup meets constrained columns; the grid is
+    tall enough that columns are split into several layer ranges."""
+    say("gather scattered dirichlet", fname, numbering)
+    mesh = W.structured_mesh((9, 6, 40), jitter=0.1, seed=11)
+    nf = O.form_nf(kind, 3)
+    params, ep, src, state = make_inputs(kind, mesh, seed=13)
+    mask = (np.random.default_rng(14).random(nf * mesh.n_nodes) < 0.2).astype(np.uint8)
+    ref_pat = O.Pattern(mesh, nf, numbering=numbering)
+    Kr, dr = O.assemble(ref_pat, kind, params, elem_param=ep, nodal_src=src, dirichlet=mask)
+    pat = gpu_pattern(mf, mesh, nf, numbering=numbering)
+    assert pat.grid()[0]
+    K, d = run_gpu(mf, pat, kind, params, mesh, 0, ep, src, state, mask=mask, scatter=mf.SCATTER_GATHER)
+    assert rowscaled_error(ref_pat, K, Kr) <= TOL[0]
+    assert vec_error(d, dr) <= TOL[0]
