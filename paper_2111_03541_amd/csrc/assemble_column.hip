@@ -606,7 +606,21 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
         if (node < 0) continue;
         const int bits = S.ni[il][3];
         const int P = S.ni[il][1];
-        if (plain && bits == 63) {
+        bool contiguous = plain && bits == 63;
+        if constexpr (MASK) {
+            // an interior node with no flag on itself or its 26 neighbours keeps the
+            // contiguous copy (one lane per neighbour; the node is wave-uniform)
+            if (masked && !p.field_major && bits == 63) {
+                bool hit = false;
+                if (lane < 27) {
+                    const int tn = il % CX + 1 + TX * (il / CX + 1) + (lane % 3 - 1) + TX * ((lane / 3) % 3 - 1);
+#pragma unroll
+                    for (int k = 0; k < NF; ++k) hit |= S.msk[(L + lane / 9 - 1) & 3][tn][k] != 0;
+                }
+                contiguous = !__any(hit);
+            }
+        }
+        if (contiguous) {
             T* dst = K + (int64_t)P * NB;
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
