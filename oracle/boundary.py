@@ -14,6 +14,20 @@ R = -d_paper, K = dR/dU, exported d = -R(U):
   flux                  R_a     = - int coef N_a n . grad T   (grad T of the face's element)
   traction              R_(a,i) = - int N_a sigma^l_ij n_j
 
+and the flow boundaries of Sec. 4.3 with the flow form's reading R = +d_paper (fields
+u_0, u_1, u_2, p; coef = tau^b, value[0..3) = u^w unless a target gives it per node,
+value[3] = rho, value[4] = mu; (A, B) is the integral of B times the variation of A):
+
+  every flow kind (base)  R_(a,i) += int N_a (p n_i - mu u_i,j n_j)
+  inflow                  R_(a,i) += int rho N_a u^w_i (u^w . n) + mu (n . grad N_a) (u^w_i - u_i)
+                                     + tau^b rho N_a (u_i - u^w_i)
+                          R_(a,p) += int N_a (u^w - u) . n
+  outflow                 R_(a,i) += int rho N_a u_i (u . n)
+  fix                     inflow with u^w = 0 (its rho u^w u^w.n term vanishes)
+
+The test gradient in the inflow and fix terms makes every node of the face's element a
+row, not only the four face nodes.
+
 Each face of a hexahedron is xi_axis = -1 or +1 of the reference cube; the face rule is
 the 2x2 Gauss rule in the two other reference coordinates, the surface element is
 |dx/dxi_u x dx/dxi_v| and the outward normal is that cross product with the sign of the
@@ -22,7 +36,11 @@ side.  The basis and its reference gradients come from the oracle's C code (or_b
 Pins (tests/test_oracle_boundary.py): face mass sums to the area and has the closed form
 of a flat square face; a uniform traction integrates to t times the area; domain Laplacian
 plus flux term annihilates linear fields (divergence theorem); the radiation tangent
-matches central differences.
+matches central differences.  Flow: hand-integrated values of every inflow and outflow
+term on one unit cube; the flow domain form (no stabilisation) plus outflow on every face
+equals the mass matrix times rho div(u u) + grad p and div u for linear u, p (integration
+by parts); inflow with u^w = u equals outflow; tangents match central differences; the
+fix condition's pressure-velocity blocks are antisymmetric.
 """
 from __future__ import annotations
 
@@ -30,7 +48,8 @@ import numpy as np
 
 from . import NODE_MAJOR, basis
 
-PENALTY, CONVECTION, RADIATION, FLUX, TRACTION = 0, 1, 2, 3, 4
+PENALTY, CONVECTION, RADIATION, FLUX, TRACTION, NS_INFLOW, NS_OUTFLOW, NS_FIX = range(8)
+FLOW_KINDS = (NS_INFLOW, NS_OUTFLOW, NS_FIX)
 
 
 def _dof(pat, node, i):
@@ -71,6 +90,10 @@ def assemble_boundary(pat, kind, coef, value, face_elem, face_id, state=None, ta
                 w = dS
                 uq = N @ U
                 gq = N @ G
+                if kind in FLOW_KINDS:
+                    grad = np.linalg.solve(J.T, dN.T).T  # rows: grad N_b = J^-T grad_xi N_b
+                    _flow_point(kind, coef, value, w, n, N, grad @ n, U, uq, gq, Ke, Re)
+                    continue
                 for a in range(8):
                     for i in range(nf):
                         if kind in (PENALTY, CONVECTION):
@@ -101,3 +124,32 @@ def assemble_boundary(pat, kind, coef, value, face_elem, face_id, state=None, ta
                             vals.append(Ke[a, i, b, j])
     K = sp.coo_matrix((vals, (rows, cols)), shape=(pat.n_rows, pat.n_rows)).tocsr()
     return K, d
+
+
+def _flow_point(kind, coef, value, w, n, N, gn, U, uq, gq, Ke, Re):
+    """One face point of a flow boundary form: adds to the element residual Re [8][4] and
+    tangent Ke [8][4][8][4] (gn[b] = n . grad N_b)."""
+    rho, mu, tau = value[3], value[4], coef
+    u, p = uq[:3], uq[3]
+    uw = gq[:3] if kind == NS_INFLOW else np.zeros(3)
+    un = u @ n
+    for a in range(8):
+        for i in range(3):
+            # base: p n_i - mu u_i,j n_j
+            Re[a, i] += w * N[a] * (p * n[i] - mu * (gn @ U[:, i]))
+            Ke[a, i, :, 3] += w * N[a] * n[i] * N
+            Ke[a, i, :, i] -= w * mu * N[a] * gn
+            if kind in (NS_INFLOW, NS_FIX):
+                Re[a, i] += w * rho * N[a] * uw[i] * (uw @ n)
+                Re[a, i] += w * mu * gn[a] * (uw[i] - u[i])
+                Ke[a, i, :, i] -= w * mu * gn[a] * N
+                Re[a, i] += w * tau * rho * N[a] * (u[i] - uw[i])
+                Ke[a, i, :, i] += w * tau * rho * N[a] * N
+            else:
+                Re[a, i] += w * rho * N[a] * u[i] * un
+                for k in range(3):
+                    Ke[a, i, :, k] += w * rho * N[a] * N * ((un if i == k else 0.0) + u[i] * n[k])
+        if kind in (NS_INFLOW, NS_FIX):
+            Re[a, 3] += w * N[a] * ((uw - u) @ n)
+            for k in range(3):
+                Ke[a, 3, :, k] -= w * N[a] * N * n[k]

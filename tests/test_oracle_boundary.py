@@ -110,3 +110,116 @@ def test_radiation_tangent_by_central_differences():
     # at T = T_env the residual vanishes
     _, d0 = OB.assemble_boundary(pat, OB.RADIATION, c, [Te], fe, fi, state=np.full((1, mesh.n_nodes), Te))
     assert np.abs(d0).max() < 1e-14
+
+
+# ---------------------------------------------------------------- flow boundaries (Sec. 4.3)
+
+def _flow(kind, pat, faces, state=None, target=None, tau=0.0, uw=(0.0, 0.0, 0.0), rho=0.0, mu=0.0):
+    return OB.assemble_boundary(pat, kind, tau, [*uw, rho, mu], *faces, state=state, target=target)
+
+
+def test_flow_terms_on_one_unit_cube_by_hand():
+    """Face x = 1 of the unit cube: int N_a dS = 1/4 on its four nodes and
+    int n . grad N_a dS = +1/4 on them, -1/4 on the four nodes behind it."""
+    mesh = box((1, 1, 1))
+    pat = O.Pattern(mesh, 4)
+    faces = (np.array([0], np.int32), np.array([1], np.uint8))
+    front = np.array([a & 1 for a in range(8)], bool)
+    w0 = np.array([0.7, -0.4, 0.9])
+    rho, mu, tau = 1.3, 0.25, 2.0
+    # inflow at rest: rho u^w (u^w.n) + mu (n.grad N_a) u^w - tau rho u^w; p-rows (u^w.n)
+    _, d = _flow(OB.NS_INFLOW, pat, faces, tau=tau, uw=w0, rho=rho, mu=mu)
+    R = -d.reshape(8, 4)
+    for a in range(8):
+        if front[a]:
+            ref = (rho * w0 * w0[0] + mu * w0 - tau * rho * w0) / 4
+            assert np.abs(R[a, :3] - ref).max() < 1e-15 and abs(R[a, 3] - w0[0] / 4) < 1e-15
+        else:
+            assert np.abs(R[a, :3] + mu * w0 / 4).max() < 1e-15 and R[a, 3] == 0.0
+    # outflow of a uniform state (u = w0, p = p0): rho u (u.n) + p n on the face nodes
+    st = np.zeros((4, 8))
+    st[:3] = w0[:, None]
+    st[3] = -0.6
+    _, d = _flow(OB.NS_OUTFLOW, pat, faces, state=st, rho=rho, mu=mu)
+    R = -d.reshape(8, 4)
+    ref = (rho * w0 * w0[0] + np.array([-0.6, 0.0, 0.0])) / 4
+    assert np.abs(R[front, :3] - ref).max() < 1e-15
+    assert np.abs(R[~front]).max() == 0.0 and np.abs(R[:, 3]).max() == 0.0
+    # fix (u^w = 0) of the uniform velocity, p = 0: -mu (n.grad N_a) u + tau rho u; p-rows -u.n
+    st[3] = 0.0
+    _, d = _flow(OB.NS_FIX, pat, faces, state=st, tau=tau, uw=(5.0, 5.0, 5.0), rho=rho, mu=mu)
+    R = -d.reshape(8, 4)
+    assert np.abs(R[front, :3] - (-mu * w0 + tau * rho * w0) / 4).max() < 1e-15
+    assert np.abs(R[~front, :3] - mu * w0 / 4).max() < 1e-15
+    assert np.abs(R[front, 3] + w0[0] / 4).max() < 1e-15 and np.abs(R[~front, 3]).max() == 0.0
+
+
+def test_flow_domain_plus_outflow_is_integration_by_parts():
+    """For linear u and p on an affine box the Galerkin flow form plus the outflow form on
+    every face integrates the strong form against the basis:
+    R_(a,i) = int N_a (rho div(u u)_i + p_,i),  R_(a,p) = int N_a div u,
+    i.e. the mass matrix times the (linear) nodal values of those fields."""
+    n = (2, 3, 2)
+    mesh = box(n, lengths=[1.0, 1.5, 0.8])
+    pat = O.Pattern(mesh, 4)
+    rng = np.random.default_rng(21)
+    A, c, b = rng.normal(size=(3, 3)), rng.normal(size=3), rng.normal(size=3)
+    x = mesh.coords
+    u = A @ x + c[:, None]
+    st = np.vstack([u, b @ x + 0.3])
+    rho, mu = 1.7, 0.4
+    Rd = O.residual(pat, O.NS_SUPG, {"rho": rho, "mu": mu, "tau_m": 0.0, "tau_c": 0.0}, state=st)
+    _, d = _flow(OB.NS_OUTFLOW, pat, W.box_faces(n), state=st, rho=rho, mu=mu)
+    Rt = (Rd - d).reshape(-1, 4)
+    p1 = O.Pattern(mesh, 1)
+    M = p1.to_scipy(O.assemble(p1, O.MASS, {"coef": 1.0})[0])
+    f = rho * (A @ u + u * np.trace(A)) + b[:, None]
+    for i in range(3):
+        assert np.abs(Rt[:, i] - M @ f[i]).max() < 1e-13
+    assert np.abs(Rt[:, 3] - M @ np.full(mesh.n_nodes, np.trace(A))).max() < 1e-13
+
+
+def _flow_case(seed):
+    n = (2, 2, 3)
+    mesh = box(n, jitter=0.2, seed=seed)
+    pat = O.Pattern(mesh, 4)
+    rng = np.random.default_rng(seed)
+    st = rng.uniform(-1, 1, (4, mesh.n_nodes))
+    tg = rng.uniform(-1, 1, (4, mesh.n_nodes))
+    return n, mesh, pat, st, tg
+
+
+def test_inflow_with_its_own_state_is_outflow():
+    n, mesh, pat, st, _ = _flow_case(3)
+    faces = W.box_faces(n, sides=[0, 3, 5])
+    K1, d1 = _flow(OB.NS_INFLOW, pat, faces, state=st, target=st, tau=3.0, rho=1.1, mu=0.2)
+    K2, d2 = _flow(OB.NS_OUTFLOW, pat, faces, state=st, rho=1.1, mu=0.2)
+    assert np.abs(d1 - d2).max() < 1e-14
+    assert abs(K1 - K2).max() > 1e-3  # the tangents differ: inflow holds u^w fixed
+
+
+@pytest.mark.parametrize("kind", [OB.NS_INFLOW, OB.NS_OUTFLOW, OB.NS_FIX])
+def test_flow_tangent_by_central_differences(kind):
+    n, mesh, pat, st, tg = _flow_case(5)
+    faces = W.box_faces(n)
+    args = dict(target=tg, tau=2.5, rho=1.2, mu=0.3)
+    K, d0 = _flow(kind, pat, faces, state=st, **args)
+    rng = np.random.default_rng(6)
+    dv = rng.normal(size=st.shape)
+    h = 1e-6
+    _, dp = _flow(kind, pat, faces, state=st + h * dv, **args)
+    _, dm = _flow(kind, pat, faces, state=st - h * dv, **args)
+    dirn = dv.T.reshape(-1)  # node-major DOF order
+    fd = -(dp - dm) / (2 * h)
+    assert np.abs(K @ dirn - fd).max() < 1e-7 * max(1.0, np.abs(fd).max())
+
+
+def test_fix_pressure_velocity_blocks_are_antisymmetric():
+    n, mesh, pat, st, _ = _flow_case(7)
+    K, _ = _flow(OB.NS_FIX, pat, W.box_faces(n), state=st, tau=1.0, rho=1.0, mu=0.1)
+    K = K.toarray()
+    dof = np.arange(pat.n_rows)
+    up = np.ix_(dof % 4 < 3, dof % 4 == 3)
+    pu = np.ix_(dof % 4 == 3, dof % 4 < 3)
+    assert np.abs(K[up]).max() > 0.1
+    assert np.abs(K[up] + K[pu].T).max() < 1e-15
