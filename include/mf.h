@@ -256,23 +256,35 @@ mf_status mf_heat_transient(const mf_pattern_t* P, double capacity, double condu
 /* ------------------------------------------------------------------------------------
  * Boundary forms: the physics one dimension lower (Sec. 2.2, opening of the algorithm),
  * integrated over element faces with the 2x2 Gauss rule of the face and added into an
- * assembled K and d.  Forms of Sec. 4.1 (thermal) and Sec. 4.2 (elasticity), with the
- * sign reading of the domain forms (R = -d_paper, K = dR/dU, d = -R(U)):
+ * assembled K and d.  Forms of Sec. 4.1 (thermal), Sec. 4.2 (elasticity) and Sec. 4.3
+ * (flow), with the sign reading of the domain forms (R = -d_paper for the thermal and
+ * elastic forms, R = +d_paper for the flow; K = dR/dU, d = -R(U)):
  *   MF_BFORM_PENALTY     R_(a,i) = int coef N_a (u_i - g_i)          fix (1 or 3 fields)
  *   MF_BFORM_CONVECTION  R_a     = int coef N_a (T - T_env)           coef = h   (1 field)
  *   MF_BFORM_RADIATION   R_a     = int coef N_a (T^4 - T_env^4)       coef = e_m sigma^b
  *   MF_BFORM_FLUX        R_a     = - int coef N_a n . grad T          coef = k: the flux
  *                        term of the thermal fix condition (grad T of the face's element)
  *   MF_BFORM_TRACTION    R_(a,i) = - int N_a sigma^l_ij n_j           load (3 fields)
- * g / T_env come from `target` ([nf][n_nodes] nodal values, interpolated) when given,
- * else from value[0..nf); sigma^l is value[0..9) row-major; n is the outward unit normal.
+ * Flow (4 fields u_0, u_1, u_2, p; coef = tau^b, value[3] = rho, value[4] = mu), every
+ * kind with the base term R_(a,i) += int N_a (p n_i - mu u_i,j n_j):
+ *   MF_BFORM_NS_INFLOW   R_(a,i) += int rho N_a u^w_i (u^w . n) + mu (n . grad N_a)(u^w_i - u_i)
+ *                                   + tau^b rho N_a (u_i - u^w_i);  R_(a,p) += int N_a (u^w - u) . n
+ *   MF_BFORM_NS_OUTFLOW  R_(a,i) += int rho N_a u_i (u . n)
+ *   MF_BFORM_NS_FIX      the inflow form with u^w = 0
+ *   (grad N_a is the gradient of the face's element, so all 8 of its nodes get rows.)
+ * g / T_env / u^w come from `target` ([nf][n_nodes] nodal values, interpolated; rows
+ * 0..2 for u^w) when given, else from value[0..nf) (value[0..3) for u^w); sigma^l is
+ * value[0..9) row-major; n is the outward unit normal.
  * ------------------------------------------------------------------------------------ */
 typedef enum {
     MF_BFORM_PENALTY = 0,
     MF_BFORM_CONVECTION = 1,
     MF_BFORM_RADIATION = 2,
     MF_BFORM_FLUX = 3,
-    MF_BFORM_TRACTION = 4
+    MF_BFORM_TRACTION = 4,
+    MF_BFORM_NS_INFLOW = 5,
+    MF_BFORM_NS_OUTFLOW = 6,
+    MF_BFORM_NS_FIX = 7
 } mf_bform_kind;
 
 typedef struct {
@@ -287,7 +299,7 @@ typedef struct {
  * Dirichlet mask there (boundary forms replace the elimination).  Faces: face_elem
  * [n_faces] element ids and face_id [n_faces] local faces 2 * axis + side (side 1: the
  * face at xi_axis = +1), device arrays.  state [nf][n_nodes] (device, precision prec, or
- * NULL = 0) is the linearisation point of the radiation, flux and penalty residuals.
+ * NULL = 0) is the linearisation point of the radiation, flux, penalty and flow residuals.
  * P must be a 3D hex pattern with full coupling.  Async on the stream.  Reported by
  * mf_status_poll (until the next mf_assemble clears the status): a face whose element id
  * or local face is out of range (skipped; MF_ERR_ARG with the first such face), and a

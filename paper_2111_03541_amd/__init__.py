@@ -80,7 +80,8 @@ PRECOND_NONE, PRECOND_JACOBI, PRECOND_NN = 0, 1, 2
 
 NEWTON_MAX_HISTORY = 64
 
-BFORM_PENALTY, BFORM_CONVECTION, BFORM_RADIATION, BFORM_FLUX, BFORM_TRACTION = range(5)
+BFORM_PENALTY, BFORM_CONVECTION, BFORM_RADIATION, BFORM_FLUX, BFORM_TRACTION, BFORM_NS_INFLOW, \
+    BFORM_NS_OUTFLOW, BFORM_NS_FIX = range(8)
 
 
 class _TransientOpts(C.Structure):
@@ -291,8 +292,8 @@ class Pattern:
                           target=None, K=None, d=None, precision: int = F64, stream=None):
         """Add the face integrals of a boundary form into K and d (zeros when not given).
 
-        face_elem int32 / face_id uint8 CUDA tensors; value: up to 9 constants (g, T_env or
-        the load stress sigma^l row-major)."""
+        face_elem int32 / face_id uint8 CUDA tensors; value: up to 9 constants (g, T_env,
+        the load stress sigma^l row-major, or for the flow forms u^w, rho, mu)."""
         import torch
         lib = load()
         dt = torch.float64 if precision == F64 else torch.float32

@@ -1,10 +1,13 @@
 // Boundary forms: the physics one dimension lower (Sec. 2.2 opening of the algorithm),
 // integrated over element faces and added into an assembled K and d.  The forms are the
-// ones of Sec. 4.1 (convection, radiation, penalty fix with its flux term) and Sec. 4.2
-// (load traction, penalty fix), with the sign reading of the domain forms: R = -d_paper
-// for the thermal and elastic physics, K = dR/dU, exported d = -R(U).
+// ones of Sec. 4.1 (convection, radiation, penalty fix with its flux term), Sec. 4.2
+// (load traction, penalty fix) and Sec. 4.3 (flow inflow, outflow and fix), with the sign
+// reading of the domain forms: R = -d_paper for the thermal and elastic physics,
+// R = +d_paper for the flow, K = dR/dU, exported d = -R(U).
 //
-// One thread per (face f, face node k, field i): the thread gathers the 8 nodes of the
+// One thread per (face f, row node k, field i); the row nodes are the four face nodes,
+// and for the flow forms, whose inflow and fix terms carry the test gradient, all eight
+// nodes of the face's element.  The thread gathers the 8 nodes of the
 // face's element, evaluates the 2x2 Gauss rule on the face (xi_axis = -1 or +1) with the
 // element's trilinear map in FP64 (surface measure |t_u x t_v|, outward unit normal, and
 // for the flux term the volume gradients J^-T grad_xi N_b), accumulates row (a, i) of the
@@ -44,11 +47,36 @@ struct BParams {
 
 __device__ __forceinline__ double lin1(int s, double xi) { return 0.5 * (1.0 + (s ? xi : -xi)); }
 
+// (J^-1)[n][m] = dxi_n / dx_m by cofactors; false when det J <= 0
+__device__ __forceinline__ bool inverse_jacobian(const double (&J)[3][3], double (&Ji)[3][3])
+{
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    if (!(det > 0.0)) return false;
+    const double r = 1.0 / det;
+    Ji[0][0] = c00 * r;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+    Ji[1][0] = c01 * r;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+    Ji[2][0] = c02 * r;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+    return true;
+}
+
+// row nodes per face: the flow forms (four fields) take every node of the element
+template <int NF>
+constexpr int kRowNodes = NF == 4 ? 8 : 4;
+
 template <int NF, typename T>
 __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= p.n_faces * 4 * NF) return;
+    if (t >= p.n_faces * kRowNodes<NF> * NF) return;
     const int64_t f = t % p.n_faces;
     const int ki = (int)(t / p.n_faces);
     const int kf = ki / NF, i = ki % NF;
@@ -62,7 +90,7 @@ __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
     const int u = (axis + 1) % 3, v = (axis + 2) % 3;
     // element-local node of face node k: bit axis = side, bits u, v from k
     auto fnode = [&](int k) { return (side << axis) | ((k & 1) << u) | ((k >> 1) << v); };
-    const int a = fnode(kf);
+    const int a = NF == 4 ? kf : fnode(kf);
 
     int32_t node[8];
     double x[8][3];
@@ -134,7 +162,59 @@ __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
                 gq[j] = fma(N[b], G[b][j], gq[j]);
             }
         }
-        if (kind == MF_BFORM_PENALTY || kind == MF_BFORM_CONVECTION) {
+        if constexpr (NF == 4) {
+            // flow forms (value: u^w [0..3), rho [3], mu [4]; coef = tau^b)
+            double Ji[3][3];
+            if (!inverse_jacobian(J, Ji)) {
+                atomicMin(p.status, (unsigned long long)e);
+                return;
+            }
+            double gn[8];  // n . grad N_b
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                gn[b] = 0.0;
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    gn[b] += nv[m] * (Ji[0][m] * dN[b][0] + Ji[1][m] * dN[b][1] + Ji[2][m] * dN[b][2]);
+            }
+            const double rho = p.form.value[3], mu = p.form.value[4], tau = c;
+            const bool wall = kind != MF_BFORM_NS_OUTFLOW;
+            double uw[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) uw[m] = kind == MF_BFORM_NS_INFLOW ? gq[m] : 0.0;
+            const double un = uq[0] * nv[0] + uq[1] * nv[1] + uq[2] * nv[2];
+            if (i < 3) {
+                // base: p n_i - mu u_i,j n_j
+                double gu = 0.0;
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    gu = fma(gn[b], U[b][i], gu);
+                    krow[b][3] += w * Na * nv[i] * N[b];
+                    krow[b][i] -= w * mu * Na * gn[b];
+                }
+                rrow += w * Na * (uq[3] * nv[i] - mu * gu);
+                if (wall) {
+                    const double uwn = uw[0] * nv[0] + uw[1] * nv[1] + uw[2] * nv[2];
+                    rrow += w * (rho * Na * uw[i] * uwn + mu * gn[a] * (uw[i] - uq[i]) +
+                                 tau * rho * Na * (uq[i] - uw[i]));
+#pragma unroll
+                    for (int b = 0; b < 8; ++b) krow[b][i] += w * (tau * rho * Na - mu * gn[a]) * N[b];
+                } else {
+                    rrow += w * rho * Na * uq[i] * un;
+#pragma unroll
+                    for (int b = 0; b < 8; ++b)
+#pragma unroll
+                        for (int k = 0; k < 3; ++k)
+                            krow[b][k] += w * rho * Na * N[b] * ((k == i ? un : 0.0) + uq[i] * nv[k]);
+                }
+            } else if (wall) {
+                rrow += w * Na * ((uw[0] - uq[0]) * nv[0] + (uw[1] - uq[1]) * nv[1] + (uw[2] - uq[2]) * nv[2]);
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) krow[b][k] -= w * Na * N[b] * nv[k];
+            }
+        } else if (kind == MF_BFORM_PENALTY || kind == MF_BFORM_CONVECTION) {
             // R = int c N_a (u_i - g_i)
 #pragma unroll
             for (int b = 0; b < 8; ++b) krow[b][i] += c * w * Na * N[b];
@@ -151,25 +231,11 @@ __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
             const double ti = S[3 * i] * nv[0] + S[3 * i + 1] * nv[1] + S[3 * i + 2] * nv[2];
             rrow -= w * Na * ti;
         } else {  // MF_BFORM_FLUX: R = -int c N_a n . grad T
-            const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-            const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-            const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-            const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-            if (!(det > 0.0)) {
+            double Ji[3][3];
+            if (!inverse_jacobian(J, Ji)) {
                 atomicMin(p.status, (unsigned long long)e);
                 return;
             }
-            double Ji[3][3];  // (J^-1)[n][m] = dxi_n / dx_m
-            const double r = 1.0 / det;
-            Ji[0][0] = c00 * r;
-            Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
-            Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
-            Ji[1][0] = c01 * r;
-            Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
-            Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
-            Ji[2][0] = c02 * r;
-            Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
-            Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
             double ngT = 0.0;
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
@@ -209,8 +275,9 @@ __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
 template <int NF, typename T>
 mf_status launch_boundary(const BParams& p, hipStream_t s)
 {
-    const int64_t n = p.n_faces * 4 * NF;
+    const int64_t n = p.n_faces * kRowNodes<NF> * NF;
     if (n == 0) return MF_OK;
+    if (n > 0xffffffffLL - kThreads) return set_error(MF_ERR_ARG, "too many faces for one launch");
     k_boundary<NF, T><<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(p);
     MF_HIP(hipGetLastError());
     return MF_OK;
@@ -247,6 +314,11 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
             if (nf != 3) return set_error(MF_ERR_ARG, "traction needs 3 fields, pattern has %d", nf);
             if (target) return set_error(MF_ERR_ARG, "traction takes its load from form->value, not a target");
             break;
+        case MF_BFORM_NS_INFLOW:
+        case MF_BFORM_NS_OUTFLOW:
+        case MF_BFORM_NS_FIX:
+            if (nf != 4) return set_error(MF_ERR_ARG, "flow boundary forms need 4 fields, pattern has %d", nf);
+            break;
         default: return set_error(MF_ERR_ARG, "unknown boundary form %d", (int)form->kind);
     }
     hipStream_t s = (hipStream_t)stream;
@@ -269,6 +341,10 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
     p.d = d;
     p.status = P->status;
     const_cast<mf_pattern_s*>(P)->last_stream = s;
-    if (prec == MF_F64) return nf == 1 ? launch_boundary<1, double>(p, s) : launch_boundary<3, double>(p, s);
+    if (prec == MF_F64) {
+        if (nf == 4) return launch_boundary<4, double>(p, s);
+        return nf == 1 ? launch_boundary<1, double>(p, s) : launch_boundary<3, double>(p, s);
+    }
+    if (nf == 4) return launch_boundary<4, float>(p, s);
     return nf == 1 ? launch_boundary<1, float>(p, s) : launch_boundary<3, float>(p, s);
 }

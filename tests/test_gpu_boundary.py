@@ -28,6 +28,11 @@ CASES = [  # (name, kind, nf, coef, value, uses state, uses target)
     ("radiation", OB.RADIATION, 1, 0.8, [1.3], True, False),
     ("flux", OB.FLUX, 1, 1.7, [0.0], True, False),
     ("traction", OB.TRACTION, 3, 1.0, S_LOAD, False, False),
+    # flow forms: coef = tau^b, value = (u^w, rho, mu)
+    ("ns_inflow", OB.NS_INFLOW, 4, 2.5, [0.4, -0.3, 0.2, 1.2, 0.05], True, False),
+    ("ns_inflow_target", OB.NS_INFLOW, 4, 2.5, [0.0, 0.0, 0.0, 1.2, 0.05], True, True),
+    ("ns_outflow", OB.NS_OUTFLOW, 4, 0.0, [0.0, 0.0, 0.0, 1.2, 0.05], True, False),
+    ("ns_fix", OB.NS_FIX, 4, 2.5, [0.0, 0.0, 0.0, 1.2, 0.05], True, False),
 ]
 
 
@@ -111,6 +116,79 @@ def test_boundary_argument_errors(mf):
     pat.assemble(mf.Form(mf.POISSON), coords)
     with pytest.raises(mf.MFError):  # traction needs 3 fields
         pat.assemble_boundary(mf.BFORM_TRACTION, coords, fe, torch.tensor([0, 1], dtype=torch.uint8, device=dev))
+    with pytest.raises(mf.MFError):  # the flow forms need 4 fields
+        pat.assemble_boundary(mf.BFORM_NS_OUTFLOW, coords, fe, torch.tensor([0, 1], dtype=torch.uint8, device=dev))
     # an empty face list adds nothing
     K, d = pat.assemble_boundary(mf.BFORM_PENALTY, coords, fe[:0], torch.zeros(0, dtype=torch.uint8, device=dev))
     assert float(K.abs().max()) == 0.0 and float(d.abs().max()) == 0.0
+
+
+
+def _pin_positions(rp, ci, r):
+    """Positions in a CSR value array of row r and column r, and of their diagonal entry
+    (host arrays): replacing that row and column by the identity fixes the pressure level,
+    which the flow form with boundary terms on every face leaves free."""
+    lo, hi = int(rp[r]), int(rp[r + 1])
+    pos = np.union1d(np.nonzero(ci == r)[0], np.arange(lo, hi))
+    return torch.from_numpy(pos), lo + int(np.nonzero(ci[lo:hi] == r)[0][0])
+
+
+def test_cavity_newton_with_weak_boundaries(mf):
+    """Lid-driven cavity whose walls (fix) and lid (inflow with a tangential u^w) are all
+    weak boundary forms (Sec. 4.3): Newton steps with domain and faces assembled and the
+    non-symmetric system solved on the GPU.  The residual falls quadratically and the
+    result matches the oracle's Newton iteration with direct solves."""
+    import scipy.sparse.linalg as spla
+    say("cavity newton, weak boundaries")
+    n = (6, 6, 6)
+    mesh = W.structured_mesh(n, jitter=0.1, seed=12)
+    rho, mu, tau_b = 1.0, 0.05, 10.0
+    params = {"rho": rho, "mu": mu, "tau_m": 0.02, "tau_c": 0.05}
+    sets = [(OB.NS_INFLOW, W.box_faces(n, sides=[5]), [1.0, 0.0, 0.0, rho, mu]),
+            (OB.NS_FIX, W.box_faces(n, sides=[0, 1, 2, 3, 4]), [0.0, 0.0, 0.0, rho, mu])]
+    steps = 5
+    # oracle
+    opat = O.Pattern(mesh, 4)
+    sr = np.zeros((4, mesh.n_nodes))
+    for _ in range(steps):
+        Kr, dr = O.assemble(opat, O.NS_SUPG, params, state=sr)
+        Kr = opat.to_scipy(Kr)
+        for kind, faces, value in sets:
+            Kb, db = OB.assemble_boundary(opat, kind, tau_b, value, *faces, state=sr)
+            Kr, dr = Kr + Kb, dr + db
+        Kr = Kr.tolil()
+        Kr[3, :] = 0.0
+        Kr[:, 3] = 0.0
+        Kr[3, 3] = 1.0
+        dr[3] = 0.0
+        sr = sr + spla.spsolve(Kr.tocsr().tocsc(), dr).reshape(-1, 4).T
+    # GPU
+    dev = torch.device("cuda:0")
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 4)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    rp, ci, _ = pat.device_arrays()
+    pin, diag = _pin_positions(*pat.arrays()[:2], 3)
+    pin = pin.to(dev)
+    faces = [(kind, torch.from_numpy(fe).to(dev), torch.from_numpy(fi).to(dev), value)
+             for kind, (fe, fi), value in sets]
+    st = torch.zeros((4, mesh.n_nodes), dtype=torch.float64, device=dev)
+    norms = []
+    for _ in range(steps):
+        K, d = pat.assemble(mf.Form(mf.NS_SUPG, **params), coords, precision=mf.F64, lin_state=st)
+        for kind, fe, fi, value in faces:
+            pat.assemble_boundary(kind, coords, fe, fi, coef=tau_b, value=value, state=st, K=K, d=d)
+        assert pat.status()[0] == mf.OK
+        K[pin] = 0.0
+        K[diag] = 1.0
+        d[3] = 0.0
+        norms.append(float(d.abs().max()))
+        x, res = mf.bicgstab(rp, ci, K, d, tol=1e-12)
+        assert res["converged"], res
+        st += x.view(-1, 4).T
+    say(f"  |d| per step {norms}")
+    # quadratic: |d_k+1| <= C |d_k|^2 (the oracle's run has C < 1)
+    assert all(norms[k + 1] <= 2.0 * norms[k] ** 2 for k in range(1, 3)) and norms[4] < 1e-15 * norms[0]
+    sg = st.cpu().numpy()
+    assert np.abs(sg - sr).max() < 1e-8 * np.abs(sr).max()
+    # recirculation under the lid: the axial velocity changes sign
+    assert sg[0].min() < -0.1 and sg[0][np.abs(mesh.coords[2] - 1.0) < 1e-12].mean() > 0.5
