@@ -12,7 +12,8 @@ R = -d_paper, K = dR/dU, exported d = -R(U):
   penalty / convection  R_(a,i) = int coef N_a (u_i - g_i)
   radiation             R_a     = int coef N_a (T^4 - T_env^4)
   flux                  R_a     = - int coef N_a n . grad T   (grad T of the face's element)
-  traction              R_(a,i) = - int N_a sigma^l_ij n_j
+  traction              R_(a,i) = - int N_a sigma^l_ij n_j, or - int N_a t_i with a nodal
+                        traction t given as the target
 
 and the flow boundaries of Sec. 4.3 with the flow form's reading R = +d_paper (fields
 u_0, u_1, u_2, p; coef = tau^b, value[0..3) = u^w unless a target gives it per node,
@@ -103,8 +104,8 @@ def assemble_boundary(pat, kind, coef, value, face_elem, face_id, state=None, ta
                             Ke[a, 0, :, 0] += coef * w * N[a] * 4.0 * uq[0] ** 3 * N
                             Re[a, 0] += coef * w * N[a] * (uq[0] ** 4 - gq[0] ** 4)
                         elif kind == TRACTION:
-                            S = value.reshape(3, 3)
-                            Re[a, i] -= w * N[a] * (S[i] @ n)
+                            t = gq if target is not None else value.reshape(3, 3) @ n
+                            Re[a, i] -= w * N[a] * t[i]
                         elif kind == FLUX:
                             grad = np.linalg.solve(J.T, dN.T).T  # rows: grad N_b = J^-T grad_xi N_b
                             ng = grad @ n

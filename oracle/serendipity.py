@@ -15,7 +15,8 @@ Forms as the Q1 oracle defines them at the zero state (Sec. 4.1, 4.2; K = dR/dU,
   conduction  K = int c grad N_a . grad N_b,            d = int N_a f
   elasticity  K = int lam g_ai g_bj + mu g_aj g_bi + mu delta_ij g_a . g_b,  d = int N_a b_i
 with c = coef * elem_param and lam, mu from E = coef * elem_param and nu.  The pattern
-is built by brute force: N(v) = sorted nodes sharing an element with v.
+is built by brute force: N(v) = sorted nodes sharing an element with v.  Boundary forms on
+the element faces (8 nodes, 3x3 face rule): assemble_boundary20.
 """
 from __future__ import annotations
 
@@ -153,4 +154,89 @@ def assemble20(pat: Pattern20, kind, params=None, elem_param=None, nodal_src=Non
     S.sum_duplicates()
     rr = np.repeat(np.arange(pat.n_rows), np.diff(pat.row_ptr))
     K = np.asarray(S[rr, pat.col_idx]).ravel()
+    return K, d
+
+
+def ref_nodes20():
+    """Reference coordinates [20][3] of the local nodes."""
+    X = np.zeros((20, 3))
+    X[:8] = CORNER
+    for m, (ax, (s1, s2)) in enumerate(EDGES):
+        oth = sorted(((ax + 1) % 3, (ax + 2) % 3))
+        X[8 + m, oth[0]], X[8 + m, oth[1]] = s1, s2
+    return X
+
+
+def assemble_boundary20(pat: Pattern20, kind, coef, value, face_elem, face_id, state=None, target=None):
+    """Boundary forms on faces of 20-node hexahedra: (scipy CSR [n_rows x n_rows], d).
+
+    The forms and sign of the Q1 oracle (oracle/boundary.py; Sec. 2.2 opening, Sec. 4.1,
+    4.2), R = -d_paper, K = dR/dU, d = -R:
+      penalty / convection  R_(a,i) = int coef N_a (u_i - g_i)
+      radiation             R_a     = int coef N_a (T^4 - T_env^4)
+      traction              R_(a,i) = - int N_a t_i,  t = sigma^l n, or the nodal traction
+                            `target` interpolated with the basis
+    Face (axis, side) is xi_axis = -1 or +1 with its eight nodes; the face rule is 3x3
+    Gauss in the two other reference coordinates, dS = |t_u x t_v|, n = (t_u x t_v)/dS
+    signed by the side.
+    """
+    import scipy.sparse as sp
+    from .boundary import CONVECTION, PENALTY, RADIATION, TRACTION
+    mesh, nf = pat.mesh, pat.nf
+    value = np.asarray(value, dtype=np.float64)
+    p1, w1 = gauss3()[0][:3, 0], np.array([5.0, 8.0, 5.0]) / 9.0
+    R0 = ref_nodes20()
+    rows, cols, vals = [], [], []
+    d = np.zeros(pat.n_rows)
+    for e, fid in zip(np.asarray(face_elem), np.asarray(face_id)):
+        e, fid = int(e), int(fid)
+        axis, side = fid >> 1, fid & 1
+        u, v = (axis + 1) % 3, (axis + 2) % 3
+        nodes = mesh.conn[:, e]
+        X = mesh.coords[:, nodes].T
+        U = state[:, nodes].T if state is not None else np.zeros((20, nf))
+        if target is not None:
+            G = np.asarray(target)[:, nodes].T
+        else:
+            G = np.tile(value[:nf], (20, 1))
+        Ke = np.zeros((20, nf, 20, nf))
+        Re = np.zeros((20, nf))
+        for jv in range(3):
+            for ju in range(3):
+                xi = np.zeros(3)
+                xi[axis] = 1.0 if side else -1.0
+                xi[u], xi[v] = p1[ju], p1[jv]
+                N, dN = basis20(xi)
+                J = X.T @ dN
+                nr = (1.0 if side else -1.0) * np.cross(J[:, u], J[:, v])
+                dS = np.linalg.norm(nr)
+                n = nr / dS
+                w = w1[ju] * w1[jv] * dS
+                uq, gq = N @ U, N @ G
+                for i in range(nf):
+                    if kind in (PENALTY, CONVECTION):
+                        Ke[:, i, :, i] += coef * w * np.outer(N, N)
+                        Re[:, i] += coef * w * N * (uq[i] - gq[i])
+                    elif kind == RADIATION:
+                        Ke[:, 0, :, 0] += coef * w * 4.0 * uq[0] ** 3 * np.outer(N, N)
+                        Re[:, 0] += coef * w * N * (uq[0] ** 4 - gq[0] ** 4)
+                    elif kind == TRACTION:
+                        t = gq if target is not None else value.reshape(3, 3) @ n
+                        Re[:, i] -= w * N * t[i]
+                    else:
+                        raise ValueError(kind)
+        on_face = R0[:, axis] == (1.0 if side else -1.0)
+        for a in np.nonzero(on_face)[0]:
+            for i in range(nf):
+                r = pat.dof(nodes[a], i)
+                d[r] -= Re[a, i]
+                for b in np.nonzero(on_face)[0]:
+                    for j in range(nf):
+                        if Ke[a, i, b, j] != 0.0:
+                            rows.append(r)
+                            cols.append(pat.dof(nodes[b], j))
+                            vals.append(Ke[a, i, b, j])
+        # the basis of the other twelve nodes vanishes on the face
+        assert np.abs(Re[~on_face]).max(initial=0.0) < 1e-13 * max(1.0, np.abs(Re).max())
+    K = sp.coo_matrix((vals, (rows, cols)), shape=(pat.n_rows, pat.n_rows)).tocsr()
     return K, d

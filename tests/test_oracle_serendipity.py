@@ -1,6 +1,8 @@
 """Oracle pins for 20-node serendipity hexahedra (oracle/serendipity.py): basis identities,
-exact volume, patch tests for linear and quadratic fields, rigid-body modes."""
+exact volume, patch tests for linear and quadratic fields, rigid-body modes, face loads,
+and the paper's cantilever against beam theory."""
 import numpy as np
+import pytest
 
 import oracle as O
 import oracle.serendipity as S
@@ -91,3 +93,118 @@ def test_elasticity_rigid_body_modes():
     for m in modes:
         u = np.stack(m, axis=1).reshape(-1)  # node-major
         assert np.abs(Km @ u).max() < 1e-12 * abs(Km).max()
+
+
+# ---------------------------------------------------------------- faces (boundary forms)
+
+def test_face_loads_of_the_eight_node_face():
+    """A uniform traction on a flat 8-node serendipity face loads its corners with -1/12
+    and its mid-side nodes with 1/3 of the total (the classic consistent loads)."""
+    import oracle.boundary as OB
+    mesh = W.serendipity_mesh((1, 1, 1), lengths=[2.0, 1.5, 1.0])
+    pat = S.Pattern20(mesh, 3)
+    sig = np.zeros((3, 3))
+    sig[:, 2] = [0.4, -0.7, 1.3]  # t = sigma^l e_z on the top face
+    K, d = S.assemble_boundary20(pat, OB.TRACTION, 1.0, sig.reshape(-1), [0], [5])
+    F = d.reshape(-1, 3)
+    area = 2.0 * 1.5
+    top = np.nonzero(np.abs(mesh.coords[2] - 1.0) < 1e-12)[0]
+    corner = [v for v in top if v in set(mesh.conn[:8, 0])]
+    mid = [v for v in top if v not in corner]
+    assert len(corner) == 4 and len(mid) == 4
+    assert np.abs(F[corner] + area / 12 * sig[:, 2]).max() < 1e-14
+    assert np.abs(F[mid] - area / 3 * sig[:, 2]).max() < 1e-14
+    assert np.abs(np.delete(F, top, axis=0)).max() == 0.0
+    # the same load as a nodal traction target
+    tg = np.tile(sig[:, 2][:, None], (1, mesh.n_nodes))
+    _, d2 = S.assemble_boundary20(pat, OB.TRACTION, 1.0, [], [0], [5], target=tg)
+    assert np.abs(d2 - d).max() < 1e-15
+
+
+def test_face_mass_and_closed_surface_load():
+    import oracle.boundary as OB
+    n, L = (2, 3, 2), [1.0, 1.5, 0.8]
+    mesh = W.serendipity_mesh(n, jitter=0.2, seed=4, lengths=L)
+    fe, fi = W.box_faces(n)
+    pat = S.Pattern20(mesh, 1)
+    K, _ = S.assemble_boundary20(pat, OB.PENALTY, 1.0, [0.0], fe, fi)
+    area = 2 * (L[0] * L[1] + L[1] * L[2] + L[0] * L[2])
+    assert abs(K.sum() - area) < 1e-12 * area
+    pat3 = S.Pattern20(mesh, 3)
+    sig = np.array([[0.3, -0.2, 0.7], [0.1, 0.5, -0.4], [0.6, 0.2, -1.1]])
+    _, d = S.assemble_boundary20(pat3, OB.TRACTION, 1.0, sig.reshape(-1), fe, fi)
+    assert np.abs(d.reshape(-1, 3).sum(axis=0)).max() < 1e-14
+    fe1, fi1 = W.box_faces(n, sides=[3])  # y = L_y, n = +y, area L_x L_z
+    _, d = S.assemble_boundary20(pat3, OB.TRACTION, 1.0, sig.reshape(-1), fe1, fi1)
+    assert np.abs(d.reshape(-1, 3).sum(axis=0) - sig[:, 1] * L[0] * L[2]).max() < 1e-14
+
+
+def test_radiation_tangent_on_quadratic_faces():
+    import oracle.boundary as OB
+    n = (2, 1, 2)
+    mesh = W.serendipity_mesh(n, jitter=0.2, seed=6)
+    pat = S.Pattern20(mesh, 1)
+    fe, fi = W.box_faces(n)
+    T = 1.0 + np.random.default_rng(2).random((1, mesh.n_nodes))
+    K, d0 = S.assemble_boundary20(pat, OB.RADIATION, 0.7, [1.2], fe, fi, state=T)
+    dv = np.random.default_rng(3).normal(size=T.shape)
+    h = 1e-6
+    _, dp = S.assemble_boundary20(pat, OB.RADIATION, 0.7, [1.2], fe, fi, state=T + h * dv)
+    _, dm = S.assemble_boundary20(pat, OB.RADIATION, 0.7, [1.2], fe, fi, state=T - h * dv)
+    assert np.abs(K @ dv[0] + (dp - dm) / (2 * h)).max() < 1e-7
+
+
+def cantilever(case, mesh, P=1.0):
+    """The paper's 3D cantilever (Sec. 4.2): L = 10, h = 1, E = 1, nu = 0, the face x = 0
+    clamped; case 1 end load P (uniform shear traction on x = L), case 2 uniform pressure P
+    on the top face y = h, case 3 pressure P (1 - x/L) on the top.  Returns the oracle's
+    displacement [n_nodes][3] (direct solve)."""
+    import scipy.sparse.linalg as spla
+    import oracle.boundary as OB
+    n = (10, 4, 4)
+    pat = S.Pattern20(mesh, 3)
+    Kv, _ = S.assemble20(pat, O.ELASTICITY, {"coef": 1.0, "nu": 0.0})
+    K = pat.to_scipy(Kv)
+    if case == 1:
+        sig = np.zeros((3, 3))
+        sig[1, 0] = -P  # t = sigma^l e_x = (0, -P, 0) over the unit end face
+        _, d = S.assemble_boundary20(pat, OB.TRACTION, 1.0, sig.reshape(-1), *W.box_faces(n, sides=[1]))
+    else:
+        t = np.zeros((3, mesh.n_nodes))
+        t[1] = -P * (1.0 if case == 2 else 1.0 - mesh.coords[0] / 10.0)
+        _, d = S.assemble_boundary20(pat, OB.TRACTION, 1.0, [], *W.box_faces(n, sides=[3]), target=t)
+    fixed = np.repeat(np.abs(mesh.coords[0]) < 1e-12, 3)
+    free = ~fixed
+    u = np.zeros(pat.n_rows)
+    u[free] = spla.spsolve(K[free][:, free].tocsc(), d[free])
+    return u.reshape(-1, 3)
+
+
+def beam_deflection(case, x, P=1.0, L=10.0):
+    """Euler-Bernoulli deflections of the three load cases (E = 1, I = h^4/12, h = 1)."""
+    EI = 1.0 / 12.0
+    if case == 1:
+        return -P * x ** 2 / (6 * EI) * (3 * L - x)
+    if case == 2:
+        return -P * x ** 2 / (24 * EI) * (6 * L ** 2 - 4 * L * x + x ** 2)
+    return -P * x ** 2 / (120 * L * EI) * (10 * L ** 3 - 10 * L ** 2 * x + 5 * L * x ** 2 - x ** 3)
+
+
+@pytest.mark.parametrize("case", [1, 2, 3])
+def test_cantilever_matches_beam_theory(case):
+    """10 x 4 x 4 quadratic serendipity bricks against beam theory along the centre line
+    y = z = h/2: within 2% of the tip deflection (shear deformation and the clamped end
+    account for less than that at L/h = 10)."""
+    mesh = W.serendipity_mesh((10, 4, 4), lengths=[10.0, 1.0, 1.0])
+    u = cantilever(case, mesh)
+    c = mesh.coords
+    line = np.nonzero((np.abs(c[1] - 0.5) < 1e-12) & (np.abs(c[2] - 0.5) < 1e-12))[0]
+    x = c[0, line]
+    ref = beam_deflection(case, x)
+    tip = np.abs(ref).max()
+    assert np.abs(u[line, 1] - ref).max() < 0.02 * tip
+    # symmetric about the plane z = h/2: no out-of-plane motion on the line (to rounding);
+    # the end load is also antisymmetric about y = h/2, so the line does not stretch
+    assert np.abs(u[line, 2]).max() < 1e-9 * tip
+    if case == 1:
+        assert np.abs(u[line, 0]).max() < 1e-9 * tip
