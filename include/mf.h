@@ -264,7 +264,8 @@ mf_status mf_heat_transient(const mf_pattern_t* P, double capacity, double condu
  *   MF_BFORM_RADIATION   R_a     = int coef N_a (T^4 - T_env^4)       coef = e_m sigma^b
  *   MF_BFORM_FLUX        R_a     = - int coef N_a n . grad T          coef = k: the flux
  *                        term of the thermal fix condition (grad T of the face's element)
- *   MF_BFORM_TRACTION    R_(a,i) = - int N_a sigma^l_ij n_j           load (3 fields)
+ *   MF_BFORM_TRACTION    R_(a,i) = - int N_a sigma^l_ij n_j           load (3 fields), or
+ *                        - int N_a t_i with a nodal traction t given as `target`
  * Flow (4 fields u_0, u_1, u_2, p; coef = tau^b, value[3] = rho, value[4] = mu), every
  * kind with the base term R_(a,i) += int N_a (p n_i - mu u_i,j n_j):
  *   MF_BFORM_NS_INFLOW   R_(a,i) += int rho N_a u^w_i (u^w . n) + mu (n . grad N_a)(u^w_i - u_i)
@@ -300,7 +301,10 @@ typedef struct {
  * [n_faces] element ids and face_id [n_faces] local faces 2 * axis + side (side 1: the
  * face at xi_axis = +1), device arrays.  state [nf][n_nodes] (device, precision prec, or
  * NULL = 0) is the linearisation point of the radiation, flux, penalty and flow residuals.
- * P must be a 3D hex pattern with full coupling.  Async on the stream.  Reported by
+ * P must be a 3D hex pattern with full coupling: 8-node hexahedra (all forms, 2x2 face
+ * rule) or 20-node hexahedra (penalty, convection, radiation and traction, over the
+ * eight nodes of the face with the 3x3 face rule; MF_ERR_UNSUPPORTED otherwise).
+ * Async on the stream.  Reported by
  * mf_status_poll (until the next mf_assemble clears the status): a face whose element id
  * or local face is out of range (skipped; MF_ERR_ARG with the first such face), and a
  * degenerate face (zero area) or element (det J <= 0, flux form; MF_ERR_BAD_JACOBIAN).

@@ -21,6 +21,7 @@
 #include <cmath>
 
 #include "mf_internal.h"
+#include "serendipity.h"
 
 namespace mf {
 namespace {
@@ -28,32 +29,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kNQ = 27;
 constexpr int kQuarters = 4;  // column nodes b split in four groups of five
-
-__device__ __forceinline__ double bit_sign(int b) { return b ? 1.0 : -1.0; }
-
-// Shape functions and reference gradients of node a at xi.
-__device__ __forceinline__ void shape20(int a, const double (&x)[3], double& N, double (&dN)[3])
-{
-    if (a < 8) {
-        const double s[3] = {bit_sign(a & 1), bit_sign((a >> 1) & 1), bit_sign(a >> 2)};
-        const double f[3] = {1.0 + s[0] * x[0], 1.0 + s[1] * x[1], 1.0 + s[2] * x[2]};
-        const double t = s[0] * x[0] + s[1] * x[1] + s[2] * x[2] - 2.0;
-        N = 0.125 * f[0] * f[1] * f[2] * t;
-        dN[0] = 0.125 * s[0] * f[1] * f[2] * (t + f[0]);
-        dN[1] = 0.125 * s[1] * f[0] * f[2] * (t + f[1]);
-        dN[2] = 0.125 * s[2] * f[0] * f[1] * (t + f[2]);
-        return;
-    }
-    const int m = a - 8, ax = m >> 2, k = m & 3;
-    // the two other axes in ascending order carry the signs of bits 0 and 1 of k
-    const int o0 = ax == 0 ? 1 : 0, o1 = ax == 2 ? 1 : 2;
-    const double s0 = bit_sign(k & 1), s1 = bit_sign(k >> 1);
-    const double g = 1.0 - x[ax] * x[ax], h0 = 1.0 + s0 * x[o0], h1 = 1.0 + s1 * x[o1];
-    N = 0.25 * g * h0 * h1;
-    dN[ax] = -0.5 * x[ax] * h0 * h1;
-    dN[o0] = 0.25 * g * s0 * h1;
-    dN[o1] = 0.25 * g * h0 * s1;
-}
 
 __device__ __forceinline__ void gauss_point(int q, double (&x)[3], double& w)
 {

@@ -21,6 +21,7 @@
 
 #include "element.h"
 #include "mf_internal.h"
+#include "serendipity.h"
 
 namespace mf {
 namespace {
@@ -226,9 +227,9 @@ __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
             for (int b = 0; b < 8; ++b) krow[b][0] += c * w * Na * 4.0 * T1 * T1 * T1 * N[b];
             rrow += c * w * Na * (T1 * T1 * T1 * T1 - Te * Te * Te * Te);
         } else if (kind == MF_BFORM_TRACTION) {
-            // R = -int N_a sigma^l_ij n_j
+            // R = -int N_a t_i, t = sigma^l n or the interpolated nodal traction
             const double* S = p.form.value;
-            const double ti = S[3 * i] * nv[0] + S[3 * i + 1] * nv[1] + S[3 * i + 2] * nv[2];
+            const double ti = tg ? gq[i] : S[3 * i] * nv[0] + S[3 * i + 1] * nv[1] + S[3 * i + 2] * nv[2];
             rrow -= w * Na * ti;
         } else {  // MF_BFORM_FLUX: R = -int c N_a n . grad T
             double Ji[3][3];
@@ -272,6 +273,124 @@ __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
     if (rrow != 0.0) unsafeAtomicAdd(d + row, (T)(-rrow));
 }
 
+// Faces of 20-node hexahedra: one thread per (face f, face node k, field i), with the
+// eight nodes of the face (the other twelve basis functions vanish on it, with their
+// tangential derivatives) and the 3x3 Gauss rule of the face; penalty, convection,
+// radiation and traction as above.
+template <int NF, typename T>
+__global__ void __launch_bounds__(kThreads) k_boundary20(BParams p)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p.n_faces * 8 * NF) return;
+    const int64_t f = t % p.n_faces;
+    const int ki = (int)(t / p.n_faces);
+    const int kf = ki / NF, i = ki % NF;
+    const int64_t e = p.face_elem[f];
+    const int fid = p.face_id[f];
+    if (e < 0 || e >= p.n_el || fid > 5) {
+        if (ki == 0) atomicMin(p.status + 1, (unsigned long long)f);
+        return;
+    }
+    const int axis = fid >> 1, side = fid & 1;
+    const int u = (axis + 1) % 3, v = (axis + 2) % 3;
+    int loc[8];  // local ids of the face nodes, ascending
+    for (int a = 0, k = 0; a < 20; ++a)
+        if (on_face20(a, axis, side)) loc[k++] = a;
+    double x[8][3], U[8], G[8];  // coordinates, and field i of the state and target
+    int32_t node[8];
+    const T* st = (const T*)p.state;
+    const T* tg = (const T*)p.target;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        node[b] = p.conn[(int64_t)loc[b] * p.n_el + e];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) x[b][m] = p.coords[(int64_t)m * p.n_nodes + node[b]];
+        U[b] = st ? (double)st[(int64_t)i * p.n_nodes + node[b]] : 0.0;
+        G[b] = tg ? (double)tg[(int64_t)i * p.n_nodes + node[b]] : p.form.value[i];
+    }
+    const mf_bform_kind kind = p.form.kind;
+    const double c = p.form.coef;
+    double krow[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) krow[b] = 0.0;
+    double rrow = 0.0;
+    const double gp = 0.7745966692414834;  // sqrt(3/5)
+    for (int q = 0; q < 9; ++q) {
+        const int qu = q % 3, qv = q / 3;
+        double xi[3];
+        xi[axis] = side ? 1.0 : -1.0;
+        xi[u] = (qu - 1) * gp;
+        xi[v] = (qv - 1) * gp;
+        const double wq = (qu == 1 ? 8.0 : 5.0) * (qv == 1 ? 8.0 : 5.0) / 81.0;
+        double N[8], tu[3] = {0, 0, 0}, tv[3] = {0, 0, 0};
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            double dN[3];
+            shape20(loc[b], xi, N[b], dN);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                tu[m] = fma(x[b][m], dN[u], tu[m]);
+                tv[m] = fma(x[b][m], dN[v], tv[m]);
+            }
+        }
+        const double sg = side ? 1.0 : -1.0;
+        const double nr[3] = {sg * (tu[1] * tv[2] - tu[2] * tv[1]), sg * (tu[2] * tv[0] - tu[0] * tv[2]),
+                              sg * (tu[0] * tv[1] - tu[1] * tv[0])};
+        const double dS = sqrt(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
+        if (!(dS > 0.0)) {
+            atomicMin(p.status, (unsigned long long)e);
+            return;
+        }
+        const double w = wq * dS;
+        const double Na = N[kf];
+        double uq = 0.0, gq = 0.0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uq = fma(N[b], U[b], uq);
+            gq = fma(N[b], G[b], gq);
+        }
+        if (kind == MF_BFORM_PENALTY || kind == MF_BFORM_CONVECTION) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) krow[b] += c * w * Na * N[b];
+            rrow += c * w * Na * (uq - gq);
+        } else if (kind == MF_BFORM_RADIATION) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) krow[b] += c * w * Na * 4.0 * uq * uq * uq * N[b];
+            rrow += c * w * Na * (uq * uq * uq * uq - gq * gq * gq * gq);
+        } else {  // MF_BFORM_TRACTION
+            const double* S = p.form.value;
+            const double ti = tg ? gq : (S[3 * i] * nr[0] + S[3 * i + 1] * nr[1] + S[3 * i + 2] * nr[2]) / dS;
+            rrow -= w * Na * ti;
+        }
+    }
+    const int a = loc[kf];
+    const int64_t va = node[kf];
+    const int64_t row = p.field_major ? (int64_t)i * p.n_nodes + va : (int64_t)NF * va + i;
+    const int64_t rs = p.row_ptr[row];
+    const int64_t deg = p.nbr_ptr[va + 1] - p.nbr_ptr[va];
+    T* K = (T*)p.K;
+    T* d = (T*)p.d;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        if (krow[b] == 0.0) continue;
+        const int64_t rk = p.rank[(int64_t)(a * 20 + loc[b]) * p.n_el + e];
+        const int64_t pos = p.field_major ? rs + i * deg + rk : rs + rk * NF + i;
+        unsafeAtomicAdd(K + pos, (T)krow[b]);
+    }
+    if (rrow != 0.0) unsafeAtomicAdd(d + row, (T)(-rrow));
+}
+
+template <int NF, typename T>
+mf_status launch_boundary20(const BParams& p, hipStream_t s)
+{
+    const int64_t n = p.n_faces * 8 * NF;
+    if (n == 0) return MF_OK;
+    if (n > 0xffffffffLL - kThreads) return set_error(MF_ERR_ARG, "too many faces for one launch");
+    k_boundary20<NF, T><<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(p);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
 template <int NF, typename T>
 mf_status launch_boundary(const BParams& p, hipStream_t s)
 {
@@ -294,7 +413,9 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
                                           void* d, void* stream)
 {
     if (!P || !form) return set_error(MF_ERR_ARG, "pattern or form is NULL");
-    if (P->dim != 3 || P->nen != 8) return set_error(MF_ERR_UNSUPPORTED, "boundary forms need a 3D hex pattern");
+    if (P->dim != 3 || (P->nen != 8 && P->nen != 20))
+        return set_error(MF_ERR_UNSUPPORTED, "boundary forms need a 3D hex pattern");
+    const bool quad = P->nen == 20;
     if (prec != MF_F64 && prec != MF_F32) return set_error(MF_ERR_ARG, "unknown precision %d", (int)prec);
     if (n_faces < 0 || n_faces > ((int64_t)1 << 28)) return set_error(MF_ERR_ARG, "n_faces out of range");
     if (n_faces > 0 && (!face_elem || !face_id || !coords || !K || !d))
@@ -312,7 +433,6 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
             break;
         case MF_BFORM_TRACTION:
             if (nf != 3) return set_error(MF_ERR_ARG, "traction needs 3 fields, pattern has %d", nf);
-            if (target) return set_error(MF_ERR_ARG, "traction takes its load from form->value, not a target");
             break;
         case MF_BFORM_NS_INFLOW:
         case MF_BFORM_NS_OUTFLOW:
@@ -321,6 +441,8 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
             break;
         default: return set_error(MF_ERR_ARG, "unknown boundary form %d", (int)form->kind);
     }
+    if (quad && (form->kind == MF_BFORM_FLUX || nf == 4))
+        return set_error(MF_ERR_UNSUPPORTED, "the flux and flow boundary forms need 8-node hexahedra");
     hipStream_t s = (hipStream_t)stream;
     BParams p{};
     p.form = *form;
@@ -341,6 +463,10 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
     p.d = d;
     p.status = P->status;
     const_cast<mf_pattern_s*>(P)->last_stream = s;
+    if (quad) {
+        if (prec == MF_F64) return nf == 1 ? launch_boundary20<1, double>(p, s) : launch_boundary20<3, double>(p, s);
+        return nf == 1 ? launch_boundary20<1, float>(p, s) : launch_boundary20<3, float>(p, s);
+    }
     if (prec == MF_F64) {
         if (nf == 4) return launch_boundary<4, double>(p, s);
         return nf == 1 ? launch_boundary<1, double>(p, s) : launch_boundary<3, double>(p, s);

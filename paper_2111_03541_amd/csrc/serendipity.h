@@ -1,0 +1,49 @@
+// The 20-node serendipity hexahedron (quadratic element of Sec. 4): shape functions and
+// reference gradients on [-1, 1]^3.  Local node order: corners a = ax + 2 ay + 4 az, then
+// the midpoints of the x-, y- and z-directed edges, four each, ordered by the bits of the
+// two other axes (ascending axis order).
+//   corner   N = (1/8)(1 + s_x x)(1 + s_y y)(1 + s_z z)(s_x x + s_y y + s_z z - 2)
+//   edge     N = (1/4)(1 - x_e^2)(1 + s_0 x_0)(1 + s_1 x_1)
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mf {
+
+__device__ __forceinline__ double bit_sign(int b) { return b ? 1.0 : -1.0; }
+
+// Shape functions and reference gradients of node a at xi.
+__device__ __forceinline__ void shape20(int a, const double (&x)[3], double& N, double (&dN)[3])
+{
+    if (a < 8) {
+        const double s[3] = {bit_sign(a & 1), bit_sign((a >> 1) & 1), bit_sign(a >> 2)};
+        const double f[3] = {1.0 + s[0] * x[0], 1.0 + s[1] * x[1], 1.0 + s[2] * x[2]};
+        const double t = s[0] * x[0] + s[1] * x[1] + s[2] * x[2] - 2.0;
+        N = 0.125 * f[0] * f[1] * f[2] * t;
+        dN[0] = 0.125 * s[0] * f[1] * f[2] * (t + f[0]);
+        dN[1] = 0.125 * s[1] * f[0] * f[2] * (t + f[1]);
+        dN[2] = 0.125 * s[2] * f[0] * f[1] * (t + f[2]);
+        return;
+    }
+    const int m = a - 8, ax = m >> 2, k = m & 3;
+    // the two other axes in ascending order carry the signs of bits 0 and 1 of k
+    const int o0 = ax == 0 ? 1 : 0, o1 = ax == 2 ? 1 : 2;
+    const double s0 = bit_sign(k & 1), s1 = bit_sign(k >> 1);
+    const double g = 1.0 - x[ax] * x[ax], h0 = 1.0 + s0 * x[o0], h1 = 1.0 + s1 * x[o1];
+    N = 0.25 * g * h0 * h1;
+    dN[ax] = -0.5 * x[ax] * h0 * h1;
+    dN[o0] = 0.25 * g * s0 * h1;
+    dN[o1] = 0.25 * g * h0 * s1;
+}
+
+// Whether local node a lies on the face xi_axis = (side ? +1 : -1).
+__device__ __forceinline__ bool on_face20(int a, int axis, int side)
+{
+    if (a < 8) return ((a >> axis) & 1) == side;
+    const int m = a - 8, ax = m >> 2, k = m & 3;
+    if (ax == axis) return false;
+    const int o0 = ax == 0 ? 1 : 0;
+    return (axis == o0 ? (k & 1) : (k >> 1)) == side;
+}
+
+}  // namespace mf

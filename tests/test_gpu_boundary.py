@@ -28,6 +28,7 @@ CASES = [  # (name, kind, nf, coef, value, uses state, uses target)
     ("radiation", OB.RADIATION, 1, 0.8, [1.3], True, False),
     ("flux", OB.FLUX, 1, 1.7, [0.0], True, False),
     ("traction", OB.TRACTION, 3, 1.0, S_LOAD, False, False),
+    ("traction_target", OB.TRACTION, 3, 1.0, [], False, True),
     # flow forms: coef = tau^b, value = (u^w, rho, mu)
     ("ns_inflow", OB.NS_INFLOW, 4, 2.5, [0.4, -0.3, 0.2, 1.2, 0.05], True, False),
     ("ns_inflow_target", OB.NS_INFLOW, 4, 2.5, [0.0, 0.0, 0.0, 1.2, 0.05], True, True),

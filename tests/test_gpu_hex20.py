@@ -121,3 +121,97 @@ def test_hex20_argument_errors(mf):
         pat4.assemble(mf.Form(mf.NS_SUPG, rho=1.0, mu=0.01), coords, lin_state=st)
     with pytest.raises(mf.MFError):  # unknown element type
         mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 1, elem=7)
+
+
+# ---------------------------------------------------------------- faces (boundary forms)
+
+import oracle.boundary as OB  # noqa: E402
+
+FACE_CASES = [  # (name, kind, nf, coef, value, uses state, uses target)
+    ("penalty1", OB.PENALTY, 1, 40.0, [0.7], True, False),
+    ("penalty3_target", OB.PENALTY, 3, 20.0, [0.0, 0.0, 0.0], True, True),
+    ("convection", OB.CONVECTION, 1, 3.0, [2.5], True, False),
+    ("radiation", OB.RADIATION, 1, 0.8, [1.3], True, False),
+    ("traction", OB.TRACTION, 3, 1.0, [0.3, -0.2, 0.7, 0.1, 0.5, -0.4, 0.6, 0.2, -1.1], False, False),
+    ("traction_target", OB.TRACTION, 3, 1.0, [], False, True),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("numbering", [0, 1])
+@pytest.mark.parametrize("case", FACE_CASES, ids=[c[0] for c in FACE_CASES])
+def test_boundary_form_matches_oracle(mf, case, numbering, prec):
+    name, kind, nf, coef, value, use_state, use_target = case
+    say("hex20 boundary", name, "numbering", numbering, "prec", prec)
+    n = (3, 2, 2)
+    mesh = W.serendipity_mesh(n, jitter=0.2, seed=5, lengths=[1.0, 0.8, 1.3])
+    fe, fi = W.box_faces(n)
+    sel = np.random.default_rng(2).permutation(fe.shape[0])[: fe.shape[0] * 3 // 4]
+    fe, fi = fe[sel], fi[sel]
+    rng = np.random.default_rng(4)
+    state = 1.0 + rng.random((nf, mesh.n_nodes)) if use_state else None
+    target = rng.standard_normal((nf, mesh.n_nodes)) if use_target else None
+    fdt = np.float64 if prec == 0 else np.float32
+    if prec == 1:
+        state = None if state is None else state.astype(np.float32).astype(np.float64)
+        target = None if target is None else target.astype(np.float32).astype(np.float64)
+    ref = S.Pattern20(mesh, nf, numbering)
+    Kr, dr = S.assemble_boundary20(ref, kind, coef, value, fe, fi, state=state, target=target)
+    dev = torch.device("cuda:0")
+    pat = gpu_pattern(mf, mesh, nf, numbering)
+    tt = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=fdt)).to(dev)
+    K, d = pat.assemble_boundary(kind, torch.from_numpy(mesh.coords).to(dev), torch.from_numpy(fe).to(dev),
+                                 torch.from_numpy(fi).to(dev), coef=coef, value=value, state=tt(state),
+                                 target=tt(target), precision=prec)
+    assert pat.status()[0] == mf.OK
+    Kg = ref.to_scipy(K.double().cpu().numpy())
+    dg = d.double().cpu().numpy()
+    tol = 1e-12 if prec == 0 else 1e-5
+    kscale = abs(Kr).max() if Kr.nnz else 0.0
+    assert (abs(Kg - Kr).max() <= tol * kscale) if kscale > 0 else abs(Kg).max() == 0.0
+    assert np.abs(dg - dr).max() <= tol * max(np.abs(dr).max(), 1e-300)
+
+
+@pytest.mark.parametrize("case", [1, 2, 3])
+def test_cantilever_on_the_gpu(mf, case):
+    """The paper's 3D cantilever (10 x 4 x 4 quadratic bricks, E = 1, nu = 0, x = 0
+    clamped): elasticity and the load assembled on the GPU, solved by Jacobi-PCG; the
+    centre-line deflection against the oracle's direct solve and beam theory."""
+    sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    from test_oracle_serendipity import beam_deflection, cantilever
+    say("hex20 cantilever case", case)
+    n = (10, 4, 4)
+    mesh = W.serendipity_mesh(n, lengths=[10.0, 1.0, 1.0])
+    ur = cantilever(case, mesh)
+    dev = torch.device("cuda:0")
+    pat = gpu_pattern(mf, mesh, 3)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    clamp = np.repeat(np.abs(mesh.coords[0]) < 1e-12, 3).astype(np.uint8)
+    K, d = pat.assemble(mf.Form(mf.ELASTICITY, coef=1.0, nu=0.0), coords,
+                        dirichlet=torch.from_numpy(clamp).to(dev))
+    if case == 1:
+        sig = [0.0, 0.0, 0.0, -1.0, 0.0, 0.0, 0.0, 0.0, 0.0]  # t = (0, -1, 0) on x = L
+        fe, fi = W.box_faces(n, sides=[1])
+        tg = None
+    else:
+        sig = []
+        fe, fi = W.box_faces(n, sides=[3])  # the top face y = h
+        t = np.zeros((3, mesh.n_nodes))
+        t[1] = -(1.0 if case == 2 else 1.0 - mesh.coords[0] / 10.0)
+        tg = torch.from_numpy(t).to(dev)
+    pat.assemble_boundary(mf.BFORM_TRACTION, coords, torch.from_numpy(fe).to(dev), torch.from_numpy(fi).to(dev),
+                          value=sig, target=tg, K=K, d=d)
+    assert pat.status()[0] == mf.OK
+    d[torch.from_numpy(clamp.astype(bool)).to(dev)] = 0.0  # the load on clamped DOFs is a reaction
+    rp, ci, _ = pat.device_arrays()
+    # Jacobi-scaled K has cond ~7e6: the attainable relative residual is about 1e-9
+    x, res = mf.pcg(rp, ci, K, d, tol=1e-9, maxit=20000)
+    say(f"  {res}")
+    assert res["converged"]
+    u = x.cpu().numpy().reshape(-1, 3)
+    c = mesh.coords
+    line = np.nonzero((np.abs(c[1] - 0.5) < 1e-12) & (np.abs(c[2] - 0.5) < 1e-12))[0]
+    ref = beam_deflection(case, c[0, line])
+    tip = np.abs(ref).max()
+    assert np.abs(u - ur).max() < 1e-6 * np.abs(ur).max()
+    assert np.abs(u[line, 1] - ref).max() < 0.02 * tip
