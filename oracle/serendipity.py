@@ -1,4 +1,5 @@
-"""Oracle: 20-node serendipity hexahedra (quadratic elements) in plain numpy.
+"""Oracle: 20-node serendipity hexahedra and 8-node serendipity quadrilaterals (quadratic
+elements) in plain numpy.
 
 TEST INFRASTRUCTURE ONLY.  Only `tests/`, the smoke check and the benchmark's CPU
 baseline leg may import this module; the product library never does.
@@ -9,7 +10,9 @@ local nodes as workloads.serendipity_mesh numbers them (corners a = ax + 2 ay + 
 then the x-, y- and z-edge midpoints).  Shape functions, with s the corner signs:
   corner   N = (1/8)(1 + s_x x)(1 + s_y y)(1 + s_z z)(s_x x + s_y y + s_z z - 2)
   x-edge   N = (1/4)(1 - x^2)(1 + s_y y)(1 + s_z z)       (and cyclically for y, z)
-Quadrature: 3 Gauss points per axis, +-sqrt(3/5) and 0 with weights 5/9 and 8/9.
+Quadrature: 3 Gauss points per axis, +-sqrt(3/5) and 0 with weights 5/9 and 8/9.  The
+8-node quadrilateral (basis8) is the same construction in 2D; assemble20 and Pattern20
+take either mesh.
 Forms as the Q1 oracle defines them at the zero state (Sec. 4.1, 4.2; K = dR/dU, d = -R):
   mass        K = int c N_a N_b,                        d = int c N_a f
   conduction  K = int c grad N_a . grad N_b,            d = int N_a f
@@ -54,6 +57,39 @@ def basis20(xi):
         dN[8 + m, oth[0]] = 0.25 * g0 * sg[oth[0]] * h2
         dN[8 + m, oth[1]] = 0.25 * g0 * h1 * sg[oth[1]]
     return N, dN
+
+
+def basis8(xi):
+    """N [8], dN [8][2] of the 8-node serendipity quadrilateral at the reference point xi.
+
+    Local nodes: corners a = ax + 2 ay, then the x-edge midpoints at y = -1, +1, then the
+    y-edge midpoints at x = -1, +1:
+      corner  N = (1/4)(1 + s_x x)(1 + s_y y)(s_x x + s_y y - 1)
+      x-edge  N = (1/2)(1 - x^2)(1 + s_y y),   y-edge  N = (1/2)(1 - y^2)(1 + s_x x)
+    """
+    x, y = (float(v) for v in xi)
+    N = np.zeros(8)
+    dN = np.zeros((8, 2))
+    for a in range(4):
+        sx, sy = (1.0 if a & 1 else -1.0), (1.0 if a >> 1 else -1.0)
+        fx, fy, t = 1.0 + sx * x, 1.0 + sy * y, sx * x + sy * y - 1.0
+        N[a] = 0.25 * fx * fy * t
+        dN[a] = [0.25 * (sx * fy * t + fx * fy * sx), 0.25 * (fx * sy * t + fx * fy * sy)]
+    for b in range(2):
+        s = 1.0 if b else -1.0
+        N[4 + b] = 0.5 * (1.0 - x * x) * (1.0 + s * y)
+        dN[4 + b] = [-x * (1.0 + s * y), 0.5 * (1.0 - x * x) * s]
+        N[6 + b] = 0.5 * (1.0 - y * y) * (1.0 + s * x)
+        dN[6 + b] = [0.5 * (1.0 - y * y) * s, -y * (1.0 + s * x)]
+    return N, dN
+
+
+def gauss3_2d():
+    p = np.sqrt(3.0 / 5.0)
+    pts, wts = np.array([-p, 0.0, p]), np.array([5.0, 8.0, 5.0]) / 9.0
+    xi = np.array([[pts[i], pts[j]] for j in range(3) for i in range(3)])
+    w = np.array([wts[i] * wts[j] for j in range(3) for i in range(3)])
+    return xi, w
 
 
 def gauss3():
@@ -104,23 +140,24 @@ def assemble20(pat: Pattern20, kind, params=None, elem_param=None, nodal_src=Non
     prm = dict(coef=1.0, nu=0.0)
     prm.update(params or {})
     mesh, nf = pat.mesh, pat.nf
-    xi, w = gauss3()
-    tables = [basis20(x) for x in xi]
+    dim, nen = mesh.dim, mesh.nen
+    xi, w = gauss3() if dim == 3 else gauss3_2d()
+    tables = [(basis20 if dim == 3 else basis8)(x) for x in xi]
     rows, cols, vals = [], [], []
     d = np.zeros(pat.n_rows)
     for e in range(mesh.n_elems):
         nodes = mesh.conn[:, e]
-        X = mesh.coords[:, nodes].T  # [20][3]
+        X = mesh.coords[:, nodes].T  # [nen][dim]
         ep = 1.0 if elem_param is None else float(elem_param[e])
-        src = np.zeros((20, nf)) if nodal_src is None else np.asarray(nodal_src)[:, nodes].T
-        Ke = np.zeros((20, nf, 20, nf))
-        De = np.zeros((20, nf))
+        src = np.zeros((nen, nf)) if nodal_src is None else np.asarray(nodal_src)[:, nodes].T
+        Ke = np.zeros((nen, nf, nen, nf))
+        De = np.zeros((nen, nf))
         for (N, dN), wq in zip(tables, w):
             J = X.T @ dN  # J[m][n] = dx_m / dxi_n
             det = np.linalg.det(J)
             if not det > 0.0:
                 raise FloatingPointError(f"det J <= 0 in element {e}")
-            g = np.linalg.solve(J.T, dN.T).T  # [20][3] physical gradients
+            g = np.linalg.solve(J.T, dN.T).T  # [nen][dim] physical gradients
             W = wq * det
             fq = N @ src
             if kind == MASS:
@@ -137,15 +174,15 @@ def assemble20(pat: Pattern20, kind, params=None, elem_param=None, nodal_src=Non
                 mu = E / (2 * (1 + nu))
                 gg = g @ g.T
                 Ke += W * (lam * np.einsum("ai,bj->aibj", g, g) + mu * np.einsum("aj,bi->aibj", g, g)
-                           + mu * np.einsum("ab,ij->aibj", gg, np.eye(3)))
+                           + mu * np.einsum("ab,ij->aibj", gg, np.eye(dim)))
                 De += W * np.outer(N, fq)
             else:
                 raise ValueError(kind)
-        for a in range(20):
+        for a in range(nen):
             for i in range(nf):
                 r = pat.dof(nodes[a], i)
                 d[r] += De[a, i]
-                for b in range(20):
+                for b in range(nen):
                     for j in range(nf):
                         rows.append(r)
                         cols.append(pat.dof(nodes[b], j))

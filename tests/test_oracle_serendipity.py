@@ -208,3 +208,86 @@ def test_cantilever_matches_beam_theory(case):
     assert np.abs(u[line, 2]).max() < 1e-9 * tip
     if case == 1:
         assert np.abs(u[line, 0]).max() < 1e-9 * tip
+
+
+# ---------------------------------------------------------------- 8-node quadrilaterals
+
+def ref_nodes8():
+    X = np.zeros((8, 2))
+    for a in range(4):
+        X[a] = [1.0 if a & 1 else -1.0, 1.0 if a >> 1 else -1.0]
+    X[4], X[5], X[6], X[7] = [0, -1], [0, 1], [-1, 0], [1, 0]
+    return X
+
+
+def test_quad8_basis_kronecker_unity_and_gradients():
+    X = ref_nodes8()
+    for a in range(8):
+        N, _ = S.basis8(X[a])
+        assert np.abs(N - np.eye(8)[a]).max() < 1e-15
+    rng = np.random.default_rng(1)
+    for _ in range(10):
+        x = rng.uniform(-1, 1, 2)
+        N, dN = S.basis8(x)
+        assert abs(N.sum() - 1.0) < 1e-14 and np.abs(dN.sum(axis=0)).max() < 1e-14
+        assert np.abs(N @ X - x).max() < 1e-14 and np.abs(X.T @ dN - np.eye(2)).max() < 1e-14
+        # the complete quadratics and x^2 y, x y^2 lie in the span: interpolation is exact
+        for f in (lambda p: p[0] ** 2, lambda p: p[0] * p[1], lambda p: p[1] ** 2,
+                  lambda p: p[0] ** 2 * p[1], lambda p: p[0] * p[1] ** 2):
+            assert abs(N @ np.array([f(p) for p in X]) - f(x)) < 1e-14
+        for d in range(2):
+            h = np.zeros(2)
+            h[d] = 1e-6
+            fd = (S.basis8(x + h)[0] - S.basis8(x - h)[0]) / 2e-6
+            assert np.abs(fd - dN[:, d]).max() < 1e-8
+
+
+def test_quad8_mesh_area_and_pattern():
+    mesh = W.serendipity_mesh_2d((3, 2), jitter=0.2, seed=3, lengths=[1.5, 0.8])
+    assert mesh.nen == 8 and mesh.n_nodes == 4 * 3 + 3 * 3 + 4 * 2
+    pat = S.Pattern20(mesh, 1)
+    K, d = S.assemble20(pat, O.MASS, {"coef": 1.0}, nodal_src=np.ones((1, mesh.n_nodes)))
+    assert abs(K.sum() - 1.2) < 1e-14 and abs(d.sum() - 1.2) < 1e-14
+    Sm = pat.to_scipy(np.ones(pat.nnz))
+    assert (Sm != Sm.T).nnz == 0 and np.all(Sm.diagonal() == 1)
+
+
+def test_quad8_patch_tests():
+    mesh = W.serendipity_mesh_2d((3, 4), jitter=0.2, seed=5)
+    pat = S.Pattern20(mesh, 1)
+    Km = pat.to_scipy(S.assemble20(pat, O.POISSON, {"coef": 1.7})[0])
+    c = mesh.coords
+    interior = np.all((c > 1e-12) & (c < 1 - 1e-12), axis=0)
+    assert np.abs((Km @ (0.4 * c[0] - 1.1 * c[1]))[interior]).max() < 1e-13
+    assert np.abs(Km @ np.ones(mesh.n_nodes)).max() < 1e-13
+    # quadratic fields on an affine rectangle: (K u)_a = -int N_a lap u on interior rows
+    mesh = W.serendipity_mesh_2d((3, 4), lengths=[1.0, 1.4])
+    pat = S.Pattern20(mesh, 1)
+    K = pat.to_scipy(S.assemble20(pat, O.POISSON, {"coef": 1.0})[0])
+    M = pat.to_scipy(S.assemble20(pat, O.MASS, {"coef": 1.0})[0])
+    c = mesh.coords
+    hi = np.array([1.0, 1.4])[:, None]
+    interior = np.all((c > 1e-12) & (c < hi - 1e-12), axis=0)
+    u = 1.5 * c[0] ** 2 + c[0] * c[1] - 0.5 * c[1] ** 2  # lap u = 3 - 1 = 2
+    assert np.abs((K @ u + M @ np.full(mesh.n_nodes, 2.0))[interior]).max() < 1e-13
+
+
+def test_quad8_elasticity_rigid_modes():
+    mesh = W.serendipity_mesh_2d((3, 2), jitter=0.2, seed=8)
+    pat = S.Pattern20(mesh, 2)
+    E = W.lognormal_elem(mesh.n_elems, 0.5, 9)
+    Km = pat.to_scipy(S.assemble20(pat, O.ELASTICITY, {"coef": 2.0, "nu": 0.3}, elem_param=E)[0])
+    assert abs(Km - Km.T).max() < 1e-12 * abs(Km).max()
+    x, y = mesh.coords
+    one, zero = np.ones_like(x), np.zeros_like(x)
+    for m in ((one, zero), (zero, one), (-y, x)):
+        assert np.abs(Km @ np.stack(m, axis=1).reshape(-1)).max() < 1e-12 * abs(Km).max()
+    # uniaxial strain e_xx = 1 (plane strain): interior rows vanish, and the reaction on the
+    # face x = 1 sums to (lam + 2 mu) times its length for E = 1 everywhere
+    mesh = W.serendipity_mesh_2d((3, 2), jitter=0.2, seed=8)
+    pat = S.Pattern20(mesh, 2)
+    Km = pat.to_scipy(S.assemble20(pat, O.ELASTICITY, {"coef": 1.0, "nu": 0.3})[0])
+    F = (Km @ np.stack((mesh.coords[0], np.zeros(mesh.n_nodes)), axis=1).reshape(-1)).reshape(-1, 2)
+    lam, mu = 0.3 / (1.3 * 0.4), 1.0 / 2.6
+    right = np.abs(mesh.coords[0] - 1.0) < 1e-12
+    assert abs(F[right, 0].sum() - (lam + 2 * mu)) < 1e-12

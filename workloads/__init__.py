@@ -288,6 +288,42 @@ def serendipity_mesh(n, jitter: float = 0.0, seed=None, lengths=None) -> Mesh:
     return Mesh(coords, conn)
 
 
+def serendipity_mesh_2d(n, jitter: float = 0.0, seed=None, lengths=None) -> Mesh:
+    """Structured rectangle of 8-node serendipity quadrilaterals, n = (nx, ny) elements.
+
+    Nodes: the (nx+1)(ny+1) corner lattice (lexicographic, as structured_mesh), then the
+    midpoints of the x-directed edges, then of the y-directed edges, each set
+    lexicographic.  Local nodes: 0..3 the corners a = ax + 2 ay; 4, 5 the x-edges at y
+    bit 0, 1; 6, 7 the y-edges at x bit 0, 1.  Jitter moves interior corners only and
+    every edge midpoint is the midpoint of its corners.  Returns a Mesh with nen = 8."""
+    nx, ny = (int(v) for v in n)
+    base = structured_mesh((nx, ny), jitter=jitter, seed=seed, lengths=lengths)
+    X = base.coords
+    NX, NY = nx + 1, ny + 1
+    cid = lambda i, j: i + NX * j
+    n_c, n_ex = NX * NY, nx * NY
+    ex_id = lambda i, j: n_c + i + nx * j
+    ey_id = lambda i, j: n_c + n_ex + i + NX * j
+    coords = np.zeros((2, n_c + n_ex + NX * ny))
+    coords[:, :n_c] = X
+    for j in range(NY):
+        for i in range(nx):
+            coords[:, ex_id(i, j)] = 0.5 * (X[:, cid(i, j)] + X[:, cid(i + 1, j)])
+    for j in range(ny):
+        for i in range(NX):
+            coords[:, ey_id(i, j)] = 0.5 * (X[:, cid(i, j)] + X[:, cid(i, j + 1)])
+    conn = np.zeros((8, nx * ny), dtype=np.int32)
+    for ey in range(ny):
+        for ex in range(nx):
+            e = ex + nx * ey
+            for a in range(4):
+                conn[a, e] = cid(ex + (a & 1), ey + (a >> 1))
+            for b in range(2):
+                conn[4 + b, e] = ex_id(ex, ey + b)
+                conn[6 + b, e] = ey_id(ex + b, ey)
+    return Mesh(coords, conn)
+
+
 def box_faces(n, sides=None):
     """Element faces on the sides of a structured 3D box mesh of n = (nx, ny, nz) elements.
 
