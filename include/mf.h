@@ -50,10 +50,15 @@ typedef enum {
 typedef enum {
     MF_QUAD4 = 1,   /* 4-node quadrilateral, order 1                                        */
     MF_HEX8 = 2,    /* 8-node hexahedron, order 1 (corners a = ax + 2 ay + 4 az)             */
-    MF_HEX20 = 3    /* 20-node serendipity hexahedron, order 2: corners as MF_HEX8, then the
+    MF_HEX20 = 3,   /* 20-node serendipity hexahedron, order 2: corners as MF_HEX8, then the
                        midpoints of the x-, y- and z-directed edges, four each, ordered by
                        the bits of the two other axes; mass, conduction and elasticity forms
-                       with 3 Gauss points per axis (element-parallel, atomic scatter)     */
+                       with 3 Gauss points per axis (element colours, one workgroup per
+                       element)                                                              */
+    MF_QUAD8 = 4    /* 8-node serendipity quadrilateral, order 2: corners as MF_QUAD4, then the
+                       midpoints of the x-directed edges at y = -1, +1 and of the y-directed
+                       edges at x = -1, +1; the forms of MF_HEX20 (plane-strain elasticity)
+                       with 3 Gauss points per axis                                          */
 } mf_elem_type;
 /* DOF numbering.  Field-major is the paper's map (Sec. 2.2 B-3): dof = field*n_nodes + node.
    Node-major interleaves the fields of a node: dof = n_fields*node + field. */
@@ -70,7 +75,7 @@ typedef enum {
 typedef enum { MF_F64 = 0, MF_F32 = 1 } mf_precision;
 
 typedef struct {
-    int32_t dim;           /* 2 (MF_QUAD4) or 3 (MF_HEX8, MF_HEX20) */
+    int32_t dim;           /* 2 (MF_QUAD4, MF_QUAD8) or 3 (MF_HEX8, MF_HEX20) */
     int64_t n_nodes;
     int64_t n_elems;
     const int32_t* conn;   /* [nen][n_elems] (device) */

@@ -65,18 +65,19 @@ mf_status mf_pattern(const mf_mesh* mesh, mf_elem_type type, int32_t order, cons
     if (!out) return set_error(MF_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (!mesh || !dofs) return set_error(MF_ERR_ARG, "mesh or dofs is NULL");
-    if (type != MF_QUAD4 && type != MF_HEX8 && type != MF_HEX20)
+    if (type != MF_QUAD4 && type != MF_HEX8 && type != MF_HEX20 && type != MF_QUAD8)
         return set_error(MF_ERR_UNSUPPORTED, "element type %d", (int)type);
-    if (order != (type == MF_HEX20 ? 2 : 1))
+    const int elem_order = (type == MF_HEX20 || type == MF_QUAD8) ? 2 : 1;
+    if (order != elem_order)
         return set_error(MF_ERR_UNSUPPORTED, "element order %d for element type %d", (int)order, (int)type);
-    const int dim = type == MF_QUAD4 ? 2 : 3;
+    const int dim = (type == MF_QUAD4 || type == MF_QUAD8) ? 2 : 3;
     if (mesh->dim != dim) return set_error(MF_ERR_ARG, "mesh dim %d does not match the element", (int)mesh->dim);
     if (mesh->n_nodes < 0 || mesh->n_elems < 0) return set_error(MF_ERR_ARG, "negative mesh size");
     if (mesh->n_elems > 0 && !mesh->conn) return set_error(MF_ERR_ARG, "conn is NULL");
     if (dofs->n_fields < 1 || dofs->n_fields > 4) return set_error(MF_ERR_ARG, "n_fields %d not in 1..4", (int)dofs->n_fields);
     if (dofs->numbering != MF_NODE_MAJOR && dofs->numbering != MF_FIELD_MAJOR)
         return set_error(MF_ERR_ARG, "unknown numbering %d", (int)dofs->numbering);
-    const int nen = type == MF_HEX20 ? 20 : 1 << dim;
+    const int nen = type == MF_HEX20 ? 20 : (type == MF_QUAD8 ? 8 : 1 << dim);
     if ((int64_t)nen * nen * mesh->n_elems >= ((int64_t)1 << 31) || mesh->n_nodes * dofs->n_fields >= ((int64_t)1 << 31))
         return set_error(MF_ERR_OVERFLOW, "mesh too large for int32 indices");
 
@@ -84,6 +85,7 @@ mf_status mf_pattern(const mf_mesh* mesh, mf_elem_type type, int32_t order, cons
     if (!P) return set_error(MF_ERR_OOM, "host allocation failed");
     P->dim = dim;
     P->nen = nen;
+    P->order = elem_order;
     P->nf = dofs->n_fields;
     P->numbering = dofs->numbering;
     P->n_nodes = mesh->n_nodes;
@@ -158,7 +160,7 @@ mf_status mf_assemble_ex(const mf_pattern_t* P, const mf_form* form, const doubl
 {
     g_err[0] = 0;
     if (!P || !form || !quad) return set_error(MF_ERR_ARG, "pattern, form or quadrature is NULL");
-    const int want_q = P->nen == 20 ? 3 : 2;
+    const int want_q = P->order == 2 ? 3 : 2;
     if (quad->points_per_axis != want_q)
         return set_error(MF_ERR_UNSUPPORTED, "%d Gauss points per axis (this element takes %d)",
                          (int)quad->points_per_axis, want_q);
@@ -200,8 +202,8 @@ mf_status mf_assemble_ex(const mf_pattern_t* P, const mf_form* form, const doubl
 
     mf_status st = reset_status(P, A.stream);
     if (st != MF_OK) return st;
-    if (P->nen == 20) {  // quadratic elements: one wave per element, atomic scatter
-        st = assemble_hex20(A);
+    if (P->order == 2) {  // quadratic elements: colour by colour, one workgroup per element
+        st = assemble_quadratic(A);
         if (st != MF_OK) return st;
         return apply_dirichlet(A);
     }

@@ -1,21 +1,21 @@
-// Assembly on 20-node serendipity hexahedra (quadratic elements, used by every experiment
-// of Sec. 4; element order is an input of the problem statement, Sec. 1), with the
-// 3-point Gauss rule per axis and the mass, conduction and elasticity forms of the linear
-// kernel (Sec. 4.1, 4.2; K = dR/dU, d = -R at the zero state).
+// Assembly on serendipity elements (quadratic elements, used by every experiment of
+// Sec. 4; element order is an input of the problem statement, Sec. 1): 20-node hexahedra
+// and 8-node quadrilaterals, with the 3-point Gauss rule per axis and the mass,
+// conduction and elasticity forms of the linear kernel (Sec. 4.1, 4.2; K = dR/dU, d = -R
+// at the zero state; plane strain in 2D).
 //
-// One 256-thread workgroup per element:
-//   1. lanes load the element's 20 node coordinates and sources into LDS;
-//   2. lanes 0..26, one per Gauss point, build J = sum_b x_b (x) grad_xi N_b in FP64, its
-//      determinant and inverse, and store g_b = J^-T grad_xi N_b for the 20 nodes, the
+// One workgroup per element (256 threads in 3D, 64 in 2D):
+//   1. lanes load the element's node coordinates and sources into LDS;
+//   2. one lane per Gauss point builds J = sum_b x_b (x) grad_xi N_b in FP64, its
+//      determinant and inverse, and stores g_b = J^-T grad_xi N_b for every node, the
 //      weight W = w det J and the interpolated source in LDS;
-//   3. lane (row (a, i), quarter) sums the entries of row (a, i) for the five column
-//      nodes b of its quarter over the 27 points and adds them into K through the
-//      element-to-nonzero rank map (quarter 0 also adds d_(a,i) into d).
+//   3. lane (row (a, i), quarter) sums the entries of row (a, i) for the column nodes b of
+//      its quarter (a quarter of the element's nodes) over the Gauss points and adds them
+//      into K through the element-to-nonzero rank map (quarter 0 also adds d_(a,i)).
 // Elements go colour by colour (no two elements of one colour share a node), one launch
 // per colour, so the adds are plain read-modify-writes: every entry of K and d has one
 // writer per launch, and the stream orders the launches.
-// Local node order: corners a = ax + 2 ay + 4 az, then the midpoints of the x-, y- and
-// z-directed edges, four each, ordered by the bits of the two other axes.
+// Local node orders: serendipity.h.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -26,20 +26,70 @@
 namespace mf {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kNQ = 27;
-constexpr int kQuarters = 4;  // column nodes b split in four groups of five
+constexpr int kQuarters = 4;  // the column nodes b of a row, in four groups
 
-__device__ __forceinline__ void gauss_point(int q, double (&x)[3], double& w)
+template <int DIM>
+struct Elem {
+    static constexpr int NEN = DIM == 3 ? 20 : 8;  // nodes
+    static constexpr int NQ = DIM == 3 ? 27 : 9;   // Gauss points
+    static constexpr int THREADS = DIM == 3 ? 256 : 64;
+};
+
+template <int DIM>
+__device__ __forceinline__ void shape(int a, const double (&x)[DIM], double& N, double (&dN)[DIM])
+{
+    if constexpr (DIM == 3)
+        shape20(a, x, N, dN);
+    else
+        shape8(a, x, N, dN);
+}
+
+// Gauss point q (first axis fastest) of the 3-point rule per axis, and its weight.
+template <int DIM>
+__device__ __forceinline__ void gauss_point(int q, double (&x)[DIM], double& w)
 {
     const double p = 0.7745966692414834;  // sqrt(3/5)
     const double pts[3] = {-p, 0.0, p};
     const double wts[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
-    const int i = q % 3, j = (q / 3) % 3, k = q / 9;
-    x[0] = pts[i];
-    x[1] = pts[j];
-    x[2] = pts[k];
-    w = wts[i] * wts[j] * wts[k];
+    w = 1.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const int k = q % 3;
+        q /= 3;
+        x[d] = pts[k];
+        w *= wts[k];
+    }
+}
+
+// det J and (J^-1)[n][m] = dxi_n / dx_m (zero when det J <= 0)
+template <int DIM>
+__device__ __forceinline__ double invert(const double (&J)[DIM][DIM], double (&Ji)[DIM][DIM])
+{
+    if constexpr (DIM == 3) {
+        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        const double r = det > 0.0 ? 1.0 / det : 0.0;
+        Ji[0][0] = c00 * r;
+        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
+        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
+        Ji[1][0] = c01 * r;
+        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
+        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
+        Ji[2][0] = c02 * r;
+        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
+        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
+        return det;
+    } else {
+        const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const double r = det > 0.0 ? 1.0 / det : 0.0;
+        Ji[0][0] = J[1][1] * r;
+        Ji[0][1] = -J[0][1] * r;
+        Ji[1][0] = -J[1][0] * r;
+        Ji[1][1] = J[0][0] * r;
+        return det;
+    }
 }
 
 struct Q2Params {
@@ -60,14 +110,15 @@ struct Q2Params {
     unsigned long long* status;
 };
 
-template <int NF>
+template <int DIM, int NF>
 struct Q2Shared {
-    double x[20][3];
-    double src[20][NF];
-    double g[kNQ][20][3];
-    double N[kNQ][20];
-    double W[kNQ];
-    double f[kNQ][NF];
+    static constexpr int NEN = Elem<DIM>::NEN, NQ = Elem<DIM>::NQ;
+    double x[NEN][DIM];
+    double src[NEN][NF];
+    double g[NQ][NEN][DIM];
+    double N[NQ][NEN];
+    double W[NQ];
+    double f[NQ][NF];
     int bad;
 };
 
@@ -78,22 +129,26 @@ __global__ void k_fill(T* p, int64_t n)
     if (i < n) p[i] = T(0);
 }
 
-template <int FORM, typename T>
-__global__ void __launch_bounds__(kThreads) k_assemble_hex20(Q2Params p)
+template <int DIM, int FORM, typename T>
+__global__ void __launch_bounds__(Elem<DIM>::THREADS) k_assemble_quadratic(Q2Params p)
 {
-    constexpr int NF = FORM == MF_FORM_ELASTICITY ? 3 : 1;
-    __shared__ Q2Shared<NF> S;
+    constexpr int NEN = Elem<DIM>::NEN, NQ = Elem<DIM>::NQ, NBQ = NEN / kQuarters;
+    constexpr int NF = FORM == MF_FORM_ELASTICITY ? DIM : 1;
+    static_assert(NEN * NF * kQuarters <= Elem<DIM>::THREADS && NQ <= Elem<DIM>::THREADS &&
+                      NEN * DIM <= Elem<DIM>::THREADS && NEN % kQuarters == 0,
+                  "one lane per row quarter, Gauss point and coordinate");
+    __shared__ Q2Shared<DIM, NF> S;
     const int lane = threadIdx.x;
     const int64_t li = blockIdx.x;
     const bool live = li < p.n_list;  // uniform across the workgroup
     const int64_t e = live ? p.elems[li] : 0;
     if (live) {
-        if (lane < 60) {
-            const int b = lane / 3, m = lane % 3;
+        if (lane < NEN * DIM) {
+            const int b = lane / DIM, m = lane % DIM;
             const int32_t v = p.conn[(int64_t)b * p.n_el + e];
             S.x[b][m] = p.coords[(int64_t)m * p.n_nodes + v];
         }
-        if (lane < 20 * NF) {
+        if (lane < NEN * NF) {
             const int b = lane / NF, j = lane % NF;
             const int32_t v = p.conn[(int64_t)b * p.n_el + e];
             S.src[b][j] = p.src ? (double)((const T*)p.src)[(int64_t)j * p.n_nodes + v] : 0.0;
@@ -101,45 +156,41 @@ __global__ void __launch_bounds__(kThreads) k_assemble_hex20(Q2Params p)
         if (lane == 0) S.bad = 0;
     }
     __syncthreads();
-    if (live && lane < kNQ) {
-        double xi[3], w;
-        gauss_point(lane, xi, w);
-        double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        for (int b = 0; b < 20; ++b) {
-            double Nb, dN[3];
-            shape20(b, xi, Nb, dN);
+    if (live && lane < NQ) {
+        double xi[DIM], w;
+        gauss_point<DIM>(lane, xi, w);
+        double J[DIM][DIM];
 #pragma unroll
-            for (int m = 0; m < 3; ++m)
+        for (int m = 0; m < DIM; ++m)
 #pragma unroll
-                for (int n = 0; n < 3; ++n) J[m][n] = fma(S.x[b][m], dN[n], J[m][n]);
+            for (int n = 0; n < DIM; ++n) J[m][n] = 0.0;
+        for (int b = 0; b < NEN; ++b) {
+            double Nb, dN[DIM];
+            shape<DIM>(b, xi, Nb, dN);
+#pragma unroll
+            for (int m = 0; m < DIM; ++m)
+#pragma unroll
+                for (int n = 0; n < DIM; ++n) J[m][n] = fma(S.x[b][m], dN[n], J[m][n]);
         }
-        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-        const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-        const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-        const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        double Ji[DIM][DIM];
+        const double det = invert<DIM>(J, Ji);
         if (!(det > 0.0)) {
             atomicMin(p.status, (unsigned long long)e);
             S.bad = 1;
         }
-        const double r = det > 0.0 ? 1.0 / det : 0.0;
-        double Ji[3][3];  // (J^-1)[n][m]
-        Ji[0][0] = c00 * r;
-        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * r;
-        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * r;
-        Ji[1][0] = c01 * r;
-        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * r;
-        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * r;
-        Ji[2][0] = c02 * r;
-        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * r;
-        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * r;
         double f[NF];
 #pragma unroll
         for (int j = 0; j < NF; ++j) f[j] = 0.0;
-        for (int b = 0; b < 20; ++b) {
-            double Nb, dN[3];
-            shape20(b, xi, Nb, dN);
+        for (int b = 0; b < NEN; ++b) {
+            double Nb, dN[DIM];
+            shape<DIM>(b, xi, Nb, dN);
 #pragma unroll
-            for (int m = 0; m < 3; ++m) S.g[lane][b][m] = Ji[0][m] * dN[0] + Ji[1][m] * dN[1] + Ji[2][m] * dN[2];
+            for (int m = 0; m < DIM; ++m) {
+                double gm = 0.0;
+#pragma unroll
+                for (int n = 0; n < DIM; ++n) gm = fma(Ji[n][m], dN[n], gm);
+                S.g[lane][b][m] = gm;
+            }
             S.N[lane][b] = Nb;
 #pragma unroll
             for (int j = 0; j < NF; ++j) f[j] = fma(Nb, S.src[b][j], f[j]);
@@ -149,9 +200,9 @@ __global__ void __launch_bounds__(kThreads) k_assemble_hex20(Q2Params p)
         for (int j = 0; j < NF; ++j) S.f[lane][j] = f[j];
     }
     __syncthreads();
-    if (!live || S.bad || lane >= 20 * NF * kQuarters) return;
+    if (!live || S.bad || lane >= NEN * NF * kQuarters) return;
 
-    const int rowl = lane % (20 * NF), quarter = lane / (20 * NF);
+    const int rowl = lane % (NEN * NF), quarter = lane / (NEN * NF);
     const int a = rowl / NF, i = rowl % NF;
     const double ep = p.elem_param ? (double)((const T*)p.elem_param)[e] : 1.0;
     const double coef = p.form.coef * ep;
@@ -166,18 +217,22 @@ __global__ void __launch_bounds__(kThreads) k_assemble_hex20(Q2Params p)
     const int64_t rs = p.row_ptr[row];
     const int64_t deg = p.nbr_ptr[va + 1] - p.nbr_ptr[va];
     T* K = (T*)p.K;
-    for (int b = 5 * quarter; b < 5 * quarter + 5; ++b) {
+    for (int b = NBQ * quarter; b < NBQ * quarter + NBQ; ++b) {
         double acc[NF];
 #pragma unroll
         for (int j = 0; j < NF; ++j) acc[j] = 0.0;
-        for (int q = 0; q < kNQ; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             const double W = S.W[q];
             if constexpr (FORM == MF_FORM_MASS) {
                 acc[0] = fma(W * coef * S.N[q][a], S.N[q][b], acc[0]);
             } else {
-                const double ga[3] = {S.g[q][a][0], S.g[q][a][1], S.g[q][a][2]};
-                const double gb[3] = {S.g[q][b][0], S.g[q][b][1], S.g[q][b][2]};
-                const double gg = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+                double ga[DIM], gb[DIM], gg = 0.0;
+#pragma unroll
+                for (int m = 0; m < DIM; ++m) {
+                    ga[m] = S.g[q][a][m];
+                    gb[m] = S.g[q][b][m];
+                    gg = fma(ga[m], gb[m], gg);
+                }
                 if constexpr (FORM == MF_FORM_POISSON) {
                     acc[0] = fma(W * coef, gg, acc[0]);
                 } else {
@@ -187,7 +242,7 @@ __global__ void __launch_bounds__(kThreads) k_assemble_hex20(Q2Params p)
                 }
             }
         }
-        const int64_t rk = p.rank[(int64_t)(a * 20 + b) * p.n_el + e];
+        const int64_t rk = p.rank[(int64_t)(a * NEN + b) * p.n_el + e];
 #pragma unroll
         for (int j = 0; j < NF; ++j) {
             const int64_t pos = p.field_major ? rs + j * deg + rk : rs + rk * NF + j;
@@ -197,13 +252,14 @@ __global__ void __launch_bounds__(kThreads) k_assemble_hex20(Q2Params p)
     if (quarter != 0) return;
     double dv = 0.0;
     const double cd = FORM == MF_FORM_MASS ? coef : 1.0;
-    for (int q = 0; q < kNQ; ++q) dv = fma(S.W[q] * cd * S.N[q][a], S.f[q][i], dv);
+    for (int q = 0; q < NQ; ++q) dv = fma(S.W[q] * cd * S.N[q][a], S.f[q][i], dv);
     ((T*)p.d)[row] += (T)dv;
 }
 
-int blocks_for(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }
+constexpr int kFillThreads = 256;
+int blocks_for(int64_t n) { return (int)((n + kFillThreads - 1) / kFillThreads); }
 
-template <int FORM, typename T>
+template <int DIM, int FORM, typename T>
 mf_status launch(const AssembleArgs& A)
 {
     const mf_pattern_s* P = A.P;
@@ -222,8 +278,8 @@ mf_status launch(const AssembleArgs& A)
     p.K = A.K;
     p.d = A.d;
     p.status = P->status;
-    if (P->nnz > 0) k_fill<T><<<blocks_for(P->nnz), kThreads, 0, A.stream>>>((T*)A.K, P->nnz);
-    if (P->n_rows > 0) k_fill<T><<<blocks_for(P->n_rows), kThreads, 0, A.stream>>>((T*)A.d, P->n_rows);
+    if (P->nnz > 0) k_fill<T><<<blocks_for(P->nnz), kFillThreads, 0, A.stream>>>((T*)A.K, P->nnz);
+    if (P->n_rows > 0) k_fill<T><<<blocks_for(P->n_rows), kFillThreads, 0, A.stream>>>((T*)A.d, P->n_rows);
     MF_HIP(hipGetLastError());
     if (P->n_elems == 0) return MF_OK;
     mf_status st = ensure_coloring(P, A.stream);
@@ -231,28 +287,30 @@ mf_status launch(const AssembleArgs& A)
     for (size_t c = 0; c + 1 < P->color_ptr.size(); ++c) {
         p.elems = P->color_elems + P->color_ptr[c];
         p.n_list = P->color_ptr[c + 1] - P->color_ptr[c];
-        if (p.n_list > 0) k_assemble_hex20<FORM, T><<<(unsigned)p.n_list, kThreads, 0, A.stream>>>(p);
+        if (p.n_list > 0)
+            k_assemble_quadratic<DIM, FORM, T><<<(unsigned)p.n_list, Elem<DIM>::THREADS, 0, A.stream>>>(p);
     }
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
 
-template <typename T>
+template <int DIM, typename T>
 mf_status dispatch(const AssembleArgs& A)
 {
     switch (A.form->kind) {
-        case MF_FORM_MASS: return launch<MF_FORM_MASS, T>(A);
-        case MF_FORM_POISSON: return launch<MF_FORM_POISSON, T>(A);
-        case MF_FORM_ELASTICITY: return launch<MF_FORM_ELASTICITY, T>(A);
-        default: return set_error(MF_ERR_UNSUPPORTED, "form %d on 20-node hexahedra", (int)A.form->kind);
+        case MF_FORM_MASS: return launch<DIM, MF_FORM_MASS, T>(A);
+        case MF_FORM_POISSON: return launch<DIM, MF_FORM_POISSON, T>(A);
+        case MF_FORM_ELASTICITY: return launch<DIM, MF_FORM_ELASTICITY, T>(A);
+        default: return set_error(MF_ERR_UNSUPPORTED, "form %d on serendipity elements", (int)A.form->kind);
     }
 }
 
 }  // namespace
 
-mf_status assemble_hex20(const AssembleArgs& A)
+mf_status assemble_quadratic(const AssembleArgs& A)
 {
-    return A.prec == MF_F64 ? dispatch<double>(A) : dispatch<float>(A);
+    if (A.P->dim == 3) return A.prec == MF_F64 ? dispatch<3, double>(A) : dispatch<3, float>(A);
+    return A.prec == MF_F64 ? dispatch<2, double>(A) : dispatch<2, float>(A);
 }
 
 }  // namespace mf

@@ -415,7 +415,7 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
     if (!P || !form) return set_error(MF_ERR_ARG, "pattern or form is NULL");
     if (P->dim != 3 || (P->nen != 8 && P->nen != 20))
         return set_error(MF_ERR_UNSUPPORTED, "boundary forms need a 3D hex pattern");
-    const bool quad = P->nen == 20;
+    const bool quad = P->order == 2;
     if (prec != MF_F64 && prec != MF_F32) return set_error(MF_ERR_ARG, "unknown precision %d", (int)prec);
     if (n_faces < 0 || n_faces > ((int64_t)1 << 28)) return set_error(MF_ERR_ARG, "n_faces out of range");
     if (n_faces > 0 && (!face_elem || !face_id || !coords || !K || !d))

@@ -12,6 +12,7 @@
 // Library-owned state of one pattern (Sec. 2.2 Block B).
 struct mf_pattern_s {
     int dim = 0, nen = 0, nf = 0;
+    int order = 1;  // element order: 2 for the serendipity elements
     mf_numbering numbering = MF_NODE_MAJOR;
     int64_t n_nodes = 0, n_elems = 0, n_rows = 0, nnz = 0, n_pairs = 0;
     uint8_t coupling[16] = {0};
@@ -68,7 +69,7 @@ struct AssembleArgs {
     hipStream_t stream;
 };
 mf_status assemble_atomic(const AssembleArgs& a);
-mf_status assemble_hex20(const AssembleArgs& a);
+mf_status assemble_quadratic(const AssembleArgs& a);  // assemble_hex20.hip: MF_HEX20, MF_QUAD8
 mf_status assemble_column(const AssembleArgs& a);
 mf_status apply_dirichlet(const AssembleArgs& a);
 mf_status reset_status(const mf_pattern_s* P, hipStream_t s);

@@ -1,5 +1,6 @@
-// The 20-node serendipity hexahedron (quadratic element of Sec. 4): shape functions and
-// reference gradients on [-1, 1]^3.  Local node order: corners a = ax + 2 ay + 4 az, then
+// The serendipity elements (quadratic elements of Sec. 4): shape functions and reference
+// gradients of the 20-node hexahedron on [-1, 1]^3 and of the 8-node quadrilateral on
+// [-1, 1]^2.  Local node order: corners a = ax + 2 ay + 4 az, then
 // the midpoints of the x-, y- and z-directed edges, four each, ordered by the bits of the
 // two other axes (ascending axis order).
 //   corner   N = (1/8)(1 + s_x x)(1 + s_y y)(1 + s_z z)(s_x x + s_y y + s_z z - 2)
@@ -34,6 +35,28 @@ __device__ __forceinline__ void shape20(int a, const double (&x)[3], double& N, 
     dN[ax] = -0.5 * x[ax] * h0 * h1;
     dN[o0] = 0.25 * g * s0 * h1;
     dN[o1] = 0.25 * g * h0 * s1;
+}
+
+// The 8-node serendipity quadrilateral: corners a = ax + 2 ay, then the x-edge midpoints
+// at y = -1, +1 and the y-edge midpoints at x = -1, +1.
+//   corner  N = (1/4)(1 + s_x x)(1 + s_y y)(s_x x + s_y y - 1)
+//   x-edge  N = (1/2)(1 - x^2)(1 + s_y y),   y-edge  N = (1/2)(1 - y^2)(1 + s_x x)
+__device__ __forceinline__ void shape8(int a, const double (&x)[2], double& N, double (&dN)[2])
+{
+    if (a < 4) {
+        const double sx = bit_sign(a & 1), sy = bit_sign(a >> 1);
+        const double fx = 1.0 + sx * x[0], fy = 1.0 + sy * x[1], t = sx * x[0] + sy * x[1] - 1.0;
+        N = 0.25 * fx * fy * t;
+        dN[0] = 0.25 * sx * fy * (t + fx);
+        dN[1] = 0.25 * sy * fx * (t + fy);
+        return;
+    }
+    const int ax = (a - 4) >> 1;  // 0: edge along x, 1: edge along y
+    const double s = bit_sign((a - 4) & 1);
+    const double g = 1.0 - x[ax] * x[ax], h = 1.0 + s * x[1 - ax];
+    N = 0.5 * g * h;
+    dN[ax] = -x[ax] * h;
+    dN[1 - ax] = 0.5 * g * s;
 }
 
 // Whether local node a lies on the face xi_axis = (side ? +1 : -1).
