@@ -416,6 +416,67 @@ def bench_hex20(dev, n=24, steps=10, warmup=3, cpu=True):
     return out
 
 
+def bench_cantilever(dev, cpu=True):
+    """The paper's 3D cantilever (Sec. 4.2): 10 x 4 x 4 quadratic bricks, L = 10, h = 1,
+    E = 1, nu = 0, the face x = 0 clamped, a unit end load as a uniform shear traction on
+    x = L.  Timed: assembly, the traction, and Jacobi-PCG to the attainable 1e-9.  The
+    centre-line deflection is compared with the Euler-Bernoulli closed form
+    -P x^2 (3L - x) / (6 E I), I = h^4 / 12."""
+    import torch
+    import workloads as W
+    import paper_2111_03541_amd as mf
+    n, L = (10, 4, 4), 10.0
+    mesh = W.serendipity_mesh(n, lengths=[L, 1.0, 1.0])
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 3)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    clamp = torch.from_numpy(np.repeat(np.abs(mesh.coords[0]) < 1e-12, 3).astype(np.uint8)).to(dev)
+    fe, fi = (torch.from_numpy(a).to(dev) for a in W.box_faces(n, sides=[1]))
+    sig = [0.0, 0.0, 0.0, -1.0, 0.0, 0.0, 0.0, 0.0, 0.0]
+    rp, ci, _ = pat.device_arrays()
+    form = mf.Form(mf.ELASTICITY, coef=1.0, nu=0.0)
+
+    def solve():
+        K, d = pat.assemble(form, coords, dirichlet=clamp)
+        pat.assemble_boundary(mf.BFORM_TRACTION, coords, fe, fi, value=sig, K=K, d=d)
+        return mf.pcg(rp, ci, K, d, tol=1e-9, maxit=20000)
+
+    solve()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        x, res = solve()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    u = x.cpu().numpy().reshape(-1, 3)
+    c = mesh.coords
+    line = np.nonzero((np.abs(c[1] - 0.5) < 1e-12) & (np.abs(c[2] - 0.5) < 1e-12))[0]
+    xs = c[0, line]
+    beam = -xs ** 2 * (3 * L - xs) / (6 * (1.0 / 12.0))
+    err = float(np.abs(u[line, 1] - beam).max() / np.abs(beam).max())
+    out = {"n_elems": mesh.n_elems, "n_dofs": pat.n_rows, "ms": float(np.median(times)) * 1e3,
+           "pcg_iterations": res["iterations"], "tip_deflection": float(u[line, 1][np.argmax(xs)]),
+           "beam_tip": float(beam[np.argmax(xs)]), "max_err_vs_beam_over_tip": err}
+    log(f"[bench] cantilever 10x4x4 hex20: {out['ms']:.2f} ms, {res['iterations']} PCG it, "
+        f"tip {out['tip_deflection']:.1f} vs beam {out['beam_tip']:.1f}")
+    if cpu:
+        import scipy.sparse.linalg as spla
+        import oracle as O
+        import oracle.boundary as OB
+        import oracle.serendipity as S
+        t0 = time.perf_counter()
+        op = S.Pattern20(mesh, 3)
+        Kr = op.to_scipy(S.assemble20(op, O.ELASTICITY, {"coef": 1.0, "nu": 0.0})[0])
+        sg = np.zeros((3, 3))
+        sg[1, 0] = -1.0
+        _, dr = S.assemble_boundary20(op, OB.TRACTION, 1.0, sg.reshape(-1), *W.box_faces(n, sides=[1]))
+        free = np.abs(np.repeat(mesh.coords[0], 3)) > 1e-12
+        spla.spsolve(Kr[free][:, free].tocsc(), dr[free])
+        out["cpu_oracle"] = {"ms": (time.perf_counter() - t0) * 1e3, "cores": 1,
+                             "kind": "oracle (numpy element loop, scipy direct solve)"}
+    return out
+
+
 def cpu_baseline(mesh, E, b):
     import oracle as O
     t0 = time.perf_counter()
@@ -538,6 +599,7 @@ def main():
     record["secondary"]["ns_newton_cavity_32"] = bench_newton(dev, cpu=not args.no_cpu)
     record["secondary"]["transient_96"] = bench_transient(dev, cpu=not args.no_cpu)
     record["secondary"]["hex20_elasticity_24"] = bench_hex20(dev, cpu=not args.no_cpu)
+    record["secondary"]["cantilever_hex20_10x4x4"] = bench_cantilever(dev, cpu=not args.no_cpu)
     if not args.no_cpu:
         log("[bench] timing the oracle on the host")
         record["cpu_baseline"] = cpu_baseline(mesh, E, b)
