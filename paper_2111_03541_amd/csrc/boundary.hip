@@ -73,14 +73,13 @@ __device__ __forceinline__ bool inverse_jacobian(const double (&J)[3][3], double
 template <int NF>
 constexpr int kRowNodes = NF == 4 ? 8 : 4;
 
-template <int NF, typename T>
-__global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
+// Row (a, i) of face f.  FI >= 0 fixes the field at compile time (the flow forms, so
+// that every per-field array index is static); FI < 0 takes the runtime field fi, and
+// then only field fi of the state and target and the (a, fi) x (b, fi) block are held.
+template <int NF, int FI, typename T>
+__device__ __forceinline__ void boundary_row(const BParams& p, int64_t f, int ki, int kf, int fi)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= p.n_faces * kRowNodes<NF> * NF) return;
-    const int64_t f = t % p.n_faces;
-    const int ki = (int)(t / p.n_faces);
-    const int kf = ki / NF, i = ki % NF;
+    const int i = FI >= 0 ? FI : fi;
     const int64_t e = p.face_elem[f];
     const int fid = p.face_id[f];
     if (e < 0 || e >= p.n_el || fid > 5) {  // skipped, and reported by mf_status_poll
@@ -93,9 +92,13 @@ __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
     auto fnode = [&](int k) { return (side << axis) | ((k & 1) << u) | ((k >> 1) << v); };
     const int a = NF == 4 ? kf : fnode(kf);
 
+    // fields of the state and target held: all four for the flow forms, else the
+    // thread's own field i (slot li)
+    constexpr int NL = NF == 4 ? 4 : 1;
+    const int li = NL == 1 ? 0 : i;
     int32_t node[8];
     double x[8][3];
-    double U[8][NF], G[8][NF];
+    double U[8][NL], G[8][NL];
     const T* st = (const T*)p.state;
     const T* tg = (const T*)p.target;
 #pragma unroll
@@ -104,18 +107,20 @@ __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
 #pragma unroll
         for (int m = 0; m < 3; ++m) x[b][m] = p.coords[(int64_t)m * p.n_nodes + node[b]];
 #pragma unroll
-        for (int j = 0; j < NF; ++j) {
-            U[b][j] = st ? (double)st[(int64_t)j * p.n_nodes + node[b]] : 0.0;
-            G[b][j] = tg ? (double)tg[(int64_t)j * p.n_nodes + node[b]] : p.form.value[j];
+        for (int l = 0; l < NL; ++l) {
+            const int j = NL == 1 ? i : l;
+            U[b][l] = st ? (double)st[(int64_t)j * p.n_nodes + node[b]] : 0.0;
+            G[b][l] = tg ? (double)tg[(int64_t)j * p.n_nodes + node[b]] : p.form.value[j];
         }
     }
     const mf_bform_kind kind = p.form.kind;
     const double c = p.form.coef;
-    double krow[8][NF];
+    constexpr int KC = NL;  // columns held per node: all fields, or field i alone (slot li)
+    double krow[8][KC];
 #pragma unroll
     for (int b = 0; b < 8; ++b)
 #pragma unroll
-        for (int j = 0; j < NF; ++j) krow[b][j] = 0.0;
+        for (int j = 0; j < KC; ++j) krow[b][j] = 0.0;
     double rrow = 0.0;
 
     for (int q = 0; q < 4; ++q) {
@@ -152,9 +157,9 @@ __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
         const double nv[3] = {nr[0] / dS, nr[1] / dS, nr[2] / dS};
         const double w = dS;  // unit Gauss weights on [-1, 1]^2
         const double Na = N[a];
-        double uq[NF], gq[NF];
+        double uq[NL], gq[NL];
 #pragma unroll
-        for (int j = 0; j < NF; ++j) {
+        for (int j = 0; j < NL; ++j) {
             uq[j] = 0.0;
             gq[j] = 0.0;
 #pragma unroll
@@ -218,18 +223,18 @@ __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
         } else if (kind == MF_BFORM_PENALTY || kind == MF_BFORM_CONVECTION) {
             // R = int c N_a (u_i - g_i)
 #pragma unroll
-            for (int b = 0; b < 8; ++b) krow[b][i] += c * w * Na * N[b];
-            rrow += c * w * Na * (uq[i] - gq[i]);
+            for (int b = 0; b < 8; ++b) krow[b][li] += c * w * Na * N[b];
+            rrow += c * w * Na * (uq[li] - gq[li]);
         } else if (kind == MF_BFORM_RADIATION) {
             // R = int c N_a (T^4 - T_env^4), c = e_m sigma
             const double T1 = uq[0], Te = gq[0];
 #pragma unroll
-            for (int b = 0; b < 8; ++b) krow[b][0] += c * w * Na * 4.0 * T1 * T1 * T1 * N[b];
+            for (int b = 0; b < 8; ++b) krow[b][li] += c * w * Na * 4.0 * T1 * T1 * T1 * N[b];
             rrow += c * w * Na * (T1 * T1 * T1 * T1 - Te * Te * Te * Te);
         } else if (kind == MF_BFORM_TRACTION) {
             // R = -int N_a t_i, t = sigma^l n or the interpolated nodal traction
             const double* S = p.form.value;
-            const double ti = tg ? gq[i] : S[3 * i] * nv[0] + S[3 * i + 1] * nv[1] + S[3 * i + 2] * nv[2];
+            const double ti = tg ? gq[li] : S[3 * i] * nv[0] + S[3 * i + 1] * nv[1] + S[3 * i + 2] * nv[2];
             rrow -= w * Na * ti;
         } else {  // MF_BFORM_FLUX: R = -int c N_a n . grad T
             double Ji[3][3];
@@ -244,8 +249,8 @@ __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
 #pragma unroll
                 for (int m = 0; m < 3; ++m)
                     ng += nv[m] * (Ji[0][m] * dN[b][0] + Ji[1][m] * dN[b][1] + Ji[2][m] * dN[b][2]);
-                krow[b][0] -= c * w * Na * ng;
-                ngT = fma(ng, U[b][0], ngT);
+                krow[b][li] -= c * w * Na * ng;
+                ngT = fma(ng, U[b][li], ngT);
             }
             rrow -= c * w * Na * ngT;
         }
@@ -260,17 +265,38 @@ __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
     for (int b = 0; b < 8; ++b) {
         bool any = false;
 #pragma unroll
-        for (int j = 0; j < NF; ++j) any = any || krow[b][j] != 0.0;
+        for (int l = 0; l < KC; ++l) any = any || krow[b][l] != 0.0;
         if (!any) continue;
         const int64_t rk = p.rank[(int64_t)(a * 8 + b) * p.n_el + e];
 #pragma unroll
-        for (int j = 0; j < NF; ++j) {
-            if (krow[b][j] == 0.0) continue;
+        for (int l = 0; l < KC; ++l) {
+            if (krow[b][l] == 0.0) continue;
+            const int j = KC == 1 ? i : l;
             const int64_t pos = p.field_major ? rs + j * deg + rk : rs + rk * NF + j;
-            unsafeAtomicAdd(K + pos, (T)krow[b][j]);
+            unsafeAtomicAdd(K + pos, (T)krow[b][l]);
         }
     }
     if (rrow != 0.0) unsafeAtomicAdd(d + row, (T)(-rrow));
+}
+
+template <int NF, typename T>
+__global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p.n_faces * kRowNodes<NF> * NF) return;
+    const int64_t f = t % p.n_faces;
+    const int ki = (int)(t / p.n_faces);
+    const int kf = ki / NF, i = ki % NF;
+    if constexpr (NF == 4) {
+        switch (i) {
+            case 0: boundary_row<NF, 0, T>(p, f, ki, kf, i); break;
+            case 1: boundary_row<NF, 1, T>(p, f, ki, kf, i); break;
+            case 2: boundary_row<NF, 2, T>(p, f, ki, kf, i); break;
+            default: boundary_row<NF, 3, T>(p, f, ki, kf, i); break;
+        }
+    } else {
+        boundary_row<NF, -1, T>(p, f, ki, kf, i);
+    }
 }
 
 // Faces of 20-node hexahedra: one thread per (face f, face node k, field i), with the
