@@ -350,9 +350,8 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
     } else if constexpr (FORM == MF_FORM_MASS) {
         hq[0] = (T)det;
     } else {
-        const double r = 1.0 / det;
-        double A[3][3];  // sqrt(det) * J^-1, with (J^-1)_{jm} = cofactor_{mj} / det
-        const double s = sqrt(det) * r;
+        double A[3][3];  // sqrt(det) * J^-1 = cofactor^T / sqrt(det): one reciprocal square root
+        const double s = rsqrt(det);
         A[0][0] = c00 * s;
         A[1][0] = c01 * s;
         A[2][0] = c02 * s;
