@@ -89,6 +89,7 @@ struct ColParams {
     void* K;
     void* d;
     unsigned long long* status;
+    double lam_f, mu_f;  // elasticity: lambda = E lam_f, mu = E mu_f (from nu, on the host)
 };
 
 // Row-buffer accumulators: FP64 for the symmetric forms in both precisions, FP32 for the
@@ -271,9 +272,9 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
     const double ep = FORM == MF_FORM_NS_SUPG ? 1.0 : S.ep[slot][el];
     double coefA = 0.0, coefB = 0.0;
     if constexpr (FORM == MF_FORM_ELASTICITY) {
-        const double E = p.form.coef * ep, nu = p.form.nu;
-        coefA = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
-        coefB = E / (2.0 * (1.0 + nu));
+        const double E = p.form.coef * ep;
+        coefA = E * p.lam_f;
+        coefB = E * p.mu_f;
     } else {
         coefA = p.form.coef * ep;
     }
@@ -860,6 +861,9 @@ ColParams make_params(const AssembleArgs& A)
     p.d = A.d;
     p.status = P->status;
     p.lz = p.nz + 1;
+    const double nu = A.form->nu;
+    p.lam_f = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    p.mu_f = 1.0 / (2.0 * (1.0 + nu));
     return p;
 }
 
