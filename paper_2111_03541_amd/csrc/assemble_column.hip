@@ -280,8 +280,9 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
     }
     T* hq = S.h + slot * HLayout<FORM, T>::SL + el * HLayout<FORM, T>::SE + q * HLayout<FORM, T>::SQ;
     if constexpr (FORM == MF_FORM_NS_SUPG) {
-        // g = J^-T grad_xi N (FP64); state at the point: u, grad u, p, grad p, Rm, div u
-        const double r = 1.0 / det;
+        // g = J^-T grad_xi N (FP64); state at the point: u, grad u, p, grad p, Rm, div u.
+        // 1/det and sqrt(det) both from one reciprocal square root
+        const double rs = rsqrt(det), r = rs * rs;
         double Ji[3][3];
         Ji[0][0] = c00 * r;
         Ji[1][0] = c01 * r;
@@ -319,7 +320,7 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
             for (int k = 0; k < 3; ++k) gp[k] = fma(g[k], Pb, gp[k]);
         }
         const double rho = p.form.rho;
-        const double sw = sqrt(det);
+        const double sw = det * rs;
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
             double g[3];
