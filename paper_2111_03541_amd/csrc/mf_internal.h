@@ -69,7 +69,7 @@ struct AssembleArgs {
     hipStream_t stream;
 };
 mf_status assemble_atomic(const AssembleArgs& a);
-mf_status assemble_quadratic(const AssembleArgs& a);  // assemble_hex20.hip: MF_HEX20, MF_QUAD8
+mf_status assemble_quadratic(const AssembleArgs& a);  // assemble_quadratic.hip: MF_HEX20, MF_QUAD8
 mf_status assemble_column(const AssembleArgs& a);
 mf_status apply_dirichlet(const AssembleArgs& a);
 mf_status reset_status(const mf_pattern_s* P, hipStream_t s);
