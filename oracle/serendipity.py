@@ -1,5 +1,5 @@
-"""Oracle: 20-node serendipity hexahedra and 8-node serendipity quadrilaterals (quadratic
-elements) in plain numpy.
+"""Oracle: quadratic elements in plain numpy: 20-node serendipity hexahedra, 8-node
+serendipity quadrilaterals and 10-node tetrahedra.
 
 TEST INFRASTRUCTURE ONLY.  Only `tests/`, the smoke check and the benchmark's CPU
 baseline leg may import this module; the product library never does.
@@ -11,8 +11,9 @@ then the x-, y- and z-edge midpoints).  Shape functions, with s the corner signs
   corner   N = (1/8)(1 + s_x x)(1 + s_y y)(1 + s_z z)(s_x x + s_y y + s_z z - 2)
   x-edge   N = (1/4)(1 - x^2)(1 + s_y y)(1 + s_z z)       (and cyclically for y, z)
 Quadrature: 3 Gauss points per axis, +-sqrt(3/5) and 0 with weights 5/9 and 8/9.  The
-8-node quadrilateral (basis8) is the same construction in 2D; assemble20 and Pattern20
-take either mesh.
+8-node quadrilateral (basis8) is the same construction in 2D; the 10-node tetrahedron
+(basis10) uses the collapsed 64-point rule gauss_tet; assemble20 and Pattern20 take any
+of these meshes.
 Forms as the Q1 oracle defines them at the zero state (Sec. 4.1, 4.2; K = dR/dU, d = -R):
   mass        K = int c N_a N_b,                        d = int c N_a f
   conduction  K = int c grad N_a . grad N_b,            d = int N_a f
@@ -84,6 +85,41 @@ def basis8(xi):
     return N, dN
 
 
+def basis10(xi):
+    """N [10], dN [10][3] of the 10-node quadratic tetrahedron at the reference point xi
+    (reference tetrahedron xi >= 0, xi_1 + xi_2 + xi_3 <= 1).  Barycentric coordinates
+    l_0 = 1 - xi_1 - xi_2 - xi_3, l_k = xi_k; vertices N_i = l_i (2 l_i - 1), edge
+    midpoints N_ij = 4 l_i l_j for the edges (0,1), (1,2), (2,0), (0,3), (1,3), (2,3)."""
+    x = np.asarray(xi, dtype=np.float64)
+    lam = np.array([1.0 - x.sum(), x[0], x[1], x[2]])
+    dlam = np.array([[-1.0, -1.0, -1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    N = np.zeros(10)
+    dN = np.zeros((10, 3))
+    for i in range(4):
+        N[i] = lam[i] * (2.0 * lam[i] - 1.0)
+        dN[i] = (4.0 * lam[i] - 1.0) * dlam[i]
+    for m, (i, j) in enumerate([(0, 1), (1, 2), (2, 0), (0, 3), (1, 3), (2, 3)]):
+        N[4 + m] = 4.0 * lam[i] * lam[j]
+        dN[4 + m] = 4.0 * (lam[i] * dlam[j] + lam[j] * dlam[i])
+    return N, dN
+
+
+def gauss_tet():
+    """64-point rule on the reference tetrahedron: the 4-point Gauss-Legendre rule on each
+    axis of the unit cube, collapsed onto the tetrahedron by xi_1 = u, xi_2 = v (1 - u),
+    xi_3 = w (1 - u)(1 - v) with Jacobian (1 - u)^2 (1 - v); exact for total degree 5."""
+    g, gw = np.polynomial.legendre.leggauss(4)
+    t, tw = 0.5 * (g + 1.0), 0.5 * gw
+    pts, wts = [], []
+    for k in range(4):
+        for j in range(4):
+            for i in range(4):
+                u, v, w = t[i], t[j], t[k]
+                pts.append([u, v * (1.0 - u), w * (1.0 - u) * (1.0 - v)])
+                wts.append(tw[i] * tw[j] * tw[k] * (1.0 - u) ** 2 * (1.0 - v))
+    return np.array(pts), np.array(wts)
+
+
 def gauss3_2d():
     p = np.sqrt(3.0 / 5.0)
     pts, wts = np.array([-p, 0.0, p]), np.array([5.0, 8.0, 5.0]) / 9.0
@@ -141,8 +177,13 @@ def assemble20(pat: Pattern20, kind, params=None, elem_param=None, nodal_src=Non
     prm.update(params or {})
     mesh, nf = pat.mesh, pat.nf
     dim, nen = mesh.dim, mesh.nen
-    xi, w = gauss3() if dim == 3 else gauss3_2d()
-    tables = [(basis20 if dim == 3 else basis8)(x) for x in xi]
+    if nen == 10:
+        xi, w = gauss_tet()
+        basis = basis10
+    else:
+        xi, w = gauss3() if dim == 3 else gauss3_2d()
+        basis = basis20 if dim == 3 else basis8
+    tables = [basis(x) for x in xi]
     rows, cols, vals = [], [], []
     d = np.zeros(pat.n_rows)
     for e in range(mesh.n_elems):

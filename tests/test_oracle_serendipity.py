@@ -291,3 +291,70 @@ def test_quad8_elasticity_rigid_modes():
     lam, mu = 0.3 / (1.3 * 0.4), 1.0 / 2.6
     right = np.abs(mesh.coords[0] - 1.0) < 1e-12
     assert abs(F[right, 0].sum() - (lam + 2 * mu)) < 1e-12
+
+
+# ---------------------------------------------------------------- 10-node tetrahedra
+
+TET_NODES = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1],
+                      [0.5, 0, 0], [0.5, 0.5, 0], [0, 0.5, 0], [0, 0, 0.5], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+
+
+def test_tet10_basis_and_rule():
+    import math
+    for a in range(10):
+        N, _ = S.basis10(TET_NODES[a])
+        assert np.abs(N - np.eye(10)[a]).max() < 1e-15
+    rng = np.random.default_rng(3)
+    for _ in range(10):
+        x = rng.dirichlet(np.ones(4))[1:]
+        N, dN = S.basis10(x)
+        assert abs(N.sum() - 1.0) < 1e-14 and np.abs(dN.sum(axis=0)).max() < 1e-14
+        assert np.abs(N @ TET_NODES - x).max() < 1e-14 and np.abs(TET_NODES.T @ dN - np.eye(3)).max() < 1e-14
+        for f in (lambda p: p[0] ** 2, lambda p: p[0] * p[2], lambda p: p[1] * p[2], lambda p: p[2] ** 2):
+            assert abs(N @ np.array([f(p) for p in TET_NODES]) - f(x)) < 1e-14
+        for d in range(3):
+            h = np.zeros(3)
+            h[d] = 1e-6
+            fd = (S.basis10(x + h)[0] - S.basis10(x - h)[0]) / 2e-6
+            assert np.abs(fd - dN[:, d]).max() < 1e-8
+    # the collapsed rule against the closed form a! b! c! / (a + b + c + 3)! up to degree 5
+    xq, wq = S.gauss_tet()
+    for a in range(6):
+        for b in range(6 - a):
+            for c in range(6 - a - b):
+                exact = math.factorial(a) * math.factorial(b) * math.factorial(c) / math.factorial(a + b + c + 3)
+                got = (wq * xq[:, 0] ** a * xq[:, 1] ** b * xq[:, 2] ** c).sum()
+                assert abs(got - exact) < 1e-15, (a, b, c)
+
+
+def test_tet10_mesh_volume_pattern_and_patch_tests():
+    L = [1.0, 1.3, 0.7]
+    mesh = W.tet10_mesh((2, 3, 2), jitter=0.2, seed=4, lengths=L)
+    assert mesh.nen == 10 and mesh.n_elems == 6 * 12
+    pat = S.Pattern20(mesh, 1)
+    M, d = S.assemble20(pat, O.MASS, {"coef": 1.0}, nodal_src=np.ones((1, mesh.n_nodes)))
+    vol = L[0] * L[1] * L[2]
+    assert abs(M.sum() - vol) < 1e-14 and abs(d.sum() - vol) < 1e-14
+    Sm = pat.to_scipy(np.ones(pat.nnz))
+    assert (Sm != Sm.T).nnz == 0
+    K = pat.to_scipy(S.assemble20(pat, O.POISSON, {"coef": 1.0})[0])
+    Mm = pat.to_scipy(M)
+    c = mesh.coords
+    hi = np.array(L)[:, None]
+    interior = np.all((c > 1e-12) & (c < hi - 1e-12), axis=0)
+    assert np.abs((K @ (0.3 * c[0] - 0.8 * c[1] + 1.1 * c[2]))[interior]).max() < 1e-13
+    # every element map is affine, so quadratic fields pass on the jittered mesh too
+    u = c[0] ** 2 + 2.0 * c[1] * c[2] - 0.5 * c[2] ** 2 + c[0] * c[1]  # lap u = 2 - 1 = 1
+    assert np.abs((K @ u + Mm @ np.ones(mesh.n_nodes))[interior]).max() < 1e-12
+
+
+def test_tet10_elasticity_rigid_modes():
+    mesh = W.tet10_mesh((2, 2, 1), jitter=0.2, seed=5)
+    pat = S.Pattern20(mesh, 3)
+    E = W.lognormal_elem(mesh.n_elems, 0.5, 6)
+    Km = pat.to_scipy(S.assemble20(pat, O.ELASTICITY, {"coef": 2.0, "nu": 0.3}, elem_param=E)[0])
+    assert abs(Km - Km.T).max() < 1e-12 * abs(Km).max()
+    x, y, z = mesh.coords
+    one, zero = np.ones_like(x), np.zeros_like(x)
+    for m in ((one, zero, zero), (zero, one, zero), (zero, zero, one), (-y, x, zero), (zero, -z, y), (z, zero, -x)):
+        assert np.abs(Km @ np.stack(m, axis=1).reshape(-1)).max() < 1e-12 * abs(Km).max()

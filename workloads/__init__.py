@@ -324,6 +324,56 @@ def serendipity_mesh_2d(n, jitter: float = 0.0, seed=None, lengths=None) -> Mesh
     return Mesh(coords, conn)
 
 
+# Kuhn triangulation of a cube: for each ordering (p0, p1, p2) of the axes, the tetrahedron
+# with vertices 0, e_p0, e_p0 + e_p1, (1, 1, 1) (corner bits as in structured_mesh).
+_KUHN = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+TET10_EDGES = [(0, 1), (1, 2), (2, 0), (0, 3), (1, 3), (2, 3)]
+
+
+def tet10_mesh(n, jitter: float = 0.0, seed=None, lengths=None) -> Mesh:
+    """Quadratic tetrahedra (10 nodes) filling a structured box of n = (nx, ny, nz) cubes.
+
+    Each cube splits into the six Kuhn tetrahedra around its main diagonal, which match
+    across cube faces; vertices are ordered so that every tetrahedron is positively
+    oriented.  Nodes: the corner lattice of structured_mesh (jittered the same way), then
+    one midpoint per edge, numbered in order of first appearance.  Local nodes: vertices
+    0..3, then the midpoints of the edges (0,1), (1,2), (2,0), (0,3), (1,3), (2,3).
+    Midpoints sit at the middle of straight edges, so every element map is affine."""
+    nx, ny, nz = (int(v) for v in n)
+    base = structured_mesh((nx, ny, nz), jitter=jitter, seed=seed, lengths=lengths)
+    X = base.coords
+    NX, NY = nx + 1, ny + 1
+    cid = lambda i, j, k: i + NX * (j + NY * k)
+    verts = []
+    for ez in range(nz):
+        for ey in range(ny):
+            for ex in range(nx):
+                for perm in _KUHN:
+                    c = [0, 0, 0]
+                    tet = [cid(ex, ey, ez)]
+                    for ax in perm:
+                        c[ax] = 1
+                        tet.append(cid(ex + c[0], ey + c[1], ez + c[2]))
+                    P = X[:, tet]
+                    if np.linalg.det(np.stack([P[:, m] - P[:, 0] for m in (1, 2, 3)], axis=1)) < 0.0:
+                        tet[1], tet[2] = tet[2], tet[1]
+                    verts.append(tet)
+    edge_id = {}
+    mids = []
+    conn = np.zeros((10, len(verts)), dtype=np.int64)
+    n_c = X.shape[1]
+    for e, tet in enumerate(verts):
+        conn[:4, e] = tet
+        for m, (a, b) in enumerate(TET10_EDGES):
+            key = (min(tet[a], tet[b]), max(tet[a], tet[b]))
+            if key not in edge_id:
+                edge_id[key] = n_c + len(mids)
+                mids.append(0.5 * (X[:, key[0]] + X[:, key[1]]))
+            conn[4 + m, e] = edge_id[key]
+    coords = np.concatenate([X, np.array(mids).T], axis=1)
+    return Mesh(coords, conn.astype(np.int32))
+
+
 def box_faces(n, sides=None):
     """Element faces on the sides of a structured 3D box mesh of n = (nx, ny, nz) elements.
 
