@@ -55,10 +55,14 @@ typedef enum {
                        the bits of the two other axes; mass, conduction and elasticity forms
                        with 3 Gauss points per axis (element colours, one workgroup per
                        element)                                                              */
-    MF_QUAD8 = 4    /* 8-node serendipity quadrilateral, order 2: corners as MF_QUAD4, then the
+    MF_QUAD8 = 4,   /* 8-node serendipity quadrilateral, order 2: corners as MF_QUAD4, then the
                        midpoints of the x-directed edges at y = -1, +1 and of the y-directed
                        edges at x = -1, +1; the forms of MF_HEX20 (plane-strain elasticity)
                        with 3 Gauss points per axis                                          */
+    MF_TET10 = 5    /* 10-node quadratic tetrahedron, order 2: vertices 0..3 (positively
+                       oriented), then the midpoints of the edges (0,1), (1,2), (2,0), (0,3),
+                       (1,3), (2,3); the forms of MF_HEX20 with the 64-point collapsed Gauss
+                       rule (points_per_axis = 4)                                            */
 } mf_elem_type;
 /* DOF numbering.  Field-major is the paper's map (Sec. 2.2 B-3): dof = field*n_nodes + node.
    Node-major interleaves the fields of a node: dof = n_fields*node + field. */
@@ -75,7 +79,7 @@ typedef enum {
 typedef enum { MF_F64 = 0, MF_F32 = 1 } mf_precision;
 
 typedef struct {
-    int32_t dim;           /* 2 (MF_QUAD4, MF_QUAD8) or 3 (MF_HEX8, MF_HEX20) */
+    int32_t dim;           /* 2 (MF_QUAD4, MF_QUAD8) or 3 (MF_HEX8, MF_HEX20, MF_TET10) */
     int64_t n_nodes;
     int64_t n_elems;
     const int32_t* conn;   /* [nen][n_elems] (device) */

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmf.so")
 # enums of mf.h
 OK, ERR_ARG, ERR_UNSUPPORTED, ERR_OVERFLOW, ERR_HIP, ERR_BAD_JACOBIAN, ERR_NONFINITE, \
     ERR_NOT_CONVERGED, ERR_OOM, ERR_BAD_MESH = range(10)
-QUAD4, HEX8, HEX20, QUAD8 = 1, 2, 3, 4
+QUAD4, HEX8, HEX20, QUAD8, TET10 = 1, 2, 3, 4, 5
 NODE_MAJOR, FIELD_MAJOR = 0, 1
 MASS, POISSON, ELASTICITY, NS_SUPG = 0, 1, 2, 3
 F64, F32 = 0, 1
@@ -215,11 +215,11 @@ class Pattern:
         h = C.c_void_p()
         if elem is None:
             if dim == 3:
-                elem = HEX20 if conn.shape[0] == 20 else HEX8
+                elem = {20: HEX20, 10: TET10}.get(int(conn.shape[0]), HEX8)
             else:
                 elem = QUAD8 if conn.shape[0] == 8 else QUAD4
         self.elem = elem
-        check(lib.mf_pattern(C.byref(mesh), elem, 2 if elem in (HEX20, QUAD8) else 1, C.byref(dofs),
+        check(lib.mf_pattern(C.byref(mesh), elem, 2 if elem in (HEX20, QUAD8, TET10) else 1, C.byref(dofs),
                              _stream(stream), C.byref(h)))
         self._h = h
         n_rows, nnz = C.c_int64(), C.c_int64()
@@ -250,7 +250,7 @@ class Pattern:
         rp, ci, rk = C.c_void_p(), C.c_void_p(), C.c_void_p()
         check(lib.mf_pattern_info(self._h, None, None, C.byref(rp), C.byref(ci), C.byref(rk)))
         torch.cuda.synchronize()
-        nen = {HEX20: 20, QUAD8: 8}.get(self.elem, 1 << self.dim)
+        nen = {HEX20: 20, QUAD8: 8, TET10: 10}.get(self.elem, 1 << self.dim)
         out = []
         for ptr, n, dt in ((rp, self.n_rows + 1, np.int32), (ci, self.nnz, np.int32),
                            (rk, nen * nen * self.n_elems, np.uint8)):
@@ -286,7 +286,7 @@ class Pattern:
         if dirichlet is not None:
             assert dirichlet.dtype == torch.uint8 and dirichlet.is_cuda
         f = _Fields(_ptr(elem_param), _ptr(nodal_src), _ptr(lin_state), _ptr(dirichlet))
-        q = _Quad(points_per_axis or (3 if self.elem in (HEX20, QUAD8) else 2))
+        q = _Quad(points_per_axis or {HEX20: 3, QUAD8: 3, TET10: 4}.get(self.elem, 2))
         check(lib.mf_assemble_ex(self._h, C.byref(form.c), _ptr(coords), C.byref(f), C.byref(q), precision,
                                  scatter, _ptr(K), _ptr(d), _stream(stream)))
         return K, d

@@ -65,9 +65,9 @@ mf_status mf_pattern(const mf_mesh* mesh, mf_elem_type type, int32_t order, cons
     if (!out) return set_error(MF_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (!mesh || !dofs) return set_error(MF_ERR_ARG, "mesh or dofs is NULL");
-    if (type != MF_QUAD4 && type != MF_HEX8 && type != MF_HEX20 && type != MF_QUAD8)
+    if (type != MF_QUAD4 && type != MF_HEX8 && type != MF_HEX20 && type != MF_QUAD8 && type != MF_TET10)
         return set_error(MF_ERR_UNSUPPORTED, "element type %d", (int)type);
-    const int elem_order = (type == MF_HEX20 || type == MF_QUAD8) ? 2 : 1;
+    const int elem_order = (type == MF_HEX20 || type == MF_QUAD8 || type == MF_TET10) ? 2 : 1;
     if (order != elem_order)
         return set_error(MF_ERR_UNSUPPORTED, "element order %d for element type %d", (int)order, (int)type);
     const int dim = (type == MF_QUAD4 || type == MF_QUAD8) ? 2 : 3;
@@ -77,7 +77,7 @@ mf_status mf_pattern(const mf_mesh* mesh, mf_elem_type type, int32_t order, cons
     if (dofs->n_fields < 1 || dofs->n_fields > 4) return set_error(MF_ERR_ARG, "n_fields %d not in 1..4", (int)dofs->n_fields);
     if (dofs->numbering != MF_NODE_MAJOR && dofs->numbering != MF_FIELD_MAJOR)
         return set_error(MF_ERR_ARG, "unknown numbering %d", (int)dofs->numbering);
-    const int nen = type == MF_HEX20 ? 20 : (type == MF_QUAD8 ? 8 : 1 << dim);
+    const int nen = type == MF_HEX20 ? 20 : type == MF_QUAD8 ? 8 : type == MF_TET10 ? 10 : 1 << dim;
     if ((int64_t)nen * nen * mesh->n_elems >= ((int64_t)1 << 31) || mesh->n_nodes * dofs->n_fields >= ((int64_t)1 << 31))
         return set_error(MF_ERR_OVERFLOW, "mesh too large for int32 indices");
 
@@ -160,7 +160,7 @@ mf_status mf_assemble_ex(const mf_pattern_t* P, const mf_form* form, const doubl
 {
     g_err[0] = 0;
     if (!P || !form || !quad) return set_error(MF_ERR_ARG, "pattern, form or quadrature is NULL");
-    const int want_q = P->order == 2 ? 3 : 2;
+    const int want_q = P->nen == 10 && P->dim == 3 ? 4 : (P->order == 2 ? 3 : 2);
     if (quad->points_per_axis != want_q)
         return set_error(MF_ERR_UNSUPPORTED, "%d Gauss points per axis (this element takes %d)",
                          (int)quad->points_per_axis, want_q);

@@ -26,38 +26,67 @@
 namespace mf {
 namespace {
 
-constexpr int kQuarters = 4;  // the column nodes b of a row, in four groups
+enum ElemKind { kHex20 = 0, kQuad8 = 1, kTet10 = 2 };
 
-template <int DIM>
-struct Elem {
-    static constexpr int NEN = DIM == 3 ? 20 : 8;  // nodes
-    static constexpr int NQ = DIM == 3 ? 27 : 9;   // Gauss points
-    static constexpr int THREADS = DIM == 3 ? 256 : 64;
+// Per element type: dimension, nodes, Gauss points, threads per workgroup, and the number
+// of groups the column nodes of a row are split into (one lane per row and group).
+template <int ET>
+struct Elem;
+template <>
+struct Elem<kHex20> {
+    static constexpr int DIM = 3, NEN = 20, NQ = 27, THREADS = 256, NPART = 4;
+};
+template <>
+struct Elem<kQuad8> {
+    static constexpr int DIM = 2, NEN = 8, NQ = 9, THREADS = 64, NPART = 4;
+};
+template <>
+struct Elem<kTet10> {
+    static constexpr int DIM = 3, NEN = 10, NQ = 64, THREADS = 64, NPART = 2;
 };
 
-template <int DIM>
-__device__ __forceinline__ void shape(int a, const double (&x)[DIM], double& N, double (&dN)[DIM])
+template <int ET>
+__device__ __forceinline__ void shape(int a, const double (&x)[Elem<ET>::DIM], double& N,
+                                      double (&dN)[Elem<ET>::DIM])
 {
-    if constexpr (DIM == 3)
+    if constexpr (ET == kHex20)
         shape20(a, x, N, dN);
-    else
+    else if constexpr (ET == kQuad8)
         shape8(a, x, N, dN);
+    else
+        shape10(a, x, N, dN);
 }
 
-// Gauss point q (first axis fastest) of the 3-point rule per axis, and its weight.
-template <int DIM>
-__device__ __forceinline__ void gauss_point(int q, double (&x)[DIM], double& w)
+// Gauss point q and its weight.  Bricks: 3 points per axis, first axis fastest.
+// Tetrahedra: the 4-point Gauss-Legendre rule on each axis of the unit cube (u, v, w),
+// collapsed by xi = (u, v (1 - u), w (1 - u)(1 - v)) with Jacobian (1 - u)^2 (1 - v).
+template <int ET>
+__device__ __forceinline__ void gauss_point(int q, double (&x)[Elem<ET>::DIM], double& w)
 {
-    const double p = 0.7745966692414834;  // sqrt(3/5)
-    const double pts[3] = {-p, 0.0, p};
-    const double wts[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
-    w = 1.0;
+    if constexpr (ET == kTet10) {
+        const double pts[4] = {0.5 * (1.0 - 0.8611363115940526), 0.5 * (1.0 - 0.3399810435848563),
+                               0.5 * (1.0 + 0.3399810435848563), 0.5 * (1.0 + 0.8611363115940526)};
+        const double wts[4] = {0.5 * 0.3478548451374538, 0.5 * 0.6521451548625461, 0.5 * 0.6521451548625461,
+                               0.5 * 0.3478548451374538};
+        const int i = q & 3, j = (q >> 2) & 3, k = q >> 4;
+        const double u = pts[i], v = pts[j], t = pts[k];
+        x[0] = u;
+        x[1] = v * (1.0 - u);
+        x[2] = t * (1.0 - u) * (1.0 - v);
+        w = wts[i] * wts[j] * wts[k] * (1.0 - u) * (1.0 - u) * (1.0 - v);
+    } else {
+        constexpr int DIM = Elem<ET>::DIM;
+        const double p = 0.7745966692414834;  // sqrt(3/5)
+        const double pts[3] = {-p, 0.0, p};
+        const double wts[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+        w = 1.0;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        const int k = q % 3;
-        q /= 3;
-        x[d] = pts[k];
-        w *= wts[k];
+        for (int d = 0; d < DIM; ++d) {
+            const int k = q % 3;
+            q /= 3;
+            x[d] = pts[k];
+            w *= wts[k];
+        }
     }
 }
 
@@ -110,9 +139,9 @@ struct Q2Params {
     unsigned long long* status;
 };
 
-template <int DIM, int NF>
+template <int ET, int NF>
 struct Q2Shared {
-    static constexpr int NEN = Elem<DIM>::NEN, NQ = Elem<DIM>::NQ;
+    static constexpr int DIM = Elem<ET>::DIM, NEN = Elem<ET>::NEN, NQ = Elem<ET>::NQ;
     double x[NEN][DIM];
     double src[NEN][NF];
     double g[NQ][NEN][DIM];
@@ -129,15 +158,16 @@ __global__ void k_fill(T* p, int64_t n)
     if (i < n) p[i] = T(0);
 }
 
-template <int DIM, int FORM, typename T>
-__global__ void __launch_bounds__(Elem<DIM>::THREADS) k_assemble_quadratic(Q2Params p)
+template <int ET, int FORM, typename T>
+__global__ void __launch_bounds__(Elem<ET>::THREADS) k_assemble_quadratic(Q2Params p)
 {
-    constexpr int NEN = Elem<DIM>::NEN, NQ = Elem<DIM>::NQ, NBQ = NEN / kQuarters;
+    constexpr int DIM = Elem<ET>::DIM, NEN = Elem<ET>::NEN, NQ = Elem<ET>::NQ, NPART = Elem<ET>::NPART;
+    constexpr int NBQ = NEN / NPART;
     constexpr int NF = FORM == MF_FORM_ELASTICITY ? DIM : 1;
-    static_assert(NEN * NF * kQuarters <= Elem<DIM>::THREADS && NQ <= Elem<DIM>::THREADS &&
-                      NEN * DIM <= Elem<DIM>::THREADS && NEN % kQuarters == 0,
-                  "one lane per row quarter, Gauss point and coordinate");
-    __shared__ Q2Shared<DIM, NF> S;
+    static_assert(NEN * NF * NPART <= Elem<ET>::THREADS && NQ <= Elem<ET>::THREADS &&
+                      NEN * DIM <= Elem<ET>::THREADS && NEN % NPART == 0,
+                  "one lane per row part, Gauss point and coordinate");
+    __shared__ Q2Shared<ET, NF> S;
     const int lane = threadIdx.x;
     const int64_t li = blockIdx.x;
     const bool live = li < p.n_list;  // uniform across the workgroup
@@ -158,7 +188,7 @@ __global__ void __launch_bounds__(Elem<DIM>::THREADS) k_assemble_quadratic(Q2Par
     __syncthreads();
     if (live && lane < NQ) {
         double xi[DIM], w;
-        gauss_point<DIM>(lane, xi, w);
+        gauss_point<ET>(lane, xi, w);
         double J[DIM][DIM];
 #pragma unroll
         for (int m = 0; m < DIM; ++m)
@@ -166,7 +196,7 @@ __global__ void __launch_bounds__(Elem<DIM>::THREADS) k_assemble_quadratic(Q2Par
             for (int n = 0; n < DIM; ++n) J[m][n] = 0.0;
         for (int b = 0; b < NEN; ++b) {
             double Nb, dN[DIM];
-            shape<DIM>(b, xi, Nb, dN);
+            shape<ET>(b, xi, Nb, dN);
 #pragma unroll
             for (int m = 0; m < DIM; ++m)
 #pragma unroll
@@ -183,7 +213,7 @@ __global__ void __launch_bounds__(Elem<DIM>::THREADS) k_assemble_quadratic(Q2Par
         for (int j = 0; j < NF; ++j) f[j] = 0.0;
         for (int b = 0; b < NEN; ++b) {
             double Nb, dN[DIM];
-            shape<DIM>(b, xi, Nb, dN);
+            shape<ET>(b, xi, Nb, dN);
 #pragma unroll
             for (int m = 0; m < DIM; ++m) {
                 double gm = 0.0;
@@ -200,7 +230,7 @@ __global__ void __launch_bounds__(Elem<DIM>::THREADS) k_assemble_quadratic(Q2Par
         for (int j = 0; j < NF; ++j) S.f[lane][j] = f[j];
     }
     __syncthreads();
-    if (!live || S.bad || lane >= NEN * NF * kQuarters) return;
+    if (!live || S.bad || lane >= NEN * NF * NPART) return;
 
     const int rowl = lane % (NEN * NF), quarter = lane / (NEN * NF);
     const int a = rowl / NF, i = rowl % NF;
@@ -259,7 +289,7 @@ __global__ void __launch_bounds__(Elem<DIM>::THREADS) k_assemble_quadratic(Q2Par
 constexpr int kFillThreads = 256;
 int blocks_for(int64_t n) { return (int)((n + kFillThreads - 1) / kFillThreads); }
 
-template <int DIM, int FORM, typename T>
+template <int ET, int FORM, typename T>
 mf_status launch(const AssembleArgs& A)
 {
     const mf_pattern_s* P = A.P;
@@ -288,19 +318,19 @@ mf_status launch(const AssembleArgs& A)
         p.elems = P->color_elems + P->color_ptr[c];
         p.n_list = P->color_ptr[c + 1] - P->color_ptr[c];
         if (p.n_list > 0)
-            k_assemble_quadratic<DIM, FORM, T><<<(unsigned)p.n_list, Elem<DIM>::THREADS, 0, A.stream>>>(p);
+            k_assemble_quadratic<ET, FORM, T><<<(unsigned)p.n_list, Elem<ET>::THREADS, 0, A.stream>>>(p);
     }
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
 
-template <int DIM, typename T>
+template <int ET, typename T>
 mf_status dispatch(const AssembleArgs& A)
 {
     switch (A.form->kind) {
-        case MF_FORM_MASS: return launch<DIM, MF_FORM_MASS, T>(A);
-        case MF_FORM_POISSON: return launch<DIM, MF_FORM_POISSON, T>(A);
-        case MF_FORM_ELASTICITY: return launch<DIM, MF_FORM_ELASTICITY, T>(A);
+        case MF_FORM_MASS: return launch<ET, MF_FORM_MASS, T>(A);
+        case MF_FORM_POISSON: return launch<ET, MF_FORM_POISSON, T>(A);
+        case MF_FORM_ELASTICITY: return launch<ET, MF_FORM_ELASTICITY, T>(A);
         default: return set_error(MF_ERR_UNSUPPORTED, "form %d on serendipity elements", (int)A.form->kind);
     }
 }
@@ -309,8 +339,9 @@ mf_status dispatch(const AssembleArgs& A)
 
 mf_status assemble_quadratic(const AssembleArgs& A)
 {
-    if (A.P->dim == 3) return A.prec == MF_F64 ? dispatch<3, double>(A) : dispatch<3, float>(A);
-    return A.prec == MF_F64 ? dispatch<2, double>(A) : dispatch<2, float>(A);
+    if (A.P->nen == 20) return A.prec == MF_F64 ? dispatch<kHex20, double>(A) : dispatch<kHex20, float>(A);
+    if (A.P->nen == 10) return A.prec == MF_F64 ? dispatch<kTet10, double>(A) : dispatch<kTet10, float>(A);
+    return A.prec == MF_F64 ? dispatch<kQuad8, double>(A) : dispatch<kQuad8, float>(A);
 }
 
 }  // namespace mf

@@ -1,6 +1,6 @@
-// The serendipity elements (quadratic elements of Sec. 4): shape functions and reference
-// gradients of the 20-node hexahedron on [-1, 1]^3 and of the 8-node quadrilateral on
-// [-1, 1]^2.  Local node order: corners a = ax + 2 ay + 4 az, then
+// The quadratic elements of Sec. 4: shape functions and reference gradients of the
+// 20-node serendipity hexahedron on [-1, 1]^3, the 8-node serendipity quadrilateral on
+// [-1, 1]^2 and the 10-node tetrahedron on the reference tetrahedron.  Local node order: corners a = ax + 2 ay + 4 az, then
 // the midpoints of the x-, y- and z-directed edges, four each, ordered by the bits of the
 // two other axes (ascending axis order).
 //   corner   N = (1/8)(1 + s_x x)(1 + s_y y)(1 + s_z z)(s_x x + s_y y + s_z z - 2)
@@ -57,6 +57,28 @@ __device__ __forceinline__ void shape8(int a, const double (&x)[2], double& N, d
     N = 0.5 * g * h;
     dN[ax] = -x[ax] * h;
     dN[1 - ax] = 0.5 * g * s;
+}
+
+// The 10-node quadratic tetrahedron on the reference tetrahedron xi >= 0, sum xi <= 1:
+// barycentric l_0 = 1 - xi_1 - xi_2 - xi_3, l_k = xi_k; vertices N_i = l_i (2 l_i - 1),
+// edge midpoints N_ij = 4 l_i l_j for the edges (0,1), (1,2), (2,0), (0,3), (1,3), (2,3).
+__device__ __forceinline__ void shape10(int a, const double (&x)[3], double& N, double (&dN)[3])
+{
+    auto lam = [&](int i) { return i == 0 ? 1.0 - x[0] - x[1] - x[2] : x[i - 1]; };
+    auto dlam = [&](int i, int m) { return i == 0 ? -1.0 : (m == i - 1 ? 1.0 : 0.0); };
+    if (a < 4) {
+        const double l = lam(a);
+        N = l * (2.0 * l - 1.0);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) dN[m] = (4.0 * l - 1.0) * dlam(a, m);
+        return;
+    }
+    constexpr int EI[6] = {0, 1, 2, 0, 1, 2}, EJ[6] = {1, 2, 0, 3, 3, 3};
+    const int i = EI[a - 4], j = EJ[a - 4];
+    const double li = lam(i), lj = lam(j);
+    N = 4.0 * li * lj;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) dN[m] = 4.0 * (li * dlam(j, m) + lj * dlam(i, m));
 }
 
 // Whether local node a lies on the face xi_axis = (side ? +1 : -1).
