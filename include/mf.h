@@ -141,10 +141,16 @@ typedef struct {
 } mf_fields;
 
 typedef struct { int32_t points_per_axis; } mf_quadrature;   /* Gauss-Legendre: 2 for order 1,
-                                                                  3 for MF_HEX20         */
+                                                                  3 for MF_HEX20 and MF_QUAD8,
+                                                                  4 for MF_TET10 (collapsed) */
 
-/* Assembly strategies.  AUTO picks the owner-computes gather for structured grids and
-   element-parallel atomics otherwise. */
+/* Assembly strategies.  AUTO picks the owner-computes gather for structured grids, and
+   otherwise (or for a form without a gather kernel) the element-parallel scatter colour
+   by colour with plain adds, whose sums are the same on every run.  ATOMIC is the
+   element-parallel scatter with hardware atomics in one launch (the paper's scheme).  In
+   ATOMIC and in the gather (which sums a node's element blocks with LDS atomics) the
+   order of the additions, and so the last bits, may vary between runs.  GATHER asks for
+   the owner-computes kernel. */
 typedef enum { MF_SCATTER_AUTO = 0, MF_SCATTER_ATOMIC = 1, MF_SCATTER_GATHER = 2 } mf_scatter;
 
 /*

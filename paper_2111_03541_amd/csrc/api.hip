@@ -207,14 +207,18 @@ mf_status mf_assemble_ex(const mf_pattern_t* P, const mf_form* form, const doubl
         if (st != MF_OK) return st;
         return apply_dirichlet(A);
     }
-    if (scatter == MF_SCATTER_AUTO) scatter = P->is_grid ? MF_SCATTER_GATHER : MF_SCATTER_ATOMIC;
+    // AUTO: the owner-computes gather on structured grids, else (and for forms without a
+    // gather kernel) the element-parallel scatter colour by colour, whose sums do not
+    // depend on the run; ATOMIC asks for the paper's atomic scatter explicitly.
+    const bool auto_mode = scatter == MF_SCATTER_AUTO;
+    if (auto_mode) scatter = P->is_grid ? MF_SCATTER_GATHER : MF_SCATTER_ATOMIC;
     bool gathered = false;
     if (scatter == MF_SCATTER_GATHER) {
         st = assemble_column(A);  // applies the Dirichlet elimination while writing K
         gathered = st == MF_OK;
-        if (st == MF_ERR_UNSUPPORTED) st = assemble_atomic(A);  // e.g. a form without a gather kernel
+        if (st == MF_ERR_UNSUPPORTED) st = assemble_atomic(A, true);  // e.g. a form without a gather kernel
     } else {
-        st = assemble_atomic(A);
+        st = assemble_atomic(A, auto_mode);
     }
     if (st != MF_OK) return st;
     return gathered ? MF_OK : apply_dirichlet(A);

@@ -1,11 +1,14 @@
-// Element-parallel assembly with atomic scatter (Sec. 2.2 D-2 and D-3): the paper's own
-// scheme, kept as the strategy for meshes of any topology.
+// Element-parallel assembly for meshes of any topology (Sec. 2.2 D-2 and D-3).
 //
 // One thread per (element e, local row (a, i)).  The thread computes the FP64 geometry
 // at every Gauss point of e, accumulates row (a, i) of the element tangent and the
-// element residual in precision T, and adds them into K and d with hardware atomics,
-// locating each entry through the element-to-nonzero rank map.  K and d are cleared by
-// fill kernels first, so the call overwrites them entirely.
+// element residual in precision T, and adds them into K and d, locating each entry
+// through the element-to-nonzero rank map.  Two ways to add:
+//   atomic    the paper's own scheme: all elements in one launch, hardware atomics;
+//   coloured  the elements of one colour per launch (no two share a node), plain
+//             read-modify-writes: each entry has one writer per launch and the stream
+//             orders the colours, so the sums are the same on every run.
+// K and d are cleared by fill kernels first, so the call overwrites them entirely.
 #include <hip/hip_runtime.h>
 
 #include "element.h"
@@ -26,6 +29,8 @@ struct AtomicParams {
     const uint8_t* rank;
     const void* elem_param;
     const void* src;  // nodal sources (MASS/POISSON/ELASTICITY) or state (NS)
+    const int32_t* elems;  // coloured: the elements of one colour
+    int64_t n_list;        // coloured: their count
     int field_major;
     void* K;
     void* d;
@@ -39,17 +44,18 @@ __global__ void k_fill(T* p, int64_t n)
     if (i < n) p[i] = T(0);
 }
 
-template <int FORM, int DIM, typename T>
+template <int FORM, int DIM, bool COLOURED, typename T>
 __global__ void __launch_bounds__(kThreads) k_assemble_atomic(AtomicParams p)
 {
     constexpr int NEN = 1 << DIM;
     constexpr int NF = FormTraits<FORM, DIM>::NF;
     constexpr int NSRC = FormTraits<FORM, DIM>::NSRC;
     const int64_t n_el = p.n_el;
+    const int64_t n_items = COLOURED ? p.n_list : n_el;
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_el * NEN * NF) return;
-    const int64_t e = t % n_el;
-    const int ai = (int)(t / n_el);
+    if (t >= n_items * NEN * NF) return;
+    const int64_t e = COLOURED ? (int64_t)p.elems[t % n_items] : t % n_el;
+    const int ai = (int)(t / n_items);
     const int a = ai / NF, i = ai % NF;
 
     int32_t node[NEN];
@@ -101,10 +107,16 @@ __global__ void __launch_bounds__(kThreads) k_assemble_atomic(AtomicParams p)
 #pragma unroll
         for (int j = 0; j < NF; ++j) {
             const int64_t pos = p.field_major ? rs + j * deg + rk : rs + rk * NF + j;
-            unsafeAtomicAdd(K + pos, krow[b * NF + j]);
+            if constexpr (COLOURED)
+                K[pos] += krow[b * NF + j];
+            else
+                unsafeAtomicAdd(K + pos, krow[b * NF + j]);
         }
     }
-    unsafeAtomicAdd(d + row, -rrow);
+    if constexpr (COLOURED)
+        d[row] -= rrow;
+    else
+        unsafeAtomicAdd(d + row, -rrow);
 }
 
 template <typename T>
@@ -131,7 +143,7 @@ __global__ void k_reset_status(unsigned long long* s)
 }
 
 template <int FORM, int DIM, typename T>
-mf_status launch_atomic(const AssembleArgs& A)
+mf_status launch_atomic(const AssembleArgs& A, bool coloured)
 {
     constexpr int NEN = 1 << DIM;
     constexpr int NF = FormTraits<FORM, DIM>::NF;
@@ -153,35 +165,49 @@ mf_status launch_atomic(const AssembleArgs& A)
     p.status = P->status;
     if (P->nnz > 0) k_fill<T><<<blocks_for(P->nnz, kThreads), kThreads, 0, A.stream>>>((T*)A.K, P->nnz);
     if (P->n_rows > 0) k_fill<T><<<blocks_for(P->n_rows, kThreads), kThreads, 0, A.stream>>>((T*)A.d, P->n_rows);
-    const int64_t n = P->n_elems * NEN * NF;
-    if (n > 0) k_assemble_atomic<FORM, DIM, T><<<blocks_for(n, kThreads), kThreads, 0, A.stream>>>(p);
+    MF_HIP(hipGetLastError());
+    if (P->n_elems == 0) return MF_OK;
+    if (!coloured) {
+        const int64_t n = P->n_elems * NEN * NF;
+        k_assemble_atomic<FORM, DIM, false, T><<<blocks_for(n, kThreads), kThreads, 0, A.stream>>>(p);
+        MF_HIP(hipGetLastError());
+        return MF_OK;
+    }
+    const mf_status st = ensure_coloring(P, A.stream);
+    if (st != MF_OK) return st;
+    for (size_t c = 0; c + 1 < P->color_ptr.size(); ++c) {
+        p.elems = P->color_elems + P->color_ptr[c];
+        p.n_list = P->color_ptr[c + 1] - P->color_ptr[c];
+        const int64_t n = p.n_list * NEN * NF;
+        if (n > 0) k_assemble_atomic<FORM, DIM, true, T><<<blocks_for(n, kThreads), kThreads, 0, A.stream>>>(p);
+    }
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
 
 template <typename T>
-mf_status dispatch_atomic(const AssembleArgs& A)
+mf_status dispatch_atomic(const AssembleArgs& A, bool c)
 {
     const int dim = A.P->dim;
     switch (A.form->kind) {
         case MF_FORM_MASS:
-            return dim == 2 ? launch_atomic<MF_FORM_MASS, 2, T>(A) : launch_atomic<MF_FORM_MASS, 3, T>(A);
+            return dim == 2 ? launch_atomic<MF_FORM_MASS, 2, T>(A, c) : launch_atomic<MF_FORM_MASS, 3, T>(A, c);
         case MF_FORM_POISSON:
-            return dim == 2 ? launch_atomic<MF_FORM_POISSON, 2, T>(A) : launch_atomic<MF_FORM_POISSON, 3, T>(A);
+            return dim == 2 ? launch_atomic<MF_FORM_POISSON, 2, T>(A, c) : launch_atomic<MF_FORM_POISSON, 3, T>(A, c);
         case MF_FORM_ELASTICITY:
-            return dim == 2 ? launch_atomic<MF_FORM_ELASTICITY, 2, T>(A)
-                            : launch_atomic<MF_FORM_ELASTICITY, 3, T>(A);
+            return dim == 2 ? launch_atomic<MF_FORM_ELASTICITY, 2, T>(A, c)
+                            : launch_atomic<MF_FORM_ELASTICITY, 3, T>(A, c);
         case MF_FORM_NS_SUPG:
-            return dim == 2 ? launch_atomic<MF_FORM_NS_SUPG, 2, T>(A) : launch_atomic<MF_FORM_NS_SUPG, 3, T>(A);
+            return dim == 2 ? launch_atomic<MF_FORM_NS_SUPG, 2, T>(A, c) : launch_atomic<MF_FORM_NS_SUPG, 3, T>(A, c);
     }
     return set_error(MF_ERR_ARG, "unknown form kind %d", (int)A.form->kind);
 }
 
 }  // namespace
 
-mf_status assemble_atomic(const AssembleArgs& A)
+mf_status assemble_atomic(const AssembleArgs& A, bool coloured)
 {
-    return A.prec == MF_F64 ? dispatch_atomic<double>(A) : dispatch_atomic<float>(A);
+    return A.prec == MF_F64 ? dispatch_atomic<double>(A, coloured) : dispatch_atomic<float>(A, coloured);
 }
 
 mf_status apply_dirichlet(const AssembleArgs& A)

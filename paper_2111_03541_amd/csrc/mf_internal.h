@@ -68,7 +68,9 @@ struct AssembleArgs {
     void* d;
     hipStream_t stream;
 };
-mf_status assemble_atomic(const AssembleArgs& a);
+// element-parallel scatter: hardware atomics, or colour by colour with plain adds
+// (deterministic sums)
+mf_status assemble_atomic(const AssembleArgs& a, bool coloured);
 mf_status assemble_quadratic(const AssembleArgs& a);  // assemble_quadratic.hip: MF_HEX20, MF_QUAD8
 mf_status assemble_column(const AssembleArgs& a);
 mf_status apply_dirichlet(const AssembleArgs& a);

@@ -367,3 +367,21 @@ def test_gather_scattered_dirichlet(mf, fname, kind, numbering):
     K, d = run_gpu(mf, pat, kind, params, mesh, 0, ep, src, state, mask=mask, scatter=mf.SCATTER_GATHER)
     assert rowscaled_error(ref_pat, K, Kr) <= TOL[0]
     assert vec_error(d, dr) <= TOL[0]
+
+
+@pytest.mark.parametrize("mname,make,kinds", [(MESHES[0][0], MESHES[0][1], (O.NS_SUPG,)),
+                                              (MESHES[1][0], MESHES[1][1], (O.ELASTICITY, O.NS_SUPG))],
+                         ids=["grid_flow", "permuted"])
+def test_coloured_scatter_is_deterministic(mf, mname, make, kinds):
+    """Where the default path scatters element by element (meshes that are not grids, and
+    the FP64 flow form, which has no gather kernel) it goes colour by colour with plain
+    adds, so two assemblies are bitwise equal."""
+    say("deterministic coloured scatter", mname)
+    mesh = make()
+    for kind in kinds:
+        nf = O.form_nf(kind, mesh.dim)
+        params, ep, src, state = make_inputs(kind, mesh)
+        pat = gpu_pattern(mf, mesh, nf)
+        K1, d1 = run_gpu(mf, pat, kind, params, mesh, 0, ep, src, state)
+        K2, d2 = run_gpu(mf, pat, kind, params, mesh, 0, ep, src, state)
+        assert np.array_equal(K1, K2) and np.array_equal(d1, d2)
