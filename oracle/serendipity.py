@@ -318,3 +318,84 @@ def assemble_boundary20(pat: Pattern20, kind, coef, value, face_elem, face_id, s
         assert np.abs(Re[~on_face]).max(initial=0.0) < 1e-13 * max(1.0, np.abs(Re).max())
     K = sp.coo_matrix((vals, (rows, cols)), shape=(pat.n_rows, pat.n_rows)).tocsr()
     return K, d
+
+
+# face k of a tetrahedron: the three vertices other than k, and the local ids of the
+# midpoints of the edges among them
+TET_FACE_VERTS = [(1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2)]
+_TET_EDGES = [(0, 1), (1, 2), (2, 0), (0, 3), (1, 3), (2, 3)]
+
+
+def tet_face_nodes(k):
+    """Local ids of the six nodes of face k (opposite vertex k): vertices, then edges."""
+    vs = TET_FACE_VERTS[k]
+    es = [4 + m for m, (i, j) in enumerate(_TET_EDGES) if i in vs and j in vs]
+    return list(vs) + es
+
+
+def assemble_boundary_tet10(pat: Pattern20, kind, coef, value, face_elem, face_id, state=None, target=None):
+    """Boundary forms on faces of 10-node tetrahedra: (scipy CSR, d); the forms and signs of
+    assemble_boundary20.  Face k (opposite vertex k) is parametrised by the reference point
+    p0 + s (p1 - p0) + t (p2 - p0) over its vertices p0, p1, p2 (s, t >= 0, s + t <= 1), with
+    the collapsed 4 x 4 Gauss rule of the triangle (exact to total degree 5); dS =
+    |dx/ds x dx/dt|, n signed to point away from vertex k."""
+    import scipy.sparse as sp
+    from .boundary import CONVECTION, PENALTY, RADIATION, TRACTION
+    mesh, nf = pat.mesh, pat.nf
+    value = np.asarray(value, dtype=np.float64)
+    g, gw = np.polynomial.legendre.leggauss(4)
+    t1, w1 = 0.5 * (g + 1.0), 0.5 * gw
+    tri = [(t1[i], t1[j] * (1.0 - t1[i]), w1[i] * w1[j] * (1.0 - t1[i])) for j in range(4) for i in range(4)]
+    ref = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64)
+    rows, cols, vals = [], [], []
+    d = np.zeros(pat.n_rows)
+    for e, k in zip(np.asarray(face_elem), np.asarray(face_id)):
+        e, k = int(e), int(k)
+        nodes = mesh.conn[:, e]
+        X = mesh.coords[:, nodes].T
+        U = state[:, nodes].T if state is not None else np.zeros((10, nf))
+        G = np.asarray(target)[:, nodes].T if target is not None else np.tile(value[:nf], (10, 1))
+        v0, v1, v2 = (ref[m] for m in TET_FACE_VERTS[k])
+        Ke = np.zeros((10, nf, 10, nf))
+        Re = np.zeros((10, nf))
+        # outward: away from vertex k
+        xk = X[k]
+        for s_, t_, wq in tri:
+            xi = v0 + s_ * (v1 - v0) + t_ * (v2 - v0)
+            N, dN = basis10(xi)
+            J = X.T @ dN
+            ts, tt = J @ (v1 - v0), J @ (v2 - v0)
+            nr = np.cross(ts, tt)
+            if nr @ (N @ X - xk) < 0.0:
+                nr = -nr
+            dS = np.linalg.norm(nr)
+            n = nr / dS
+            w = wq * dS
+            uq, gq = N @ U, N @ G
+            for i in range(nf):
+                if kind in (PENALTY, CONVECTION):
+                    Ke[:, i, :, i] += coef * w * np.outer(N, N)
+                    Re[:, i] += coef * w * N * (uq[i] - gq[i])
+                elif kind == RADIATION:
+                    Ke[:, 0, :, 0] += coef * w * 4.0 * uq[0] ** 3 * np.outer(N, N)
+                    Re[:, 0] += coef * w * N * (uq[0] ** 4 - gq[0] ** 4)
+                elif kind == TRACTION:
+                    tv = gq if target is not None else value.reshape(3, 3) @ n
+                    Re[:, i] -= w * N * tv[i]
+                else:
+                    raise ValueError(kind)
+        fn = tet_face_nodes(k)
+        for a in fn:
+            for i in range(nf):
+                r = pat.dof(nodes[a], i)
+                d[r] -= Re[a, i]
+                for b in fn:
+                    for j in range(nf):
+                        if Ke[a, i, b, j] != 0.0:
+                            rows.append(r)
+                            cols.append(pat.dof(nodes[b], j))
+                            vals.append(Ke[a, i, b, j])
+        off = [a for a in range(10) if a not in fn]
+        assert np.abs(Re[off]).max(initial=0.0) < 1e-13 * max(1.0, np.abs(Re).max())
+    K = sp.coo_matrix((vals, (rows, cols)), shape=(pat.n_rows, pat.n_rows)).tocsr()
+    return K, d

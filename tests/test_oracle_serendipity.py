@@ -358,3 +358,45 @@ def test_tet10_elasticity_rigid_modes():
     one, zero = np.ones_like(x), np.zeros_like(x)
     for m in ((one, zero, zero), (zero, one, zero), (zero, zero, one), (-y, x, zero), (zero, -z, y), (z, zero, -x)):
         assert np.abs(Km @ np.stack(m, axis=1).reshape(-1)).max() < 1e-12 * abs(Km).max()
+
+
+def test_tet10_faces():
+    """Faces of 10-node tetrahedra: a uniform traction on a flat 6-node face loads its
+    vertices with nothing and each mid-side node with a third of the total; face mass
+    sums to the surface area; a uniform stress over the closed surface sums to zero; the
+    radiation tangent by central differences."""
+    import oracle.boundary as OB
+    L = [1.0, 1.3, 0.7]
+    mesh = W.tet10_mesh((2, 2, 1), jitter=0.2, seed=3, lengths=L)
+    fe, fi = W.tet10_box_faces(mesh, L)
+    pat = S.Pattern20(mesh, 1)
+    K, _ = S.assemble_boundary_tet10(pat, OB.PENALTY, 1.0, [0.0], fe, fi)
+    area = 2 * (L[0] * L[1] + L[1] * L[2] + L[0] * L[2])
+    assert abs(K.sum() - area) < 1e-13 * area
+    pat3 = S.Pattern20(mesh, 3)
+    sig = np.array([[0.3, -0.2, 0.7], [0.1, 0.5, -0.4], [0.6, 0.2, -1.1]])
+    _, d = S.assemble_boundary_tet10(pat3, OB.TRACTION, 1.0, sig.reshape(-1), fe, fi)
+    assert np.abs(d.reshape(-1, 3).sum(axis=0)).max() < 1e-14
+    # one face: vertices 0, mid-sides 1/3 of t times its area
+    e, k = int(fe[0]), int(fi[0])
+    _, d1 = S.assemble_boundary_tet10(pat3, OB.TRACTION, 1.0, sig.reshape(-1), fe[:1], fi[:1])
+    F = d1.reshape(-1, 3)
+    fn = S.tet_face_nodes(k)
+    P = mesh.coords[:, mesh.conn[fn[:3], e]]
+    nr = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+    c_in = mesh.coords[:, mesh.conn[:4, e]].mean(axis=1)
+    if nr @ (P[:, 0] - c_in) < 0:
+        nr = -nr
+    a_f = 0.5 * np.linalg.norm(nr)
+    t = sig @ (nr / np.linalg.norm(nr))
+    for m, a in enumerate(fn):
+        want = np.zeros(3) if m < 3 else a_f * t / 3.0
+        assert np.abs(F[mesh.conn[a, e]] - want).max() < 1e-14
+    # radiation tangent
+    T = 1.0 + np.random.default_rng(2).random((1, mesh.n_nodes))
+    Kr, _ = S.assemble_boundary_tet10(pat, OB.RADIATION, 0.7, [1.2], fe, fi, state=T)
+    dv = np.random.default_rng(3).normal(size=T.shape)
+    h = 1e-6
+    _, dp = S.assemble_boundary_tet10(pat, OB.RADIATION, 0.7, [1.2], fe, fi, state=T + h * dv)
+    _, dm = S.assemble_boundary_tet10(pat, OB.RADIATION, 0.7, [1.2], fe, fi, state=T - h * dv)
+    assert np.abs(Kr @ dv[0] + (dp - dm) / (2 * h)).max() < 1e-7

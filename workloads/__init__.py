@@ -374,6 +374,26 @@ def tet10_mesh(n, jitter: float = 0.0, seed=None, lengths=None) -> Mesh:
     return Mesh(coords, conn.astype(np.int32))
 
 
+def tet10_box_faces(mesh: Mesh, lengths=None):
+    """Boundary faces of a tet10_mesh box: (element ids int32, local faces uint8), where
+    local face k is the face opposite vertex k; a face is on the boundary when its three
+    vertices lie on one side of the box [0, L]^3."""
+    L = np.ones(3) if lengths is None else np.asarray(lengths, dtype=np.float64)
+    X = mesh.coords
+    elems, fids = [], []
+    for e in range(mesh.n_elems):
+        v = mesh.conn[:4, e]
+        for k in range(4):
+            f = [v[m] for m in range(4) if m != k]
+            P = X[:, f]
+            for ax in range(3):
+                if np.all(np.abs(P[ax]) < 1e-12) or np.all(np.abs(P[ax] - L[ax]) < 1e-12):
+                    elems.append(e)
+                    fids.append(k)
+                    break
+    return np.array(elems, dtype=np.int32), np.array(fids, dtype=np.uint8)
+
+
 def box_faces(n, sides=None):
     """Element faces on the sides of a structured 3D box mesh of n = (nx, ny, nz) elements.
 
