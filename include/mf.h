@@ -316,9 +316,11 @@ typedef struct {
  * [n_faces] element ids and face_id [n_faces] local faces 2 * axis + side (side 1: the
  * face at xi_axis = +1), device arrays.  state [nf][n_nodes] (device, precision prec, or
  * NULL = 0) is the linearisation point of the radiation, flux, penalty and flow residuals.
- * P must be a 3D hex pattern with full coupling: 8-node hexahedra (all forms, 2x2 face
- * rule) or 20-node hexahedra (penalty, convection, radiation and traction, over the
- * eight nodes of the face with the 3x3 face rule; MF_ERR_UNSUPPORTED otherwise).
+ * P must be a 3D pattern with full coupling: 8-node hexahedra (all forms, 2x2 face
+ * rule), 20-node hexahedra (penalty, convection, radiation and traction, over the eight
+ * nodes of the face with the 3x3 face rule) or 10-node tetrahedra (the same four forms
+ * over the six nodes of the face; face_id k is the face opposite vertex k, 0..3;
+ * collapsed 4x4 Gauss rule of the triangle); MF_ERR_UNSUPPORTED otherwise.
  * Async on the stream.  Reported by
  * mf_status_poll (until the next mf_assemble clears the status): a face whose element id
  * or local face is out of range (skipped; MF_ERR_ARG with the first such face), and a

@@ -406,6 +406,149 @@ __global__ void __launch_bounds__(kThreads) k_boundary20(BParams p)
     if (rrow != 0.0) unsafeAtomicAdd(d + row, (T)(-rrow));
 }
 
+// Faces of 10-node tetrahedra: one thread per (face f, face node m, field i).  Face k is
+// the face opposite vertex k: its three vertices and the three edge midpoints among them.
+// The face is the reference triangle p0 + s (p1 - p0) + t (p2 - p0) over its vertices,
+// integrated with the collapsed 4 x 4 Gauss rule of the triangle; the normal points away
+// from vertex k.  Penalty, convection, radiation and traction as above.
+template <int NF, typename T>
+__global__ void __launch_bounds__(kThreads) k_boundary_tet10(BParams p)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p.n_faces * 6 * NF) return;
+    const int64_t f = t % p.n_faces;
+    const int ki = (int)(t / p.n_faces);
+    const int mf = ki / NF, i = ki % NF;
+    const int64_t e = p.face_elem[f];
+    const int k = p.face_id[f];
+    if (e < 0 || e >= p.n_el || k > 3) {
+        if (ki == 0) atomicMin(p.status + 1, (unsigned long long)f);
+        return;
+    }
+    // face nodes: the vertices other than k, then the edges among them (local ids 4..9 are
+    // the edges (0,1), (1,2), (2,0), (0,3), (1,3), (2,3))
+    constexpr int EI[6] = {0, 1, 2, 0, 1, 2}, EJ[6] = {1, 2, 0, 3, 3, 3};
+    int loc[6];
+    for (int v = 0, c = 0; v < 4; ++v)
+        if (v != k) loc[c++] = v;
+    for (int m = 0, c = 3; m < 6; ++m)
+        if (EI[m] != k && EJ[m] != k) loc[c++] = 4 + m;
+    double pv[3][3];  // reference coordinates of the face vertices
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) pv[c][m] = loc[c] == m + 1 ? 1.0 : 0.0;
+    double x[6][3], U[6], G[6], xk[3];
+    int32_t node[6];
+    const T* st = (const T*)p.state;
+    const T* tg = (const T*)p.target;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+        node[b] = p.conn[(int64_t)loc[b] * p.n_el + e];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) x[b][m] = p.coords[(int64_t)m * p.n_nodes + node[b]];
+        U[b] = st ? (double)st[(int64_t)i * p.n_nodes + node[b]] : 0.0;
+        G[b] = tg ? (double)tg[(int64_t)i * p.n_nodes + node[b]] : p.form.value[i];
+    }
+    {
+        const int32_t vk = p.conn[(int64_t)k * p.n_el + e];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) xk[m] = p.coords[(int64_t)m * p.n_nodes + vk];
+    }
+    const mf_bform_kind kind = p.form.kind;
+    const double c = p.form.coef;
+    double krow[6];
+#pragma unroll
+    for (int b = 0; b < 6; ++b) krow[b] = 0.0;
+    double rrow = 0.0;
+    const double g4[4] = {0.5 * (1.0 - 0.8611363115940526), 0.5 * (1.0 - 0.3399810435848563),
+                          0.5 * (1.0 + 0.3399810435848563), 0.5 * (1.0 + 0.8611363115940526)};
+    const double w4[4] = {0.5 * 0.3478548451374538, 0.5 * 0.6521451548625461, 0.5 * 0.6521451548625461,
+                          0.5 * 0.3478548451374538};
+    for (int q = 0; q < 16; ++q) {
+        const double s_ = g4[q & 3], t_ = g4[q >> 2] * (1.0 - s_);
+        const double wq = w4[q & 3] * w4[q >> 2] * (1.0 - s_);
+        double xi[3], e1[3], e2[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            e1[m] = pv[1][m] - pv[0][m];
+            e2[m] = pv[2][m] - pv[0][m];
+            xi[m] = pv[0][m] + s_ * e1[m] + t_ * e2[m];
+        }
+        double N[6], ts[3] = {0, 0, 0}, tt[3] = {0, 0, 0}, xq[3] = {0, 0, 0};
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+            double dN[3];
+            shape10(loc[b], xi, N[b], dN);
+            const double ds = dN[0] * e1[0] + dN[1] * e1[1] + dN[2] * e1[2];
+            const double dt = dN[0] * e2[0] + dN[1] * e2[1] + dN[2] * e2[2];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                ts[m] = fma(x[b][m], ds, ts[m]);
+                tt[m] = fma(x[b][m], dt, tt[m]);
+                xq[m] = fma(x[b][m], N[b], xq[m]);
+            }
+        }
+        double nr[3] = {ts[1] * tt[2] - ts[2] * tt[1], ts[2] * tt[0] - ts[0] * tt[2], ts[0] * tt[1] - ts[1] * tt[0]};
+        if (nr[0] * (xq[0] - xk[0]) + nr[1] * (xq[1] - xk[1]) + nr[2] * (xq[2] - xk[2]) < 0.0) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) nr[m] = -nr[m];
+        }
+        const double dS = sqrt(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
+        if (!(dS > 0.0)) {
+            atomicMin(p.status, (unsigned long long)e);
+            return;
+        }
+        const double w = wq * dS;
+        const double Na = N[mf];
+        double uq = 0.0, gq = 0.0;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+            uq = fma(N[b], U[b], uq);
+            gq = fma(N[b], G[b], gq);
+        }
+        if (kind == MF_BFORM_PENALTY || kind == MF_BFORM_CONVECTION) {
+#pragma unroll
+            for (int b = 0; b < 6; ++b) krow[b] += c * w * Na * N[b];
+            rrow += c * w * Na * (uq - gq);
+        } else if (kind == MF_BFORM_RADIATION) {
+#pragma unroll
+            for (int b = 0; b < 6; ++b) krow[b] += c * w * Na * 4.0 * uq * uq * uq * N[b];
+            rrow += c * w * Na * (uq * uq * uq * uq - gq * gq * gq * gq);
+        } else {  // MF_BFORM_TRACTION
+            const double* S = p.form.value;
+            const double ti = tg ? gq : (S[3 * i] * nr[0] + S[3 * i + 1] * nr[1] + S[3 * i + 2] * nr[2]) / dS;
+            rrow -= w * Na * ti;
+        }
+    }
+    const int a = loc[mf];
+    const int64_t va = node[mf];
+    const int64_t row = p.field_major ? (int64_t)i * p.n_nodes + va : (int64_t)NF * va + i;
+    const int64_t rs = p.row_ptr[row];
+    const int64_t deg = p.nbr_ptr[va + 1] - p.nbr_ptr[va];
+    T* K = (T*)p.K;
+    T* d = (T*)p.d;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+        if (krow[b] == 0.0) continue;
+        const int64_t rk = p.rank[(int64_t)(a * 10 + loc[b]) * p.n_el + e];
+        const int64_t pos = p.field_major ? rs + i * deg + rk : rs + rk * NF + i;
+        unsafeAtomicAdd(K + pos, (T)krow[b]);
+    }
+    if (rrow != 0.0) unsafeAtomicAdd(d + row, (T)(-rrow));
+}
+
+template <int NF, typename T>
+mf_status launch_boundary_tet10(const BParams& p, hipStream_t s)
+{
+    const int64_t n = p.n_faces * 6 * NF;
+    if (n == 0) return MF_OK;
+    if (n > 0xffffffffLL - kThreads) return set_error(MF_ERR_ARG, "too many faces for one launch");
+    k_boundary_tet10<NF, T><<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(p);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
 template <int NF, typename T>
 mf_status launch_boundary20(const BParams& p, hipStream_t s)
 {
@@ -439,9 +582,10 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
                                           void* d, void* stream)
 {
     if (!P || !form) return set_error(MF_ERR_ARG, "pattern or form is NULL");
-    if (P->dim != 3 || (P->nen != 8 && P->nen != 20))
-        return set_error(MF_ERR_UNSUPPORTED, "boundary forms need a 3D hex pattern");
+    if (P->dim != 3 || (P->nen != 8 && P->nen != 20 && P->nen != 10))
+        return set_error(MF_ERR_UNSUPPORTED, "boundary forms need a 3D hexahedron or tetrahedron pattern");
     const bool quad = P->order == 2;
+    const bool tet = P->nen == 10;
     if (prec != MF_F64 && prec != MF_F32) return set_error(MF_ERR_ARG, "unknown precision %d", (int)prec);
     if (n_faces < 0 || n_faces > ((int64_t)1 << 28)) return set_error(MF_ERR_ARG, "n_faces out of range");
     if (n_faces > 0 && (!face_elem || !face_id || !coords || !K || !d))
@@ -469,6 +613,7 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
     }
     if (quad && (form->kind == MF_BFORM_FLUX || nf == 4))
         return set_error(MF_ERR_UNSUPPORTED, "the flux and flow boundary forms need 8-node hexahedra");
+    if (tet && n_faces > 0 && !face_id) return set_error(MF_ERR_ARG, "NULL face_id");
     hipStream_t s = (hipStream_t)stream;
     BParams p{};
     p.form = *form;
@@ -489,6 +634,10 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
     p.d = d;
     p.status = P->status;
     const_cast<mf_pattern_s*>(P)->last_stream = s;
+    if (tet) {
+        if (prec == MF_F64) return nf == 1 ? launch_boundary_tet10<1, double>(p, s) : launch_boundary_tet10<3, double>(p, s);
+        return nf == 1 ? launch_boundary_tet10<1, float>(p, s) : launch_boundary_tet10<3, float>(p, s);
+    }
     if (quad) {
         if (prec == MF_F64) return nf == 1 ? launch_boundary20<1, double>(p, s) : launch_boundary20<3, double>(p, s);
         return nf == 1 ? launch_boundary20<1, float>(p, s) : launch_boundary20<3, float>(p, s);

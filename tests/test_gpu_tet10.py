@@ -112,6 +112,65 @@ def test_tet10_argument_errors(mf):
     coords = torch.from_numpy(mesh.coords).to(dev)
     with pytest.raises(mf.MFError):  # the collapsed rule takes 4 points per axis
         pat.assemble(mf.Form(mf.POISSON), coords, points_per_axis=3)
-    with pytest.raises(mf.MFError):  # boundary forms are for hexahedra
-        pat.assemble_boundary(mf.BFORM_PENALTY, coords, torch.zeros(1, dtype=torch.int32, device=dev),
+    with pytest.raises(mf.MFError):  # the flux form needs 8-node hexahedra
+        pat.assemble_boundary(mf.BFORM_FLUX, coords, torch.zeros(1, dtype=torch.int32, device=dev),
                               torch.zeros(1, dtype=torch.uint8, device=dev))
+
+
+import oracle.boundary as OB  # noqa: E402
+
+FACE_CASES = [  # (name, kind, nf, coef, value, uses state, uses target)
+    ("penalty1", OB.PENALTY, 1, 40.0, [0.7], True, False),
+    ("penalty3_target", OB.PENALTY, 3, 20.0, [0.0, 0.0, 0.0], True, True),
+    ("convection", OB.CONVECTION, 1, 3.0, [2.5], True, False),
+    ("radiation", OB.RADIATION, 1, 0.8, [1.3], True, False),
+    ("traction", OB.TRACTION, 3, 1.0, [0.3, -0.2, 0.7, 0.1, 0.5, -0.4, 0.6, 0.2, -1.1], False, False),
+    ("traction_target", OB.TRACTION, 3, 1.0, [], False, True),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("numbering", [0, 1])
+@pytest.mark.parametrize("case", FACE_CASES, ids=[c[0] for c in FACE_CASES])
+def test_boundary_form_matches_oracle(mf, case, numbering, prec):
+    name, kind, nf, coef, value, use_state, use_target = case
+    say("tet10 boundary", name, "numbering", numbering, "prec", prec)
+    L = [1.0, 0.8, 1.3]
+    mesh = W.tet10_mesh((2, 2, 2), jitter=0.2, seed=5, lengths=L)
+    fe, fi = W.tet10_box_faces(mesh, L)
+    sel = np.random.default_rng(2).permutation(fe.shape[0])[: fe.shape[0] * 3 // 4]
+    fe, fi = fe[sel], fi[sel]
+    rng = np.random.default_rng(4)
+    state = 1.0 + rng.random((nf, mesh.n_nodes)) if use_state else None
+    target = rng.standard_normal((nf, mesh.n_nodes)) if use_target else None
+    fdt = np.float64 if prec == 0 else np.float32
+    if prec == 1:
+        state = None if state is None else state.astype(np.float32).astype(np.float64)
+        target = None if target is None else target.astype(np.float32).astype(np.float64)
+    ref = S.Pattern20(mesh, nf, numbering)
+    Kr, dr = S.assemble_boundary_tet10(ref, kind, coef, value, fe, fi, state=state, target=target)
+    dev = torch.device("cuda:0")
+    pat = gpu_pattern(mf, mesh, nf, numbering)
+    tt = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=fdt)).to(dev)
+    K, d = pat.assemble_boundary(kind, torch.from_numpy(mesh.coords).to(dev), torch.from_numpy(fe).to(dev),
+                                 torch.from_numpy(fi).to(dev), coef=coef, value=value, state=tt(state),
+                                 target=tt(target), precision=prec)
+    assert pat.status()[0] == mf.OK
+    Kg = ref.to_scipy(K.double().cpu().numpy())
+    dg = d.double().cpu().numpy()
+    tol = 1e-12 if prec == 0 else 1e-5
+    kscale = abs(Kr).max() if Kr.nnz else 0.0
+    assert (abs(Kg - Kr).max() <= tol * kscale) if kscale > 0 else abs(Kg).max() == 0.0
+    assert np.abs(dg - dr).max() <= tol * max(np.abs(dr).max(), 1e-300)
+
+
+def test_boundary_bad_face_is_reported(mf):
+    say("tet10 bad face id")
+    mesh = W.tet10_mesh((1, 1, 1))
+    dev = torch.device("cuda:0")
+    pat = gpu_pattern(mf, mesh, 1)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    pat.assemble(mf.Form(mf.POISSON), coords)  # clears the status
+    pat.assemble_boundary(mf.BFORM_PENALTY, coords, torch.tensor([0, 1], dtype=torch.int32, device=dev),
+                          torch.tensor([2, 4], dtype=torch.uint8, device=dev))
+    assert pat.status()[0] == mf.ERR_ARG  # local face 4 of a tetrahedron
