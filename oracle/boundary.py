@@ -154,3 +154,82 @@ def _flow_point(kind, coef, value, w, n, N, gn, U, uq, gq, Ke, Re):
             Re[a, 3] += w * N[a] * ((uw - u) @ n)
             for k in range(3):
                 Ke[a, 3, :, k] -= w * N[a] * N * n[k]
+
+
+def edge_nodes_2d(nen, eid):
+    """Local ids of the nodes on edge eid = 2 * axis + side of a quadrilateral: the two
+    corners with bit `axis` equal to `side`, then (8-node element) the edge midpoint."""
+    axis, side = eid >> 1, eid & 1
+    nodes = [a for a in range(4) if ((a >> axis) & 1) == side]
+    if nen == 8:
+        nodes.append(6 + side if axis == 0 else 4 + side)
+    return nodes
+
+
+def assemble_boundary_2d(pat, kind, coef, value, edge_elem, edge_id, state=None, target=None):
+    """Boundary forms on edges of 4- and 8-node quadrilaterals: (scipy CSR, d), the forms
+    and signs of the 3D faces (penalty, convection, radiation, traction with sigma^l the
+    leading 2x2 block of value or a nodal traction target).  Edge eid = 2 * axis + side is
+    xi_axis = -1 or +1; Gauss rule with 2 (4-node) or 3 (8-node) points along it;
+    ds = |dx/dt|, n the unit normal to the tangent pointing away from the element's
+    centre."""
+    import scipy.sparse as sp
+    from .serendipity import basis8
+    mesh = pat.mesh
+    nf, nen = pat.nf, mesh.nen
+    value = np.asarray(value, dtype=np.float64)
+    npts = 3 if nen == 8 else 2
+    gp, gw = np.polynomial.legendre.leggauss(npts)
+    rows, cols, vals = [], [], []
+    d = np.zeros(pat.n_rows)
+    for e, eid in zip(np.asarray(edge_elem), np.asarray(edge_id)):
+        e, eid = int(e), int(eid)
+        axis, side = eid >> 1, eid & 1
+        other = 1 - axis
+        nodes = mesh.conn[:, e]
+        X = mesh.coords[:, nodes].T
+        centre = X[:4].mean(axis=0)
+        U = state[:, nodes].T if state is not None else np.zeros((nen, nf))
+        G = np.asarray(target)[:, nodes].T if target is not None else np.tile(value[:nf], (nen, 1))
+        Ke = np.zeros((nen, nf, nen, nf))
+        Re = np.zeros((nen, nf))
+        for t, wq in zip(gp, gw):
+            xi = np.zeros(2)
+            xi[axis] = 1.0 if side else -1.0
+            xi[other] = t
+            N, dN = basis8(xi) if nen == 8 else basis(2, xi)
+            tang = X.T @ dN[:, other]
+            nr = np.array([tang[1], -tang[0]])
+            if nr @ (N @ X - centre) < 0.0:
+                nr = -nr
+            ds = np.linalg.norm(tang)
+            n = nr / np.linalg.norm(nr)
+            w = wq * ds
+            uq, gq = N @ U, N @ G
+            for i in range(nf):
+                if kind in (PENALTY, CONVECTION):
+                    Ke[:, i, :, i] += coef * w * np.outer(N, N)
+                    Re[:, i] += coef * w * N * (uq[i] - gq[i])
+                elif kind == RADIATION:
+                    Ke[:, 0, :, 0] += coef * w * 4.0 * uq[0] ** 3 * np.outer(N, N)
+                    Re[:, 0] += coef * w * N * (uq[0] ** 4 - gq[0] ** 4)
+                elif kind == TRACTION:
+                    tv = gq if target is not None else value.reshape(3, 3)[:2, :2] @ n
+                    Re[:, i] -= w * N * tv[i]
+                else:
+                    raise ValueError(kind)
+        en = edge_nodes_2d(nen, eid)
+        for a in en:
+            for i in range(nf):
+                r = _dof(pat, nodes[a], i)
+                d[r] -= Re[a, i]
+                for b in en:
+                    for j in range(nf):
+                        if Ke[a, i, b, j] != 0.0:
+                            rows.append(r)
+                            cols.append(_dof(pat, nodes[b], j))
+                            vals.append(Ke[a, i, b, j])
+        off = [a for a in range(nen) if a not in en]
+        assert np.abs(Re[off]).max(initial=0.0) < 1e-13 * max(1.0, np.abs(Re).max())
+    K = sp.coo_matrix((vals, (rows, cols)), shape=(pat.n_rows, pat.n_rows)).tocsr()
+    return K, d

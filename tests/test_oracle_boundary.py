@@ -223,3 +223,46 @@ def test_fix_pressure_velocity_blocks_are_antisymmetric():
     pu = np.ix_(dof % 4 == 3, dof % 4 < 3)
     assert np.abs(K[up]).max() > 0.1
     assert np.abs(K[up] + K[pu].T).max() < 1e-15
+
+
+# ---------------------------------------------------------------- 2D edges
+
+@pytest.mark.parametrize("nen", [4, 8])
+def test_quadrilateral_edges(nen):
+    """Edges of 4- and 8-node quadrilaterals: edge mass sums to the perimeter; a uniform
+    traction on a straight edge gives the consistent loads (1/2, 1/2) or (1/6, 2/3, 1/6)
+    of the total; a uniform stress over the closed boundary sums to zero and over one
+    side to sigma n times its length; the radiation tangent by central differences."""
+    import oracle.serendipity as S
+    L, n = [1.5, 0.8], (3, 2)
+    mesh = (W.structured_mesh(n, jitter=0.2, seed=1, lengths=L) if nen == 4
+            else W.serendipity_mesh_2d(n, jitter=0.2, seed=1, lengths=L))
+    P1 = (lambda nf: O.Pattern(mesh, nf)) if nen == 4 else (lambda nf: S.Pattern20(mesh, nf))
+    edges = W.rect_edges(n)
+    K, _ = OB.assemble_boundary_2d(P1(1), OB.PENALTY, 1.0, [0.0], *edges)
+    assert abs(K.sum() - 2 * (L[0] + L[1])) < 1e-13
+    sig = np.zeros(9)
+    sig[[0, 1, 3, 4]] = [0.3, -0.7, 0.4, 1.1]  # leading 2x2 block
+    _, d = OB.assemble_boundary_2d(P1(2), OB.TRACTION, 1.0, sig, *edges)
+    assert np.abs(d.reshape(-1, 2).sum(axis=0)).max() < 1e-14
+    top = W.rect_edges(n, sides=[3])  # y = L_y, n = +y
+    _, d = OB.assemble_boundary_2d(P1(2), OB.TRACTION, 1.0, sig, *top)
+    assert np.abs(d.reshape(-1, 2).sum(axis=0) - np.array([sig[1], sig[4]]) * L[0]).max() < 1e-14
+    # one edge: consistent loads
+    e, eid = int(top[0][0]), int(top[1][0])
+    _, d1 = OB.assemble_boundary_2d(P1(2), OB.TRACTION, 1.0, sig, top[0][:1], top[1][:1])
+    F = d1.reshape(-1, 2)
+    en = OB.edge_nodes_2d(nen, eid)
+    x = mesh.coords[:, mesh.conn[en[:2], e]]
+    length = np.linalg.norm(x[:, 1] - x[:, 0])
+    t = np.array([sig[1], sig[4]])
+    share = [0.5, 0.5] if nen == 4 else [1 / 6, 1 / 6, 2 / 3]
+    for a, s in zip(en, share):
+        assert np.abs(F[mesh.conn[a, e]] - s * length * t).max() < 1e-14
+    T = 1.0 + np.random.default_rng(2).random((1, mesh.n_nodes))
+    Kr, _ = OB.assemble_boundary_2d(P1(1), OB.RADIATION, 0.7, [1.2], *edges, state=T)
+    dv = np.random.default_rng(3).normal(size=T.shape)
+    h = 1e-6
+    _, dp = OB.assemble_boundary_2d(P1(1), OB.RADIATION, 0.7, [1.2], *edges, state=T + h * dv)
+    _, dm = OB.assemble_boundary_2d(P1(1), OB.RADIATION, 0.7, [1.2], *edges, state=T - h * dv)
+    assert np.abs(Kr @ dv[0] + (dp - dm) / (2 * h)).max() < 1e-7

@@ -374,6 +374,27 @@ def tet10_mesh(n, jitter: float = 0.0, seed=None, lengths=None) -> Mesh:
     return Mesh(coords, conn.astype(np.int32))
 
 
+def rect_edges(n, sides=None):
+    """Element edges on the sides of a structured 2D rectangle of n = (nx, ny) elements.
+
+    sides: local edge ids 2 * axis + side (axis 0: the edges xi = -1 / +1, on x = 0 and
+    x = L_x; axis 1: eta = -1 / +1, on y = 0 and y = L_y); default all four.  Returns
+    (element ids int32, local edge ids uint8)."""
+    nx, ny = (int(v) for v in n)
+    sides = range(4) if sides is None else sides
+    ex, ey = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    eid = (ex + nx * ey).astype(np.int64)
+    idx = (ex, ey)
+    elems, ids = [], []
+    for f in sides:
+        axis, side = f >> 1, f & 1
+        sel = idx[axis] == ((n[axis] - 1) if side else 0)
+        e = np.sort(eid[sel])
+        elems.append(e)
+        ids.append(np.full(e.shape, f))
+    return np.concatenate(elems).astype(np.int32), np.concatenate(ids).astype(np.uint8)
+
+
 def tet10_box_faces(mesh: Mesh, lengths=None):
     """Boundary faces of a tet10_mesh box: (element ids int32, local faces uint8), where
     local face k is the face opposite vertex k; a face is on the boundary when its three
