@@ -316,11 +316,14 @@ typedef struct {
  * [n_faces] element ids and face_id [n_faces] local faces 2 * axis + side (side 1: the
  * face at xi_axis = +1), device arrays.  state [nf][n_nodes] (device, precision prec, or
  * NULL = 0) is the linearisation point of the radiation, flux, penalty and flow residuals.
- * P must be a 3D pattern with full coupling: 8-node hexahedra (all forms, 2x2 face
- * rule), 20-node hexahedra (penalty, convection, radiation and traction, over the eight
- * nodes of the face with the 3x3 face rule) or 10-node tetrahedra (the same four forms
- * over the six nodes of the face; face_id k is the face opposite vertex k, 0..3;
- * collapsed 4x4 Gauss rule of the triangle); MF_ERR_UNSUPPORTED otherwise.
+ * P must have full coupling and be: 8-node hexahedra (all forms, 2x2 face rule),
+ * 20-node hexahedra (penalty, convection, radiation and traction, over the eight nodes of
+ * the face with the 3x3 face rule), 10-node tetrahedra (the same four forms over the six
+ * nodes of the face; face_id k is the face opposite vertex k, 0..3; collapsed 4x4 Gauss
+ * rule of the triangle) or 4- and 8-node quadrilaterals (the same four forms on element
+ * edges: face_id 2 * axis + side as for hexahedra, 2 or 3 Gauss points along the edge,
+ * 1 or 2 fields, sigma^l the leading 2x2 block of value[0..9)); MF_ERR_UNSUPPORTED
+ * otherwise.
  * Async on the stream.  Reported by
  * mf_status_poll (until the next mf_assemble clears the status): a face whose element id
  * or local face is out of range (skipped; MF_ERR_ARG with the first such face), and a

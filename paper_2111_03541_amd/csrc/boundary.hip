@@ -538,6 +538,143 @@ __global__ void __launch_bounds__(kThreads) k_boundary_tet10(BParams p)
     if (rrow != 0.0) unsafeAtomicAdd(d + row, (T)(-rrow));
 }
 
+// Edges of quadrilaterals (NEN = 4 or 8): one thread per (edge, edge node, field).  Edge
+// eid = 2 * axis + side is xi_axis = -1 or +1, with its two corners and, for the 8-node
+// element, its midpoint; Gauss rule with 2 or 3 points along the edge; ds = |dx/dt| and n
+// the unit normal pointing away from the element's centre.  Penalty, convection,
+// radiation and traction (sigma^l: the leading 2x2 block of value, or a nodal target).
+template <int NEN, int NF, typename T>
+__global__ void __launch_bounds__(kThreads) k_boundary_2d(BParams p)
+{
+    constexpr int NE = NEN == 8 ? 3 : 2;  // nodes per edge, and Gauss points
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p.n_faces * NE * NF) return;
+    const int64_t f = t % p.n_faces;
+    const int ki = (int)(t / p.n_faces);
+    const int me = ki / NF, i = ki % NF;
+    const int64_t e = p.face_elem[f];
+    const int eid = p.face_id[f];
+    if (e < 0 || e >= p.n_el || eid > 3) {
+        if (ki == 0) atomicMin(p.status + 1, (unsigned long long)f);
+        return;
+    }
+    const int axis = eid >> 1, side = eid & 1, other = 1 - axis;
+    int loc[3];
+    for (int a = 0, c = 0; a < 4; ++a)
+        if (((a >> axis) & 1) == side) loc[c++] = a;
+    if (NEN == 8) loc[2] = axis == 0 ? 6 + side : 4 + side;
+    double x[NE][2], U[NE], G[NE], centre[2] = {0.0, 0.0};
+    int32_t node[NE];
+    const T* st = (const T*)p.state;
+    const T* tg = (const T*)p.target;
+#pragma unroll
+    for (int b = 0; b < NE; ++b) {
+        node[b] = p.conn[(int64_t)loc[b] * p.n_el + e];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) x[b][m] = p.coords[(int64_t)m * p.n_nodes + node[b]];
+        U[b] = st ? (double)st[(int64_t)i * p.n_nodes + node[b]] : 0.0;
+        G[b] = tg ? (double)tg[(int64_t)i * p.n_nodes + node[b]] : p.form.value[i];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int32_t v = p.conn[(int64_t)a * p.n_el + e];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) centre[m] += 0.25 * p.coords[(int64_t)m * p.n_nodes + v];
+    }
+    const mf_bform_kind kind = p.form.kind;
+    const double c = p.form.coef;
+    double krow[NE];
+#pragma unroll
+    for (int b = 0; b < NE; ++b) krow[b] = 0.0;
+    double rrow = 0.0;
+    const double g3 = 0.7745966692414834;  // sqrt(3/5)
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const double tq = NE == 3 ? (q - 1) * g3 : (q ? kGaussPt : -kGaussPt);
+        const double wq = NE == 3 ? (q == 1 ? 8.0 / 9.0 : 5.0 / 9.0) : 1.0;
+        double xi[2];
+        xi[axis] = side ? 1.0 : -1.0;
+        xi[other] = tq;
+        double N[NE], tang[2] = {0.0, 0.0}, xq[2] = {0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < NE; ++b) {
+            double dN[2];
+            if constexpr (NEN == 8) {
+                shape8(loc[b], xi, N[b], dN);
+            } else {
+                const int bx = loc[b] & 1, by = loc[b] >> 1;
+                const double fx = 0.5 * (1.0 + (bx ? xi[0] : -xi[0])), fy = 0.5 * (1.0 + (by ? xi[1] : -xi[1]));
+                N[b] = fx * fy;
+                dN[0] = (bx ? 0.5 : -0.5) * fy;
+                dN[1] = (by ? 0.5 : -0.5) * fx;
+            }
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                tang[m] = fma(x[b][m], dN[other], tang[m]);
+                xq[m] = fma(x[b][m], N[b], xq[m]);
+            }
+        }
+        const double ds = sqrt(tang[0] * tang[0] + tang[1] * tang[1]);
+        if (!(ds > 0.0)) {
+            atomicMin(p.status, (unsigned long long)e);
+            return;
+        }
+        double nv[2] = {tang[1] / ds, -tang[0] / ds};
+        if (nv[0] * (xq[0] - centre[0]) + nv[1] * (xq[1] - centre[1]) < 0.0) {
+            nv[0] = -nv[0];
+            nv[1] = -nv[1];
+        }
+        const double w = wq * ds;
+        const double Na = N[me];
+        double uq = 0.0, gq = 0.0;
+#pragma unroll
+        for (int b = 0; b < NE; ++b) {
+            uq = fma(N[b], U[b], uq);
+            gq = fma(N[b], G[b], gq);
+        }
+        if (kind == MF_BFORM_PENALTY || kind == MF_BFORM_CONVECTION) {
+#pragma unroll
+            for (int b = 0; b < NE; ++b) krow[b] += c * w * Na * N[b];
+            rrow += c * w * Na * (uq - gq);
+        } else if (kind == MF_BFORM_RADIATION) {
+#pragma unroll
+            for (int b = 0; b < NE; ++b) krow[b] += c * w * Na * 4.0 * uq * uq * uq * N[b];
+            rrow += c * w * Na * (uq * uq * uq * uq - gq * gq * gq * gq);
+        } else {  // MF_BFORM_TRACTION
+            const double* S = p.form.value;
+            const double ti = tg ? gq : S[3 * i] * nv[0] + S[3 * i + 1] * nv[1];
+            rrow -= w * Na * ti;
+        }
+    }
+    const int a = loc[me];
+    const int64_t va = node[me];
+    const int64_t row = p.field_major ? (int64_t)i * p.n_nodes + va : (int64_t)NF * va + i;
+    const int64_t rs = p.row_ptr[row];
+    const int64_t deg = p.nbr_ptr[va + 1] - p.nbr_ptr[va];
+    T* K = (T*)p.K;
+    T* d = (T*)p.d;
+#pragma unroll
+    for (int b = 0; b < NE; ++b) {
+        if (krow[b] == 0.0) continue;
+        const int64_t rk = p.rank[(int64_t)(a * NEN + loc[b]) * p.n_el + e];
+        const int64_t pos = p.field_major ? rs + i * deg + rk : rs + rk * NF + i;
+        unsafeAtomicAdd(K + pos, (T)krow[b]);
+    }
+    if (rrow != 0.0) unsafeAtomicAdd(d + row, (T)(-rrow));
+}
+
+template <int NEN, int NF, typename T>
+mf_status launch_boundary_2d(const BParams& p, hipStream_t s)
+{
+    constexpr int NE = NEN == 8 ? 3 : 2;
+    const int64_t n = p.n_faces * NE * NF;
+    if (n == 0) return MF_OK;
+    if (n > 0xffffffffLL - kThreads) return set_error(MF_ERR_ARG, "too many edges for one launch");
+    k_boundary_2d<NEN, NF, T><<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(p);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
 template <int NF, typename T>
 mf_status launch_boundary_tet10(const BParams& p, hipStream_t s)
 {
@@ -582,8 +719,9 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
                                           void* d, void* stream)
 {
     if (!P || !form) return set_error(MF_ERR_ARG, "pattern or form is NULL");
-    if (P->dim != 3 || (P->nen != 8 && P->nen != 20 && P->nen != 10))
-        return set_error(MF_ERR_UNSUPPORTED, "boundary forms need a 3D hexahedron or tetrahedron pattern");
+    const bool two_d = P->dim == 2;
+    if (two_d ? (P->nen != 4 && P->nen != 8) : (P->nen != 8 && P->nen != 20 && P->nen != 10))
+        return set_error(MF_ERR_UNSUPPORTED, "boundary forms need quadrilaterals, hexahedra or tetrahedra");
     const bool quad = P->order == 2;
     const bool tet = P->nen == 10;
     if (prec != MF_F64 && prec != MF_F32) return set_error(MF_ERR_ARG, "unknown precision %d", (int)prec);
@@ -594,7 +732,8 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
     const int nf = P->nf;
     switch (form->kind) {
         case MF_BFORM_PENALTY:
-            if (nf != 1 && nf != 3) return set_error(MF_ERR_ARG, "penalty needs 1 or 3 fields, pattern has %d", nf);
+            if (nf != 1 && nf != P->dim)
+                return set_error(MF_ERR_ARG, "penalty needs 1 or %d fields, pattern has %d", P->dim, nf);
             break;
         case MF_BFORM_CONVECTION:
         case MF_BFORM_RADIATION:
@@ -602,7 +741,7 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
             if (nf != 1) return set_error(MF_ERR_ARG, "this boundary form is scalar; pattern has %d fields", nf);
             break;
         case MF_BFORM_TRACTION:
-            if (nf != 3) return set_error(MF_ERR_ARG, "traction needs 3 fields, pattern has %d", nf);
+            if (nf != P->dim) return set_error(MF_ERR_ARG, "traction needs %d fields, pattern has %d", P->dim, nf);
             break;
         case MF_BFORM_NS_INFLOW:
         case MF_BFORM_NS_OUTFLOW:
@@ -611,7 +750,7 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
             break;
         default: return set_error(MF_ERR_ARG, "unknown boundary form %d", (int)form->kind);
     }
-    if (quad && (form->kind == MF_BFORM_FLUX || nf == 4))
+    if ((quad || two_d) && (form->kind == MF_BFORM_FLUX || nf == 4))
         return set_error(MF_ERR_UNSUPPORTED, "the flux and flow boundary forms need 8-node hexahedra");
     if (tet && n_faces > 0 && !face_id) return set_error(MF_ERR_ARG, "NULL face_id");
     hipStream_t s = (hipStream_t)stream;
@@ -634,6 +773,15 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
     p.d = d;
     p.status = P->status;
     const_cast<mf_pattern_s*>(P)->last_stream = s;
+    if (two_d) {
+        if (nf != 1 && nf != 2) return set_error(MF_ERR_ARG, "edge forms need 1 or 2 fields, pattern has %d", nf);
+        if (P->nen == 8) {
+            if (prec == MF_F64) return nf == 1 ? launch_boundary_2d<8, 1, double>(p, s) : launch_boundary_2d<8, 2, double>(p, s);
+            return nf == 1 ? launch_boundary_2d<8, 1, float>(p, s) : launch_boundary_2d<8, 2, float>(p, s);
+        }
+        if (prec == MF_F64) return nf == 1 ? launch_boundary_2d<4, 1, double>(p, s) : launch_boundary_2d<4, 2, double>(p, s);
+        return nf == 1 ? launch_boundary_2d<4, 1, float>(p, s) : launch_boundary_2d<4, 2, float>(p, s);
+    }
     if (tet) {
         if (prec == MF_F64) return nf == 1 ? launch_boundary_tet10<1, double>(p, s) : launch_boundary_tet10<3, double>(p, s);
         return nf == 1 ? launch_boundary_tet10<1, float>(p, s) : launch_boundary_tet10<3, float>(p, s);

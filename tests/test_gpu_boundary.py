@@ -193,3 +193,53 @@ def test_cavity_newton_with_weak_boundaries(mf):
     assert np.abs(sg - sr).max() < 1e-8 * np.abs(sr).max()
     # recirculation under the lid: the axial velocity changes sign
     assert sg[0].min() < -0.1 and sg[0][np.abs(mesh.coords[2] - 1.0) < 1e-12].mean() > 0.5
+
+
+# ---------------------------------------------------------------- 2D edges
+
+EDGE_CASES = [  # (name, kind, nf, coef, value, uses state, uses target)
+    ("penalty1", OB.PENALTY, 1, 40.0, [0.7], True, False),
+    ("penalty2_target", OB.PENALTY, 2, 20.0, [0.0, 0.0], True, True),
+    ("convection", OB.CONVECTION, 1, 3.0, [2.5], True, False),
+    ("radiation", OB.RADIATION, 1, 0.8, [1.3], True, False),
+    ("traction", OB.TRACTION, 2, 1.0, [0.3, -0.7, 0.0, 0.4, 1.1, 0.0, 0.0, 0.0, 0.0], False, False),
+    ("traction_target", OB.TRACTION, 2, 1.0, [], False, True),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("numbering", [0, 1])
+@pytest.mark.parametrize("nen", [4, 8])
+@pytest.mark.parametrize("case", EDGE_CASES, ids=[c[0] for c in EDGE_CASES])
+def test_edge_form_matches_oracle(mf, case, nen, numbering, prec):
+    import oracle.serendipity as S
+    name, kind, nf, coef, value, use_state, use_target = case
+    say("edge", name, "nen", nen, "numbering", numbering, "prec", prec)
+    n, L = (4, 3), [1.2, 0.9]
+    mesh = (W.structured_mesh(n, jitter=0.2, seed=3, lengths=L) if nen == 4
+            else W.serendipity_mesh_2d(n, jitter=0.2, seed=3, lengths=L))
+    fe, fi = W.rect_edges(n)
+    sel = np.random.default_rng(5).permutation(fe.shape[0])[: fe.shape[0] * 3 // 4]
+    fe, fi = fe[sel], fi[sel]
+    rng = np.random.default_rng(6)
+    state = 1.0 + rng.random((nf, mesh.n_nodes)) if use_state else None
+    target = rng.standard_normal((nf, mesh.n_nodes)) if use_target else None
+    fdt = np.float64 if prec == 0 else np.float32
+    if prec == 1:
+        state = None if state is None else state.astype(np.float32).astype(np.float64)
+        target = None if target is None else target.astype(np.float32).astype(np.float64)
+    opat = O.Pattern(mesh, nf, numbering=numbering) if nen == 4 else S.Pattern20(mesh, nf, numbering)
+    Kr, dr = OB.assemble_boundary_2d(opat, kind, coef, value, fe, fi, state=state, target=target)
+    dev = torch.device("cuda:0")
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 2, nf, numbering=numbering)
+    tt = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=fdt)).to(dev)
+    K, d = pat.assemble_boundary(kind, torch.from_numpy(mesh.coords).to(dev), torch.from_numpy(fe).to(dev),
+                                 torch.from_numpy(fi).to(dev), coef=coef, value=value, state=tt(state),
+                                 target=tt(target), precision=prec)
+    assert pat.status()[0] == mf.OK
+    Kg = opat.to_scipy(K.double().cpu().numpy())
+    dg = d.double().cpu().numpy()
+    tol = 1e-12 if prec == 0 else 1e-5
+    kscale = abs(Kr).max() if Kr.nnz else 0.0
+    assert (abs(Kg - Kr).max() <= tol * kscale) if kscale > 0 else abs(Kg).max() == 0.0
+    assert np.abs(dg - dr).max() <= tol * max(np.abs(dr).max(), 1e-300)
