@@ -115,6 +115,6 @@ def test_quad8_argument_errors(mf):
     with pytest.raises(mf.MFError):  # the 2D flow form is not built on this element
         pat3.assemble(mf.Form(mf.NS_SUPG, rho=1.0, mu=0.01), coords,
                       lin_state=torch.zeros((3, mesh.n_nodes), dtype=torch.float64, device=dev))
-    with pytest.raises(mf.MFError):  # boundary forms are for 3D hexahedra
-        pat.assemble_boundary(mf.BFORM_PENALTY, coords, torch.zeros(1, dtype=torch.int32, device=dev),
+    with pytest.raises(mf.MFError):  # the flux form needs 8-node hexahedra
+        pat.assemble_boundary(mf.BFORM_FLUX, coords, torch.zeros(1, dtype=torch.int32, device=dev),
                               torch.zeros(1, dtype=torch.uint8, device=dev))
