@@ -446,6 +446,29 @@ mf_status mf_ns_newton(const mf_pattern_t* P, const mf_form* form, const double*
                        const uint8_t* dirichlet, const mf_quadrature* quad, const mf_newton_opts* opts,
                        mf_newton_result* res, void* stream);
 
+/* One set of boundary faces with its form (see mf_assemble_boundary): face_elem and
+   face_id are device arrays of n_faces entries; target is NULL or [nf][n_nodes] FP64. */
+typedef struct {
+    mf_bform form;
+    int64_t n_faces;
+    const int32_t* face_elem;
+    const uint8_t* face_id;
+    const double* target;
+} mf_bset;
+
+/*
+ * mf_ns_newton_ex - mf_ns_newton with the flow's boundary forms (Sec. 4.3: inflow, outflow,
+ * fix; any form of mf_assemble_boundary) in the residual and tangent of every step: each
+ * step assembles the domain form without elimination, adds the n_bsets face sets (host
+ * array bsets, linearised at the current state), and only then eliminates the Dirichlet
+ * rows.  With n_bsets = 0 it is mf_ns_newton.  Errors: those of mf_ns_newton and of
+ * mf_assemble_boundary (a face set whose form does not fit the pattern: MF_ERR_ARG).
+ */
+mf_status mf_ns_newton_ex(const mf_pattern_t* P, const mf_form* form, const double* coords, double* state,
+                          const uint8_t* dirichlet, const mf_bset* bsets, int32_t n_bsets,
+                          const mf_quadrature* quad, const mf_newton_opts* opts, mf_newton_result* res,
+                          void* stream);
+
 /* ------------------------------------------------------------------------------------
  * Learned preconditioner for mf_pcg on structured-grid scalar systems (node id
  * x + nx (y + ny z), one DOF per node).  A small linear multilevel 3D convolution network

@@ -97,6 +97,11 @@ class _BForm(C.Structure):
     _fields_ = [("kind", C.c_int), ("coef", C.c_double), ("value", C.c_double * 9)]
 
 
+class _BSet(C.Structure):
+    _fields_ = [("form", _BForm), ("n_faces", C.c_int64), ("face_elem", C.c_void_p), ("face_id", C.c_void_p),
+                ("target", C.c_void_p)]
+
+
 class _NewtonOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_int32), ("lin_tol", C.c_double),
                 ("lin_maxit", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32)]
@@ -120,7 +125,7 @@ EXPORTS = [
     "mf_assemble_ex", "mf_status_poll", "mf_last_error", "mf_version", "mf_pcg",
     "mf_batch_create", "mf_batch_tune", "mf_batch_run", "mf_batch_info", "mf_batch_destroy",
     "mf_nn_create", "mf_nn_params", "mf_nn_set_system", "mf_nn_apply", "mf_nn_train_step", "mf_nn_destroy", "mf_spmv",
-    "mf_bicgstab", "mf_ns_newton", "mf_assemble_boundary", "mf_heat_transient",
+    "mf_bicgstab", "mf_ns_newton", "mf_ns_newton_ex", "mf_assemble_boundary", "mf_heat_transient",
 ]
 
 
@@ -162,6 +167,8 @@ def load():
     lib.mf_bicgstab.argtypes = [C.POINTER(_CSR), P, P, C.POINTER(_PcgOpts), C.POINTER(_PcgResult), P]
     lib.mf_ns_newton.argtypes = [P, C.POINTER(_Form), P, P, P, C.POINTER(_Quad), C.POINTER(_NewtonOpts),
                                  C.POINTER(_NewtonResult), P]
+    lib.mf_ns_newton_ex.argtypes = [P, C.POINTER(_Form), P, P, P, C.POINTER(_BSet), C.c_int32, C.POINTER(_Quad),
+                                    C.POINTER(_NewtonOpts), C.POINTER(_NewtonResult), P]
     lib.mf_nn_destroy.argtypes = [P]
     lib.mf_nn_destroy.restype = None
     lib.mf_last_error.restype = C.c_char_p
@@ -511,9 +518,12 @@ def bicgstab(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond
 
 
 def ns_newton(pattern, form, coords, state, dirichlet=None, rtol=1e-10, atol=0.0, max_steps=20, lin_tol=1e-10,
-              lin_maxit=20000, check_every=8, use_graph=True, points_per_axis=2, stream=None, raise_on_fail=True):
+              lin_maxit=20000, check_every=8, use_graph=True, points_per_axis=2, stream=None, raise_on_fail=True,
+              boundary=()):
     """Newton iteration for the steady flow form; state [4][n_nodes] FP64 (cuda) is updated
-    in place.  Returns the result dict (steps, converged, lin_iterations, res_norm list)."""
+    in place.  boundary: face sets (kind, face_elem int32 cuda, face_id uint8 cuda, coef,
+    value, target or None) whose boundary forms enter every step before the Dirichlet
+    elimination.  Returns the result dict (steps, converged, lin_iterations, res_norm)."""
     import torch
     lib = load()
     assert state.dtype == torch.float64 and state.is_cuda and state.is_contiguous()
@@ -523,8 +533,16 @@ def ns_newton(pattern, form, coords, state, dirichlet=None, rtol=1e-10, atol=0.0
     opts = _NewtonOpts(rtol, atol, max_steps, lin_tol, lin_maxit, check_every, int(bool(use_graph)))
     res = _NewtonResult()
     q = _Quad(points_per_axis)
-    st = lib.mf_ns_newton(pattern.handle, C.byref(form.c), _ptr(coords), _ptr(state), _ptr(dirichlet), C.byref(q),
-                          C.byref(opts), C.byref(res), _stream(stream))
+    sets = (_BSet * max(1, len(boundary)))()
+    for k, (kind, fe, fi, coef, value, target) in enumerate(boundary):
+        assert fe.dtype == torch.int32 and fi.dtype == torch.uint8 and fe.is_cuda and fi.is_cuda
+        if target is not None:
+            assert target.dtype == torch.float64 and target.is_cuda and target.is_contiguous()
+        vals = list(value) + [0.0] * (9 - len(value))
+        sets[k] = _BSet(_BForm(kind, coef, (C.c_double * 9)(*vals)), int(fe.shape[0]), _ptr(fe), _ptr(fi),
+                        _ptr(target))
+    st = lib.mf_ns_newton_ex(pattern.handle, C.byref(form.c), _ptr(coords), _ptr(state), _ptr(dirichlet), sets,
+                             len(boundary), C.byref(q), C.byref(opts), C.byref(res), _stream(stream))
     out = {"steps": res.steps, "converged": bool(res.converged), "lin_iterations": res.lin_iterations,
            "res_norm": [res.res_norm[k] for k in range(min(res.steps + 1, NEWTON_MAX_HISTORY))], "status": st}
     if st != OK and raise_on_fail:

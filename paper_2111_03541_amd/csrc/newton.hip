@@ -71,7 +71,16 @@ extern "C" mf_status mf_ns_newton(const mf_pattern_t* P, const mf_form* form, co
                                   const uint8_t* dirichlet, const mf_quadrature* quad, const mf_newton_opts* opts,
                                   mf_newton_result* res, void* stream)
 {
+    return mf_ns_newton_ex(P, form, coords, state, dirichlet, nullptr, 0, quad, opts, res, stream);
+}
+
+extern "C" mf_status mf_ns_newton_ex(const mf_pattern_t* P, const mf_form* form, const double* coords,
+                                     double* state, const uint8_t* dirichlet, const mf_bset* bsets, int32_t n_bsets,
+                                     const mf_quadrature* quad, const mf_newton_opts* opts, mf_newton_result* res,
+                                     void* stream)
+{
     if (!P || !form || !quad || !opts || !res) return set_error(MF_ERR_ARG, "NULL pattern, form, quadrature, opts or res");
+    if (n_bsets < 0 || (n_bsets > 0 && !bsets)) return set_error(MF_ERR_ARG, "n_bsets < 0 or bsets NULL");
     if (form->kind != MF_FORM_NS_SUPG) return set_error(MF_ERR_ARG, "mf_ns_newton needs the flow form");
     if (P->dim != 3 || P->nf != 4) return set_error(MF_ERR_ARG, "mf_ns_newton needs a 3D pattern with 4 fields");
     if (P->n_rows > 0 && (!coords || !state)) return set_error(MF_ERR_ARG, "coords or state is NULL");
@@ -116,7 +125,15 @@ extern "C" mf_status mf_ns_newton(const mf_pattern_t* P, const mf_form* form, co
 
     mf_fields F{};
     F.lin_state = state;
-    F.dirichlet = dirichlet;
+    // with boundary forms the elimination comes after the faces are added
+    F.dirichlet = n_bsets > 0 ? nullptr : dirichlet;
+    AssembleArgs elim{};
+    elim.P = P;
+    elim.dirichlet = dirichlet;
+    elim.prec = MF_F64;
+    elim.K = K;
+    elim.d = d;
+    elim.stream = s;
     mf_csr A{n, P->row_ptr, P->col_idx, K};
     mf_pcg_opts lo{};
     lo.tol = opts->lin_tol;
@@ -129,6 +146,16 @@ extern "C" mf_status mf_ns_newton(const mf_pattern_t* P, const mf_form* form, co
     for (int k = 0;; ++k) {
         mf_status st = mf_assemble(P, form, coords, &F, quad, MF_F64, K, d, stream);
         if (st != MF_OK) return st;
+        if (n_bsets > 0) {
+            for (int b = 0; b < n_bsets; ++b) {
+                const mf_bset& B = bsets[b];
+                st = mf_assemble_boundary(P, &B.form, coords, B.n_faces, B.face_elem, B.face_id, state, B.target,
+                                          MF_F64, K, d, stream);
+                if (st != MF_OK) return st;
+            }
+            st = apply_dirichlet(elim);
+            if (st != MF_OK) return st;
+        }
         int64_t bad = -1;
         st = mf_status_poll(P, &bad);
         if (st != MF_OK) return st;

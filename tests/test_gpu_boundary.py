@@ -243,3 +243,48 @@ def test_edge_form_matches_oracle(mf, case, nen, numbering, prec):
     kscale = abs(Kr).max() if Kr.nnz else 0.0
     assert (abs(Kg - Kr).max() <= tol * kscale) if kscale > 0 else abs(Kg).max() == 0.0
     assert np.abs(dg - dr).max() <= tol * max(np.abs(dr).max(), 1e-300)
+
+
+def test_newton_driver_with_weak_boundaries(mf):
+    """The same weakly bounded cavity through the library's Newton driver
+    (mf_ns_newton_ex: face sets added every step before the elimination of the one pinned
+    pressure DOF): converges and matches the oracle's converged Newton state."""
+    import scipy.sparse.linalg as spla
+    say("newton driver, weak boundaries")
+    n = (6, 6, 6)
+    mesh = W.structured_mesh(n, jitter=0.1, seed=12)
+    rho, mu, tau_b = 1.0, 0.05, 10.0
+    params = {"rho": rho, "mu": mu, "tau_m": 0.02, "tau_c": 0.05}
+    sets = [(OB.NS_INFLOW, W.box_faces(n, sides=[5]), [1.0, 0.0, 0.0, rho, mu]),
+            (OB.NS_FIX, W.box_faces(n, sides=[0, 1, 2, 3, 4]), [0.0, 0.0, 0.0, rho, mu])]
+    opat = O.Pattern(mesh, 4)
+    sr = np.zeros((4, mesh.n_nodes))
+    for _ in range(6):
+        Kr, dr = O.assemble(opat, O.NS_SUPG, params, state=sr)
+        Kr = opat.to_scipy(Kr)
+        for kind, faces, value in sets:
+            Kb, db = OB.assemble_boundary(opat, kind, tau_b, value, *faces, state=sr)
+            Kr, dr = Kr + Kb, dr + db
+        Kr = Kr.tolil()
+        Kr[3, :] = 0.0
+        Kr[:, 3] = 0.0
+        Kr[3, 3] = 1.0
+        dr[3] = 0.0
+        sr = sr + spla.spsolve(Kr.tocsr().tocsc(), dr).reshape(-1, 4).T
+    dev = torch.device("cuda:0")
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 4)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    mask = np.zeros(pat.n_rows, np.uint8)
+    mask[3] = 1  # the pressure of node 0
+    st = torch.zeros((4, mesh.n_nodes), dtype=torch.float64, device=dev)
+    bnd = [(kind, torch.from_numpy(fe).to(dev), torch.from_numpy(fi).to(dev), tau_b, value, None)
+           for kind, (fe, fi), value in sets]
+    res = mf.ns_newton(pat, mf.Form(mf.NS_SUPG, **params), coords, st, dirichlet=torch.from_numpy(mask).to(dev),
+                       rtol=1e-12, lin_tol=1e-12, boundary=bnd)
+    say(f"  {res}")
+    assert res["converged"] and res["steps"] <= 8
+    sg = st.cpu().numpy()
+    assert np.abs(sg - sr).max() < 1e-8 * np.abs(sr).max()
+    with pytest.raises(mf.MFError):  # a face set whose form does not fit the pattern
+        mf.ns_newton(pat, mf.Form(mf.NS_SUPG, **params), coords, st, boundary=[
+            (mf.BFORM_TRACTION, bnd[0][1], bnd[0][2], 1.0, [0.0] * 9, None)])
