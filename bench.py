@@ -285,6 +285,37 @@ def bench_newton(dev, n=32, cpu=True, n_cpu=16):
     return out
 
 
+def bench_newton_weak(dev, n=32):
+    """The lid-driven cavity of bench_newton with every wall a weak boundary form (Sec.
+    4.3): the lid as inflow with u^w = (1, 0, 0), the other faces as fix, tau^b = 10, one
+    pressure DOF pinned; Newton through mf_ns_newton_ex to |R| / |R_0| < 1e-10."""
+    import torch
+    import workloads as W
+    import paper_2111_03541_amd as mf
+    mesh = W.structured_mesh((n, n, n))
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 4)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    tm, tc = ns_taus(n)
+    form = mf.Form(mf.NS_SUPG, rho=1.0, mu=0.01, tau_m=tm, tau_c=tc)
+    mask = np.zeros(pat.n_rows, np.uint8)
+    mask[3] = 1  # the pressure of node 0: boundary terms on every face leave its level free
+    sets = [(mf.BFORM_NS_INFLOW, W.box_faces((n, n, n), sides=[5]), [1.0, 0.0, 0.0, 1.0, 0.01]),
+            (mf.BFORM_NS_FIX, W.box_faces((n, n, n), sides=[0, 1, 2, 3, 4]), [0.0, 0.0, 0.0, 1.0, 0.01])]
+    bnd = [(k, torch.from_numpy(fe).to(dev), torch.from_numpy(fi).to(dev), 10.0, v, None) for k, (fe, fi), v in sets]
+    dm = torch.from_numpy(mask).to(dev)
+    st = torch.zeros((4, mesh.n_nodes), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = mf.ns_newton(pat, form, coords, st, dirichlet=dm, rtol=1e-10, boundary=bnd)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    log(f"[bench] Newton weak-boundary cavity {n}^3: {res['steps']} steps, {res['lin_iterations']} BiCGStab "
+        f"iterations, {ms:.1f} ms")
+    return {"n": n, "n_dofs": pat.n_rows, "n_faces": int(sum(int(b[1].shape[0]) for b in bnd)), "steps": res["steps"],
+            "converged": res["converged"], "lin_iterations": res["lin_iterations"], "ms": ms,
+            "res_norm": res["res_norm"]}
+
+
 def bench_boundary(dev, mesh, pat, coords, K, d, cpu=True, steps=10, warmup=3):
     """Boundary forms on the 64^3 elasticity mesh: penalty fix (3 fields) on all six sides
     (24,576 faces), added into the assembled K and d.  The oracle's face loops are timed on
@@ -600,6 +631,7 @@ def main():
     record["secondary"]["transient_96"] = bench_transient(dev, cpu=not args.no_cpu)
     record["secondary"]["hex20_elasticity_24"] = bench_hex20(dev, cpu=not args.no_cpu)
     record["secondary"]["cantilever_hex20_10x4x4"] = bench_cantilever(dev, cpu=not args.no_cpu)
+    record["secondary"]["ns_newton_weak_cavity_32"] = bench_newton_weak(dev)
     if not args.no_cpu:
         log("[bench] timing the oracle on the host")
         record["cpu_baseline"] = cpu_baseline(mesh, E, b)
