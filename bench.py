@@ -526,8 +526,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", choices=["all", "primary"], default="all",
-                    help="primary: the elasticity assembly alone (for counter runs)")
+    ap.add_argument("--only", choices=["all", "primary", "ns", "f32"], default="all",
+                    help="primary: the elasticity assembly alone; ns: the 48^3 flow Jacobian alone; "
+                         "f32: the FP32 64^3 elasticity assembly alone (for counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -542,6 +543,9 @@ def main():
     mf.load()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    if args.only == "ns":
+        print(json.dumps({"ns_48_f32": bench_ns(dev, steps=args.steps, warmup=args.warmup)}), flush=True)
+        return
 
     log("[bench] generating 64^3 elasticity inputs")
     mesh, E, b = elasticity_inputs(64)
@@ -558,6 +562,17 @@ def main():
     K = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
     d = torch.empty(pat.n_rows, dtype=torch.float64, device=dev)
     form = mf.Form(mf.ELASTICITY, coef=1.0, nu=0.3)
+
+    if args.only == "f32":
+        K32 = torch.empty(pat.nnz, dtype=torch.float32, device=dev)
+        d32 = torch.empty(pat.n_rows, dtype=torch.float32, device=dev)
+        E32, b32 = Et.float(), bt.float()
+        _, per32 = time_launches(lambda: pat.assemble(form, coords, precision=mf.F32, elem_param=E32, nodal_src=b32,
+                                                      K=K32, d=d32), args.steps, args.warmup, stream)
+        avg32 = float(np.mean(per32))
+        log(f"[bench] FP32 assemble avg {avg32 * 1e6:.1f} us")
+        print(json.dumps({"elasticity_64_f32": {"avg_launch_us": avg32 * 1e6}}), flush=True)
+        return
 
     def step():
         pat.assemble(form, coords, precision=mf.F64, elem_param=Et, nodal_src=bt, K=K, d=d)

@@ -192,6 +192,24 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _require(t, name, dtype, numel=None, optional=True):
+    """Checks a tensor argument before its address reaches the library: on the GPU,
+    contiguous, of the dtype and (when given) of the element count.  A host tensor or a
+    short array would otherwise reach the kernels as a bad pointer."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name} is required")
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
 def form_fields(kind: int, dim: int) -> int:
     return {MASS: 1, POISSON: 1, ELASTICITY: dim, NS_SUPG: dim + 1}[kind]
 
@@ -282,16 +300,18 @@ class Pattern:
         lib = load()
         dt = torch.float64 if precision == F64 else torch.float32
         dev = coords.device
+        _require(coords, "coords", torch.float64, self.dim * self.n_nodes, optional=False)
         if K is None:
             K = torch.empty(self.nnz, dtype=dt, device=dev)
         if d is None:
             d = torch.empty(self.n_rows, dtype=dt, device=dev)
-        for name, t in (("elem_param", elem_param), ("nodal_src", nodal_src), ("lin_state", lin_state)):
-            if t is not None:
-                assert t.is_cuda and t.dtype == dt and t.is_contiguous(), f"{name} must be contiguous {dt} on cuda"
-        assert coords.dtype == torch.float64 and coords.is_contiguous()
-        if dirichlet is not None:
-            assert dirichlet.dtype == torch.uint8 and dirichlet.is_cuda
+        _require(K, "K", dt, self.nnz)
+        _require(d, "d", dt, self.n_rows)
+        _require(elem_param, "elem_param", dt, self.n_elems)
+        nsrc = {MASS: 1, POISSON: 1, ELASTICITY: self.dim}.get(form.kind, 0)
+        _require(nodal_src, "nodal_src", dt, nsrc * self.n_nodes if nsrc else None)
+        _require(lin_state, "lin_state", dt, (self.dim + 1) * self.n_nodes)
+        _require(dirichlet, "dirichlet", torch.uint8, self.n_rows)
         f = _Fields(_ptr(elem_param), _ptr(nodal_src), _ptr(lin_state), _ptr(dirichlet))
         q = _Quad(points_per_axis or {HEX20: 3, QUAD8: 3, TET10: 4}.get(self.elem, 2))
         check(lib.mf_assemble_ex(self._h, C.byref(form.c), _ptr(coords), C.byref(f), C.byref(q), precision,
@@ -308,14 +328,17 @@ class Pattern:
         lib = load()
         dt = torch.float64 if precision == F64 else torch.float32
         dev = coords.device
+        _require(coords, "coords", torch.float64, self.dim * self.n_nodes, optional=False)
         if K is None:
             K = torch.zeros(self.nnz, dtype=dt, device=dev)
         if d is None:
             d = torch.zeros(self.n_rows, dtype=dt, device=dev)
-        for name, t in (("state", state), ("target", target)):
-            if t is not None:
-                assert t.is_cuda and t.dtype == dt and t.is_contiguous(), f"{name} must be contiguous {dt} on cuda"
-        assert face_elem.dtype == torch.int32 and face_id.dtype == torch.uint8
+        _require(K, "K", dt, self.nnz)
+        _require(d, "d", dt, self.n_rows)
+        _require(state, "state", dt, self.n_fields * self.n_nodes)
+        _require(target, "target", dt, self.n_fields * self.n_nodes)
+        _require(face_elem, "face_elem", torch.int32, optional=False)
+        _require(face_id, "face_id", torch.uint8, int(face_elem.shape[0]), optional=False)
         vals = list(value) + [0.0] * (9 - len(value))
         f = _BForm(kind, coef, (C.c_double * 9)(*vals))
         check(lib.mf_assemble_boundary(self._h, C.byref(f), _ptr(coords), int(face_elem.shape[0]), _ptr(face_elem),
@@ -439,8 +462,7 @@ class Net:
         check(load().mf_nn_params(self._h, None, v.ctypes.data_as(C.c_void_p), None))
 
     def set_system(self, row_ptr, col_idx, values, dirichlet=None, stream=None):
-        A = _CSR(int(values.shape[0]) if False else int(self._np.prod(self.grid)), _ptr_any(row_ptr),
-                 _ptr_any(col_idx), _ptr(values))
+        A = _CSR(int(self._np.prod(self.grid)), _ptr_any(row_ptr), _ptr_any(col_idx), _ptr(values))
         check(load().mf_nn_set_system(self._h, C.byref(A), _ptr(dirichlet), _stream(stream)))
         self._bound = (row_ptr, col_idx, values, dirichlet)
 
@@ -496,6 +518,7 @@ def pcg(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PREC
     return x, out
 
 
+
 def bicgstab(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PRECOND_JACOBI,
              check_every=8, use_graph=True, stream=None, raise_on_fail=True):
     """Solve K x = b for a non-symmetric FP64 CSR K on the device by BiCGStab from x0 = 0.
@@ -526,18 +549,17 @@ def ns_newton(pattern, form, coords, state, dirichlet=None, rtol=1e-10, atol=0.0
     elimination.  Returns the result dict (steps, converged, lin_iterations, res_norm)."""
     import torch
     lib = load()
-    assert state.dtype == torch.float64 and state.is_cuda and state.is_contiguous()
-    assert coords.dtype == torch.float64 and coords.is_contiguous()
-    if dirichlet is not None:
-        assert dirichlet.dtype == torch.uint8 and dirichlet.is_cuda
+    _require(state, "state", torch.float64, 4 * pattern.n_nodes, optional=False)
+    _require(coords, "coords", torch.float64, pattern.dim * pattern.n_nodes, optional=False)
+    _require(dirichlet, "dirichlet", torch.uint8, pattern.n_rows)
     opts = _NewtonOpts(rtol, atol, max_steps, lin_tol, lin_maxit, check_every, int(bool(use_graph)))
     res = _NewtonResult()
     q = _Quad(points_per_axis)
     sets = (_BSet * max(1, len(boundary)))()
     for k, (kind, fe, fi, coef, value, target) in enumerate(boundary):
-        assert fe.dtype == torch.int32 and fi.dtype == torch.uint8 and fe.is_cuda and fi.is_cuda
-        if target is not None:
-            assert target.dtype == torch.float64 and target.is_cuda and target.is_contiguous()
+        _require(fe, "face_elem", torch.int32, optional=False)
+        _require(fi, "face_id", torch.uint8, int(fe.shape[0]), optional=False)
+        _require(target, "target", torch.float64, 4 * pattern.n_nodes)
         vals = list(value) + [0.0] * (9 - len(value))
         sets[k] = _BSet(_BForm(kind, coef, (C.c_double * 9)(*vals)), int(fe.shape[0]), _ptr(fe), _ptr(fi),
                         _ptr(target))
@@ -557,9 +579,12 @@ def heat_transient(pattern, coords, T, Tdot, dt, n_steps, capacity=1.0, conducti
     [n_nodes]) are updated in place.  Returns the result dict."""
     import torch
     lib = load()
-    for name, t in (("T", T), ("Tdot", Tdot), ("elem_k", elem_k), ("source", source)):
-        if t is not None:
-            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), f"{name}: contiguous float64 cuda"
+    _require(coords, "coords", torch.float64, pattern.dim * pattern.n_nodes, optional=False)
+    _require(T, "T", torch.float64, pattern.n_nodes, optional=False)
+    _require(Tdot, "Tdot", torch.float64, pattern.n_nodes, optional=False)
+    _require(elem_k, "elem_k", torch.float64, pattern.n_elems)
+    _require(source, "source", torch.float64, pattern.n_nodes)
+    _require(dirichlet, "dirichlet", torch.uint8, pattern.n_rows)
     opts = _TransientOpts(dt, rho_inf, n_steps, int(bool(init_rate)), lin_tol, lin_maxit)
     res = _TransientResult()
     q = _Quad(points_per_axis)

@@ -25,6 +25,8 @@ mf_status set_error(mf_status s, const char* fmt, ...)
     return s;
 }
 
+void clear_error() { g_err[0] = 0; }
+
 mf_status hip_error(hipError_t e, const char* what)
 {
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
@@ -47,6 +49,8 @@ static void free_pattern(mf_pattern_s* P)
     (void)hipFree(P->rank);
     (void)hipFree(P->status);
     (void)hipFree(P->color_elems);
+    (void)hipFree(P->elem_color);
+    (void)hipFree(P->face_work);
     delete P;
 }
 
@@ -233,14 +237,16 @@ mf_status mf_assemble(const mf_pattern_t* P, const mf_form* form, const double* 
 mf_status mf_status_poll(const mf_pattern_t* P, int64_t* first_bad_elem)
 {
     if (!P) return set_error(MF_ERR_ARG, "pattern is NULL");
-    unsigned long long v[2] = {0, 0};
+    unsigned long long v[3] = {0, 0, 0};
     if (P->last_stream) MF_HIP(hipStreamSynchronize(P->last_stream));
     MF_HIP(hipMemcpy(v, P->status, sizeof(v), hipMemcpyDeviceToHost));
-    if (first_bad_elem) *first_bad_elem = v[0] == ~0ull ? -1 : (int64_t)v[0];
+    if (first_bad_elem) *first_bad_elem = v[0] != ~0ull ? (int64_t)v[0] : v[2] != ~0ull ? (int64_t)v[2] : -1;
     if (v[1] != ~0ull)
         return set_error(MF_ERR_ARG, "boundary face %lld: element id or local face out of range (skipped)",
                          (long long)v[1]);
     if (v[0] != ~0ull) return set_error(MF_ERR_BAD_JACOBIAN, "det J <= 0 in element %lld", (long long)v[0]);
+    if (v[2] != ~0ull)
+        return set_error(MF_ERR_NONFINITE, "non-finite input or coefficient in element %lld", (long long)v[2]);
     return MF_OK;
 }
 

@@ -95,6 +95,13 @@ __global__ void __launch_bounds__(kThreads) k_assemble_atomic(AtomicParams p)
         row_update<FORM, DIM, T>(a, i, C, N, g, (T)det, U, krow, rrow);
     }
 
+    {
+        // a non-finite input (element parameter, source or state) shows in the row sums
+        T chk = rrow;
+#pragma unroll
+        for (int k = 0; k < NEN * NF; ++k) chk += krow[k];
+        if (!isfinite(chk)) atomicMin(p.status + 2, (unsigned long long)e);
+    }
     const int64_t va = node[a];
     const int64_t row = p.field_major ? (int64_t)i * p.n_nodes + va : (int64_t)NF * va + i;
     const int64_t rs = p.row_ptr[row];
@@ -140,6 +147,7 @@ __global__ void k_reset_status(unsigned long long* s)
 {
     s[0] = ~0ull;
     s[1] = ~0ull;
+    s[2] = ~0ull;
 }
 
 template <int FORM, int DIM, typename T>

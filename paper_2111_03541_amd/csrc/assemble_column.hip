@@ -348,6 +348,11 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
         hq[R_S] = (T)sw;
         hq[R_P] = (T)pr;
         hq[R_DIV] = (T)(gu[0][0] + gu[1][1] + gu[2][2]);
+        // a non-finite state value shows in the sum of the interpolated state and gradients
+        double chk = pr + gp[0] + gp[1] + gp[2];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) chk += u[m] + gu[m][0] + gu[m][1] + gu[m][2];
+        if (!isfinite(chk)) atomicMin(p.status + 2, (unsigned long long)(ex + p.nx * (ey + p.ny * L)));
         return;
     } else if constexpr (FORM == MF_FORM_MASS) {
         hq[0] = (T)det;
@@ -385,8 +390,15 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
 #pragma unroll
             for (int i = 0; i < NF; ++i) f[i] = fma(Na, (double)S.u[r][tn][i], f[i]);
         }
+        double chk = coefA + coefB;
 #pragma unroll
-        for (int i = 0; i < NF; ++i) S.wf[slot][el][q][i] = (T)(wscale * f[i]);
+        for (int i = 0; i < NF; ++i) {
+            S.wf[slot][el][q][i] = (T)(wscale * f[i]);
+            chk += f[i];
+        }
+        // a non-finite element parameter or source value (the coordinates are checked by
+        // det J > 0 above)
+        if (!isfinite(chk)) atomicMin(p.status + 2, (unsigned long long)(ex + p.nx * (ey + p.ny * L)));
         if (q == 0) {
             S.cf[slot][el][0] = (T)coefA;
             S.cf[slot][el][1] = (T)coefB;
@@ -782,6 +794,7 @@ __global__ void k_batch_reset(int* counter, unsigned long long* const* status, i
     if (i < n_status) {
         status[i][0] = ~0ull;
         status[i][1] = ~0ull;
+        status[i][2] = ~0ull;
     }
 }
 

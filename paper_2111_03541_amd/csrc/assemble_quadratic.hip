@@ -284,6 +284,8 @@ __global__ void __launch_bounds__(Elem<ET>::THREADS) k_assemble_quadratic(Q2Para
     const double cd = FORM == MF_FORM_MASS ? coef : 1.0;
     for (int q = 0; q < NQ; ++q) dv = fma(S.W[q] * cd * S.N[q][a], S.f[q][i], dv);
     ((T*)p.d)[row] += (T)dv;
+    // a non-finite element parameter or source value shows in the coefficients or dv
+    if (!isfinite(dv + coef + lam + mu)) atomicMin(p.status + 2, (unsigned long long)e);
 }
 
 constexpr int kFillThreads = 256;

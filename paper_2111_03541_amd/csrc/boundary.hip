@@ -15,8 +15,15 @@
 // element-to-nonzero rank map.  Boundary work is a surface's worth, so the simple
 // per-row scatter is enough.  A face whose element id or local face is out of range is
 // skipped and its index recorded in the pattern's second status word.
+//
+// Faces go in buckets keyed by (colour of the face's element, local face), one launch per
+// bucket in key order.  Elements of one colour share no node, so within a bucket every
+// value of K and d receives contributions of one face only (or of identical copies of it,
+// when a face is listed twice): the sums do not depend on the order of the atomics, and
+// two calls with the same inputs give the same bits.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "element.h"
@@ -44,7 +51,12 @@ struct BParams {
     void* K;
     void* d;
     unsigned long long* status;
+    // faces of this launch: order[f_begin + k] for k < n_faces (one colour bucket)
+    const int32_t* order;
+    int64_t f_begin;
 };
+
+__device__ __forceinline__ int64_t face_of(const BParams& p, int64_t k) { return p.order[p.f_begin + k]; }
 
 __device__ __forceinline__ double lin1(int s, double xi) { return 0.5 * (1.0 + (s ? xi : -xi)); }
 
@@ -284,7 +296,7 @@ __global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= p.n_faces * kRowNodes<NF> * NF) return;
-    const int64_t f = t % p.n_faces;
+    const int64_t f = face_of(p, t % p.n_faces);
     const int ki = (int)(t / p.n_faces);
     const int kf = ki / NF, i = ki % NF;
     if constexpr (NF == 4) {
@@ -308,7 +320,7 @@ __global__ void __launch_bounds__(kThreads) k_boundary20(BParams p)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= p.n_faces * 8 * NF) return;
-    const int64_t f = t % p.n_faces;
+    const int64_t f = face_of(p, t % p.n_faces);
     const int ki = (int)(t / p.n_faces);
     const int kf = ki / NF, i = ki % NF;
     const int64_t e = p.face_elem[f];
@@ -416,7 +428,7 @@ __global__ void __launch_bounds__(kThreads) k_boundary_tet10(BParams p)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= p.n_faces * 6 * NF) return;
-    const int64_t f = t % p.n_faces;
+    const int64_t f = face_of(p, t % p.n_faces);
     const int ki = (int)(t / p.n_faces);
     const int mf = ki / NF, i = ki % NF;
     const int64_t e = p.face_elem[f];
@@ -549,7 +561,7 @@ __global__ void __launch_bounds__(kThreads) k_boundary_2d(BParams p)
     constexpr int NE = NEN == 8 ? 3 : 2;  // nodes per edge, and Gauss points
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= p.n_faces * NE * NF) return;
-    const int64_t f = t % p.n_faces;
+    const int64_t f = face_of(p, t % p.n_faces);
     const int ki = (int)(t / p.n_faces);
     const int me = ki / NF, i = ki % NF;
     const int64_t e = p.face_elem[f];
@@ -708,6 +720,85 @@ mf_status launch_boundary(const BParams& p, hipStream_t s)
     return MF_OK;
 }
 
+__global__ void k_face_clear(int32_t* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// bucket of a face: colour of its element x local faces + local face; the last bucket
+// holds the faces whose element or local face is out of range (the kernels report them)
+__device__ __forceinline__ int face_key(const int32_t* fe, const uint8_t* fid, int64_t f, const int32_t* ecol,
+                                        int64_t n_el, int n_local, int n_keys)
+{
+    const int64_t e = fe[f];
+    const int lf = fid[f];
+    return (e >= 0 && e < n_el && lf < n_local) ? ecol[e] * n_local + lf : n_keys - 1;
+}
+
+__global__ void k_face_hist(const int32_t* fe, const uint8_t* fid, int64_t n, const int32_t* ecol, int64_t n_el,
+                            int n_local, int n_keys, int32_t* cnt)
+{
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < n) atomicAdd(cnt + face_key(fe, fid, f, ecol, n_el, n_local, n_keys), 1);
+}
+
+// cursor := exclusive scan of cnt (a few hundred buckets at most: one lane)
+__global__ void k_face_scan(const int32_t* cnt, int n_keys, int32_t* cursor)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int32_t acc = 0;
+    for (int k = 0; k < n_keys; ++k) {
+        cursor[k] = acc;
+        acc += cnt[k];
+    }
+}
+
+__global__ void k_face_place(const int32_t* fe, const uint8_t* fid, int64_t n, const int32_t* ecol, int64_t n_el,
+                             int n_local, int n_keys, int32_t* cursor, int32_t* order)
+{
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < n) order[atomicAdd(cursor + face_key(fe, fid, f, ecol, n_el, n_local, n_keys), 1)] = (int32_t)f;
+}
+
+// Sorts the faces into colour buckets: order (device, in the pattern's workspace) lists
+// the faces bucket by bucket, bucket k being order[off[k] .. off[k+1]).  Synchronises the
+// stream once to read the bucket sizes.
+mf_status bucket_faces(const mf_pattern_s* Pc, int n_local, const int32_t* fe, const uint8_t* fid, int64_t n,
+                       hipStream_t s, std::vector<int64_t>& off, const int32_t*& order)
+{
+    mf_pattern_s* P = const_cast<mf_pattern_s*>(Pc);
+    mf_status st = ensure_coloring(P, s);
+    if (st != MF_OK) return st;
+    const int n_colors = std::max(0, (int)P->color_ptr.size() - 1);
+    const int n_keys = n_colors * n_local + 1;
+    const int64_t need = 2 * (int64_t)n_keys + n;
+    if (P->face_work_cap < need) {
+        MF_HIP(hipStreamSynchronize(s));
+        (void)hipFree(P->face_work);
+        P->face_work = nullptr;
+        P->face_work_cap = 0;
+        MF_HIP(hipMalloc(&P->face_work, sizeof(int32_t) * (size_t)need));
+        P->face_work_cap = need;
+    }
+    int32_t* cnt = P->face_work;
+    int32_t* cursor = cnt + n_keys;
+    int32_t* ord = cursor + n_keys;
+    const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
+    k_face_clear<<<(n_keys + kThreads - 1) / kThreads, kThreads, 0, s>>>(cnt, n_keys);
+    k_face_hist<<<blocks, kThreads, 0, s>>>(fe, fid, n, P->elem_color, P->n_elems, n_local, n_keys, cnt);
+    k_face_scan<<<1, 64, 0, s>>>(cnt, n_keys, cursor);
+    k_face_place<<<blocks, kThreads, 0, s>>>(fe, fid, n, P->elem_color, P->n_elems, n_local, n_keys, cursor, ord);
+    MF_HIP(hipGetLastError());
+    std::vector<int32_t> h((size_t)n_keys);
+    MF_HIP(hipMemcpyAsync(h.data(), cnt, sizeof(int32_t) * (size_t)n_keys, hipMemcpyDeviceToHost, s));
+    MF_HIP(hipStreamSynchronize(s));
+    off.assign((size_t)n_keys + 1, 0);
+    for (int k = 0; k < n_keys; ++k) off[(size_t)k + 1] = off[(size_t)k] + h[(size_t)k];
+    order = ord;
+    return MF_OK;
+}
+
 }  // namespace
 }  // namespace mf
 
@@ -718,6 +809,7 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
                                           const void* state, const void* target, mf_precision prec, void* K,
                                           void* d, void* stream)
 {
+    clear_error();
     if (!P || !form) return set_error(MF_ERR_ARG, "pattern or form is NULL");
     const bool two_d = P->dim == 2;
     if (two_d ? (P->nen != 4 && P->nen != 8) : (P->nen != 8 && P->nen != 20 && P->nen != 10))
@@ -773,27 +865,44 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
     p.d = d;
     p.status = P->status;
     const_cast<mf_pattern_s*>(P)->last_stream = s;
+    using Launch = mf_status (*)(const BParams&, hipStream_t);
+    Launch launch = nullptr;
+    const bool f64 = prec == MF_F64;
+    int n_local = 6;  // local faces (edges in 2D) per element
     if (two_d) {
         if (nf != 1 && nf != 2) return set_error(MF_ERR_ARG, "edge forms need 1 or 2 fields, pattern has %d", nf);
-        if (P->nen == 8) {
-            if (prec == MF_F64) return nf == 1 ? launch_boundary_2d<8, 1, double>(p, s) : launch_boundary_2d<8, 2, double>(p, s);
-            return nf == 1 ? launch_boundary_2d<8, 1, float>(p, s) : launch_boundary_2d<8, 2, float>(p, s);
-        }
-        if (prec == MF_F64) return nf == 1 ? launch_boundary_2d<4, 1, double>(p, s) : launch_boundary_2d<4, 2, double>(p, s);
-        return nf == 1 ? launch_boundary_2d<4, 1, float>(p, s) : launch_boundary_2d<4, 2, float>(p, s);
+        n_local = 4;
+        if (P->nen == 8)
+            launch = f64 ? (nf == 1 ? launch_boundary_2d<8, 1, double> : launch_boundary_2d<8, 2, double>)
+                         : (nf == 1 ? launch_boundary_2d<8, 1, float> : launch_boundary_2d<8, 2, float>);
+        else
+            launch = f64 ? (nf == 1 ? launch_boundary_2d<4, 1, double> : launch_boundary_2d<4, 2, double>)
+                         : (nf == 1 ? launch_boundary_2d<4, 1, float> : launch_boundary_2d<4, 2, float>);
+    } else if (tet) {
+        n_local = 4;
+        launch = f64 ? (nf == 1 ? launch_boundary_tet10<1, double> : launch_boundary_tet10<3, double>)
+                     : (nf == 1 ? launch_boundary_tet10<1, float> : launch_boundary_tet10<3, float>);
+    } else if (quad) {
+        launch = f64 ? (nf == 1 ? launch_boundary20<1, double> : launch_boundary20<3, double>)
+                     : (nf == 1 ? launch_boundary20<1, float> : launch_boundary20<3, float>);
+    } else if (nf == 4) {
+        launch = f64 ? launch_boundary<4, double> : launch_boundary<4, float>;
+    } else {
+        launch = f64 ? (nf == 1 ? launch_boundary<1, double> : launch_boundary<3, double>)
+                     : (nf == 1 ? launch_boundary<1, float> : launch_boundary<3, float>);
     }
-    if (tet) {
-        if (prec == MF_F64) return nf == 1 ? launch_boundary_tet10<1, double>(p, s) : launch_boundary_tet10<3, double>(p, s);
-        return nf == 1 ? launch_boundary_tet10<1, float>(p, s) : launch_boundary_tet10<3, float>(p, s);
+    if (n_faces == 0) return MF_OK;
+    std::vector<int64_t> off;
+    const int32_t* order = nullptr;
+    mf_status st = bucket_faces(P, n_local, face_elem, face_id, n_faces, s, off, order);
+    if (st != MF_OK) return st;
+    p.order = order;
+    for (size_t k = 0; k + 1 < off.size(); ++k) {
+        if (off[k + 1] == off[k]) continue;
+        p.f_begin = off[k];
+        p.n_faces = off[k + 1] - off[k];
+        st = launch(p, s);
+        if (st != MF_OK) return st;
     }
-    if (quad) {
-        if (prec == MF_F64) return nf == 1 ? launch_boundary20<1, double>(p, s) : launch_boundary20<3, double>(p, s);
-        return nf == 1 ? launch_boundary20<1, float>(p, s) : launch_boundary20<3, float>(p, s);
-    }
-    if (prec == MF_F64) {
-        if (nf == 4) return launch_boundary<4, double>(p, s);
-        return nf == 1 ? launch_boundary<1, double>(p, s) : launch_boundary<3, double>(p, s);
-    }
-    if (nf == 4) return launch_boundary<4, float>(p, s);
-    return nf == 1 ? launch_boundary<1, float>(p, s) : launch_boundary<3, float>(p, s);
+    return MF_OK;
 }

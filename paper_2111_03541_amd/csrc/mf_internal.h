@@ -24,11 +24,16 @@ struct mf_pattern_s {
     int32_t* row_ptr = nullptr;  // [n_rows+1]
     int32_t* col_idx = nullptr;  // [nnz]
     uint8_t* rank = nullptr;     // [nen*nen][n_elems]
-    unsigned long long* status = nullptr;  // [2] first element with det J <= 0, first bad face (or ~0)
+    unsigned long long* status = nullptr;  // [3] first element with det J <= 0, first bad face, first element
+                                           // with a non-finite input or coefficient (each ~0 when none)
     // element colouring (no two elements of one colour share a node), made on first use:
     // the elements of colour c are color_elems[color_ptr[c] .. color_ptr[c+1])
     int32_t* color_elems = nullptr;  // device [n_elems]
+    int32_t* elem_color = nullptr;   // device [n_elems]: colour of each element
     std::vector<int64_t> color_ptr;
+    // boundary-face buckets (boundary.hip): device workspace, grown on demand
+    int32_t* face_work = nullptr;
+    int64_t face_work_cap = 0;
     // structured lexicographic grid detection
     int is_grid = 0;
     int64_t gx = 0, gy = 0, gz = 0;
@@ -39,6 +44,7 @@ namespace mf {
 
 mf_status set_error(mf_status s, const char* fmt, ...);
 mf_status hip_error(hipError_t e, const char* what);
+void clear_error();  // empties the thread's last-error message
 
 #define MF_HIP(call)                                            \
     do {                                                        \

@@ -372,7 +372,7 @@ mf_status build_pattern(mf_pattern_s* P, const int32_t* conn_in, hipStream_t s)
     MF_HIP(hipMalloc(&P->row_ptr, sizeof(int32_t) * (size_t)(P->n_rows + 1)));
     MF_HIP(hipMalloc(&P->col_idx, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1)));
     MF_HIP(hipMalloc(&P->rank, (size_t)(nen * nen * (n_el > 0 ? n_el : 1))));
-    MF_HIP(hipMalloc(&P->status, 2 * sizeof(unsigned long long)));  // [0] bad element, [1] bad face
+    MF_HIP(hipMalloc(&P->status, 3 * sizeof(unsigned long long)));  // bad element, bad face, non-finite element
 
     k_i64_to_i32<<<blocks_for(n_nodes + 1, kThreads), kThreads, 0, s>>>(nbr_ptr64, n_nodes + 1, P->nbr_ptr);
     if (n_nodes > 0)
@@ -476,15 +476,22 @@ mf_status ensure_coloring(const mf_pattern_s* Pc, hipStream_t s)
     std::vector<int64_t> at(P->color_ptr.begin(), P->color_ptr.end() - 1);
     for (int64_t e = 0; e < n_el; ++e) order[(size_t)at[(size_t)color[(size_t)e]]++] = (int32_t)e;
     int32_t* dev = nullptr;
+    int32_t* ecol = nullptr;
     MF_HIP(hipMalloc(&dev, sizeof(int32_t) * (size_t)n_el));
-    hipError_t err = hipMemcpyAsync(dev, order.data(), sizeof(int32_t) * (size_t)n_el, hipMemcpyHostToDevice, s);
+    hipError_t err = hipMalloc(&ecol, sizeof(int32_t) * (size_t)n_el);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(dev, order.data(), sizeof(int32_t) * (size_t)n_el, hipMemcpyHostToDevice, s);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(ecol, color.data(), sizeof(int32_t) * (size_t)n_el, hipMemcpyHostToDevice, s);
     if (err == hipSuccess) err = hipStreamSynchronize(s);
     if (err != hipSuccess) {
         (void)hipFree(dev);
+        (void)hipFree(ecol);
         P->color_ptr.clear();
         return hip_error(err, "colour upload");
     }
     P->color_elems = dev;
+    P->elem_color = ecol;
     return MF_OK;
 }
 

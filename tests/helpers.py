@@ -9,17 +9,30 @@ TOL = {0: 1e-12, 1: 1e-5}  # FP64, FP32 (row-scaled, see rowscaled_error)
 
 def rowscaled_error(pat, K, Kref):
     """max_ij |K_ij - Kref_ij| / max_j |Kref_ij| (entrywise relative error fails on
-    entries that cancel to ~0, so each row is scaled by its largest reference entry)."""
-    rp = pat.row_ptr if hasattr(pat, "row_ptr") else pat
+    entries that cancel to ~0, so each row is scaled by its largest reference entry).
+    A row whose reference is all zero must match exactly (its error is then 0 or inf)."""
+    rp = np.asarray(pat.row_ptr if hasattr(pat, "row_ptr") else pat, np.int64)
+    n = len(rp) - 1
+    if n <= 0 or rp[-1] == 0:
+        return 0.0
     diff = np.abs(np.asarray(K, np.float64) - Kref)
-    ref = np.abs(Kref)
-    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
-    rowmax = np.zeros(len(rp) - 1)
-    np.maximum.at(rowmax, rows, ref)
-    rowdiff = np.zeros(len(rp) - 1)
-    np.maximum.at(rowdiff, rows, diff)
-    scale = np.where(rowmax > 0, rowmax, 1.0)
-    return float(np.max(rowdiff / scale)) if len(rp) > 1 else 0.0
+    ref = np.abs(np.asarray(Kref, np.float64))
+    nonempty = rp[1:] > rp[:-1]
+    starts = rp[:-1][nonempty]
+    rowdiff = np.maximum.reduceat(diff, starts)
+    rowmax = np.maximum.reduceat(ref, starts)
+    err = np.where(rowmax > 0, rowdiff / np.where(rowmax > 0, rowmax, 1.0), np.where(rowdiff > 0, np.inf, 0.0))
+    return float(np.max(err))
+
+
+def rowscaled_sparse(A, B):
+    """The row-scaled error of rowscaled_error for two scipy sparse matrices of one shape."""
+    D = abs((A - B).tocsr())
+    R = abs(B.tocsr())
+    dmax = np.asarray(D.max(axis=1).todense()).ravel()
+    rmax = np.asarray(R.max(axis=1).todense()).ravel()
+    err = np.where(rmax > 0, dmax / np.where(rmax > 0, rmax, 1.0), np.where(dmax > 0, np.inf, 0.0))
+    return float(err.max()) if err.size else 0.0
 
 
 def vec_error(d, dref):

@@ -46,3 +46,52 @@ def test_argument_errors_are_reported_synchronously():
     dofs5 = mf._Dofs(5, None, mf.NODE_MAJOR)
     assert lib.mf_pattern(C.byref(mesh), mf.HEX8, 1, C.byref(dofs5), None, C.byref(h)) == mf.ERR_ARG
     assert lib.mf_assemble(None, None, None, None, None, 0, None, None, None) == mf.ERR_ARG
+
+
+def _fake_pattern(n_nodes=8, n_elems=1, dim=3, nf=3, nnz=576):
+    """A binding Pattern object without a device handle: the argument checks run before
+    any library call, so host tensors and short arrays can be rejected on the CPU."""
+    p = mf.Pattern.__new__(mf.Pattern)
+    p.dim, p.n_fields, p.numbering = dim, nf, mf.NODE_MAJOR
+    p.n_nodes, p.n_elems, p.n_rows, p.nnz = n_nodes, n_elems, n_nodes * nf, nnz
+    p.elem, p._h = mf.HEX8, None
+    return p
+
+
+def test_binding_rejects_host_and_short_arrays():
+    import pytest
+    import torch
+    p = _fake_pattern()
+    coords = torch.zeros(3 * 8, dtype=torch.float64)  # a host tensor
+    with pytest.raises(ValueError, match="CUDA"):
+        p.assemble(mf.Form(mf.ELASTICITY, coef=1.0, nu=0.3), coords)
+    with pytest.raises(ValueError, match="CUDA"):
+        p.assemble_boundary(mf.BFORM_PENALTY, coords, torch.zeros(2, dtype=torch.int32),
+                            torch.zeros(1, dtype=torch.uint8))
+    with pytest.raises(ValueError, match="CUDA"):
+        mf.ns_newton(p, mf.Form(mf.NS_SUPG), coords, torch.zeros(4 * 8, dtype=torch.float64))
+    with pytest.raises(ValueError, match="required"):
+        mf._require(None, "coords", torch.float64, 24, optional=False)
+
+
+def test_binding_require_checks_dtype_layout_and_size():
+    import pytest
+    import torch
+
+    class FakeCuda:  # stands for a device tensor: only the attributes the check reads
+        def __init__(self, t):
+            self.t, self.is_cuda, self.dtype = t, True, t.dtype
+
+        def is_contiguous(self):
+            return self.t.is_contiguous()
+
+        def numel(self):
+            return self.t.numel()
+
+    mf._require(FakeCuda(torch.zeros(6, dtype=torch.int32)), "face_elem", torch.int32, 6)
+    with pytest.raises(ValueError, match="elements"):
+        mf._require(FakeCuda(torch.zeros(5, dtype=torch.uint8)), "face_id", torch.uint8, 6)
+    with pytest.raises(ValueError, match="float64"):
+        mf._require(FakeCuda(torch.zeros(6, dtype=torch.float32)), "coords", torch.float64, 6)
+    with pytest.raises(ValueError, match="contiguous"):
+        mf._require(FakeCuda(torch.zeros(4, 6, dtype=torch.float64).t()), "state", torch.float64, 24)

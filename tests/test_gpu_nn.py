@@ -46,6 +46,33 @@ def bind(mf, net, pat, K, mask):
 
 CH = [1, 4, 8, 8]
 
+# Element-wise bars for the BF16 kernels against the FP64 oracle run on the same
+# BF16-rounded weights.  Activations are stored in BF16 (unit roundoff 2^-9 = 1.95e-3)
+# and accumulated in FP32; an output passes through at most six roundings on its way
+# from the input (input scaling, three convolutions, the level sum and the final
+# scaling), so no entry may be off by more than 6 x 2^-9 of the largest output.
+FWD_TOL = 6 * 2.0 ** -9
+# Gradients: every parameter block (one level's convolution) is compared on its own,
+# scaled by its largest reference entry.  Each weight gradient is a sum over grid
+# points of products of two BF16-rounded activation fields, each a forward or backward
+# chain of at most six roundings: 12 x 2^-9 per block.
+GRAD_TOL = 12 * 2.0 ** -9
+
+
+def elementwise_error(z, ref):
+    return float(np.max(np.abs(z - ref)) / np.max(np.abs(ref)))
+
+
+def blockwise_errors(g, gr, channels):
+    """max |g - g_ref| / max |g_ref| for each convolution's weight block."""
+    errs, o = [], 0
+    for a, b, t in NR.param_layout(channels):
+        n = a * b * t
+        errs.append(elementwise_error(g[o:o + n], gr[o:o + n]))
+        o += n
+    assert o == g.size == gr.size
+    return errs
+
 
 def test_forward_matches_oracle(mf):
     say("nn forward 17^3")
@@ -58,9 +85,10 @@ def test_forward_matches_oracle(mf):
     r = np.where(mask != 0, 0.0, rng.standard_normal(pat.n_rows))
     z = net.apply(torch.from_numpy(r).cuda()).cpu().numpy()
     ref = NR.Net((17, 17, 17), CH).forward(bf16(theta), r, pat.to_scipy(K).diagonal(), mask)
-    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
-    say(f"  forward rel err {err:.2e}")
-    assert err < 2e-2
+    err = elementwise_error(z, ref)
+    say(f"  forward max error / max |z_ref| {err:.2e} (norm {np.linalg.norm(z - ref) / np.linalg.norm(ref):.2e})")
+    assert err <= FWD_TOL
+    assert np.all(z[mask != 0] == 0.0)
     # linear in r: a power-of-two factor commutes with every BF16 rounding, so exactly
     z2 = net.apply(torch.from_numpy(-4.0 * r).cuda()).cpu().numpy()
     assert np.linalg.norm(z2 + 4.0 * z) <= 1e-6 * np.linalg.norm(z)
@@ -80,9 +108,10 @@ def test_forward_large_tiles_matches_oracle(mf):
     r = np.where(mask != 0, 0.0, rng.standard_normal(pat.n_rows))
     z = net.apply(torch.from_numpy(r).cuda()).cpu().numpy()
     ref = NR.Net((73, 73, 73), ch).forward(bf16(theta), r, pat.to_scipy(K).diagonal(), mask)
-    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
-    say(f"  forward rel err {err:.2e}")
-    assert err < 2e-2
+    err = elementwise_error(z, ref)
+    say(f"  forward max error / max |z_ref| {err:.2e} (norm {np.linalg.norm(z - ref) / np.linalg.norm(ref):.2e})")
+    assert err <= FWD_TOL
+    assert np.all(z[mask != 0] == 0.0)
 
 
 def test_gradient_matches_oracle(mf):
@@ -97,11 +126,10 @@ def test_gradient_matches_oracle(mf):
     loss, g = net.grad(torch.from_numpy(r).cuda())
     Lr, gr = NR.Net((17, 17, 17), CH).loss_and_grad(bf16(theta), r, pat.to_scipy(K).diagonal(),
                                                      pat.to_scipy(K), mask)
-    say(f"  loss {loss:.6f} vs {Lr:.6f}; grad rel err {np.linalg.norm(g - gr) / np.linalg.norm(gr):.2e}")
-    assert abs(loss - Lr) <= 2e-2 * Lr
-    assert np.linalg.norm(g - gr) <= 5e-2 * np.linalg.norm(gr)
-    # per level, the gradient blocks point the same way
-    assert float(g @ gr) / (np.linalg.norm(g) * np.linalg.norm(gr)) > 0.998
+    errs = blockwise_errors(g, gr, CH)
+    say(f"  loss {loss:.6f} vs {Lr:.6f}; per-block grad errors " + " ".join(f"{e:.2e}" for e in errs))
+    assert abs(loss - Lr) <= FWD_TOL * Lr
+    assert max(errs) <= GRAD_TOL
     # parameters are untouched by a gradient query
     assert np.array_equal(net.get_params(), theta)
 
@@ -118,9 +146,10 @@ def test_energy_gradient_matches_oracle(mf):
     e = np.where(mask != 0, 0.0, rng.standard_normal(pat.n_rows))
     Lr, r, gr = NR.energy_loss_and_grad(NR.Net((17, 17, 17), CH), bf16(theta), e, S.diagonal(), S, mask)
     loss, g = net.grad(torch.from_numpy(r).cuda(), e=torch.from_numpy(e).cuda())
-    say(f"  loss {loss:.6f} vs {Lr:.6f}; grad rel err {np.linalg.norm(g - gr) / np.linalg.norm(gr):.2e}")
-    assert abs(loss - Lr) <= 2e-2 * Lr
-    assert np.linalg.norm(g - gr) <= 5e-2 * np.linalg.norm(gr)
+    errs = blockwise_errors(g, gr, CH)
+    say(f"  loss {loss:.6f} vs {Lr:.6f}; per-block grad errors " + " ".join(f"{e:.2e}" for e in errs))
+    assert abs(loss - Lr) <= FWD_TOL * Lr
+    assert max(errs) <= GRAD_TOL
 
 
 def test_training_reduces_loss_and_pcg_converges(mf):
@@ -184,3 +213,30 @@ def test_shipped_weights_beat_jacobi_on_held_out_96(mf):
             its[name] = res["iterations"]
         say("iterations", its)
         assert its["learned"] <= 0.5 * its["jacobi"], its
+
+
+@pytest.mark.parametrize("bad", ["nan", "zero"])
+def test_broken_network_falls_back_to_jacobi(mf, bad):
+    """A network whose output is useless (non-finite weights, or all-zero weights so that
+    z.r = 0) must not break the solve: each such application takes the Jacobi direction,
+    the solve counts it as a fallback and still reaches the 1e-8 true residual in
+    Jacobi's iteration count."""
+    say("nn fallback", bad)
+    pat, K, d, mask = system(16, 31)
+    net = mf.Net((17, 17, 17), CH, seed=4)
+    rp, ci, v, m = bind(mf, net, pat, K, mask)
+    theta = np.zeros(net.n_params, np.float32)
+    if bad == "nan":
+        theta[:] = 0.01
+        theta[5] = np.nan
+    net.set_params(theta)
+    b = torch.from_numpy(d).cuda()
+    x, res = mf.pcg(rp, ci, v, b, tol=1e-8, precond=mf.PRECOND_NN, net=net, check_every=1)
+    _, it_j, _ = O.pcg_jacobi(pat.row_ptr, pat.col_idx, K, d, tol=1e-8)
+    say(f"  {res}, jacobi {it_j}")
+    assert res["converged"] and res["true_relres"] <= 1e-8
+    # every application fell back: the initial one and one per iteration
+    assert res["fallbacks"] == res["iterations"] + 1
+    assert abs(res["iterations"] - it_j) <= max(2, 0.02 * it_j)
+    S = pat.to_scipy(K)
+    assert np.linalg.norm(d - S @ x.cpu().numpy()) / np.linalg.norm(d) <= 1e-8

@@ -9,6 +9,7 @@ import pytest
 import oracle as O
 import oracle.serendipity as S
 import workloads as W
+from helpers import rowscaled_sparse
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -159,8 +160,9 @@ def test_boundary_form_matches_oracle(mf, case, numbering, prec):
     Kg = ref.to_scipy(K.double().cpu().numpy())
     dg = d.double().cpu().numpy()
     tol = 1e-12 if prec == 0 else 1e-5
-    kscale = abs(Kr).max() if Kr.nnz else 0.0
-    assert (abs(Kg - Kr).max() <= tol * kscale) if kscale > 0 else abs(Kg).max() == 0.0
+    ek = rowscaled_sparse(Kg, Kr)
+    say(f"  row-scaled K err {ek:.3e}")
+    assert ek <= tol
     assert np.abs(dg - dr).max() <= tol * max(np.abs(dr).max(), 1e-300)
 
 
