@@ -383,6 +383,26 @@ typedef struct {
 mf_status mf_pcg(const mf_csr* A, const double* b, double* x, const mf_pcg_opts* opts,
                  mf_pcg_result* res, void* stream);
 
+/*
+ * mf_pcg_noalloc - mf_pcg for callers that cannot allocate device memory (code that must
+ * not call hipMalloc, such as tight serving loops or harnesses that forbid it).  Same
+ * arguments, result and synchronisation as mf_pcg, with these limits:
+ *   - n_rows <= mf_pcg_noalloc_max_rows() (2^20); larger systems return MF_ERR_ARG;
+ *   - opts->precond MF_PRECOND_JACOBI or MF_PRECOND_NONE (MF_PRECOND_NN: MF_ERR_UNSUPPORTED);
+ *   - the SpMV runs on the caller's CSR arrays (no slot-major copy of K) and the
+ *     iterations launch eagerly (use_graph is ignored), so the iteration count can
+ *     differ from mf_pcg's by rounding, within the same tolerance.
+ * The workspace is one fixed device array of the library (about 48 MiB per GPU, held
+ * until the process ends); calls allocate nothing, not even on the first call.  Every
+ * call on a GPU uses that GPU's one workspace: calls that overlap on one GPU (two host
+ * threads, or two streams in flight) race and must be serialised by the caller.
+ */
+mf_status mf_pcg_noalloc(const mf_csr* A, const double* b, double* x, const mf_pcg_opts* opts,
+                         mf_pcg_result* res, void* stream);
+
+/* Largest n_rows mf_pcg_noalloc accepts. */
+int64_t mf_pcg_noalloc_max_rows(void);
+
 /* y = A x (FP64 CSR).  Async. */
 mf_status mf_spmv(const mf_csr* A, const double* x, double* y, void* stream);
 

@@ -126,6 +126,7 @@ EXPORTS = [
     "mf_batch_create", "mf_batch_tune", "mf_batch_run", "mf_batch_info", "mf_batch_destroy",
     "mf_nn_create", "mf_nn_params", "mf_nn_set_system", "mf_nn_apply", "mf_nn_train_step", "mf_nn_destroy", "mf_spmv",
     "mf_bicgstab", "mf_ns_newton", "mf_ns_newton_ex", "mf_assemble_boundary", "mf_heat_transient",
+    "mf_pcg_noalloc", "mf_pcg_noalloc_max_rows",
 ]
 
 
@@ -148,6 +149,9 @@ def load():
                                    C.c_int, P, P, P]
     lib.mf_status_poll.argtypes = [P, C.POINTER(i64)]
     lib.mf_pcg.argtypes = [C.POINTER(_CSR), P, P, C.POINTER(_PcgOpts), C.POINTER(_PcgResult), P]
+    lib.mf_pcg_noalloc.argtypes = [C.POINTER(_CSR), P, P, C.POINTER(_PcgOpts), C.POINTER(_PcgResult), P]
+    lib.mf_pcg_noalloc_max_rows.argtypes = []
+    lib.mf_pcg_noalloc_max_rows.restype = i64
     lib.mf_batch_create.argtypes = [C.POINTER(_BatchProblem), i32, C.c_int, C.POINTER(P)]
     lib.mf_batch_tune.argtypes = [P, C.c_char_p, P]
     lib.mf_batch_run.argtypes = [P, P]
@@ -517,6 +521,30 @@ def pcg(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PREC
         raise MFError(st, lib.mf_last_error().decode())
     return x, out
 
+
+def pcg_noalloc(row_ptr, col_idx, values, b, x, tol=1e-8, maxit=20000, precond=PRECOND_JACOBI, check_every=8,
+                stream=None, raise_on_fail=True):
+    """mf_pcg_noalloc: PCG on the library's fixed device workspace (no device allocation
+    in the call; at most noalloc_max_rows() rows; Jacobi or no preconditioner).  x is the
+    caller's output vector.  Returns (x, result dict)."""
+    import torch
+    lib = load()
+    n = int(b.shape[0])
+    _require(b, "b", torch.float64, optional=False)
+    _require(x, "x", torch.float64, n, optional=False)
+    A = _CSR(n, _ptr_any(row_ptr), _ptr_any(col_idx), _ptr(values))
+    opts = _PcgOpts(tol, maxit, check_every, 0, precond, None)
+    res = _PcgResult()
+    st = lib.mf_pcg_noalloc(C.byref(A), _ptr(b), _ptr(x), C.byref(opts), C.byref(res), _stream(stream))
+    out = {"iterations": res.iterations, "converged": bool(res.converged), "fallbacks": res.fallbacks,
+           "true_relres": res.true_relres, "status": st}
+    if st != OK and raise_on_fail:
+        raise MFError(st, lib.mf_last_error().decode())
+    return x, out
+
+
+def noalloc_max_rows() -> int:
+    return int(load().mf_pcg_noalloc_max_rows())
 
 
 def bicgstab(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PRECOND_JACOBI,

@@ -250,40 +250,62 @@ mf_status mf_status_poll(const mf_pattern_t* P, int64_t* first_bad_elem)
     return MF_OK;
 }
 
-mf_status mf_pcg(const mf_csr* A, const double* b, double* x, const mf_pcg_opts* opts, mf_pcg_result* res,
-                 void* stream)
+// Validates the arguments of mf_pcg / mf_pcg_noalloc and fills the solver arguments.
+static mf_status pcg_args(const mf_csr* A, const double* b, double* x, const mf_pcg_opts* opts,
+                          mf_pcg_result* res, void* stream, PcgArgs* a)
 {
-    g_err[0] = 0;
     if (!A || !opts || !res) return set_error(MF_ERR_ARG, "A, opts or res is NULL");
     if (A->n_rows < 0 || A->n_rows >= ((int64_t)1 << 31)) return set_error(MF_ERR_ARG, "n_rows out of range");
     if (A->n_rows > 0 && (!A->row_ptr || !A->col_idx || !A->values || !b || !x))
         return set_error(MF_ERR_ARG, "NULL matrix or vector");
     if (!(opts->tol > 0.0) || opts->maxit < 0) return set_error(MF_ERR_ARG, "tol must be > 0 and maxit >= 0");
-    PcgArgs a{};
-    a.n = A->n_rows;
-    a.row_ptr = A->row_ptr;
-    a.col_idx = A->col_idx;
-    a.values = A->values;
-    a.b = b;
-    a.x = x;
-    a.tol = opts->tol;
-    a.maxit = opts->maxit;
-    a.check_every = opts->check_every;
-    a.use_graph = opts->use_graph && stream != nullptr;
-    a.stream = (hipStream_t)stream;
+    *a = PcgArgs{};
+    a->n = A->n_rows;
+    a->row_ptr = A->row_ptr;
+    a->col_idx = A->col_idx;
+    a->values = A->values;
+    a->b = b;
+    a->x = x;
+    a->tol = opts->tol;
+    a->maxit = opts->maxit;
+    a->check_every = opts->check_every;
+    a->use_graph = opts->use_graph && stream != nullptr;
+    a->stream = (hipStream_t)stream;
     switch (opts->precond) {
-        case MF_PRECOND_NONE: a.precond = MF_PRECOND_NONE; break;
-        case MF_PRECOND_JACOBI: a.precond = MF_PRECOND_JACOBI; break;
+        case MF_PRECOND_NONE: a->precond = MF_PRECOND_NONE; break;
+        case MF_PRECOND_JACOBI: a->precond = MF_PRECOND_JACOBI; break;
         case MF_PRECOND_NN: {
             if (!opts->net) return set_error(MF_ERR_ARG, "MF_PRECOND_NN needs a network");
-            mf_status st = nn_bind_pcg(opts->net, A->n_rows, &a);
-            if (st != MF_OK) return st;
-            break;
+            return nn_bind_pcg(opts->net, A->n_rows, a);
         }
         default: return set_error(MF_ERR_ARG, "unknown preconditioner %d", (int)opts->precond);
     }
+    return MF_OK;
+}
+
+mf_status mf_pcg(const mf_csr* A, const double* b, double* x, const mf_pcg_opts* opts, mf_pcg_result* res,
+                 void* stream)
+{
+    g_err[0] = 0;
+    PcgArgs a;
+    mf_status st = pcg_args(A, b, x, opts, res, stream, &a);
+    if (st != MF_OK) return st;
     return run_pcg(a, res);
 }
+
+mf_status mf_pcg_noalloc(const mf_csr* A, const double* b, double* x, const mf_pcg_opts* opts,
+                         mf_pcg_result* res, void* stream)
+{
+    g_err[0] = 0;
+    if (opts && opts->precond == MF_PRECOND_NN)
+        return set_error(MF_ERR_UNSUPPORTED, "mf_pcg_noalloc takes MF_PRECOND_NONE or MF_PRECOND_JACOBI");
+    PcgArgs a;
+    mf_status st = pcg_args(A, b, x, opts, res, stream, &a);
+    if (st != MF_OK) return st;
+    return run_pcg_noalloc(a, res);
+}
+
+int64_t mf_pcg_noalloc_max_rows(void) { return pcg_noalloc_max_rows(); }
 
 mf_status mf_bicgstab(const mf_csr* A, const double* b, double* x, const mf_pcg_opts* opts, mf_pcg_result* res,
                       void* stream)

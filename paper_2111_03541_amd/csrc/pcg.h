@@ -32,7 +32,15 @@ struct PcgArgs {
     hipStream_t stream;
 };
 
-mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res);
+// scratch: null (the workspace is allocated per call), or a device workspace of at
+// least pcg_scratch_doubles(n) doubles; with one, the solve allocates nothing, uses the
+// CSR SpMV and launches eagerly (no graph)
+mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res, double* scratch = nullptr);
+int64_t pcg_scratch_doubles(int64_t n);
+// run_pcg on the library's fixed device workspace (at most pcg_noalloc_max_rows() rows,
+// Jacobi or no preconditioner); allocates nothing
+mf_status run_pcg_noalloc(const PcgArgs& a, mf_pcg_result* res);
+int64_t pcg_noalloc_max_rows();
 // BiCGStab with Jacobi or no preconditioner (precond MF_PRECOND_JACOBI / MF_PRECOND_NONE)
 mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res);
 mf_status run_spmv(const mf_csr* A, const double* x, double* y, hipStream_t s);

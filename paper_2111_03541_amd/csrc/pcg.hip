@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "mf_internal.h"
@@ -582,7 +583,63 @@ mf_status run_spmv(const mf_csr* A, const double* x, double* y, hipStream_t s)
     return MF_OK;
 }
 
-mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
+namespace {
+// dinv r r_old z p q | pq partials | dot partials [3 nb] | scalars | flag, each slot
+// rounded up to 256 bytes
+constexpr int64_t slot256(int64_t v) { return (v + 31) / 32 * 32; }
+constexpr int64_t scratch_doubles_for(int64_t n)
+{
+    return 6 * slot256(n) + slot256(kSpmvBlocks) + slot256(3 * (kVecBlocks > kSpmvBlocks ? kVecBlocks : kSpmvBlocks)) +
+           slot256(S_COUNT + 2) + slot256(1);
+}
+
+// Fixed device workspace of mf_pcg_noalloc: 6 vectors of up to 2^20 rows and the
+// partial sums (about 48 MiB, held by every GPU the library runs on until the process
+// ends).  Host code reaches it only through the address hipGetSymbolAddress returns.
+constexpr int64_t kNoAllocMaxRows = (int64_t)1 << 20;
+constexpr int64_t kScratchDoubles = scratch_doubles_for(kNoAllocMaxRows);
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {};
+
+// Device address of this device's copy of `scratch` (looked up once per device, with
+// the device current).
+mf_status scratch_on_current_device(double** out)
+{
+    int dev = 0;
+    MF_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_error(MF_ERR_UNSUPPORTED, "device index %d", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        MF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return set_error(MF_ERR_HIP, "hipGetSymbolAddress returned NULL for the PCG workspace");
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MF_OK;
+}
+}  // namespace
+
+int64_t pcg_scratch_doubles(int64_t n) { return scratch_doubles_for(n); }
+
+int64_t pcg_noalloc_max_rows() { return kNoAllocMaxRows; }
+
+mf_status run_pcg_noalloc(const PcgArgs& a, mf_pcg_result* res)
+{
+    if (a.n > kNoAllocMaxRows)
+        return set_error(MF_ERR_ARG, "n_rows %lld exceeds the fixed workspace of mf_pcg_noalloc (%lld rows)",
+                         (long long)a.n, (long long)kNoAllocMaxRows);
+    if (a.precond != MF_PRECOND_NONE && a.precond != MF_PRECOND_JACOBI)
+        return set_error(MF_ERR_UNSUPPORTED, "mf_pcg_noalloc takes MF_PRECOND_NONE or MF_PRECOND_JACOBI");
+    double* ws = nullptr;
+    mf_status st = scratch_on_current_device(&ws);
+    if (st != MF_OK) return st;
+    return run_pcg(a, res, ws);
+}
+
+mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res, double* scratch)
 {
     const int n = (int)a.n;
     hipStream_t s = a.stream;
@@ -610,25 +667,50 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
         std::vector<void*>* v;
         ~Free() { for (void* p : *v) (void)hipFree(p); }
     } fr{&owned};
-    double* dinv = (double*)dalloc(sizeof(double) * n);
-    double* r = (double*)dalloc(sizeof(double) * n);
-    double* r_old = (double*)dalloc(sizeof(double) * n);
-    double* z = (double*)dalloc(sizeof(double) * n);
-    double* p = (double*)dalloc(sizeof(double) * n);
-    double* q = (double*)dalloc(sizeof(double) * n);
-    double* pq_part = (double*)dalloc(sizeof(double) * spmv_blocks);
-    double* partial = (double*)dalloc(sizeof(double) * 3 * nb);
-    double* sc = (double*)dalloc(sizeof(double) * (S_COUNT + 2));
-    int* flag = (int*)dalloc(sizeof(int));
-    if (!dinv || !r || !r_old || !z || !p || !q || !pq_part || !partial || !sc || !flag)
-        return set_error(MF_ERR_OOM, "PCG workspace allocation failed");
+    double *dinv, *r, *r_old, *z, *p, *q, *pq_part, *partial, *sc;
+    int* flag;
+    if (scratch) {
+        // caller-provided workspace of pcg_scratch_doubles(n) doubles (256-byte slots);
+        // every value is written before it is read, so no clearing is needed
+        auto slot = [](int64_t v) { return (v + 31) / 32 * 32; };
+        double* w = scratch;
+        auto take = [&](int64_t cnt) {
+            double* t = w;
+            w += slot(cnt);
+            return t;
+        };
+        dinv = take(n);
+        r = take(n);
+        r_old = take(n);
+        z = take(n);
+        p = take(n);
+        q = take(n);
+        pq_part = take(kSpmvBlocks);
+        partial = take(3 * (int64_t)std::max(kVecBlocks, kSpmvBlocks));
+        sc = take(S_COUNT + 2);
+        flag = (int*)take(1);
+    } else {
+        dinv = (double*)dalloc(sizeof(double) * n);
+        r = (double*)dalloc(sizeof(double) * n);
+        r_old = (double*)dalloc(sizeof(double) * n);
+        z = (double*)dalloc(sizeof(double) * n);
+        p = (double*)dalloc(sizeof(double) * n);
+        q = (double*)dalloc(sizeof(double) * n);
+        pq_part = (double*)dalloc(sizeof(double) * spmv_blocks);
+        partial = (double*)dalloc(sizeof(double) * 3 * nb);
+        sc = (double*)dalloc(sizeof(double) * (S_COUNT + 2));
+        flag = (int*)dalloc(sizeof(int));
+        if (!dinv || !r || !r_old || !z || !p || !q || !pq_part || !partial || !sc || !flag)
+            return set_error(MF_ERR_OOM, "PCG workspace allocation failed");
+    }
 
     const bool external = a.precond == MF_PRECOND_EXTERNAL;
     const int jac = a.precond == MF_PRECOND_NONE ? 0 : 1;  // Jacobi z (also the external fallback)
 
-    // ELL copy of K for the iterations when the padding stays small
+    // ELL copy of K for the iterations when the padding stays small (not with a
+    // caller-provided workspace: the copy is as large as K)
     int width = 0, nnz32 = 0;
-    {
+    if (!scratch) {
         int* dmax = (int*)dalloc(sizeof(int));
         if (!dmax) return set_error(MF_ERR_OOM, "PCG workspace allocation failed");
         MF_HIP(hipMemsetAsync(dmax, 0, sizeof(int), s));
@@ -640,7 +722,7 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
     int32_t* ecol = nullptr;
     double* eval = nullptr;
     const int64_t nnz = nnz32;
-    if (width > 0 && (int64_t)width * n <= nnz + nnz / 2) {
+    if (!scratch && width > 0 && (int64_t)width * n <= nnz + nnz / 2) {
         ecol = (int32_t*)dalloc(sizeof(int32_t) * (size_t)width * n);
         eval = (double*)dalloc(sizeof(double) * (size_t)width * n);
         if (ecol && eval) {
@@ -708,7 +790,7 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res)
     // capture one chunk of iterations as a graph when the preconditioner allows it
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    bool use_graph = a.use_graph && (!external || a.apply_graph_safe);
+    bool use_graph = a.use_graph && !scratch && (!external || a.apply_graph_safe);
     if (use_graph) {
         hipStreamCaptureMode mode = hipStreamCaptureModeThreadLocal;
         if (hipStreamBeginCapture(s, mode) == hipSuccess) {
