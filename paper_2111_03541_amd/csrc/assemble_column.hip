@@ -66,13 +66,14 @@ static_assert(kTileNodes <= kPfElemT0 && kPfElemT0 + kLayerElems <= kPfInfoT0 &&
 template <int FORM, typename T>
 struct HLayout {
     static constexpr bool NS = FORM == MF_FORM_NS_SUPG;
-    static constexpr int SQ = NS ? 60 : (sizeof(T) == 8 ? 26 : 28);           // per Gauss point
+    static constexpr int SQ = NS ? 52 : (sizeof(T) == 8 ? 26 : 28);           // per Gauss point
     static constexpr int SE = 8 * SQ + (sizeof(T) == 8 ? 1 : 4);              // per element
     static constexpr int SL = kLayerElems * SE;                               // per element layer
 };
 
-// Offsets inside one flow-form record.
-enum NsRec { R_H = 0, R_N = 24, R_ADV = 32, R_U = 40, R_GU = 43, R_RM = 52, R_S = 55, R_P = 56, R_DIV = 57 };
+// Offsets inside one flow-form record: for each element node a, the four values
+// (sqrt(W) N_a, sqrt(W) grad N_a) at R_PHI + 4 a, then the state at the point.
+enum NsRec { R_PHI = 0, R_U = 32, R_GU = 35, R_RM = 44, R_S = 47, R_P = 48, R_DIV = 49 };
 
 struct ColParams {
     mf_form form;
@@ -133,14 +134,21 @@ struct ColShared {
     static constexpr int NSRC = FormTraits<FORM, 3>::NSRC;
     static constexpr int NB = NF * NF;
     static constexpr bool NS = FORM == MF_FORM_NS_SUPG;
-    T h[2 * HLayout<FORM, T>::SL];
+    // the flow form keeps one element layer of records and two row buffers (node layers kz
+    // and kz + 1, which element layer kz feeds); the symmetric forms two element layers
+    // and one row buffer
+    static constexpr int RING = NS ? 1 : 2;
+    static constexpr int NRB = NS ? 2 : 1;
+    alignas(16) T h[RING * HLayout<FORM, T>::SL];
     T wf[2][kLayerElems][NS ? 1 : 8][NF];
     T cf[2][kLayerElems][2];
     double x[3][kTileNodes][3];
     T u[3][kTileNodes][NSRC];
     double ep[2][kLayerElems];
-    AccT<FORM> rowK[kColNodes][27 * NB];
-    AccT<FORM> rowD[kColNodes][NF];
+    alignas(16) AccT<FORM> rowK[NRB][kColNodes][27 * NB];
+    AccT<FORM> rowD[NRB][kColNodes][NF];
+    // flow form: per wave, the coefficient tiles of two (node, element) pairs, [pair][q][16][4]
+    alignas(16) float dt[NS ? kThreads / 64 : 1][NS ? 2 * 8 * 16 * 4 : 1];
     int ni[kColNodes][4];  // node id, first pair offset, degree, boundary bits
     // Dirichlet flags of the tile's DOFs for node layers L = kz-2 .. kz+1 (slot L & 3): the
     // write-out of layer kz-1 reads its rows' and its neighbours' flags here, so no global
@@ -278,7 +286,8 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
     } else {
         coefA = p.form.coef * ep;
     }
-    T* hq = S.h + slot * HLayout<FORM, T>::SL + el * HLayout<FORM, T>::SE + q * HLayout<FORM, T>::SQ;
+    T* hq = S.h + (ColShared<FORM, T>::RING == 1 ? 0 : slot) * HLayout<FORM, T>::SL + el * HLayout<FORM, T>::SE +
+            q * HLayout<FORM, T>::SQ;
     if constexpr (FORM == MF_FORM_NS_SUPG) {
         // g = J^-T grad_xi N (FP64); state at the point: u, grad u, p, grad p, Rm, div u.
         // 1/det and sqrt(det) both from one reciprocal square root
@@ -325,14 +334,9 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
         for (int a = 0; a < 8; ++a) {
             double g[3];
             g_of(a, g);
-            double adv = 0.0;
+            hq[R_PHI + 4 * a] = (T)(sw * N_of(a));
 #pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                hq[R_H + 3 * a + m] = (T)(sw * g[m]);
-                adv = fma(u[m], g[m], adv);
-            }
-            hq[R_N + a] = (T)(sw * N_of(a));
-            hq[R_ADV + a] = (T)(sw * adv);
+            for (int m = 0; m < 3; ++m) hq[R_PHI + 4 * a + 1 + m] = (T)(sw * g[m]);
         }
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
@@ -415,7 +419,8 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
 {
     constexpr int NF = FormTraits<FORM, 3>::NF;
     using Acc = AccT<FORM>;
-    constexpr int NV = FORM == MF_FORM_ELASTICITY ? 9 : (FORM == MF_FORM_NS_SUPG ? 16 : 1);
+    static_assert(FORM != MF_FORM_NS_SUPG, "the flow form has its own phase B");
+    constexpr int NV = FORM == MF_FORM_ELASTICITY ? 9 : 1;
     const int tid = threadIdx.x;
     const int bq = tid & 3, pe = tid >> 2;
     const int al = pe & (kColNodes - 1), eps = pe / kColNodes;
@@ -443,48 +448,7 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
 #pragma unroll 2
         for (int q = 0; q < 8; ++q) {
             const T* hq = he + q * HLayout<FORM, T>::SQ;
-            if constexpr (FORM == MF_FORM_NS_SUPG) {
-                // block (a, b) = sum over the point of (a-side term) x (b-side term) x (state
-                // coefficient); every product below carries W through the sqrt(W) factors
-                const T rho = (T)p.form.rho, mu = (T)p.form.mu, tm = (T)p.form.tau_m, tc = (T)p.form.tau_c;
-                T ha[3], u[3], gu[3][3], Rm[3];
-#pragma unroll
-                for (int m = 0; m < 3; ++m) {
-                    ha[m] = hq[R_H + 3 * alpha + m];
-                    u[m] = hq[R_U + m];
-                    Rm[m] = hq[R_RM + m];
-#pragma unroll
-                    for (int k2 = 0; k2 < 3; ++k2) gu[m][k2] = hq[R_GU + 3 * m + k2];
-                }
-                const T Nta = hq[R_N + alpha], aa = hq[R_ADV + alpha];
-                T cN[3][3], cH[3], sgu[3];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const T ci = -rho * u[i] + tm * rho * Rm[i];
-#pragma unroll
-                    for (int l = 0; l < 3; ++l) cN[i][l] = ci * ha[l] + tm * rho * rho * aa * gu[i][l];
-                    cH[i] = tc * ha[i];
-                    sgu[i] = ha[0] * gu[0][i] + ha[1] * gu[1][i] + ha[2] * gu[2][i];
-                }
-                const T d1 = -rho * aa, d3 = tm * rho * rho * aa, pa = tm * rho * aa;
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const int B = fb + b;
-                    const T hb[3] = {hq[R_H + 3 * B], hq[R_H + 3 * B + 1], hq[R_H + 3 * B + 2]};
-                    const T Nb = hq[R_N + B], ab = hq[R_ADV + B];
-                    const T hab = ha[0] * hb[0] + ha[1] * hb[1] + ha[2] * hb[2];
-                    const T dg = d1 * Nb + mu * hab + d3 * ab;
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-#pragma unroll
-                        for (int l = 0; l < 3; ++l)
-                            M[b][4 * i + l] += cN[i][l] * Nb + cH[i] * hb[l] + (i == l ? dg : T(0));
-                        M[b][4 * i + 3] += -ha[i] * Nb + pa * hb[i];
-                        M[b][12 + i] += Nta * hb[i] + tm * rho * (sgu[i] * Nb + ha[i] * ab);
-                    }
-                    M[b][15] += tm * hab;
-                }
-            } else if constexpr (FORM == MF_FORM_MASS) {
+            if constexpr (FORM == MF_FORM_MASS) {
                 double Fx[2], Fy[2], Fz[2];
                 gauss_factors(q & 1, Fx);
                 gauss_factors((q >> 1) & 1, Fy);
@@ -515,56 +479,31 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
                 }
             }
         }
-        // load vector (d = -R for the flow form) over this lane's two points
+        // load vector over this lane's two points
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int q = 2 * bq + k;
-            const T* hq = he + q * HLayout<FORM, T>::SQ;
-            if constexpr (FORM == MF_FORM_NS_SUPG) {
-                const T rho = (T)p.form.rho, mu = (T)p.form.mu, tm = (T)p.form.tau_m, tc = (T)p.form.tau_c;
-                T ha[3], u[3], Rm[3];
+            double Fx[2], Fy[2], Fz[2];
+            gauss_factors(k, Fx);
+            gauss_factors(bq & 1, Fy);
+            gauss_factors(bq >> 1, Fz);
+            const double Na = Fx[alpha & 1] * Fy[(alpha >> 1) & 1] * Fz[alpha >> 2];
 #pragma unroll
-                for (int m = 0; m < 3; ++m) {
-                    ha[m] = hq[R_H + 3 * alpha + m];
-                    u[m] = hq[R_U + m];
-                    Rm[m] = hq[R_RM + m];
-                }
-                const T Nta = hq[R_N + alpha], aa = hq[R_ADV + alpha];
-                const T sw = hq[R_S], pr = hq[R_P], div = hq[R_DIV];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const T visc = ha[0] * hq[R_GU + 3 * i] + ha[1] * hq[R_GU + 3 * i + 1] + ha[2] * hq[R_GU + 3 * i + 2];
-                    dp[i] -= sw * (-rho * aa * u[i] - ha[i] * pr + mu * visc + tm * rho * aa * Rm[i] + tc * ha[i] * div);
-                }
-                dp[3] -= sw * (Nta * div + tm * (ha[0] * Rm[0] + ha[1] * Rm[1] + ha[2] * Rm[2]));
-            } else {
-                double Fx[2], Fy[2], Fz[2];
-                gauss_factors(k, Fx);
-                gauss_factors(bq & 1, Fy);
-                gauss_factors(bq >> 1, Fz);
-                const double Na = Fx[alpha & 1] * Fy[(alpha >> 1) & 1] * Fz[alpha >> 2];
-#pragma unroll
-                for (int i = 0; i < NF; ++i) dp[i] += (T)Na * S.wf[slot][el][q][i];
-            }
+            for (int i = 0; i < NF; ++i) dp[i] += (T)Na * S.wf[slot][el][q][i];
         }
     }
 #pragma unroll
     for (int i = 0; i < NF; ++i) dp[i] = quad_sum(dp[i]);
     if (!valid) return;
 
-    const T cA = FORM == MF_FORM_NS_SUPG ? T(0) : S.cf[slot][el][0];
-    const T cB = FORM == MF_FORM_NS_SUPG ? T(0) : S.cf[slot][el][1];
+    const T cA = S.cf[slot][el][0];
+    const T cB = S.cf[slot][el][1];
     const int ax = alpha & 1, ay = (alpha >> 1) & 1, az = alpha >> 2;
-    Acc* row = &S.rowK[al][0];  // K order: [(i * 27 + slot) * NF + j]
+    Acc* row = &S.rowK[0][al][0];  // K order: [(i * 27 + slot) * NF + j]
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
         const int nslot = ((bq >> 1) - az + 1) * 9 + ((bq & 1) - ay + 1) * 3 + (b - ax + 1);
-        if constexpr (FORM == MF_FORM_NS_SUPG) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int l = 0; l < 4; ++l) unsafeAtomicAdd(row + (i * 27 + nslot) * 4 + l, (Acc)M[b][4 * i + l]);
-        } else if constexpr (FORM == MF_FORM_ELASTICITY) {
+        if constexpr (FORM == MF_FORM_ELASTICITY) {
             const T tr = M[b][0] + M[b][4] + M[b][8];
 #pragma unroll
             for (int i = 0; i < 3; ++i)
@@ -579,7 +518,7 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
     }
     if (bq == 0) {
 #pragma unroll
-        for (int i = 0; i < NF; ++i) unsafeAtomicAdd(&S.rowD[al][i], (Acc)dp[i]);
+        for (int i = 0; i < NF; ++i) unsafeAtomicAdd(&S.rowD[0][al][i], (Acc)dp[i]);
     }
 }
 
@@ -590,7 +529,8 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
 // copy; boundary nodes, field-major numbering and Dirichlet masks take the general
 // mapping.  K is written once and is far larger than the caches: non-temporal stores.
 template <int FORM, bool MASK, typename T>
-__device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, T>& S, int L, int wid, int nw)
+__device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, T>& S, int L, int wid, int nw,
+                                            int rb = 0)
 {
     constexpr int NF = FormTraits<FORM, 3>::NF;
     constexpr int NB = NF * NF;
@@ -608,12 +548,12 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int o = lane + 64 * c;
-            vals[c] = o < kNodeVals ? S.rowK[il][o] : Acc(0);
+            vals[c] = o < kNodeVals ? S.rowK[rb][il][o] : Acc(0);
         }
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int o = lane + 64 * c;
-            if (o < kNodeVals) S.rowK[il][o] = Acc(0);
+            if (o < kNodeVals) S.rowK[rb][il][o] = Acc(0);
         }
         const int node = S.ni[il][0];
         if (node < 0) continue;
@@ -670,8 +610,8 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
     }
     if (wid < kColNodes * NF) {
         const int il = wid / NF, i = wid - il * NF;
-        const Acc acc = S.rowD[il][i];
-        S.rowD[il][i] = Acc(0);
+        const Acc acc = S.rowD[rb][il][i];
+        S.rowD[rb][il][i] = Acc(0);
         const int node = S.ni[il][0];
         if (node >= 0) {
             const int row = p.field_major ? i * nn + node : NF * node + i;
@@ -696,8 +636,8 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
     const int z0 = ch * p.lz, z1 = min(z0 + p.lz, NZ);
     const bool f32 = sizeof(T) == 4;
 
-    for (int k = tid; k < kColNodes * 27 * NB; k += kThreads) (&S.rowK[0][0])[k] = 0.0;
-    for (int k = tid; k < kColNodes * NF; k += kThreads) (&S.rowD[0][0])[k] = 0.0;
+    for (int k = tid; k < kColNodes * 27 * NB; k += kThreads) (&S.rowK[0][0][0])[k] = 0.0;
+    for (int k = tid; k < kColNodes * NF; k += kThreads) (&S.rowD[0][0][0])[k] = 0.0;
     // prologue: node layers z0-1 .. z0+1, element parameters of layers z0-1 and z0
     for (int it = tid; it < 3 * kTileNodes; it += kThreads) {
         NodeLoad<NSRC, NF, MASK, T> ld;
@@ -761,13 +701,287 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
     if (z0 < z1) write_layer<FORM, MASK, T>(p, S, z1 - 1, tid, kThreads);
 }
 
+// ------------------------------------------------------------------------------------
+// Flow form (FP32): the pair contraction on the matrix cores.
+//
+// For one owned node a and one element e around it, the 4x4 blocks of row a against the
+// eight element nodes b factor through the b-side values phi_t(b) at each Gauss point q
+// (t = 0: sqrt(W) N_b, t = 1..3: sqrt(W) dN_b/dx_t, so every product carries W):
+//     K[(a,i),(b,l)] += sum_{q,t} C[a,q][i][l][t] phi_t(b, q),
+// where C collects the a-side factors of each term of the Jacobian (Sec. 4.3 form,
+// differentiated as the oracle does).  That is a product of a [16 x 32] coefficient tile
+// (rows (i, l), columns (q, t)) and the [32 x 8] table phi (rows (q, t), columns b).
+// v_mfma_f32_4x4x1_16b runs sixteen independent 4x4 outer products: block (pair, i, b
+// half) takes row i's four l values against four b, one (q, t) per instruction, so a wave
+// forms two (node, element) pairs in 32 instructions with every lane busy.  The
+// coefficient tiles are computed once per (node, element, q) by 16 lanes and passed
+// through LDS; each wave owns two nodes, so its row-buffer updates are plain
+// read-modify-writes with no atomics.
+//
+// Element layer kz feeds node layer kz (through the elements above it) and node layer
+// kz + 1 (below it); the body keeps one element layer of records and two row buffers.
+// ------------------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// orders the LDS accesses of the lanes of one wave
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// owned node al, element eps around it (bits dx, dy, dz), node layer Ln: whether the pair
+// contributes, the element's position in the layer's record ring and the node's local
+// index in the element
+struct NsPair {
+    bool ok;
+    int el;
+    int alpha;
+};
+__device__ __forceinline__ NsPair ns_pair(const ColParams& p, int al, int eps, int Ln, int zend, int i0, int j0)
+{
+    const int alx = al % CX, aly = al / CX;
+    const int gi = i0 + alx, gj = j0 + aly;
+    const int dx = eps & 1, dy = (eps >> 1) & 1, dz = eps >> 2;
+    const int ex = gi - 1 + dx, ey = gj - 1 + dy, ez = Ln - 1 + dz;
+    NsPair r;
+    r.ok = gi <= p.nx && gj <= p.ny && Ln < zend && ex >= 0 && ex < p.nx && ey >= 0 && ey < p.ny && ez >= 0 &&
+           ez < p.nz;
+    r.el = (alx + dx) + EXH * (aly + dy);
+    r.alpha = 7 - eps;
+    return r;
+}
+
+// Coefficient tile C[a,q] of one pair at one Gauss point (16 rows (i, l) of 4 values t),
+// written to dst [16][4]; the pair's share of d = -R at the point is added to dp.
+__device__ __forceinline__ void ns_coef_tile(const ColParams& p, const float* __restrict__ hq, int a,
+                                             float* __restrict__ dst, float (&dp)[4])
+{
+    const float rho = (float)p.form.rho, mu = (float)p.form.mu, tm = (float)p.form.tau_m, tc = (float)p.form.tau_c;
+    const f32x4 pa4 = *(const f32x4*)(hq + R_PHI + 4 * a);
+    const float Nta = pa4.x, ha[3] = {pa4.y, pa4.z, pa4.w};
+    float u[3], gu[3][3], Rm[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        u[m] = hq[R_U + m];
+        Rm[m] = hq[R_RM + m];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gu[m][k] = hq[R_GU + 3 * m + k];  // du_m / dx_k
+    }
+    const float aa = u[0] * ha[0] + u[1] * ha[1] + u[2] * ha[2];  // sqrt(W) u . grad N_a
+    const float d1 = -rho * aa, d3 = tm * rho * rho * aa, pa = tm * rho * aa;
+    f32x4 row[16];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float ci = tm * rho * Rm[i] - rho * u[i];
+        const float cH = tc * ha[i];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            f32x4 v;
+            v.x = ci * ha[l] + d3 * gu[i][l] + (i == l ? d1 : 0.0f);
+            v.y = (i == l ? mu * ha[0] + d3 * u[0] : 0.0f) + (l == 0 ? cH : 0.0f);
+            v.z = (i == l ? mu * ha[1] + d3 * u[1] : 0.0f) + (l == 1 ? cH : 0.0f);
+            v.w = (i == l ? mu * ha[2] + d3 * u[2] : 0.0f) + (l == 2 ? cH : 0.0f);
+            row[4 * i + l] = v;
+        }
+        f32x4 v;  // column field p
+        v.x = -ha[i];
+        v.y = i == 0 ? pa : 0.0f;
+        v.z = i == 1 ? pa : 0.0f;
+        v.w = i == 2 ? pa : 0.0f;
+        row[4 * i + 3] = v;
+    }
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {  // row field p
+        const float sgu = ha[0] * gu[0][l] + ha[1] * gu[1][l] + ha[2] * gu[2][l];
+        f32x4 v;
+        v.x = tm * rho * sgu;
+        v.y = (l == 0 ? Nta : 0.0f) + tm * rho * ha[l] * u[0];
+        v.z = (l == 1 ? Nta : 0.0f) + tm * rho * ha[l] * u[1];
+        v.w = (l == 2 ? Nta : 0.0f) + tm * rho * ha[l] * u[2];
+        row[12 + l] = v;
+    }
+    {
+        f32x4 v;
+        v.x = 0.0f;
+        v.y = tm * ha[0];
+        v.z = tm * ha[1];
+        v.w = tm * ha[2];
+        row[15] = v;
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) *(f32x4*)(dst + 4 * m) = row[m];
+    // d = -R at the point
+    const float sw = hq[R_S], pr = hq[R_P], div = hq[R_DIV];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float visc = ha[0] * gu[i][0] + ha[1] * gu[i][1] + ha[2] * gu[i][2];
+        dp[i] -= sw * (-rho * aa * u[i] - ha[i] * pr + mu * visc + tm * rho * aa * Rm[i] + tc * ha[i] * div);
+    }
+    dp[3] -= sw * (Nta * div + tm * (ha[0] * Rm[0] + ha[1] * Rm[1] + ha[2] * Rm[2]));
+}
+
+// Contributions of element layer Le (its records in the ring) to the rows of node layer
+// Le (when hi) and node layer Le + 1 (when lo; rows in buffer (Le + 1) & 1), for the
+// two nodes of this wave.
+template <typename T>
+__device__ __forceinline__ void ns_phase_b(const ColParams& p, ColShared<MF_FORM_NS_SUPG, T>& S, int Le, int zend,
+                                           int i0, int j0, bool hi, bool lo)
+{
+    static_assert(sizeof(T) == 4, "the flow-form gather is FP32");
+    constexpr int SE = HLayout<MF_FORM_NS_SUPG, T>::SE, SQ = HLayout<MF_FORM_NS_SUPG, T>::SQ;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    float* dt = S.dt[w];
+    // coefficient lanes: (pair n, Gauss point q)
+    const int cn = (lane >> 3) & 1, cq = lane & 7;
+    float dph[4] = {0, 0, 0, 0}, dpl[4] = {0, 0, 0, 0};
+    // product lanes: block (pair n, row field i, b half), lane r in the block
+    const int n = lane >> 5, ri = (lane >> 3) & 3, bh = (lane >> 2) & 1, r = lane & 3;
+    const int b = 4 * bh + r;
+    for (int g = 0; g < 8; ++g) {
+        const bool to_hi = g < 4;
+        if (to_hi ? !hi : !lo) continue;  // wave-uniform
+        const int eps = to_hi ? 4 + g : g - 4;
+        const int Ln = to_hi ? Le : Le + 1;
+        // coefficient tiles of the two pairs (node 2w + n, element eps)
+        if (lane < 16) {
+            const NsPair pr = ns_pair(p, 2 * w + cn, eps, Ln, zend, i0, j0);
+            float* dst = dt + (cn * 8 + cq) * 64;
+            if (pr.ok) {
+                ns_coef_tile(p, S.h + pr.el * SE + cq * SQ, pr.alpha, dst, to_hi ? dph : dpl);
+            } else {
+#pragma unroll
+                for (int m = 0; m < 16; ++m) *(f32x4*)(dst + 4 * m) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+        }
+        wave_lds_sync();
+        // products on the matrix cores: 8 Gauss points x 4 values t
+        const NsPair pr = ns_pair(p, 2 * w + n, eps, Ln, zend, i0, j0);
+        const float* At = dt + n * 8 * 64 + (4 * ri + r) * 4;
+        const float* Bt = S.h + pr.el * SE + R_PHI + 4 * b;
+        f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const f32x4 A = *(const f32x4*)(At + q * 64);
+            const f32x4 B = *(const f32x4*)(Bt + q * SQ);
+            acc0 = __builtin_amdgcn_mfma_f32_4x4x1f32(A.x, B.x, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_4x4x1f32(A.y, B.y, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_4x4x1f32(A.z, B.z, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_4x4x1f32(A.w, B.w, acc1, 0, 0, 0);
+        }
+        if (pr.ok) {
+            // lane holds K[(a, i), (b, l)] for l = 0..3: one 16-byte row-buffer update
+            const int ax = pr.alpha & 1, ay = (pr.alpha >> 1) & 1, az = pr.alpha >> 2;
+            const int nslot = ((b >> 2) - az + 1) * 9 + (((b >> 1) & 1) - ay + 1) * 3 + ((b & 1) - ax + 1);
+            f32x4* dstk = (f32x4*)&S.rowK[Ln & 1][2 * w + n][(ri * 27 + nslot) * 4];
+            *dstk = *dstk + acc0 + acc1;
+        }
+        wave_lds_sync();  // the tiles are rewritten by the next pair
+    }
+    // d: sum the Gauss-point lanes of each node (lanes cn * 8 + cq)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int off = 1; off < 8; off <<= 1) {
+            dph[i] += __shfl_xor(dph[i], off, 64);
+            dpl[i] += __shfl_xor(dpl[i], off, 64);
+        }
+    }
+    if (lane < 16 && cq == 0) {
+        const int al = 2 * w + cn;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (hi) S.rowD[Le & 1][al][i] += dph[i];
+            if (lo) S.rowD[(Le + 1) & 1][al][i] += dpl[i];
+        }
+    }
+}
+
+// One column chunk of the flow form: element layer by element layer, each feeding the
+// node layer below it and the one above it.
+template <bool MASK, typename T>
+__device__ __forceinline__ void column_body_ns(const ColParams& p, int b, ColShared<MF_FORM_NS_SUPG, T>& S)
+{
+    constexpr int FORM = MF_FORM_NS_SUPG;
+    constexpr int NF = 4, NSRC = 4, NB = 16;
+    using Sh = ColShared<FORM, T>;
+    const int tid = threadIdx.x;
+    const int NX = p.nx + 1, NY = p.ny + 1, NZ = p.nz + 1;
+    const int ncx = (NX + CX - 1) / CX, ncy = (NY + CY - 1) / CY;
+    const int cx = b % ncx, cy = (b / ncx) % ncy, ch = b / (ncx * ncy);
+    const int i0 = cx * CX, j0 = cy * CY;
+    const int z0 = ch * p.lz, z1 = min(z0 + p.lz, NZ);
+
+    for (int k = tid; k < Sh::NRB * kColNodes * 27 * NB; k += kThreads) (&S.rowK[0][0][0])[k] = 0.0f;
+    for (int k = tid; k < Sh::NRB * kColNodes * NF; k += kThreads) (&S.rowD[0][0][0])[k] = 0.0f;
+    for (int it = tid; it < 3 * kTileNodes; it += kThreads) {
+        NodeLoad<NSRC, NF, MASK, T> ld;
+        const int L = z0 - 1 + it / kTileNodes, tn = it % kTileNodes;
+        ld.load(p, L, tn, i0, j0);
+        ld.template store<FORM>(S, L, tn);
+    }
+    __syncthreads();
+    // element layer z0 - 1 feeds the first node layer of the chunk
+    if (tid < kGeomThreads) {
+        for (int it = tid; it < kGeomItems; it += kGeomThreads)
+            geometry_item<FORM, T>(p, S, z0 - 1, it >> 3, it & 7, i0, j0);
+    }
+    __syncthreads();
+    ns_phase_b<T>(p, S, z0 - 1, z1, i0, j0, false, true);
+    __syncthreads();
+
+    for (int kz = z0; kz < z1; ++kz) {
+        // ---- phase A: records of element layer kz; rows of node layer kz - 1
+        if (tid < kGeomThreads) {
+            for (int it = tid; it < kGeomItems; it += kGeomThreads)
+                geometry_item<FORM, T>(p, S, kz, it >> 3, it & 7, i0, j0);
+        } else if (kz > z0) {
+            write_layer<FORM, MASK, T>(p, S, kz - 1, tid - kGeomThreads, kThreads - kGeomThreads, (kz - 1) & 1);
+        }
+        __syncthreads();
+
+        // ---- phase B: element layer kz into node layers kz and kz + 1; prefetch
+        NodeLoad<NSRC, NF, MASK, T> ld;
+        ld.ok = false;
+        int info[4] = {-1, 0, 0, 0};
+        if (tid < kTileNodes) {
+            ld.load(p, kz + 2, tid, i0, j0);
+        } else if (tid >= kPfInfoT0 && tid < kPfInfoT0 + kColNodes) {
+            const int il = tid - kPfInfoT0;
+            const int gi = i0 + il % CX, gj = j0 + il / CX;
+            if (gi < NX && gj < NY) {
+                const int node = gi + NX * (gj + NY * kz);
+                const int mx = 1 + (gi > 0) + (gi < p.nx), my = 1 + (gj > 0) + (gj < p.ny),
+                          mz = 1 + (kz > 0) + (kz < p.nz);
+                info[0] = node;
+                info[1] = p.nbr_ptr[node];
+                info[2] = mx * my * mz;
+                info[3] = (gi > 0) | ((gi < p.nx) << 1) | ((gj > 0) << 2) | ((gj < p.ny) << 3) | ((kz > 0) << 4) |
+                          ((kz < p.nz) << 5);
+            }
+        }
+        ns_phase_b<T>(p, S, kz, z1, i0, j0, true, kz + 1 < z1);
+        if (tid < kTileNodes) ld.template store<FORM>(S, kz + 2, tid);
+        if (tid >= kPfInfoT0 && tid < kPfInfoT0 + kColNodes) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) S.ni[tid - kPfInfoT0][k] = info[k];
+        }
+        __syncthreads();
+    }
+    if (z0 < z1) write_layer<FORM, MASK, T>(p, S, z1 - 1, tid, kThreads, (z1 - 1) & 1);
+}
+
 // MASK: the problem has Dirichlet flags (the unmasked instantiation carries none of their
 // loads or registers)
 template <int FORM, bool MASK, typename T>
 __global__ void __launch_bounds__(kThreads, (MinBlocks<FORM, T>::value)) k_assemble_column(ColParams p)
 {
     __shared__ ColShared<FORM, T> S;
-    column_body<FORM, MASK, T>(p, blockIdx.x, S);
+    if constexpr (FORM == MF_FORM_NS_SUPG)
+        column_body_ns<MASK, T>(p, blockIdx.x, S);
+    else
+        column_body<FORM, MASK, T>(p, blockIdx.x, S);
 }
 
 // ------------------------------------------------------------------------------------
