@@ -71,6 +71,8 @@ struct HLayout {
     static constexpr int SL = kLayerElems * SE;                               // per element layer
 };
 
+constexpr int kNsTile = 68;  // floats per coefficient tile in LDS (64 used)
+
 // Offsets inside one flow-form record: for each element node a, the four values
 // (sqrt(W) N_a, sqrt(W) grad N_a) at R_PHI + 4 a, then the state at the point.
 enum NsRec { R_PHI = 0, R_U = 32, R_GU = 35, R_RM = 44, R_S = 47, R_P = 48, R_DIV = 49 };
@@ -147,8 +149,9 @@ struct ColShared {
     double ep[2][kLayerElems];
     alignas(16) AccT<FORM> rowK[NRB][kColNodes][27 * NB];
     AccT<FORM> rowD[NRB][kColNodes][NF];
-    // flow form: per wave, the coefficient tiles of two (node, element) pairs, [pair][q][16][4]
-    alignas(16) float dt[NS ? kThreads / 64 : 1][NS ? 2 * 8 * 16 * 4 : 1];
+    // flow form: per wave, the coefficient tiles of two (node, element) pairs, [pair][q]
+    // tiles of [16][4] values, each padded to kNsTile floats (spreads the LDS banks)
+    alignas(16) float dt[NS ? kThreads / 64 : 1][NS ? 2 * 8 * kNsTile : 1];
     int ni[kColNodes][4];  // node id, first pair offset, degree, boundary bits
     // Dirichlet flags of the tile's DOFs for node layers L = kz-2 .. kz+1 (slot L & 3): the
     // write-out of layer kz-1 reads its rows' and its neighbours' flags here, so no global
@@ -542,7 +545,12 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
     const int nn = p.n_nodes;
     const bool masked = MASK && p.dirichlet;
     const bool plain = !p.field_major && !masked;
-    const int lane = wid & 63, wv = wid >> 6, nwv = nw >> 6;
+    int lane = wid & 63;
+    // flow form: the per-chunk index arithmetic below depends only on the lane; keep the
+    // compiler from hoisting it out of the layer loop, where it would hold registers
+    // throughout (the kernel spilled)
+    if constexpr (FORM == MF_FORM_NS_SUPG) asm volatile("" : "+v"(lane));
+    const int wv = wid >> 6, nwv = nw >> 6;
     for (int il = wv; il < kColNodes; il += nwv) {
         Acc vals[NCH];
 #pragma unroll
@@ -753,73 +761,71 @@ __device__ __forceinline__ NsPair ns_pair(const ColParams& p, int al, int eps, i
     return r;
 }
 
-// Coefficient tile C[a,q] of one pair at one Gauss point (16 rows (i, l) of 4 values t),
-// written to dst [16][4]; the pair's share of d = -R at the point is added to dp.
-__device__ __forceinline__ void ns_coef_tile(const ColParams& p, const float* __restrict__ hq, int a,
-                                             float* __restrict__ dst, float (&dp)[4])
+// Row i of the coefficient tile C[a,q] of one pair at one Gauss point (four column
+// fields l of four values t), written to dst [4][4]; the pair's share of (d = -R)_i at
+// the point is added to dpi.  i is the lane's row field (3 = pressure).
+__device__ __forceinline__ void ns_coef_row(const ColParams& p, const float* __restrict__ hq, int a, int i,
+                                            float* __restrict__ dst, float& dpi)
 {
     const float rho = (float)p.form.rho, mu = (float)p.form.mu, tm = (float)p.form.tau_m, tc = (float)p.form.tau_c;
     const f32x4 pa4 = *(const f32x4*)(hq + R_PHI + 4 * a);
     const float Nta = pa4.x, ha[3] = {pa4.y, pa4.z, pa4.w};
-    float u[3], gu[3][3], Rm[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        u[m] = hq[R_U + m];
-        Rm[m] = hq[R_RM + m];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) gu[m][k] = hq[R_GU + 3 * m + k];  // du_m / dx_k
-    }
+    // state at the point: u (3), grad u (9, du_m/dx_k at 3 m + k), Rm (3), sqrt(W), p, div u
+    const f32x4 s0 = *(const f32x4*)(hq + R_U), s1 = *(const f32x4*)(hq + R_U + 4),
+                s2 = *(const f32x4*)(hq + R_U + 8), s3 = *(const f32x4*)(hq + R_U + 12),
+                s4 = *(const f32x4*)(hq + R_U + 16);
+    const float u[3] = {s0.x, s0.y, s0.z};
+    const float gu[3][3] = {{s0.w, s1.x, s1.y}, {s1.z, s1.w, s2.x}, {s2.y, s2.z, s2.w}};
+    const float Rm[3] = {s3.x, s3.y, s3.z};
+    const float sw = s3.w, pr = s4.x, div = s4.y;
     const float aa = u[0] * ha[0] + u[1] * ha[1] + u[2] * ha[2];  // sqrt(W) u . grad N_a
-    const float d1 = -rho * aa, d3 = tm * rho * rho * aa, pa = tm * rho * aa;
-    f32x4 row[16];
+    const float d3 = tm * rho * rho * aa;
+    // the lane's row values (i < 3; i = 3 reads row 2, unused)
+    const bool r0 = i == 0, r1 = i == 1;
+    const float ui = r0 ? u[0] : (r1 ? u[1] : u[2]);
+    const float Rmi = r0 ? Rm[0] : (r1 ? Rm[1] : Rm[2]);
+    const float hai = r0 ? ha[0] : (r1 ? ha[1] : ha[2]);
+    float gui[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const float ci = tm * rho * Rm[i] - rho * u[i];
-        const float cH = tc * ha[i];
+    for (int k = 0; k < 3; ++k) gui[k] = r0 ? gu[0][k] : (r1 ? gu[1][k] : gu[2][k]);
+    f32x4 v[4];
+    if (i < 3) {
+        const float ci = tm * rho * Rmi - rho * ui;
+        const float cH = tc * hai;
+        const float dd = -rho * aa;                                   // (i == l) part of the N column
+        const float dk[3] = {mu * ha[0] + d3 * u[0], mu * ha[1] + d3 * u[1], mu * ha[2] + d3 * u[2]};
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
-            f32x4 v;
-            v.x = ci * ha[l] + d3 * gu[i][l] + (i == l ? d1 : 0.0f);
-            v.y = (i == l ? mu * ha[0] + d3 * u[0] : 0.0f) + (l == 0 ? cH : 0.0f);
-            v.z = (i == l ? mu * ha[1] + d3 * u[1] : 0.0f) + (l == 1 ? cH : 0.0f);
-            v.w = (i == l ? mu * ha[2] + d3 * u[2] : 0.0f) + (l == 2 ? cH : 0.0f);
-            row[4 * i + l] = v;
+            const bool il = i == l;
+            v[l].x = ci * ha[l] + d3 * gui[l] + (il ? dd : 0.0f);
+            v[l].y = (il ? dk[0] : 0.0f) + (l == 0 ? cH : 0.0f);
+            v[l].z = (il ? dk[1] : 0.0f) + (l == 1 ? cH : 0.0f);
+            v[l].w = (il ? dk[2] : 0.0f) + (l == 2 ? cH : 0.0f);
         }
-        f32x4 v;  // column field p
-        v.x = -ha[i];
-        v.y = i == 0 ? pa : 0.0f;
-        v.z = i == 1 ? pa : 0.0f;
-        v.w = i == 2 ? pa : 0.0f;
-        row[4 * i + 3] = v;
+        const float pa = tm * rho * aa;
+        v[3].x = -hai;
+        v[3].y = r0 ? pa : 0.0f;
+        v[3].z = r1 ? pa : 0.0f;
+        v[3].w = i == 2 ? pa : 0.0f;
+        const float visc = ha[0] * gui[0] + ha[1] * gui[1] + ha[2] * gui[2];
+        dpi -= sw * (-rho * aa * ui - hai * pr + mu * visc + tm * rho * aa * Rmi + tc * hai * div);
+    } else {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const float sgu = ha[0] * gu[0][l] + ha[1] * gu[1][l] + ha[2] * gu[2][l];
+            v[l].x = tm * rho * sgu;
+            v[l].y = (l == 0 ? Nta : 0.0f) + tm * rho * ha[l] * u[0];
+            v[l].z = (l == 1 ? Nta : 0.0f) + tm * rho * ha[l] * u[1];
+            v[l].w = (l == 2 ? Nta : 0.0f) + tm * rho * ha[l] * u[2];
+        }
+        v[3].x = 0.0f;
+        v[3].y = tm * ha[0];
+        v[3].z = tm * ha[1];
+        v[3].w = tm * ha[2];
+        dpi -= sw * (Nta * div + tm * (ha[0] * Rm[0] + ha[1] * Rm[1] + ha[2] * Rm[2]));
     }
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {  // row field p
-        const float sgu = ha[0] * gu[0][l] + ha[1] * gu[1][l] + ha[2] * gu[2][l];
-        f32x4 v;
-        v.x = tm * rho * sgu;
-        v.y = (l == 0 ? Nta : 0.0f) + tm * rho * ha[l] * u[0];
-        v.z = (l == 1 ? Nta : 0.0f) + tm * rho * ha[l] * u[1];
-        v.w = (l == 2 ? Nta : 0.0f) + tm * rho * ha[l] * u[2];
-        row[12 + l] = v;
-    }
-    {
-        f32x4 v;
-        v.x = 0.0f;
-        v.y = tm * ha[0];
-        v.z = tm * ha[1];
-        v.w = tm * ha[2];
-        row[15] = v;
-    }
-#pragma unroll
-    for (int m = 0; m < 16; ++m) *(f32x4*)(dst + 4 * m) = row[m];
-    // d = -R at the point
-    const float sw = hq[R_S], pr = hq[R_P], div = hq[R_DIV];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const float visc = ha[0] * gu[i][0] + ha[1] * gu[i][1] + ha[2] * gu[i][2];
-        dp[i] -= sw * (-rho * aa * u[i] - ha[i] * pr + mu * visc + tm * rho * aa * Rm[i] + tc * ha[i] * div);
-    }
-    dp[3] -= sw * (Nta * div + tm * (ha[0] * Rm[0] + ha[1] * Rm[1] + ha[2] * Rm[2]));
+    for (int l = 0; l < 4; ++l) *(f32x4*)(dst + 4 * l) = v[l];
 }
 
 // Contributions of element layer Le (its records in the ring) to the rows of node layer
@@ -833,37 +839,38 @@ __device__ __forceinline__ void ns_phase_b(const ColParams& p, ColShared<MF_FORM
     constexpr int SE = HLayout<MF_FORM_NS_SUPG, T>::SE, SQ = HLayout<MF_FORM_NS_SUPG, T>::SQ;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     float* dt = S.dt[w];
-    // coefficient lanes: (pair n, Gauss point q)
-    const int cn = (lane >> 3) & 1, cq = lane & 7;
-    float dph[4] = {0, 0, 0, 0}, dpl[4] = {0, 0, 0, 0};
+    // coefficient lanes: (pair n, Gauss point q, row field i)
+    const int cn = lane >> 5, cq = (lane >> 2) & 7, ci = lane & 3;
+    float dph = 0.0f, dpl = 0.0f;
     // product lanes: block (pair n, row field i, b half), lane r in the block
     const int n = lane >> 5, ri = (lane >> 3) & 3, bh = (lane >> 2) & 1, r = lane & 3;
     const int b = 4 * bh + r;
+#pragma unroll 1
     for (int g = 0; g < 8; ++g) {
         const bool to_hi = g < 4;
         if (to_hi ? !hi : !lo) continue;  // wave-uniform
         const int eps = to_hi ? 4 + g : g - 4;
         const int Ln = to_hi ? Le : Le + 1;
-        // coefficient tiles of the two pairs (node 2w + n, element eps)
-        if (lane < 16) {
+        // coefficient tiles of the two pairs (node 2w + n, element eps), one row per lane
+        {
             const NsPair pr = ns_pair(p, 2 * w + cn, eps, Ln, zend, i0, j0);
-            float* dst = dt + (cn * 8 + cq) * 64;
+            float* dst = dt + (cn * 8 + cq) * kNsTile + 16 * ci;
             if (pr.ok) {
-                ns_coef_tile(p, S.h + pr.el * SE + cq * SQ, pr.alpha, dst, to_hi ? dph : dpl);
+                ns_coef_row(p, S.h + pr.el * SE + cq * SQ, pr.alpha, ci, dst, to_hi ? dph : dpl);
             } else {
 #pragma unroll
-                for (int m = 0; m < 16; ++m) *(f32x4*)(dst + 4 * m) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                for (int l = 0; l < 4; ++l) *(f32x4*)(dst + 4 * l) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
             }
         }
         wave_lds_sync();
         // products on the matrix cores: 8 Gauss points x 4 values t
         const NsPair pr = ns_pair(p, 2 * w + n, eps, Ln, zend, i0, j0);
-        const float* At = dt + n * 8 * 64 + (4 * ri + r) * 4;
+        const float* At = dt + n * 8 * kNsTile + (4 * ri + r) * 4;
         const float* Bt = S.h + pr.el * SE + R_PHI + 4 * b;
         f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const f32x4 A = *(const f32x4*)(At + q * 64);
+            const f32x4 A = *(const f32x4*)(At + q * kNsTile);
             const f32x4 B = *(const f32x4*)(Bt + q * SQ);
             acc0 = __builtin_amdgcn_mfma_f32_4x4x1f32(A.x, B.x, acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_4x4x1f32(A.y, B.y, acc1, 0, 0, 0);
@@ -879,22 +886,16 @@ __device__ __forceinline__ void ns_phase_b(const ColParams& p, ColShared<MF_FORM
         }
         wave_lds_sync();  // the tiles are rewritten by the next pair
     }
-    // d: sum the Gauss-point lanes of each node (lanes cn * 8 + cq)
+    // d: sum the Gauss-point lanes of each (node, row field): lanes cn * 32 + 4 cq + ci
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-#pragma unroll
-        for (int off = 1; off < 8; off <<= 1) {
-            dph[i] += __shfl_xor(dph[i], off, 64);
-            dpl[i] += __shfl_xor(dpl[i], off, 64);
-        }
+    for (int off = 4; off < 32; off <<= 1) {
+        dph += __shfl_xor(dph, off, 64);
+        dpl += __shfl_xor(dpl, off, 64);
     }
-    if (lane < 16 && cq == 0) {
+    if (cq == 0) {
         const int al = 2 * w + cn;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (hi) S.rowD[Le & 1][al][i] += dph[i];
-            if (lo) S.rowD[(Le + 1) & 1][al][i] += dpl[i];
-        }
+        if (hi) S.rowD[Le & 1][al][ci] += dph;
+        if (lo) S.rowD[(Le + 1) & 1][al][ci] += dpl;
     }
 }
 
