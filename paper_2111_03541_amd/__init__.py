@@ -137,6 +137,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2111_03541_amd.build`")
+    try:  # torch first: the library then binds to the HIP runtime torch has loaded, not a second copy
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     P, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
     lib.mf_pattern.argtypes = [C.POINTER(_Mesh), C.c_int, i32, C.POINTER(_Dofs), P, C.POINTER(P)]

@@ -830,7 +830,9 @@ __device__ __forceinline__ void ns_coef_row(const ColParams& p, const float* __r
 
 // Contributions of element layer Le (its records in the ring) to the rows of node layer
 // Le (when hi) and node layer Le + 1 (when lo; rows in buffer (Le + 1) & 1), for the
-// two nodes of this wave.
+// two nodes of this wave.  Software-pipelined over the eight pair groups: the operands
+// of group g are read into registers, then the coefficient rows of group g + 1 are
+// formed (vector units) while the products of group g run (matrix cores).
 template <typename T>
 __device__ __forceinline__ void ns_phase_b(const ColParams& p, ColShared<MF_FORM_NS_SUPG, T>& S, int Le, int zend,
                                            int i0, int j0, bool hi, bool lo)
@@ -845,37 +847,46 @@ __device__ __forceinline__ void ns_phase_b(const ColParams& p, ColShared<MF_FORM
     // product lanes: block (pair n, row field i, b half), lane r in the block
     const int n = lane >> 5, ri = (lane >> 3) & 3, bh = (lane >> 2) & 1, r = lane & 3;
     const int b = 4 * bh + r;
-#pragma unroll 1
-    for (int g = 0; g < 8; ++g) {
+    // groups: g < 4 -> node layer Le through the elements above it (eps = 4 + g),
+    // g >= 4 -> node layer Le + 1 through the elements below it (eps = g - 4)
+    const int g0 = hi ? 0 : 4, g1 = lo ? 8 : 4;
+    auto coef = [&](int g) {
         const bool to_hi = g < 4;
-        if (to_hi ? !hi : !lo) continue;  // wave-uniform
+        const int eps = to_hi ? 4 + g : g - 4;
+        const NsPair pr = ns_pair(p, 2 * w + cn, eps, to_hi ? Le : Le + 1, zend, i0, j0);
+        float* dst = dt + (cn * 8 + cq) * kNsTile + 16 * ci;
+        if (pr.ok) {
+            ns_coef_row(p, S.h + pr.el * SE + cq * SQ, pr.alpha, ci, dst, to_hi ? dph : dpl);
+        } else {
+#pragma unroll
+            for (int l = 0; l < 4; ++l) *(f32x4*)(dst + 4 * l) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+    };
+    if (g0 < g1) coef(g0);
+#pragma unroll 1
+    for (int g = g0; g < g1; ++g) {
+        const bool to_hi = g < 4;
         const int eps = to_hi ? 4 + g : g - 4;
         const int Ln = to_hi ? Le : Le + 1;
-        // coefficient tiles of the two pairs (node 2w + n, element eps), one row per lane
-        {
-            const NsPair pr = ns_pair(p, 2 * w + cn, eps, Ln, zend, i0, j0);
-            float* dst = dt + (cn * 8 + cq) * kNsTile + 16 * ci;
-            if (pr.ok) {
-                ns_coef_row(p, S.h + pr.el * SE + cq * SQ, pr.alpha, ci, dst, to_hi ? dph : dpl);
-            } else {
-#pragma unroll
-                for (int l = 0; l < 4; ++l) *(f32x4*)(dst + 4 * l) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            }
-        }
-        wave_lds_sync();
-        // products on the matrix cores: 8 Gauss points x 4 values t
+        wave_lds_sync();  // the tiles of group g are written
         const NsPair pr = ns_pair(p, 2 * w + n, eps, Ln, zend, i0, j0);
         const float* At = dt + n * 8 * kNsTile + (4 * ri + r) * 4;
         const float* Bt = S.h + pr.el * SE + R_PHI + 4 * b;
+        f32x4 A[8], B[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            A[q] = *(const f32x4*)(At + q * kNsTile);
+            B[q] = *(const f32x4*)(Bt + q * SQ);
+        }
+        wave_lds_sync();  // every lane has its operands: the tiles may be rewritten
+        if (g + 1 < g1) coef(g + 1);
         f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const f32x4 A = *(const f32x4*)(At + q * kNsTile);
-            const f32x4 B = *(const f32x4*)(Bt + q * SQ);
-            acc0 = __builtin_amdgcn_mfma_f32_4x4x1f32(A.x, B.x, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_4x4x1f32(A.y, B.y, acc1, 0, 0, 0);
-            acc0 = __builtin_amdgcn_mfma_f32_4x4x1f32(A.z, B.z, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_4x4x1f32(A.w, B.w, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_4x4x1f32(A[q].x, B[q].x, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_4x4x1f32(A[q].y, B[q].y, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_4x4x1f32(A[q].z, B[q].z, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_4x4x1f32(A[q].w, B[q].w, acc1, 0, 0, 0);
         }
         if (pr.ok) {
             // lane holds K[(a, i), (b, l)] for l = 0..3: one 16-byte row-buffer update
@@ -884,7 +895,6 @@ __device__ __forceinline__ void ns_phase_b(const ColParams& p, ColShared<MF_FORM
             f32x4* dstk = (f32x4*)&S.rowK[Ln & 1][2 * w + n][(ri * 27 + nslot) * 4];
             *dstk = *dstk + acc0 + acc1;
         }
-        wave_lds_sync();  // the tiles are rewritten by the next pair
     }
     // d: sum the Gauss-point lanes of each (node, row field): lanes cn * 32 + 4 cq + ci
 #pragma unroll
