@@ -1,6 +1,6 @@
 """Benchmark of the assembly hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--only all|primary] [--copy-probe]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu] [--only all|primary|ns|f32] [--copy-probe]
 
 One step = one mf_assemble of 3D linear elasticity on the unit cube: 64^3 trilinear Q1
 hexes (274,625 nodes, 823,875 DOFs), interior nodes jittered by +-15% of h, per-element
@@ -8,10 +8,13 @@ Young's modulus lognormal(0, 0.5^2), nu = 0.3, nodal body force U[-1,1], 2x2x2 G
 FP64 (K = 64,701,513 nonzeros).  Inputs are resident in HBM before timing starts.
 
 Printed: one JSON line with throughput (elements/s), the roofline of the assembly
-launch (algorithmic HBM bytes / measured time vs 8 TB/s) and the oracle timed on the
-host (one core) on the same workload.  Secondary records: the same assembly in FP32,
-PCG to 1e-8 on 96^3 Poisson with Jacobi and with the learned preconditioner, the
-batched launch of 256 problems, and the 48^3 Navier-Stokes Jacobian in FP32.
+launch (algorithmic HBM bytes / measured time vs 8 TB/s, warm and with a 512 MB scrub
+between launches) and the oracle timed on the host's cores on the same workload (all
+cores colour by colour, and one core).  Secondary records: the same assembly in FP32,
+2D Poisson 32^2 (latency), boundary forms, PCG to 1e-8 on 96^3 Poisson with Jacobi and
+with the learned preconditioner, the batched launch of 256 problems, the 48^3
+Navier-Stokes Jacobian in FP32 (against the FP32 matrix peak), Newton on the
+lid-driven cavity, transient conduction and quadratic-element elasticity.
 """
 from __future__ import annotations
 
@@ -31,9 +34,10 @@ HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
 # FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a 1 GiB copy (summary in
 # profiles/assemble_column_elasticity64_f64_counters.md); used only while the library
 # reports the kernel revision it was measured on.
-MEASURED_TRAFFIC = {"revision": "assembly column-4x2 r8", "bytes": 649.14e6}
+MEASURED_TRAFFIC = {"revision": "assembly column-4x2 r9", "bytes": 649.34e6}
 FP64_PEAK = 78.6e12        # flop/s, vector and matrix
 FP32_PEAK = 157.3e12       # flop/s, matrix (vector without packed math: half)
+NS_FLOP_PER_ELEM = 8 * 8 * 16 * 8 * 4 * 2  # flow Jacobian: (a, q) pairs x tile product, FMA = 2 flop
 
 
 def log(*a):
@@ -219,8 +223,13 @@ def bench_ns(dev, steps=10, warmup=3, n=48):
     avg = float(np.mean(per))
     B = pat.nnz * 4 + pat.n_rows * 4 + 3 * mesh.n_nodes * 8 + 4 * mesh.n_nodes * 4
     log(f"[bench] NS 48^3 FP32 avg {avg * 1e6:.1f} us ({mesh.n_elems / avg / 1e6:.1f} M el/s)")
+    # compute roofline: the factored contraction, per (node a, element, Gauss point) a
+    # 16 x 32 coefficient tile times the 32 x 8 table of b-side values (1,024 flop), 64 such
+    # per element, on the FP32 matrix cores
+    F = NS_FLOP_PER_ELEM * mesh.n_elems
     return {"avg_us": avg * 1e6, "elems_per_s": mesh.n_elems / avg, "n_elems": mesh.n_elems, "nnz": pat.nnz,
-            "alg_bytes": B, "hbm_frac": B / avg / HBM_PEAK}
+            "alg_bytes": B, "hbm_frac": B / avg / HBM_PEAK, "alg_flop": F, "tflops": F / avg / 1e12,
+            "fp32_peak_frac": F / avg / FP32_PEAK}
 
 
 def ns_taus(n, U=1.0, nu=0.01):
@@ -447,77 +456,67 @@ def bench_hex20(dev, n=24, steps=10, warmup=3, cpu=True):
     return out
 
 
-def bench_cantilever(dev, cpu=True):
-    """The paper's 3D cantilever (Sec. 4.2): 10 x 4 x 4 quadratic bricks, L = 10, h = 1,
-    E = 1, nu = 0, the face x = 0 clamped, a unit end load as a uniform shear traction on
-    x = L.  Timed: assembly, the traction, and Jacobi-PCG to the attainable 1e-9.  The
-    centre-line deflection is compared with the Euler-Bernoulli closed form
-    -P x^2 (3L - x) / (6 E I), I = h^4 / 12."""
-    import torch
-    import workloads as W
-    import paper_2111_03541_amd as mf
-    n, L = (10, 4, 4), 10.0
-    mesh = W.serendipity_mesh(n, lengths=[L, 1.0, 1.0])
-    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 3)
-    coords = torch.from_numpy(mesh.coords).to(dev)
-    clamp = torch.from_numpy(np.repeat(np.abs(mesh.coords[0]) < 1e-12, 3).astype(np.uint8)).to(dev)
-    fe, fi = (torch.from_numpy(a).to(dev) for a in W.box_faces(n, sides=[1]))
-    sig = [0.0, 0.0, 0.0, -1.0, 0.0, 0.0, 0.0, 0.0, 0.0]
-    rp, ci, _ = pat.device_arrays()
-    form = mf.Form(mf.ELASTICITY, coef=1.0, nu=0.0)
-
-    def solve():
-        K, d = pat.assemble(form, coords, dirichlet=clamp)
-        pat.assemble_boundary(mf.BFORM_TRACTION, coords, fe, fi, value=sig, K=K, d=d)
-        return mf.pcg(rp, ci, K, d, tol=1e-9, maxit=20000)
-
-    solve()
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(3):
-        t0 = time.perf_counter()
-        x, res = solve()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    u = x.cpu().numpy().reshape(-1, 3)
-    c = mesh.coords
-    line = np.nonzero((np.abs(c[1] - 0.5) < 1e-12) & (np.abs(c[2] - 0.5) < 1e-12))[0]
-    xs = c[0, line]
-    beam = -xs ** 2 * (3 * L - xs) / (6 * (1.0 / 12.0))
-    err = float(np.abs(u[line, 1] - beam).max() / np.abs(beam).max())
-    out = {"n_elems": mesh.n_elems, "n_dofs": pat.n_rows, "ms": float(np.median(times)) * 1e3,
-           "pcg_iterations": res["iterations"], "tip_deflection": float(u[line, 1][np.argmax(xs)]),
-           "beam_tip": float(beam[np.argmax(xs)]), "max_err_vs_beam_over_tip": err}
-    log(f"[bench] cantilever 10x4x4 hex20: {out['ms']:.2f} ms, {res['iterations']} PCG it, "
-        f"tip {out['tip_deflection']:.1f} vs beam {out['beam_tip']:.1f}")
-    if cpu:
-        import scipy.sparse.linalg as spla
-        import oracle as O
-        import oracle.boundary as OB
-        import oracle.serendipity as S
-        t0 = time.perf_counter()
-        op = S.Pattern20(mesh, 3)
-        Kr = op.to_scipy(S.assemble20(op, O.ELASTICITY, {"coef": 1.0, "nu": 0.0})[0])
-        sg = np.zeros((3, 3))
-        sg[1, 0] = -1.0
-        _, dr = S.assemble_boundary20(op, OB.TRACTION, 1.0, sg.reshape(-1), *W.box_faces(n, sides=[1]))
-        free = np.abs(np.repeat(mesh.coords[0], 3)) > 1e-12
-        spla.spsolve(Kr[free][:, free].tocsc(), dr[free])
-        out["cpu_oracle"] = {"ms": (time.perf_counter() - t0) * 1e3, "cores": 1,
-                             "kind": "oracle (numpy element loop, scipy direct solve)"}
-    return out
+def host_threads():
+    """Threads for the all-core oracle: the cores this process may run on, at most 16
+    (the host share of one GPU)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 def cpu_baseline(mesh, E, b):
+    """The oracle on the full 64^3 elasticity mesh: element colour by colour on every
+    host core this process may use (the reported value), and sequentially on one core."""
     import oracle as O
     t0 = time.perf_counter()
     pat = O.Pattern(mesh, 3)
     t1 = time.perf_counter()
-    O.assemble(pat, O.ELASTICITY, {"coef": 1.0, "nu": 0.3}, elem_param=E, nodal_src=b)
+    threads = host_threads()
+    prm = {"coef": 1.0, "nu": 0.3}
+    _, _, used = O.assemble_parallel(pat, O.ELASTICITY, prm, elem_param=E, nodal_src=b, threads=threads)
     t2 = time.perf_counter()
-    return {"value": mesh.n_elems / (t2 - t1), "unit": "elems/s", "cores": 1, "kind": "oracle",
-            "sample": f"full {mesh.n_elems}-element elasticity mesh, one sequential FP64 assembly "
-                      f"({t2 - t1:.2f} s; pattern build {t1 - t0:.2f} s not counted)"}
+    O.assemble(pat, O.ELASTICITY, prm, elem_param=E, nodal_src=b)
+    t3 = time.perf_counter()
+    log(f"[bench] oracle 64^3: {t2 - t1:.2f} s on {used} threads, {t3 - t2:.2f} s on one core")
+    return {"value": mesh.n_elems / (t2 - t1), "unit": "elems/s", "cores": used, "kind": "oracle",
+            "sample": f"full {mesh.n_elems}-element elasticity mesh, one FP64 assembly colour by colour on "
+                      f"{used} threads ({t2 - t1:.2f} s; pattern build {t1 - t0:.2f} s not counted)",
+            "affinity_cores": len(os.sched_getaffinity(0)),
+            "one_core": {"value": mesh.n_elems / (t3 - t2), "unit": "elems/s", "cores": 1,
+                         "seconds": t3 - t2}}
+
+
+def bench_poisson2d(dev, steps=50, warmup=10, cpu=True):
+    """Thermal conduction on the unit square, 32 x 32 Q1, k = 1, f ~ U[0,1] (seed 1),
+    u = 0 on the 128 boundary nodes, FP64: the whole system is about 127 kB, so the
+    figure is launch latency."""
+    import torch
+    import workloads as W
+    import paper_2111_03541_amd as mf
+    mesh = W.structured_mesh((32, 32))
+    f = W.uniform_nodal(1, mesh.n_nodes, 0, 1, 1)
+    mask = W.boundary_node_mask(mesh.shape)
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 2, 1)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    ft = torch.from_numpy(f).to(dev)
+    mt = torch.from_numpy(mask).to(dev)
+    K = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
+    d = torch.empty(pat.n_rows, dtype=torch.float64, device=dev)
+    form = mf.Form(mf.POISSON, coef=1.0)
+    stream = torch.cuda.current_stream(dev)
+    _, per = time_launches(lambda: pat.assemble(form, coords, nodal_src=ft, dirichlet=mt, K=K, d=d), steps, warmup,
+                           stream)
+    t = float(np.median(per))
+    out = {"n_elems": mesh.n_elems, "n_dofs": pat.n_rows, "nnz": pat.nnz, "latency_us": t * 1e6,
+           "elems_per_s": mesh.n_elems / t}
+    log(f"[bench] Poisson 2D 32^2: {t * 1e6:.1f} us per assembly (median of {steps})")
+    if cpu:
+        import oracle as O
+        op = O.Pattern(mesh, 1)
+        t0 = time.perf_counter()
+        for _ in range(20):
+            O.assemble(op, O.POISSON, {"coef": 1.0}, nodal_src=f, dirichlet=mask)
+        tc = (time.perf_counter() - t0) / 20
+        out["cpu_oracle"] = {"latency_us": tc * 1e6, "cores": 1, "kind": "oracle"}
+    return out
 
 
 def main():
@@ -581,10 +580,24 @@ def main():
     st, bad = pat.status()
     assert st == mf.OK, (st, bad)
     avg = float(np.mean(per))
+    # the same launch with 512 MB written between launches (caches and MALL hold none of
+    # the inputs): the cold figure beside the warm one
+    scrub = torch.empty(1 << 26, dtype=torch.float64, device=dev)
+    cold = []
+    for k in range(args.steps):
+        scrub.fill_(float(k))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        cold.append(e0.elapsed_time(e1) * 1e-3)
+    del scrub
+    cold_avg = float(np.mean(cold))
     B = alg_bytes_elasticity(mesh, pat.nnz, pat.n_rows, 8)
     achieved = B / avg
     log(f"[bench] assemble avg {avg * 1e6:.1f} us  ({mesh.n_elems / avg / 1e9:.3f} G el/s, "
-        f"{achieved / 1e9:.0f} GB/s algorithmic)")
+        f"{achieved / 1e9:.0f} GB/s algorithmic); cold {cold_avg * 1e6:.1f} us")
 
     record = {
         "metric": "assembly elems/s + %HBM roofline",
@@ -607,7 +620,10 @@ def main():
                      "frac": achieved / HBM_PEAK,
                      "traffic": (MEASURED_TRAFFIC["bytes"] if MEASURED_TRAFFIC["revision"] in mf.version()
                                  else None),
-                     "alg_bytes_per_launch": B, "avg_launch_us": avg * 1e6},
+                     "alg_bytes_per_launch": B, "avg_launch_us": avg * 1e6,
+                     "traffic_source": f"rocprofv3 FETCH_SIZE + WRITE_SIZE on kernel revision "
+                                       f"'{MEASURED_TRAFFIC['revision']}', scaled by a 1 GiB copy",
+                     "cold_avg_launch_us": cold_avg * 1e6, "cold_frac": B / cold_avg / HBM_PEAK},
     }
     if args.copy_probe:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
@@ -638,6 +654,7 @@ def main():
         "elasticity_64_f32": {"avg_launch_us": avg32 * 1e6, "elems_per_s": mesh.n_elems / avg32,
                               "alg_bytes": B32, "hbm_frac": B32 / avg32 / HBM_PEAK},
     }
+    record["secondary"]["poisson2d_32_f64"] = bench_poisson2d(dev, cpu=not args.no_cpu)
     record["secondary"]["boundary_64_f64"] = bench_boundary(dev, mesh, pat, coords, K, d, cpu=not args.no_cpu)
     record["secondary"]["poisson_96_pcg_time_to_1e-8"] = bench_pcg(dev)
     record["secondary"]["batched_256_f32"] = bench_batch(dev)
@@ -645,7 +662,6 @@ def main():
     record["secondary"]["ns_newton_cavity_32"] = bench_newton(dev, cpu=not args.no_cpu)
     record["secondary"]["transient_96"] = bench_transient(dev, cpu=not args.no_cpu)
     record["secondary"]["hex20_elasticity_24"] = bench_hex20(dev, cpu=not args.no_cpu)
-    record["secondary"]["cantilever_hex20_10x4x4"] = bench_cantilever(dev, cpu=not args.no_cpu)
     record["secondary"]["ns_newton_weak_cavity_32"] = bench_newton_weak(dev)
     if not args.no_cpu:
         log("[bench] timing the oracle on the host")

@@ -30,7 +30,7 @@ def build(force: bool = False) -> str:
     """Compile oracle.c into liboracle.so with gcc (plain -O2, no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -56,6 +56,8 @@ def _load():
     lib.or_assemble.restype = C.c_int
     lib.or_residual.argtypes = [P, C.c_int, P, P, P, P, P, C.c_int, P, P]
     lib.or_residual.restype = C.c_int
+    lib.or_assemble_colored.argtypes = [P, C.c_int, P, P, P, P, P, C.c_int, C.c_int, P, P, P, P]
+    lib.or_assemble_colored.restype = C.c_int
     lib.or_pcg_jacobi.argtypes = [i64, P, P, P, P, C.c_double, i64, P, P]
     lib.or_pcg_jacobi.restype = i64
     _lib = lib
@@ -155,6 +157,27 @@ def assemble(pat: Pattern, kind: int, params=None, elem_param=None, nodal_src=No
     if rc:
         raise RuntimeError(f"oracle assemble failed with code {rc}")
     return K, d
+
+
+def assemble_parallel(pat: Pattern, kind: int, params=None, elem_param=None, nodal_src=None, state=None,
+                      qpa: int = 2, threads: int = 1, want_K: bool = True):
+    """The same assembly as assemble() without constraints, element colour by element
+    colour on `threads` OpenMP threads (the timed CPU baseline).  Returns (K, d, threads
+    actually used)."""
+    lib = _load()
+    prm = _params(**(params or {}))
+    K = np.zeros(pat.nnz) if want_K else None
+    d = np.zeros(pat.n_rows)
+    bad = np.zeros(1, np.int64)
+    used = np.zeros(1, np.int32)
+    ep, ns, st = _opt(elem_param), _opt(nodal_src), _opt(state)
+    rc = lib.or_assemble_colored(pat._h, kind, _ptr(prm), _ptr(pat.mesh.coords), _ptr(ep), _ptr(ns), _ptr(st),
+                                 qpa, int(threads), _ptr(K), _ptr(d), _ptr(bad), _ptr(used))
+    if rc == ERR_BAD_JACOBIAN:
+        raise FloatingPointError(f"det J <= 0 in element {int(bad[0])}")
+    if rc:
+        raise RuntimeError(f"oracle parallel assemble failed with code {rc}")
+    return K, d, int(used[0])
 
 
 def residual(pat: Pattern, kind: int, params=None, elem_param=None, nodal_src=None, state=None,

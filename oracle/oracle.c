@@ -7,7 +7,9 @@
  *
  * Plain, sequential, FP64 C.  Every routine is the textbook definition of what it
  * computes, written out element by element and scattered in element-id order; no
- * blocking, fusion or reordering.  Sections cited are those of the paper:
+ * blocking, fusion or reordering.  One exception, for the timed CPU baseline only:
+ * or_assemble_colored runs the same element routine on all host cores, one element
+ * colour at a time (checked against or_assemble by the test suite).  Sections cited are those of the paper:
  *   Sec. 2.1        weak form as a sum of bilinear forms, numerical integration,
  *                   residual component d_a and tangent K = dd/dphi (Eqs. Newton-Raphson,
  *                   stiffness)
@@ -29,6 +31,7 @@
  *   - Dirichlet constraints: symmetric elimination keeping the sparsity structure.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -595,6 +598,150 @@ int or_assemble(void* h, int kind, const double* params, const double* coords,
         }
     }
     return OR_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The same assembly on all host cores, for the timed CPU baseline            */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Element colours: elements in id order, each taking the smallest colour that no
+ * element sharing one of its nodes has taken.  Two elements of one colour touch
+ * disjoint nodes, hence disjoint rows of K and d.  Returns the number of colours and
+ * fills color [n_el], or -1 on allocation failure.
+ */
+static int color_elements(const or_pattern* P, int32_t* color)
+{
+    int64_t nn = P->n_nodes, n_el = P->n_el;
+    int nen = P->nen;
+    int64_t* inc_ptr = (int64_t*)calloc((size_t)nn + 1, sizeof(int64_t));
+    int64_t* inc = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_el * nen + 1));
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nn + 1));
+    if (!inc_ptr || !inc || !fill) { free(inc_ptr); free(inc); free(fill); return -1; }
+    for (int64_t e = 0; e < n_el; ++e)
+        for (int a = 0; a < nen; ++a) ++inc_ptr[P->conn[a * n_el + e] + 1];
+    for (int64_t v = 0; v < nn; ++v) inc_ptr[v + 1] += inc_ptr[v];
+    memcpy(fill, inc_ptr, sizeof(int64_t) * (size_t)nn);
+    for (int64_t e = 0; e < n_el; ++e)
+        for (int a = 0; a < nen; ++a) inc[fill[P->conn[a * n_el + e]]++] = e;
+    int n_colors = 0;
+    for (int64_t e = 0; e < n_el; ++e) color[e] = -1;
+    for (int64_t e = 0; e < n_el; ++e) {
+        uint64_t used = 0; /* at most 64 colours (27 suffice for hexahedra) */
+        for (int a = 0; a < nen; ++a) {
+            int64_t v = P->conn[a * n_el + e];
+            for (int64_t k = inc_ptr[v]; k < inc_ptr[v + 1]; ++k) {
+                int32_t c = color[inc[k]];
+                if (c >= 0) used |= (uint64_t)1 << c;
+            }
+        }
+        int c = 0;
+        while (c < 64 && ((used >> c) & 1)) ++c;
+        if (c == 64) { free(inc_ptr); free(inc); free(fill); return -1; }
+        color[e] = c;
+        if (c + 1 > n_colors) n_colors = c + 1;
+    }
+    free(inc_ptr); free(inc); free(fill);
+    return n_colors;
+}
+
+/*
+ * or_assemble without constraints, on n_threads OpenMP threads: the elements of one
+ * colour at a time, each element computed and scattered exactly as in or_assemble.
+ * Within a colour no two elements share a row, so the adds need no synchronisation;
+ * the sums differ from the sequential ones only in the order of the (at most 8)
+ * element contributions to an entry.  Returns the status as or_assemble; *threads_used
+ * receives the number of threads that ran.
+ */
+int or_assemble_colored(void* h, int kind, const double* params, const double* coords,
+                        const double* elem_param, const double* nodal_src, const double* state,
+                        int qpa, int n_threads, double* K, double* d, int64_t* bad_elem,
+                        int* threads_used)
+{
+    const or_pattern* P = (const or_pattern*)h;
+    int dim = P->dim, nen = P->nen, nf = form_nf(kind, dim), ne = nen * nf;
+    int64_t nn = P->n_nodes, n_el = P->n_el;
+    if (nf != P->nf || n_threads < 1) return OR_ERR_ARG;
+    or_params prm = {params[0], params[1], params[2], params[3], params[4], params[5]};
+    int nsrc = (kind == OR_ELASTICITY) ? dim : 1;
+    int32_t* color = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_el + 1));
+    if (!color) return OR_ERR_OOM;
+    int n_colors = color_elements(P, color);
+    if (n_colors < 0) { free(color); return OR_ERR_OOM; }
+    int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_el + 1));
+    int64_t* cptr = (int64_t*)calloc((size_t)n_colors + 1, sizeof(int64_t));
+    if (!order || !cptr) { free(color); free(order); free(cptr); return OR_ERR_OOM; }
+    for (int64_t e = 0; e < n_el; ++e) ++cptr[color[e] + 1];
+    for (int c = 0; c < n_colors; ++c) cptr[c + 1] += cptr[c];
+    {
+        int64_t* at = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_colors + 1));
+        if (!at) { free(color); free(order); free(cptr); return OR_ERR_OOM; }
+        memcpy(at, cptr, sizeof(int64_t) * (size_t)n_colors);
+        for (int64_t e = 0; e < n_el; ++e) order[at[color[e]]++] = e;
+        free(at);
+    }
+    free(color);
+    if (K) memset(K, 0, sizeof(double) * (size_t)P->nnz);
+    memset(d, 0, sizeof(double) * (size_t)P->n_rows);
+    *bad_elem = -1;
+    int status = OR_OK;
+    int used = 1;
+    for (int c = 0; c < n_colors && status == OR_OK; ++c) {
+        int64_t c0 = cptr[c], c1 = cptr[c + 1];
+#pragma omp parallel num_threads(n_threads)
+        {
+#pragma omp single
+            used = omp_get_num_threads();
+            double* Ke = (double*)malloc(sizeof(double) * ne * ne);
+            int st = Ke ? OR_OK : OR_ERR_OOM;
+            int64_t bad = -1;
+#pragma omp for schedule(static)
+            for (int64_t k = c0; k < c1; ++k) {
+                if (st != OR_OK) continue;
+                int64_t e = order[k];
+                double x[OR_MAXNEN][OR_MAXDIM], U[OR_MAXNEN * OR_MAXNF], src[OR_MAXNEN * OR_MAXDIM];
+                double Re[OR_MAXNEN * OR_MAXNF];
+                int64_t node[OR_MAXNEN];
+                for (int a = 0; a < nen; ++a) {
+                    node[a] = P->conn[a * n_el + e];
+                    for (int m = 0; m < dim; ++m) x[a][m] = coords[m * nn + node[a]];
+                    for (int i = 0; i < nf; ++i) U[a * nf + i] = state ? state[i * nn + node[a]] : 0.0;
+                    for (int s2 = 0; s2 < nsrc; ++s2)
+                        src[a * nsrc + s2] = nodal_src ? nodal_src[s2 * nn + node[a]] : 0.0;
+                }
+                double cp = elem_param ? elem_param[e] : 1.0;
+                int rc = element(kind, dim, &prm, cp, x, U, nodal_src ? src : NULL, qpa, Re, Ke, K != NULL);
+                if (rc) {
+                    st = rc;
+                    if (rc == OR_ERR_BAD_JACOBIAN && (bad < 0 || e < bad)) bad = e;
+                    continue;
+                }
+                for (int a = 0; a < nen; ++a)
+                    for (int i = 0; i < nf; ++i) {
+                        int64_t r = dof_of(P, node[a], i);
+                        d[r] -= Re[a * nf + i];
+                        if (!K) continue;
+                        for (int b = 0; b < nen; ++b)
+                            for (int j = 0; j < nf; ++j) {
+                                int64_t pos = find_col(P, r, dof_of(P, node[b], j));
+                                if (pos >= 0) K[pos] += Ke[(a * nf + i) * ne + b * nf + j];
+                            }
+                    }
+            }
+            free(Ke);
+            if (st != OR_OK) {
+#pragma omp critical
+                {
+                    status = st;
+                    if (bad >= 0 && (*bad_elem < 0 || bad < *bad_elem)) *bad_elem = bad;
+                }
+            }
+        }
+    }
+    free(order);
+    free(cptr);
+    *threads_used = used;
+    return status;
 }
 
 /* Residual R(U) of a form (no constraints), [n_rows]; the Newton tangent K is dR/dU. */

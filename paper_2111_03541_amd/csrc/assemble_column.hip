@@ -14,7 +14,8 @@
 //            (a, e, half) contracts the four Gauss points of its half for the eight
 //            node pairs (a, b), b in e; the two halves are added across adjacent lanes
 //            and the blocks of the eight elements around a are summed into a per-node
-//            LDS row buffer (FP64 in both precisions).
+//            LDS row buffer (FP64 in both precisions).  The flow form has its own
+//            phase B on the matrix cores, described further down.
 // Each value of K is written exactly once, in CSR row order, with the Dirichlet
 // elimination applied on the way out.  The geometry of an element is computed once per
 // column that sees it (15 elements per 8 owned nodes per layer); the small cross-section
@@ -95,9 +96,10 @@ struct ColParams {
     double lam_f, mu_f;  // elasticity: lambda = E lam_f, mu = E mu_f (from nu, on the host)
 };
 
-// Row-buffer accumulators: FP64 for the symmetric forms in both precisions, FP32 for the
-// flow form (its 16-value blocks would not fit the LDS in FP64 next to the ring).
-template <int FORM>
+// Row-buffer accumulators: FP64 for the symmetric forms in both precisions (FP32 rows,
+// added with ds_add_f32, made the FP32 64^3 elasticity assembly 3.5x slower: 1,026 vs
+// 291 us), FP32 for the flow form, whose rows are updated without atomics.
+template <int FORM, typename T>
 using AccT = typename std::conditional<FORM == MF_FORM_NS_SUPG, float, double>::type;
 
 // value of the lane (lane ^ 1) or (lane ^ 2) of the same quad: DPP quad_perm [1,0,3,2]
@@ -147,8 +149,8 @@ struct ColShared {
     double x[3][kTileNodes][3];
     T u[3][kTileNodes][NSRC];
     double ep[2][kLayerElems];
-    alignas(16) AccT<FORM> rowK[NRB][kColNodes][27 * NB];
-    AccT<FORM> rowD[NRB][kColNodes][NF];
+    alignas(16) AccT<FORM, T> rowK[NRB][kColNodes][27 * NB];
+    AccT<FORM, T> rowD[NRB][kColNodes][NF];
     // flow form: per wave, the coefficient tiles of two (node, element) pairs, [pair][q]
     // tiles of [16][4] values, each padded to kNsTile floats (spreads the LDS banks)
     alignas(16) float dt[NS ? kThreads / 64 : 1][NS ? 2 * 8 * kNsTile : 1];
@@ -421,7 +423,7 @@ template <int FORM, typename T>
 __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>& S, int kz, int i0, int j0)
 {
     constexpr int NF = FormTraits<FORM, 3>::NF;
-    using Acc = AccT<FORM>;
+    using Acc = AccT<FORM, T>;
     static_assert(FORM != MF_FORM_NS_SUPG, "the flow form has its own phase B");
     constexpr int NV = FORM == MF_FORM_ELASTICITY ? 9 : 1;
     const int tid = threadIdx.x;
@@ -539,7 +541,7 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
     constexpr int NB = NF * NF;
     constexpr int kNodeVals = 27 * NB;
     constexpr int NCH = (kNodeVals + 63) / 64;
-    using Acc = AccT<FORM>;
+    using Acc = AccT<FORM, T>;
     T* K = (T*)p.K;
     T* d = (T*)p.d;
     const int nn = p.n_nodes;

@@ -317,3 +317,25 @@ def test_pcg_jacobi_matches_direct_solve():
     # maxit reached -> -1 and the true residual of the last iterate
     _, it2, rel2 = O.pcg_jacobi(pat.row_ptr, pat.col_idx, K, d, tol=1e-10, maxit=3)
     assert it2 == -1 and rel2 > 1e-10
+
+
+def test_colour_parallel_assembly_matches_sequential():
+    """The all-core oracle (element colour by colour on OpenMP threads) against the
+    sequential one on a jittered elasticity mesh and a flow Jacobian: same K and d up to
+    the order of the at most 8 contributions per entry."""
+    import os
+    from helpers import rowscaled_error, vec_error
+    threads = max(1, min(8, len(os.sched_getaffinity(0))))
+    for kind, nf, n in ((O.ELASTICITY, 3, (9, 7, 6)), (O.NS_SUPG, 4, (5, 4, 4))):
+        mesh = W.structured_mesh(n, jitter=0.15, seed=3)
+        pat = O.Pattern(mesh, nf)
+        if kind == O.ELASTICITY:
+            kw = dict(params={"coef": 1.0, "nu": 0.3}, elem_param=W.lognormal_elem(mesh.n_elems, 0.5, 1),
+                      nodal_src=W.uniform_nodal(3, mesh.n_nodes, -1, 1, 2))
+        else:
+            st = np.vstack([W.fourier_velocity(mesh.coords, 4), W.uniform_nodal(1, mesh.n_nodes, -0.5, 0.5, 5)])
+            kw = dict(params={"rho": 1.0, "mu": 0.01, "tau_m": 0.02, "tau_c": 0.05}, state=st)
+        K1, d1 = O.assemble(pat, kind, **kw)
+        K2, d2, used = O.assemble_parallel(pat, kind, threads=threads, **kw)
+        assert used == threads
+        assert rowscaled_error(pat, K2, K1) <= 1e-13 and vec_error(d2, d1) <= 1e-13
