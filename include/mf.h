@@ -1,8 +1,9 @@
 /*
  * mf.h - C ABI of the MI355X finite-element assembly library (libmf.so).
  *
- * The library assembles the sparse linear system K x = d of a weak form on a Q1 mesh
- * (MetaFEM, arXiv 2111.03541).  Sec. 1 of the paper states that K x = d is fixed by
+ * The library assembles the sparse linear system K x = d of a weak form on a mesh of
+ * linear (4-node quadrilateral, 8-node hexahedron) or quadratic (8-node quadrilateral,
+ * 20-node hexahedron, 10-node tetrahedron) elements (MetaFEM, arXiv 2111.03541).  Sec. 1 of the paper states that K x = d is fixed by
  * six inputs: the weak forms, their linearisation, the element type and order, the
  * quadrature, the time scheme and the numbering of the unknowns.  These become the
  * arguments below.  The time scheme is steady here, so the time coefficient of the
@@ -99,7 +100,9 @@ typedef struct mf_pattern_s mf_pattern_t;   /* opaque, library-owned */
  *   N(v) = sorted set of nodes sharing an element with node v (v included).
  *   Row dof(v,i) holds columns dof(w,j) for w in N(v) and coupling(i,j), ascending.
  *   rank[(a*nen+b)*n_elems + e] = position of conn[b][e] in N(conn[a][e]).
- * order must be 1.  Runs on `stream` and synchronises it (sync); allocates the
+ * order must match the element type: 1 for MF_QUAD4 and MF_HEX8, 2 for MF_QUAD8,
+ * MF_HEX20 and MF_TET10 (MF_ERR_UNSUPPORTED otherwise).  Runs on `stream` and
+ * synchronises it (sync); allocates the
  * pattern's device arrays.  Errors: MF_ERR_ARG, MF_ERR_BAD_MESH (node id out of
  * range), MF_ERR_OVERFLOW (nnz or nen*n_elems >= 2^31, or more than 255 neighbours of
  * one node), MF_ERR_OOM, MF_ERR_HIP.  *out is NULL on error.
@@ -324,12 +327,16 @@ typedef struct {
  * edges: face_id 2 * axis + side as for hexahedra, 2 or 3 Gauss points along the edge,
  * 1 or 2 fields, sigma^l the leading 2x2 block of value[0..9)); MF_ERR_UNSUPPORTED
  * otherwise.
- * Async on the stream.  Reported by
+ * Queued on the stream (after one synchronisation that sizes the face buckets).  Reported by
  * mf_status_poll (until the next mf_assemble clears the status): a face whose element id
  * or local face is out of range (skipped; MF_ERR_ARG with the first such face), and a
  * degenerate face (zero area) or element (det J <= 0, flux form; MF_ERR_BAD_JACOBIAN).
  * Errors: MF_ERR_ARG (a form/field-count mismatch or bad arguments), MF_ERR_UNSUPPORTED
- * (not a 3D hex pattern), MF_ERR_HIP.
+ * (an element type the boundary kernels do not cover, or the flux and flow forms on
+ * anything but 8-node hexahedra), MF_ERR_HIP.  Faces are scattered in buckets of
+ * (colour of the face's element, local face), one launch per non-empty bucket, so two
+ * calls with the same inputs give the same bits; the call synchronises the stream once
+ * to size the buckets.
  */
 mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform* form, const double* coords,
                                int64_t n_faces, const int32_t* face_elem, const uint8_t* face_id,
@@ -498,7 +505,9 @@ mf_status mf_ns_newton_ex(const mf_pattern_t* P, const mf_form* form, const doub
  *   y_l = conv(conv(conv(R^l v))) (1 -> c_l -> c_l -> 1), R full weighting, P = R^T,
  *   3x3x3 kernels, zero padding, no bias; z = 0 on Dirichlet rows.
  * Weights and activations are BF16, accumulation FP32; parameters are kept in FP32 for
- * the optimiser.  Training minimises |K z - r|^2 / |r|^2 with Adam.
+ * the optimiser.  Training (Adam) minimises either the residual loss |K z - r|^2 / |r|^2
+ * or the energy-norm error of z (mf_nn_train_step); the shipped weights were trained
+ * with the energy loss.
  * ------------------------------------------------------------------------------------ */
 
 /* grid (host) [3] = node counts (nx, ny, nz), odd and >= 3 on every level but the last;
@@ -529,6 +538,17 @@ mf_status mf_nn_apply(mf_nn_t* net, const double* r, double* z, void* stream);
    (host) receives the loss.  (sync) */
 mf_status mf_nn_train_step(mf_nn_t* net, const double* r, const double* e, double lr, double* loss,
                            float* grad, void* stream);
+
+/* Checkpoint of training (the resumable state: parameters, both Adam moment vectors, the
+   step count that sets Adam's bias corrections, the seed of the initial weights, and the
+   architecture).  mf_nn_checkpoint_size gives the byte count; mf_nn_save copies the state
+   into buf (host, at least that many bytes); mf_nn_load restores it into a network of the
+   same grid, levels and channels (MF_ERR_ARG otherwise), after which training continues
+   exactly as it would have without the interruption.  The training data is the caller's:
+   a caller that draws its systems from the step count resumes them too.  (sync) */
+mf_status mf_nn_checkpoint_size(const mf_nn_t* net, int64_t* bytes);
+mf_status mf_nn_save(const mf_nn_t* net, void* buf, int64_t bytes);
+mf_status mf_nn_load(mf_nn_t* net, const void* buf, int64_t bytes);
 
 void mf_nn_destroy(mf_nn_t* net);
 

@@ -126,7 +126,7 @@ EXPORTS = [
     "mf_batch_create", "mf_batch_tune", "mf_batch_run", "mf_batch_info", "mf_batch_destroy",
     "mf_nn_create", "mf_nn_params", "mf_nn_set_system", "mf_nn_apply", "mf_nn_train_step", "mf_nn_destroy", "mf_spmv",
     "mf_bicgstab", "mf_ns_newton", "mf_ns_newton_ex", "mf_assemble_boundary", "mf_heat_transient",
-    "mf_pcg_noalloc", "mf_pcg_noalloc_max_rows",
+    "mf_pcg_noalloc", "mf_pcg_noalloc_max_rows", "mf_nn_checkpoint_size", "mf_nn_save", "mf_nn_load",
 ]
 
 
@@ -156,6 +156,9 @@ def load():
     lib.mf_pcg_noalloc.argtypes = [C.POINTER(_CSR), P, P, C.POINTER(_PcgOpts), C.POINTER(_PcgResult), P]
     lib.mf_pcg_noalloc_max_rows.argtypes = []
     lib.mf_pcg_noalloc_max_rows.restype = i64
+    lib.mf_nn_checkpoint_size.argtypes = [P, C.POINTER(i64)]
+    lib.mf_nn_save.argtypes = [P, P, i64]
+    lib.mf_nn_load.argtypes = [P, P, i64]
     lib.mf_batch_create.argtypes = [C.POINTER(_BatchProblem), i32, C.c_int, C.POINTER(P)]
     lib.mf_batch_tune.argtypes = [P, C.c_char_p, P]
     lib.mf_batch_run.argtypes = [P, P]
@@ -493,14 +496,41 @@ class Net:
                                       _stream(stream)))
         return loss.value, g
 
-    def save(self, path):
+    def save(self, path, trained_with=None):
+        """Parameters to path.npy and the architecture (and, when given, how the weights
+        were trained) to path.json."""
         import json
         self._np.save(path + ".npy", self.get_params())
+        meta = {"grid": self.grid, "channels": self.channels, "n_params": self.n_params}
+        if trained_with:
+            meta["trained_with"] = trained_with
         with open(path + ".json", "w") as f:
-            json.dump({"grid": self.grid, "channels": self.channels, "n_params": self.n_params}, f)
+            json.dump(meta, f)
 
     def load_params(self, path):
         self.set_params(self._np.load(path + ".npy"))
+
+    def checkpoint(self):
+        """The training state (mf_nn_save) as bytes."""
+        lib = load()
+        n = C.c_int64()
+        check(lib.mf_nn_checkpoint_size(self._h, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        check(lib.mf_nn_save(self._h, buf, n.value))
+        return buf.raw
+
+    def restore(self, data: bytes):
+        """Restore a training state made by checkpoint() (mf_nn_load)."""
+        buf = C.create_string_buffer(data, len(data))
+        check(load().mf_nn_load(self._h, buf, len(data)))
+
+    def save_checkpoint(self, path):
+        with open(path, "wb") as f:
+            f.write(self.checkpoint())
+
+    def load_checkpoint(self, path):
+        with open(path, "rb") as f:
+            self.restore(f.read())
 
 
 def pcg(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PRECOND_JACOBI, net=None,

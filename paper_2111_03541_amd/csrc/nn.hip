@@ -634,6 +634,7 @@ struct mf_nn_s {
     float* m = nullptr;
     float* v = nullptr;
     int step = 0;
+    uint64_t seed = 0;  // of the initial weights (recorded in checkpoints)
     // activations
     mf::bf16* vin[mf::kMaxLevels] = {nullptr};
     mf::bf16* h1[mf::kMaxLevels] = {nullptr};
@@ -866,6 +867,7 @@ mf_status mf_nn_create(const int32_t* grid, int32_t levels, const int32_t* chann
     if (channels[0] != 1) return set_error(MF_ERR_ARG, "channels[0] must be 1 (the level-0 stencil)");
     mf_nn_s* N = new mf_nn_s();
     N->L = levels;
+    N->seed = seed;
     N->g[0] = Grid{grid[0], grid[1], grid[2]};
     for (int l = 0; l < levels; ++l) {
         const int c = channels[l];
@@ -1048,6 +1050,69 @@ mf_status mf_nn_train_step(mf_nn_t* N, const double* r, const double* e, double 
         k_round_bf16<<<(N->n_params + 255) / 256, 256, 0, s>>>(N->p, N->pb, N->n_params);
         MF_HIP(hipGetLastError());
     }
+    return MF_OK;
+}
+
+// Checkpoint layout (host bytes, little endian): header of 16 int64 words
+//   [0] magic "MFNNCKP1", [1] n_params, [2] step, [3] seed, [4] levels,
+//   [5..7] node grid, [8..8+levels) channels, rest zero;
+// then the FP32 parameters, the first Adam moments and the second Adam moments.
+namespace {
+constexpr int64_t kCkpMagic = 0x31504B434E4E464DLL;  // "MFNNCKP1"
+constexpr int kCkpHeader = 16;
+int64_t ckp_bytes(const mf_nn_s* N) { return (int64_t)sizeof(int64_t) * kCkpHeader + 3 * (int64_t)sizeof(float) * N->n_params; }
+}  // namespace
+
+mf_status mf_nn_checkpoint_size(const mf_nn_t* N, int64_t* bytes)
+{
+    if (!N || !bytes) return set_error(MF_ERR_ARG, "NULL argument");
+    *bytes = ckp_bytes(N);
+    return MF_OK;
+}
+
+mf_status mf_nn_save(const mf_nn_t* N, void* buf, int64_t bytes)
+{
+    if (!N || !buf) return set_error(MF_ERR_ARG, "NULL argument");
+    if (bytes < ckp_bytes(N)) return set_error(MF_ERR_ARG, "checkpoint buffer of %lld bytes, %lld needed",
+                                               (long long)bytes, (long long)ckp_bytes(N));
+    int64_t* h = (int64_t*)buf;
+    for (int k = 0; k < kCkpHeader; ++k) h[k] = 0;
+    h[0] = kCkpMagic;
+    h[1] = N->n_params;
+    h[2] = N->step;
+    h[3] = (int64_t)N->seed;
+    h[4] = N->L;
+    h[5] = N->g[0].nx;
+    h[6] = N->g[0].ny;
+    h[7] = N->g[0].nz;
+    for (int l = 0; l < N->L; ++l) h[8 + l] = N->ch[l];
+    float* f = (float*)(h + kCkpHeader);
+    MF_HIP(hipDeviceSynchronize());
+    MF_HIP(hipMemcpy(f, N->p, sizeof(float) * N->n_params, hipMemcpyDeviceToHost));
+    MF_HIP(hipMemcpy(f + N->n_params, N->m, sizeof(float) * N->n_params, hipMemcpyDeviceToHost));
+    MF_HIP(hipMemcpy(f + 2 * (int64_t)N->n_params, N->v, sizeof(float) * N->n_params, hipMemcpyDeviceToHost));
+    return MF_OK;
+}
+
+mf_status mf_nn_load(mf_nn_t* N, const void* buf, int64_t bytes)
+{
+    if (!N || !buf) return set_error(MF_ERR_ARG, "NULL argument");
+    if (bytes < (int64_t)sizeof(int64_t) * kCkpHeader) return set_error(MF_ERR_ARG, "checkpoint too short");
+    const int64_t* h = (const int64_t*)buf;
+    if (h[0] != kCkpMagic) return set_error(MF_ERR_ARG, "not a network checkpoint");
+    bool same = h[1] == N->n_params && h[4] == N->L && h[5] == N->g[0].nx && h[6] == N->g[0].ny && h[7] == N->g[0].nz;
+    for (int l = 0; same && l < N->L; ++l) same = h[8 + l] == N->ch[l];
+    if (!same) return set_error(MF_ERR_ARG, "checkpoint of a different network (grid, levels or channels)");
+    if (bytes < ckp_bytes(N)) return set_error(MF_ERR_ARG, "checkpoint truncated");
+    const float* f = (const float*)(h + kCkpHeader);
+    MF_HIP(hipDeviceSynchronize());
+    MF_HIP(hipMemcpy(N->p, f, sizeof(float) * N->n_params, hipMemcpyHostToDevice));
+    MF_HIP(hipMemcpy(N->m, f + N->n_params, sizeof(float) * N->n_params, hipMemcpyHostToDevice));
+    MF_HIP(hipMemcpy(N->v, f + 2 * (int64_t)N->n_params, sizeof(float) * N->n_params, hipMemcpyHostToDevice));
+    N->step = (int)h[2];
+    N->seed = (uint64_t)h[3];
+    k_round_bf16<<<(N->n_params + 255) / 256, 256>>>(N->p, N->pb, N->n_params);
+    MF_HIP(hipDeviceSynchronize());
     return MF_OK;
 }
 

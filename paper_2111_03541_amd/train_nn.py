@@ -73,8 +73,16 @@ class PoissonFamily:
         return sigma
 
 
+def checkpoint_step(path):
+    """Training step recorded in a checkpoint file (header word 2, see mf_nn_save)."""
+    return int(np.fromfile(path, dtype=np.int64, count=3)[2])
+
+
 def train(n=96, n_systems=2000, channels=None, lr=2e-3, pool=64, seed=0, log_every=100, dev=None,
-          net=None, epochs=1):
+          net=None, epochs=1, checkpoint=None, checkpoint_every=0, resume=None):
+    """Train on n_systems systems per epoch.  The system and the error of global step k
+    are functions of k alone, so a run resumed from a checkpoint (parameters, Adam state
+    and step, mf_nn_save) continues exactly where the interrupted one stopped."""
     import torch
     import paper_2111_03541_amd as mf
     import workloads as W
@@ -85,12 +93,19 @@ def train(n=96, n_systems=2000, channels=None, lr=2e-3, pool=64, seed=0, log_eve
     fam = PoissonFamily(n, dev, pool=pool, seed=seed)
     if net is None:
         net = mf.Net((nn_nodes,) * 3, channels, seed=seed + 1)
+    start = 0
+    if resume:
+        net.load_checkpoint(resume)
+        start = checkpoint_step(resume)
     mask = fam.mask_np != 0
     hist = []
     t0 = time.perf_counter()
     step = 0
     for ep in range(epochs):
         for s in range(n_systems):
+            if step < start:
+                step += 1
+                continue
             fam.system(s)
             net.set_system(fam.rp, fam.ci, fam.K, fam.mask)
             e_np = W.multiscale_nodal(nn_nodes, len(channels), 1_000_000 + ep * n_systems + s)
@@ -101,6 +116,8 @@ def train(n=96, n_systems=2000, channels=None, lr=2e-3, pool=64, seed=0, log_eve
             loss = net.train_step(r, cur_lr, e=e)
             hist.append(loss)
             step += 1
+            if checkpoint and checkpoint_every and step % checkpoint_every == 0:
+                net.save_checkpoint(checkpoint)
             if log_every and step % log_every == 0:
                 print(f"[train] step {step} loss {np.mean(hist[-log_every:]):.4f} "
                       f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
@@ -144,14 +161,20 @@ def main():
     ap.add_argument("--channels", type=str, default=",".join(map(str, DEFAULT_CHANNELS)))
     ap.add_argument("--out", type=str, default=None)
     ap.add_argument("--eval", type=int, default=3)
+    ap.add_argument("--checkpoint", type=str, default=None, help="training-state file written every --every steps")
+    ap.add_argument("--every", type=int, default=500)
+    ap.add_argument("--resume", type=str, default=None, help="continue from this training-state file")
     args = ap.parse_args()
     net, hist, fam = train(args.n, args.systems, [int(v) for v in args.channels.split(",")], args.lr,
-                           args.pool, epochs=args.epochs)
+                           args.pool, epochs=args.epochs, checkpoint=args.checkpoint, checkpoint_every=args.every,
+                           resume=args.resume)
     res = compare(net, fam, [10_000 + i for i in range(args.eval)])
-    print(json.dumps({"final_loss": float(np.mean(hist[-100:])), "eval": res}), flush=True)
+    print(json.dumps({"final_loss": float(np.mean(hist[-100:])) if hist else None, "eval": res}), flush=True)
     if args.out:
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
-        net.save(args.out)
+        net.save(args.out, trained_with={"command": " ".join(["python -m paper_2111_03541_amd.train_nn"] + sys.argv[1:]),
+                                         "n": args.n, "systems": args.systems, "epochs": args.epochs, "lr": args.lr,
+                                         "pool": args.pool, "loss": "energy norm", "seed": 0})
 
 
 if __name__ == "__main__":

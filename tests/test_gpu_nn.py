@@ -240,3 +240,35 @@ def test_broken_network_falls_back_to_jacobi(mf, bad):
     assert abs(res["iterations"] - it_j) <= max(2, 0.02 * it_j)
     S = pat.to_scipy(K)
     assert np.linalg.norm(d - S @ x.cpu().numpy()) / np.linalg.norm(d) <= 1e-8
+
+
+def test_checkpoint_resumes_training_exactly(mf, tmp_path):
+    """Train 10 steps, checkpoint (parameters, Adam moments, step, seed), train 10 more;
+    a fresh network restored from the checkpoint and trained on the same 10 systems ends
+    with bitwise the same parameters.  A checkpoint of another architecture is refused."""
+    say("nn checkpoint")
+    pat, K, d, mask = system(16, 41)
+    S = pat.to_scipy(K)
+    es = [W.multiscale_nodal(17, len(CH), 60 + k) * (mask == 0) for k in range(4)]
+    rs = [torch.from_numpy(S @ e).cuda() for e in es]
+    es = [torch.from_numpy(e).cuda() for e in es]
+    net = mf.Net((17, 17, 17), CH, seed=9)
+    bind(mf, net, pat, K, mask)
+    for it in range(10):
+        net.train_step(rs[it % 4], 3e-3, e=es[it % 4])
+    path = str(tmp_path / "net.ckp")
+    net.save_checkpoint(path)
+    for it in range(10, 20):
+        net.train_step(rs[it % 4], 3e-3, e=es[it % 4])
+    a = net.get_params()
+    net2 = mf.Net((17, 17, 17), CH, seed=123)
+    bind(mf, net2, pat, K, mask)
+    assert not np.array_equal(net2.get_params(), a)
+    net2.load_checkpoint(path)
+    for it in range(10, 20):
+        net2.train_step(rs[it % 4], 3e-3, e=es[it % 4])
+    b = net2.get_params()
+    assert np.array_equal(a, b)
+    net3 = mf.Net((17, 17, 17), [1, 4, 8], seed=1)
+    with pytest.raises(mf.MFError):
+        net3.load_checkpoint(path)
