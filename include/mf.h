@@ -212,11 +212,20 @@ typedef struct {
 mf_status mf_batch_create(const mf_batch_problem* problems /* (host) [n] */, int32_t n,
                           mf_precision precision, mf_batch_t** out);
 
-/* (sync) Autotuner: times each candidate launch shape (work-item order: problem-major,
-   round-robin, elasticity-first; workgroups per CU: 1, 2, 4) on the batch itself and
-   keeps the fastest.  cache_path (host string, may be NULL) is a text file of tuned
-   choices keyed by device, precision, problem mix and size bucket: a hit skips timing. */
+/* (sync) Autotuner, timing candidates on the batch itself.  First the tile shape per class
+   of problems, a class being (form: mass/Poisson or elasticity) x (size bucket of the
+   column height NZ = nz + 1: <= 20, <= 34, larger): a tile is a 4x2 node column cut along
+   z into 1..4 chunks, and the chunk count of each class is chosen by coordinate descent.
+   Then the launch shape for those tiles (work-item order: problem-major, round-robin,
+   elasticity-first; workgroups per CU: 1, 2).  cache_path (host string, may be NULL) is a
+   text file of tuned choices keyed by device, precision, problems per class and column
+   count: a hit skips timing. */
 mf_status mf_batch_tune(mf_batch_t* batch, const char* cache_path, void* stream);
+
+/* (sync) Tile shapes: *n_classes (6) classes ordered (form: 0 mass/Poisson, 1 elasticity)
+   x (size bucket 0..2); problems[c] (host, may be NULL) the number of problems in class c;
+   chunks[c] (host, may be NULL) the chunks per column (tile height NZ / chunks). */
+mf_status mf_batch_tiles(const mf_batch_t* batch, int32_t* n_classes, int32_t* problems, int32_t* chunks);
 
 /* One persistent launch assembling every problem (K and d overwritten; device status
    words of all patterns reset first).  On a non-default stream the launch is captured

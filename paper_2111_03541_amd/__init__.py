@@ -127,6 +127,7 @@ EXPORTS = [
     "mf_nn_create", "mf_nn_params", "mf_nn_set_system", "mf_nn_apply", "mf_nn_train_step", "mf_nn_destroy", "mf_spmv",
     "mf_bicgstab", "mf_ns_newton", "mf_ns_newton_ex", "mf_assemble_boundary", "mf_heat_transient",
     "mf_pcg_noalloc", "mf_pcg_noalloc_max_rows", "mf_nn_checkpoint_size", "mf_nn_save", "mf_nn_load",
+    "mf_batch_tiles",
 ]
 
 
@@ -157,6 +158,7 @@ def load():
     lib.mf_pcg_noalloc_max_rows.argtypes = []
     lib.mf_pcg_noalloc_max_rows.restype = i64
     lib.mf_nn_checkpoint_size.argtypes = [P, C.POINTER(i64)]
+    lib.mf_batch_tiles.argtypes = [P, C.POINTER(i32), P, P]
     lib.mf_nn_save.argtypes = [P, P, i64]
     lib.mf_nn_load.argtypes = [P, P, i64]
     lib.mf_batch_create.argtypes = [C.POINTER(_BatchProblem), i32, C.c_int, C.POINTER(P)]
@@ -430,8 +432,14 @@ class Batch:
         n, wg, order, graphed, us = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
         check(load().mf_batch_info(self._h, C.byref(n), C.byref(wg), C.byref(order), C.byref(graphed),
                                    C.byref(us)))
+        nc = C.c_int32()
+        probs, chunks = (C.c_int32 * 8)(), (C.c_int32 * 8)()
+        check(load().mf_batch_tiles(self._h, C.byref(nc), probs, chunks))
+        names = ["poisson", "elasticity"]
+        tiles = {f"{names[c // 3]}/bucket{c % 3}": {"problems": probs[c], "chunks": chunks[c]}
+                 for c in range(nc.value) if probs[c] > 0}
         return {"items": n.value, "workgroups": wg.value, "order": order.value, "graphed": bool(graphed.value),
-                "tuned_us": us.value}
+                "tuned_us": us.value, "tiles": tiles}
 
 
 class Net:

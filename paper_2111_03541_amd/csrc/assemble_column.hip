@@ -1148,9 +1148,17 @@ mf_status dispatch(const AssembleArgs& A)
 }  // namespace
 
 // ---------------- batched launch: host side ----------------
-// Each problem is one item per column (the whole column height in one workgroup).
+// A work item is one tile of a problem: a node column of the cross-section, cut along z
+// into a number of chunks (the tile height) that the autotuner chooses per (form, size)
+// class of problems.
 
-int64_t batch_units_of(const mf_pattern_s* P) { return column_count(P); }
+int64_t batch_units_of(const mf_pattern_s* P, int chunks)
+{
+    const int NZ = (int)P->gz + 1;
+    const int c = std::max(1, std::min(chunks, NZ));
+    const int lz = (NZ + c - 1) / c;
+    return column_count(P) * ((NZ + lz - 1) / lz);
+}
 
 mf_status batch_check(const AssembleArgs& A)
 {
@@ -1162,18 +1170,23 @@ mf_status batch_check(const AssembleArgs& A)
     return MF_OK;
 }
 
-mf_status batch_upload(const std::vector<AssembleArgs>& probs, void** dev_probs, void** dev_status)
+mf_status batch_upload(const std::vector<AssembleArgs>& probs, const std::vector<int>& chunks, void** dev_probs,
+                       void** dev_status)
 {
     std::vector<BatchProblemDev> h(probs.size());
     std::vector<unsigned long long*> st(probs.size());
     for (size_t k = 0; k < probs.size(); ++k) {
         h[k].cp = make_params(probs[k]);
+        // tile height: the column of NZ node layers in `chunks` work items
+        const int NZ = h[k].cp.nz + 1;
+        const int c = std::max(1, std::min(chunks[k], NZ));
+        h[k].cp.lz = (NZ + c - 1) / c;
         h[k].kind = probs[k].form->kind;
         st[k] = probs[k].P->status;
     }
-    MF_HIP(hipMalloc(dev_probs, sizeof(BatchProblemDev) * (h.size() > 0 ? h.size() : 1)));
+    if (!*dev_probs) MF_HIP(hipMalloc(dev_probs, sizeof(BatchProblemDev) * (h.size() > 0 ? h.size() : 1)));
     MF_HIP(hipMemcpy(*dev_probs, h.data(), sizeof(BatchProblemDev) * h.size(), hipMemcpyHostToDevice));
-    MF_HIP(hipMalloc(dev_status, sizeof(void*) * (st.size() > 0 ? st.size() : 1)));
+    if (!*dev_status) MF_HIP(hipMalloc(dev_status, sizeof(void*) * (st.size() > 0 ? st.size() : 1)));
     MF_HIP(hipMemcpy(*dev_status, st.data(), sizeof(void*) * st.size(), hipMemcpyHostToDevice));
     return MF_OK;
 }

@@ -1,6 +1,8 @@
 // Batched assembly of many structured problems in one persistent launch, replayed as a
-// HIP graph, with a small autotuner for the launch shape (workgroup count and work-item
-// order).  The per-problem offsets play the role of the paper's workpiece offsets
+// HIP graph, with a small autotuner for the tile shape and the launch shape.  A tile is a
+// 4x2 node column of a problem cut along z into chunks; the tuner chooses the number of
+// chunks (the tile height) per class of problems, a class being (form, size bucket of the
+// column height), then the work-item order and the workgroup count.  The per-problem offsets play the role of the paper's workpiece offsets
 // n_dense / n_sp (Sec. 2.2 B-2): every problem keeps its own CSR and vector, located by
 // the pointers in its descriptor.
 #include <hip/hip_runtime.h>
@@ -17,15 +19,23 @@
 
 #include "mf_internal.h"
 
+// tile-shape classes: (form, size bucket of the column height NZ = nz + 1)
+constexpr int kBuckets = 3;            // NZ <= 20, NZ <= 34, larger
+constexpr int kClasses = 2 * kBuckets; // Poisson / mass, elasticity
+constexpr int kMaxChunks = 4;          // tile heights tried: NZ / 1 .. NZ / 4
+
 struct mf_batch_s {
     std::vector<mf::AssembleArgs> probs;
     std::vector<mf_form> forms;
-    std::vector<int64_t> units;  // work items (columns) per problem
+    std::vector<int64_t> units;  // work items (tiles) per problem
+    std::vector<int> cls;        // class of each problem
+    int chunks[kClasses] = {1, 1, 1, 1, 1, 1};
     mf_precision prec = MF_F64;
     void* dprobs = nullptr;
     void* dstatus = nullptr;
     int* counter = nullptr;
     int2* items = nullptr;
+    int64_t items_cap = 0;
     int n_items = 0;
     int n_wg = 0;
     int order = 1;
@@ -39,6 +49,13 @@ struct mf_batch_s {
 namespace {
 
 using namespace mf;
+
+int class_of(const mf_form& f, const mf_pattern_s* P)
+{
+    const int NZ = (int)P->gz + 1;
+    const int bucket = NZ <= 20 ? 0 : (NZ <= 34 ? 1 : 2);
+    return (f.kind == MF_FORM_ELASTICITY ? kBuckets : 0) + bucket;
+}
 
 void drop_graph(mf_batch_s* B)
 {
@@ -86,10 +103,26 @@ std::vector<int2> build_items(const mf_batch_s* B, int order)
     return it;
 }
 
+// descriptors (tile heights) and the item list for the current shapes and `order`
 mf_status upload_items(mf_batch_s* B, int order)
 {
+    std::vector<int> ch(B->probs.size());
+    for (size_t k = 0; k < B->probs.size(); ++k) {
+        ch[k] = B->chunks[B->cls[k]];
+        B->units[k] = batch_units_of(B->probs[k].P, ch[k]);
+    }
+    MF_HIP(hipDeviceSynchronize());  // a launch in flight may still read the old lists
+    mf_status st = batch_upload(B->probs, ch, &B->dprobs, &B->dstatus);
+    if (st != MF_OK) return st;
     std::vector<int2> it = build_items(B, order);
-    if (!B->items) MF_HIP(hipMalloc(&B->items, sizeof(int2) * (it.size() > 0 ? it.size() : 1)));
+    if (B->items && (int64_t)it.size() > B->items_cap) {
+        (void)hipFree(B->items);
+        B->items = nullptr;
+    }
+    if (!B->items) {
+        B->items_cap = (int64_t)(it.size() > 0 ? it.size() : 1);
+        MF_HIP(hipMalloc(&B->items, sizeof(int2) * B->items_cap));
+    }
     MF_HIP(hipMemcpy(B->items, it.data(), sizeof(int2) * it.size(), hipMemcpyHostToDevice));
     B->n_items = (int)it.size();
     B->order = order;
@@ -99,18 +132,24 @@ mf_status upload_items(mf_batch_s* B, int order)
 
 std::string tune_key(const mf_batch_s* B)
 {
-    int n_el = 0;
-    for (auto& f : B->forms) n_el += f.kind == MF_FORM_ELASTICITY;
-    // bucket the item count to two significant digits
-    double lg = std::floor(std::log10(std::max(1, B->n_items)));
-    long bucket = (long)(std::round(B->n_items / std::pow(10.0, lg - 1)) * std::pow(10.0, lg - 1));
+    int per[kClasses] = {0};
+    int64_t cols = 0;
+    for (size_t k = 0; k < B->probs.size(); ++k) {
+        ++per[B->cls[k]];
+        cols += batch_units_of(B->probs[k].P, 1);
+    }
+    // bucket the column count to two significant digits
+    double lg = std::floor(std::log10((double)std::max<int64_t>(1, cols)));
+    long bucket = (long)(std::round(cols / std::pow(10.0, lg - 1)) * std::pow(10.0, lg - 1));
     std::ostringstream os;
-    os << "gfx950|column-v1|prec=" << (B->prec == MF_F64 ? "f64" : "f32") << "|problems=" << B->probs.size()
-       << "|elasticity=" << n_el << "|items~" << bucket;
+    os << "gfx950|column-v2|prec=" << (B->prec == MF_F64 ? "f64" : "f32") << "|classes=";
+    for (int c = 0; c < kClasses; ++c) os << per[c] << (c + 1 < kClasses ? "," : "");
+    os << "|columns~" << bucket;
     return os.str();
 }
 
-bool cache_lookup(const char* path, const std::string& key, int* order, int* mult, double* us)
+// cache line: key order mult us chunks[0..kClasses)
+bool cache_lookup(const char* path, const std::string& key, int* order, int* mult, double* us, int* chunks)
 {
     if (!path) return false;
     std::ifstream f(path);
@@ -121,16 +160,20 @@ bool cache_lookup(const char* path, const std::string& key, int* order, int* mul
         int o, m;
         double u;
         if (is >> k >> o >> m >> u && k == key) {
+            int c[kClasses];
+            for (int j = 0; j < kClasses; ++j)
+                if (!(is >> c[j]) || c[j] < 1 || c[j] > kMaxChunks) return false;
             *order = o;
             *mult = m;
             *us = u;
+            for (int j = 0; j < kClasses; ++j) chunks[j] = c[j];
             return true;
         }
     }
     return false;
 }
 
-void cache_store(const char* path, const std::string& key, int order, int mult, double us)
+void cache_store(const char* path, const std::string& key, int order, int mult, double us, const int* chunks)
 {
     if (!path) return;
     std::vector<std::string> keep;
@@ -142,7 +185,9 @@ void cache_store(const char* path, const std::string& key, int order, int mult, 
     }
     std::ofstream f(path, std::ios::trunc);
     for (auto& l : keep) f << l << "\n";
-    f << key << " " << order << " " << mult << " " << us << "\n";
+    f << key << " " << order << " " << mult << " " << us;
+    for (int j = 0; j < kClasses; ++j) f << " " << chunks[j];
+    f << "\n";
 }
 
 mf_status launch(mf_batch_s* B, hipStream_t s)
@@ -235,10 +280,11 @@ mf_status mf_batch_create(const mf_batch_problem* problems, int32_t n, mf_precis
             return st;
         }
         B->probs.push_back(a);
-        B->units.push_back(batch_units_of(q.pattern));
+        B->cls.push_back(class_of(B->forms[k], q.pattern));
+        B->units.push_back(batch_units_of(q.pattern, 1));
     }
-    mf_status st = batch_upload(B->probs, &B->dprobs, &B->dstatus);
-    if (st == MF_OK && hipMalloc(&B->counter, sizeof(int)) != hipSuccess) st = set_error(MF_ERR_OOM, "counter");
+    mf_status st = MF_OK;
+    if (hipMalloc(&B->counter, sizeof(int)) != hipSuccess) st = set_error(MF_ERR_OOM, "counter");
     int dev = 0, cus = 256;
     if (st == MF_OK && hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
@@ -260,14 +306,51 @@ mf_status mf_batch_tune(mf_batch_t* B, const char* cache_path, void* stream)
     const std::string key = tune_key(B);
     int order = 1, mult = 1;
     double us = 0;
-    if (cache_lookup(cache_path, key, &order, &mult, &us)) {
+    int cached[kClasses];
+    if (cache_lookup(cache_path, key, &order, &mult, &us, cached)) {
+        for (int c = 0; c < kClasses; ++c) B->chunks[c] = cached[c];
         mf_status st = upload_items(B, order);
         if (st != MF_OK) return st;
         B->n_wg = B->num_cus * mult;
         B->tuned_us = us;
         return MF_OK;
     }
+    // 1. tile height per class, by coordinate descent on the whole batch's time (round-
+    //    robin order, two workgroups per CU), classes with the
+    //    most columns first
+    int present[kClasses] = {0};
+    for (size_t k = 0; k < B->probs.size(); ++k) present[B->cls[k]] += (int)batch_units_of(B->probs[k].P, 1);
+    std::vector<int> byw;
+    for (int c = 0; c < kClasses; ++c)
+        if (present[c] > 0) byw.push_back(c);
+    std::sort(byw.begin(), byw.end(), [&](int a, int b) { return present[a] > present[b]; });
+    for (int c = 0; c < kClasses; ++c) B->chunks[c] = 1;
+    B->n_wg = B->num_cus * 2;
     double best = 1e300;
+    {
+        mf_status st = upload_items(B, 1);
+        if (st != MF_OK) return st;
+        st = time_config(B, s, &best);
+        if (st != MF_OK) return st;
+    }
+    for (int c : byw) {
+        int keep = B->chunks[c];
+        for (int ch = 2; ch <= kMaxChunks; ++ch) {
+            B->chunks[c] = ch;
+            mf_status st = upload_items(B, 1);
+            if (st != MF_OK) return st;
+            double t = 0;
+            st = time_config(B, s, &t);
+            if (st != MF_OK) return st;
+            if (t < best) {
+                best = t;
+                keep = ch;
+            }
+        }
+        B->chunks[c] = keep;
+    }
+    // 2. launch shape for those tiles: work-item order x workgroups per CU
+    best = 1e300;
     int best_order = 1, best_mult = 1;
     const int max_mult = 2;
     for (int o = 0; o < 3; ++o) {
@@ -289,7 +372,7 @@ mf_status mf_batch_tune(mf_batch_t* B, const char* cache_path, void* stream)
     if (st != MF_OK) return st;
     B->n_wg = B->num_cus * best_mult;
     B->tuned_us = best;
-    cache_store(cache_path, key, best_order, best_mult, best);
+    cache_store(cache_path, key, best_order, best_mult, best, B->chunks);
     return MF_OK;
 }
 
@@ -324,6 +407,20 @@ mf_status mf_batch_info(const mf_batch_t* B, int64_t* n_items, int32_t* n_workgr
     if (order) *order = B->order;
     if (graphed) *graphed = B->exec != nullptr;
     if (tuned_us) *tuned_us = B->tuned_us;
+    return MF_OK;
+}
+
+mf_status mf_batch_tiles(const mf_batch_t* B, int32_t* n_classes, int32_t* problems, int32_t* chunks)
+{
+    if (!B) return set_error(MF_ERR_ARG, "batch is NULL");
+    if (n_classes) *n_classes = kClasses;
+    for (int c = 0; c < kClasses; ++c) {
+        if (problems) {
+            problems[c] = 0;
+            for (int k : B->cls) problems[c] += k == c;
+        }
+        if (chunks) chunks[c] = B->chunks[c];
+    }
     return MF_OK;
 }
 

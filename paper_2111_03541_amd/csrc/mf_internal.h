@@ -84,8 +84,11 @@ mf_status reset_status(const mf_pattern_s* P, hipStream_t s);
 
 // batched persistent launch (assemble_column.hip)
 mf_status batch_check(const AssembleArgs& a);
-mf_status batch_upload(const std::vector<AssembleArgs>& probs, void** dev_probs, void** dev_status);
-int64_t batch_units_of(const mf_pattern_s* P);
+// chunks[k]: problem k's columns are cut into that many work items along z (the tile
+// height); *dev_probs and *dev_status are allocated on the first call, reused after
+mf_status batch_upload(const std::vector<AssembleArgs>& probs, const std::vector<int>& chunks, void** dev_probs,
+                       void** dev_status);
+int64_t batch_units_of(const mf_pattern_s* P, int chunks);
 mf_status batch_launch(const void* dev_probs, void* dev_status, int n_probs, const int2* items, int n_items,
                        int* counter, int n_wg, mf_precision prec, hipStream_t s);
 

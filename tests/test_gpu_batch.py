@@ -120,6 +120,8 @@ def test_batch_256_problems_sampled_against_oracle(mf):
         host.append((mesh, elastic, ep, src))
     batch = mf.Batch(probs, precision=mf.F32)
     stream = torch.cuda.Stream()
+    info = batch.tune(None, stream)  # the tuned tile shapes are the ones checked
+    say("  tuned", info)
     batch.run(stream)
     stream.synchronize()
     el = [p for p in range(256) if p % 2 == 1]
@@ -141,3 +143,33 @@ def test_batch_256_problems_sampled_against_oracle(mf):
         d = pr["d"].double().cpu().numpy()
         assert rowscaled_error(ref, K, Kr) <= TOL[1]
         assert vec_error(d, dr) <= TOL[1]
+
+
+@pytest.mark.parametrize("chunks", [2, 3, 4])
+def test_batch_tile_heights_match_oracle(mf, chunks):
+    """Every class's columns cut into `chunks` tiles along z (set through the tuner's
+    cache file, which the tuner then reads back): whole systems against the oracle."""
+    sizes = [(3, 2, 7), (5, 4, 9), (2, 3, 22), (4, 3, 25), (3, 3, 40), (2, 2, 37), (1, 1, 5), (6, 2, 3)]
+    say("batch tiles", chunks, sizes)
+    probs, host = make_problems(mf, sizes, 1, seed0=500)
+    stream = torch.cuda.Stream()
+    with tempfile.TemporaryDirectory() as tmp:
+        cache = os.path.join(tmp, "tune.txt")
+        mf.Batch(probs, precision=mf.F32).tune(cache, stream)
+        key, order, mult, us, *_ = open(cache).read().split()
+        with open(cache, "w") as f:
+            f.write(" ".join([key, order, mult, us] + [str(chunks)] * 6) + "\n")
+        batch = mf.Batch(probs, precision=mf.F32)
+        info = batch.tune(cache, stream)
+    assert all(t["chunks"] == chunks for t in info["tiles"].values()), info
+    batch.run(stream)
+    stream.synchronize()
+    for pr, (mesh, elastic, ep, src, mask) in zip(batch.problems, host):
+        assert pr["pattern"].status()[0] == mf.OK
+        kind = O.ELASTICITY if elastic else O.POISSON
+        params = {"coef": 1.0, "nu": 0.3} if elastic else {"coef": 1.0}
+        ref = O.Pattern(mesh, 3 if elastic else 1)
+        Kr, dr = O.assemble(ref, kind, params, elem_param=rounded(ep, 1), nodal_src=rounded(src, 1),
+                            dirichlet=mask)
+        assert rowscaled_error(ref, pr["K"].double().cpu().numpy(), Kr) <= TOL[1]
+        assert vec_error(pr["d"].double().cpu().numpy(), dr) <= TOL[1]
