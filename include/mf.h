@@ -336,16 +336,17 @@ typedef struct {
  * edges: face_id 2 * axis + side as for hexahedra, 2 or 3 Gauss points along the edge,
  * 1 or 2 fields, sigma^l the leading 2x2 block of value[0..9)); MF_ERR_UNSUPPORTED
  * otherwise.
- * Queued on the stream (after one synchronisation that sizes the face buckets).  Reported by
+ * Queued on the stream (see below for the one synchronisation).  Reported by
  * mf_status_poll (until the next mf_assemble clears the status): a face whose element id
  * or local face is out of range (skipped; MF_ERR_ARG with the first such face), and a
  * degenerate face (zero area) or element (det J <= 0, flux form; MF_ERR_BAD_JACOBIAN).
  * Errors: MF_ERR_ARG (a form/field-count mismatch or bad arguments), MF_ERR_UNSUPPORTED
  * (an element type the boundary kernels do not cover, or the flux and flow forms on
- * anything but 8-node hexahedra), MF_ERR_HIP.  Faces are scattered in buckets of
- * (colour of the face's element, local face), one launch per non-empty bucket, so two
- * calls with the same inputs give the same bits; the call synchronises the stream once
- * to size the buckets.
+ * anything but 8-node hexahedra), MF_ERR_HIP.  Two calls with the same inputs give the
+ * same bits: on 8-node hexahedra the faces are marked per element and added element
+ * colour by element colour (async); on the other elements they go in buckets of (colour
+ * of the face's element, local face), one launch per non-empty bucket, and the call
+ * synchronises the stream once to size the buckets.
  */
 mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform* form, const double* coords,
                                int64_t n_faces, const int32_t* face_elem, const uint8_t* face_id,

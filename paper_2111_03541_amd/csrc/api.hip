@@ -51,6 +51,7 @@ static void free_pattern(mf_pattern_s* P)
     (void)hipFree(P->color_elems);
     (void)hipFree(P->elem_color);
     (void)hipFree(P->face_work);
+    (void)hipFree(P->face_elem_work);
     delete P;
 }
 

@@ -5,22 +5,27 @@
 // reading of the domain forms: R = -d_paper for the thermal and elastic physics,
 // R = +d_paper for the flow, K = dR/dU, exported d = -R(U).
 //
-// One thread per (face f, row node k, field i); the row nodes are the four face nodes,
-// and for the flow forms, whose inflow and fix terms carry the test gradient, all eight
-// nodes of the face's element.  The thread gathers the 8 nodes of the
-// face's element, evaluates the 2x2 Gauss rule on the face (xi_axis = -1 or +1) with the
-// element's trilinear map in FP64 (surface measure |t_u x t_v|, outward unit normal, and
-// for the flux term the volume gradients J^-T grad_xi N_b), accumulates row (a, i) of the
-// face tangent and residual, and adds them into K and d with atomics through the
-// element-to-nonzero rank map.  Boundary work is a surface's worth, so the simple
-// per-row scatter is enough.  A face whose element id or local face is out of range is
-// skipped and its index recorded in the pattern's second status word.
+// 8-node hexahedra (all forms): one thread per (element, element node a, field i), one
+// launch per element colour.  The faces are first marked per element (a bit per listed
+// local face and its count); a thread of an element with listed faces loops over them,
+// integrates the 2x2 Gauss rule of each face (xi_axis = -1 or +1) with the element's
+// trilinear map in FP64 (surface measure |t_u x t_v|, outward unit normal, and for the
+// flux term the volume gradients J^-T grad_xi N_b), and accumulates row (a, i) of the
+// face tangent and residual.  The row nodes of a face are its four nodes, or every node
+// of the element for the flow forms, whose inflow and fix terms carry the test gradient.
+// Elements of one colour share no node, so each row is added by a single thread of the
+// launch with plain stores through the element-to-nonzero rank map, and the colours run
+// in stream order: the sums are the same on every run, with no host synchronisation.
 //
-// Faces go in buckets keyed by (colour of the face's element, local face), one launch per
-// bucket in key order.  Elements of one colour share no node, so within a bucket every
-// value of K and d receives contributions of one face only (or of identical copies of it,
-// when a face is listed twice): the sums do not depend on the order of the atomics, and
-// two calls with the same inputs give the same bits.
+// 20-node hexahedra, 10-node tetrahedra and quadrilateral edges: one thread per (face,
+// row node, field), atomics through the rank map, with the faces in buckets keyed by
+// (colour of the face's element, local face), one launch per bucket in key order.
+// Within a bucket every value of K and d receives contributions of one face only (or of
+// identical copies of it, when a face is listed twice): again run-to-run identical sums;
+// the call synchronises once to size the buckets.
+//
+// A face whose element id or local face is out of range is skipped and its index
+// recorded in the pattern's second status word.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -54,6 +59,9 @@ struct BParams {
     // faces of this launch: order[f_begin + k] for k < n_faces (one colour bucket)
     const int32_t* order;
     int64_t f_begin;
+    // 8-node hexahedra: per element, the listed local faces (bit fid) and their counts
+    const uint32_t* face_mask;  // [n_el]
+    const uint32_t* face_cnt;   // [n_el][6]
 };
 
 __device__ __forceinline__ int64_t face_of(const BParams& p, int64_t k) { return p.order[p.f_begin + k]; }
@@ -82,27 +90,16 @@ __device__ __forceinline__ bool inverse_jacobian(const double (&J)[3][3], double
 }
 
 // row nodes per face: the flow forms (four fields) take every node of the element
-template <int NF>
-constexpr int kRowNodes = NF == 4 ? 8 : 4;
-
-// Row (a, i) of face f.  FI >= 0 fixes the field at compile time (the flow forms, so
-// that every per-field array index is static); FI < 0 takes the runtime field fi, and
-// then only field fi of the state and target and the (a, fi) x (b, fi) block are held.
+// Row (a, i) of element e over the listed faces of e (local faces in `fmask`, each
+// counted cnt[6 e + fid] times), for 8-node hexahedra.  FI >= 0 fixes the field at compile
+// time (the flow forms, so that every per-field array index is static); FI < 0 takes the
+// runtime field fi, and then only field fi of the state and target and the (a, fi) x
+// (b, fi) block are held.  The caller runs one element colour per launch: no other
+// thread of the launch touches row a, so the row is added with plain stores.
 template <int NF, int FI, typename T>
-__device__ __forceinline__ void boundary_row(const BParams& p, int64_t f, int ki, int kf, int fi)
+__device__ __forceinline__ void boundary_row(const BParams& p, int64_t e, uint32_t fmask, int a, int fi)
 {
     const int i = FI >= 0 ? FI : fi;
-    const int64_t e = p.face_elem[f];
-    const int fid = p.face_id[f];
-    if (e < 0 || e >= p.n_el || fid > 5) {  // skipped, and reported by mf_status_poll
-        if (ki == 0) atomicMin(p.status + 1, (unsigned long long)f);
-        return;
-    }
-    const int axis = fid >> 1, side = fid & 1;
-    const int u = (axis + 1) % 3, v = (axis + 2) % 3;
-    // element-local node of face node k: bit axis = side, bits u, v from k
-    auto fnode = [&](int k) { return (side << axis) | ((k & 1) << u) | ((k >> 1) << v); };
-    const int a = NF == 4 ? kf : fnode(kf);
 
     // fields of the state and target held: all four for the flow forms, else the
     // thread's own field i (slot li)
@@ -135,6 +132,14 @@ __device__ __forceinline__ void boundary_row(const BParams& p, int64_t f, int ki
         for (int j = 0; j < KC; ++j) krow[b][j] = 0.0;
     double rrow = 0.0;
 
+    for (int fid = 0; fid < 6; ++fid) {
+    if (!((fmask >> fid) & 1)) continue;
+    const int axis = fid >> 1, side = fid & 1;
+    // the row nodes of a face are its four nodes (every node of the element for the
+    // flow forms, whose terms carry the test gradient)
+    if (NF != 4 && ((a >> axis) & 1) != side) continue;
+    const double mult = (double)p.face_cnt[6 * e + fid];
+    const int u = (axis + 1) % 3, v = (axis + 2) % 3;
     for (int q = 0; q < 4; ++q) {
         double xi[3];
         xi[axis] = side ? 1.0 : -1.0;
@@ -167,7 +172,7 @@ __device__ __forceinline__ void boundary_row(const BParams& p, int64_t f, int ki
             return;
         }
         const double nv[3] = {nr[0] / dS, nr[1] / dS, nr[2] / dS};
-        const double w = dS;  // unit Gauss weights on [-1, 1]^2
+        const double w = mult * dS;  // unit Gauss weights on [-1, 1]^2, times the face's count
         const double Na = N[a];
         double uq[NL], gq[NL];
 #pragma unroll
@@ -267,6 +272,7 @@ __device__ __forceinline__ void boundary_row(const BParams& p, int64_t f, int ki
             rrow -= c * w * Na * ngT;
         }
     }
+    }
 
     const int64_t va = node[a];
     const int64_t row = p.field_major ? (int64_t)i * p.n_nodes + va : (int64_t)NF * va + i;
@@ -285,29 +291,35 @@ __device__ __forceinline__ void boundary_row(const BParams& p, int64_t f, int ki
             if (krow[b][l] == 0.0) continue;
             const int j = KC == 1 ? i : l;
             const int64_t pos = p.field_major ? rs + j * deg + rk : rs + rk * NF + j;
-            unsafeAtomicAdd(K + pos, (T)krow[b][l]);
+            K[pos] += (T)krow[b][l];
         }
     }
-    if (rrow != 0.0) unsafeAtomicAdd(d + row, (T)(-rrow));
+    if (rrow != 0.0) d[row] += (T)(-rrow);
 }
 
+// Items (element with listed faces of the colour, element node a, field i), strided over
+// the grid; the colour's element list and its length come from k_face_mark.
 template <int NF, typename T>
-__global__ void __launch_bounds__(kThreads) k_boundary(BParams p)
+__global__ void __launch_bounds__(kThreads) k_boundary(BParams p, const int32_t* __restrict__ elems,
+                                                       const uint32_t* __restrict__ n_el_c)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= p.n_faces * kRowNodes<NF> * NF) return;
-    const int64_t f = face_of(p, t % p.n_faces);
-    const int ki = (int)(t / p.n_faces);
-    const int kf = ki / NF, i = ki % NF;
-    if constexpr (NF == 4) {
-        switch (i) {
-            case 0: boundary_row<NF, 0, T>(p, f, ki, kf, i); break;
-            case 1: boundary_row<NF, 1, T>(p, f, ki, kf, i); break;
-            case 2: boundary_row<NF, 2, T>(p, f, ki, kf, i); break;
-            default: boundary_row<NF, 3, T>(p, f, ki, kf, i); break;
+    const int64_t nc = *n_el_c;
+    const int64_t n = nc * 8 * NF;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = elems[t % nc];
+        const uint32_t fmask = p.face_mask[e];
+        const int ki = (int)(t / nc);
+        const int a = ki / NF, i = ki % NF;
+        if constexpr (NF == 4) {
+            switch (i) {
+                case 0: boundary_row<NF, 0, T>(p, e, fmask, a, i); break;
+                case 1: boundary_row<NF, 1, T>(p, e, fmask, a, i); break;
+                case 2: boundary_row<NF, 2, T>(p, e, fmask, a, i); break;
+                default: boundary_row<NF, 3, T>(p, e, fmask, a, i); break;
+            }
+        } else {
+            boundary_row<NF, -1, T>(p, e, fmask, a, i);
         }
-    } else {
-        boundary_row<NF, -1, T>(p, f, ki, kf, i);
     }
 }
 
@@ -709,13 +721,77 @@ mf_status launch_boundary20(const BParams& p, hipStream_t s)
     return MF_OK;
 }
 
-template <int NF, typename T>
-mf_status launch_boundary(const BParams& p, hipStream_t s)
+__global__ void k_face_zero(uint32_t* __restrict__ w, int64_t n)
 {
-    const int64_t n = p.n_faces * kRowNodes<NF> * NF;
-    if (n == 0) return MF_OK;
-    if (n > 0xffffffffLL - kThreads) return set_error(MF_ERR_ARG, "too many faces for one launch");
-    k_boundary<NF, T><<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(p);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) w[i] = 0u;
+}
+
+// per element: bit fid of mask[e] for each listed local face, cnt[6 e + fid] its count;
+// an element's first face appends it to the list of its colour (list of colour c at
+// clist[cptr[c] ..], length ccount[c]; the order within a list does not matter, as
+// elements of one colour write disjoint rows).  A face out of range is skipped and
+// reported through the second status word.
+__global__ void k_face_mark(const int32_t* __restrict__ fe, const uint8_t* __restrict__ fid, int64_t n,
+                            int64_t n_el, const int32_t* __restrict__ ecol, const int64_t* __restrict__ cptr,
+                            uint32_t* __restrict__ mask, uint32_t* __restrict__ cnt, int32_t* __restrict__ clist,
+                            uint32_t* __restrict__ ccount, unsigned long long* __restrict__ status)
+{
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n) return;
+    const int64_t e = fe[f];
+    const int lf = fid[f];
+    if (e < 0 || e >= n_el || lf > 5) {
+        atomicMin(status + 1, (unsigned long long)f);
+        return;
+    }
+    atomicAdd(cnt + 6 * e + lf, 1u);
+    if (atomicOr(mask + e, 1u << lf) == 0u) {
+        const int c = ecol[e];
+        clist[cptr[c] + atomicAdd(ccount + c, 1u)] = (int32_t)e;
+    }
+}
+
+// 8-node hexahedra: mark the listed faces per element, then one launch per element
+// colour (elements of a colour share no node, so each row is added by one thread of the
+// launch, and the colours follow each other in the stream: the sums do not depend on
+// the run, and nothing waits on the host)
+template <int NF, typename T>
+mf_status launch_boundary(BParams p, const mf_pattern_s* Pc, hipStream_t s)
+{
+    mf_pattern_s* P = const_cast<mf_pattern_s*>(Pc);
+    if (p.n_faces == 0 || P->n_elems == 0) return MF_OK;
+    mf_status st = ensure_coloring(P, s);
+    if (st != MF_OK) return st;
+    const int n_col = (int)P->color_ptr.size() - 1;
+    // workspace: mask [n_el], counts [6 n_el], colour lists [n_el], list lengths [n_col],
+    // colour offsets (int64) [n_col + 1]
+    const int64_t n_el = P->n_elems;
+    const int64_t words = 8 * n_el + n_col + 2 * (n_col + 1) + 2;
+    if (!P->face_elem_work) {
+        MF_HIP(hipMalloc(&P->face_elem_work, sizeof(uint32_t) * (size_t)words));
+        int64_t* cptr = (int64_t*)(P->face_elem_work + 8 * n_el + n_col + ((8 * n_el + n_col) & 1));
+        MF_HIP(hipMemcpyAsync(cptr, P->color_ptr.data(), sizeof(int64_t) * (n_col + 1), hipMemcpyHostToDevice, s));
+        MF_HIP(hipStreamSynchronize(s));
+    }
+    uint32_t* mask = P->face_elem_work;
+    uint32_t* cnt = mask + n_el;
+    int32_t* clist = (int32_t*)(cnt + 6 * n_el);
+    uint32_t* ccount = (uint32_t*)(clist + n_el);
+    const int64_t* cptr = (const int64_t*)(P->face_elem_work + 8 * n_el + n_col + ((8 * n_el + n_col) & 1));
+    k_face_zero<<<(unsigned)((7 * n_el + kThreads - 1) / kThreads), kThreads, 0, s>>>(mask, 7 * n_el);
+    k_face_zero<<<(unsigned)((n_col + kThreads - 1) / kThreads), kThreads, 0, s>>>(ccount, n_col);
+    k_face_mark<<<(unsigned)((p.n_faces + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+        p.face_elem, p.face_id, p.n_faces, n_el, P->elem_color, cptr, mask, cnt, clist, ccount, P->status);
+    p.face_mask = mask;
+    p.face_cnt = cnt;
+    for (int c = 0; c < n_col; ++c) {
+        // at most min(colour size, faces) elements of the colour carry faces
+        const int64_t bound = std::min<int64_t>(P->color_ptr[c + 1] - P->color_ptr[c], p.n_faces) * 8 * NF;
+        if (bound == 0) continue;
+        const unsigned blocks = (unsigned)std::min<int64_t>(2048, (bound + kThreads - 1) / kThreads);
+        k_boundary<NF, T><<<blocks, kThreads, 0, s>>>(p, clist + P->color_ptr[c], ccount + c);
+    }
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
@@ -885,11 +961,11 @@ extern "C" mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform*
     } else if (quad) {
         launch = f64 ? (nf == 1 ? launch_boundary20<1, double> : launch_boundary20<3, double>)
                      : (nf == 1 ? launch_boundary20<1, float> : launch_boundary20<3, float>);
-    } else if (nf == 4) {
-        launch = f64 ? launch_boundary<4, double> : launch_boundary<4, float>;
     } else {
-        launch = f64 ? (nf == 1 ? launch_boundary<1, double> : launch_boundary<3, double>)
-                     : (nf == 1 ? launch_boundary<1, float> : launch_boundary<3, float>);
+        // 8-node hexahedra: element by element, colour by colour (no buckets)
+        if (nf == 4) return f64 ? launch_boundary<4, double>(p, P, s) : launch_boundary<4, float>(p, P, s);
+        if (nf == 1) return f64 ? launch_boundary<1, double>(p, P, s) : launch_boundary<1, float>(p, P, s);
+        return f64 ? launch_boundary<3, double>(p, P, s) : launch_boundary<3, float>(p, P, s);
     }
     if (n_faces == 0) return MF_OK;
     std::vector<int64_t> off;

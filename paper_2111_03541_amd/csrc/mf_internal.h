@@ -34,6 +34,8 @@ struct mf_pattern_s {
     // boundary-face buckets (boundary.hip): device workspace, grown on demand
     int32_t* face_work = nullptr;
     int64_t face_work_cap = 0;
+    // 8-node hexahedra faces per element (boundary.hip): mask [n_elems], counts [6][n_elems]
+    uint32_t* face_elem_work = nullptr;
     // structured lexicographic grid detection
     int is_grid = 0;
     int64_t gx = 0, gy = 0, gz = 0;
