@@ -18,7 +18,11 @@ Forms as the Q1 oracle defines them at the zero state (Sec. 4.1, 4.2; K = dR/dU,
   mass        K = int c N_a N_b,                        d = int c N_a f
   conduction  K = int c grad N_a . grad N_b,            d = int N_a f
   elasticity  K = int lam g_ai g_bj + mu g_aj g_bi + mu delta_ij g_a . g_b,  d = int N_a b_i
-with c = coef * elem_param and lam, mu from E = coef * elem_param and nu.  The pattern
+with c = coef * elem_param and lam, mu from E = coef * elem_param and nu.  The steady
+flow form (Sec. 4.3, base terms with the SUPG/PSPG/LSIC terms) is the one of the Q1
+oracle at a given state (u, p) per node: R and its full Newton tangent K = dR/dU, d = -R,
+with Rm_i = rho u_k du_i/dx_k + dp/dx_i (the second derivatives of u left out of Rm, as
+for the linear elements).  The pattern
 is built by brute force: N(v) = sorted nodes sharing an element with v.  Boundary forms on
 the element faces (8 nodes, 3x3 face rule): assemble_boundary20.
 """
@@ -26,7 +30,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import ELASTICITY, MASS, NODE_MAJOR, POISSON
+from . import ELASTICITY, MASS, NODE_MAJOR, NS_SUPG, POISSON
 
 CORNER = np.array([[1.0 if (a >> d) & 1 else -1.0 for d in range(3)] for a in range(8)])
 # edge nodes: (axis along the edge, signs of the two other axes in cyclic order)
@@ -170,10 +174,49 @@ class Pattern20:
         return sp.csr_matrix((values, self.col_idx, self.row_ptr), shape=(self.n_rows, self.n_rows))
 
 
-def assemble20(pat: Pattern20, kind, params=None, elem_param=None, nodal_src=None):
-    """(K values [nnz] in the pattern's order, d [n_rows])."""
+def ns_element(N, g, W, Ue, prm, Ke, De):
+    """Flow form at one integration point: adds W times the tangent and -W times the
+    residual of the element to Ke [nen][nf][nen][nf] and De [nen][nf].  N [nen], g [nen][dim]
+    (physical gradients), Ue [nen][nf] the element state (velocity, then pressure)."""
+    rho, mu, tm, tc = prm["rho"], prm["mu"], prm["tau_m"], prm["tau_c"]
+    dim = g.shape[1]
+    u = N @ Ue[:, :dim]                     # velocity
+    gu = Ue[:, :dim].T @ g                  # gu[i][k] = du_i / dx_k
+    p = N @ Ue[:, dim]
+    gp = g.T @ Ue[:, dim]
+    div = np.trace(gu)
+    Rm = rho * gu @ u + gp                  # rho u_k du_i/dx_k + dp/dx_i
+    adv = g @ u                             # u . grad N_a
+    gg = g @ g.T
+    I = np.eye(dim)
+    # residual: momentum rows (a, i), continuity rows (a, p)
+    Ru = (-rho * np.outer(adv, u) - g * p + mu * g @ gu.T + tm * rho * np.outer(adv, Rm) + tc * g * div)
+    Rp = N * div + tm * g @ Rm
+    De[:, :dim] -= W * Ru
+    De[:, dim] -= W * Rp
+    # tangent dR/dU: velocity-velocity, velocity-pressure, pressure-velocity, pressure-pressure
+    Kuu = (-rho * np.einsum("il,a,b->aibl", I, adv, N)
+           - rho * np.einsum("i,al,b->aibl", u, g, N)
+           + mu * np.einsum("il,ab->aibl", I, gg)
+           + tm * rho * np.einsum("i,al,b->aibl", Rm, g, N)
+           + tm * rho * rho * np.einsum("a,b,il->aibl", adv, N, gu)
+           + tm * rho * rho * np.einsum("il,a,b->aibl", I, adv, adv)
+           + tc * np.einsum("ai,bl->aibl", g, g))
+    Kup = -np.einsum("ai,b->aib", g, N) + tm * rho * np.einsum("a,bi->aib", adv, g)
+    Kpu = (np.einsum("a,bl->abl", N, g)
+           + tm * rho * (np.einsum("b,al->abl", N, g @ gu) + np.einsum("al,b->abl", g, adv)))
+    Kpp = tm * gg
+    Ke[:, :dim, :, :dim] += W * Kuu
+    Ke[:, :dim, :, dim] += W * Kup
+    Ke[:, dim, :, :dim] += W * Kpu
+    Ke[:, dim, :, dim] += W * Kpp
+
+
+def assemble20(pat: Pattern20, kind, params=None, elem_param=None, nodal_src=None, state=None):
+    """(K values [nnz] in the pattern's order, d [n_rows]).  state [nf][n_nodes]: the point
+    of linearisation of the flow form (zero when None)."""
     import scipy.sparse as sp
-    prm = dict(coef=1.0, nu=0.0)
+    prm = dict(coef=1.0, nu=0.0, rho=0.0, mu=0.0, tau_m=0.0, tau_c=0.0)
     prm.update(params or {})
     mesh, nf = pat.mesh, pat.nf
     dim, nen = mesh.dim, mesh.nen
@@ -191,6 +234,7 @@ def assemble20(pat: Pattern20, kind, params=None, elem_param=None, nodal_src=Non
         X = mesh.coords[:, nodes].T  # [nen][dim]
         ep = 1.0 if elem_param is None else float(elem_param[e])
         src = np.zeros((nen, nf)) if nodal_src is None else np.asarray(nodal_src)[:, nodes].T
+        Ue = np.zeros((nen, nf)) if state is None else np.asarray(state, np.float64)[:, nodes].T
         Ke = np.zeros((nen, nf, nen, nf))
         De = np.zeros((nen, nf))
         for (N, dN), wq in zip(tables, w):
@@ -217,6 +261,8 @@ def assemble20(pat: Pattern20, kind, params=None, elem_param=None, nodal_src=Non
                 Ke += W * (lam * np.einsum("ai,bj->aibj", g, g) + mu * np.einsum("aj,bi->aibj", g, g)
                            + mu * np.einsum("ab,ij->aibj", gg, np.eye(dim)))
                 De += W * np.outer(N, fq)
+            elif kind == NS_SUPG:
+                ns_element(N, g, W, Ue, prm, Ke, De)
             else:
                 raise ValueError(kind)
         for a in range(nen):
