@@ -53,9 +53,9 @@ typedef enum {
     MF_HEX8 = 2,    /* 8-node hexahedron, order 1 (corners a = ax + 2 ay + 4 az)             */
     MF_HEX20 = 3,   /* 20-node serendipity hexahedron, order 2: corners as MF_HEX8, then the
                        midpoints of the x-, y- and z-directed edges, four each, ordered by
-                       the bits of the two other axes; mass, conduction and elasticity forms
-                       with 3 Gauss points per axis (element colours, one workgroup per
-                       element)                                                              */
+                       the bits of the two other axes; mass, conduction, elasticity and
+                       flow forms with 3 Gauss points per axis (element colours, one
+                       workgroup per element)                                                */
     MF_QUAD8 = 4,   /* 8-node serendipity quadrilateral, order 2: corners as MF_QUAD4, then the
                        midpoints of the x-directed edges at y = -1, +1 and of the y-directed
                        edges at x = -1, +1; the forms of MF_HEX20 (plane-strain elasticity)

@@ -1,17 +1,21 @@
-// Assembly on serendipity elements (quadratic elements, used by every experiment of
-// Sec. 4; element order is an input of the problem statement, Sec. 1): 20-node hexahedra
-// and 8-node quadrilaterals, with the 3-point Gauss rule per axis and the mass,
-// conduction and elasticity forms of the linear kernel (Sec. 4.1, 4.2; K = dR/dU, d = -R
-// at the zero state; plane strain in 2D).
+// Assembly on quadratic elements (used by every experiment of Sec. 4; element order is
+// an input of the problem statement, Sec. 1): 20-node serendipity hexahedra, 8-node
+// serendipity quadrilaterals (3-point Gauss rule per axis) and 10-node tetrahedra
+// (collapsed 64-point rule), with the mass, conduction and elasticity forms of the linear
+// kernel (Sec. 4.1, 4.2; K = dR/dU, d = -R at the zero state; plane strain in 2D) and the
+// steady flow form with its stabilisation terms at a given state (Sec. 4.3; K the full
+// Newton tangent, d = -R).
 //
-// One workgroup per element (256 threads in 3D, 64 in 2D):
-//   1. lanes load the element's node coordinates and sources into LDS;
+// One workgroup per element:
+//   1. lanes load the element's node coordinates and sources (the state, for the flow
+//      form) into LDS;
 //   2. one lane per Gauss point builds J = sum_b x_b (x) grad_xi N_b in FP64, its
 //      determinant and inverse, and stores g_b = J^-T grad_xi N_b for every node, the
-//      weight W = w det J and the interpolated source in LDS;
-//   3. lane (row (a, i), quarter) sums the entries of row (a, i) for the column nodes b of
-//      its quarter (a quarter of the element's nodes) over the Gauss points and adds them
-//      into K through the element-to-nonzero rank map (quarter 0 also adds d_(a,i)).
+//      weight W = w det J and the interpolated source in LDS (for the flow form: the
+//      velocity, its gradient, the pressure, the momentum residual Rm and div u);
+//   3. lane (row (a, i), part) sums the entries of row (a, i) for the column nodes b of
+//      its part (a fixed share of the element's nodes) over the Gauss points and adds them
+//      into K through the element-to-nonzero rank map (part 0 also adds d_(a,i)).
 // Elements go colour by colour (no two elements of one colour share a node), one launch
 // per colour, so the adds are plain read-modify-writes: every entry of K and d has one
 // writer per launch, and the stream orders the launches.
@@ -28,21 +32,38 @@ namespace {
 
 enum ElemKind { kHex20 = 0, kQuad8 = 1, kTet10 = 2 };
 
-// Per element type: dimension, nodes, Gauss points, threads per workgroup, and the number
-// of groups the column nodes of a row are split into (one lane per row and group).
+// Per element type: dimension, nodes and Gauss points.
 template <int ET>
 struct Elem;
 template <>
 struct Elem<kHex20> {
-    static constexpr int DIM = 3, NEN = 20, NQ = 27, THREADS = 256, NPART = 4;
+    static constexpr int DIM = 3, NEN = 20, NQ = 27;
 };
 template <>
 struct Elem<kQuad8> {
-    static constexpr int DIM = 2, NEN = 8, NQ = 9, THREADS = 64, NPART = 4;
+    static constexpr int DIM = 2, NEN = 8, NQ = 9;
 };
 template <>
 struct Elem<kTet10> {
-    static constexpr int DIM = 3, NEN = 10, NQ = 64, THREADS = 64, NPART = 2;
+    static constexpr int DIM = 3, NEN = 10, NQ = 64;
+};
+
+// Per element type and form: fields per node, the number of parts the column nodes of a
+// row are split into (one lane per row and part), threads per workgroup, and the values
+// per Gauss point that the flow form keeps in LDS (u, grad u, p, Rm, div u).
+template <int ET, int FORM>
+struct Cfg {
+    static constexpr int DIM = Elem<ET>::DIM, NEN = Elem<ET>::NEN, NQ = Elem<ET>::NQ;
+    static constexpr bool NS = FORM == MF_FORM_NS_SUPG;
+    static constexpr int NF = FORM == MF_FORM_ELASTICITY ? DIM : NS ? DIM + 1 : 1;
+    static constexpr int NPART = (NS || ET == kTet10) ? 2 : 4;
+    static constexpr int ROWS = NEN * NF * NPART;
+    static constexpr int NEED = ROWS > NQ ? ROWS : NQ;
+    static constexpr int THREADS = (NEED + 63) / 64 * 64;
+    static constexpr int NSQ = NS ? 2 * DIM + DIM * DIM + 2 : 1;
+    static constexpr int Q_U = 0, Q_GU = DIM, Q_P = DIM + DIM * DIM, Q_RM = Q_P + 1, Q_DIV = Q_RM + DIM;
+    static_assert(NEN * DIM <= THREADS && NEN * NF <= THREADS && NEN % NPART == 0,
+                  "one lane per row part, Gauss point and coordinate");
 };
 
 template <int ET>
@@ -139,17 +160,83 @@ struct Q2Params {
     unsigned long long* status;
 };
 
-template <int ET, int NF>
+template <int ET, int FORM>
 struct Q2Shared {
-    static constexpr int DIM = Elem<ET>::DIM, NEN = Elem<ET>::NEN, NQ = Elem<ET>::NQ;
-    double x[NEN][DIM];
-    double src[NEN][NF];
-    double g[NQ][NEN][DIM];
-    double N[NQ][NEN];
-    double W[NQ];
-    double f[NQ][NF];
+    using C = Cfg<ET, FORM>;
+    double x[C::NEN][C::DIM];
+    double src[C::NEN][C::NF];
+    double g[C::NQ][C::NEN][C::DIM];
+    double N[C::NQ][C::NEN];
+    double W[C::NQ];
+    double f[C::NQ][C::NF];
+    double fs[C::NQ][C::NSQ];  // flow form: the state at the Gauss point
     int bad;
 };
+
+// Flow form, entries of row (a, i) against the columns (b, 0..dim) at one Gauss point
+// (the tangent of the Q1 kernel, Sec. 4.3): i < dim a momentum row, i = dim the continuity
+// row.  F holds u, grad u (gu[i][k] = du_i/dx_k), p, Rm and div u at the point.
+template <int DIM>
+__device__ __forceinline__ void ns_entries(const mf_form& fm, int i, double Na, const double* ga, double Nb,
+                                           const double* gb, const double* F, double (&v)[DIM + 1])
+{
+    const double rho = fm.rho, mu = fm.mu, tm = fm.tau_m, tc = fm.tau_c;
+    const double* u = F;
+    const double* gu = F + DIM;
+    const double* Rm = F + DIM + DIM * DIM + 1;  // after p
+    double adva = 0.0, advb = 0.0, gg = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        adva = fma(u[k], ga[k], adva);
+        advb = fma(u[k], gb[k], advb);
+        gg = fma(ga[k], gb[k], gg);
+    }
+    if (i < DIM) {
+        const double gai = ga[i];
+        const double c_nb = (tm * rho * Rm[i] - rho * u[i]) * Nb;  // times g_al
+        const double c_diag = -rho * adva * Nb + mu * gg + tm * rho * rho * adva * advb;
+        const double c_gu = tm * rho * rho * adva * Nb;  // times gu[i][l]
+#pragma unroll
+        for (int l = 0; l < DIM; ++l)
+            v[l] = c_nb * ga[l] + c_gu * gu[i * DIM + l] + tc * gai * gb[l] + (l == i ? c_diag : 0.0);
+        v[DIM] = -gai * Nb + tm * rho * adva * gb[i];
+    } else {
+#pragma unroll
+        for (int l = 0; l < DIM; ++l) {
+            double sl = 0.0;
+#pragma unroll
+            for (int m = 0; m < DIM; ++m) sl = fma(ga[m], gu[m * DIM + l], sl);
+            v[l] = Na * gb[l] + tm * rho * (Nb * sl + ga[l] * advb);
+        }
+        v[DIM] = tm * gg;
+    }
+}
+
+// Flow form, the residual entry R_(a,i) at one Gauss point.
+template <int DIM>
+__device__ __forceinline__ double ns_residual(const mf_form& fm, int i, double Na, const double* ga,
+                                              const double* F)
+{
+    const double rho = fm.rho, mu = fm.mu, tm = fm.tau_m, tc = fm.tau_c;
+    const double* u = F;
+    const double* gu = F + DIM;
+    const double p = F[DIM + DIM * DIM];
+    const double* Rm = F + DIM + DIM * DIM + 1;
+    const double div = F[2 * DIM + DIM * DIM + 1];
+    if (i < DIM) {
+        double adva = 0.0, visc = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            adva = fma(u[k], ga[k], adva);
+            visc = fma(ga[k], gu[i * DIM + k], visc);
+        }
+        return -rho * adva * u[i] - ga[i] * p + mu * visc + tm * rho * adva * Rm[i] + tc * ga[i] * div;
+    }
+    double gRm = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) gRm = fma(ga[k], Rm[k], gRm);
+    return Na * div + tm * gRm;
+}
 
 template <typename T>
 __global__ void k_fill(T* p, int64_t n)
@@ -159,15 +246,12 @@ __global__ void k_fill(T* p, int64_t n)
 }
 
 template <int ET, int FORM, typename T>
-__global__ void __launch_bounds__(Elem<ET>::THREADS) k_assemble_quadratic(Q2Params p)
+__global__ void __launch_bounds__((Cfg<ET, FORM>::THREADS)) k_assemble_quadratic(Q2Params p)
 {
-    constexpr int DIM = Elem<ET>::DIM, NEN = Elem<ET>::NEN, NQ = Elem<ET>::NQ, NPART = Elem<ET>::NPART;
+    using C = Cfg<ET, FORM>;
+    constexpr int DIM = C::DIM, NEN = C::NEN, NQ = C::NQ, NPART = C::NPART, NF = C::NF;
     constexpr int NBQ = NEN / NPART;
-    constexpr int NF = FORM == MF_FORM_ELASTICITY ? DIM : 1;
-    static_assert(NEN * NF * NPART <= Elem<ET>::THREADS && NQ <= Elem<ET>::THREADS &&
-                      NEN * DIM <= Elem<ET>::THREADS && NEN % NPART == 0,
-                  "one lane per row part, Gauss point and coordinate");
-    __shared__ Q2Shared<ET, NF> S;
+    __shared__ Q2Shared<ET, FORM> S;
     const int lane = threadIdx.x;
     const int64_t li = blockIdx.x;
     const bool live = li < p.n_list;  // uniform across the workgroup
@@ -228,9 +312,44 @@ __global__ void __launch_bounds__(Elem<ET>::THREADS) k_assemble_quadratic(Q2Para
         S.W[lane] = w * det;
 #pragma unroll
         for (int j = 0; j < NF; ++j) S.f[lane][j] = f[j];
+        if constexpr (C::NS) {
+            // the state at the point: f holds (u, p) interpolated; the gradients from g
+            double gu[DIM][DIM], gp[DIM];
+#pragma unroll
+            for (int m = 0; m < DIM; ++m) {
+                gp[m] = 0.0;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) gu[m][k] = 0.0;
+            }
+            for (int b = 0; b < NEN; ++b) {
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) {
+                    const double gbk = S.g[lane][b][k];
+#pragma unroll
+                    for (int m = 0; m < DIM; ++m) gu[m][k] = fma(gbk, S.src[b][m], gu[m][k]);
+                    gp[k] = fma(gbk, S.src[b][DIM], gp[k]);
+                }
+            }
+            double* F = S.fs[lane];
+            double div = 0.0;
+#pragma unroll
+            for (int m = 0; m < DIM; ++m) {
+                F[C::Q_U + m] = f[m];
+                div += gu[m][m];
+                double c = 0.0;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) {
+                    F[C::Q_GU + m * DIM + k] = gu[m][k];
+                    c = fma(f[k], gu[m][k], c);
+                }
+                F[C::Q_RM + m] = p.form.rho * c + gp[m];
+            }
+            F[C::Q_P] = f[DIM];
+            F[C::Q_DIV] = div;
+        }
     }
     __syncthreads();
-    if (!live || S.bad || lane >= NEN * NF * NPART) return;
+    if (!live || S.bad || lane >= C::ROWS) return;
 
     const int rowl = lane % (NEN * NF), quarter = lane / (NEN * NF);
     const int a = rowl / NF, i = rowl % NF;
@@ -253,7 +372,12 @@ __global__ void __launch_bounds__(Elem<ET>::THREADS) k_assemble_quadratic(Q2Para
         for (int j = 0; j < NF; ++j) acc[j] = 0.0;
         for (int q = 0; q < NQ; ++q) {
             const double W = S.W[q];
-            if constexpr (FORM == MF_FORM_MASS) {
+            if constexpr (C::NS) {
+                double v[NF];
+                ns_entries<DIM>(p.form, i, S.N[q][a], S.g[q][a], S.N[q][b], S.g[q][b], S.fs[q], v);
+#pragma unroll
+                for (int j = 0; j < NF; ++j) acc[j] = fma(W, v[j], acc[j]);
+            } else if constexpr (FORM == MF_FORM_MASS) {
                 acc[0] = fma(W * coef * S.N[q][a], S.N[q][b], acc[0]);
             } else {
                 double ga[DIM], gb[DIM], gg = 0.0;
@@ -281,11 +405,18 @@ __global__ void __launch_bounds__(Elem<ET>::THREADS) k_assemble_quadratic(Q2Para
     }
     if (quarter != 0) return;
     double dv = 0.0;
-    const double cd = FORM == MF_FORM_MASS ? coef : 1.0;
-    for (int q = 0; q < NQ; ++q) dv = fma(S.W[q] * cd * S.N[q][a], S.f[q][i], dv);
+    if constexpr (C::NS) {
+        for (int q = 0; q < NQ; ++q) dv -= S.W[q] * ns_residual<DIM>(p.form, i, S.N[q][a], S.g[q][a], S.fs[q]);
+    } else {
+        const double cd = FORM == MF_FORM_MASS ? coef : 1.0;
+        for (int q = 0; q < NQ; ++q) dv = fma(S.W[q] * cd * S.N[q][a], S.f[q][i], dv);
+    }
     ((T*)p.d)[row] += (T)dv;
-    // a non-finite element parameter or source value shows in the coefficients or dv
-    if (!isfinite(dv + coef + lam + mu)) atomicMin(p.status + 2, (unsigned long long)e);
+    // a non-finite element parameter, source, state or form constant shows in the
+    // coefficients or in dv
+    double chk = dv + coef + lam + mu;
+    if constexpr (C::NS) chk += p.form.rho + p.form.mu + p.form.tau_m + p.form.tau_c;
+    if (!isfinite(chk)) atomicMin(p.status + 2, (unsigned long long)e);
 }
 
 constexpr int kFillThreads = 256;
@@ -305,7 +436,7 @@ mf_status launch(const AssembleArgs& A)
     p.nbr_ptr = P->nbr_ptr;
     p.rank = P->rank;
     p.elem_param = A.elem_param;
-    p.src = A.nodal_src;
+    p.src = FORM == MF_FORM_NS_SUPG ? A.lin_state : A.nodal_src;
     p.field_major = P->numbering == MF_FIELD_MAJOR;
     p.K = A.K;
     p.d = A.d;
@@ -320,7 +451,7 @@ mf_status launch(const AssembleArgs& A)
         p.elems = P->color_elems + P->color_ptr[c];
         p.n_list = P->color_ptr[c + 1] - P->color_ptr[c];
         if (p.n_list > 0)
-            k_assemble_quadratic<ET, FORM, T><<<(unsigned)p.n_list, Elem<ET>::THREADS, 0, A.stream>>>(p);
+            k_assemble_quadratic<ET, FORM, T><<<(unsigned)p.n_list, Cfg<ET, FORM>::THREADS, 0, A.stream>>>(p);
     }
     MF_HIP(hipGetLastError());
     return MF_OK;
@@ -333,6 +464,7 @@ mf_status dispatch(const AssembleArgs& A)
         case MF_FORM_MASS: return launch<ET, MF_FORM_MASS, T>(A);
         case MF_FORM_POISSON: return launch<ET, MF_FORM_POISSON, T>(A);
         case MF_FORM_ELASTICITY: return launch<ET, MF_FORM_ELASTICITY, T>(A);
+        case MF_FORM_NS_SUPG: return launch<ET, MF_FORM_NS_SUPG, T>(A);
         default: return set_error(MF_ERR_UNSUPPORTED, "form %d on serendipity elements", (int)A.form->kind);
     }
 }

@@ -117,8 +117,8 @@ def test_hex20_argument_errors(mf):
     with pytest.raises(mf.MFError):  # the quadratic element takes 3 points per axis
         pat.assemble(mf.Form(mf.POISSON), coords, points_per_axis=2)
     pat4 = gpu_pattern(mf, mesh, 4)
-    st = torch.zeros((4, mesh.n_nodes), dtype=torch.float64, device=dev)
-    with pytest.raises(mf.MFError):  # no flow form on this element
+    st = torch.zeros((3, mesh.n_nodes), dtype=torch.float64, device=dev)
+    with pytest.raises(ValueError):  # the flow state holds dim + 1 fields
         pat4.assemble(mf.Form(mf.NS_SUPG, rho=1.0, mu=0.01), coords, lin_state=st)
     with pytest.raises(mf.MFError):  # unknown element type
         mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 1, elem=7)

@@ -111,10 +111,9 @@ def test_quad8_argument_errors(mf):
     coords = torch.from_numpy(mesh.coords).to(dev)
     with pytest.raises(mf.MFError):  # three points per axis
         pat.assemble(mf.Form(mf.POISSON), coords, points_per_axis=2)
-    pat3 = gpu_pattern(mf, mesh, 3)
-    with pytest.raises(mf.MFError):  # the 2D flow form is not built on this element
-        pat3.assemble(mf.Form(mf.NS_SUPG, rho=1.0, mu=0.01), coords,
-                      lin_state=torch.zeros((3, mesh.n_nodes), dtype=torch.float64, device=dev))
+    with pytest.raises(mf.MFError):  # the flow form needs dim + 1 = 3 fields, not 1
+        pat.assemble(mf.Form(mf.NS_SUPG, rho=1.0, mu=0.01), coords,
+                     lin_state=torch.zeros((3, mesh.n_nodes), dtype=torch.float64, device=dev))
     with pytest.raises(mf.MFError):  # the flux form needs 8-node hexahedra
         pat.assemble_boundary(mf.BFORM_FLUX, coords, torch.zeros(1, dtype=torch.int32, device=dev),
                               torch.zeros(1, dtype=torch.uint8, device=dev))
