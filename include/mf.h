@@ -380,6 +380,10 @@ typedef struct {
     int32_t use_graph;        /* 1: replay each chunk of iterations as a HIP graph (needs a
                                  non-default stream; silently off otherwise)              */
     mf_precond_kind precond;
+    int32_t stall_iters;      /* mf_pcg: iterations without the recurrence residual
+                                 falling below 0.9 x its best that count as stagnation
+                                 (0 = 512; judged at the host checks); ignored by
+                                 mf_bicgstab                                             */
     const mf_nn_t* net;       /* MF_PRECOND_NN only */
 } mf_pcg_opts;
 
@@ -387,6 +391,7 @@ typedef struct {
     int32_t iterations;       /* iterations run (a multiple of check_every unless maxit)  */
     int32_t converged;        /* 1 when the true residual met tol                         */
     int32_t fallbacks;        /* MF_PRECOND_NN: iterations that used the Jacobi z         */
+    int32_t restarts;         /* restarts from the current x (stagnation, breakdown)      */
     double true_relres;       /* |b - K x|_2 / |b|_2 at exit                              */
 } mf_pcg_result;
 
@@ -394,6 +399,10 @@ typedef struct {
  * mf_pcg - solve K x = b from x0 = 0.  x [n_rows] is overwritten.  (sync: returns when
  * the solve is done.)  Scalars stay on the device; the host reads the recurrence
  * residual every check_every iterations and accepts only a true residual <= tol.
+ * Stagnation (opts->stall_iters iterations without progress), or a recurrence residual that
+ * meets tol while the true residual does not, restarts the method from the current x:
+ * r = b - K x, z = Jacobi r, p = z; an MF_PRECOND_NN solve continues as Jacobi-PCG after
+ * its first restart.  At most 8 restarts; res->restarts counts them.
  * Errors: MF_ERR_ARG, MF_ERR_NOT_CONVERGED (maxit reached; x and res hold the last
  * iterate), MF_ERR_NONFINITE (breakdown: p.Kp <= 0 or r.z <= 0), MF_ERR_OOM, MF_ERR_HIP.
  */

@@ -68,12 +68,12 @@ class _CSR(C.Structure):
 
 class _PcgOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
-                ("precond", C.c_int), ("net", C.c_void_p)]
+                ("precond", C.c_int), ("stall_iters", C.c_int32), ("net", C.c_void_p)]
 
 
 class _PcgResult(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("fallbacks", C.c_int32),
-                ("true_relres", C.c_double)]
+                ("restarts", C.c_int32), ("true_relres", C.c_double)]
 
 
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_NN = 0, 1, 2
@@ -542,23 +542,24 @@ class Net:
 
 
 def pcg(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PRECOND_JACOBI, net=None,
-        check_every=8, use_graph=True, stream=None, raise_on_fail=True):
+        check_every=8, use_graph=True, stream=None, raise_on_fail=True, stall_iters=0):
     """Solve K x = b (FP64 CSR on the device; row_ptr/col_idx int32) by PCG from x0 = 0.
 
     Returns (x, result dict).  use_graph needs a non-default stream; with the default
-    stream the iterations run eagerly."""
+    stream the iterations run eagerly.  stall_iters: iterations without progress that
+    restart the solve from the current x (0 = the library default)."""
     import torch
     lib = load()
     n = int(b.shape[0])
     if x is None:
         x = torch.empty(n, dtype=torch.float64, device=b.device)
     A = _CSR(n, _ptr_any(row_ptr), _ptr_any(col_idx), _ptr(values))
-    opts = _PcgOpts(tol, maxit, check_every, int(bool(use_graph)), precond,
+    opts = _PcgOpts(tol, maxit, check_every, int(bool(use_graph)), precond, stall_iters,
                     None if net is None else net.handle)
     res = _PcgResult()
     st = lib.mf_pcg(C.byref(A), _ptr(b), _ptr(x), C.byref(opts), C.byref(res), _stream(stream))
     out = {"iterations": res.iterations, "converged": bool(res.converged), "fallbacks": res.fallbacks,
-           "true_relres": res.true_relres, "status": st}
+           "restarts": res.restarts, "true_relres": res.true_relres, "status": st}
     if st != OK and raise_on_fail:
         raise MFError(st, lib.mf_last_error().decode())
     return x, out
@@ -575,11 +576,11 @@ def pcg_noalloc(row_ptr, col_idx, values, b, x, tol=1e-8, maxit=20000, precond=P
     _require(b, "b", torch.float64, optional=False)
     _require(x, "x", torch.float64, n, optional=False)
     A = _CSR(n, _ptr_any(row_ptr), _ptr_any(col_idx), _ptr(values))
-    opts = _PcgOpts(tol, maxit, check_every, 0, precond, None)
+    opts = _PcgOpts(tol, maxit, check_every, 0, precond, 0, None)
     res = _PcgResult()
     st = lib.mf_pcg_noalloc(C.byref(A), _ptr(b), _ptr(x), C.byref(opts), C.byref(res), _stream(stream))
     out = {"iterations": res.iterations, "converged": bool(res.converged), "fallbacks": res.fallbacks,
-           "true_relres": res.true_relres, "status": st}
+           "restarts": res.restarts, "true_relres": res.true_relres, "status": st}
     if st != OK and raise_on_fail:
         raise MFError(st, lib.mf_last_error().decode())
     return x, out
@@ -600,11 +601,11 @@ def bicgstab(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond
     if x is None:
         x = torch.empty(n, dtype=torch.float64, device=b.device)
     A = _CSR(n, _ptr_any(row_ptr), _ptr_any(col_idx), _ptr(values))
-    opts = _PcgOpts(tol, maxit, check_every, int(bool(use_graph)), precond, None)
+    opts = _PcgOpts(tol, maxit, check_every, int(bool(use_graph)), precond, 0, None)
     res = _PcgResult()
     st = lib.mf_bicgstab(C.byref(A), _ptr(b), _ptr(x), C.byref(opts), C.byref(res), _stream(stream))
     out = {"iterations": res.iterations, "converged": bool(res.converged), "true_relres": res.true_relres,
-           "status": st}
+           "restarts": res.restarts, "status": st}
     if st != OK and raise_on_fail:
         raise MFError(st, lib.mf_last_error().decode())
     return x, out

@@ -272,6 +272,8 @@ static mf_status pcg_args(const mf_csr* A, const double* b, double* x, const mf_
     a->check_every = opts->check_every;
     a->use_graph = opts->use_graph && stream != nullptr;
     a->stream = (hipStream_t)stream;
+    if (opts->stall_iters < 0) return set_error(MF_ERR_ARG, "stall_iters must be >= 0");
+    a->stall_iters = opts->stall_iters;
     switch (opts->precond) {
         case MF_PRECOND_NONE: a->precond = MF_PRECOND_NONE; break;
         case MF_PRECOND_JACOBI: a->precond = MF_PRECOND_JACOBI; break;

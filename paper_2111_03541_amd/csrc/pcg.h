@@ -26,6 +26,7 @@ struct PcgArgs {
     int check_every;
     int use_graph;
     int precond;  // MF_PRECOND_NONE, MF_PRECOND_JACOBI or MF_PRECOND_EXTERNAL
+    int stall_iters;  // iterations without progress that trigger a restart (0 = 512)
     PcgApply apply;
     void* apply_ctx;
     int apply_graph_safe;

@@ -346,6 +346,33 @@ __global__ void __launch_bounds__(kThreads) k_true_res(int n, const int32_t* __r
     }
 }
 
+// restart from the current x: r = b - A x, z = D^-1 r (or r), p = z
+__global__ void __launch_bounds__(kThreads) k_restart(int n, const int32_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                                      const double* __restrict__ x, const double* __restrict__ b,
+                                                      const double* __restrict__ dinv, int jacobi,
+                                                      double* __restrict__ r, double* __restrict__ z,
+                                                      double* __restrict__ p)
+{
+    const int lane = threadIdx.x % kLanesPerRow;
+    const int sub = threadIdx.x / kLanesPerRow;
+    int r0, r1;
+    row_range(n, r0, r1);
+    for (int base = r0; base < r1; base += kSlots) {
+        const int row = base + sub;
+        double sacc = 0.0;
+        if (row < r1) sacc = row_dot(rp[row], rp[row + 1], lane, ci, v, x);
+        sacc = row_lanes_sum(sacc);
+        if (row < r1 && lane == 0) {
+            const double ri = b[row] - sacc;
+            const double zi = jacobi ? dinv[row] * ri : ri;
+            r[row] = ri;
+            z[row] = zi;
+            p[row] = zi;
+        }
+    }
+}
+
 __global__ void k_reduce2(const double* __restrict__ partial, int nb, double* __restrict__ out)
 {
     __shared__ double sh[kThreads / 64];
@@ -646,6 +673,7 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res, double* scratch)
     res->iterations = 0;
     res->true_relres = 0.0;
     res->fallbacks = 0;
+    res->restarts = 0;
     res->converged = 0;
     if (n == 0) {
         res->converged = 1;
@@ -704,7 +732,7 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res, double* scratch)
             return set_error(MF_ERR_OOM, "PCG workspace allocation failed");
     }
 
-    const bool external = a.precond == MF_PRECOND_EXTERNAL;
+    bool external = a.precond == MF_PRECOND_EXTERNAL;  // false again after a restart
     const int jac = a.precond == MF_PRECOND_NONE ? 0 : 1;  // Jacobi z (also the external fallback)
 
     // ELL copy of K for the iterations when the padding stays small (not with a
@@ -816,8 +844,31 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res, double* scratch)
         }
     } gf{&exec, &graph};
 
+    // Stagnation: stall_iters iterations without the recurrence residual falling below
+    // kStallDrop times its best (judged at the host checks), or a recurrence residual
+    // below tol whose true residual is not.  Either restarts from the current x with the
+    // true residual and a Jacobi (or no) preconditioner, at most kMaxRestarts times.
+    constexpr int kMaxRestarts = 8;
+    constexpr double kStallDrop = 0.9;
+    const int stall_iters = a.stall_iters > 0 ? a.stall_iters : 512;
+    double best = 1.0;
+    int it = 0, it_best = 0;
+    auto restart = [&]() -> mf_status {
+        if (external) {  // the rest of the solve is Jacobi-PCG; the graph held the external step
+            external = false;
+            use_graph = false;
+        }
+        k_restart<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, a.x, a.b, dinv, jac, r, z, p);
+        k_dots<<<vec_blocks, kThreads, 0, s>>>(n, r, z, nullptr, partial);
+        k_reduce_beta<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, 0, 1);
+        MF_HIP(hipGetLastError());
+        ++res->restarts;
+        it_best = it;
+        best = 1.0;
+        return MF_OK;
+    };
+
     double h[S_COUNT];
-    int it = 0;
     const double tol = a.tol;
     while (it < a.maxit) {
         const int todo = std::min(chunk, a.maxit - it);
@@ -838,7 +889,8 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res, double* scratch)
             res->iterations = it;
             return set_error(MF_ERR_NONFINITE, "PCG breakdown (p.Kp <= 0 or r.z <= 0) near iteration %d", it);
         }
-        if (std::sqrt(h[S_RR]) / bnorm <= tol) {
+        const double rel = std::sqrt(h[S_RR]) / bnorm;
+        if (rel <= tol) {
             // true residual as judge
             k_true_res<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, a.x, a.b, partial);
             k_reduce2<<<1, kThreads, 0, s>>>(partial, spmv_blocks, sc + S_COUNT);
@@ -850,6 +902,18 @@ mf_status run_pcg(const PcgArgs& a, mf_pcg_result* res, double* scratch)
                 res->converged = 1;
                 return MF_OK;
             }
+            if (res->restarts < kMaxRestarts) {  // the recurrence drifted from b - K x
+                mf_status st = restart();
+                if (st != MF_OK) return st;
+            }
+            continue;
+        }
+        if (rel < kStallDrop * best) {
+            best = rel;
+            it_best = it;
+        } else if (it - it_best >= stall_iters && res->restarts < kMaxRestarts) {
+            mf_status st = restart();
+            if (st != MF_OK) return st;
         }
     }
     k_true_res<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, a.x, a.b, partial);
@@ -870,6 +934,7 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
     res->iterations = 0;
     res->true_relres = 0.0;
     res->fallbacks = 0;
+    res->restarts = 0;
     res->converged = 0;
     if (n == 0) {
         res->converged = 1;
@@ -1031,6 +1096,7 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
                                  "BiCGStab breakdown near iteration %d after %d restarts (true relative residual %.3e)",
                                  it, restarts - 1, res->true_relres);
             }
+            res->restarts = restarts;
             spmv(a.x, t, nullptr, nullptr);
             k_bcg_restart<<<vec_blocks, kThreads, 0, s>>>(n, a.b, t, r, rh, p, v, partial);
             k_bcg_beta<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, 1);

@@ -95,3 +95,39 @@ def test_binding_require_checks_dtype_layout_and_size():
         mf._require(FakeCuda(torch.zeros(6, dtype=torch.float32)), "coords", torch.float64, 6)
     with pytest.raises(ValueError, match="contiguous"):
         mf._require(FakeCuda(torch.zeros(4, 6, dtype=torch.float64).t()), "state", torch.float64, 24)
+
+
+STRUCTS = {  # binding structure -> C type in mf.h
+    "_Mesh": "mf_mesh", "_Dofs": "mf_dofs", "_Form": "mf_form", "_Fields": "mf_fields",
+    "_Quad": "mf_quadrature", "_CSR": "mf_csr", "_PcgOpts": "mf_pcg_opts", "_PcgResult": "mf_pcg_result",
+    "_TransientOpts": "mf_transient_opts", "_TransientResult": "mf_transient_result", "_BForm": "mf_bform",
+    "_BSet": "mf_bset", "_NewtonOpts": "mf_newton_opts", "_NewtonResult": "mf_newton_result",
+    "_BatchProblem": "mf_batch_problem",
+}
+
+
+def test_binding_structures_match_the_header_layout(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets of its C type
+    (a C probe compiled against include/mf.h prints them)."""
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mf.h"', "int main(void) {"]
+    for py, c in STRUCTS.items():
+        lines.append(f'printf("{py} size %zu\\n", sizeof({c}));')
+        for name, _ in getattr(mf, py)._fields_:
+            lines.append(f'printf("{py} {name} %zu\\n", offsetof({c}, {name}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for py in STRUCTS:
+        S = getattr(mf, py)
+        assert got[(py, "size")] == C_sizeof(S), py
+        for name, _ in S._fields_:
+            assert got[(py, name)] == getattr(S, name).offset, (py, name)
+
+
+def C_sizeof(S):
+    import ctypes
+    return ctypes.sizeof(S)

@@ -109,3 +109,51 @@ def test_jacobi_pcg_96cubed_matches_oracle(mf):
     dx = np.max(np.abs(xh - x_ref)) / np.max(np.abs(x_ref))
     say(f"  solution difference {dx:.2e}")
     assert dx <= 1e-7
+
+
+def test_pcg_restarts_at_the_attainable_accuracy(mf):
+    """A tolerance below what FP64 can reach: the recurrence residual keeps falling while
+    the true residual stays at its rounding floor, or the recurrence stalls.  Either way
+    the solve restarts from the current x (true residual, Jacobi direction) until the
+    cap of 8 restarts, ends with MF_ERR_NOT_CONVERGED at maxit, and leaves the accurate
+    iterate it reached."""
+    say("pcg restart at the rounding floor")
+    pat, K, d = poisson_system((16, 16, 16), 1.5, 3)
+    rp, ci, v, b = to_dev(pat, K, d)
+    x, res = mf.pcg(rp, ci, v, b, tol=1e-17, maxit=3000, check_every=4, stall_iters=16, raise_on_fail=False)
+    torch.cuda.synchronize()
+    say(f"  {res}")
+    assert res["status"] == mf.ERR_NOT_CONVERGED and not res["converged"]
+    assert res["restarts"] == 8 and res["iterations"] == 3000
+    S = pat.to_scipy(K)
+    xh = x.cpu().numpy()
+    assert np.all(np.isfinite(xh)) and res["true_relres"] < 1e-13
+    direct = spla.spsolve(S.tocsc(), d)
+    assert np.max(np.abs(xh - direct)) <= 1e-9 * np.max(np.abs(direct))
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "nn"])
+def test_stagnation_restart_keeps_the_solve_converging(mf, precond):
+    """Stagnation forced from the host: with stall_iters = 1 every iteration that does not
+    cut the residual by 10% counts as a stall, so the solve restarts (at most 8 times);
+    an NN-preconditioned solve (an untrained network here) continues as Jacobi-PCG.  The
+    solve still reaches the 1e-8 true residual and the direct solution."""
+    say("pcg forced stagnation", precond)
+    pat, K, d = poisson_system((16, 16, 16), 1.5, 5)
+    rp, ci, v, b = to_dev(pat, K, d)
+    net = None
+    if precond == "nn":
+        mask = W.boundary_node_mask(pat.mesh.shape)
+        net = mf.Net((17, 17, 17), [1, 4, 8, 8], seed=4)
+        net.set_system(rp, ci, v, torch.from_numpy(mask).cuda())
+    pc = mf.PRECOND_NN if net is not None else mf.PRECOND_JACOBI
+    x, res = mf.pcg(rp, ci, v, b, tol=1e-8, maxit=5000, precond=pc, net=net, check_every=1, stall_iters=1)
+    torch.cuda.synchronize()
+    say(f"  {res}")
+    assert res["converged"] and res["true_relres"] <= 1e-8
+    assert 1 <= res["restarts"] <= 8
+    S = pat.to_scipy(K)
+    xh = x.cpu().numpy()
+    assert np.linalg.norm(d - S @ xh) / np.linalg.norm(d) <= 1e-8
+    direct = spla.spsolve(S.tocsc(), d)
+    assert np.max(np.abs(xh - direct)) <= 1e-6 * np.max(np.abs(direct))
