@@ -450,7 +450,10 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
 
     if (valid) {
         const int fb = 2 * bq;  // first element node of this lane's pair
-#pragma unroll 2
+        // FP64: unrolled over the eight points; FP32 (three workgroups per CU) keeps two
+        // per trip, which holds it within its register budget
+        constexpr int kUnrollQ = sizeof(T) == 8 ? 8 : 2;
+#pragma unroll kUnrollQ
         for (int q = 0; q < 8; ++q) {
             const T* hq = he + q * HLayout<FORM, T>::SQ;
             if constexpr (FORM == MF_FORM_MASS) {
@@ -991,10 +994,18 @@ template <int FORM, bool MASK, typename T>
 __global__ void __launch_bounds__(kThreads, (MinBlocks<FORM, T>::value)) k_assemble_column(ColParams p)
 {
     __shared__ ColShared<FORM, T> S;
-    if constexpr (FORM == MF_FORM_NS_SUPG)
+    if constexpr (FORM == MF_FORM_NS_SUPG) {
         column_body_ns<MASK, T>(p, blockIdx.x, S);
-    else
+    } else if constexpr (sizeof(T) == 8) {
+        // workgroups are dealt to the eight XCDs in turn; give each XCD a run of
+        // consecutive columns, so that the halo nodes neighbouring columns share are read
+        // into one L2 (a bijection of [0, gridDim.x); the FP32 forms measured slower with it)
+        const int nb = (int)gridDim.x, full = nb / 8, rem = nb % 8;
+        const int x = (int)blockIdx.x % 8, k = (int)blockIdx.x / 8;
+        column_body<FORM, MASK, T>(p, x * full + min(x, rem) + k, S);
+    } else {
         column_body<FORM, MASK, T>(p, blockIdx.x, S);
+    }
 }
 
 // ------------------------------------------------------------------------------------
