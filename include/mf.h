@@ -461,7 +461,9 @@ typedef struct {
     double atol;            /* ... or |d|_2 <= atol (d_0: the residual of the initial state) */
     int32_t max_steps;      /* updates at most                                              */
     double lin_tol;         /* floor of the linear solves' relative true-residual tolerance:
-                               step k asks for max(lin_tol, min(0.1, |d_k|_2 / |d_0|_2))   */
+                               step k asks for max(lin_tol, min(0.1, |d_k|_2 / |d_0|_2),
+                               min(0.5, 0.5 t / |d_k|_2)), t = max(rtol |d_0|_2, atol): no
+                               tighter than the final residual test needs                 */
     int32_t lin_maxit;
     int32_t check_every;    /* linear solve: iterations between host checks (0 = 8)          */
     int32_t use_graph;      /* linear solve: replay chunks as a HIP graph (non-default stream) */

@@ -175,7 +175,12 @@ extern "C" mf_status mf_ns_newton_ex(const mf_pattern_t* P, const mf_form* form,
         }
         if (k == opts->max_steps) break;
         mf_pcg_result lr{};
-        lo.tol = std::max(opts->lin_tol, std::min(0.1, d0 > 0.0 ? norm / d0 : 0.1));
+        // forcing term: the relative residual reached so far (at most 0.1), but no tighter
+        // than half of what the final test still needs (target / |d_k|), so the last
+        // steps do not ask the linear solver for accuracy the Newton test never uses
+        const double target = std::max(opts->rtol * d0, opts->atol);
+        lo.tol = std::max({opts->lin_tol, std::min(0.1, d0 > 0.0 ? norm / d0 : 0.1),
+                           std::min(0.5, 0.5 * target / norm)});
         st = mf_bicgstab(&A, d, du, &lo, &lr, stream);
         res->lin_iterations += lr.iterations;
         const bool usable = (st == MF_ERR_NOT_CONVERGED || st == MF_ERR_NONFINITE) &&

@@ -161,3 +161,24 @@ def test_newton_max_steps_and_converged_start(mf):
     # a state that already satisfies the test takes no step
     st, res, st0, mask = run_gpu_newton(mf, mesh, "cavity", p, atol=1e3)
     assert res["converged"] and res["steps"] == 0 and np.array_equal(st, st0)
+
+
+def test_newton_cavity_48_converges_reproducibly(mf):
+    """The cavity on the flow Jacobian's 48^3 mesh (470,596 unknowns): Newton with Jacobi-
+    BiCGStab converges to |R| / |R_0| <= 1e-10, two runs take the same linear iterations
+    and end in the same state bit for bit, and the oracle's own residual of that state
+    meets the same test."""
+    say("newton cavity 48^3")
+    n = 48
+    mesh = W.structured_mesh((n, n, n))
+    p = prm(n)
+    st, res, st0, mask = run_gpu_newton(mf, mesh, "cavity", p, rtol=1e-10, lin_tol=1e-10)
+    say(f"  steps {res['steps']} lin {res['lin_iterations']} res {['%.2e' % r for r in res['res_norm']]}")
+    assert res["converged"] and res["steps"] <= 8
+    st2, res2, _, _ = run_gpu_newton(mf, mesh, "cavity", p, rtol=1e-10, lin_tol=1e-10)
+    assert res2["lin_iterations"] == res["lin_iterations"] and np.array_equal(st2, st)
+    pat = O.Pattern(mesh, 4)
+    _, d0 = O.assemble(pat, O.NS_SUPG, p, state=st0, dirichlet=mask, want_K=False)
+    _, d = O.assemble(pat, O.NS_SUPG, p, state=st, dirichlet=mask, want_K=False)
+    assert abs(res["res_norm"][0] - np.linalg.norm(d0)) <= 1e-12 * np.linalg.norm(d0)
+    assert np.linalg.norm(d) <= 1e-10 * np.linalg.norm(d0)
