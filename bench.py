@@ -34,7 +34,7 @@ HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
 # FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a 1 GiB copy (summary in
 # profiles/assemble_column_elasticity64_f64_counters.md); used only while the library
 # reports the kernel revision it was measured on.
-MEASURED_TRAFFIC = {"revision": "assembly column-4x2 r9", "bytes": 649.34e6}
+MEASURED_TRAFFIC = {"revision": "assembly column-4x2 r10", "bytes": 564.87e6}
 FP64_PEAK = 78.6e12        # flop/s, vector and matrix
 FP32_PEAK = 157.3e12       # flop/s, matrix (vector without packed math: half)
 NS_FLOP_PER_ELEM = 8 * 8 * 16 * 8 * 4 * 2  # flow Jacobian: (a, q) pairs x tile product, FMA = 2 flop

@@ -61,7 +61,7 @@ const char* mf_last_error(void) { return g_err; }
 
 // The assembly kernel revision is part of the string so that measurements taken on one
 // revision (for example HBM byte counters) can be matched to it.
-const char* mf_version(void) { return "metafem-mi 0.2 (gfx950; assembly column-4x2 r9; flow mfma-4x4 r3)"; }
+const char* mf_version(void) { return "metafem-mi 0.2 (gfx950; assembly column-4x2 r10; flow mfma-4x4 r3)"; }
 
 mf_status mf_pattern(const mf_mesh* mesh, mf_elem_type type, int32_t order, const mf_dofs* dofs,
                      void* stream, mf_pattern_t** out)
