@@ -59,8 +59,8 @@ static_assert(kTileNodes <= kPfElemT0 && kPfElemT0 + kLayerElems <= kPfInfoT0 &&
               "prefetch roles");
 
 // LDS layout of the per-Gauss-point records (in units of T).  Symmetric forms store h
-// (24 values); the flow form stores h, sqrt(W) N, sqrt(W) u.grad N, the state terms
-// u, grad u, Rm, sqrt(W), p and div u (58 values, NsRec below).  The strides spread the
+// (24 values); the flow form stores (sqrt(W) N_a, sqrt(W) grad N_a) for the eight nodes
+// and the state terms u, grad u, Rm, sqrt(W), p and div u (50 values, NsRec below).  The strides spread the
 // phase-B reads of one wave (eight nodes x two elements x four quarters) over the LDS
 // banks: with an odd FP64 element stride the ten elements a wave reads start on distinct
 // banks, which cuts the conflict degree of the h_b reads from 5 to 3 (32 banks).
