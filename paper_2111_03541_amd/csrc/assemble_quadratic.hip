@@ -366,19 +366,26 @@ __global__ void __launch_bounds__((Cfg<ET, FORM>::THREADS)) k_assemble_quadratic
     const int64_t rs = p.row_ptr[row];
     const int64_t deg = p.nbr_ptr[va + 1] - p.nbr_ptr[va];
     T* K = (T*)p.K;
-    for (int b = NBQ * quarter; b < NBQ * quarter + NBQ; ++b) {
-        double acc[NF];
+    const int b0 = NBQ * quarter;
+    // the part's column nodes all at once, Gauss point by Gauss point (the sum over the
+    // points of each entry keeps its order)
+    double acc[NBQ][NF];
 #pragma unroll
-        for (int j = 0; j < NF; ++j) acc[j] = 0.0;
-        for (int q = 0; q < NQ; ++q) {
-            const double W = S.W[q];
+    for (int bb = 0; bb < NBQ; ++bb)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) acc[bb][j] = 0.0;
+    for (int q = 0; q < NQ; ++q) {
+        const double W = S.W[q];
+#pragma unroll
+        for (int bb = 0; bb < NBQ; ++bb) {
+            const int b = b0 + bb;
             if constexpr (C::NS) {
                 double v[NF];
                 ns_entries<DIM>(p.form, i, S.N[q][a], S.g[q][a], S.N[q][b], S.g[q][b], S.fs[q], v);
 #pragma unroll
-                for (int j = 0; j < NF; ++j) acc[j] = fma(W, v[j], acc[j]);
+                for (int j = 0; j < NF; ++j) acc[bb][j] = fma(W, v[j], acc[bb][j]);
             } else if constexpr (FORM == MF_FORM_MASS) {
-                acc[0] = fma(W * coef * S.N[q][a], S.N[q][b], acc[0]);
+                acc[bb][0] = fma(W * coef * S.N[q][a], S.N[q][b], acc[bb][0]);
             } else {
                 double ga[DIM], gb[DIM], gg = 0.0;
 #pragma unroll
@@ -388,21 +395,32 @@ __global__ void __launch_bounds__((Cfg<ET, FORM>::THREADS)) k_assemble_quadratic
                     gg = fma(ga[m], gb[m], gg);
                 }
                 if constexpr (FORM == MF_FORM_POISSON) {
-                    acc[0] = fma(W * coef, gg, acc[0]);
+                    acc[bb][0] = fma(W * coef, gg, acc[bb][0]);
                 } else {
 #pragma unroll
                     for (int j = 0; j < NF; ++j)
-                        acc[j] += W * (lam * ga[i] * gb[j] + mu * ga[j] * gb[i] + (i == j ? mu * gg : 0.0));
+                        acc[bb][j] += W * (lam * ga[i] * gb[j] + mu * ga[j] * gb[i] + (i == j ? mu * gg : 0.0));
                 }
             }
         }
-        const int64_t rk = p.rank[(int64_t)(a * NEN + b) * p.n_el + e];
-#pragma unroll
-        for (int j = 0; j < NF; ++j) {
-            const int64_t pos = p.field_major ? rs + j * deg + rk : rs + rk * NF + j;
-            K[pos] += (T)acc[j];
-        }
     }
+    // every old value of the part is loaded before the first store, so the lane's
+    // read-modify-writes overlap instead of running one after another
+    int rk[NBQ];
+#pragma unroll
+    for (int bb = 0; bb < NBQ; ++bb) rk[bb] = p.rank[(int64_t)(a * NEN + b0 + bb) * p.n_el + e];
+    auto pos_of = [&](int bb, int j) -> int64_t {
+        return p.field_major ? rs + j * deg + rk[bb] : rs + (int64_t)rk[bb] * NF + j;
+    };
+    T old[NBQ][NF];
+#pragma unroll
+    for (int bb = 0; bb < NBQ; ++bb)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) old[bb][j] = K[pos_of(bb, j)];
+#pragma unroll
+    for (int bb = 0; bb < NBQ; ++bb)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) K[pos_of(bb, j)] = old[bb][j] + (T)acc[bb][j];
     if (quarter != 0) return;
     double dv = 0.0;
     if constexpr (C::NS) {
