@@ -108,22 +108,33 @@ __global__ void __launch_bounds__(kThreads) k_assemble_atomic(AtomicParams p)
     const int64_t deg = p.nbr_ptr[va + 1] - p.nbr_ptr[va];
     T* K = (T*)p.K;
     T* d = (T*)p.d;
+    int rk[NEN];
 #pragma unroll
-    for (int b = 0; b < NEN; ++b) {
-        const int64_t rk = p.rank[(int64_t)(a * NEN + b) * n_el + e];
+    for (int b = 0; b < NEN; ++b) rk[b] = p.rank[(int64_t)(a * NEN + b) * n_el + e];
+    auto pos_of = [&](int b, int j) -> int64_t {
+        return p.field_major ? rs + j * deg + rk[b] : rs + (int64_t)rk[b] * NF + j;
+    };
+    if constexpr (COLOURED) {
+        // every old value of the row is loaded before the first store, so the thread's
+        // read-modify-writes overlap instead of running one after another
+        T old[NEN * NF];
 #pragma unroll
-        for (int j = 0; j < NF; ++j) {
-            const int64_t pos = p.field_major ? rs + j * deg + rk : rs + rk * NF + j;
-            if constexpr (COLOURED)
-                K[pos] += krow[b * NF + j];
-            else
-                unsafeAtomicAdd(K + pos, krow[b * NF + j]);
-        }
-    }
-    if constexpr (COLOURED)
-        d[row] -= rrow;
-    else
+        for (int b = 0; b < NEN; ++b)
+#pragma unroll
+            for (int j = 0; j < NF; ++j) old[b * NF + j] = K[pos_of(b, j)];
+        const T dold = d[row];
+#pragma unroll
+        for (int b = 0; b < NEN; ++b)
+#pragma unroll
+            for (int j = 0; j < NF; ++j) K[pos_of(b, j)] = old[b * NF + j] + krow[b * NF + j];
+        d[row] = dold - rrow;
+    } else {
+#pragma unroll
+        for (int b = 0; b < NEN; ++b)
+#pragma unroll
+            for (int j = 0; j < NF; ++j) unsafeAtomicAdd(K + pos_of(b, j), krow[b * NF + j]);
         unsafeAtomicAdd(d + row, -rrow);
+    }
 }
 
 template <typename T>

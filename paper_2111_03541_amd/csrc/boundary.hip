@@ -280,21 +280,32 @@ __device__ __forceinline__ void boundary_row(const BParams& p, int64_t e, uint32
     const int64_t deg = p.nbr_ptr[va + 1] - p.nbr_ptr[va];
     T* K = (T*)p.K;
     T* d = (T*)p.d;
+    // nonzero entries only; every old value is loaded before the first store, so the
+    // thread's read-modify-writes overlap instead of running one after another
+    int rk[8];
+#pragma unroll
     for (int b = 0; b < 8; ++b) {
         bool any = false;
 #pragma unroll
         for (int l = 0; l < KC; ++l) any = any || krow[b][l] != 0.0;
-        if (!any) continue;
-        const int64_t rk = p.rank[(int64_t)(a * 8 + b) * p.n_el + e];
-#pragma unroll
-        for (int l = 0; l < KC; ++l) {
-            if (krow[b][l] == 0.0) continue;
-            const int j = KC == 1 ? i : l;
-            const int64_t pos = p.field_major ? rs + j * deg + rk : rs + rk * NF + j;
-            K[pos] += (T)krow[b][l];
-        }
+        rk[b] = any ? (int)p.rank[(int64_t)(a * 8 + b) * p.n_el + e] : 0;
     }
-    if (rrow != 0.0) d[row] += (T)(-rrow);
+    auto pos_of = [&](int b, int l) -> int64_t {
+        const int j = KC == 1 ? i : l;
+        return p.field_major ? rs + j * deg + rk[b] : rs + (int64_t)rk[b] * NF + j;
+    };
+    T old[8][KC];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+        for (int l = 0; l < KC; ++l) old[b][l] = krow[b][l] != 0.0 ? K[pos_of(b, l)] : T(0);
+    const T dold = rrow != 0.0 ? d[row] : T(0);
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+        for (int l = 0; l < KC; ++l)
+            if (krow[b][l] != 0.0) K[pos_of(b, l)] = old[b][l] + (T)krow[b][l];
+    if (rrow != 0.0) d[row] = dold + (T)(-rrow);
 }
 
 // Items (element with listed faces of the colour, element node a, field i), strided over
