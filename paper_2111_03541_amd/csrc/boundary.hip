@@ -749,17 +749,34 @@ __global__ void k_face_mark(const int32_t* __restrict__ fe, const uint8_t* __res
                             uint32_t* __restrict__ ccount, unsigned long long* __restrict__ status)
 {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= n) return;
-    const int64_t e = fe[f];
-    const int lf = fid[f];
-    if (e < 0 || e >= n_el || lf > 5) {
-        atomicMin(status + 1, (unsigned long long)f);
-        return;
+    int64_t e = -1;
+    int c = -1;  // colour of an element this face touches first
+    if (f < n) {
+        e = fe[f];
+        const int lf = fid[f];
+        if (e < 0 || e >= n_el || lf > 5) {
+            atomicMin(status + 1, (unsigned long long)f);
+        } else {
+            atomicAdd(cnt + 6 * e + lf, 1u);
+            if (atomicOr(mask + e, 1u << lf) == 0u) c = ecol[e];
+        }
     }
-    atomicAdd(cnt + 6 * e + lf, 1u);
-    if (atomicOr(mask + e, 1u << lf) == 0u) {
-        const int c = ecol[e];
-        clist[cptr[c] + atomicAdd(ccount + c, 1u)] = (int32_t)e;
+    // append to the colour lists with one counter update per (wave, colour): the lanes
+    // of one colour take consecutive slots after the leader's atomic add
+    const int lane = (int)(threadIdx.x & 63);
+    unsigned long long pending = __ballot(c >= 0);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int cc = __shfl(c, leader, 64);
+        const unsigned long long group = __ballot(c == cc);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(ccount + cc, (uint32_t)__popcll(group));
+        base = (uint32_t)__shfl((int)base, leader, 64);
+        if (c == cc) {
+            const uint32_t below = (uint32_t)__popcll(group & ((1ull << lane) - 1ull));
+            clist[cptr[cc] + base + below] = (int32_t)e;
+        }
+        pending &= ~group;
     }
 }
 
