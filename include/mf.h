@@ -207,8 +207,8 @@ typedef struct {
 } mf_batch_problem;
 
 /* (sync) Copies the problem descriptors to the device; the arrays they point to must
-   stay valid while the batch is used.  Default launch: round-robin items, one (FP64) or
-   two (FP32) workgroups per CU. */
+   stay valid while the batch is used.  Default launch (before mf_batch_tune): round-
+   robin items, whole columns, one workgroup per CU. */
 mf_status mf_batch_create(const mf_batch_problem* problems /* (host) [n] */, int32_t n,
                           mf_precision precision, mf_batch_t** out);
 
@@ -217,9 +217,9 @@ mf_status mf_batch_create(const mf_batch_problem* problems /* (host) [n] */, int
    column height NZ = nz + 1: <= 20, <= 34, larger): a tile is a 4x2 node column cut along
    z into 1..4 chunks, and the chunk count of each class is chosen by coordinate descent.
    Then the launch shape for those tiles (work-item order: problem-major, round-robin,
-   elasticity-first; workgroups per CU: 1, 2).  cache_path (host string, may be NULL) is a
-   text file of tuned choices keyed by device, precision, problems per class and column
-   count: a hit skips timing. */
+   elasticity-first; workgroups per CU: 1, 2 in FP64, 1..3 in FP32).  cache_path (host
+   string, may be NULL) is a text file of tuned choices keyed by device, precision,
+   Dirichlet flags, problems per class and column count: a hit skips timing. */
 mf_status mf_batch_tune(mf_batch_t* batch, const char* cache_path, void* stream);
 
 /* (sync) Tile shapes: *n_classes (6) classes ordered (form: 0 mass/Poisson, 1 elasticity)

@@ -50,7 +50,11 @@ template <int FORM, typename T>
 struct MinBlocks {
     static constexpr int value = (sizeof(T) == 4 && FORM != MF_FORM_NS_SUPG) ? 3 : 2;
 };
-constexpr int kMinBlocks = 2;                // the batched kernel (largest case)
+// the batched kernel: its LDS is the union of the symmetric forms' (FP32: 49.5 KB)
+template <typename T>
+struct BatchMinBlocks {
+    static constexpr int value = sizeof(T) == 4 ? 3 : 2;
+};
 constexpr int kGeomItems = kLayerElems * 8;  // (element, Gauss point)
 constexpr int kPfElemT0 = 64, kPfInfoT0 = 96;  // phase B prefetch roles: [0, tile), [64, ..), [96, ..)
 static_assert(kGeomItems <= kGeomThreads && kGeomThreads < kThreads, "one lane per (element, Gauss point)");
@@ -1036,8 +1040,9 @@ __global__ void k_batch_reset(int* counter, unsigned long long* const* status, i
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kThreads, kMinBlocks)
+// MASK: some problem of the batch has Dirichlet flags
+template <typename T, bool MASK>
+__global__ void __launch_bounds__(kThreads, (BatchMinBlocks<T>::value))
     k_batch_persistent(const BatchProblemDev* __restrict__ probs, const int2* __restrict__ items, int n_items,
                        int* __restrict__ counter)
 {
@@ -1053,11 +1058,11 @@ __global__ void __launch_bounds__(kThreads, kMinBlocks)
         const ColParams cp = probs[w.x].cp;
         const int kind = probs[w.x].kind;
         if (kind == MF_FORM_ELASTICITY)
-            column_body<MF_FORM_ELASTICITY, true, T>(cp, w.y, S.elasticity);
+            column_body<MF_FORM_ELASTICITY, MASK, T>(cp, w.y, S.elasticity);
         else if (kind == MF_FORM_POISSON)
-            column_body<MF_FORM_POISSON, true, T>(cp, w.y, S.poisson);
+            column_body<MF_FORM_POISSON, MASK, T>(cp, w.y, S.poisson);
         else
-            column_body<MF_FORM_MASS, true, T>(cp, w.y, S.mass);
+            column_body<MF_FORM_MASS, MASK, T>(cp, w.y, S.mass);
     }
 }
 
@@ -1203,17 +1208,27 @@ mf_status batch_upload(const std::vector<AssembleArgs>& probs, const std::vector
 }
 
 mf_status batch_launch(const void* dev_probs, void* dev_status, int n_probs, const int2* items, int n_items,
-                       int* counter, int n_wg, mf_precision prec, hipStream_t s)
+                       int* counter, int n_wg, mf_precision prec, bool masked, hipStream_t s)
 {
     k_batch_reset<<<(n_probs + 255) / 256 > 0 ? (n_probs + 255) / 256 : 1, 256, 0, s>>>(
         counter, (unsigned long long* const*)dev_status, n_probs);
-    if (prec == MF_F64)
-        k_batch_persistent<double><<<n_wg, kThreads, 0, s>>>((const BatchProblemDev*)dev_probs, items, n_items, counter);
-    else
-        k_batch_persistent<float><<<n_wg, kThreads, 0, s>>>((const BatchProblemDev*)dev_probs, items, n_items, counter);
+    const BatchProblemDev* pr = (const BatchProblemDev*)dev_probs;
+    if (prec == MF_F64) {
+        if (masked)
+            k_batch_persistent<double, true><<<n_wg, kThreads, 0, s>>>(pr, items, n_items, counter);
+        else
+            k_batch_persistent<double, false><<<n_wg, kThreads, 0, s>>>(pr, items, n_items, counter);
+    } else {
+        if (masked)
+            k_batch_persistent<float, true><<<n_wg, kThreads, 0, s>>>(pr, items, n_items, counter);
+        else
+            k_batch_persistent<float, false><<<n_wg, kThreads, 0, s>>>(pr, items, n_items, counter);
+    }
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
+
+int batch_max_wg_per_cu(mf_precision prec) { return prec == MF_F64 ? BatchMinBlocks<double>::value : BatchMinBlocks<float>::value; }
 
 // Returns MF_ERR_UNSUPPORTED (without launching) when the case is not covered:
 // unstructured meshes, 2D, partial coupling, or the flow form in FP64.

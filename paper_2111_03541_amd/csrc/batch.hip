@@ -31,6 +31,7 @@ struct mf_batch_s {
     std::vector<int> cls;        // class of each problem
     int chunks[kClasses] = {1, 1, 1, 1, 1, 1};
     mf_precision prec = MF_F64;
+    bool masked = false;  // some problem has Dirichlet flags
     void* dprobs = nullptr;
     void* dstatus = nullptr;
     int* counter = nullptr;
@@ -142,7 +143,8 @@ std::string tune_key(const mf_batch_s* B)
     double lg = std::floor(std::log10((double)std::max<int64_t>(1, cols)));
     long bucket = (long)(std::round(cols / std::pow(10.0, lg - 1)) * std::pow(10.0, lg - 1));
     std::ostringstream os;
-    os << "gfx950|column-v2|prec=" << (B->prec == MF_F64 ? "f64" : "f32") << "|classes=";
+    os << "gfx950|column-v3|prec=" << (B->prec == MF_F64 ? "f64" : "f32") << "|mask=" << (B->masked ? 1 : 0)
+       << "|classes=";
     for (int c = 0; c < kClasses; ++c) os << per[c] << (c + 1 < kClasses ? "," : "");
     os << "|columns~" << bucket;
     return os.str();
@@ -193,7 +195,7 @@ void cache_store(const char* path, const std::string& key, int order, int mult, 
 mf_status launch(mf_batch_s* B, hipStream_t s)
 {
     return batch_launch(B->dprobs, B->dstatus, (int)B->probs.size(), B->items, B->n_items, B->counter, B->n_wg,
-                        B->prec, s);
+                        B->prec, B->masked, s);
 }
 
 mf_status time_config(mf_batch_s* B, hipStream_t s, double* us)
@@ -271,6 +273,7 @@ mf_status mf_batch_create(const mf_batch_problem* problems, int32_t n, mf_precis
         a.nodal_src = q.fields.nodal_src;
         a.lin_state = nullptr;
         a.dirichlet = q.fields.dirichlet;
+        if (a.dirichlet) B->masked = true;
         a.prec = prec;
         a.K = q.K;
         a.d = q.d;
@@ -316,8 +319,8 @@ mf_status mf_batch_tune(mf_batch_t* B, const char* cache_path, void* stream)
         return MF_OK;
     }
     // 1. tile height per class, by coordinate descent on the whole batch's time (round-
-    //    robin order, two workgroups per CU), classes with the
-    //    most columns first
+    //    robin order, as many workgroups per CU as the kernel is built for), classes with
+    //    the most columns first
     int present[kClasses] = {0};
     for (size_t k = 0; k < B->probs.size(); ++k) present[B->cls[k]] += (int)batch_units_of(B->probs[k].P, 1);
     std::vector<int> byw;
@@ -325,7 +328,8 @@ mf_status mf_batch_tune(mf_batch_t* B, const char* cache_path, void* stream)
         if (present[c] > 0) byw.push_back(c);
     std::sort(byw.begin(), byw.end(), [&](int a, int b) { return present[a] > present[b]; });
     for (int c = 0; c < kClasses; ++c) B->chunks[c] = 1;
-    B->n_wg = B->num_cus * 2;
+    const int max_mult = batch_max_wg_per_cu(B->prec);
+    B->n_wg = B->num_cus * max_mult;
     double best = 1e300;
     {
         mf_status st = upload_items(B, 1);
@@ -352,11 +356,10 @@ mf_status mf_batch_tune(mf_batch_t* B, const char* cache_path, void* stream)
     // 2. launch shape for those tiles: work-item order x workgroups per CU
     best = 1e300;
     int best_order = 1, best_mult = 1;
-    const int max_mult = 2;
     for (int o = 0; o < 3; ++o) {
         mf_status st = upload_items(B, o);
         if (st != MF_OK) return st;
-        for (int m = 1; m <= max_mult; m *= 2) {
+        for (int m = 1; m <= max_mult; ++m) {
             B->n_wg = B->num_cus * m;
             double t = 0;
             st = time_config(B, s, &t);

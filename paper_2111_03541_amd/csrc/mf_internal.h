@@ -92,7 +92,9 @@ mf_status batch_upload(const std::vector<AssembleArgs>& probs, const std::vector
                        void** dev_status);
 int64_t batch_units_of(const mf_pattern_s* P, int chunks);
 mf_status batch_launch(const void* dev_probs, void* dev_status, int n_probs, const int2* items, int n_items,
-                       int* counter, int n_wg, mf_precision prec, hipStream_t s);
+                       int* counter, int n_wg, mf_precision prec, bool masked, hipStream_t s);
+// workgroups per CU the batched kernel is built for
+int batch_max_wg_per_cu(mf_precision prec);
 
 inline unsigned blocks_for(int64_t n, int threads) {
     return (unsigned)((n + threads - 1) / threads);
