@@ -214,22 +214,27 @@ mf_status mf_batch_create(const mf_batch_problem* problems /* (host) [n] */, int
 
 /* (sync) Autotuner, timing candidates on the batch itself.  First the tile shape per class
    of problems, a class being (form: mass/Poisson or elasticity) x (size bucket of the
-   column height NZ = nz + 1: <= 20, <= 34, larger): a tile is a 4x2 node column cut along
-   z into 1..4 chunks, and the chunk count of each class is chosen by coordinate descent.
-   Then the launch shape for those tiles (work-item order: problem-major, round-robin,
-   elasticity-first; workgroups per CU: 1, 2 in FP64, 1..3 in FP32).  cache_path (host
+   column height NZ = nz + 1: <= 20, <= 34, larger): a tile is a 4x2 or 2x4 node column cut
+   along z into 1..4 chunks, and the shape of each class is chosen by coordinate descent.
+   Then the launch shape for those tiles (work-item order within each kernel: problem-
+   major or round-robin, elasticity kernel first; or round-robin with the mass/Poisson
+   kernel first; workgroups per CU: 1, 2 in FP64, 1..3 in FP32).  cache_path (host
    string, may be NULL) is a text file of tuned choices keyed by device, precision,
    Dirichlet flags, problems per class and column count: a hit skips timing. */
 mf_status mf_batch_tune(mf_batch_t* batch, const char* cache_path, void* stream);
 
 /* (sync) Tile shapes: *n_classes (6) classes ordered (form: 0 mass/Poisson, 1 elasticity)
    x (size bucket 0..2); problems[c] (host, may be NULL) the number of problems in class c;
-   chunks[c] (host, may be NULL) the chunks per column (tile height NZ / chunks). */
-mf_status mf_batch_tiles(const mf_batch_t* batch, int32_t* n_classes, int32_t* problems, int32_t* chunks);
+   chunks[c] (host, may be NULL) the chunks per column (tile height NZ / chunks);
+   cross_x[c] (host, may be NULL) the column cross-section's width along x in nodes: 4 for
+   4x2 columns, 2 for 2x4. */
+mf_status mf_batch_tiles(const mf_batch_t* batch, int32_t* n_classes, int32_t* problems, int32_t* chunks,
+                         int32_t* cross_x);
 
-/* One persistent launch assembling every problem (K and d overwritten; device status
-   words of all patterns reset first).  On a non-default stream the launch is captured
-   once as a HIP graph and replayed on later calls.  Async. */
+/* Assembles every problem (K and d overwritten; device status words of all patterns reset
+   first): two persistent launches, one for the elasticity problems and one for the mass
+   and Poisson problems (each built for its own forms' registers).  On a non-default stream
+   the launches are captured once as a HIP graph and replayed on later calls.  Async. */
 mf_status mf_batch_run(mf_batch_t* batch, void* stream);
 
 /* (sync) Work items, workgroups, item order, whether a graph exists, tuned time (us). */

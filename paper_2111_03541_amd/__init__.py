@@ -158,7 +158,7 @@ def load():
     lib.mf_pcg_noalloc_max_rows.argtypes = []
     lib.mf_pcg_noalloc_max_rows.restype = i64
     lib.mf_nn_checkpoint_size.argtypes = [P, C.POINTER(i64)]
-    lib.mf_batch_tiles.argtypes = [P, C.POINTER(i32), P, P]
+    lib.mf_batch_tiles.argtypes = [P, C.POINTER(i32), P, P, P]
     lib.mf_nn_save.argtypes = [P, P, i64]
     lib.mf_nn_load.argtypes = [P, P, i64]
     lib.mf_batch_create.argtypes = [C.POINTER(_BatchProblem), i32, C.c_int, C.POINTER(P)]
@@ -433,10 +433,11 @@ class Batch:
         check(load().mf_batch_info(self._h, C.byref(n), C.byref(wg), C.byref(order), C.byref(graphed),
                                    C.byref(us)))
         nc = C.c_int32()
-        probs, chunks = (C.c_int32 * 8)(), (C.c_int32 * 8)()
-        check(load().mf_batch_tiles(self._h, C.byref(nc), probs, chunks))
+        probs, chunks, cross = (C.c_int32 * 8)(), (C.c_int32 * 8)(), (C.c_int32 * 8)()
+        check(load().mf_batch_tiles(self._h, C.byref(nc), probs, chunks, cross))
         names = ["poisson", "elasticity"]
-        tiles = {f"{names[c // 3]}/bucket{c % 3}": {"problems": probs[c], "chunks": chunks[c]}
+        tiles = {f"{names[c // 3]}/bucket{c % 3}": {"problems": probs[c], "chunks": chunks[c],
+                                                      "cross_section": f"{cross[c]}x{8 // cross[c]}"}
                  for c in range(nc.value) if probs[c] > 0}
         return {"items": n.value, "workgroups": wg.value, "order": order.value, "graphed": bool(graphed.value),
                 "tuned_us": us.value, "tiles": tiles}

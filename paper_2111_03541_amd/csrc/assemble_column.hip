@@ -42,6 +42,16 @@ constexpr int EXH = CX + 1, EYH = CY + 1;  // elements per layer around the colu
 constexpr int kLayerElems = EXH * EYH;
 constexpr int TX = CX + 2, TY = CY + 2;    // node tile per layer
 constexpr int kTileNodes = TX * TY;
+// Column cross-sections of the symmetric forms: XW owned nodes along x by kColNodes / XW
+// along y, 4x2 or 2x4.  Both have the same node, element and tile counts, so one LDS
+// layout and one lane layout serve both; only the index arithmetic differs.
+template <int XW>
+struct Cs {
+    static constexpr int CX = XW, CY = kColNodes / XW;
+    static constexpr int EXH = CX + 1, EYH = CY + 1, TX = CX + 2, TY = CY + 2;
+    static_assert(CX * CY == kColNodes && EXH * EYH == kLayerElems && TX * TY == kTileNodes,
+                  "the counts of the 4x2 cross-section");
+};
 constexpr int kThreads = kColNodes * 8 * 4;  // phase B: one lane per (node, element, quarter)
 constexpr int kGeomThreads = 128;            // phase A: geometry on these, write-out on the rest
 // workgroups per CU that the LDS of each case allows (FP64 and the flow form: 2; FP32
@@ -98,6 +108,7 @@ struct ColParams {
     void* d;
     unsigned long long* status;
     double lam_f, mu_f;  // elasticity: lambda = E lam_f, mu = E mu_f (from nu, on the host)
+    int xw;              // cross-section of the batched launch's columns: 4 (4x2) or 2 (2x4)
 };
 
 // Row-buffer accumulators: FP64 for the symmetric forms in both precisions (FP32 rows,
@@ -174,10 +185,11 @@ struct NodeLoad {
     T u[NSRC];
     int m;  // Dirichlet flag of field k in bit k
     bool ok;
+    template <int XW = CX>
     __device__ __forceinline__ void load(const ColParams& p, int L, int tn, int i0, int j0)
     {
         const int NX = p.nx + 1, NY = p.ny + 1;
-        const int gi = i0 - 1 + tn % TX, gj = j0 - 1 + tn / TX;
+        const int gi = i0 - 1 + tn % Cs<XW>::TX, gj = j0 - 1 + tn / Cs<XW>::TX;
         ok = L >= 0 && L <= p.nz && gi >= 0 && gi < NX && gj >= 0 && gj < NY;
         if (!ok) return;
         const int node = gi + NX * (gj + NY * L);
@@ -209,10 +221,11 @@ struct NodeLoad {
     }
 };
 
+template <int XW = CX>
 __device__ __forceinline__ bool elem_param_of(const ColParams& p, int L, int el, int i0, int j0, bool f32,
                                               double& v)
 {
-    const int ex = i0 - 1 + el % EXH, ey = j0 - 1 + el / EXH;
+    const int ex = i0 - 1 + el % Cs<XW>::EXH, ey = j0 - 1 + el / Cs<XW>::EXH;
     if (L < 0 || L >= p.nz || ex < 0 || ex >= p.nx || ey < 0 || ey >= p.ny) return false;
     const int e = ex + p.nx * (ey + p.ny * L);
     v = p.elem_param ? (f32 ? (double)((const float*)p.elem_param)[e] : ((const double*)p.elem_param)[e]) : 1.0;
@@ -220,12 +233,12 @@ __device__ __forceinline__ bool elem_param_of(const ColParams& p, int L, int el,
 }
 
 // Phase A: geometry of element `el` of element layer L at Gauss point q.
-template <int FORM, typename T>
+template <int FORM, typename T, int XW = CX>
 __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM, T>& S, int L, int el, int q,
                                               int i0, int j0)
 {
     constexpr int NF = FormTraits<FORM, 3>::NF;
-    const int hx = el % EXH, hy = el / EXH;
+    const int hx = el % Cs<XW>::EXH, hy = el / Cs<XW>::EXH;
     const int ex = i0 - 1 + hx, ey = j0 - 1 + hy;
     if (L < 0 || L >= p.nz || ex < 0 || ex >= p.nx || ey < 0 || ey >= p.ny) return;
     // nodes are streamed from the LDS tile and the basis at the point is rebuilt from the
@@ -236,7 +249,7 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
     gauss_factors((q >> 2) & 1, F[2]);
     auto node_slot = [&](int a, int& r, int& tn) {
         r = ring3(L + (a >> 2));
-        tn = (hx + (a & 1)) + TX * (hy + ((a >> 1) & 1));
+        tn = (hx + (a & 1)) + Cs<XW>::TX * (hy + ((a >> 1) & 1));
     };
     auto N_of = [&](int a) { return F[0][a & 1] * F[1][(a >> 1) & 1] * F[2][a >> 2]; };
     auto dN_of = [&](int a, double (&d)[3]) {
@@ -423,7 +436,7 @@ __device__ __forceinline__ void geometry_item(const ColParams& p, ColShared<FORM
 // blocks (a, b) for the two element nodes b = 2 bq, 2 bq + 1, over all eight Gauss
 // points.  The element's load-vector share of a is split by Gauss-point pairs between
 // the four lanes of (al, eps) and added across them.
-template <int FORM, typename T>
+template <int FORM, typename T, int XW>
 __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>& S, int kz, int i0, int j0)
 {
     constexpr int NF = FormTraits<FORM, 3>::NF;
@@ -433,14 +446,14 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
     const int tid = threadIdx.x;
     const int bq = tid & 3, pe = tid >> 2;
     const int al = pe & (kColNodes - 1), eps = pe / kColNodes;
-    const int alx = al % CX, aly = al / CX;
+    const int alx = al % Cs<XW>::CX, aly = al / Cs<XW>::CX;
     const int gi = i0 + alx, gj = j0 + aly;
     const int dx = eps & 1, dy = (eps >> 1) & 1, dz = eps >> 2;
     const int ex = gi - 1 + dx, ey = gj - 1 + dy, ez = kz - 1 + dz;
     const bool valid = gi <= p.nx && gj <= p.ny && ex >= 0 && ex < p.nx && ey >= 0 && ey < p.ny && ez >= 0 &&
                        ez < p.nz;
     const int alpha = 7 - eps;  // the node's local index in the element
-    const int slot = ez & 1, el = (alx + dx) + EXH * (aly + dy);
+    const int slot = ez & 1, el = (alx + dx) + Cs<XW>::EXH * (aly + dy);
     const T* he = S.h + slot * HLayout<FORM, T>::SL + el * HLayout<FORM, T>::SE;
 
     T M[2][NV];
@@ -540,10 +553,11 @@ __device__ __forceinline__ void pair_item(const ColParams& p, ColShared<FORM, T>
 // the order of a node-major CSR row block, so an interior node's rows are one contiguous
 // copy; boundary nodes, field-major numbering and Dirichlet masks take the general
 // mapping.  K is written once and is far larger than the caches: non-temporal stores.
-template <int FORM, bool MASK, typename T>
+template <int FORM, bool MASK, typename T, int XW = CX>
 __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, T>& S, int L, int wid, int nw,
                                             int rb = 0)
 {
+    constexpr int WX = Cs<XW>::CX, WTX = Cs<XW>::TX;
     constexpr int NF = FormTraits<FORM, 3>::NF;
     constexpr int NB = NF * NF;
     constexpr int kNodeVals = 27 * NB;
@@ -583,7 +597,7 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
             if (masked && !p.field_major && bits == 63) {
                 bool hit = false;
                 if (lane < 27) {
-                    const int tn = il % CX + 1 + TX * (il / CX + 1) + (lane % 3 - 1) + TX * ((lane / 3) % 3 - 1);
+                    const int tn = il % WX + 1 + WTX * (il / WX + 1) + (lane % 3 - 1) + WTX * ((lane / 3) % 3 - 1);
 #pragma unroll
                     for (int k = 0; k < NF; ++k) hit |= S.msk[(L + lane / 9 - 1) & 3][tn][k] != 0;
                 }
@@ -618,9 +632,9 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
                                            : P * NB + i * NF * deg + rank * NF + j;
             T v = (T)vals[c];
             if (masked) {
-                const int tn = il % CX + 1 + TX * (il / CX + 1);  // the node in the tile
+                const int tn = il % WX + 1 + WTX * (il / WX + 1);  // the node in the tile
                 if (S.msk[L & 3][tn][i]) v = (slot == 13 && j == i) ? T(1) : T(0);
-                else if (S.msk[(L + ddz) & 3][tn + ddx + TX * ddy][j]) v = T(0);
+                else if (S.msk[(L + ddz) & 3][tn + ddx + WTX * ddy][j]) v = T(0);
             }
             __builtin_nontemporal_store(v, &K[kpos]);
         }
@@ -632,14 +646,14 @@ __device__ __forceinline__ void write_layer(const ColParams& p, ColShared<FORM, 
         const int node = S.ni[il][0];
         if (node >= 0) {
             const int row = p.field_major ? i * nn + node : NF * node + i;
-            d[row] = (masked && S.msk[L & 3][il % CX + 1 + TX * (il / CX + 1)][i]) ? T(0) : (T)acc;
+            d[row] = (masked && S.msk[L & 3][il % WX + 1 + WTX * (il / WX + 1)][i]) ? T(0) : (T)acc;
         }
     }
 }
 
 // One column chunk b of one problem (b = column + columns * chunk); called by the
 // single-problem kernel and by the persistent batched kernel.
-template <int FORM, bool MASK, typename T>
+template <int FORM, bool MASK, typename T, int XW = CX>
 __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared<FORM, T>& S)
 {
     constexpr int NF = FormTraits<FORM, 3>::NF;
@@ -647,9 +661,10 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
     constexpr int NB = NF * NF;
     const int tid = threadIdx.x;
     const int NX = p.nx + 1, NY = p.ny + 1, NZ = p.nz + 1;
-    const int ncx = (NX + CX - 1) / CX, ncy = (NY + CY - 1) / CY;
+    constexpr int BX = Cs<XW>::CX, BY = Cs<XW>::CY;
+    const int ncx = (NX + BX - 1) / BX, ncy = (NY + BY - 1) / BY;
     const int cx = b % ncx, cy = (b / ncx) % ncy, ch = b / (ncx * ncy);
-    const int i0 = cx * CX, j0 = cy * CY;
+    const int i0 = cx * BX, j0 = cy * BY;
     const int z0 = ch * p.lz, z1 = min(z0 + p.lz, NZ);
     const bool f32 = sizeof(T) == 4;
 
@@ -659,13 +674,13 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
     for (int it = tid; it < 3 * kTileNodes; it += kThreads) {
         NodeLoad<NSRC, NF, MASK, T> ld;
         const int L = z0 - 1 + it / kTileNodes, tn = it % kTileNodes;
-        ld.load(p, L, tn, i0, j0);
+        ld.template load<XW>(p, L, tn, i0, j0);
         ld.template store<FORM>(S, L, tn);
     }
     for (int it = tid; it < 2 * kLayerElems; it += kThreads) {
         const int L = z0 - 1 + it / kLayerElems, el = it % kLayerElems;
         double v;
-        if (elem_param_of(p, L, el, i0, j0, f32, v)) S.ep[L & 1][el] = v;
+        if (elem_param_of<XW>(p, L, el, i0, j0, f32, v)) S.ep[L & 1][el] = v;
     }
     __syncthreads();
 
@@ -675,10 +690,10 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
         if (tid < kGeomThreads) {
             for (int it = tid; it < (kz - first + 1) * kGeomItems; it += kGeomThreads) {
                 const int L = first + it / kGeomItems, r = it % kGeomItems;
-                geometry_item<FORM, T>(p, S, L, r >> 3, r & 7, i0, j0);
+                geometry_item<FORM, T, XW>(p, S, L, r >> 3, r & 7, i0, j0);
             }
         } else if (kz > z0) {
-            write_layer<FORM, MASK, T>(p, S, kz - 1, tid - kGeomThreads, kThreads - kGeomThreads);
+            write_layer<FORM, MASK, T, XW>(p, S, kz - 1, tid - kGeomThreads, kThreads - kGeomThreads);
         }
         __syncthreads();
 
@@ -689,12 +704,12 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
         bool ep_ok = false;
         int info[4] = {-1, 0, 0, 0};
         if (tid < kTileNodes) {
-            ld.load(p, kz + 2, tid, i0, j0);
+            ld.template load<XW>(p, kz + 2, tid, i0, j0);
         } else if (tid >= kPfElemT0 && tid < kPfElemT0 + kLayerElems) {
-            ep_ok = elem_param_of(p, kz + 1, tid - kPfElemT0, i0, j0, f32, epv);
+            ep_ok = elem_param_of<XW>(p, kz + 1, tid - kPfElemT0, i0, j0, f32, epv);
         } else if (tid >= kPfInfoT0 && tid < kPfInfoT0 + kColNodes) {
             const int il = tid - kPfInfoT0;
-            const int gi = i0 + il % CX, gj = j0 + il / CX;
+            const int gi = i0 + il % BX, gj = j0 + il / BX;
             if (gi < NX && gj < NY) {
                 const int node = gi + NX * (gj + NY * kz);
                 const int mx = 1 + (gi > 0) + (gi < p.nx), my = 1 + (gj > 0) + (gj < p.ny),
@@ -706,7 +721,7 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
                           ((kz < p.nz) << 5);
             }
         }
-        pair_item<FORM, T>(p, S, kz, i0, j0);
+        pair_item<FORM, T, XW>(p, S, kz, i0, j0);
         if (tid < kTileNodes) ld.template store<FORM>(S, kz + 2, tid);
         if (ep_ok) S.ep[(kz + 1) & 1][tid - kPfElemT0] = epv;
         if (tid >= kPfInfoT0 && tid < kPfInfoT0 + kColNodes) {
@@ -715,7 +730,7 @@ __device__ __forceinline__ void column_body(const ColParams& p, int b, ColShared
         }
         __syncthreads();
     }
-    if (z0 < z1) write_layer<FORM, MASK, T>(p, S, z1 - 1, tid, kThreads);
+    if (z0 < z1) write_layer<FORM, MASK, T, XW>(p, S, z1 - 1, tid, kThreads);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1022,17 +1037,22 @@ struct BatchProblemDev {
     int kind;
 };
 
+template <typename T, bool ELAST>
+union BatchShared;
 template <typename T>
-union BatchShared {
+union BatchShared<T, true> {
+    ColShared<MF_FORM_ELASTICITY, T> elasticity;
+};
+template <typename T>
+union BatchShared<T, false> {
     ColShared<MF_FORM_MASS, T> mass;
     ColShared<MF_FORM_POISSON, T> poisson;
-    ColShared<MF_FORM_ELASTICITY, T> elasticity;
 };
 
 __global__ void k_batch_reset(int* counter, unsigned long long* const* status, int n_status)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *counter = 0;
+    if (i < 2) counter[i] = 0;
     if (i < n_status) {
         status[i][0] = ~0ull;
         status[i][1] = ~0ull;
@@ -1040,13 +1060,15 @@ __global__ void k_batch_reset(int* counter, unsigned long long* const* status, i
     }
 }
 
-// MASK: some problem of the batch has Dirichlet flags
-template <typename T, bool MASK>
+// MASK: some problem of the batch has Dirichlet flags; ELAST: the elasticity items (one
+// kernel), else the mass and Poisson items (another), so that each kernel's registers are
+// those of its own forms
+template <typename T, bool MASK, bool ELAST>
 __global__ void __launch_bounds__(kThreads, (BatchMinBlocks<T>::value))
     k_batch_persistent(const BatchProblemDev* __restrict__ probs, const int2* __restrict__ items, int n_items,
                        int* __restrict__ counter)
 {
-    __shared__ BatchShared<T> S;
+    __shared__ BatchShared<T, ELAST> S;
     __shared__ int sItem;
     while (true) {
         __syncthreads();  // the previous item's write-out is done with the LDS
@@ -1056,13 +1078,25 @@ __global__ void __launch_bounds__(kThreads, (BatchMinBlocks<T>::value))
         if (it >= n_items) break;
         const int2 w = items[it];
         const ColParams cp = probs[w.x].cp;
-        const int kind = probs[w.x].kind;
-        if (kind == MF_FORM_ELASTICITY)
-            column_body<MF_FORM_ELASTICITY, MASK, T>(cp, w.y, S.elasticity);
-        else if (kind == MF_FORM_POISSON)
-            column_body<MF_FORM_POISSON, MASK, T>(cp, w.y, S.poisson);
-        else
-            column_body<MF_FORM_MASS, MASK, T>(cp, w.y, S.mass);
+        if constexpr (ELAST) {
+            if (cp.xw == 2)
+                column_body<MF_FORM_ELASTICITY, MASK, T, 2>(cp, w.y, S.elasticity);
+            else
+                column_body<MF_FORM_ELASTICITY, MASK, T, 4>(cp, w.y, S.elasticity);
+        } else {
+            const int kind = probs[w.x].kind;
+            if (cp.xw == 2) {
+                if (kind == MF_FORM_POISSON)
+                    column_body<MF_FORM_POISSON, MASK, T, 2>(cp, w.y, S.poisson);
+                else
+                    column_body<MF_FORM_MASS, MASK, T, 2>(cp, w.y, S.mass);
+            } else {
+                if (kind == MF_FORM_POISSON)
+                    column_body<MF_FORM_POISSON, MASK, T, 4>(cp, w.y, S.poisson);
+                else
+                    column_body<MF_FORM_MASS, MASK, T, 4>(cp, w.y, S.mass);
+            }
+        }
     }
 }
 
@@ -1118,15 +1152,17 @@ ColParams make_params(const AssembleArgs& A)
     p.d = A.d;
     p.status = P->status;
     p.lz = p.nz + 1;
+    p.xw = CX;
     const double nu = A.form->nu;
     p.lam_f = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
     p.mu_f = 1.0 / (2.0 * (1.0 + nu));
     return p;
 }
 
-int64_t column_count(const mf_pattern_s* P)
+int64_t column_count(const mf_pattern_s* P, int xw = CX)
 {
-    return (int64_t)((P->gx + 1 + CX - 1) / CX) * ((P->gy + 1 + CY - 1) / CY);
+    const int cy = kColNodes / xw;
+    return (int64_t)((P->gx + 1 + xw - 1) / xw) * ((P->gy + 1 + cy - 1) / cy);
 }
 
 template <int FORM, typename T>
@@ -1168,12 +1204,12 @@ mf_status dispatch(const AssembleArgs& A)
 // into a number of chunks (the tile height) that the autotuner chooses per (form, size)
 // class of problems.
 
-int64_t batch_units_of(const mf_pattern_s* P, int chunks)
+int64_t batch_units_of(const mf_pattern_s* P, int chunks, int xw)
 {
     const int NZ = (int)P->gz + 1;
     const int c = std::max(1, std::min(chunks, NZ));
     const int lz = (NZ + c - 1) / c;
-    return column_count(P) * ((NZ + lz - 1) / lz);
+    return column_count(P, xw) * ((NZ + lz - 1) / lz);
 }
 
 mf_status batch_check(const AssembleArgs& A)
@@ -1186,8 +1222,8 @@ mf_status batch_check(const AssembleArgs& A)
     return MF_OK;
 }
 
-mf_status batch_upload(const std::vector<AssembleArgs>& probs, const std::vector<int>& chunks, void** dev_probs,
-                       void** dev_status)
+mf_status batch_upload(const std::vector<AssembleArgs>& probs, const std::vector<int>& chunks,
+                       const std::vector<int>& xw, void** dev_probs, void** dev_status)
 {
     std::vector<BatchProblemDev> h(probs.size());
     std::vector<unsigned long long*> st(probs.size());
@@ -1197,6 +1233,7 @@ mf_status batch_upload(const std::vector<AssembleArgs>& probs, const std::vector
         const int NZ = h[k].cp.nz + 1;
         const int c = std::max(1, std::min(chunks[k], NZ));
         h[k].cp.lz = (NZ + c - 1) / c;
+        h[k].cp.xw = xw[k] == 2 ? 2 : 4;
         h[k].kind = probs[k].form->kind;
         st[k] = probs[k].P->status;
     }
@@ -1207,22 +1244,40 @@ mf_status batch_upload(const std::vector<AssembleArgs>& probs, const std::vector
     return MF_OK;
 }
 
-mf_status batch_launch(const void* dev_probs, void* dev_status, int n_probs, const int2* items, int n_items,
-                       int* counter, int n_wg, mf_precision prec, bool masked, hipStream_t s)
+template <typename T, bool MASK>
+void launch_batch_group(bool elast, const BatchProblemDev* pr, const int2* it, int n, int* ctr, int n_wg,
+                        hipStream_t s)
+{
+    if (elast)
+        k_batch_persistent<T, MASK, true><<<n_wg, kThreads, 0, s>>>(pr, it, n, ctr);
+    else
+        k_batch_persistent<T, MASK, false><<<n_wg, kThreads, 0, s>>>(pr, it, n, ctr);
+}
+
+mf_status batch_launch(const void* dev_probs, void* dev_status, int n_probs, const int2* items, int n_first,
+                       int n_items, bool first_elastic, int* counter, int n_wg, mf_precision prec, bool masked,
+                       hipStream_t s)
 {
     k_batch_reset<<<(n_probs + 255) / 256 > 0 ? (n_probs + 255) / 256 : 1, 256, 0, s>>>(
         counter, (unsigned long long* const*)dev_status, n_probs);
     const BatchProblemDev* pr = (const BatchProblemDev*)dev_probs;
-    if (prec == MF_F64) {
-        if (masked)
-            k_batch_persistent<double, true><<<n_wg, kThreads, 0, s>>>(pr, items, n_items, counter);
-        else
-            k_batch_persistent<double, false><<<n_wg, kThreads, 0, s>>>(pr, items, n_items, counter);
-    } else {
-        if (masked)
-            k_batch_persistent<float, true><<<n_wg, kThreads, 0, s>>>(pr, items, n_items, counter);
-        else
-            k_batch_persistent<float, false><<<n_wg, kThreads, 0, s>>>(pr, items, n_items, counter);
+    // items [0, n_first) of one group (elasticity when first_elastic), then the other's
+    for (int g = 0; g < 2; ++g) {
+        const int2* it = items + (g == 0 ? 0 : n_first);
+        const int n = g == 0 ? n_first : n_items - n_first;
+        if (n <= 0) continue;
+        const bool elast = (g == 0) == first_elastic;
+        if (prec == MF_F64) {
+            if (masked)
+                launch_batch_group<double, true>(elast, pr, it, n, counter + g, n_wg, s);
+            else
+                launch_batch_group<double, false>(elast, pr, it, n, counter + g, n_wg, s);
+        } else {
+            if (masked)
+                launch_batch_group<float, true>(elast, pr, it, n, counter + g, n_wg, s);
+            else
+                launch_batch_group<float, false>(elast, pr, it, n, counter + g, n_wg, s);
+        }
     }
     MF_HIP(hipGetLastError());
     return MF_OK;

@@ -30,6 +30,7 @@ struct mf_batch_s {
     std::vector<int64_t> units;  // work items (tiles) per problem
     std::vector<int> cls;        // class of each problem
     int chunks[kClasses] = {1, 1, 1, 1, 1, 1};
+    int xw[kClasses] = {4, 4, 4, 4, 4, 4};  // cross-section per class: 4 (4x2) or 2 (2x4)
     mf_precision prec = MF_F64;
     bool masked = false;  // some problem has Dirichlet flags
     void* dprobs = nullptr;
@@ -38,6 +39,7 @@ struct mf_batch_s {
     int2* items = nullptr;
     int64_t items_cap = 0;
     int n_items = 0;
+    int n_first = 0;  // items of the kernel launched first (elasticity unless order 2)
     int n_wg = 0;
     int order = 1;
     int num_cus = 256;
@@ -67,55 +69,49 @@ void drop_graph(mf_batch_s* B)
     B->graph_stream = nullptr;
 }
 
-// order 0: problem-major; 1: round-robin over problems; 2: elasticity problems first,
-// then round-robin (costlier items early, so the tail is short)
-std::vector<int2> build_items(const mf_batch_s* B, int order)
+// Items in two groups, one per kernel: elasticity and the scalar forms (mass, Poisson).
+// order 0: problem-major within each group, elasticity group first; 1: round-robin over
+// the group's problems, elasticity first; 2: round-robin, scalar group first.
+// *n_first: items of the group launched first.
+std::vector<int2> build_items(const mf_batch_s* B, int order, int* n_first)
 {
     std::vector<int2> it;
     const int np = (int)B->probs.size();
-    if (order == 0) {
-        for (int p = 0; p < np; ++p)
-            for (int64_t b = 0; b < B->units[p]; ++b) it.push_back(make_int2(p, (int)b));
-        return it;
-    }
-    std::vector<int> sel;
-    if (order == 2) {
-        for (int p = 0; p < np; ++p)
-            if (B->forms[p].kind == MF_FORM_ELASTICITY) sel.push_back(p);
-        for (int p = 0; p < np; ++p)
-            if (B->forms[p].kind != MF_FORM_ELASTICITY) sel.push_back(p);
-        // two groups, each round-robin
-        std::vector<int> a, b;
-        for (int p : sel) (B->forms[p].kind == MF_FORM_ELASTICITY ? a : b).push_back(p);
-        for (auto* grp : {&a, &b}) {
+    std::vector<int> el, sc;
+    for (int p = 0; p < np; ++p) (B->forms[p].kind == MF_FORM_ELASTICITY ? el : sc).push_back(p);
+    const std::vector<int>* groups[2] = {&el, &sc};
+    if (order == 2) std::swap(groups[0], groups[1]);
+    for (int g = 0; g < 2; ++g) {
+        const std::vector<int>& grp = *groups[g];
+        if (order == 0) {
+            for (int p : grp)
+                for (int64_t b = 0; b < B->units[p]; ++b) it.push_back(make_int2(p, (int)b));
+        } else {
             int64_t mx = 0;
-            for (int p : *grp) mx = std::max(mx, B->units[p]);
+            for (int p : grp) mx = std::max(mx, B->units[p]);
             for (int64_t k = 0; k < mx; ++k)
-                for (int p : *grp)
+                for (int p : grp)
                     if (k < B->units[p]) it.push_back(make_int2(p, (int)k));
         }
-        return it;
+        if (g == 0) *n_first = (int)it.size();
     }
-    int64_t mx = 0;
-    for (int p = 0; p < np; ++p) mx = std::max(mx, B->units[p]);
-    for (int64_t k = 0; k < mx; ++k)
-        for (int p = 0; p < np; ++p)
-            if (k < B->units[p]) it.push_back(make_int2(p, (int)k));
     return it;
 }
 
 // descriptors (tile heights) and the item list for the current shapes and `order`
 mf_status upload_items(mf_batch_s* B, int order)
 {
-    std::vector<int> ch(B->probs.size());
+    std::vector<int> ch(B->probs.size()), xw(B->probs.size());
     for (size_t k = 0; k < B->probs.size(); ++k) {
         ch[k] = B->chunks[B->cls[k]];
-        B->units[k] = batch_units_of(B->probs[k].P, ch[k]);
+        xw[k] = B->xw[B->cls[k]];
+        B->units[k] = batch_units_of(B->probs[k].P, ch[k], xw[k]);
     }
     MF_HIP(hipDeviceSynchronize());  // a launch in flight may still read the old lists
-    mf_status st = batch_upload(B->probs, ch, &B->dprobs, &B->dstatus);
+    mf_status st = batch_upload(B->probs, ch, xw, &B->dprobs, &B->dstatus);
     if (st != MF_OK) return st;
-    std::vector<int2> it = build_items(B, order);
+    int n_first = 0;
+    std::vector<int2> it = build_items(B, order, &n_first);
     if (B->items && (int64_t)it.size() > B->items_cap) {
         (void)hipFree(B->items);
         B->items = nullptr;
@@ -126,6 +122,7 @@ mf_status upload_items(mf_batch_s* B, int order)
     }
     MF_HIP(hipMemcpy(B->items, it.data(), sizeof(int2) * it.size(), hipMemcpyHostToDevice));
     B->n_items = (int)it.size();
+    B->n_first = n_first;
     B->order = order;
     drop_graph(B);
     return MF_OK;
@@ -137,21 +134,22 @@ std::string tune_key(const mf_batch_s* B)
     int64_t cols = 0;
     for (size_t k = 0; k < B->probs.size(); ++k) {
         ++per[B->cls[k]];
-        cols += batch_units_of(B->probs[k].P, 1);
+        cols += batch_units_of(B->probs[k].P, 1, 4);
     }
     // bucket the column count to two significant digits
     double lg = std::floor(std::log10((double)std::max<int64_t>(1, cols)));
     long bucket = (long)(std::round(cols / std::pow(10.0, lg - 1)) * std::pow(10.0, lg - 1));
     std::ostringstream os;
-    os << "gfx950|column-v3|prec=" << (B->prec == MF_F64 ? "f64" : "f32") << "|mask=" << (B->masked ? 1 : 0)
+    os << "gfx950|column-v4|prec=" << (B->prec == MF_F64 ? "f64" : "f32") << "|mask=" << (B->masked ? 1 : 0)
        << "|classes=";
     for (int c = 0; c < kClasses; ++c) os << per[c] << (c + 1 < kClasses ? "," : "");
     os << "|columns~" << bucket;
     return os.str();
 }
 
-// cache line: key order mult us chunks[0..kClasses)
-bool cache_lookup(const char* path, const std::string& key, int* order, int* mult, double* us, int* chunks)
+// cache line: key order mult us chunks[0..kClasses) xw[0..kClasses)
+bool cache_lookup(const char* path, const std::string& key, int* order, int* mult, double* us, int* chunks,
+                  int* xw)
 {
     if (!path) return false;
     std::ifstream f(path);
@@ -162,20 +160,27 @@ bool cache_lookup(const char* path, const std::string& key, int* order, int* mul
         int o, m;
         double u;
         if (is >> k >> o >> m >> u && k == key) {
-            int c[kClasses];
+            int c[kClasses], x[kClasses];
             for (int j = 0; j < kClasses; ++j)
                 if (!(is >> c[j]) || c[j] < 1 || c[j] > kMaxChunks) return false;
+            for (int j = 0; j < kClasses; ++j)
+                if (!(is >> x[j]) || (x[j] != 2 && x[j] != 4)) return false;
+            if (o < 0 || o > 2 || m < 1 || m > 3) return false;
             *order = o;
             *mult = m;
             *us = u;
-            for (int j = 0; j < kClasses; ++j) chunks[j] = c[j];
+            for (int j = 0; j < kClasses; ++j) {
+                chunks[j] = c[j];
+                xw[j] = x[j];
+            }
             return true;
         }
     }
     return false;
 }
 
-void cache_store(const char* path, const std::string& key, int order, int mult, double us, const int* chunks)
+void cache_store(const char* path, const std::string& key, int order, int mult, double us, const int* chunks,
+                 const int* xw)
 {
     if (!path) return;
     std::vector<std::string> keep;
@@ -189,13 +194,14 @@ void cache_store(const char* path, const std::string& key, int order, int mult, 
     for (auto& l : keep) f << l << "\n";
     f << key << " " << order << " " << mult << " " << us;
     for (int j = 0; j < kClasses; ++j) f << " " << chunks[j];
+    for (int j = 0; j < kClasses; ++j) f << " " << xw[j];
     f << "\n";
 }
 
 mf_status launch(mf_batch_s* B, hipStream_t s)
 {
-    return batch_launch(B->dprobs, B->dstatus, (int)B->probs.size(), B->items, B->n_items, B->counter, B->n_wg,
-                        B->prec, B->masked, s);
+    return batch_launch(B->dprobs, B->dstatus, (int)B->probs.size(), B->items, B->n_first, B->n_items,
+                        B->order != 2, B->counter, B->n_wg, B->prec, B->masked, s);
 }
 
 mf_status time_config(mf_batch_s* B, hipStream_t s, double* us)
@@ -284,10 +290,10 @@ mf_status mf_batch_create(const mf_batch_problem* problems, int32_t n, mf_precis
         }
         B->probs.push_back(a);
         B->cls.push_back(class_of(B->forms[k], q.pattern));
-        B->units.push_back(batch_units_of(q.pattern, 1));
+        B->units.push_back(batch_units_of(q.pattern, 1, 4));
     }
     mf_status st = MF_OK;
-    if (hipMalloc(&B->counter, sizeof(int)) != hipSuccess) st = set_error(MF_ERR_OOM, "counter");
+    if (hipMalloc(&B->counter, 2 * sizeof(int)) != hipSuccess) st = set_error(MF_ERR_OOM, "counter");
     int dev = 0, cus = 256;
     if (st == MF_OK && hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
@@ -309,25 +315,31 @@ mf_status mf_batch_tune(mf_batch_t* B, const char* cache_path, void* stream)
     const std::string key = tune_key(B);
     int order = 1, mult = 1;
     double us = 0;
-    int cached[kClasses];
-    if (cache_lookup(cache_path, key, &order, &mult, &us, cached)) {
-        for (int c = 0; c < kClasses; ++c) B->chunks[c] = cached[c];
+    int cached[kClasses], cached_xw[kClasses];
+    if (cache_lookup(cache_path, key, &order, &mult, &us, cached, cached_xw)) {
+        for (int c = 0; c < kClasses; ++c) {
+            B->chunks[c] = cached[c];
+            B->xw[c] = cached_xw[c];
+        }
         mf_status st = upload_items(B, order);
         if (st != MF_OK) return st;
         B->n_wg = B->num_cus * mult;
         B->tuned_us = us;
         return MF_OK;
     }
-    // 1. tile height per class, by coordinate descent on the whole batch's time (round-
-    //    robin order, as many workgroups per CU as the kernel is built for), classes with
-    //    the most columns first
+    // 1. tile shape per class (cross-section 4x2 or 2x4, tile height NZ / 1..4), by
+    //    coordinate descent on the whole batch's time (round-robin order, as many
+    //    workgroups per CU as the kernel is built for), classes with the most columns first
     int present[kClasses] = {0};
-    for (size_t k = 0; k < B->probs.size(); ++k) present[B->cls[k]] += (int)batch_units_of(B->probs[k].P, 1);
+    for (size_t k = 0; k < B->probs.size(); ++k) present[B->cls[k]] += (int)batch_units_of(B->probs[k].P, 1, 4);
     std::vector<int> byw;
     for (int c = 0; c < kClasses; ++c)
         if (present[c] > 0) byw.push_back(c);
     std::sort(byw.begin(), byw.end(), [&](int a, int b) { return present[a] > present[b]; });
-    for (int c = 0; c < kClasses; ++c) B->chunks[c] = 1;
+    for (int c = 0; c < kClasses; ++c) {
+        B->chunks[c] = 1;
+        B->xw[c] = 4;
+    }
     const int max_mult = batch_max_wg_per_cu(B->prec);
     B->n_wg = B->num_cus * max_mult;
     double best = 1e300;
@@ -338,20 +350,26 @@ mf_status mf_batch_tune(mf_batch_t* B, const char* cache_path, void* stream)
         if (st != MF_OK) return st;
     }
     for (int c : byw) {
-        int keep = B->chunks[c];
-        for (int ch = 2; ch <= kMaxChunks; ++ch) {
-            B->chunks[c] = ch;
-            mf_status st = upload_items(B, 1);
-            if (st != MF_OK) return st;
-            double t = 0;
-            st = time_config(B, s, &t);
-            if (st != MF_OK) return st;
-            if (t < best) {
-                best = t;
-                keep = ch;
+        int keep = B->chunks[c], keep_xw = B->xw[c];
+        for (int x : {4, 2}) {
+            for (int ch = 1; ch <= kMaxChunks; ++ch) {
+                if (x == 4 && ch == 1) continue;  // the starting shape, timed above
+                B->chunks[c] = ch;
+                B->xw[c] = x;
+                mf_status st = upload_items(B, 1);
+                if (st != MF_OK) return st;
+                double t = 0;
+                st = time_config(B, s, &t);
+                if (st != MF_OK) return st;
+                if (t < best) {
+                    best = t;
+                    keep = ch;
+                    keep_xw = x;
+                }
             }
         }
         B->chunks[c] = keep;
+        B->xw[c] = keep_xw;
     }
     // 2. launch shape for those tiles: work-item order x workgroups per CU
     best = 1e300;
@@ -375,7 +393,7 @@ mf_status mf_batch_tune(mf_batch_t* B, const char* cache_path, void* stream)
     if (st != MF_OK) return st;
     B->n_wg = B->num_cus * best_mult;
     B->tuned_us = best;
-    cache_store(cache_path, key, best_order, best_mult, best, B->chunks);
+    cache_store(cache_path, key, best_order, best_mult, best, B->chunks, B->xw);
     return MF_OK;
 }
 
@@ -413,7 +431,8 @@ mf_status mf_batch_info(const mf_batch_t* B, int64_t* n_items, int32_t* n_workgr
     return MF_OK;
 }
 
-mf_status mf_batch_tiles(const mf_batch_t* B, int32_t* n_classes, int32_t* problems, int32_t* chunks)
+mf_status mf_batch_tiles(const mf_batch_t* B, int32_t* n_classes, int32_t* problems, int32_t* chunks,
+                         int32_t* cross_x)
 {
     if (!B) return set_error(MF_ERR_ARG, "batch is NULL");
     if (n_classes) *n_classes = kClasses;
@@ -423,6 +442,7 @@ mf_status mf_batch_tiles(const mf_batch_t* B, int32_t* n_classes, int32_t* probl
             for (int k : B->cls) problems[c] += k == c;
         }
         if (chunks) chunks[c] = B->chunks[c];
+        if (cross_x) cross_x[c] = B->xw[c];
     }
     return MF_OK;
 }

@@ -87,12 +87,16 @@ mf_status reset_status(const mf_pattern_s* P, hipStream_t s);
 // batched persistent launch (assemble_column.hip)
 mf_status batch_check(const AssembleArgs& a);
 // chunks[k]: problem k's columns are cut into that many work items along z (the tile
-// height); *dev_probs and *dev_status are allocated on the first call, reused after
-mf_status batch_upload(const std::vector<AssembleArgs>& probs, const std::vector<int>& chunks, void** dev_probs,
-                       void** dev_status);
-int64_t batch_units_of(const mf_pattern_s* P, int chunks);
-mf_status batch_launch(const void* dev_probs, void* dev_status, int n_probs, const int2* items, int n_items,
-                       int* counter, int n_wg, mf_precision prec, bool masked, hipStream_t s);
+// height); xw[k]: their cross-section, 4 (4x2 nodes) or 2 (2x4); *dev_probs and
+// *dev_status are allocated on the first call, reused after
+mf_status batch_upload(const std::vector<AssembleArgs>& probs, const std::vector<int>& chunks,
+                       const std::vector<int>& xw, void** dev_probs, void** dev_status);
+int64_t batch_units_of(const mf_pattern_s* P, int chunks, int xw);
+// items [0, n_first) belong to one kernel (elasticity when first_elastic), the rest to the
+// other (mass and Poisson); counter holds two ints
+mf_status batch_launch(const void* dev_probs, void* dev_status, int n_probs, const int2* items, int n_first,
+                       int n_items, bool first_elastic, int* counter, int n_wg, mf_precision prec, bool masked,
+                       hipStream_t s);
 // workgroups per CU the batched kernel is built for
 int batch_max_wg_per_cu(mf_precision prec);
 

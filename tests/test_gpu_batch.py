@@ -145,12 +145,13 @@ def test_batch_256_problems_sampled_against_oracle(mf):
         assert vec_error(d, dr) <= TOL[1]
 
 
-@pytest.mark.parametrize("chunks", [2, 3, 4])
-def test_batch_tile_heights_match_oracle(mf, chunks):
-    """Every class's columns cut into `chunks` tiles along z (set through the tuner's
-    cache file, which the tuner then reads back): whole systems against the oracle."""
+@pytest.mark.parametrize("chunks,xw", [(2, 4), (3, 4), (4, 4), (1, 2), (3, 2)])
+def test_batch_tile_shapes_match_oracle(mf, chunks, xw):
+    """Every class's columns with an xw x (8 / xw) node cross-section, cut into `chunks`
+    tiles along z (set through the tuner's cache file, which the tuner then reads back):
+    whole systems against the oracle."""
     sizes = [(3, 2, 7), (5, 4, 9), (2, 3, 22), (4, 3, 25), (3, 3, 40), (2, 2, 37), (1, 1, 5), (6, 2, 3)]
-    say("batch tiles", chunks, sizes)
+    say("batch tiles", chunks, xw, sizes)
     probs, host = make_problems(mf, sizes, 1, seed0=500)
     stream = torch.cuda.Stream()
     with tempfile.TemporaryDirectory() as tmp:
@@ -158,10 +159,11 @@ def test_batch_tile_heights_match_oracle(mf, chunks):
         mf.Batch(probs, precision=mf.F32).tune(cache, stream)
         key, order, mult, us, *_ = open(cache).read().split()
         with open(cache, "w") as f:
-            f.write(" ".join([key, order, mult, us] + [str(chunks)] * 6) + "\n")
+            f.write(" ".join([key, order, mult, us] + [str(chunks)] * 6 + [str(xw)] * 6) + "\n")
         batch = mf.Batch(probs, precision=mf.F32)
         info = batch.tune(cache, stream)
-    assert all(t["chunks"] == chunks for t in info["tiles"].values()), info
+    shape = f"{xw}x{8 // xw}"
+    assert all(t["chunks"] == chunks and t["cross_section"] == shape for t in info["tiles"].values()), info
     batch.run(stream)
     stream.synchronize()
     for pr, (mesh, elastic, ep, src, mask) in zip(batch.problems, host):
