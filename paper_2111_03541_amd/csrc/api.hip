@@ -205,7 +205,13 @@ mf_status mf_assemble_ex(const mf_pattern_t* P, const mf_form* form, const doubl
     A.stream = (hipStream_t)stream;
     const_cast<mf_pattern_s*>(P)->last_stream = A.stream;
 
-    mf_status st = reset_status(P, A.stream);
+    mf_status st;
+    if (scatter == MF_SCATTER_AUTO && P->dim == 2 && P->order == 1) {
+        // small 2D meshes: the whole call as one launch
+        st = assemble_small(A);
+        if (st != MF_ERR_UNSUPPORTED) return st;
+    }
+    st = reset_status(P, A.stream);
     if (st != MF_OK) return st;
     if (P->order == 2) {  // quadratic elements: colour by colour, one workgroup per element
         st = assemble_quadratic(A);

@@ -44,15 +44,15 @@ __global__ void k_fill(T* p, int64_t n)
     if (i < n) p[i] = T(0);
 }
 
+// Item t = (local row (a, i), element of the list): the row's entries of K and d.
 template <int FORM, int DIM, bool COLOURED, typename T>
-__global__ void __launch_bounds__(kThreads) k_assemble_atomic(AtomicParams p)
+__device__ __forceinline__ void atomic_item(const AtomicParams& p, int64_t t)
 {
     constexpr int NEN = 1 << DIM;
     constexpr int NF = FormTraits<FORM, DIM>::NF;
     constexpr int NSRC = FormTraits<FORM, DIM>::NSRC;
     const int64_t n_el = p.n_el;
     const int64_t n_items = COLOURED ? p.n_list : n_el;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_items * NEN * NF) return;
     const int64_t e = COLOURED ? (int64_t)p.elems[t % n_items] : t % n_el;
     const int ai = (int)(t / n_items);
@@ -137,13 +137,19 @@ __global__ void __launch_bounds__(kThreads) k_assemble_atomic(AtomicParams p)
     }
 }
 
-template <typename T>
-__global__ void k_dirichlet(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-                            const uint8_t* __restrict__ mask, int64_t n_rows, T* __restrict__ K,
-                            T* __restrict__ d)
+template <int FORM, int DIM, bool COLOURED, typename T>
+__global__ void __launch_bounds__(kThreads) k_assemble_atomic(AtomicParams p)
 {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_rows) return;
+    atomic_item<FORM, DIM, COLOURED, T>(p, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Homogeneous Dirichlet elimination of row r (structure kept): a constrained row becomes a
+// unit row with d = 0, a constrained column is zeroed in the other rows.
+template <typename T>
+__device__ __forceinline__ void dirichlet_row(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                                              const uint8_t* __restrict__ mask, int64_t r, T* __restrict__ K,
+                                              T* __restrict__ d)
+{
     const int64_t k0 = row_ptr[r], k1 = row_ptr[r + 1];
     if (mask[r]) {
         for (int64_t k = k0; k < k1; ++k) K[k] = (col_idx[k] == r) ? T(1) : T(0);
@@ -152,6 +158,55 @@ __global__ void k_dirichlet(const int32_t* __restrict__ row_ptr, const int32_t* 
         for (int64_t k = k0; k < k1; ++k)
             if (mask[col_idx[k]]) K[k] = T(0);
     }
+}
+
+// Small 2D meshes in one launch of one workgroup: status reset, clear, the colours one after
+// another behind workgroup barriers (the same plain read-modify-writes and order as the
+// per-colour launches), then the Dirichlet elimination.  The whole call is then one launch
+// instead of eight, which is what its time is made of at this size.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallMaxColors = 16;
+constexpr int64_t kSmallMaxItems = 16 * kSmallThreads;  // per colour: at most 16 items a thread
+struct SmallColors {
+    int n;
+    int64_t off[kSmallMaxColors + 1];
+};
+
+template <int FORM, typename T>
+__global__ void __launch_bounds__(kSmallThreads) k_assemble_small(AtomicParams p, const int32_t* __restrict__ color_elems,
+                                                                  SmallColors cl, const uint8_t* __restrict__ mask,
+                                                                  int64_t nnz, int64_t n_rows,
+                                                                  const int32_t* __restrict__ col_idx)
+{
+    constexpr int NEN = 4;
+    constexpr int NF = FormTraits<FORM, 2>::NF;
+    const int tid = threadIdx.x;
+    if (tid < 3) p.status[tid] = ~0ull;
+    T* K = (T*)p.K;
+    T* d = (T*)p.d;
+    for (int64_t k = tid; k < nnz; k += kSmallThreads) K[k] = T(0);
+    for (int64_t k = tid; k < n_rows; k += kSmallThreads) d[k] = T(0);
+    __syncthreads();
+    for (int c = 0; c < cl.n; ++c) {
+        AtomicParams pc = p;
+        pc.elems = color_elems + cl.off[c];
+        pc.n_list = cl.off[c + 1] - cl.off[c];
+        const int64_t n = pc.n_list * NEN * NF;
+        for (int64_t t = tid; t < n; t += kSmallThreads) atomic_item<FORM, 2, true, T>(pc, t);
+        __syncthreads();
+    }
+    if (mask)
+        for (int64_t r = tid; r < n_rows; r += kSmallThreads) dirichlet_row(p.row_ptr, col_idx, mask, r, K, d);
+}
+
+template <typename T>
+__global__ void k_dirichlet(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                            const uint8_t* __restrict__ mask, int64_t n_rows, T* __restrict__ K,
+                            T* __restrict__ d)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    dirichlet_row(row_ptr, col_idx, mask, r, K, d);
 }
 
 __global__ void k_reset_status(unsigned long long* s)
@@ -204,6 +259,43 @@ mf_status launch_atomic(const AssembleArgs& A, bool coloured)
     return MF_OK;
 }
 
+template <int FORM, typename T>
+mf_status launch_small(const AssembleArgs& A, const SmallColors& cl)
+{
+    const mf_pattern_s* P = A.P;
+    AtomicParams p{};
+    p.form = *A.form;
+    p.n_el = P->n_elems;
+    p.n_nodes = P->n_nodes;
+    p.conn = P->conn;
+    p.coords = A.coords;
+    p.row_ptr = P->row_ptr;
+    p.nbr_ptr = P->nbr_ptr;
+    p.rank = P->rank;
+    p.elem_param = A.elem_param;
+    p.src = FORM == MF_FORM_NS_SUPG ? A.lin_state : A.nodal_src;
+    p.field_major = P->numbering == MF_FIELD_MAJOR;
+    p.K = A.K;
+    p.d = A.d;
+    p.status = P->status;
+    k_assemble_small<FORM, T><<<1, kSmallThreads, 0, A.stream>>>(p, P->color_elems, cl, A.dirichlet, P->nnz,
+                                                                  P->n_rows, P->col_idx);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+template <typename T>
+mf_status dispatch_small(const AssembleArgs& A, const SmallColors& cl)
+{
+    switch (A.form->kind) {
+        case MF_FORM_MASS: return launch_small<MF_FORM_MASS, T>(A, cl);
+        case MF_FORM_POISSON: return launch_small<MF_FORM_POISSON, T>(A, cl);
+        case MF_FORM_ELASTICITY: return launch_small<MF_FORM_ELASTICITY, T>(A, cl);
+        case MF_FORM_NS_SUPG: return launch_small<MF_FORM_NS_SUPG, T>(A, cl);
+    }
+    return set_error(MF_ERR_ARG, "unknown form kind %d", (int)A.form->kind);
+}
+
 template <typename T>
 mf_status dispatch_atomic(const AssembleArgs& A, bool c)
 {
@@ -227,6 +319,23 @@ mf_status dispatch_atomic(const AssembleArgs& A, bool c)
 mf_status assemble_atomic(const AssembleArgs& A, bool coloured)
 {
     return A.prec == MF_F64 ? dispatch_atomic<double>(A, coloured) : dispatch_atomic<float>(A, coloured);
+}
+
+mf_status assemble_small(const AssembleArgs& A)
+{
+    const mf_pattern_s* P = A.P;
+    if (P->dim != 2 || P->order != 1 || P->n_elems == 0) return MF_ERR_UNSUPPORTED;
+    mf_status st = ensure_coloring(P, A.stream);
+    if (st != MF_OK) return st;
+    const int n_col = (int)P->color_ptr.size() - 1;
+    if (n_col < 1 || n_col > kSmallMaxColors) return MF_ERR_UNSUPPORTED;
+    SmallColors cl{};
+    cl.n = n_col;
+    const int64_t rows_per_elem = 4 * (int64_t)P->nf;
+    for (int c = 0; c <= n_col; ++c) cl.off[c] = P->color_ptr[c];
+    for (int c = 0; c < n_col; ++c)
+        if ((cl.off[c + 1] - cl.off[c]) * rows_per_elem > kSmallMaxItems) return MF_ERR_UNSUPPORTED;
+    return A.prec == MF_F64 ? dispatch_small<double>(A, cl) : dispatch_small<float>(A, cl);
 }
 
 mf_status apply_dirichlet(const AssembleArgs& A)

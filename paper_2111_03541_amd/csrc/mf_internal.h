@@ -79,6 +79,11 @@ struct AssembleArgs {
 // element-parallel scatter: hardware atomics, or colour by colour with plain adds
 // (deterministic sums)
 mf_status assemble_atomic(const AssembleArgs& a, bool coloured);
+// small 2D meshes (at most 16 colours of at most 16k rows each): status reset, clear,
+// coloured scatter and Dirichlet elimination in one single-workgroup launch; the same sums
+// as assemble_atomic(a, true) + apply_dirichlet.  MF_ERR_UNSUPPORTED (nothing launched,
+// no error recorded) for any other mesh.
+mf_status assemble_small(const AssembleArgs& a);
 mf_status assemble_quadratic(const AssembleArgs& a);  // assemble_quadratic.hip: MF_HEX20, MF_QUAD8
 mf_status assemble_column(const AssembleArgs& a);
 mf_status apply_dirichlet(const AssembleArgs& a);
