@@ -963,10 +963,11 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
     double* v = (double*)dalloc(sizeof(double) * n);
     double* sh = (double*)dalloc(sizeof(double) * n);
     double* t = (double*)dalloc(sizeof(double) * n);
+    double* xbest = (double*)dalloc(sizeof(double) * n);  // iterate of the smallest residual seen
     double* rv_part = (double*)dalloc(sizeof(double) * spmv_blocks);
     double* partial = (double*)dalloc(sizeof(double) * 2 * nb);
     double* sc = (double*)dalloc(sizeof(double) * (B_COUNT + 2));
-    if (!dinv || !r || !rh || !p || !ph || !v || !sh || !t || !rv_part || !partial || !sc)
+    if (!dinv || !r || !rh || !p || !ph || !v || !sh || !t || !xbest || !rv_part || !partial || !sc)
         return set_error(MF_ERR_OOM, "BiCGStab workspace allocation failed");
     const int jac = a.precond == MF_PRECOND_JACOBI ? 1 : 0;
 
@@ -1066,10 +1067,31 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
     };
     // When the recurrence claims convergence that the true residual denies (rounding
     // after large intermediate residuals separates the two), or on a breakdown, the
-    // method restarts from the current x with r = rh = b - Kx.
+    // method restarts with r = rh = b - Kx: from the current x, or from the iterate of the
+    // smallest recurrence residual seen when the current one has drifted more than ten
+    // times above it.  A solve that ends unconverged leaves whichever of the two has the
+    // smaller true residual in x.
     constexpr int kMaxRestarts = 64;
+    constexpr double kDrift = 10.0;
     int restarts = 0;
     int it = 0;
+    double best_rec = 1.0;  // x0 = 0
+    MF_HIP(hipMemcpyAsync(xbest, a.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    auto finish_unconverged = [&]() -> mf_status {
+        mf_status st = true_relres();
+        if (st != MF_OK) return st;
+        const double tx = res->true_relres;
+        MF_HIP(hipMemcpyAsync(t, a.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        MF_HIP(hipMemcpyAsync(a.x, xbest, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        st = true_relres();
+        if (st != MF_OK) return st;
+        if (!(res->true_relres < tx) && std::isfinite(tx)) {
+            MF_HIP(hipMemcpyAsync(a.x, t, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            MF_HIP(hipStreamSynchronize(s));
+            res->true_relres = tx;
+        }
+        return MF_OK;
+    };
     while (it < a.maxit) {
         const int todo = std::min(chunk, a.maxit - it);
         if (use_graph && todo == chunk) {
@@ -1082,7 +1104,12 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
         MF_HIP(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s));
         MF_HIP(hipStreamSynchronize(s));
         const bool broke = h[B_BREAK] != 0.0 || !std::isfinite(h[B_RR]);
-        if (std::sqrt(h[B_RR]) / bnorm <= a.tol || broke) {
+        const double rec = std::sqrt(h[B_RR]) / bnorm;
+        if (!broke && rec < best_rec) {
+            best_rec = rec;
+            MF_HIP(hipMemcpyAsync(xbest, a.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        }
+        if (rec <= a.tol || broke) {
             mf_status st = true_relres();
             if (st != MF_OK) return st;
             if (res->true_relres <= a.tol) {
@@ -1092,11 +1119,15 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
             }
             if (!std::isfinite(res->true_relres) || ++restarts > kMaxRestarts) {
                 res->iterations = it;
+                st = finish_unconverged();
+                if (st != MF_OK) return st;
                 return set_error(MF_ERR_NONFINITE,
                                  "BiCGStab breakdown near iteration %d after %d restarts (true relative residual %.3e)",
                                  it, restarts - 1, res->true_relres);
             }
             res->restarts = restarts;
+            if (res->true_relres > kDrift * best_rec)
+                MF_HIP(hipMemcpyAsync(a.x, xbest, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
             spmv(a.x, t, nullptr, nullptr);
             k_bcg_restart<<<vec_blocks, kThreads, 0, s>>>(n, a.b, t, r, rh, p, v, partial);
             k_bcg_beta<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc, 1);
@@ -1106,6 +1137,12 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
     mf_status st = true_relres();
     if (st != MF_OK) return st;
     res->iterations = it;
+    if (res->true_relres <= a.tol) {
+        res->converged = 1;
+        return MF_OK;
+    }
+    st = finish_unconverged();
+    if (st != MF_OK) return st;
     if (res->true_relres <= a.tol) {
         res->converged = 1;
         return MF_OK;
