@@ -417,8 +417,9 @@ def bench_transient(dev, n=96, steps=20, cpu=True, n_cpu=24):
 
 def bench_hex20(dev, n=24, steps=10, warmup=3, cpu=True):
     """Elasticity on 24^3 quadratic 20-node serendipity hexahedra (+-15% corner jitter,
-    lognormal E sigma 0.5, nu 0.3, body force U[-1,1]; 27 Gauss points), FP64 and FP32.
-    The oracle (numpy element loop) is timed on a 2^3 sample."""
+    lognormal E sigma 0.5, nu 0.3, body force U[-1,1]; 27 Gauss points), FP64 and FP32,
+    and the flow form on the same mesh.  The oracle (numpy element loop) is timed on a 2^3
+    sample of the elasticity."""
     import torch
     import workloads as W
     import paper_2111_03541_amd as mf
@@ -443,6 +444,28 @@ def bench_hex20(dev, n=24, steps=10, warmup=3, cpu=True):
         avg = float(np.mean(per))
         out[key] = {"avg_us": avg * 1e6, "elems_per_s": mesh.n_elems / avg}
         log(f"[bench] hex20 elasticity {n}^3 {key}: {avg * 1e6:.1f} us ({mesh.n_elems / avg / 1e6:.2f} M el/s)")
+        del K, d
+    # the flow form on the same bricks: tangent and residual at a smooth random state
+    # (8 Fourier modes, max |u| = 1; pressure U[-0.5, 0.5]), rho 1, mu 0.01
+    st = np.zeros((4, mesh.n_nodes))
+    st[:3] = W.fourier_velocity(mesh.coords, 5)
+    st[3] = W.uniform_nodal(1, mesh.n_nodes, -0.5, 0.5, 3)[0]
+    tm, tc = ns_taus(2 * n)  # a brick of 2 x 2 x 2 Gauss-point spacings
+    patf = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 4)
+    flow = mf.Form(mf.NS_SUPG, rho=1.0, mu=0.01, tau_m=tm, tau_c=tc)
+    out["flow"] = {"nnz": patf.nnz}
+    for prec, dt, key in ((mf.F64, torch.float64, "f64"), (mf.F32, torch.float32, "f32")):
+        stt = torch.from_numpy(st).to(dt).to(dev)
+        K = torch.empty(patf.nnz, dtype=dt, device=dev)
+        d = torch.empty(patf.n_rows, dtype=dt, device=dev)
+
+        def step_flow():
+            patf.assemble(flow, coords, precision=prec, lin_state=stt, K=K, d=d)
+
+        _, per = time_launches(step_flow, steps, warmup, stream)
+        avg = float(np.mean(per))
+        out["flow"][key] = {"avg_us": avg * 1e6, "elems_per_s": mesh.n_elems / avg}
+        log(f"[bench] hex20 flow {n}^3 {key}: {avg * 1e6:.1f} us ({mesh.n_elems / avg / 1e6:.2f} M el/s)")
         del K, d
     if cpu:
         import oracle as O
