@@ -1,0 +1,119 @@
+"""Oracle pins for the geometric multigrid V-cycle (oracle/multigrid.py), the preconditioner
+of the Newton step's Krylov solve (Sec. 2.1; the solver of Sec. 2.2 D-4 is left open by
+the paper).
+
+  * trilinear interpolation is exact on trilinear functions of the node indices, in both
+    DOF numberings;
+  * R = P^T has the textbook full-weighting weights (1, 1/2, 1/4, 1/8 by the number of
+    axes along which a fine node is offset from the coarse one);
+  * Galerkin identity: on an undistorted (here anisotropic) box, the coarse space is a
+    subspace of the fine one and 2-point Gauss integrates Q1 mass, conduction and
+    elasticity exactly, so P^T A_fine P is the coarse rediscretisation;
+  * the V-cycle as a stationary iteration on Q1 conduction with Dirichlet walls reduces the
+    error by a grid-independent factor well below 1;
+  * the cycle is a linear map (fixed sweeps, zero initial guesses).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.multigrid as MG
+import workloads as W
+
+
+def test_prolongation_is_exact_on_trilinear_functions():
+    rng = np.random.default_rng(0)
+    fine = (4, 6, 2)
+    c = rng.uniform(-1, 1, size=8)
+
+    def f(i, j, k):
+        return (c[0] + c[1] * i + c[2] * j + c[3] * k + c[4] * i * j + c[5] * j * k + c[6] * i * k
+                + c[7] * i * j * k)
+
+    fi, fj, fk = MG.node_ijk(fine)
+    ci, cj, ck = MG.node_ijk((2, 3, 1))
+    for numbering in (O.NODE_MAJOR, O.FIELD_MAJOR):
+        nf = 2
+        P = MG.prolongation(fine, nf, numbering)
+        vc = np.zeros(P.shape[1])
+        expect = np.zeros(P.shape[0])
+        nnc, nnf = ci.size, fi.size
+        for fld in range(nf):
+            s = 1.0 + fld
+            vc[MG.dof_index(np.arange(nnc), fld, nnc, nf, numbering)] = s * f(ci, cj, ck)
+            expect[MG.dof_index(np.arange(nnf), fld, nnf, nf, numbering)] = s * f(fi / 2, fj / 2, fk / 2)
+        np.testing.assert_allclose(P @ vc, expect, rtol=0, atol=1e-13)
+
+
+def test_restriction_has_full_weighting_weights():
+    fine = (4, 4, 4)
+    R = MG.prolongation(fine, 1).T.tocsr()
+    # coarse node (1,1,1): the interior one, fine node (2,2,2)
+    row = 1 + 3 * (1 + 3 * 1)
+    cols = R.indices[R.indptr[row]:R.indptr[row + 1]]
+    vals = R.data[R.indptr[row]:R.indptr[row + 1]]
+    fi, fj, fk = MG.node_ijk(fine)
+    assert cols.size == 27
+    for col, v in zip(cols, vals):
+        off = abs(fi[col] - 2) + abs(fj[col] - 2) + abs(fk[col] - 2)
+        assert max(abs(fi[col] - 2), abs(fj[col] - 2), abs(fk[col] - 2)) == 1 or off == 0
+        assert v == 0.5 ** off
+    assert vals.sum() == 8.0
+
+
+@pytest.mark.parametrize("kind,nf,prm", [(O.POISSON, 1, dict(coef=1.7)), (O.MASS, 1, dict(coef=2.0)),
+                                         (O.ELASTICITY, 3, dict(coef=1.0, nu=0.3))])
+@pytest.mark.parametrize("numbering", [O.NODE_MAJOR, O.FIELD_MAJOR])
+def test_galerkin_identity_on_an_undistorted_box(kind, nf, prm, numbering):
+    mesh = W.structured_mesh((4, 4, 6), lengths=(1.0, 2.0, 0.5))
+    levels = MG.build_levels((4, 4, 6), mesh.coords, nf, kind, [prm, prm], 2, numbering=numbering)
+    Af, Ac, P = levels[0]["A"], levels[1]["A"], levels[0]["P"]
+    G = (P.T @ Af @ P).toarray()
+    ref = Ac.toarray()
+    scale = np.abs(ref).max()
+    assert np.abs(G - ref).max() <= 1e-12 * scale
+    # and the coarse grid's own geometry is the fine grid's at even nodes
+    assert levels[1]["dims"] == (2, 2, 3)
+    np.testing.assert_array_equal(levels[1]["mesh"].coords[:, 0], mesh.coords[:, 0])
+
+
+def _conduction_rate(n, cycles=8):
+    mesh = W.structured_mesh((n, n, n), jitter=0.1, seed=4)
+    mask = W.boundary_node_mask(mesh.shape)
+    n_levels = int(np.log2(n))  # down to 2 elements per axis
+    levels = MG.build_levels((n, n, n), mesh.coords, 1, O.POISSON, [dict(coef=1.0)] * n_levels, n_levels,
+                             dirichlet=mask)
+    A = levels[0]["A"]
+    rng = np.random.default_rng(1)
+    b = rng.uniform(-1, 1, A.shape[0])
+    b[mask.astype(bool)] = 0.0
+    import scipy.sparse.linalg as spla
+    xs = spla.spsolve(A.tocsc(), b)
+    x = np.zeros_like(b)
+    e0 = np.linalg.norm(xs)
+    for _ in range(cycles):
+        x = x + MG.vcycle(levels, b - A @ x, omega=0.5, pre=2, post=2, coarse_sweeps=20)
+    return (np.linalg.norm(xs - x) / e0) ** (1.0 / cycles)
+
+
+def test_vcycle_converges_at_a_grid_independent_rate():
+    r8 = _conduction_rate(8)
+    r16 = _conduction_rate(16)
+    # V(2,2) with omega = 1/2 damped Jacobi: 0.21 on both grids; a restriction scaled by
+    # half (a plausible slip) gives 0.30 and 0.60
+    assert r8 < 0.25 and r16 < 0.25, (r8, r16)
+    assert abs(r16 - r8) < 0.05, (r8, r16)
+
+
+def test_vcycle_is_linear_on_the_flow_tangent():
+    n = 8
+    mesh = W.structured_mesh((n, n, n), jitter=0.1, seed=3)
+    st, mask = W.flow_boundary(mesh, "cavity")
+    st[:3] += 0.3 * W.fourier_velocity(mesh.coords, 2) * (1 - W.boundary_node_mask(mesh.shape))[None, :]
+    prm = [dict(rho=1.0, mu=0.01, tau_m=0.01 * 2 ** l, tau_c=0.02 * 2 ** l) for l in range(3)]
+    levels = MG.build_levels((n, n, n), mesh.coords, 4, O.NS_SUPG, prm, 3, state=st, dirichlet=mask)
+    rng = np.random.default_rng(5)
+    a, b = rng.standard_normal((2, levels[0]["A"].shape[0]))
+    za, zb = MG.vcycle(levels, a), MG.vcycle(levels, b)
+    z = MG.vcycle(levels, 2.0 * a - 3.0 * b)
+    np.testing.assert_allclose(z, 2.0 * za - 3.0 * zb, rtol=0, atol=1e-11 * np.abs(z).max())
