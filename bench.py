@@ -239,8 +239,10 @@ def ns_taus(n, U=1.0, nu=0.01):
     return tm, h * h / (12 * tm)
 
 
-def run_newton(dev, n, rtol=1e-10):
-    """Lid-driven cavity on n^3 Q1 hexes (rho 1, mu 0.01): mf_ns_newton from a zero interior."""
+def run_newton(dev, n, rtol=1e-10, multigrid=False):
+    """Lid-driven cavity on n^3 Q1 hexes (rho 1, mu 0.01): mf_ns_newton from a zero interior;
+    with multigrid, mf_ns_newton_mg (each level's stabilisation constants from its own
+    element size)."""
     import torch
     import workloads as W
     import paper_2111_03541_amd as mf
@@ -255,8 +257,13 @@ def run_newton(dev, n, rtol=1e-10):
     s = torch.cuda.Stream(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    mgo = None
+    if multigrid:
+        lv = [ns_taus(n / 2 ** l) for l in range(8)]
+        mgo = dict(tau_m=[t[0] for t in lv], tau_c=[t[1] for t in lv])
     with torch.cuda.stream(s):
-        res = mf.ns_newton(pat, form, coords, state, dirichlet=m, rtol=rtol, lin_tol=1e-10, stream=s)
+        res = mf.ns_newton(pat, form, coords, state, dirichlet=m, rtol=rtol, lin_tol=1e-10, stream=s,
+                           multigrid=mgo)
     s.synchronize()
     wall = time.perf_counter() - t0
     return mesh, pat, res, wall
@@ -292,6 +299,22 @@ def bench_newton(dev, n=32, cpu=True, n_cpu=16):
         out["cpu_oracle_small"] = {"n": n_cpu, "steps": len(hist) - 1, "converged": ok, "ms": t * 1e3,
                                    "kind": "oracle (FP64 assembly, scipy sparse LU per step)", "cores": 1}
         log(f"[bench] oracle Newton {n_cpu}^3: {len(hist) - 1} steps in {t:.1f} s; GPU {wall_s * 1e3:.1f} ms")
+    return out
+
+
+def bench_newton_mg(dev, sizes=(32, 48)):
+    """The cavity of bench_newton with the multigrid-preconditioned BiCGStab
+    (mf_ns_newton_mg: rediscretised coarse tangents down to at most 512 rows, damped Jacobi
+    V(2,2)), on the benchmark's 32^3 mesh and on the flow Jacobian's 48^3 mesh, where
+    Jacobi-BiCGStab breaks down."""
+    run_newton(dev, 8, multigrid=True)  # warm-up
+    out = {}
+    for n in sizes:
+        _, pat, res, wall = run_newton(dev, n, multigrid=True)
+        log(f"[bench] Newton cavity {n}^3, multigrid: {res['steps']} steps, {res['lin_iterations']} BiCGStab "
+            f"iterations, {wall * 1e3:.1f} ms, |R| {['%.1e' % r for r in res['res_norm']]}")
+        out[str(n)] = {"n_dofs": pat.n_rows, "steps": res["steps"], "converged": res["converged"],
+                       "lin_iterations": res["lin_iterations"], "ms": wall * 1e3, "res_norm": res["res_norm"]}
     return out
 
 
@@ -684,6 +707,7 @@ def main():
     record["secondary"]["batched_256_f32"] = bench_batch(dev)
     record["secondary"]["ns_48_f32"] = bench_ns(dev)
     record["secondary"]["ns_newton_cavity_32"] = bench_newton(dev, cpu=not args.no_cpu)
+    record["secondary"]["ns_newton_cavity_multigrid"] = bench_newton_mg(dev)
     record["secondary"]["transient_96"] = bench_transient(dev, cpu=not args.no_cpu)
     record["secondary"]["hex20_elasticity_24"] = bench_hex20(dev, cpu=not args.no_cpu)
     record["secondary"]["ns_newton_weak_cavity_32"] = bench_newton_weak(dev)

@@ -365,11 +365,14 @@ mf_status mf_assemble_boundary(const mf_pattern_t* P, const mf_bform* form, cons
 typedef enum {
     MF_PRECOND_NONE = 0,    /* plain CG                                                 */
     MF_PRECOND_JACOBI = 1,  /* z = r / diag(K)                                          */
-    MF_PRECOND_NN = 2       /* learned network (mf_nn_t), flexible CG; an iteration whose
+    MF_PRECOND_NN = 2,      /* learned network (mf_nn_t), flexible CG; an iteration whose
                                z.r <= 0 or non-finite z falls back to the Jacobi z      */
+    MF_PRECOND_MG = 3       /* one geometric multigrid V-cycle (mf_mg_t, see below); mf_pcg
+                               uses the flexible beta with it                           */
 } mf_precond_kind;
 
 typedef struct mf_nn_s mf_nn_t;   /* opaque learned preconditioner, see below */
+typedef struct mf_mg_s mf_mg_t;   /* opaque multigrid preconditioner, see below */
 
 typedef struct {
     int64_t n_rows;
@@ -390,6 +393,7 @@ typedef struct {
                                  (0 = 512; judged at the host checks); ignored by
                                  mf_bicgstab                                             */
     const mf_nn_t* net;       /* MF_PRECOND_NN only */
+    const mf_mg_t* mg;        /* MF_PRECOND_MG only: updated for this K (mf_mg_update)    */
 } mf_pcg_opts;
 
 typedef struct {
@@ -440,8 +444,9 @@ mf_status mf_spmv(const mf_csr* A, const double* x, double* y, void* stream);
 /*
  * mf_bicgstab - solve K x = b for a non-symmetric K (the Newton tangent of the flow form
  * of Sec. 4.3; Sec. 2.2 D-4 leaves the solver open) by BiCGStab from x0 = 0 with shadow
- * residual b, right-preconditioned by Jacobi (opts->precond MF_PRECOND_JACOBI) or
- * unpreconditioned (MF_PRECOND_NONE).  Options, result and synchronisation as mf_pcg
+ * residual b, right-preconditioned by Jacobi (opts->precond MF_PRECOND_JACOBI), by one
+ * multigrid V-cycle (MF_PRECOND_MG) or unpreconditioned (MF_PRECOND_NONE).  Options, result
+ * and synchronisation as mf_pcg
  * (opts->net is ignored, res->fallbacks is 0); the true residual |b - K x|_2 / |b|_2
  * decides convergence.  On a breakdown (rh.r, rh.Kp or t.t exactly 0 or non-finite), or
  * when the recurrence residual meets tol but the true residual does not, the method
@@ -521,6 +526,73 @@ mf_status mf_ns_newton_ex(const mf_pattern_t* P, const mf_form* form, const doub
                           const uint8_t* dirichlet, const mf_bset* bsets, int32_t n_bsets,
                           const mf_quadrature* quad, const mf_newton_opts* opts, mf_newton_result* res,
                           void* stream);
+
+/* ------------------------------------------------------------------------------------
+ * Geometric multigrid preconditioner on a structured grid of 8-node hexahedra (the
+ * lexicographic grid of mf_pattern_grid).  The paper leaves the solver of Sec. 2.2 D-4
+ * open; this one serves the Newton step of Sec. 2.1 where the Jacobi preconditioner is too
+ * weak (the flow tangent of Sec. 4.3 past about 36^3 elements).
+ *   Levels: level 0 is the pattern's grid; level l+1 halves the elements per axis while
+ *     every axis of level l has an even element count, and its node (i,j,k) is the level-l
+ *     node (2i,2j,2k).  Coarsening stops at max_levels levels, or at the first level with at
+ *     most coarse_rows rows, or when an axis is odd.
+ *   Coarse operators: the same form assembled (FP64, column kernel) on each coarser grid
+ *     from the coordinates, linearisation state and Dirichlet flags of the coincident fine
+ *     nodes (injection), with the flow form's stabilisation constants of that level.
+ *   Transfers: P = trilinear interpolation (field by field), restriction R = P^T.
+ *   Smoother: damped Jacobi x <- x + omega D^-1 (b - A x), D^-1 = 0 where diag A = 0.
+ *   V-cycle V(l, b): on the coarsest level coarse_sweeps sweeps from x = 0; otherwise
+ *     pre_sweeps sweeps from x = 0, r = b - A x, b_c = R r with the coarse Dirichlet rows set
+ *     to 0, x += P V(l+1, b_c), post_sweeps sweeps.  It is a fixed linear map of b.
+ * ------------------------------------------------------------------------------------ */
+#define MF_MG_MAX_LEVELS 8
+typedef struct {
+    int32_t max_levels;     /* levels including level 0, 1..MF_MG_MAX_LEVELS (0 = 8)         */
+    int32_t coarse_rows;    /* stop coarsening at a level with at most this many rows (0 = 512) */
+    int32_t pre_sweeps;     /* >= 0 */
+    int32_t post_sweeps;    /* >= 0 */
+    int32_t coarse_sweeps;  /* >= 0 */
+    double omega;           /* Jacobi damping, in (0, 1]                                      */
+    double tau_m[MF_MG_MAX_LEVELS];  /* flow form: tau_m, tau_c of level l's tangent (entry 0 */
+    double tau_c[MF_MG_MAX_LEVELS];  /* unused: level 0 is the caller's K); 0 = the form's    */
+} mf_mg_opts;
+
+/* Builds the level grids and their patterns (the pattern's numbering and field count) and
+   allocates every level's vectors.  P: 3D 8-node hexahedra on a structured grid with full
+   coupling (MF_ERR_UNSUPPORTED otherwise).  (sync)  Errors: MF_ERR_ARG, MF_ERR_UNSUPPORTED,
+   MF_ERR_OOM, MF_ERR_HIP.  *out is NULL on error. */
+mf_status mf_mg_create(const mf_pattern_t* P, const mf_mg_opts* opts, void* stream, mf_mg_t** out);
+
+/* (host) number of levels and each level's element counts per axis (dims [n_levels][3],
+   may be NULL; room for MF_MG_MAX_LEVELS). */
+mf_status mf_mg_levels(const mf_mg_t* mg, int32_t* n_levels, int64_t* dims);
+
+/* Prepares the cycle for the level-0 operator K [nnz of P] (device FP64, borrowed: it must
+   stay unchanged until the next update): injects coords [3][n_nodes] and the fields'
+   lin_state and dirichlet to every coarser level, assembles each coarse operator with
+   `form` and `quad`, and forms every level's D^-1.  fields may be NULL; its elem_param and
+   nodal_src must be NULL (MF_ERR_UNSUPPORTED).  (sync)  Errors: those of mf_assemble (a
+   coarse element with det J <= 0: MF_ERR_BAD_JACOBIAN), MF_ERR_ARG, MF_ERR_HIP. */
+mf_status mf_mg_update(mf_mg_t* mg, const mf_form* form, const double* coords, const mf_fields* fields,
+                       const mf_quadrature* quad, const double* K, void* stream);
+
+/* z = V(0, r): one cycle, r and z [n_rows] device FP64 (distinct).  Kernels only, on the
+   stream (async, no allocation, no memset: can be captured in a HIP graph).  Calls that
+   overlap on one mf_mg_t race (they share its level vectors).  Errors: MF_ERR_ARG (not
+   updated yet, NULL vectors), MF_ERR_HIP. */
+mf_status mf_mg_apply(const mf_mg_t* mg, const double* r, double* z, void* stream);
+
+void mf_mg_destroy(mf_mg_t* mg);
+
+/*
+ * mf_ns_newton_mg - mf_ns_newton with the multigrid preconditioner in every linear solve:
+ * each step assembles K and d, updates the cycle for that K (mf_mg_update with the current
+ * state) and solves with mf_bicgstab (MF_PRECOND_MG).  P must be a structured grid as for
+ * mf_mg_create.  (sync)  Errors: those of mf_ns_newton, mf_mg_create and mf_mg_update.
+ */
+mf_status mf_ns_newton_mg(const mf_pattern_t* P, const mf_form* form, const double* coords, double* state,
+                          const uint8_t* dirichlet, const mf_mg_opts* mg, const mf_quadrature* quad,
+                          const mf_newton_opts* opts, mf_newton_result* res, void* stream);
 
 /* ------------------------------------------------------------------------------------
  * Learned preconditioner for mf_pcg on structured-grid scalar systems (node id

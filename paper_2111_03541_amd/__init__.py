@@ -68,7 +68,16 @@ class _CSR(C.Structure):
 
 class _PcgOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32), ("use_graph", C.c_int32),
-                ("precond", C.c_int), ("stall_iters", C.c_int32), ("net", C.c_void_p)]
+                ("precond", C.c_int), ("stall_iters", C.c_int32), ("net", C.c_void_p), ("mg", C.c_void_p)]
+
+
+MG_MAX_LEVELS = 8
+
+
+class _MgOpts(C.Structure):
+    _fields_ = [("max_levels", C.c_int32), ("coarse_rows", C.c_int32), ("pre_sweeps", C.c_int32),
+                ("post_sweeps", C.c_int32), ("coarse_sweeps", C.c_int32), ("omega", C.c_double),
+                ("tau_m", C.c_double * MG_MAX_LEVELS), ("tau_c", C.c_double * MG_MAX_LEVELS)]
 
 
 class _PcgResult(C.Structure):
@@ -76,7 +85,7 @@ class _PcgResult(C.Structure):
                 ("restarts", C.c_int32), ("true_relres", C.c_double)]
 
 
-PRECOND_NONE, PRECOND_JACOBI, PRECOND_NN = 0, 1, 2
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_NN, PRECOND_MG = 0, 1, 2, 3
 
 NEWTON_MAX_HISTORY = 64
 
@@ -127,7 +136,8 @@ EXPORTS = [
     "mf_nn_create", "mf_nn_params", "mf_nn_set_system", "mf_nn_apply", "mf_nn_train_step", "mf_nn_destroy", "mf_spmv",
     "mf_bicgstab", "mf_ns_newton", "mf_ns_newton_ex", "mf_assemble_boundary", "mf_heat_transient",
     "mf_pcg_noalloc", "mf_pcg_noalloc_max_rows", "mf_nn_checkpoint_size", "mf_nn_save", "mf_nn_load",
-    "mf_batch_tiles",
+    "mf_batch_tiles", "mf_mg_create", "mf_mg_levels", "mf_mg_update", "mf_mg_apply", "mf_mg_destroy",
+    "mf_ns_newton_mg",
 ]
 
 
@@ -184,6 +194,14 @@ def load():
                                     C.POINTER(_NewtonOpts), C.POINTER(_NewtonResult), P]
     lib.mf_nn_destroy.argtypes = [P]
     lib.mf_nn_destroy.restype = None
+    lib.mf_mg_create.argtypes = [P, C.POINTER(_MgOpts), P, C.POINTER(P)]
+    lib.mf_mg_levels.argtypes = [P, C.POINTER(i32), P]
+    lib.mf_mg_update.argtypes = [P, C.POINTER(_Form), P, C.POINTER(_Fields), C.POINTER(_Quad), P, P]
+    lib.mf_mg_apply.argtypes = [P, P, P, P]
+    lib.mf_mg_destroy.argtypes = [P]
+    lib.mf_mg_destroy.restype = None
+    lib.mf_ns_newton_mg.argtypes = [P, C.POINTER(_Form), P, P, P, C.POINTER(_MgOpts), C.POINTER(_Quad),
+                                    C.POINTER(_NewtonOpts), C.POINTER(_NewtonResult), P]
     lib.mf_last_error.restype = C.c_char_p
     lib.mf_version.restype = C.c_char_p
     _lib = lib
@@ -542,8 +560,68 @@ class Net:
             self.restore(f.read())
 
 
+def mg_opts(max_levels=0, coarse_rows=0, pre_sweeps=2, post_sweeps=2, coarse_sweeps=20, omega=0.5, tau_m=(),
+            tau_c=()):
+    """Options of the multigrid cycle (mf_mg_opts); tau_m[l], tau_c[l]: the flow form's
+    stabilisation constants on level l (entry 0 unused, 0 = the form's own)."""
+    tm = list(tau_m) + [0.0] * (MG_MAX_LEVELS - len(tau_m))
+    tc = list(tau_c) + [0.0] * (MG_MAX_LEVELS - len(tau_c))
+    return _MgOpts(max_levels, coarse_rows, pre_sweeps, post_sweeps, coarse_sweeps, omega,
+                   (C.c_double * MG_MAX_LEVELS)(*tm[:MG_MAX_LEVELS]), (C.c_double * MG_MAX_LEVELS)(*tc[:MG_MAX_LEVELS]))
+
+
+class Multigrid:
+    """Geometric multigrid V-cycle on a structured-grid pattern (mf_mg_t)."""
+
+    def __init__(self, pattern, stream=None, **opts):
+        lib = load()
+        self.pattern = pattern
+        self.opts = mg_opts(**opts)
+        h = C.c_void_p()
+        check(lib.mf_mg_create(pattern.handle, C.byref(self.opts), _stream(stream), C.byref(h)))
+        self.handle = h
+        self._K = None
+
+    def levels(self):
+        """Element counts per axis of every level, finest first."""
+        n = C.c_int32()
+        dims = (C.c_int64 * (3 * MG_MAX_LEVELS))()
+        check(load().mf_mg_levels(self.handle, C.byref(n), dims))
+        return [tuple(dims[3 * l:3 * l + 3]) for l in range(n.value)]
+
+    def update(self, form, coords, K, lin_state=None, dirichlet=None, points_per_axis=2, stream=None):
+        """Assemble the coarse levels for the level-0 operator K (kept referenced)."""
+        import torch
+        p = self.pattern
+        _require(coords, "coords", torch.float64, p.dim * p.n_nodes, optional=False)
+        _require(K, "K", torch.float64, p.nnz, optional=False)
+        _require(lin_state, "lin_state", torch.float64, 4 * p.n_nodes)
+        _require(dirichlet, "dirichlet", torch.uint8, p.n_rows)
+        F = _Fields(None, None, _ptr(lin_state), _ptr(dirichlet))
+        q = _Quad(points_per_axis)
+        check(load().mf_mg_update(self.handle, C.byref(form.c), _ptr(coords), C.byref(F), C.byref(q), _ptr(K),
+                                  _stream(stream)))
+        self._K = K
+
+    def apply(self, r, z=None, stream=None):
+        """z = V(0, r), one cycle on the stream."""
+        import torch
+        _require(r, "r", torch.float64, self.pattern.n_rows, optional=False)
+        if z is None:
+            z = torch.empty_like(r)
+        _require(z, "z", torch.float64, self.pattern.n_rows, optional=False)
+        check(load().mf_mg_apply(self.handle, _ptr(r), _ptr(z), _stream(stream)))
+        return z
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.mf_mg_destroy(h)
+            self.handle = None
+
+
 def pcg(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PRECOND_JACOBI, net=None,
-        check_every=8, use_graph=True, stream=None, raise_on_fail=True, stall_iters=0):
+        check_every=8, use_graph=True, stream=None, raise_on_fail=True, stall_iters=0, mg=None):
     """Solve K x = b (FP64 CSR on the device; row_ptr/col_idx int32) by PCG from x0 = 0.
 
     Returns (x, result dict).  use_graph needs a non-default stream; with the default
@@ -556,7 +634,7 @@ def pcg(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PREC
         x = torch.empty(n, dtype=torch.float64, device=b.device)
     A = _CSR(n, _ptr_any(row_ptr), _ptr_any(col_idx), _ptr(values))
     opts = _PcgOpts(tol, maxit, check_every, int(bool(use_graph)), precond, stall_iters,
-                    None if net is None else net.handle)
+                    None if net is None else net.handle, None if mg is None else mg.handle)
     res = _PcgResult()
     st = lib.mf_pcg(C.byref(A), _ptr(b), _ptr(x), C.byref(opts), C.byref(res), _stream(stream))
     out = {"iterations": res.iterations, "converged": bool(res.converged), "fallbacks": res.fallbacks,
@@ -577,7 +655,7 @@ def pcg_noalloc(row_ptr, col_idx, values, b, x, tol=1e-8, maxit=20000, precond=P
     _require(b, "b", torch.float64, optional=False)
     _require(x, "x", torch.float64, n, optional=False)
     A = _CSR(n, _ptr_any(row_ptr), _ptr_any(col_idx), _ptr(values))
-    opts = _PcgOpts(tol, maxit, check_every, 0, precond, 0, None)
+    opts = _PcgOpts(tol, maxit, check_every, 0, precond, 0, None, None)
     res = _PcgResult()
     st = lib.mf_pcg_noalloc(C.byref(A), _ptr(b), _ptr(x), C.byref(opts), C.byref(res), _stream(stream))
     out = {"iterations": res.iterations, "converged": bool(res.converged), "fallbacks": res.fallbacks,
@@ -592,7 +670,7 @@ def noalloc_max_rows() -> int:
 
 
 def bicgstab(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond=PRECOND_JACOBI,
-             check_every=8, use_graph=True, stream=None, raise_on_fail=True):
+             check_every=8, use_graph=True, stream=None, raise_on_fail=True, mg=None):
     """Solve K x = b for a non-symmetric FP64 CSR K on the device by BiCGStab from x0 = 0.
 
     Returns (x, result dict) like pcg."""
@@ -602,7 +680,8 @@ def bicgstab(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond
     if x is None:
         x = torch.empty(n, dtype=torch.float64, device=b.device)
     A = _CSR(n, _ptr_any(row_ptr), _ptr_any(col_idx), _ptr(values))
-    opts = _PcgOpts(tol, maxit, check_every, int(bool(use_graph)), precond, 0, None)
+    opts = _PcgOpts(tol, maxit, check_every, int(bool(use_graph)), precond, 0, None,
+                    None if mg is None else mg.handle)
     res = _PcgResult()
     st = lib.mf_bicgstab(C.byref(A), _ptr(b), _ptr(x), C.byref(opts), C.byref(res), _stream(stream))
     out = {"iterations": res.iterations, "converged": bool(res.converged), "true_relres": res.true_relres,
@@ -614,11 +693,13 @@ def bicgstab(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond
 
 def ns_newton(pattern, form, coords, state, dirichlet=None, rtol=1e-10, atol=0.0, max_steps=20, lin_tol=1e-10,
               lin_maxit=20000, check_every=8, use_graph=True, points_per_axis=2, stream=None, raise_on_fail=True,
-              boundary=()):
+              boundary=(), multigrid=None):
     """Newton iteration for the steady flow form; state [4][n_nodes] FP64 (cuda) is updated
     in place.  boundary: face sets (kind, face_elem int32 cuda, face_id uint8 cuda, coef,
     value, target or None) whose boundary forms enter every step before the Dirichlet
-    elimination.  Returns the result dict (steps, converged, lin_iterations, res_norm)."""
+    elimination.  multigrid: None (Jacobi-preconditioned solves) or a dict of mg_opts
+    arguments (mf_ns_newton_mg; no boundary face sets).  Returns the result dict (steps,
+    converged, lin_iterations, res_norm)."""
     import torch
     lib = load()
     _require(state, "state", torch.float64, 4 * pattern.n_nodes, optional=False)
@@ -635,8 +716,15 @@ def ns_newton(pattern, form, coords, state, dirichlet=None, rtol=1e-10, atol=0.0
         vals = list(value) + [0.0] * (9 - len(value))
         sets[k] = _BSet(_BForm(kind, coef, (C.c_double * 9)(*vals)), int(fe.shape[0]), _ptr(fe), _ptr(fi),
                         _ptr(target))
-    st = lib.mf_ns_newton_ex(pattern.handle, C.byref(form.c), _ptr(coords), _ptr(state), _ptr(dirichlet), sets,
-                             len(boundary), C.byref(q), C.byref(opts), C.byref(res), _stream(stream))
+    if multigrid is not None:
+        if boundary:
+            raise ValueError("the multigrid Newton takes no boundary face sets")
+        mo = mg_opts(**multigrid)
+        st = lib.mf_ns_newton_mg(pattern.handle, C.byref(form.c), _ptr(coords), _ptr(state), _ptr(dirichlet),
+                                 C.byref(mo), C.byref(q), C.byref(opts), C.byref(res), _stream(stream))
+    else:
+        st = lib.mf_ns_newton_ex(pattern.handle, C.byref(form.c), _ptr(coords), _ptr(state), _ptr(dirichlet), sets,
+                                 len(boundary), C.byref(q), C.byref(opts), C.byref(res), _stream(stream))
     out = {"steps": res.steps, "converged": bool(res.converged), "lin_iterations": res.lin_iterations,
            "res_norm": [res.res_norm[k] for k in range(min(res.steps + 1, NEWTON_MAX_HISTORY))], "status": st}
     if st != OK and raise_on_fail:

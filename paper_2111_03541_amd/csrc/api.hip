@@ -287,6 +287,10 @@ static mf_status pcg_args(const mf_csr* A, const double* b, double* x, const mf_
             if (!opts->net) return set_error(MF_ERR_ARG, "MF_PRECOND_NN needs a network");
             return nn_bind_pcg(opts->net, A->n_rows, a);
         }
+        case MF_PRECOND_MG: {
+            if (!opts->mg) return set_error(MF_ERR_ARG, "MF_PRECOND_MG needs a multigrid cycle");
+            return mg_bind_pcg(opts->mg, A->n_rows, A->values, a);
+        }
         default: return set_error(MF_ERR_ARG, "unknown preconditioner %d", (int)opts->precond);
     }
     return MF_OK;
@@ -306,7 +310,7 @@ mf_status mf_pcg_noalloc(const mf_csr* A, const double* b, double* x, const mf_p
                          mf_pcg_result* res, void* stream)
 {
     g_err[0] = 0;
-    if (opts && opts->precond == MF_PRECOND_NN)
+    if (opts && (opts->precond == MF_PRECOND_NN || opts->precond == MF_PRECOND_MG))
         return set_error(MF_ERR_UNSUPPORTED, "mf_pcg_noalloc takes MF_PRECOND_NONE or MF_PRECOND_JACOBI");
     PcgArgs a;
     mf_status st = pcg_args(A, b, x, opts, res, stream, &a);
@@ -325,8 +329,8 @@ mf_status mf_bicgstab(const mf_csr* A, const double* b, double* x, const mf_pcg_
     if (A->n_rows > 0 && (!A->row_ptr || !A->col_idx || !A->values || !b || !x))
         return set_error(MF_ERR_ARG, "NULL matrix or vector");
     if (!(opts->tol > 0.0) || opts->maxit < 0) return set_error(MF_ERR_ARG, "tol must be > 0 and maxit >= 0");
-    if (opts->precond != MF_PRECOND_NONE && opts->precond != MF_PRECOND_JACOBI)
-        return set_error(MF_ERR_ARG, "BiCGStab takes MF_PRECOND_NONE or MF_PRECOND_JACOBI, not %d",
+    if (opts->precond != MF_PRECOND_NONE && opts->precond != MF_PRECOND_JACOBI && opts->precond != MF_PRECOND_MG)
+        return set_error(MF_ERR_ARG, "BiCGStab takes MF_PRECOND_NONE, MF_PRECOND_JACOBI or MF_PRECOND_MG, not %d",
                          (int)opts->precond);
     PcgArgs a{};
     a.n = A->n_rows;
@@ -341,6 +345,11 @@ mf_status mf_bicgstab(const mf_csr* A, const double* b, double* x, const mf_pcg_
     a.use_graph = opts->use_graph && stream != nullptr;
     a.stream = (hipStream_t)stream;
     a.precond = opts->precond;
+    if (opts->precond == MF_PRECOND_MG) {
+        if (!opts->mg) return set_error(MF_ERR_ARG, "MF_PRECOND_MG needs a multigrid cycle");
+        mf_status st = mg_bind_pcg(opts->mg, A->n_rows, A->values, &a);
+        if (st != MF_OK) return st;
+    }
     return run_bicgstab(a, res);
 }
 

@@ -61,6 +61,8 @@ mf_status ensure_coloring(const mf_pattern_s* P, hipStream_t s);
 
 struct PcgArgs;
 mf_status nn_bind_pcg(const mf_nn_t* net, int64_t n_rows, PcgArgs* a);
+// multigrid.hip: one V-cycle as the external preconditioner of a solve on `values`
+mf_status mg_bind_pcg(const mf_mg_t* mg, int64_t n_rows, const double* values, PcgArgs* a);
 
 // assemble.hip
 struct AssembleArgs {

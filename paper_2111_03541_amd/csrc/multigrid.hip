@@ -1,0 +1,567 @@
+// Geometric multigrid V-cycle on structured grids of 8-node hexahedra, the preconditioner
+// of the Newton step's Krylov solve (Sec. 2.1) where Jacobi is too weak; the paper leaves
+// the solver of Sec. 2.2 D-4 open.  Textbook multigrid:
+//   levels     level l+1 halves the elements per axis of level l; its node (i,j,k) is the
+//              level-l node (2i,2j,2k)
+//   operators  rediscretisation: the same form assembled (FP64) on each coarse grid from the
+//              coordinates, linearisation state and Dirichlet flags of the coincident fine
+//              nodes (injection)
+//   transfers  P = trilinear interpolation field by field, R = P^T (full weighting)
+//   smoother   damped Jacobi x <- x + omega D^-1 (b - A x)
+//   cycle      V(l, b): pre sweeps from x = 0, r = b - A x, b_c = R r (0 on coarse Dirichlet
+//              rows), x += P V(l+1, b_c), post sweeps; coarsest level: sweeps from x = 0.
+//
+// Kernels (one grid-stride pass each, all on the caller's stream, nothing allocated or
+// cleared with memset, so a cycle can be captured in a HIP graph):
+//   k_mg_sweep     one Jacobi sweep, out of place, with the SpMV fused (8 lanes per row for
+//                  the 4-field flow rows of up to 108 entries, 4 otherwise); the same kernel
+//                  forms the first sweep from x = 0 (no SpMV) and the residual b - A x
+//   k_mg_restrict  one thread per coarse node gathers its 27 fine neighbours, every field
+//   k_mg_prolong   one thread per fine node interpolates from its 1, 2, 4 or 8 parents
+//   k_mg_coarse    the coarsest level in one workgroup, the iterate in LDS, all sweeps in
+//                  one launch (levels of at most kCoarseMax rows; larger ones use k_mg_sweep)
+// Sweeps alternate between two buffers per level; the first one is chosen so that the last
+// sweep writes the level's output and no copy is needed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "mf_internal.h"
+#include "pcg.h"
+
+struct mf_mg_s {
+    struct Level {
+        int64_t nx = 0, ny = 0, nz = 0, n_nodes = 0, n_rows = 0;
+        mf_pattern_s* P = nullptr;         // owned for l >= 1
+        const mf_pattern_s* Pv = nullptr;  // this level's pattern
+        double* K = nullptr;               // owned for l >= 1
+        const double* Kv = nullptr;        // this level's operator (level 0: the caller's)
+        double* d = nullptr;               // l >= 1: right side written by the assembly
+        double* coords = nullptr;          // l >= 1: [3][n_nodes]
+        double* state = nullptr;           // l >= 1: [4][n_nodes] linearisation state
+        uint8_t* mask = nullptr;           // l >= 1: [n_rows]
+        double* dinv = nullptr;            // [n_rows]
+        double* x = nullptr;               // l >= 1: the cycle's output on this level
+        double* b = nullptr;               // l >= 1: the restricted right side
+        double* t = nullptr;               // second sweep buffer and residual
+    };
+    int n_levels = 0;
+    int nf = 0;
+    int fm = 0;  // field-major numbering
+    mf_mg_opts opts{};
+    bool has_mask = false;
+    bool updated = false;
+    Level L[MF_MG_MAX_LEVELS];
+    std::vector<void*> owned;
+};
+
+namespace mf {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxBlocks = 8192;
+constexpr int kCoarseMax = 4096;      // rows of a coarsest level solved in one workgroup
+constexpr int kCoarseThreads = 1024;
+constexpr int kCoarseLanes = 4;       // lanes per row in the coarsest-level kernel
+
+__device__ __forceinline__ int64_t dof_of(int64_t node, int f, int64_t n_nodes, int nf, int fm)
+{
+    return fm ? (int64_t)f * n_nodes + node : node * nf + f;
+}
+
+// Connectivity of the lexicographic grid: corner a of element (ex,ey,ez) is node
+// (ex + (a&1), ey + ((a>>1)&1), ez + ((a>>2)&1)).
+__global__ void __launch_bounds__(kThreads) k_mg_conn(int64_t nx, int64_t ny, int64_t n_el, int32_t* __restrict__ conn)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 8 * n_el;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int a = (int)(t / n_el);
+        const int64_t e = t % n_el;
+        const int64_t ex = e % nx, r = e / nx, ey = r % ny, ez = r / ny;
+        const int64_t i = ex + (a & 1), j = ey + ((a >> 1) & 1), k = ez + ((a >> 2) & 1);
+        conn[t] = (int32_t)(i + (nx + 1) * (j + (ny + 1) * k));
+    }
+}
+
+// Coarse node v = (i,j,k) takes the values of fine node (2i,2j,2k): coordinates, the
+// 4-field state (when given) and the Dirichlet flags of every field (when given).
+__global__ void __launch_bounds__(kThreads) k_mg_inject(int64_t cx, int64_t cy, int64_t cn, int64_t fx, int64_t fy,
+                                                        int64_t fn, int nf, int fm,
+                                                        const double* __restrict__ fcoords,
+                                                        double* __restrict__ ccoords,
+                                                        const double* __restrict__ fstate,
+                                                        double* __restrict__ cstate,
+                                                        const uint8_t* __restrict__ fmask,
+                                                        uint8_t* __restrict__ cmask)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < cn; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = v % (cx + 1), r = v / (cx + 1), j = r % (cy + 1), k = r / (cy + 1);
+        const int64_t w = 2 * i + (fx + 1) * (2 * j + (fy + 1) * (2 * k));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ccoords[c * cn + v] = fcoords[c * fn + w];
+        if (fstate) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cstate[c * cn + v] = fstate[c * fn + w];
+        }
+        if (fmask) {
+            for (int f = 0; f < nf; ++f) cmask[dof_of(v, f, cn, nf, fm)] = fmask[dof_of(w, f, fn, nf, fm)];
+        }
+    }
+}
+
+// dinv[i] = 1 / A_ii, 0 where the diagonal is 0
+__global__ void __launch_bounds__(kThreads) k_mg_dinv(int64_t n, const int32_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ ci, const double* __restrict__ A,
+                                                      double* __restrict__ dinv)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double di = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] == i) di = A[k];
+        dinv[i] = di != 0.0 ? 1.0 / di : 0.0;
+    }
+}
+
+enum SweepMode { kSweep = 0, kFirst = 1, kResidual = 2 };
+
+// kSweep:    out = in + omega dinv (b - A in)
+// kFirst:    out = omega dinv b            (the sweep from x = 0; A and in unused)
+// kResidual: out = b - A in
+// LANES consecutive threads share a row; every lane of a row group runs the same trip
+// count, so the group's shuffles see only active lanes.
+template <int LANES, int MODE>
+__global__ void __launch_bounds__(kThreads) k_mg_sweep(int64_t n, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci,
+                                                       const double* __restrict__ A,
+                                                       const double* __restrict__ dinv,
+                                                       const double* __restrict__ b,
+                                                       const double* __restrict__ in, double* __restrict__ out,
+                                                       double omega)
+{
+    const int lane = threadIdx.x % LANES;
+    const int64_t rows_per_pass = (int64_t)gridDim.x * (kThreads / LANES);
+    for (int64_t row = (blockIdx.x * (int64_t)kThreads + threadIdx.x) / LANES; row < n; row += rows_per_pass) {
+        double s = 0.0;
+        if (MODE != kFirst) {
+            const int k0 = rp[row], k1 = rp[row + 1];
+#pragma unroll 4
+            for (int k = k0 + lane; k < k1; k += LANES) s = fma(A[k], in[ci[k]], s);
+#pragma unroll
+            for (int off = LANES / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, LANES);
+        }
+        if (lane == 0) {
+            if (MODE == kFirst) out[row] = omega * dinv[row] * b[row];
+            else if (MODE == kSweep) out[row] = in[row] + omega * dinv[row] * (b[row] - s);
+            else out[row] = b[row] - s;
+        }
+    }
+}
+
+// bc = R rf on every coarse DOF (0 on coarse Dirichlet rows): coarse node (i,j,k) gathers
+// the fine nodes (2i+di, 2j+dj, 2k+dk), di,dj,dk in {-1,0,1}, with weight 1/2 per nonzero
+// offset.
+__global__ void __launch_bounds__(kThreads) k_mg_restrict(int64_t cx, int64_t cy, int64_t cn, int64_t fx, int64_t fy,
+                                                          int64_t fz, int64_t fn, int nf, int fm,
+                                                          const double* __restrict__ rf,
+                                                          const uint8_t* __restrict__ cmask,
+                                                          double* __restrict__ bc)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < cn; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = v % (cx + 1), r = v / (cx + 1), j = r % (cy + 1), k = r / (cy + 1);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int dk = -1; dk <= 1; ++dk) {
+            const int64_t c = 2 * k + dk;
+            if (c < 0 || c > fz) continue;
+            const double wz = dk ? 0.5 : 1.0;
+            for (int dj = -1; dj <= 1; ++dj) {
+                const int64_t bb = 2 * j + dj;
+                if (bb < 0 || bb > fy) continue;
+                const double wy = dj ? wz * 0.5 : wz;
+                for (int di = -1; di <= 1; ++di) {
+                    const int64_t a = 2 * i + di;
+                    if (a < 0 || a > fx) continue;
+                    const double w = di ? wy * 0.5 : wy;
+                    const int64_t node = a + (fx + 1) * (bb + (fy + 1) * c);
+                    for (int f = 0; f < nf; ++f) acc[f] = fma(w, rf[dof_of(node, f, fn, nf, fm)], acc[f]);
+                }
+            }
+        }
+        for (int f = 0; f < nf; ++f) {
+            const int64_t d = dof_of(v, f, cn, nf, fm);
+            bc[d] = (cmask && cmask[d]) ? 0.0 : acc[f];
+        }
+    }
+}
+
+// x = (ADD ? x : 0) + P xc: fine node (a,b,c) interpolates from the coarse nodes
+// (floor(a/2) or a/2 +- 1/2 per axis), weight 1/2 per odd index.
+template <bool ADD>
+__global__ void __launch_bounds__(kThreads) k_mg_prolong(int64_t fx, int64_t fy, int64_t fn, int64_t cx, int64_t cy,
+                                                         int64_t cn, int nf, int fm, const double* __restrict__ xc,
+                                                         double* __restrict__ x)
+{
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < fn; w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = w % (fx + 1), r = w / (fx + 1), bb = r % (fy + 1), c = r / (fy + 1);
+        const int na = (a & 1) ? 2 : 1, nb = (bb & 1) ? 2 : 1, nc = (c & 1) ? 2 : 1;
+        const double wt = ((a & 1) ? 0.5 : 1.0) * ((bb & 1) ? 0.5 : 1.0) * ((c & 1) ? 0.5 : 1.0);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int sc = 0; sc < nc; ++sc) {
+            const int64_t kc = (c >> 1) + sc;
+            for (int sb = 0; sb < nb; ++sb) {
+                const int64_t jc = (bb >> 1) + sb;
+                for (int sa = 0; sa < na; ++sa) {
+                    const int64_t ic = (a >> 1) + sa;
+                    const int64_t node = ic + (cx + 1) * (jc + (cy + 1) * kc);
+                    for (int f = 0; f < nf; ++f) acc[f] = fma(wt, xc[dof_of(node, f, cn, nf, fm)], acc[f]);
+                }
+            }
+        }
+        for (int f = 0; f < nf; ++f) {
+            const int64_t d = dof_of(w, f, fn, nf, fm);
+            x[d] = ADD ? x[d] + acc[f] : acc[f];
+        }
+    }
+}
+
+// The coarsest level: `sweeps` damped Jacobi sweeps from x = 0 in one workgroup, the
+// iterate alternating between two LDS arrays (n <= kCoarseMax), kCoarseLanes lanes per row.
+__global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(int n, const int32_t* __restrict__ rp,
+                                                              const int32_t* __restrict__ ci,
+                                                              const double* __restrict__ A,
+                                                              const double* __restrict__ dinv,
+                                                              const double* __restrict__ b, double* __restrict__ x,
+                                                              double omega, int sweeps)
+{
+    __shared__ double xs[2][kCoarseMax];
+    const int lane = threadIdx.x % kCoarseLanes;
+    const int group = threadIdx.x / kCoarseLanes;
+    constexpr int kGroups = kCoarseThreads / kCoarseLanes;
+    if (sweeps <= 0) {
+        for (int i = threadIdx.x; i < n; i += kCoarseThreads) x[i] = 0.0;
+        return;
+    }
+    for (int i = threadIdx.x; i < n; i += kCoarseThreads) xs[0][i] = omega * dinv[i] * b[i];
+    __syncthreads();
+    int cur = 0;
+    for (int s = 1; s < sweeps; ++s) {
+        const double* xi = xs[cur];
+        double* xo = xs[cur ^ 1];
+        for (int row = group; row < n; row += kGroups) {
+            double acc = 0.0;
+            for (int k = rp[row] + lane; k < rp[row + 1]; k += kCoarseLanes) acc = fma(A[k], xi[ci[k]], acc);
+#pragma unroll
+            for (int off = kCoarseLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kCoarseLanes);
+            if (lane == 0) xo[row] = xi[row] + omega * dinv[row] * (b[row] - acc);
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    for (int i = threadIdx.x; i < n; i += kCoarseThreads) x[i] = xs[cur][i];
+}
+
+unsigned grid_for(int64_t work, int per_block)
+{
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kMaxBlocks, (work + per_block - 1) / per_block));
+}
+
+void launch_sweep(int mode, const mf_mg_s::Level& Lv, int nf, const double* b, const double* in, double* out,
+                  double omega, hipStream_t s)
+{
+    const int64_t n = Lv.n_rows;
+    const int32_t* rp = Lv.Pv->row_ptr;
+    const int32_t* ci = Lv.Pv->col_idx;
+    if (nf >= 4) {
+        const unsigned g = grid_for(n * 8, kThreads);
+        if (mode == kFirst) k_mg_sweep<8, kFirst><<<g, kThreads, 0, s>>>(n, rp, ci, Lv.Kv, Lv.dinv, b, in, out, omega);
+        else if (mode == kSweep) k_mg_sweep<8, kSweep><<<g, kThreads, 0, s>>>(n, rp, ci, Lv.Kv, Lv.dinv, b, in, out, omega);
+        else k_mg_sweep<8, kResidual><<<g, kThreads, 0, s>>>(n, rp, ci, Lv.Kv, Lv.dinv, b, in, out, omega);
+    } else {
+        const unsigned g = grid_for(n * 4, kThreads);
+        if (mode == kFirst) k_mg_sweep<4, kFirst><<<g, kThreads, 0, s>>>(n, rp, ci, Lv.Kv, Lv.dinv, b, in, out, omega);
+        else if (mode == kSweep) k_mg_sweep<4, kSweep><<<g, kThreads, 0, s>>>(n, rp, ci, Lv.Kv, Lv.dinv, b, in, out, omega);
+        else k_mg_sweep<4, kResidual><<<g, kThreads, 0, s>>>(n, rp, ci, Lv.Kv, Lv.dinv, b, in, out, omega);
+    }
+}
+
+// count sweeps; the first from x = 0 when *cur is null.  Buffers alternate: each sweep
+// writes the buffer *cur does not hold.
+void sweeps(const mf_mg_s::Level& Lv, int nf, const double* b, double** cur, double* first_dst, double* other,
+            int count, double omega, hipStream_t s)
+{
+    for (int k = 0; k < count; ++k) {
+        double* dst = *cur == nullptr ? first_dst : (*cur == first_dst ? other : first_dst);
+        launch_sweep(*cur == nullptr ? kFirst : kSweep, Lv, nf, b, *cur, dst, omega, s);
+        *cur = dst;
+    }
+}
+
+// out = V(l, b); out and the level's t are the two sweep buffers.
+void vcycle(const mf_mg_s* mg, int l, const double* b, double* out, hipStream_t s)
+{
+    const mf_mg_s::Level& Lv = mg->L[l];
+    const int nf = mg->nf, fm = mg->fm;
+    const double omega = mg->opts.omega;
+    if (l == mg->n_levels - 1) {
+        const int cs = mg->opts.coarse_sweeps;
+        if (Lv.n_rows <= kCoarseMax) {
+            k_mg_coarse<<<1, kCoarseThreads, 0, s>>>((int)Lv.n_rows, Lv.Pv->row_ptr, Lv.Pv->col_idx, Lv.Kv, Lv.dinv,
+                                                     b, out, omega, cs);
+        } else {
+            double* cur = nullptr;
+            double* first = (cs % 2 == 1) ? out : Lv.t;  // the last of cs sweeps writes out
+            sweeps(Lv, nf, b, &cur, first, first == out ? Lv.t : out, cs, omega, s);
+            if (cs == 0) launch_sweep(kFirst, Lv, nf, b, nullptr, out, 0.0, s);  // x = 0
+        }
+        return;
+    }
+    const mf_mg_s::Level& Lc = mg->L[l + 1];
+    const int pre = mg->opts.pre_sweeps, post = mg->opts.post_sweeps;
+    double* cur = nullptr;
+    // pick the first buffer so that the last write of the cycle on this level lands in out
+    double* first;
+    if (pre > 0) first = ((pre + post) % 2 == 1) ? out : Lv.t;
+    else first = (post % 2 == 0) ? out : Lv.t;
+    double* other = first == out ? Lv.t : out;
+    sweeps(Lv, nf, b, &cur, first, other, pre, omega, s);
+    const double* res = b;  // the residual of x = 0
+    if (cur) {
+        double* rbuf = cur == first ? other : first;
+        launch_sweep(kResidual, Lv, nf, b, cur, rbuf, omega, s);
+        res = rbuf;
+    }
+    k_mg_restrict<<<grid_for(Lc.n_nodes, kThreads), kThreads, 0, s>>>(Lc.nx, Lc.ny, Lc.n_nodes, Lv.nx, Lv.ny, Lv.nz,
+                                                                      Lv.n_nodes, nf, fm, res,
+                                                                      mg->has_mask ? Lc.mask : nullptr, Lc.b);
+    vcycle(mg, l + 1, Lc.b, Lc.x, s);
+    if (cur) {
+        k_mg_prolong<true><<<grid_for(Lv.n_nodes, kThreads), kThreads, 0, s>>>(Lv.nx, Lv.ny, Lv.n_nodes, Lc.nx, Lc.ny,
+                                                                              Lc.n_nodes, nf, fm, Lc.x, cur);
+    } else {
+        cur = first;
+        k_mg_prolong<false><<<grid_for(Lv.n_nodes, kThreads), kThreads, 0, s>>>(Lv.nx, Lv.ny, Lv.n_nodes, Lc.nx,
+                                                                               Lc.ny, Lc.n_nodes, nf, fm, Lc.x, cur);
+    }
+    for (int k = 0; k < post; ++k) {
+        double* dst = cur == first ? other : first;
+        launch_sweep(kSweep, Lv, nf, b, cur, dst, omega, s);
+        cur = dst;
+    }
+}
+
+mf_status mg_apply_cb(void* ctx, const double* r, double* z, hipStream_t s)
+{
+    vcycle((const mf_mg_s*)ctx, 0, r, z, s);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+}  // namespace
+
+mf_status mg_bind_pcg(const mf_mg_t* mg, int64_t n_rows, const double* values, PcgArgs* a)
+{
+    if (!mg->updated) return set_error(MF_ERR_ARG, "call mf_mg_update before the solve");
+    if (n_rows != mg->L[0].n_rows)
+        return set_error(MF_ERR_ARG, "multigrid level 0 has %lld rows, system %lld", (long long)mg->L[0].n_rows,
+                         (long long)n_rows);
+    if (values != mg->L[0].Kv) return set_error(MF_ERR_ARG, "the multigrid cycle was updated for a different matrix");
+    a->precond = MF_PRECOND_EXTERNAL;
+    a->apply = mg_apply_cb;
+    a->apply_ctx = (void*)mg;
+    a->apply_graph_safe = 1;
+    return MF_OK;
+}
+
+}  // namespace mf
+
+using namespace mf;
+
+static void free_mg(mf_mg_s* mg)
+{
+    if (!mg) return;
+    for (int l = 1; l < mg->n_levels; ++l)
+        if (mg->L[l].P) mf_pattern_destroy(mg->L[l].P);
+    for (void* p : mg->owned) (void)hipFree(p);
+    delete mg;
+}
+
+extern "C" mf_status mf_mg_create(const mf_pattern_t* P, const mf_mg_opts* opts, void* stream, mf_mg_t** out)
+{
+    if (!out) return set_error(MF_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!P || !opts) return set_error(MF_ERR_ARG, "pattern or opts is NULL");
+    if (P->dim != 3 || P->nen != 8 || !P->is_grid)
+        return set_error(MF_ERR_UNSUPPORTED, "multigrid needs a structured grid of 8-node hexahedra");
+    if (!P->full_coupling) return set_error(MF_ERR_UNSUPPORTED, "multigrid needs full field coupling");
+    const int max_levels = opts->max_levels == 0 ? MF_MG_MAX_LEVELS : opts->max_levels;
+    if (max_levels < 1 || max_levels > MF_MG_MAX_LEVELS)
+        return set_error(MF_ERR_ARG, "max_levels must be 0..%d", MF_MG_MAX_LEVELS);
+    if (opts->coarse_rows < 0 || opts->pre_sweeps < 0 || opts->post_sweeps < 0 || opts->coarse_sweeps < 0)
+        return set_error(MF_ERR_ARG, "coarse_rows and sweep counts must be >= 0");
+    if (!(opts->omega > 0.0 && opts->omega <= 1.0)) return set_error(MF_ERR_ARG, "omega must be in (0, 1]");
+    for (int l = 0; l < MF_MG_MAX_LEVELS; ++l)
+        if (!(opts->tau_m[l] >= 0.0) || !(opts->tau_c[l] >= 0.0))
+            return set_error(MF_ERR_ARG, "tau_m and tau_c must be >= 0");
+    const int64_t coarse_rows = opts->coarse_rows == 0 ? 512 : opts->coarse_rows;
+    hipStream_t s = (hipStream_t)stream;
+
+    mf_mg_s* mg = new (std::nothrow) mf_mg_s();
+    if (!mg) return set_error(MF_ERR_OOM, "host allocation failed");
+    mg->opts = *opts;
+    mg->nf = P->nf;
+    mg->fm = P->numbering == MF_FIELD_MAJOR ? 1 : 0;
+    auto dalloc = [&](size_t bytes) -> void* {
+        void* p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(bytes, 8)) != hipSuccess) return nullptr;
+        mg->owned.push_back(p);
+        return p;
+    };
+    // level grids
+    int64_t nx = P->gx, ny = P->gy, nz = P->gz;
+    int n = 0;
+    for (;;) {
+        mf_mg_s::Level& Lv = mg->L[n];
+        Lv.nx = nx;
+        Lv.ny = ny;
+        Lv.nz = nz;
+        Lv.n_nodes = (nx + 1) * (ny + 1) * (nz + 1);
+        Lv.n_rows = Lv.n_nodes * P->nf;
+        ++n;
+        const bool even = nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0;
+        if (n >= max_levels || Lv.n_rows <= coarse_rows || !even) break;
+        nx /= 2;
+        ny /= 2;
+        nz /= 2;
+    }
+    mg->n_levels = n;
+    mg->L[0].Pv = P;
+    mf_status st = MF_OK;
+    for (int l = 0; l < n && st == MF_OK; ++l) {
+        mf_mg_s::Level& Lv = mg->L[l];
+        const size_t rows = (size_t)Lv.n_rows, nodes = (size_t)Lv.n_nodes;
+        Lv.dinv = (double*)dalloc(sizeof(double) * rows);
+        Lv.t = (double*)dalloc(sizeof(double) * rows);
+        if (!Lv.dinv || !Lv.t) {
+            st = set_error(MF_ERR_OOM, "multigrid workspace allocation failed");
+            break;
+        }
+        if (l == 0) continue;
+        Lv.x = (double*)dalloc(sizeof(double) * rows);
+        Lv.b = (double*)dalloc(sizeof(double) * rows);
+        Lv.d = (double*)dalloc(sizeof(double) * rows);
+        Lv.coords = (double*)dalloc(sizeof(double) * 3 * nodes);
+        Lv.state = (double*)dalloc(sizeof(double) * 4 * nodes);
+        Lv.mask = (uint8_t*)dalloc(rows);
+        const int64_t n_el = Lv.nx * Lv.ny * Lv.nz;
+        int32_t* conn = nullptr;
+        if (hipMalloc(&conn, sizeof(int32_t) * 8 * (size_t)n_el) != hipSuccess) conn = nullptr;
+        if (!Lv.x || !Lv.b || !Lv.d || !Lv.coords || !Lv.state || !Lv.mask || !conn) {
+            if (conn) (void)hipFree(conn);
+            st = set_error(MF_ERR_OOM, "multigrid workspace allocation failed");
+            break;
+        }
+        k_mg_conn<<<grid_for(8 * n_el, kThreads), kThreads, 0, s>>>(Lv.nx, Lv.ny, n_el, conn);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            (void)hipFree(conn);
+            st = hip_error(e, "k_mg_conn");
+            break;
+        }
+        mf_mesh mesh{3, Lv.n_nodes, n_el, conn};
+        mf_dofs dofs{P->nf, nullptr, P->numbering};
+        st = mf_pattern(&mesh, MF_HEX8, 1, &dofs, stream, &Lv.P);  // synchronises the stream
+        (void)hipFree(conn);
+        if (st != MF_OK) break;
+        if (!Lv.P->is_grid) {
+            st = set_error(MF_ERR_HIP, "multigrid level %d is not recognised as a grid", l);
+            break;
+        }
+        Lv.Pv = Lv.P;
+        Lv.K = (double*)dalloc(sizeof(double) * (size_t)Lv.P->nnz);
+        Lv.Kv = Lv.K;
+        if (!Lv.K) st = set_error(MF_ERR_OOM, "multigrid workspace allocation failed");
+    }
+    if (st == MF_OK) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_error(e, "hipStreamSynchronize");
+    }
+    if (st != MF_OK) {
+        (void)hipStreamSynchronize(s);
+        free_mg(mg);
+        return st;
+    }
+    *out = mg;
+    return MF_OK;
+}
+
+extern "C" mf_status mf_mg_levels(const mf_mg_t* mg, int32_t* n_levels, int64_t* dims)
+{
+    if (!mg) return set_error(MF_ERR_ARG, "mg is NULL");
+    if (n_levels) *n_levels = mg->n_levels;
+    if (dims)
+        for (int l = 0; l < mg->n_levels; ++l) {
+            dims[3 * l] = mg->L[l].nx;
+            dims[3 * l + 1] = mg->L[l].ny;
+            dims[3 * l + 2] = mg->L[l].nz;
+        }
+    return MF_OK;
+}
+
+extern "C" mf_status mf_mg_update(mf_mg_t* mg, const mf_form* form, const double* coords, const mf_fields* fields,
+                                  const mf_quadrature* quad, const double* K, void* stream)
+{
+    if (!mg || !form || !quad) return set_error(MF_ERR_ARG, "mg, form or quad is NULL");
+    if (!coords || !K) return set_error(MF_ERR_ARG, "coords or K is NULL");
+    if (fields && (fields->elem_param || fields->nodal_src))
+        return set_error(MF_ERR_UNSUPPORTED, "multigrid coarse levels take no elem_param or nodal_src");
+    hipStream_t s = (hipStream_t)stream;
+    const double* lin_state = fields ? (const double*)fields->lin_state : nullptr;
+    const uint8_t* dirichlet = fields ? fields->dirichlet : nullptr;
+    mg->updated = false;
+    mg->has_mask = dirichlet != nullptr;
+    mg->L[0].Kv = K;
+    for (int l = 1; l < mg->n_levels; ++l) {
+        mf_mg_s::Level& Lf = mg->L[l - 1];
+        mf_mg_s::Level& Lc = mg->L[l];
+        const double* fc = l == 1 ? coords : Lf.coords;
+        const double* fs = lin_state ? (l == 1 ? lin_state : Lf.state) : nullptr;
+        const uint8_t* fmk = dirichlet ? (l == 1 ? dirichlet : Lf.mask) : nullptr;
+        k_mg_inject<<<grid_for(Lc.n_nodes, kThreads), kThreads, 0, s>>>(Lc.nx, Lc.ny, Lc.n_nodes, Lf.nx, Lf.ny,
+                                                                        Lf.n_nodes, mg->nf, mg->fm, fc, Lc.coords, fs,
+                                                                        Lc.state, fmk, Lc.mask);
+        MF_HIP(hipGetLastError());
+        mf_form fl = *form;
+        if (form->kind == MF_FORM_NS_SUPG) {
+            if (mg->opts.tau_m[l] > 0.0) fl.tau_m = mg->opts.tau_m[l];
+            if (mg->opts.tau_c[l] > 0.0) fl.tau_c = mg->opts.tau_c[l];
+        }
+        mf_fields F{};
+        F.lin_state = lin_state ? Lc.state : nullptr;
+        F.dirichlet = dirichlet ? Lc.mask : nullptr;
+        mf_status st = mf_assemble(Lc.P, &fl, Lc.coords, &F, quad, MF_F64, Lc.K, Lc.d, stream);
+        if (st != MF_OK) return st;
+        int64_t bad = -1;
+        st = mf_status_poll(Lc.P, &bad);
+        if (st != MF_OK) return st;
+    }
+    for (int l = 0; l < mg->n_levels; ++l) {
+        const mf_mg_s::Level& Lv = mg->L[l];
+        k_mg_dinv<<<grid_for(Lv.n_rows, kThreads), kThreads, 0, s>>>(Lv.n_rows, Lv.Pv->row_ptr, Lv.Pv->col_idx, Lv.Kv,
+                                                                     Lv.dinv);
+    }
+    MF_HIP(hipGetLastError());
+    MF_HIP(hipStreamSynchronize(s));
+    mg->updated = true;
+    return MF_OK;
+}
+
+extern "C" mf_status mf_mg_apply(const mf_mg_t* mg, const double* r, double* z, void* stream)
+{
+    if (!mg) return set_error(MF_ERR_ARG, "mg is NULL");
+    if (!mg->updated) return set_error(MF_ERR_ARG, "call mf_mg_update before mf_mg_apply");
+    if (mg->L[0].n_rows > 0 && (!r || !z || r == z)) return set_error(MF_ERR_ARG, "r and z must be distinct vectors");
+    return mg_apply_cb((void*)mg, r, z, (hipStream_t)stream);
+}
+
+extern "C" void mf_mg_destroy(mf_mg_t* mg) { free_mg(mg); }

@@ -2,8 +2,8 @@
 // the tangent K = dR/dU and is repeated until the residual vanishes; form of Sec. 4.3).
 // Each step: mf_assemble in FP64 at the current state (with the Dirichlet elimination,
 // so d = -R is 0 on constrained rows), |d|_2 by fixed-order partial sums, mf_bicgstab
-// (Jacobi) for dU, and the update state += dU mapped from the DOF numbering to the
-// [4][n_nodes] state layout.  The linear solves are inexact: step k asks for a relative
+// (Jacobi, or a multigrid cycle rebuilt for each step's tangent) for dU, and the update
+// state += dU mapped from the DOF numbering to the [4][n_nodes] state layout.  The linear solves are inexact: step k asks for a relative
 // residual eta_k = max(lin_tol, min(0.1, |d_k| / |d_0|)), which tightens with the Newton
 // residual and so keeps the convergence superlinear; a solve that stops short of eta_k
 // (iteration limit or breakdown) but lowers the residual still gives its update.
@@ -74,10 +74,12 @@ extern "C" mf_status mf_ns_newton(const mf_pattern_t* P, const mf_form* form, co
     return mf_ns_newton_ex(P, form, coords, state, dirichlet, nullptr, 0, quad, opts, res, stream);
 }
 
-extern "C" mf_status mf_ns_newton_ex(const mf_pattern_t* P, const mf_form* form, const double* coords,
-                                     double* state, const uint8_t* dirichlet, const mf_bset* bsets, int32_t n_bsets,
-                                     const mf_quadrature* quad, const mf_newton_opts* opts, mf_newton_result* res,
-                                     void* stream)
+// The Newton driver behind mf_ns_newton, mf_ns_newton_ex and mf_ns_newton_mg: with mgo,
+// each step's solve is preconditioned by a multigrid cycle updated for that step's K.
+static mf_status newton_run(const mf_pattern_t* P, const mf_form* form, const double* coords, double* state,
+                            const uint8_t* dirichlet, const mf_bset* bsets, int32_t n_bsets, const mf_mg_opts* mgo,
+                            const mf_quadrature* quad, const mf_newton_opts* opts, mf_newton_result* res,
+                            void* stream)
 {
     if (!P || !form || !quad || !opts || !res) return set_error(MF_ERR_ARG, "NULL pattern, form, quadrature, opts or res");
     if (n_bsets < 0 || (n_bsets > 0 && !bsets)) return set_error(MF_ERR_ARG, "n_bsets < 0 or bsets NULL");
@@ -115,6 +117,15 @@ extern "C" mf_status mf_ns_newton_ex(const mf_pattern_t* P, const mf_form* form,
             for (void* p : *v) (void)hipFree(p);
         }
     } fr{&owned, s};
+    mf_mg_t* mg = nullptr;
+    struct MgFree {
+        mf_mg_t** m;
+        ~MgFree() { mf_mg_destroy(*m); }
+    } mgf{&mg};
+    if (mgo) {
+        mf_status st = mf_mg_create(P, mgo, stream, &mg);
+        if (st != MF_OK) return st;
+    }
     const int nb = (int)std::min<int64_t>(kBlocks, (n + kThreads - 1) / kThreads);
     double* K = (double*)dalloc(sizeof(double) * (size_t)std::max<int64_t>(nnz, 1));
     double* d = (double*)dalloc(sizeof(double) * (size_t)n);
@@ -174,6 +185,15 @@ extern "C" mf_status mf_ns_newton_ex(const mf_pattern_t* P, const mf_form* form,
             return MF_OK;
         }
         if (k == opts->max_steps) break;
+        if (mg) {
+            mf_fields Fm{};
+            Fm.lin_state = state;
+            Fm.dirichlet = dirichlet;
+            st = mf_mg_update(mg, form, coords, &Fm, quad, K, stream);
+            if (st != MF_OK) return st;
+            lo.precond = MF_PRECOND_MG;
+            lo.mg = mg;
+        }
         mf_pcg_result lr{};
         // forcing term: the relative residual reached so far (at most 0.1), but no tighter
         // than half of what the final test still needs (target / |d_k|), so the last
@@ -192,4 +212,21 @@ extern "C" mf_status mf_ns_newton_ex(const mf_pattern_t* P, const mf_form* form,
     }
     return set_error(MF_ERR_NOT_CONVERGED, "Newton reached max_steps = %d (|d| %.3e from %.3e)", opts->max_steps,
                      res->res_norm[opts->max_steps], d0);
+}
+
+extern "C" mf_status mf_ns_newton_ex(const mf_pattern_t* P, const mf_form* form, const double* coords,
+                                     double* state, const uint8_t* dirichlet, const mf_bset* bsets, int32_t n_bsets,
+                                     const mf_quadrature* quad, const mf_newton_opts* opts, mf_newton_result* res,
+                                     void* stream)
+{
+    return newton_run(P, form, coords, state, dirichlet, bsets, n_bsets, nullptr, quad, opts, res, stream);
+}
+
+extern "C" mf_status mf_ns_newton_mg(const mf_pattern_t* P, const mf_form* form, const double* coords,
+                                     double* state, const uint8_t* dirichlet, const mf_mg_opts* mg,
+                                     const mf_quadrature* quad, const mf_newton_opts* opts, mf_newton_result* res,
+                                     void* stream)
+{
+    if (!mg) return set_error(MF_ERR_ARG, "multigrid options are NULL");
+    return newton_run(P, form, coords, state, dirichlet, nullptr, 0, mg, quad, opts, res, stream);
 }

@@ -42,7 +42,8 @@ int64_t pcg_scratch_doubles(int64_t n);
 // Jacobi or no preconditioner); allocates nothing
 mf_status run_pcg_noalloc(const PcgArgs& a, mf_pcg_result* res);
 int64_t pcg_noalloc_max_rows();
-// BiCGStab with Jacobi or no preconditioner (precond MF_PRECOND_JACOBI / MF_PRECOND_NONE)
+// BiCGStab with Jacobi, no or an external preconditioner (precond MF_PRECOND_JACOBI,
+// MF_PRECOND_NONE or MF_PRECOND_EXTERNAL)
 mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res);
 mf_status run_spmv(const mf_csr* A, const double* x, double* y, hipStream_t s);
 

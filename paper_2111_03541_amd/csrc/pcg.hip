@@ -412,8 +412,9 @@ __global__ void k_set(double* p, int n, double v)
 
 // ------------------------------------------------------------------------------------
 // BiCGStab for non-symmetric K (the Newton tangent of the flow form), right-preconditioned
-// by Jacobi (M = diag K), from x0 = 0 with the shadow residual rh = b, all scalars on
-// the device.  One iteration:
+// by Jacobi (M = diag K) or by an external apply (a multigrid cycle, which then overwrites
+// ph and sh), from x0 = 0 with the shadow residual rh = b, all scalars on the device.
+// One iteration:
 //   k_bcg_dir              p = r + beta (p - omega v),  ph = M^-1 p
 //   SpMV                   v = K ph, partials rh.v
 //   k_bcg_alpha (1 block)  alpha = rho / rh.v
@@ -970,6 +971,16 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
     if (!dinv || !r || !rh || !p || !ph || !v || !sh || !t || !xbest || !rv_part || !partial || !sc)
         return set_error(MF_ERR_OOM, "BiCGStab workspace allocation failed");
     const int jac = a.precond == MF_PRECOND_JACOBI ? 1 : 0;
+    // an external preconditioner (multigrid) overwrites ph and sh after the kernels that
+    // form p and s; D^-1 is then the identity
+    const bool ext = a.precond == MF_PRECOND_EXTERNAL;
+    if (ext && !a.apply) return set_error(MF_ERR_ARG, "external preconditioner without an apply function");
+    mf_status apply_status = MF_OK;
+    auto apply = [&](const double* in, double* out) {
+        if (!ext) return;
+        mf_status e = a.apply(a.apply_ctx, in, out, s);
+        if (e != MF_OK && apply_status == MF_OK) apply_status = e;
+    };
 
     // ELL copy of K when the padding stays small (as in run_pcg)
     int width = 0, nnz32 = 0;
@@ -1020,9 +1031,11 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
     // one), so the scalars hold the newest residual norm when a chunk ends
     auto iteration = [&]() {
         k_bcg_dir<<<vec_blocks, kThreads, 0, s>>>(n, sc, r, v, dinv, p, ph);
+        apply(p, ph);
         spmv(ph, v, rh, rv_part);
         k_bcg_alpha<<<1, kThreads, 0, s>>>(rv_part, spmv_blocks, sc);
         k_bcg_s<<<vec_blocks, kThreads, 0, s>>>(n, sc, r, v, dinv, sh);
+        apply(r, sh);
         spmv(sh, t, nullptr, nullptr);
         k_bcg_dots2<<<vec_blocks, kThreads, 0, s>>>(n, t, r, partial);
         k_bcg_omega<<<1, kThreads, 0, s>>>(partial, vec_blocks, sc);
@@ -1033,7 +1046,7 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
     const int chunk = a.check_every > 0 ? a.check_every : 8;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    bool use_graph = a.use_graph != 0;
+    bool use_graph = a.use_graph != 0 && (!ext || a.apply_graph_safe);
     if (use_graph) {
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
             for (int k = 0; k < chunk; ++k) iteration();
@@ -1046,6 +1059,7 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
             use_graph = false;
             (void)hipGetLastError();
         }
+        if (apply_status != MF_OK) return apply_status;
     }
     struct GraphFree {
         hipGraphExec_t* e;
@@ -1098,6 +1112,7 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
             MF_HIP(hipGraphLaunch(exec, s));
         } else {
             for (int k = 0; k < todo; ++k) iteration();
+            if (apply_status != MF_OK) return apply_status;
         }
         MF_HIP(hipGetLastError());
         it += todo;

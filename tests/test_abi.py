@@ -102,7 +102,7 @@ STRUCTS = {  # binding structure -> C type in mf.h
     "_Quad": "mf_quadrature", "_CSR": "mf_csr", "_PcgOpts": "mf_pcg_opts", "_PcgResult": "mf_pcg_result",
     "_TransientOpts": "mf_transient_opts", "_TransientResult": "mf_transient_result", "_BForm": "mf_bform",
     "_BSet": "mf_bset", "_NewtonOpts": "mf_newton_opts", "_NewtonResult": "mf_newton_result",
-    "_BatchProblem": "mf_batch_problem",
+    "_BatchProblem": "mf_batch_problem", "_MgOpts": "mf_mg_opts",
 }
 
 
