@@ -410,8 +410,10 @@ typedef struct {
  * residual every check_every iterations and accepts only a true residual <= tol.
  * Stagnation (opts->stall_iters iterations without progress), or a recurrence residual that
  * meets tol while the true residual does not, restarts the method from the current x:
- * r = b - K x, z = Jacobi r, p = z; an MF_PRECOND_NN solve continues as Jacobi-PCG after
- * its first restart.  At most 8 restarts; res->restarts counts them.
+ * r = b - K x, z = Jacobi r, p = z; an MF_PRECOND_NN or MF_PRECOND_MG solve continues as
+ * Jacobi-PCG after its first restart.  At most 8 restarts; res->restarts counts them.
+ * MF_PRECOND_MG needs opts->mg updated for this K (A->values); the cycle is applied with
+ * the flexible beta, as for the network.
  * Errors: MF_ERR_ARG, MF_ERR_NOT_CONVERGED (maxit reached; x and res hold the last
  * iterate), MF_ERR_NONFINITE (breakdown: p.Kp <= 0 or r.z <= 0), MF_ERR_OOM, MF_ERR_HIP.
  */
@@ -423,7 +425,8 @@ mf_status mf_pcg(const mf_csr* A, const double* b, double* x, const mf_pcg_opts*
  * not call hipMalloc, such as tight serving loops or harnesses that forbid it).  Same
  * arguments, result and synchronisation as mf_pcg, with these limits:
  *   - n_rows <= mf_pcg_noalloc_max_rows() (2^20); larger systems return MF_ERR_ARG;
- *   - opts->precond MF_PRECOND_JACOBI or MF_PRECOND_NONE (MF_PRECOND_NN: MF_ERR_UNSUPPORTED);
+ *   - opts->precond MF_PRECOND_JACOBI or MF_PRECOND_NONE (MF_PRECOND_NN and
+ *     MF_PRECOND_MG: MF_ERR_UNSUPPORTED);
  *   - the SpMV runs on the caller's CSR arrays (no slot-major copy of K) and the
  *     iterations launch eagerly (use_graph is ignored), so the iteration count can
  *     differ from mf_pcg's by rounding, within the same tolerance.
@@ -452,6 +455,7 @@ mf_status mf_spmv(const mf_csr* A, const double* x, double* y, void* stream);
  * when the recurrence residual meets tol but the true residual does not, the method
  * restarts from the current x with rh = r = b - K x (at most 64 restarts).
  * x [n_rows] is overwritten.  (sync)
+ * MF_PRECOND_MG needs opts->mg updated for this K (A->values), else MF_ERR_ARG.
  * Errors: MF_ERR_ARG (including MF_PRECOND_NN), MF_ERR_NOT_CONVERGED (maxit reached; x and
  * res hold the last iterate), MF_ERR_NONFINITE (a non-finite true residual, or breakdown
  * after 64 restarts), MF_ERR_OOM, MF_ERR_HIP.
@@ -464,7 +468,7 @@ mf_status mf_bicgstab(const mf_csr* A, const double* b, double* x, const mf_pcg_
  * with K = dR/dU, repeated until the residual vanishes; form of Sec. 4.3).  Each step
  * assembles K and d = -R(U) in FP64 at the current state with the Dirichlet elimination
  * (d is 0 on constrained rows, so the update keeps their values), solves K dU = d with
- * mf_bicgstab (Jacobi) and adds dU to the state.
+ * mf_bicgstab (Jacobi; mf_ns_newton_mg: a multigrid cycle) and adds dU to the state.
  * ------------------------------------------------------------------------------------ */
 typedef struct {
     double rtol;            /* converged when |d|_2 <= rtol |d_0|_2 ...                     */

@@ -19,7 +19,8 @@
 //   k_mg_restrict  one thread per coarse node gathers its 27 fine neighbours, every field
 //   k_mg_prolong   one thread per fine node interpolates from its 1, 2, 4 or 8 parents
 //   k_mg_coarse    the coarsest level in one workgroup, the iterate in LDS, all sweeps in
-//                  one launch (levels of at most kCoarseMax rows; larger ones use k_mg_sweep)
+//                  one launch, rows cached in registers when there are at most 256 (levels
+//                  of more than kCoarseMax rows use k_mg_sweep)
 // Sweeps alternate between two buffers per level; the first one is chosen so that the last
 // sweep writes the level's output and no copy is needed.
 #include <hip/hip_runtime.h>
@@ -111,16 +112,29 @@ __global__ void __launch_bounds__(kThreads) k_mg_inject(int64_t cx, int64_t cy, 
     }
 }
 
-// dinv[i] = 1 / A_ii, 0 where the diagonal is 0
+// dinv[i] = 1 / A_ii, 0 where the diagonal is 0; kDiagLanes lanes scan a row, and the
+// one that meets column i writes (a row holds its diagonal once)
+constexpr int kDiagLanes = 8;
 __global__ void __launch_bounds__(kThreads) k_mg_dinv(int64_t n, const int32_t* __restrict__ rp,
                                                       const int32_t* __restrict__ ci, const double* __restrict__ A,
                                                       double* __restrict__ dinv)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x % kDiagLanes;
+    const int64_t rows_per_pass = (int64_t)gridDim.x * (kThreads / kDiagLanes);
+    for (int64_t i = (blockIdx.x * (int64_t)kThreads + threadIdx.x) / kDiagLanes; i < n; i += rows_per_pass) {
+        const int k1 = rp[i + 1];
+        bool found = false;
         double di = 0.0;
-        for (int k = rp[i]; k < rp[i + 1]; ++k)
-            if (ci[k] == i) di = A[k];
-        dinv[i] = di != 0.0 ? 1.0 / di : 0.0;
+        for (int k = rp[i] + lane; k < k1; k += kDiagLanes)
+            if (ci[k] == i) {
+                di = A[k];
+                found = true;
+            }
+        const unsigned long long hit = __ballot(found);
+        const int base = (threadIdx.x % 64) / kDiagLanes * kDiagLanes;
+        const unsigned long long mine = (hit >> base) & ((1ull << kDiagLanes) - 1);
+        if (found) dinv[i] = di != 0.0 ? 1.0 / di : 0.0;
+        else if (mine == 0 && lane == 0) dinv[i] = 0.0;
     }
 }
 
@@ -227,6 +241,12 @@ __global__ void __launch_bounds__(kThreads) k_mg_prolong(int64_t fx, int64_t fy,
 
 // The coarsest level: `sweeps` damped Jacobi sweeps from x = 0 in one workgroup, the
 // iterate alternating between two LDS arrays (n <= kCoarseMax), kCoarseLanes lanes per row.
+// CACHED (n <= kCoarseGroups, rows of at most kCoarseLanes * kCoarseCache entries): each
+// row group keeps its row's entries and columns in registers for all sweeps, so a sweep
+// reads only LDS; otherwise the entries are read from memory (L2) every sweep.
+constexpr int kCoarseGroups = kCoarseThreads / kCoarseLanes;
+constexpr int kCoarseCache = 32;
+template <bool CACHED>
 __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(int n, const int32_t* __restrict__ rp,
                                                               const int32_t* __restrict__ ci,
                                                               const double* __restrict__ A,
@@ -237,26 +257,53 @@ __global__ void __launch_bounds__(kCoarseThreads) k_mg_coarse(int n, const int32
     __shared__ double xs[2][kCoarseMax];
     const int lane = threadIdx.x % kCoarseLanes;
     const int group = threadIdx.x / kCoarseLanes;
-    constexpr int kGroups = kCoarseThreads / kCoarseLanes;
     if (sweeps <= 0) {
         for (int i = threadIdx.x; i < n; i += kCoarseThreads) x[i] = 0.0;
         return;
     }
     for (int i = threadIdx.x; i < n; i += kCoarseThreads) xs[0][i] = omega * dinv[i] * b[i];
-    __syncthreads();
     int cur = 0;
-    for (int s = 1; s < sweeps; ++s) {
-        const double* xi = xs[cur];
-        double* xo = xs[cur ^ 1];
-        for (int row = group; row < n; row += kGroups) {
+    if (CACHED) {
+        const int row = group;  // n <= kCoarseGroups: one row per group
+        const bool live = row < n;
+        double a[kCoarseCache];
+        int c[kCoarseCache];
+        const int k0 = live ? rp[row] : 0, k1 = live ? rp[row + 1] : 0;
+#pragma unroll
+        for (int t = 0; t < kCoarseCache; ++t) {
+            const int k = k0 + lane + t * kCoarseLanes;
+            const bool in = k < k1;
+            a[t] = in ? A[k] : 0.0;
+            c[t] = in ? ci[k] : 0;  // a padded slot reads x[0] with weight 0
+        }
+        const double di = live ? omega * dinv[row] : 0.0, bi = live ? b[row] : 0.0;
+        __syncthreads();
+        for (int s = 1; s < sweeps; ++s) {
+            const double* xi = xs[cur];
             double acc = 0.0;
-            for (int k = rp[row] + lane; k < rp[row + 1]; k += kCoarseLanes) acc = fma(A[k], xi[ci[k]], acc);
+#pragma unroll
+            for (int t = 0; t < kCoarseCache; ++t) acc = fma(a[t], xi[c[t]], acc);
 #pragma unroll
             for (int off = kCoarseLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kCoarseLanes);
-            if (lane == 0) xo[row] = xi[row] + omega * dinv[row] * (b[row] - acc);
+            if (live && lane == 0) xs[cur ^ 1][row] = xi[row] + di * (bi - acc);
+            __syncthreads();
+            cur ^= 1;
         }
+    } else {
         __syncthreads();
-        cur ^= 1;
+        for (int s = 1; s < sweeps; ++s) {
+            const double* xi = xs[cur];
+            double* xo = xs[cur ^ 1];
+            for (int row = group; row < n; row += kCoarseGroups) {
+                double acc = 0.0;
+                for (int k = rp[row] + lane; k < rp[row + 1]; k += kCoarseLanes) acc = fma(A[k], xi[ci[k]], acc);
+#pragma unroll
+                for (int off = kCoarseLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kCoarseLanes);
+                if (lane == 0) xo[row] = xi[row] + omega * dinv[row] * (b[row] - acc);
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
     }
     for (int i = threadIdx.x; i < n; i += kCoarseThreads) x[i] = xs[cur][i];
 }
@@ -305,9 +352,14 @@ void vcycle(const mf_mg_s* mg, int l, const double* b, double* out, hipStream_t 
     const double omega = mg->opts.omega;
     if (l == mg->n_levels - 1) {
         const int cs = mg->opts.coarse_sweeps;
-        if (Lv.n_rows <= kCoarseMax) {
-            k_mg_coarse<<<1, kCoarseThreads, 0, s>>>((int)Lv.n_rows, Lv.Pv->row_ptr, Lv.Pv->col_idx, Lv.Kv, Lv.dinv,
-                                                     b, out, omega, cs);
+        // a hexahedral grid row holds at most 27 nodes x 4 fields = 108 <= 128 entries
+        static_assert(27 * 4 <= kCoarseLanes * kCoarseCache, "row cache too small");
+        if (Lv.n_rows <= kCoarseGroups) {
+            k_mg_coarse<true><<<1, kCoarseThreads, 0, s>>>((int)Lv.n_rows, Lv.Pv->row_ptr, Lv.Pv->col_idx, Lv.Kv,
+                                                           Lv.dinv, b, out, omega, cs);
+        } else if (Lv.n_rows <= kCoarseMax) {
+            k_mg_coarse<false><<<1, kCoarseThreads, 0, s>>>((int)Lv.n_rows, Lv.Pv->row_ptr, Lv.Pv->col_idx, Lv.Kv,
+                                                            Lv.dinv, b, out, omega, cs);
         } else {
             double* cur = nullptr;
             double* first = (cs % 2 == 1) ? out : Lv.t;  // the last of cs sweeps writes out

@@ -576,8 +576,9 @@ __global__ void __launch_bounds__(kThreads) k_bcg_init(int n, const int32_t* __r
     double a = 0.0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double di = 0.0;
-        for (int k = rp[i]; k < rp[i + 1]; ++k)
-            if (ci[k] == i) di = v[k];
+        if (jacobi)
+            for (int k = rp[i]; k < rp[i + 1]; ++k)
+                if (ci[k] == i) di = v[k];
         dinv[i] = (jacobi && di != 0.0) ? 1.0 / di : 1.0;
         x[i] = 0.0;
         const double bi = b[i];
