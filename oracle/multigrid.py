@@ -127,7 +127,7 @@ def prolongation(fine_dims, nf, numbering=NODE_MAJOR):
 
 
 def build_levels(fine_dims, coords, nf, kind, params_per_level, n_levels, state=None, dirichlet=None,
-                 numbering=NODE_MAJOR, K0=None, elem_param=None):
+                 numbering=NODE_MAJOR, K0=None):
     """The level hierarchy: a list of dicts with the grid dims, the coarse mesh, the
     pattern, the operator A (scipy CSR), the Dirichlet flags and D^-1.  Level 0's operator
     is K0 when given (the caller's assembled fine matrix), else the oracle's assembly.
@@ -154,8 +154,7 @@ def build_levels(fine_dims, coords, nf, kind, params_per_level, n_levels, state=
         if l == 0 and K0 is not None:
             A = pat.to_scipy(np.asarray(K0, np.float64))
         else:
-            K, _ = assemble(pat, kind, params_per_level[l], state=st, dirichlet=msk,
-                            elem_param=elem_param if l == 0 else None)
+            K, _ = assemble(pat, kind, params_per_level[l], state=st, dirichlet=msk)
             A = pat.to_scipy(K)
         diag = A.diagonal()
         dinv = np.where(diag != 0.0, 1.0 / np.where(diag != 0.0, diag, 1.0), 0.0)
