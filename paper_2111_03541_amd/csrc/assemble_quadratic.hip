@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "mf_internal.h"
 #include "serendipity.h"
@@ -58,7 +59,12 @@ struct Cfg {
     static constexpr int NF = FORM == MF_FORM_ELASTICITY ? DIM : NS ? DIM + 1 : 1;
     static constexpr int NPART = (NS || ET == kTet10) ? 2 : 4;
     static constexpr int ROWS = NEN * NF * NPART;
-    static constexpr int NEED = ROWS > NQ ? ROWS : NQ;
+    // flow form: the momentum row lanes first, then the continuity row lanes from the next
+    // wave on, so that no wave holds both kinds of row (their entries differ)
+    static constexpr int MOM_LANES = NEN * DIM * NPART;
+    static constexpr int CONT0 = (MOM_LANES + 63) / 64 * 64;
+    static constexpr int ROW_LANES = NS ? CONT0 + NEN * NPART : ROWS;
+    static constexpr int NEED = ROW_LANES > NQ ? ROW_LANES : NQ;
     static constexpr int THREADS = (NEED + 63) / 64 * 64;
     static constexpr int NSQ = NS ? 2 * DIM + DIM * DIM + 2 : 1;
     static constexpr int Q_U = 0, Q_GU = DIM, Q_P = DIM + DIM * DIM, Q_RM = Q_P + 1, Q_DIV = Q_RM + DIM;
@@ -174,9 +180,10 @@ struct Q2Shared {
 };
 
 // Flow form, entries of row (a, i) against the columns (b, 0..dim) at one Gauss point
-// (the tangent of the Q1 kernel, Sec. 4.3): i < dim a momentum row, i = dim the continuity
-// row.  F holds u, grad u (gu[i][k] = du_i/dx_k), p, Rm and div u at the point.
-template <int DIM>
+// (the tangent of the Q1 kernel, Sec. 4.3): a momentum row i < dim (CONT false), or the
+// continuity row i = dim (CONT true).  F holds u, grad u (gu[i][k] = du_i/dx_k), p, Rm and
+// div u at the point.
+template <int DIM, bool CONT>
 __device__ __forceinline__ void ns_entries(const mf_form& fm, int i, double Na, const double* ga, double Nb,
                                            const double* gb, const double* F, double (&v)[DIM + 1])
 {
@@ -191,7 +198,7 @@ __device__ __forceinline__ void ns_entries(const mf_form& fm, int i, double Na, 
         advb = fma(u[k], gb[k], advb);
         gg = fma(ga[k], gb[k], gg);
     }
-    if (i < DIM) {
+    if constexpr (!CONT) {
         const double gai = ga[i];
         const double c_nb = (tm * rho * Rm[i] - rho * u[i]) * Nb;  // times g_al
         const double c_diag = -rho * adva * Nb + mu * gg + tm * rho * rho * adva * advb;
@@ -349,10 +356,30 @@ __global__ void __launch_bounds__((Cfg<ET, FORM>::THREADS)) k_assemble_quadratic
         }
     }
     __syncthreads();
-    if (!live || S.bad || lane >= C::ROWS) return;
-
-    const int rowl = lane % (NEN * NF), quarter = lane / (NEN * NF);
-    const int a = rowl / NF, i = rowl % NF;
+    // lane -> (row node a, field i, part of the column nodes)
+    int a = 0, i = 0, quarter = 0;
+    bool active;
+    if constexpr (C::NS) {
+        if (lane < C::MOM_LANES) {
+            quarter = lane / (NEN * DIM);
+            a = lane % (NEN * DIM) / DIM;
+            i = lane % DIM;
+            active = true;
+        } else {
+            const int r = lane - C::CONT0;
+            active = r >= 0 && r < NEN * NPART;
+            quarter = r / NEN;
+            a = r % NEN;
+            i = DIM;
+        }
+    } else {
+        const int rowl = lane % (NEN * NF);
+        quarter = lane / (NEN * NF);
+        a = rowl / NF;
+        i = rowl % NF;
+        active = lane < C::ROWS;
+    }
+    if (!live || S.bad || !active) return;
     const double ep = p.elem_param ? (double)((const T*)p.elem_param)[e] : 1.0;
     const double coef = p.form.coef * ep;
     double lam = 0.0, mu = 0.0;
@@ -374,16 +401,31 @@ __global__ void __launch_bounds__((Cfg<ET, FORM>::THREADS)) k_assemble_quadratic
     for (int bb = 0; bb < NBQ; ++bb)
 #pragma unroll
         for (int j = 0; j < NF; ++j) acc[bb][j] = 0.0;
-    for (int q = 0; q < NQ; ++q) {
+    if constexpr (C::NS) {
+        // i is the same on every lane of the wave: each branch holds its whole loop
+        auto flow_rows = [&](auto cont) {
+            constexpr bool CONT = decltype(cont)::value;
+            for (int q = 0; q < NQ; ++q) {
+                const double W = S.W[q];
+#pragma unroll
+                for (int bb = 0; bb < NBQ; ++bb) {
+                    const int b = b0 + bb;
+                    double v[NF];
+                    ns_entries<DIM, CONT>(p.form, i, S.N[q][a], S.g[q][a], S.N[q][b], S.g[q][b], S.fs[q], v);
+#pragma unroll
+                    for (int j = 0; j < NF; ++j) acc[bb][j] = fma(W, v[j], acc[bb][j]);
+                }
+            }
+        };
+        if (i < DIM) flow_rows(std::false_type{});
+        else flow_rows(std::true_type{});
+    }
+    for (int q = 0; q < (C::NS ? 0 : NQ); ++q) {
         const double W = S.W[q];
 #pragma unroll
         for (int bb = 0; bb < NBQ; ++bb) {
             const int b = b0 + bb;
             if constexpr (C::NS) {
-                double v[NF];
-                ns_entries<DIM>(p.form, i, S.N[q][a], S.g[q][a], S.N[q][b], S.g[q][b], S.fs[q], v);
-#pragma unroll
-                for (int j = 0; j < NF; ++j) acc[bb][j] = fma(W, v[j], acc[bb][j]);
             } else if constexpr (FORM == MF_FORM_MASS) {
                 acc[bb][0] = fma(W * coef * S.N[q][a], S.N[q][b], acc[bb][0]);
             } else {
