@@ -166,16 +166,18 @@ struct Q2Params {
     unsigned long long* status;
 };
 
-template <int ET, int FORM>
+// Geometry and the state at the points are formed in FP64; what the row phase reads (g, N,
+// W, f, fs) is stored in the precision R of the assembly (FP64, or FP32 for MF_F32).
+template <int ET, int FORM, typename R>
 struct Q2Shared {
     using C = Cfg<ET, FORM>;
     double x[C::NEN][C::DIM];
     double src[C::NEN][C::NF];
-    double g[C::NQ][C::NEN][C::DIM];
-    double N[C::NQ][C::NEN];
-    double W[C::NQ];
-    double f[C::NQ][C::NF];
-    double fs[C::NQ][C::NSQ];  // flow form: the state at the Gauss point
+    R g[C::NQ][C::NEN][C::DIM];
+    R N[C::NQ][C::NEN];
+    R W[C::NQ];
+    R f[C::NQ][C::NF];
+    R fs[C::NQ][C::NSQ];  // flow form: the state at the Gauss point
     int bad;
 };
 
@@ -183,15 +185,15 @@ struct Q2Shared {
 // (the tangent of the Q1 kernel, Sec. 4.3): a momentum row i < dim (CONT false), or the
 // continuity row i = dim (CONT true).  F holds u, grad u (gu[i][k] = du_i/dx_k), p, Rm and
 // div u at the point.
-template <int DIM, bool CONT>
-__device__ __forceinline__ void ns_entries(const mf_form& fm, int i, double Na, const double* ga, double Nb,
-                                           const double* gb, const double* F, double (&v)[DIM + 1])
+template <int DIM, bool CONT, typename R>
+__device__ __forceinline__ void ns_entries(const mf_form& fm, int i, R Na, const R* ga, R Nb, const R* gb, const R* F,
+                                           R (&v)[DIM + 1])
 {
-    const double rho = fm.rho, mu = fm.mu, tm = fm.tau_m, tc = fm.tau_c;
-    const double* u = F;
-    const double* gu = F + DIM;
-    const double* Rm = F + DIM + DIM * DIM + 1;  // after p
-    double adva = 0.0, advb = 0.0, gg = 0.0;
+    const R rho = (R)fm.rho, mu = (R)fm.mu, tm = (R)fm.tau_m, tc = (R)fm.tau_c;
+    const R* u = F;
+    const R* gu = F + DIM;
+    const R* Rm = F + DIM + DIM * DIM + 1;  // after p
+    R adva = 0, advb = 0, gg = 0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         adva = fma(u[k], ga[k], adva);
@@ -199,18 +201,18 @@ __device__ __forceinline__ void ns_entries(const mf_form& fm, int i, double Na, 
         gg = fma(ga[k], gb[k], gg);
     }
     if constexpr (!CONT) {
-        const double gai = ga[i];
-        const double c_nb = (tm * rho * Rm[i] - rho * u[i]) * Nb;  // times g_al
-        const double c_diag = -rho * adva * Nb + mu * gg + tm * rho * rho * adva * advb;
-        const double c_gu = tm * rho * rho * adva * Nb;  // times gu[i][l]
+        const R gai = ga[i];
+        const R c_nb = (tm * rho * Rm[i] - rho * u[i]) * Nb;  // times g_al
+        const R c_diag = -rho * adva * Nb + mu * gg + tm * rho * rho * adva * advb;
+        const R c_gu = tm * rho * rho * adva * Nb;  // times gu[i][l]
 #pragma unroll
         for (int l = 0; l < DIM; ++l)
-            v[l] = c_nb * ga[l] + c_gu * gu[i * DIM + l] + tc * gai * gb[l] + (l == i ? c_diag : 0.0);
+            v[l] = c_nb * ga[l] + c_gu * gu[i * DIM + l] + tc * gai * gb[l] + (l == i ? c_diag : R(0));
         v[DIM] = -gai * Nb + tm * rho * adva * gb[i];
     } else {
 #pragma unroll
         for (int l = 0; l < DIM; ++l) {
-            double sl = 0.0;
+            R sl = 0;
 #pragma unroll
             for (int m = 0; m < DIM; ++m) sl = fma(ga[m], gu[m * DIM + l], sl);
             v[l] = Na * gb[l] + tm * rho * (Nb * sl + ga[l] * advb);
@@ -220,18 +222,17 @@ __device__ __forceinline__ void ns_entries(const mf_form& fm, int i, double Na, 
 }
 
 // Flow form, the residual entry R_(a,i) at one Gauss point.
-template <int DIM>
-__device__ __forceinline__ double ns_residual(const mf_form& fm, int i, double Na, const double* ga,
-                                              const double* F)
+template <int DIM, typename R>
+__device__ __forceinline__ R ns_residual(const mf_form& fm, int i, R Na, const R* ga, const R* F)
 {
-    const double rho = fm.rho, mu = fm.mu, tm = fm.tau_m, tc = fm.tau_c;
-    const double* u = F;
-    const double* gu = F + DIM;
-    const double p = F[DIM + DIM * DIM];
-    const double* Rm = F + DIM + DIM * DIM + 1;
-    const double div = F[2 * DIM + DIM * DIM + 1];
+    const R rho = (R)fm.rho, mu = (R)fm.mu, tm = (R)fm.tau_m, tc = (R)fm.tau_c;
+    const R* u = F;
+    const R* gu = F + DIM;
+    const R p = F[DIM + DIM * DIM];
+    const R* Rm = F + DIM + DIM * DIM + 1;
+    const R div = F[2 * DIM + DIM * DIM + 1];
     if (i < DIM) {
-        double adva = 0.0, visc = 0.0;
+        R adva = 0, visc = 0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             adva = fma(u[k], ga[k], adva);
@@ -239,7 +240,7 @@ __device__ __forceinline__ double ns_residual(const mf_form& fm, int i, double N
         }
         return -rho * adva * u[i] - ga[i] * p + mu * visc + tm * rho * adva * Rm[i] + tc * ga[i] * div;
     }
-    double gRm = 0.0;
+    R gRm = 0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) gRm = fma(ga[k], Rm[k], gRm);
     return Na * div + tm * gRm;
@@ -258,7 +259,8 @@ __global__ void __launch_bounds__((Cfg<ET, FORM>::THREADS)) k_assemble_quadratic
     using C = Cfg<ET, FORM>;
     constexpr int DIM = C::DIM, NEN = C::NEN, NQ = C::NQ, NPART = C::NPART, NF = C::NF;
     constexpr int NBQ = NEN / NPART;
-    __shared__ Q2Shared<ET, FORM> S;
+    using R = T;  // precision of the row phase
+    __shared__ Q2Shared<ET, FORM, R> S;
     const int lane = threadIdx.x;
     const int64_t li = blockIdx.x;
     const bool live = li < p.n_list;  // uniform across the workgroup
@@ -302,57 +304,58 @@ __global__ void __launch_bounds__((Cfg<ET, FORM>::THREADS)) k_assemble_quadratic
         double f[NF];
 #pragma unroll
         for (int j = 0; j < NF; ++j) f[j] = 0.0;
+        // flow form: the state's gradients at the point, from the FP64 basis gradients
+        double gu[DIM][DIM], gp[DIM];
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) {
+            gp[m] = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) gu[m][k] = 0.0;
+        }
         for (int b = 0; b < NEN; ++b) {
-            double Nb, dN[DIM];
+            double Nb, dN[DIM], gb[DIM];
             shape<ET>(b, xi, Nb, dN);
 #pragma unroll
             for (int m = 0; m < DIM; ++m) {
                 double gm = 0.0;
 #pragma unroll
                 for (int n = 0; n < DIM; ++n) gm = fma(Ji[n][m], dN[n], gm);
-                S.g[lane][b][m] = gm;
+                gb[m] = gm;
+                S.g[lane][b][m] = (R)gm;
             }
-            S.N[lane][b] = Nb;
+            S.N[lane][b] = (R)Nb;
 #pragma unroll
             for (int j = 0; j < NF; ++j) f[j] = fma(Nb, S.src[b][j], f[j]);
-        }
-        S.W[lane] = w * det;
-#pragma unroll
-        for (int j = 0; j < NF; ++j) S.f[lane][j] = f[j];
-        if constexpr (C::NS) {
-            // the state at the point: f holds (u, p) interpolated; the gradients from g
-            double gu[DIM][DIM], gp[DIM];
-#pragma unroll
-            for (int m = 0; m < DIM; ++m) {
-                gp[m] = 0.0;
-#pragma unroll
-                for (int k = 0; k < DIM; ++k) gu[m][k] = 0.0;
-            }
-            for (int b = 0; b < NEN; ++b) {
+            if constexpr (C::NS) {
 #pragma unroll
                 for (int k = 0; k < DIM; ++k) {
-                    const double gbk = S.g[lane][b][k];
 #pragma unroll
-                    for (int m = 0; m < DIM; ++m) gu[m][k] = fma(gbk, S.src[b][m], gu[m][k]);
-                    gp[k] = fma(gbk, S.src[b][DIM], gp[k]);
+                    for (int m = 0; m < DIM; ++m) gu[m][k] = fma(gb[k], S.src[b][m], gu[m][k]);
+                    gp[k] = fma(gb[k], S.src[b][DIM], gp[k]);
                 }
             }
-            double* F = S.fs[lane];
+        }
+        S.W[lane] = (R)(w * det);
+#pragma unroll
+        for (int j = 0; j < NF; ++j) S.f[lane][j] = (R)f[j];
+        if constexpr (C::NS) {
+            // the state at the point: f holds (u, p) interpolated
+            R* F = S.fs[lane];
             double div = 0.0;
 #pragma unroll
             for (int m = 0; m < DIM; ++m) {
-                F[C::Q_U + m] = f[m];
+                F[C::Q_U + m] = (R)f[m];
                 div += gu[m][m];
                 double c = 0.0;
 #pragma unroll
                 for (int k = 0; k < DIM; ++k) {
-                    F[C::Q_GU + m * DIM + k] = gu[m][k];
+                    F[C::Q_GU + m * DIM + k] = (R)gu[m][k];
                     c = fma(f[k], gu[m][k], c);
                 }
-                F[C::Q_RM + m] = p.form.rho * c + gp[m];
+                F[C::Q_RM + m] = (R)(p.form.rho * c + gp[m]);
             }
-            F[C::Q_P] = f[DIM];
-            F[C::Q_DIV] = div;
+            F[C::Q_P] = (R)f[DIM];
+            F[C::Q_DIV] = (R)div;
         }
     }
     __syncthreads();
@@ -396,22 +399,23 @@ __global__ void __launch_bounds__((Cfg<ET, FORM>::THREADS)) k_assemble_quadratic
     const int b0 = NBQ * quarter;
     // the part's column nodes all at once, Gauss point by Gauss point (the sum over the
     // points of each entry keeps its order)
-    double acc[NBQ][NF];
+    R acc[NBQ][NF];
 #pragma unroll
     for (int bb = 0; bb < NBQ; ++bb)
 #pragma unroll
-        for (int j = 0; j < NF; ++j) acc[bb][j] = 0.0;
+        for (int j = 0; j < NF; ++j) acc[bb][j] = 0;
+    const R coefr = (R)coef, lamr = (R)lam, mur = (R)mu;
     if constexpr (C::NS) {
         // i is the same on every lane of the wave: each branch holds its whole loop
         auto flow_rows = [&](auto cont) {
             constexpr bool CONT = decltype(cont)::value;
             for (int q = 0; q < NQ; ++q) {
-                const double W = S.W[q];
+                const R W = S.W[q];
 #pragma unroll
                 for (int bb = 0; bb < NBQ; ++bb) {
                     const int b = b0 + bb;
-                    double v[NF];
-                    ns_entries<DIM, CONT>(p.form, i, S.N[q][a], S.g[q][a], S.N[q][b], S.g[q][b], S.fs[q], v);
+                    R v[NF];
+                    ns_entries<DIM, CONT, R>(p.form, i, S.N[q][a], S.g[q][a], S.N[q][b], S.g[q][b], S.fs[q], v);
 #pragma unroll
                     for (int j = 0; j < NF; ++j) acc[bb][j] = fma(W, v[j], acc[bb][j]);
                 }
@@ -421,15 +425,15 @@ __global__ void __launch_bounds__((Cfg<ET, FORM>::THREADS)) k_assemble_quadratic
         else flow_rows(std::true_type{});
     }
     for (int q = 0; q < (C::NS ? 0 : NQ); ++q) {
-        const double W = S.W[q];
+        const R W = S.W[q];
 #pragma unroll
         for (int bb = 0; bb < NBQ; ++bb) {
             const int b = b0 + bb;
             if constexpr (C::NS) {
             } else if constexpr (FORM == MF_FORM_MASS) {
-                acc[bb][0] = fma(W * coef * S.N[q][a], S.N[q][b], acc[bb][0]);
+                acc[bb][0] = fma(W * coefr * S.N[q][a], S.N[q][b], acc[bb][0]);
             } else {
-                double ga[DIM], gb[DIM], gg = 0.0;
+                R ga[DIM], gb[DIM], gg = 0;
 #pragma unroll
                 for (int m = 0; m < DIM; ++m) {
                     ga[m] = S.g[q][a][m];
@@ -437,11 +441,11 @@ __global__ void __launch_bounds__((Cfg<ET, FORM>::THREADS)) k_assemble_quadratic
                     gg = fma(ga[m], gb[m], gg);
                 }
                 if constexpr (FORM == MF_FORM_POISSON) {
-                    acc[bb][0] = fma(W * coef, gg, acc[bb][0]);
+                    acc[bb][0] = fma(W * coefr, gg, acc[bb][0]);
                 } else {
 #pragma unroll
                     for (int j = 0; j < NF; ++j)
-                        acc[bb][j] += W * (lam * ga[i] * gb[j] + mu * ga[j] * gb[i] + (i == j ? mu * gg : 0.0));
+                        acc[bb][j] += W * (lamr * ga[i] * gb[j] + mur * ga[j] * gb[i] + (i == j ? mur * gg : R(0)));
                 }
             }
         }
@@ -464,17 +468,17 @@ __global__ void __launch_bounds__((Cfg<ET, FORM>::THREADS)) k_assemble_quadratic
 #pragma unroll
         for (int j = 0; j < NF; ++j) K[pos_of(bb, j)] = old[bb][j] + (T)acc[bb][j];
     if (quarter != 0) return;
-    double dv = 0.0;
+    R dv = 0;
     if constexpr (C::NS) {
-        for (int q = 0; q < NQ; ++q) dv -= S.W[q] * ns_residual<DIM>(p.form, i, S.N[q][a], S.g[q][a], S.fs[q]);
+        for (int q = 0; q < NQ; ++q) dv -= S.W[q] * ns_residual<DIM, R>(p.form, i, S.N[q][a], S.g[q][a], S.fs[q]);
     } else {
-        const double cd = FORM == MF_FORM_MASS ? coef : 1.0;
+        const R cd = FORM == MF_FORM_MASS ? coefr : R(1);
         for (int q = 0; q < NQ; ++q) dv = fma(S.W[q] * cd * S.N[q][a], S.f[q][i], dv);
     }
     ((T*)p.d)[row] += (T)dv;
     // a non-finite element parameter, source, state or form constant shows in the
     // coefficients or in dv
-    double chk = dv + coef + lam + mu;
+    double chk = (double)dv + coef + lam + mu;
     if constexpr (C::NS) chk += p.form.rho + p.form.mu + p.form.tau_m + p.form.tau_c;
     if (!isfinite(chk)) atomicMin(p.status + 2, (unsigned long long)e);
 }
