@@ -985,7 +985,7 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
 
     // ELL copy of K when the padding stays small (as in run_pcg)
     int width = 0, nnz32 = 0;
-    if (!ext) {
+    {
         int* dmax = (int*)dalloc(sizeof(int));
         if (!dmax) return set_error(MF_ERR_OOM, "BiCGStab workspace allocation failed");
         MF_HIP(hipMemsetAsync(dmax, 0, sizeof(int), s));
@@ -996,9 +996,7 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
     }
     int32_t* ecol = nullptr;
     double* eval = nullptr;
-    // (not with an external preconditioner: a multigrid solve takes a few tens of
-    // iterations, and the copy costs about ten SpMVs)
-    if (!ext && width > 0 && (int64_t)width * n <= (int64_t)nnz32 + nnz32 / 2) {
+    if (width > 0 && (int64_t)width * n <= (int64_t)nnz32 + nnz32 / 2) {
         ecol = (int32_t*)dalloc(sizeof(int32_t) * (size_t)width * n);
         eval = (double*)dalloc(sizeof(double) * (size_t)width * n);
         if (ecol && eval) {
