@@ -13,7 +13,13 @@ enough.  What follows is textbook geometric multigrid (Briggs, Henson and McCorm
   the elements per axis of level l, and its node (i, j, k) is the level-l node (2i, 2j, 2k).
 - Coarse operators.  Rediscretisation: the same weak form assembled on the coarse grid.
   Its node coordinates, the linearisation state and the Dirichlet flags are the values at
-  the coincident fine nodes (injection).
+  the coincident fine nodes (injection).  Boundary forms on element faces (Sec. 4.1-4.3)
+  enter every level: a coarse element face is the union of four fine ones, and the fine
+  face (element (ex,ey,ez), local face 2 axis + side) stands for the coarse face of
+  element (ex/2, ey/2, ez/2) with the same local face when its two in-plane indices are
+  even and its index along the axis is even for side 0, odd for side 1; the other fine
+  faces drop out.  Nodal targets are injected.  The operator is the domain form plus the
+  faces, then the Dirichlet elimination (unit row, zero column).
 - Prolongation P.  Trilinear interpolation of the coarse nodal values, the embedding of the
   coarse Q1 space in the fine one, field by field.  A fine node with an even index along an
   axis takes that axis's coarse node; one with an odd index takes the mean of the two
@@ -33,8 +39,9 @@ Pins are in tests/test_oracle_multigrid.py:
 - P reproduces trilinear functions exactly.
 - R^T = P, and full weighting has the textbook weights.
 - On an undistorted grid, P^T A_fine P equals the coarse rediscretisation for mass,
-  conduction and elasticity.  Nested conforming spaces with exact Gauss quadrature fix
-  this (Galerkin identity).
+  conduction and elasticity, also with a penalty boundary form on faces.  Nested
+  conforming spaces with exact Gauss quadrature fix this (Galerkin identity).
+- On a box, the coarsened face list is the coarse box's face list.
 - As a stationary iteration, the V-cycle reduces the error of the Q1 conduction problem
   at a grid-independent rate.
 """
@@ -43,6 +50,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import NODE_MAJOR, Pattern, assemble
+from . import boundary as OB
 
 
 class GridMesh:
@@ -126,21 +134,52 @@ def prolongation(fine_dims, nf, numbering=NODE_MAJOR):
     return P
 
 
+def coarsen_faces(fine_dims, face_elem, face_id):
+    """The coarse faces (element ids, local face ids) that the fine faces stand for
+    (module docstring), in the order of the fine list."""
+    nx, ny, nz = fine_dims
+    e = np.asarray(face_elem, np.int64)
+    f = np.asarray(face_id, np.int64)
+    idx = np.stack([e % nx, (e // nx) % ny, e // (nx * ny)])
+    axis, side = f >> 1, f & 1
+    keep = np.ones(e.shape, bool)
+    for a in range(3):
+        normal = axis == a
+        keep &= np.where(normal, (idx[a] % 2) == side, (idx[a] % 2) == 0)
+    cx, cy = nx // 2, ny // 2
+    ce = idx[0] // 2 + cx * (idx[1] // 2 + cy * (idx[2] // 2))
+    return ce[keep].astype(np.int32), f[keep].astype(np.uint8)
+
+
+def eliminate(A, mask):
+    """Dirichlet elimination of the rows and columns flagged in mask: unit row, zero
+    column."""
+    import scipy.sparse as sp
+    keep = sp.diags((~mask).astype(np.float64))
+    return (keep @ A @ keep + sp.diags(mask.astype(np.float64))).tocsr()
+
+
 def build_levels(fine_dims, coords, nf, kind, params_per_level, n_levels, state=None, dirichlet=None,
-                 numbering=NODE_MAJOR, K0=None):
+                 numbering=NODE_MAJOR, K0=None, face_sets=()):
     """The level hierarchy: a list of dicts with the grid dims, the coarse mesh, the
     pattern, the operator A (scipy CSR), the Dirichlet flags and D^-1.  Level 0's operator
     is K0 when given (the caller's assembled fine matrix), else the oracle's assembly.
-    params_per_level[l]: the form's scalar parameters on level l."""
+    params_per_level[l]: the form's scalar parameters on level l.  face_sets: boundary
+    forms (kind, coef, value, face_elem, face_id, target or None) given on level 0."""
     levels = []
     dims = tuple(int(v) for v in fine_dims)
     crd = np.asarray(coords, np.float64)
     st = None if state is None else np.asarray(state, np.float64)
     msk = None if dirichlet is None else np.asarray(dirichlet, np.uint8)
+    faces = [list(fs) for fs in face_sets]
     for l in range(n_levels):
         if l > 0:
             src = injection(dims)
             nn_f = crd.shape[1]
+            for fs in faces:
+                fs[3], fs[4] = coarsen_faces(dims, fs[3], fs[4])
+                if fs[5] is not None:
+                    fs[5] = np.asarray(fs[5])[:, src]
             dims = (dims[0] // 2, dims[1] // 2, dims[2] // 2)
             crd = crd[:, src]
             if st is not None:
@@ -153,6 +192,14 @@ def build_levels(fine_dims, coords, nf, kind, params_per_level, n_levels, state=
         pat = Pattern(mesh, nf, numbering=numbering)
         if l == 0 and K0 is not None:
             A = pat.to_scipy(np.asarray(K0, np.float64))
+        elif faces:
+            K, _ = assemble(pat, kind, params_per_level[l], state=st)
+            A = pat.to_scipy(K)
+            for bk, coef, value, fe, fi, tg in faces:
+                Kb, _ = OB.assemble_boundary(pat, bk, coef, value, fe, fi, state=st, target=tg)
+                A = A + Kb
+            if msk is not None:
+                A = eliminate(A, msk.astype(bool))
         else:
             K, _ = assemble(pat, kind, params_per_level[l], state=st, dirichlet=msk)
             A = pat.to_scipy(K)

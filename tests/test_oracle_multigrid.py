@@ -11,7 +11,10 @@ the paper).
     elasticity exactly, so P^T A_fine P is the coarse rediscretisation;
   * the V-cycle as a stationary iteration on Q1 conduction with Dirichlet walls reduces the
     error by a grid-independent factor well below 1;
-  * the cycle is a linear map (fixed sweeps, zero initial guesses).
+  * the cycle is a linear map (fixed sweeps, zero initial guesses);
+  * face coarsening: on a box the coarsened face list is the coarse box's own, and with a
+    penalty (face mass) form on part of the boundary the Galerkin identity still holds;
+  * the elimination leaves unit rows and zero columns.
 """
 import numpy as np
 import pytest
@@ -117,3 +120,49 @@ def test_vcycle_is_linear_on_the_flow_tangent():
     za, zb = MG.vcycle(levels, a), MG.vcycle(levels, b)
     z = MG.vcycle(levels, 2.0 * a - 3.0 * b)
     np.testing.assert_allclose(z, 2.0 * za - 3.0 * zb, rtol=0, atol=1e-11 * np.abs(z).max())
+
+
+def test_coarsened_box_faces_are_the_coarse_box_faces():
+    for dims, sides in (((4, 6, 2), None), ((8, 4, 4), [0, 3, 5])):
+        fe, fi = W.box_faces(dims, sides=sides)
+        ce, cf = MG.coarsen_faces(dims, fe, fi)
+        re_, rf = W.box_faces(tuple(v // 2 for v in dims), sides=sides)
+        assert sorted(zip(ce.tolist(), cf.tolist())) == sorted(zip(re_.tolist(), rf.tolist()))
+    # an interior face (side 1 of element (1, 0, 0)) stands for the coarse element 0's side 1
+    ce, cf = MG.coarsen_faces((4, 2, 2), np.array([1, 0]), np.array([1, 1]))
+    assert ce.tolist() == [0] and cf.tolist() == [1]
+
+
+@pytest.mark.parametrize("numbering", [O.NODE_MAJOR, O.FIELD_MAJOR])
+def test_galerkin_identity_with_a_penalty_boundary_form(numbering):
+    import oracle.boundary as OB
+    dims = (4, 6, 4)
+    mesh = W.structured_mesh(dims, lengths=(2.0, 1.0, 0.5))
+    fe, fi = W.box_faces(dims, sides=[0, 3, 5])
+    tg = W.uniform_nodal(3, mesh.n_nodes, -1, 1, 2)
+    sets = [(OB.PENALTY, 7.0, [0.0, 0.0, 0.0], fe, fi, tg)]
+    prm = dict(coef=1.0, nu=0.3)
+    levels = MG.build_levels(dims, mesh.coords, 3, O.ELASTICITY, [prm, prm], 2, numbering=numbering,
+                             face_sets=sets)
+    Af, Ac, P = levels[0]["A"], levels[1]["A"], levels[0]["P"]
+    G = (P.T @ Af @ P).toarray()
+    ref = Ac.toarray()
+    assert np.abs(G - ref).max() <= 1e-12 * np.abs(ref).max()
+    # the faces changed the operator (a penalty adds to the face rows)
+    plain = MG.build_levels(dims, mesh.coords, 3, O.ELASTICITY, [prm, prm], 2, numbering=numbering)
+    assert np.abs(plain[1]["A"].toarray() - ref).max() > 1.0
+
+
+def test_elimination_gives_unit_rows_and_zero_columns():
+    import scipy.sparse as sp
+    rng = np.random.default_rng(3)
+    A = sp.csr_matrix(rng.standard_normal((6, 6)))
+    mask = np.array([0, 1, 0, 0, 1, 0], bool)
+    E = MG.eliminate(A, mask).toarray()
+    Ad = A.toarray()
+    for r in range(6):
+        for c in range(6):
+            if mask[r] or mask[c]:
+                assert E[r, c] == (1.0 if r == c else 0.0)
+            else:
+                assert E[r, c] == Ad[r, c]
