@@ -322,7 +322,9 @@ def bench_newton_mg(dev, sizes=(24, 32, 48)):
 def bench_newton_weak(dev, n=32):
     """The lid-driven cavity of bench_newton with every wall a weak boundary form (Sec.
     4.3): the lid as inflow with u^w = (1, 0, 0), the other faces as fix, tau^b = 10, one
-    pressure DOF pinned; Newton through mf_ns_newton_ex to |R| / |R_0| < 1e-10."""
+    pressure DOF pinned; Newton to |R| / |R_0| < 1e-10 with Jacobi-BiCGStab
+    (mf_ns_newton_ex) and with the multigrid-preconditioned BiCGStab, the face sets on every
+    level (mf_ns_newton_mg)."""
     import torch
     import workloads as W
     import paper_2111_03541_amd as mf
@@ -337,17 +339,20 @@ def bench_newton_weak(dev, n=32):
             (mf.BFORM_NS_FIX, W.box_faces((n, n, n), sides=[0, 1, 2, 3, 4]), [0.0, 0.0, 0.0, 1.0, 0.01])]
     bnd = [(k, torch.from_numpy(fe).to(dev), torch.from_numpy(fi).to(dev), 10.0, v, None) for k, (fe, fi), v in sets]
     dm = torch.from_numpy(mask).to(dev)
-    st = torch.zeros((4, mesh.n_nodes), dtype=torch.float64, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = mf.ns_newton(pat, form, coords, st, dirichlet=dm, rtol=1e-10, boundary=bnd)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3
-    log(f"[bench] Newton weak-boundary cavity {n}^3: {res['steps']} steps, {res['lin_iterations']} BiCGStab "
-        f"iterations, {ms:.1f} ms")
-    return {"n": n, "n_dofs": pat.n_rows, "n_faces": int(sum(int(b[1].shape[0]) for b in bnd)), "steps": res["steps"],
-            "converged": res["converged"], "lin_iterations": res["lin_iterations"], "ms": ms,
-            "res_norm": res["res_norm"]}
+    lv = [ns_taus(n / 2 ** l) for l in range(8)]
+    out = {"n": n, "n_dofs": pat.n_rows, "n_faces": int(sum(int(b[1].shape[0]) for b in bnd))}
+    for key, mgo in (("jacobi", None), ("multigrid", dict(tau_m=[t[0] for t in lv], tau_c=[t[1] for t in lv]))):
+        st = torch.zeros((4, mesh.n_nodes), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = mf.ns_newton(pat, form, coords, st, dirichlet=dm, rtol=1e-10, boundary=bnd, multigrid=mgo)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        log(f"[bench] Newton weak-boundary cavity {n}^3, {key}: {res['steps']} steps, {res['lin_iterations']} "
+            f"BiCGStab iterations, {ms:.1f} ms")
+        out[key] = {"steps": res["steps"], "converged": res["converged"], "lin_iterations": res["lin_iterations"],
+                    "ms": ms, "res_norm": res["res_norm"]}
+    return out
 
 
 def bench_boundary(dev, mesh, pat, coords, K, d, cpu=True, steps=10, warmup=3):

@@ -580,6 +580,17 @@ mf_status mf_mg_levels(const mf_mg_t* mg, int32_t* n_levels, int64_t* dims);
 mf_status mf_mg_update(mf_mg_t* mg, const mf_form* form, const double* coords, const mf_fields* fields,
                        const mf_quadrature* quad, const double* K, void* stream);
 
+/* mf_mg_update with boundary forms on element faces (mf_bset, above; Sec. 4.1-4.3): K
+   is the domain form plus the n_bsets face sets, then the Dirichlet elimination, and each
+   coarse operator is built the same way.  A coarse face stands for four fine ones: the
+   fine face (element (ex,ey,ez), local face 2 axis + side) is kept, as the coarse face of
+   element (ex/2, ey/2, ez/2), when its in-plane indices are even and its index along the
+   axis is even for side 0, odd for side 1; nodal targets are injected.  (sync)  Errors:
+   those of mf_mg_update and mf_assemble_boundary. */
+mf_status mf_mg_update_ex(mf_mg_t* mg, const mf_form* form, const double* coords, const mf_fields* fields,
+                          const mf_bset* bsets, int32_t n_bsets, const mf_quadrature* quad, const double* K,
+                          void* stream);
+
 /* z = V(0, r): one cycle, r and z [n_rows] device FP64 (distinct).  Kernels only, on the
    stream (async, no allocation, no memset: can be captured in a HIP graph).  Calls that
    overlap on one mf_mg_t race (they share its level vectors).  Errors: MF_ERR_ARG (not
@@ -589,14 +600,17 @@ mf_status mf_mg_apply(const mf_mg_t* mg, const double* r, double* z, void* strea
 void mf_mg_destroy(mf_mg_t* mg);
 
 /*
- * mf_ns_newton_mg - mf_ns_newton with the multigrid preconditioner in every linear solve:
- * each step assembles K and d, updates the cycle for that K (mf_mg_update with the current
- * state) and solves with mf_bicgstab (MF_PRECOND_MG).  P must be a structured grid as for
- * mf_mg_create.  (sync)  Errors: those of mf_ns_newton, mf_mg_create and mf_mg_update.
+ * mf_ns_newton_mg - mf_ns_newton_ex with the multigrid preconditioner in every linear
+ * solve: each step assembles K and d (with the n_bsets face sets, as mf_ns_newton_ex),
+ * updates the cycle for that K (mf_mg_update_ex with the current state and the same face
+ * sets) and solves with mf_bicgstab (MF_PRECOND_MG).  P must be a structured grid as for
+ * mf_mg_create.  (sync)  Errors: those of mf_ns_newton_ex, mf_mg_create and
+ * mf_mg_update_ex.
  */
 mf_status mf_ns_newton_mg(const mf_pattern_t* P, const mf_form* form, const double* coords, double* state,
-                          const uint8_t* dirichlet, const mf_mg_opts* mg, const mf_quadrature* quad,
-                          const mf_newton_opts* opts, mf_newton_result* res, void* stream);
+                          const uint8_t* dirichlet, const mf_bset* bsets, int32_t n_bsets, const mf_mg_opts* mg,
+                          const mf_quadrature* quad, const mf_newton_opts* opts, mf_newton_result* res,
+                          void* stream);
 
 /* ------------------------------------------------------------------------------------
  * Learned preconditioner for mf_pcg on structured-grid scalar systems (node id

@@ -137,7 +137,7 @@ EXPORTS = [
     "mf_bicgstab", "mf_ns_newton", "mf_ns_newton_ex", "mf_assemble_boundary", "mf_heat_transient",
     "mf_pcg_noalloc", "mf_pcg_noalloc_max_rows", "mf_nn_checkpoint_size", "mf_nn_save", "mf_nn_load",
     "mf_batch_tiles", "mf_mg_create", "mf_mg_levels", "mf_mg_update", "mf_mg_apply", "mf_mg_destroy",
-    "mf_ns_newton_mg",
+    "mf_ns_newton_mg", "mf_mg_update_ex",
 ]
 
 
@@ -200,8 +200,10 @@ def load():
     lib.mf_mg_apply.argtypes = [P, P, P, P]
     lib.mf_mg_destroy.argtypes = [P]
     lib.mf_mg_destroy.restype = None
-    lib.mf_ns_newton_mg.argtypes = [P, C.POINTER(_Form), P, P, P, C.POINTER(_MgOpts), C.POINTER(_Quad),
-                                    C.POINTER(_NewtonOpts), C.POINTER(_NewtonResult), P]
+    lib.mf_mg_update_ex.argtypes = [P, C.POINTER(_Form), P, C.POINTER(_Fields), C.POINTER(_BSet), C.c_int32,
+                                    C.POINTER(_Quad), P, P]
+    lib.mf_ns_newton_mg.argtypes = [P, C.POINTER(_Form), P, P, P, C.POINTER(_BSet), C.c_int32, C.POINTER(_MgOpts),
+                                    C.POINTER(_Quad), C.POINTER(_NewtonOpts), C.POINTER(_NewtonResult), P]
     lib.mf_last_error.restype = C.c_char_p
     lib.mf_version.restype = C.c_char_p
     _lib = lib
@@ -589,8 +591,9 @@ class Multigrid:
         check(load().mf_mg_levels(self.handle, C.byref(n), dims))
         return [tuple(dims[3 * l:3 * l + 3]) for l in range(n.value)]
 
-    def update(self, form, coords, K, lin_state=None, dirichlet=None, points_per_axis=2, stream=None):
-        """Assemble the coarse levels for the level-0 operator K (kept referenced)."""
+    def update(self, form, coords, K, lin_state=None, dirichlet=None, points_per_axis=2, stream=None, boundary=()):
+        """Assemble the coarse levels for the level-0 operator K (kept referenced);
+        boundary: face sets as for ns_newton, in K and on every level."""
         import torch
         p = self.pattern
         _require(coords, "coords", torch.float64, p.dim * p.n_nodes, optional=False)
@@ -599,9 +602,11 @@ class Multigrid:
         _require(dirichlet, "dirichlet", torch.uint8, p.n_rows)
         F = _Fields(None, None, _ptr(lin_state), _ptr(dirichlet))
         q = _Quad(points_per_axis)
-        check(load().mf_mg_update(self.handle, C.byref(form.c), _ptr(coords), C.byref(F), C.byref(q), _ptr(K),
-                                  _stream(stream)))
+        sets = _bsets(boundary, p)
+        check(load().mf_mg_update_ex(self.handle, C.byref(form.c), _ptr(coords), C.byref(F), sets, len(boundary),
+                                     C.byref(q), _ptr(K), _stream(stream)))
         self._K = K
+        self._keep = boundary
 
     def apply(self, r, z=None, stream=None):
         """z = V(0, r), one cycle on the stream."""
@@ -691,6 +696,21 @@ def bicgstab(row_ptr, col_idx, values, b, x=None, tol=1e-8, maxit=20000, precond
     return x, out
 
 
+def _bsets(boundary, pattern):
+    """Face sets (kind, face_elem int32 cuda, face_id uint8 cuda, coef, value, target or None)
+    as an mf_bset array."""
+    import torch
+    sets = (_BSet * max(1, len(boundary)))()
+    for k, (kind, fe, fi, coef, value, target) in enumerate(boundary):
+        _require(fe, "face_elem", torch.int32, optional=False)
+        _require(fi, "face_id", torch.uint8, int(fe.shape[0]), optional=False)
+        _require(target, "target", torch.float64, pattern.n_fields * pattern.n_nodes)
+        vals = list(value) + [0.0] * (9 - len(value))
+        sets[k] = _BSet(_BForm(kind, coef, (C.c_double * 9)(*vals)), int(fe.shape[0]), _ptr(fe), _ptr(fi),
+                        _ptr(target))
+    return sets
+
+
 def ns_newton(pattern, form, coords, state, dirichlet=None, rtol=1e-10, atol=0.0, max_steps=20, lin_tol=1e-10,
               lin_maxit=20000, check_every=8, use_graph=True, points_per_axis=2, stream=None, raise_on_fail=True,
               boundary=(), multigrid=None):
@@ -698,8 +718,8 @@ def ns_newton(pattern, form, coords, state, dirichlet=None, rtol=1e-10, atol=0.0
     in place.  boundary: face sets (kind, face_elem int32 cuda, face_id uint8 cuda, coef,
     value, target or None) whose boundary forms enter every step before the Dirichlet
     elimination.  multigrid: None (Jacobi-preconditioned solves) or a dict of mg_opts
-    arguments (mf_ns_newton_mg; no boundary face sets).  Returns the result dict (steps,
-    converged, lin_iterations, res_norm)."""
+    arguments (mf_ns_newton_mg, the face sets on every level).  Returns the result dict
+    (steps, converged, lin_iterations, res_norm)."""
     import torch
     lib = load()
     _require(state, "state", torch.float64, 4 * pattern.n_nodes, optional=False)
@@ -708,20 +728,12 @@ def ns_newton(pattern, form, coords, state, dirichlet=None, rtol=1e-10, atol=0.0
     opts = _NewtonOpts(rtol, atol, max_steps, lin_tol, lin_maxit, check_every, int(bool(use_graph)))
     res = _NewtonResult()
     q = _Quad(points_per_axis)
-    sets = (_BSet * max(1, len(boundary)))()
-    for k, (kind, fe, fi, coef, value, target) in enumerate(boundary):
-        _require(fe, "face_elem", torch.int32, optional=False)
-        _require(fi, "face_id", torch.uint8, int(fe.shape[0]), optional=False)
-        _require(target, "target", torch.float64, 4 * pattern.n_nodes)
-        vals = list(value) + [0.0] * (9 - len(value))
-        sets[k] = _BSet(_BForm(kind, coef, (C.c_double * 9)(*vals)), int(fe.shape[0]), _ptr(fe), _ptr(fi),
-                        _ptr(target))
+    sets = _bsets(boundary, pattern)
     if multigrid is not None:
-        if boundary:
-            raise ValueError("the multigrid Newton takes no boundary face sets")
         mo = mg_opts(**multigrid)
-        st = lib.mf_ns_newton_mg(pattern.handle, C.byref(form.c), _ptr(coords), _ptr(state), _ptr(dirichlet),
-                                 C.byref(mo), C.byref(q), C.byref(opts), C.byref(res), _stream(stream))
+        st = lib.mf_ns_newton_mg(pattern.handle, C.byref(form.c), _ptr(coords), _ptr(state), _ptr(dirichlet), sets,
+                                 len(boundary), C.byref(mo), C.byref(q), C.byref(opts), C.byref(res),
+                                 _stream(stream))
     else:
         st = lib.mf_ns_newton_ex(pattern.handle, C.byref(form.c), _ptr(coords), _ptr(state), _ptr(dirichlet), sets,
                                  len(boundary), C.byref(q), C.byref(opts), C.byref(res), _stream(stream))

@@ -112,6 +112,52 @@ __global__ void __launch_bounds__(kThreads) k_mg_inject(int64_t cx, int64_t cy, 
     }
 }
 
+// rows x n_nodes nodal values (a boundary form's target) injected like the state
+__global__ void __launch_bounds__(kThreads) k_mg_inject_nodal(int64_t cx, int64_t cy, int64_t cn, int64_t fx,
+                                                              int64_t fy, int64_t fn, int rows,
+                                                              const double* __restrict__ f, double* __restrict__ c)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < cn; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = v % (cx + 1), r = v / (cx + 1), j = r % (cy + 1), k = r / (cy + 1);
+        const int64_t w = 2 * i + (fx + 1) * (2 * j + (fy + 1) * (2 * k));
+        for (int q = 0; q < rows; ++q) c[q * cn + v] = f[q * fn + w];
+    }
+}
+
+// Boundary faces of the next level: the fine face (element (ex,ey,ez), local face
+// 2 axis + side) stands for the coarse face of element (ex/2, ey/2, ez/2) with the same
+// local face when its two in-plane indices are even and its index along the axis is even
+// for side 0, odd for side 1 (so each coarse face keeps exactly one of its four fine
+// faces); other faces, and faces out of range (reported by the fine level's assembly),
+// drop out.  The kept faces are appended through *count, in no fixed order: the face
+// scatter adds an element's faces in a fixed order whatever the list order.
+__global__ void __launch_bounds__(kThreads) k_mg_faces(int64_t n, const int32_t* __restrict__ fe,
+                                                       const uint8_t* __restrict__ fi, int64_t nx, int64_t ny,
+                                                       int64_t nz, int* __restrict__ count, int32_t* __restrict__ ce,
+                                                       uint8_t* __restrict__ cf)
+{
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < n; f += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = fe[f];
+        const int lf = fi[f];
+        if (e < 0 || e >= nx * ny * nz || lf > 5) continue;
+        const int64_t idx[3] = {e % nx, (e / nx) % ny, e / (nx * ny)};
+        const int axis = lf >> 1, side = lf & 1;
+        bool keep = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) keep = keep && (idx[a] & 1) == (a == axis ? side : 0);
+        if (keep) {
+            const int slot = atomicAdd(count, 1);
+            ce[slot] = (int32_t)(idx[0] / 2 + (nx / 2) * (idx[1] / 2 + (ny / 2) * (idx[2] / 2)));
+            cf[slot] = (uint8_t)lf;
+        }
+    }
+}
+
+__global__ void k_mg_zero_int(int* p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 // dinv[i] = 1 / A_ii, 0 where the diagonal is 0; kDiagLanes lanes scan a row, and the
 // one that meets column i writes (a row holds its diagonal once)
 constexpr int kDiagLanes = 8;
@@ -560,19 +606,54 @@ extern "C" mf_status mf_mg_levels(const mf_mg_t* mg, int32_t* n_levels, int64_t*
     return MF_OK;
 }
 
-extern "C" mf_status mf_mg_update(mf_mg_t* mg, const mf_form* form, const double* coords, const mf_fields* fields,
-                                  const mf_quadrature* quad, const double* K, void* stream)
+extern "C" mf_status mf_mg_update_ex(mf_mg_t* mg, const mf_form* form, const double* coords,
+                                     const mf_fields* fields, const mf_bset* bsets, int32_t n_bsets,
+                                     const mf_quadrature* quad, const double* K, void* stream)
 {
     if (!mg || !form || !quad) return set_error(MF_ERR_ARG, "mg, form or quad is NULL");
     if (!coords || !K) return set_error(MF_ERR_ARG, "coords or K is NULL");
     if (fields && (fields->elem_param || fields->nodal_src))
         return set_error(MF_ERR_UNSUPPORTED, "multigrid coarse levels take no elem_param or nodal_src");
+    if (n_bsets < 0 || (n_bsets > 0 && !bsets)) return set_error(MF_ERR_ARG, "n_bsets < 0 or bsets NULL");
+    for (int b = 0; b < n_bsets; ++b)
+        if (bsets[b].n_faces < 0 || (bsets[b].n_faces > 0 && (!bsets[b].face_elem || !bsets[b].face_id)))
+            return set_error(MF_ERR_ARG, "face set %d: n_faces < 0 or NULL face arrays", b);
     hipStream_t s = (hipStream_t)stream;
     const double* lin_state = fields ? (const double*)fields->lin_state : nullptr;
     const uint8_t* dirichlet = fields ? fields->dirichlet : nullptr;
     mg->updated = false;
     mg->has_mask = dirichlet != nullptr;
     mg->L[0].Kv = K;
+
+    // the coarse face lists and targets live only for this call
+    std::vector<void*> tmp;
+    struct Free {
+        std::vector<void*>* v;
+        hipStream_t s;
+        ~Free() {
+            (void)hipStreamSynchronize(s);
+            for (void* p : *v) (void)hipFree(p);
+        }
+    } fr{&tmp, s};
+    auto talloc = [&](size_t bytes) -> void* {
+        void* p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(bytes, 8)) != hipSuccess) return nullptr;
+        tmp.push_back(p);
+        return p;
+    };
+    std::vector<const int32_t*> fe(n_bsets);
+    std::vector<const uint8_t*> fi(n_bsets);
+    std::vector<int64_t> nfc(n_bsets);
+    std::vector<const double*> tg(n_bsets);
+    for (int b = 0; b < n_bsets; ++b) {
+        fe[b] = bsets[b].face_elem;
+        fi[b] = bsets[b].face_id;
+        nfc[b] = bsets[b].n_faces;
+        tg[b] = bsets[b].target;
+    }
+    int* counter = n_bsets > 0 ? (int*)talloc(sizeof(int) * n_bsets) : nullptr;
+    if (n_bsets > 0 && !counter) return set_error(MF_ERR_OOM, "multigrid face workspace allocation failed");
+
     for (int l = 1; l < mg->n_levels; ++l) {
         mf_mg_s::Level& Lf = mg->L[l - 1];
         mf_mg_s::Level& Lc = mg->L[l];
@@ -583,6 +664,35 @@ extern "C" mf_status mf_mg_update(mf_mg_t* mg, const mf_form* form, const double
                                                                         Lf.n_nodes, mg->nf, mg->fm, fc, Lc.coords, fs,
                                                                         Lc.state, fmk, Lc.mask);
         MF_HIP(hipGetLastError());
+        if (n_bsets > 0) {
+            k_mg_zero_int<<<1, 64, 0, s>>>(counter, n_bsets);
+            std::vector<int32_t*> ce(n_bsets, nullptr);
+            std::vector<uint8_t*> cf(n_bsets, nullptr);
+            for (int b = 0; b < n_bsets; ++b) {
+                if (tg[b]) {
+                    double* t = (double*)talloc(sizeof(double) * mg->nf * (size_t)Lc.n_nodes);
+                    if (!t) return set_error(MF_ERR_OOM, "multigrid face workspace allocation failed");
+                    k_mg_inject_nodal<<<grid_for(Lc.n_nodes, kThreads), kThreads, 0, s>>>(
+                        Lc.nx, Lc.ny, Lc.n_nodes, Lf.nx, Lf.ny, Lf.n_nodes, mg->nf, tg[b], t);
+                    tg[b] = t;
+                }
+                if (nfc[b] == 0) continue;
+                ce[b] = (int32_t*)talloc(sizeof(int32_t) * (size_t)nfc[b]);
+                cf[b] = (uint8_t*)talloc((size_t)nfc[b]);
+                if (!ce[b] || !cf[b]) return set_error(MF_ERR_OOM, "multigrid face workspace allocation failed");
+                k_mg_faces<<<grid_for(nfc[b], kThreads), kThreads, 0, s>>>(nfc[b], fe[b], fi[b], Lf.nx, Lf.ny,
+                                                                           Lf.nz, counter + b, ce[b], cf[b]);
+            }
+            MF_HIP(hipGetLastError());
+            std::vector<int> cnt(n_bsets, 0);
+            MF_HIP(hipMemcpyAsync(cnt.data(), counter, sizeof(int) * n_bsets, hipMemcpyDeviceToHost, s));
+            MF_HIP(hipStreamSynchronize(s));
+            for (int b = 0; b < n_bsets; ++b) {
+                nfc[b] = cnt[b];
+                fe[b] = ce[b];
+                fi[b] = cf[b];
+            }
+        }
         mf_form fl = *form;
         if (form->kind == MF_FORM_NS_SUPG) {
             if (mg->opts.tau_m[l] > 0.0) fl.tau_m = mg->opts.tau_m[l];
@@ -590,9 +700,26 @@ extern "C" mf_status mf_mg_update(mf_mg_t* mg, const mf_form* form, const double
         }
         mf_fields F{};
         F.lin_state = lin_state ? Lc.state : nullptr;
-        F.dirichlet = dirichlet ? Lc.mask : nullptr;
+        // with face sets the elimination comes after the faces are added
+        F.dirichlet = (dirichlet && n_bsets == 0) ? Lc.mask : nullptr;
         mf_status st = mf_assemble(Lc.P, &fl, Lc.coords, &F, quad, MF_F64, Lc.K, Lc.d, stream);
         if (st != MF_OK) return st;
+        for (int b = 0; b < n_bsets; ++b) {
+            st = mf_assemble_boundary(Lc.P, &bsets[b].form, Lc.coords, nfc[b], fe[b], fi[b],
+                                      lin_state ? Lc.state : nullptr, tg[b], MF_F64, Lc.K, Lc.d, stream);
+            if (st != MF_OK) return st;
+        }
+        if (n_bsets > 0 && dirichlet) {
+            AssembleArgs elim{};
+            elim.P = Lc.P;
+            elim.dirichlet = Lc.mask;
+            elim.prec = MF_F64;
+            elim.K = Lc.K;
+            elim.d = Lc.d;
+            elim.stream = s;
+            st = apply_dirichlet(elim);
+            if (st != MF_OK) return st;
+        }
         int64_t bad = -1;
         st = mf_status_poll(Lc.P, &bad);
         if (st != MF_OK) return st;
@@ -606,6 +733,12 @@ extern "C" mf_status mf_mg_update(mf_mg_t* mg, const mf_form* form, const double
     MF_HIP(hipStreamSynchronize(s));
     mg->updated = true;
     return MF_OK;
+}
+
+extern "C" mf_status mf_mg_update(mf_mg_t* mg, const mf_form* form, const double* coords, const mf_fields* fields,
+                                  const mf_quadrature* quad, const double* K, void* stream)
+{
+    return mf_mg_update_ex(mg, form, coords, fields, nullptr, 0, quad, K, stream);
 }
 
 extern "C" mf_status mf_mg_apply(const mf_mg_t* mg, const double* r, double* z, void* stream)

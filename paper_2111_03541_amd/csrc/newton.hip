@@ -189,7 +189,7 @@ static mf_status newton_run(const mf_pattern_t* P, const mf_form* form, const do
             mf_fields Fm{};
             Fm.lin_state = state;
             Fm.dirichlet = dirichlet;
-            st = mf_mg_update(mg, form, coords, &Fm, quad, K, stream);
+            st = mf_mg_update_ex(mg, form, coords, &Fm, bsets, n_bsets, quad, K, stream);
             if (st != MF_OK) return st;
             lo.precond = MF_PRECOND_MG;
             lo.mg = mg;
@@ -223,10 +223,10 @@ extern "C" mf_status mf_ns_newton_ex(const mf_pattern_t* P, const mf_form* form,
 }
 
 extern "C" mf_status mf_ns_newton_mg(const mf_pattern_t* P, const mf_form* form, const double* coords,
-                                     double* state, const uint8_t* dirichlet, const mf_mg_opts* mg,
-                                     const mf_quadrature* quad, const mf_newton_opts* opts, mf_newton_result* res,
-                                     void* stream)
+                                     double* state, const uint8_t* dirichlet, const mf_bset* bsets, int32_t n_bsets,
+                                     const mf_mg_opts* mg, const mf_quadrature* quad, const mf_newton_opts* opts,
+                                     mf_newton_result* res, void* stream)
 {
     if (!mg) return set_error(MF_ERR_ARG, "multigrid options are NULL");
-    return newton_run(P, form, coords, state, dirichlet, nullptr, 0, mg, quad, opts, res, stream);
+    return newton_run(P, form, coords, state, dirichlet, bsets, n_bsets, mg, quad, opts, res, stream);
 }

@@ -6,7 +6,7 @@ Tolerance of one cycle: max |z - z_ref| <= 1e-12 max |z_ref|.  Both sides run th
 sweeps in FP64 and differ only in the order of the additions (SpMV rows, restriction
 stencils, the assembly's element sums).  A few tens of sweeps, each contractive, keep
 that rounding at a few units of 1e-16 times the operators' condition of one sweep
-(measured: 4e-16 to 2.1e-15 over the cases below); the bar leaves more than two orders of
+(measured: 4e-16 to 2.3e-15 over the cases below); the bar leaves more than two orders of
 margin.
 """
 import sys
@@ -299,3 +299,82 @@ def test_newton_cavity_48_with_multigrid_converges_reproducibly(mf):
     _, d = O.assemble(pat, O.NS_SUPG, prm, state=st, dirichlet=mask, want_K=False)
     assert abs(res["res_norm"][0] - np.linalg.norm(d0)) <= 1e-12 * np.linalg.norm(d0)
     assert np.linalg.norm(d) <= 1e-10 * np.linalg.norm(d0)
+
+
+def weak_cavity_sets(dims, rho=1.0, mu=0.01):
+    """The cavity's walls as weak boundary forms: the lid (side 5) as inflow with
+    u^w = (1, 0, 0), the other five sides as fix."""
+    import oracle.boundary as OB
+    return [(OB.NS_INFLOW, W.box_faces(dims, sides=[5]), [1.0, 0.0, 0.0, rho, mu]),
+            (OB.NS_FIX, W.box_faces(dims, sides=[0, 1, 2, 3, 4]), [0.0, 0.0, 0.0, rho, mu])]
+
+
+@pytest.mark.parametrize("numbering", [O.NODE_MAJOR, O.FIELD_MAJOR])
+def test_flow_cycle_with_face_sets_matches_oracle(mf, numbering):
+    """A jittered 16^3 cavity whose walls are weak boundary forms (no Dirichlet rows), at a
+    random state: the face sets coarsened onto every level (3 levels, 16^3 to 4^3)."""
+    n = 16
+    say(f"flow cycle with face sets {n}^3 numbering {numbering}")
+    dev = torch.device("cuda:0")
+    mesh, st, _ = flow_case(n, numbering, 31)
+    prm = flow_params(n, 3)
+    tau_b = 10.0
+    sets = weak_cavity_sets((n, n, n))
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 4, numbering=numbering)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    stt = torch.from_numpy(st).to(dev).contiguous()
+    form = mf.Form(mf.NS_SUPG, **prm[0])
+    K, d = pat.assemble(form, coords, lin_state=stt)
+    bnd = [(k, torch.from_numpy(fe).to(dev), torch.from_numpy(fi).to(dev), tau_b, v, None) for k, (fe, fi), v in sets]
+    for k, fe, fi, c, v, _ in bnd:
+        pat.assemble_boundary(k, coords, fe, fi, coef=c, value=v, state=stt, K=K, d=d)
+    mg = mf.Multigrid(pat, tau_m=[p["tau_m"] for p in prm], tau_c=[p["tau_c"] for p in prm])
+    mg.update(form, coords, K, lin_state=stt, boundary=bnd)
+    r = np.random.default_rng(32).standard_normal(pat.n_rows)
+    z = mg.apply(torch.from_numpy(r).to(dev)).cpu().numpy()
+    face_sets = [(k, tau_b, v, fe, fi, None) for k, (fe, fi), v in sets]
+    levels = MG.build_levels((n, n, n), mesh.coords, 4, O.NS_SUPG, prm, 3, state=st, numbering=numbering,
+                             face_sets=face_sets)
+    z_ref = MG.vcycle(levels, r)
+    err = np.abs(z - z_ref).max() / np.abs(z_ref).max()
+    say(f"  rel err {err:.2e}")
+    assert err <= TOL
+
+
+def weak_newton(mf, n, multigrid, jitter=0.0, seed=None, **kw):
+    dev = torch.device("cuda:0")
+    dims = (n, n, n)
+    mesh = W.structured_mesh(dims, jitter=jitter, seed=seed)
+    prm = flow_params(n, 8)
+    pat = mf.Pattern(torch.from_numpy(mesh.conn).to(dev), mesh.n_nodes, 3, 4)
+    coords = torch.from_numpy(mesh.coords).to(dev)
+    mask = np.zeros(pat.n_rows, np.uint8)
+    mask[3] = 1  # the pressure of node 0
+    bnd = [(k, torch.from_numpy(fe).to(dev), torch.from_numpy(fi).to(dev), 10.0, v, None)
+           for k, (fe, fi), v in weak_cavity_sets(dims)]
+    st = torch.zeros((4, mesh.n_nodes), dtype=torch.float64, device=dev)
+    mgo = dict(tau_m=[p["tau_m"] for p in prm], tau_c=[p["tau_c"] for p in prm]) if multigrid else None
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        res = mf.ns_newton(pat, mf.Form(mf.NS_SUPG, **prm[0]), coords, st, dirichlet=torch.from_numpy(mask).to(dev),
+                           boundary=bnd, multigrid=mgo, stream=s, **kw)
+    s.synchronize()
+    return st.cpu().numpy(), res
+
+
+def test_weak_boundary_newton_with_multigrid(mf):
+    """The weakly bounded cavity: on a jittered 8^3 mesh the multigrid Newton reaches the
+    Jacobi Newton's state; on 32^3 it converges in a fraction of the Jacobi iterations, the
+    same on two runs, bit for bit."""
+    say("weak-boundary newton with multigrid")
+    st_mg, r_mg = weak_newton(mf, 8, True, jitter=0.1, seed=12, rtol=1e-12, lin_tol=1e-12)
+    st_j, r_j = weak_newton(mf, 8, False, jitter=0.1, seed=12, rtol=1e-12, lin_tol=1e-12)
+    say(f"  8^3: mg {r_mg['steps']} steps {r_mg['lin_iterations']} it; jacobi {r_j['steps']} steps "
+        f"{r_j['lin_iterations']} it")
+    assert r_mg["converged"] and r_j["converged"]
+    assert np.abs(st_mg - st_j).max() <= 1e-8 * np.abs(st_j).max()
+    st1, r1 = weak_newton(mf, 32, True, rtol=1e-10, lin_tol=1e-10)
+    st2, r2 = weak_newton(mf, 32, True, rtol=1e-10, lin_tol=1e-10)
+    say(f"  32^3: {r1['steps']} steps {r1['lin_iterations']} it, res {['%.2e' % r for r in r1['res_norm']]}")
+    assert r1["converged"] and r1["steps"] <= 8 and r1["lin_iterations"] <= 300
+    assert r2["lin_iterations"] == r1["lin_iterations"] and np.array_equal(st1, st2)
