@@ -19,7 +19,9 @@ enough.  What follows is textbook geometric multigrid (Briggs, Henson and McCorm
   element (ex/2, ey/2, ez/2) with the same local face when its two in-plane indices are
   even and its index along the axis is even for side 0, odd for side 1; the other fine
   faces drop out.  Nodal targets are injected.  The operator is the domain form plus the
-  faces, then the Dirichlet elimination (unit row, zero column).
+  faces, then the Dirichlet elimination (unit row, zero column).  An element coefficient
+  field (conductivity, Young's modulus) is carried to a coarse element as the arithmetic
+  mean of its eight children.
 - Prolongation P.  Trilinear interpolation of the coarse nodal values, the embedding of the
   coarse Q1 space in the fine one, field by field.  A fine node with an even index along an
   axis takes that axis's coarse node; one with an odd index takes the mean of the two
@@ -151,6 +153,14 @@ def coarsen_faces(fine_dims, face_elem, face_id):
     return ce[keep].astype(np.int32), f[keep].astype(np.uint8)
 
 
+def coarsen_elem(fine_dims, values):
+    """Coarse element (ex,ey,ez): the mean of the fine elements (2ex+a, 2ey+b, 2ez+c)."""
+    nx, ny, nz = fine_dims
+    v = np.asarray(values, np.float64).reshape(nz, ny, nx)
+    kids = [v[c::2, b::2, a::2] for c in (0, 1) for b in (0, 1) for a in (0, 1)]
+    return (sum(kids) / 8.0).ravel()
+
+
 def eliminate(A, mask):
     """Dirichlet elimination of the rows and columns flagged in mask: unit row, zero
     column."""
@@ -160,21 +170,25 @@ def eliminate(A, mask):
 
 
 def build_levels(fine_dims, coords, nf, kind, params_per_level, n_levels, state=None, dirichlet=None,
-                 numbering=NODE_MAJOR, K0=None, face_sets=()):
+                 numbering=NODE_MAJOR, K0=None, face_sets=(), elem_param=None):
     """The level hierarchy: a list of dicts with the grid dims, the coarse mesh, the
     pattern, the operator A (scipy CSR), the Dirichlet flags and D^-1.  Level 0's operator
     is K0 when given (the caller's assembled fine matrix), else the oracle's assembly.
     params_per_level[l]: the form's scalar parameters on level l.  face_sets: boundary
-    forms (kind, coef, value, face_elem, face_id, target or None) given on level 0."""
+    forms (kind, coef, value, face_elem, face_id, target or None) given on level 0.
+    elem_param: the element coefficient field of level 0 (or None)."""
     levels = []
     dims = tuple(int(v) for v in fine_dims)
     crd = np.asarray(coords, np.float64)
     st = None if state is None else np.asarray(state, np.float64)
     msk = None if dirichlet is None else np.asarray(dirichlet, np.uint8)
     faces = [list(fs) for fs in face_sets]
+    ep = None if elem_param is None else np.asarray(elem_param, np.float64)
     for l in range(n_levels):
         if l > 0:
             src = injection(dims)
+            if ep is not None:
+                ep = coarsen_elem(dims, ep)
             nn_f = crd.shape[1]
             for fs in faces:
                 fs[3], fs[4] = coarsen_faces(dims, fs[3], fs[4])
@@ -193,7 +207,7 @@ def build_levels(fine_dims, coords, nf, kind, params_per_level, n_levels, state=
         if l == 0 and K0 is not None:
             A = pat.to_scipy(np.asarray(K0, np.float64))
         elif faces:
-            K, _ = assemble(pat, kind, params_per_level[l], state=st)
+            K, _ = assemble(pat, kind, params_per_level[l], state=st, elem_param=ep)
             A = pat.to_scipy(K)
             for bk, coef, value, fe, fi, tg in faces:
                 Kb, _ = OB.assemble_boundary(pat, bk, coef, value, fe, fi, state=st, target=tg)
@@ -201,7 +215,7 @@ def build_levels(fine_dims, coords, nf, kind, params_per_level, n_levels, state=
             if msk is not None:
                 A = eliminate(A, msk.astype(bool))
         else:
-            K, _ = assemble(pat, kind, params_per_level[l], state=st, dirichlet=msk)
+            K, _ = assemble(pat, kind, params_per_level[l], state=st, dirichlet=msk, elem_param=ep)
             A = pat.to_scipy(K)
         diag = A.diagonal()
         dinv = np.where(diag != 0.0, 1.0 / np.where(diag != 0.0, diag, 1.0), 0.0)

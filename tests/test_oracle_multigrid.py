@@ -14,7 +14,9 @@ the paper).
   * the cycle is a linear map (fixed sweeps, zero initial guesses);
   * face coarsening: on a box the coarsened face list is the coarse box's own, and with a
     penalty (face mass) form on part of the boundary the Galerkin identity still holds;
-  * the elimination leaves unit rows and zero columns.
+  * the elimination leaves unit rows and zero columns;
+  * a coarse element's coefficient is the mean of its eight children; with a coefficient
+    constant on each coarse element the Galerkin identity still holds.
 """
 import numpy as np
 import pytest
@@ -166,3 +168,28 @@ def test_elimination_gives_unit_rows_and_zero_columns():
                 assert E[r, c] == (1.0 if r == c else 0.0)
             else:
                 assert E[r, c] == Ad[r, c]
+
+
+def test_coarse_coefficient_is_the_mean_of_the_children():
+    dims = (4, 2, 6)
+    v = np.arange(np.prod(dims), dtype=np.float64) ** 1.5
+    c = MG.coarsen_elem(dims, v)
+    assert c.shape == (6,)  # coarse grid 2 x 1 x 3
+    # coarse element (1, 0, 2): fine ex in {2, 3}, ey in {0, 1}, ez in {4, 5}
+    kids = [ex + 4 * (ey + 2 * ez) for ex in (2, 3) for ey in (0, 1) for ez in (4, 5)]
+    assert c[1 + 2 * (0 + 1 * 2)] == pytest.approx(v[kids].mean(), rel=1e-15)
+
+
+def test_galerkin_identity_with_a_piecewise_constant_coefficient():
+    """A conductivity constant on each coarse element is the same field on both levels, so
+    the coarse rediscretisation is P^T A P again."""
+    dims = (4, 4, 4)
+    mesh = W.structured_mesh(dims, lengths=(1.0, 0.5, 2.0))
+    coarse = W.lognormal_elem(8, 1.0, 4)
+    ex, ey, ez = np.meshgrid(np.arange(4), np.arange(4), np.arange(4), indexing="ij")
+    ex, ey, ez = (a.ravel(order="F") for a in (ex, ey, ez))
+    k = coarse[ex // 2 + 2 * (ey // 2 + 2 * (ez // 2))]
+    levels = MG.build_levels(dims, mesh.coords, 1, O.POISSON, [dict(coef=1.0)] * 2, 2, elem_param=k)
+    G = (levels[0]["P"].T @ levels[0]["A"] @ levels[0]["P"]).toarray()
+    ref = levels[1]["A"].toarray()
+    assert np.abs(G - ref).max() <= 1e-12 * np.abs(ref).max()
