@@ -116,7 +116,10 @@ def learned_net(dev):
 
 def bench_pcg(dev, seeds=(10000, 10001, 10002), reps=2):
     """Time to true relative residual 1e-8 on 96^3 lognormal Poisson: Jacobi-PCG vs PCG
-    with the learned preconditioner (network inference inside the timed region)."""
+    with the learned preconditioner (network inference inside the timed region), and
+    beside them PCG with the geometric multigrid cycle (coarse conductivity the mean of the
+    children; the cycle's update for the system, which assembles the coarse levels, is
+    timed on its own, as the network's binding to the system is not timed)."""
     import torch
     import paper_2111_03541_amd as mf
     net, net_info = learned_net(dev)
@@ -128,28 +131,41 @@ def bench_pcg(dev, seeds=(10000, 10001, 10002), reps=2):
         torch.cuda.synchronize()
         rp, ci, _ = pat.device_arrays()
         net.set_system(rp, ci, K, args["dirichlet"])
+        form = mf.Form(mf.POISSON, coef=1.0)
+        mg = mf.Multigrid(pat)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mg.update(form, coords, K, dirichlet=args["dirichlet"], elem_param=args["elem_param"])
+        torch.cuda.synchronize()
+        mg_update_ms = 1e3 * (time.perf_counter() - t0)
         x = torch.empty_like(d)
         row = {"seed": seed, "sigma": sigma}
-        for name, pc in (("jacobi", mf.PRECOND_JACOBI), ("learned", mf.PRECOND_NN)):
+        for name, pc in (("jacobi", mf.PRECOND_JACOBI), ("learned", mf.PRECOND_NN), ("multigrid", mf.PRECOND_MG)):
             ts = []
             for _ in range(reps + 1):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 _, res = mf.pcg(rp, ci, K, d, x=x, tol=1e-8, maxit=20000, precond=pc,
-                                net=net if pc == mf.PRECOND_NN else None, check_every=8,
-                                use_graph=True, stream=stream)
+                                net=net if pc == mf.PRECOND_NN else None, mg=mg if pc == mf.PRECOND_MG else None,
+                                check_every=8 if pc != mf.PRECOND_MG else 4, use_graph=True, stream=stream)
                 torch.cuda.synchronize()
                 ts.append(time.perf_counter() - t0)
             assert res["converged"] and res["true_relres"] <= 1e-8
             row[name] = {"iterations": res["iterations"], "ms": 1e3 * min(ts[1:]),
                          "true_relres": res["true_relres"], "fallbacks": res["fallbacks"]}
+        row["multigrid"]["update_ms"] = mg_update_ms
         log(f"[bench] PCG 96^3 seed {seed}: jacobi {row['jacobi']['iterations']} it "
-            f"{row['jacobi']['ms']:.1f} ms, learned {row['learned']['iterations']} it {row['learned']['ms']:.1f} ms")
+            f"{row['jacobi']['ms']:.1f} ms, learned {row['learned']['iterations']} it {row['learned']['ms']:.1f} ms, "
+            f"multigrid {row['multigrid']['iterations']} it {row['multigrid']['ms']:.1f} ms "
+            f"(+ {mg_update_ms:.1f} ms update)")
         rows.append(row)
+        del mg
     jm = float(np.median([r["jacobi"]["ms"] for r in rows]))
     lm = float(np.median([r["learned"]["ms"] for r in rows]))
+    mm = float(np.median([r["multigrid"]["ms"] for r in rows]))
     return {"n_dofs": pat.n_rows, "nnz": pat.nnz, "systems": rows, "median_ms_jacobi": jm,
-            "median_ms_learned": lm, "speedup_learned_vs_jacobi": jm / lm, "network": net_info}
+            "median_ms_learned": lm, "speedup_learned_vs_jacobi": jm / lm, "median_ms_multigrid": mm,
+            "network": net_info}
 
 
 def bench_batch(dev, steps=10, warmup=3):

@@ -540,9 +540,10 @@ mf_status mf_ns_newton_ex(const mf_pattern_t* P, const mf_form* form, const doub
  *     every axis of level l has an even element count, and its node (i,j,k) is the level-l
  *     node (2i,2j,2k).  Coarsening stops at max_levels levels, or at the first level with at
  *     most coarse_rows rows, or when an axis is odd.
- *   Coarse operators: the same form assembled (FP64, column kernel) on each coarser grid
- *     from the coordinates, linearisation state and Dirichlet flags of the coincident fine
- *     nodes (injection), with the flow form's stabilisation constants of that level.
+ *   Coarse operators: the same form assembled (FP64) on each coarser grid from the
+ *     coordinates, linearisation state and Dirichlet flags of the coincident fine nodes
+ *     (injection), an element coefficient field averaged over the eight children, and the
+ *     flow form's stabilisation constants of that level.
  *   Transfers: P = trilinear interpolation (field by field), restriction R = P^T.
  *   Smoother: damped Jacobi x <- x + omega D^-1 (b - A x), D^-1 = 0 where diag A = 0.
  *   V-cycle V(l, b): on the coarsest level coarse_sweeps sweeps from x = 0; otherwise
@@ -573,10 +574,12 @@ mf_status mf_mg_levels(const mf_mg_t* mg, int32_t* n_levels, int64_t* dims);
 
 /* Prepares the cycle for the level-0 operator K [nnz of P] (device FP64, borrowed: it must
    stay unchanged until the next update): injects coords [3][n_nodes] and the fields'
-   lin_state and dirichlet to every coarser level, assembles each coarse operator with
-   `form` and `quad`, and forms every level's D^-1.  fields may be NULL; its elem_param and
-   nodal_src must be NULL (MF_ERR_UNSUPPORTED).  (sync)  Errors: those of mf_assemble (a
-   coarse element with det J <= 0: MF_ERR_BAD_JACOBIAN), MF_ERR_ARG, MF_ERR_HIP. */
+   lin_state and dirichlet to every coarser level, carries elem_param (FP64 [n_elems], or
+   NULL) to a coarse element as the mean of its eight children, assembles each coarse
+   operator with `form` and `quad`, and forms every level's D^-1.  fields may be NULL; its
+   nodal_src must be NULL (MF_ERR_UNSUPPORTED: the cycle needs no right side).  (sync)
+   Errors: those of mf_assemble (a coarse element with det J <= 0: MF_ERR_BAD_JACOBIAN),
+   MF_ERR_ARG, MF_ERR_HIP. */
 mf_status mf_mg_update(mf_mg_t* mg, const mf_form* form, const double* coords, const mf_fields* fields,
                        const mf_quadrature* quad, const double* K, void* stream);
 

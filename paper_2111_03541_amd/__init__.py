@@ -591,16 +591,19 @@ class Multigrid:
         check(load().mf_mg_levels(self.handle, C.byref(n), dims))
         return [tuple(dims[3 * l:3 * l + 3]) for l in range(n.value)]
 
-    def update(self, form, coords, K, lin_state=None, dirichlet=None, points_per_axis=2, stream=None, boundary=()):
+    def update(self, form, coords, K, lin_state=None, dirichlet=None, points_per_axis=2, stream=None, boundary=(),
+               elem_param=None):
         """Assemble the coarse levels for the level-0 operator K (kept referenced);
-        boundary: face sets as for ns_newton, in K and on every level."""
+        boundary: face sets as for ns_newton, in K and on every level; elem_param: the
+        FP64 element coefficient field K was assembled with."""
         import torch
         p = self.pattern
         _require(coords, "coords", torch.float64, p.dim * p.n_nodes, optional=False)
         _require(K, "K", torch.float64, p.nnz, optional=False)
         _require(lin_state, "lin_state", torch.float64, 4 * p.n_nodes)
         _require(dirichlet, "dirichlet", torch.uint8, p.n_rows)
-        F = _Fields(None, None, _ptr(lin_state), _ptr(dirichlet))
+        _require(elem_param, "elem_param", torch.float64, p.n_elems)
+        F = _Fields(_ptr(elem_param), None, _ptr(lin_state), _ptr(dirichlet))
         q = _Quad(points_per_axis)
         sets = _bsets(boundary, p)
         check(load().mf_mg_update_ex(self.handle, C.byref(form.c), _ptr(coords), C.byref(F), sets, len(boundary),

@@ -5,7 +5,8 @@
 //              level-l node (2i,2j,2k)
 //   operators  rediscretisation: the same form assembled (FP64) on each coarse grid from the
 //              coordinates, linearisation state and Dirichlet flags of the coincident fine
-//              nodes (injection)
+//              nodes (injection), an element coefficient field averaged over the eight
+//              children, and boundary face sets coarsened with the grid
 //   transfers  P = trilinear interpolation field by field, R = P^T (full weighting)
 //   smoother   damped Jacobi x <- x + omega D^-1 (b - A x)
 //   cycle      V(l, b): pre sweeps from x = 0, r = b - A x, b_c = R r (0 on coarse Dirichlet
@@ -43,6 +44,7 @@ struct mf_mg_s {
         double* coords = nullptr;          // l >= 1: [3][n_nodes]
         double* state = nullptr;           // l >= 1: [4][n_nodes] linearisation state
         uint8_t* mask = nullptr;           // l >= 1: [n_rows]
+        double* elem = nullptr;            // l >= 1: [n_elems] element coefficient field
         double* dinv = nullptr;            // [n_rows]
         double* x = nullptr;               // l >= 1: the cycle's output on this level
         double* b = nullptr;               // l >= 1: the restricted right side
@@ -150,6 +152,23 @@ __global__ void __launch_bounds__(kThreads) k_mg_faces(int64_t n, const int32_t*
             ce[slot] = (int32_t)(idx[0] / 2 + (nx / 2) * (idx[1] / 2 + (ny / 2) * (idx[2] / 2)));
             cf[slot] = (uint8_t)lf;
         }
+    }
+}
+
+// Coarse element (ex,ey,ez): the mean of the fine elements (2ex+a, 2ey+b, 2ez+c), summed
+// with the first axis fastest.
+__global__ void __launch_bounds__(kThreads) k_mg_coarsen_elem(int64_t cx, int64_t cy, int64_t cz, int64_t fx,
+                                                              int64_t fy, const double* __restrict__ f,
+                                                              double* __restrict__ c)
+{
+    const int64_t n = cx * cy * cz;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t ex = e % cx, r = e / cx, ey = r % cy, ez = r / cy;
+        double sum = 0.0;
+        for (int k = 0; k < 2; ++k)
+            for (int j = 0; j < 2; ++j)
+                for (int i = 0; i < 2; ++i) sum += f[(2 * ex + i) + fx * ((2 * ey + j) + fy * (2 * ez + k))];
+        c[e] = sum / 8.0;
     }
 }
 
@@ -552,9 +571,10 @@ extern "C" mf_status mf_mg_create(const mf_pattern_t* P, const mf_mg_opts* opts,
         Lv.state = (double*)dalloc(sizeof(double) * 4 * nodes);
         Lv.mask = (uint8_t*)dalloc(rows);
         const int64_t n_el = Lv.nx * Lv.ny * Lv.nz;
+        Lv.elem = (double*)dalloc(sizeof(double) * (size_t)n_el);
         int32_t* conn = nullptr;
         if (hipMalloc(&conn, sizeof(int32_t) * 8 * (size_t)n_el) != hipSuccess) conn = nullptr;
-        if (!Lv.x || !Lv.b || !Lv.d || !Lv.coords || !Lv.state || !Lv.mask || !conn) {
+        if (!Lv.x || !Lv.b || !Lv.d || !Lv.coords || !Lv.state || !Lv.mask || !Lv.elem || !conn) {
             if (conn) (void)hipFree(conn);
             st = set_error(MF_ERR_OOM, "multigrid workspace allocation failed");
             break;
@@ -612,8 +632,8 @@ extern "C" mf_status mf_mg_update_ex(mf_mg_t* mg, const mf_form* form, const dou
 {
     if (!mg || !form || !quad) return set_error(MF_ERR_ARG, "mg, form or quad is NULL");
     if (!coords || !K) return set_error(MF_ERR_ARG, "coords or K is NULL");
-    if (fields && (fields->elem_param || fields->nodal_src))
-        return set_error(MF_ERR_UNSUPPORTED, "multigrid coarse levels take no elem_param or nodal_src");
+    if (fields && fields->nodal_src)
+        return set_error(MF_ERR_UNSUPPORTED, "multigrid coarse levels take no nodal_src (the cycle needs no right side)");
     if (n_bsets < 0 || (n_bsets > 0 && !bsets)) return set_error(MF_ERR_ARG, "n_bsets < 0 or bsets NULL");
     for (int b = 0; b < n_bsets; ++b)
         if (bsets[b].n_faces < 0 || (bsets[b].n_faces > 0 && (!bsets[b].face_elem || !bsets[b].face_id)))
@@ -621,6 +641,7 @@ extern "C" mf_status mf_mg_update_ex(mf_mg_t* mg, const mf_form* form, const dou
     hipStream_t s = (hipStream_t)stream;
     const double* lin_state = fields ? (const double*)fields->lin_state : nullptr;
     const uint8_t* dirichlet = fields ? fields->dirichlet : nullptr;
+    const double* elem_param = fields ? (const double*)fields->elem_param : nullptr;
     mg->updated = false;
     mg->has_mask = dirichlet != nullptr;
     mg->L[0].Kv = K;
@@ -663,6 +684,10 @@ extern "C" mf_status mf_mg_update_ex(mf_mg_t* mg, const mf_form* form, const dou
         k_mg_inject<<<grid_for(Lc.n_nodes, kThreads), kThreads, 0, s>>>(Lc.nx, Lc.ny, Lc.n_nodes, Lf.nx, Lf.ny,
                                                                         Lf.n_nodes, mg->nf, mg->fm, fc, Lc.coords, fs,
                                                                         Lc.state, fmk, Lc.mask);
+        if (elem_param) {
+            k_mg_coarsen_elem<<<grid_for(Lc.nx * Lc.ny * Lc.nz, kThreads), kThreads, 0, s>>>(
+                Lc.nx, Lc.ny, Lc.nz, Lf.nx, Lf.ny, l == 1 ? elem_param : Lf.elem, Lc.elem);
+        }
         MF_HIP(hipGetLastError());
         if (n_bsets > 0) {
             k_mg_zero_int<<<1, 64, 0, s>>>(counter, n_bsets);
@@ -700,6 +725,7 @@ extern "C" mf_status mf_mg_update_ex(mf_mg_t* mg, const mf_form* form, const dou
         }
         mf_fields F{};
         F.lin_state = lin_state ? Lc.state : nullptr;
+        F.elem_param = elem_param ? Lc.elem : nullptr;
         // with face sets the elimination comes after the faces are added
         F.dirichlet = (dirichlet && n_bsets == 0) ? Lc.mask : nullptr;
         mf_status st = mf_assemble(Lc.P, &fl, Lc.coords, &F, quad, MF_F64, Lc.K, Lc.d, stream);
