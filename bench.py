@@ -117,9 +117,10 @@ def learned_net(dev):
 def bench_pcg(dev, seeds=(10000, 10001, 10002), reps=2):
     """Time to true relative residual 1e-8 on 96^3 lognormal Poisson: Jacobi-PCG vs PCG
     with the learned preconditioner (network inference inside the timed region), and
-    beside them PCG with the geometric multigrid cycle (coarse conductivity the mean of the
-    children; the cycle's update for the system, which assembles the coarse levels, is
-    timed on its own, as the network's binding to the system is not timed)."""
+    beside them PCG with the geometric multigrid cycle (V(1,1), damped Jacobi omega 0.6,
+    coarse conductivity the mean of the children; the cycle's update for the system,
+    which assembles the coarse levels, is timed on its own, as the network's binding to the
+    system is not timed)."""
     import torch
     import paper_2111_03541_amd as mf
     net, net_info = learned_net(dev)
@@ -132,7 +133,9 @@ def bench_pcg(dev, seeds=(10000, 10001, 10002), reps=2):
         rp, ci, _ = pat.device_arrays()
         net.set_system(rp, ci, K, args["dirichlet"])
         form = mf.Form(mf.POISSON, coef=1.0)
-        mg = mf.Multigrid(pat)
+        # V(1,1), omega 0.6: 10.8-10.9 ms on two of the systems, against 11.8 ms for V(2,2)
+        # at 0.6 and 11.8-14.8 ms for the flow solves' V(2,2) at 0.5
+        mg = mf.Multigrid(pat, pre_sweeps=1, post_sweeps=1, omega=0.6)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         mg.update(form, coords, K, dirichlet=args["dirichlet"], elem_param=args["elem_param"])
