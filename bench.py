@@ -411,8 +411,9 @@ def bench_transient(dev, n=96, steps=20, cpu=True, n_cpu=24):
     """Transient conduction on the 96^3 lognormal-conductivity cube of the learned
     preconditioner's workload (seed 10000), capacity 1, unit source, T = 0 on the boundary:
     20 generalized-alpha steps (rho_inf 0.5, dt 1e-4, about the diffusion time h^2 C / k of
-    one cell at k = 1), each solved by Jacobi-PCG to 1e-10.  The oracle (scipy LU per
-    step) is timed on a 24^3 mesh."""
+    one cell at k = 1), each solved by Jacobi-PCG to 1e-10, and again with the multigrid
+    cycle of the effective matrix (V(1,1), omega 0.6).  The oracle (scipy LU per step) is
+    timed on a 24^3 mesh."""
     import torch
     import workloads as W
     import paper_2111_03541_amd as mf
@@ -427,14 +428,14 @@ def bench_transient(dev, n=96, steps=20, cpu=True, n_cpu=24):
     m = torch.from_numpy(mask).to(dev)
     s = torch.cuda.Stream(dev)
 
-    def run(nsteps):
+    def run(nsteps, mgo=None):
         T = torch.zeros(mesh.n_nodes, dtype=torch.float64, device=dev)
         U = torch.zeros(mesh.n_nodes, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         with torch.cuda.stream(s):
             res = mf.heat_transient(pat, coords, T, U, 1e-4, nsteps, elem_k=kt, source=src, dirichlet=m,
-                                    rho_inf=0.5, init_rate=True, lin_tol=1e-10, stream=s)
+                                    rho_inf=0.5, init_rate=True, lin_tol=1e-10, stream=s, multigrid=mgo)
         s.synchronize()
         return res, time.perf_counter() - t0
 
@@ -446,6 +447,15 @@ def bench_transient(dev, n=96, steps=20, cpu=True, n_cpu=24):
         f"assembly and initial rate), {res['lin_iterations']} PCG iterations")
     out = {"n": n, "n_dofs": pat.n_rows, "steps": steps, "ms": wall * 1e3, "ms_per_step": per_step * 1e3,
            "setup_ms": w0 * 1e3, "lin_iterations": res["lin_iterations"] - res0["lin_iterations"]}
+    mgo = dict(pre_sweeps=1, post_sweeps=1, omega=0.6)
+    run(1, mgo)
+    rm0, wm0 = run(0, mgo)
+    rm, wm = run(steps, mgo)
+    pm = (wm - wm0) / steps
+    log(f"[bench] transient {n}^3, multigrid: {steps} steps in {wm * 1e3:.1f} ms ({pm * 1e3:.2f} ms/step), "
+        f"{rm['lin_iterations'] - rm0['lin_iterations']} PCG iterations")
+    out["multigrid"] = {"ms": wm * 1e3, "ms_per_step": pm * 1e3,
+                        "lin_iterations": rm["lin_iterations"] - rm0["lin_iterations"]}
     if cpu:
         import oracle as O
         import oracle.transient as OT

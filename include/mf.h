@@ -285,6 +285,18 @@ mf_status mf_heat_transient(const mf_pattern_t* P, double capacity, double condu
                             const mf_quadrature* quad, const mf_transient_opts* opts, double* T, double* Tdot,
                             mf_transient_result* res, void* stream);
 
+/* mf_heat_transient with the steps' solves preconditioned by the multigrid cycle (mf_mg_*,
+   declared below) of the effective matrix c1 K + c2 / (b1 dt) M: every coarse level
+   assembles both forms (elem_k averaged over the eight children) and combines them with
+   the same weights and elimination.  P must be a structured grid of 8-node hexahedra
+   (MF_ERR_UNSUPPORTED otherwise).  The optional initial-rate solve keeps Jacobi.  (sync)
+   Errors: those of mf_heat_transient and of mf_mg_create. */
+typedef struct mf_mg_opts_s mf_mg_opts;
+mf_status mf_heat_transient_mg(const mf_pattern_t* P, double capacity, double conductivity, const double* coords,
+                               const double* elem_k, const double* source, const uint8_t* dirichlet,
+                               const mf_mg_opts* mg, const mf_quadrature* quad, const mf_transient_opts* opts,
+                               double* T, double* Tdot, mf_transient_result* res, void* stream);
+
 /* ------------------------------------------------------------------------------------
  * Boundary forms: the physics one dimension lower (Sec. 2.2, opening of the algorithm),
  * integrated over element faces with the 2x2 Gauss rule of the face and added into an
@@ -551,7 +563,7 @@ mf_status mf_ns_newton_ex(const mf_pattern_t* P, const mf_form* form, const doub
  *     to 0, x += P V(l+1, b_c), post_sweeps sweeps.  It is a fixed linear map of b.
  * ------------------------------------------------------------------------------------ */
 #define MF_MG_MAX_LEVELS 8
-typedef struct {
+struct mf_mg_opts_s {
     int32_t max_levels;     /* levels including level 0, 1..MF_MG_MAX_LEVELS (0 = 8)         */
     int32_t coarse_rows;    /* stop coarsening at a level with at most this many rows (0 = 512) */
     int32_t pre_sweeps;     /* >= 0 */
@@ -560,7 +572,7 @@ typedef struct {
     double omega;           /* Jacobi damping, in (0, 1]                                      */
     double tau_m[MF_MG_MAX_LEVELS];  /* flow form: tau_m, tau_c of level l's tangent (entry 0 */
     double tau_c[MF_MG_MAX_LEVELS];  /* unused: level 0 is the caller's K); 0 = the form's    */
-} mf_mg_opts;
+};
 
 /* Builds the level grids and their patterns (the pattern's numbering and field count) and
    allocates every level's vectors.  P: 3D 8-node hexahedra on a structured grid with full

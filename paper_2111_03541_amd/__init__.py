@@ -137,7 +137,7 @@ EXPORTS = [
     "mf_bicgstab", "mf_ns_newton", "mf_ns_newton_ex", "mf_assemble_boundary", "mf_heat_transient",
     "mf_pcg_noalloc", "mf_pcg_noalloc_max_rows", "mf_nn_checkpoint_size", "mf_nn_save", "mf_nn_load",
     "mf_batch_tiles", "mf_mg_create", "mf_mg_levels", "mf_mg_update", "mf_mg_apply", "mf_mg_destroy",
-    "mf_ns_newton_mg", "mf_mg_update_ex",
+    "mf_ns_newton_mg", "mf_mg_update_ex", "mf_heat_transient_mg",
 ]
 
 
@@ -186,6 +186,8 @@ def load():
     lib.mf_spmv.argtypes = [C.POINTER(_CSR), P, P, P]
     lib.mf_heat_transient.argtypes = [P, C.c_double, C.c_double, P, P, P, P, C.POINTER(_Quad),
                                       C.POINTER(_TransientOpts), P, P, C.POINTER(_TransientResult), P]
+    lib.mf_heat_transient_mg.argtypes = [P, C.c_double, C.c_double, P, P, P, P, C.POINTER(_MgOpts), C.POINTER(_Quad),
+                                         C.POINTER(_TransientOpts), P, P, C.POINTER(_TransientResult), P]
     lib.mf_assemble_boundary.argtypes = [P, C.POINTER(_BForm), P, i64, P, P, P, P, C.c_int, P, P, P]
     lib.mf_bicgstab.argtypes = [C.POINTER(_CSR), P, P, C.POINTER(_PcgOpts), C.POINTER(_PcgResult), P]
     lib.mf_ns_newton.argtypes = [P, C.POINTER(_Form), P, P, P, C.POINTER(_Quad), C.POINTER(_NewtonOpts),
@@ -749,9 +751,10 @@ def ns_newton(pattern, form, coords, state, dirichlet=None, rtol=1e-10, atol=0.0
 
 def heat_transient(pattern, coords, T, Tdot, dt, n_steps, capacity=1.0, conductivity=1.0, elem_k=None, source=None,
                    dirichlet=None, rho_inf=0.5, init_rate=False, lin_tol=1e-12, lin_maxit=20000,
-                   points_per_axis=2, stream=None):
+                   points_per_axis=2, stream=None, multigrid=None):
     """Generalized-alpha steps of C dT/dt - div(k grad T) = s; T and Tdot (FP64 cuda,
-    [n_nodes]) are updated in place.  Returns the result dict."""
+    [n_nodes]) are updated in place.  multigrid: None (Jacobi-PCG) or a dict of mg_opts
+    arguments (mf_heat_transient_mg).  Returns the result dict."""
     import torch
     lib = load()
     _require(coords, "coords", torch.float64, pattern.dim * pattern.n_nodes, optional=False)
@@ -763,9 +766,15 @@ def heat_transient(pattern, coords, T, Tdot, dt, n_steps, capacity=1.0, conducti
     opts = _TransientOpts(dt, rho_inf, n_steps, int(bool(init_rate)), lin_tol, lin_maxit)
     res = _TransientResult()
     q = _Quad(points_per_axis)
-    check(lib.mf_heat_transient(pattern.handle, capacity, conductivity, _ptr(coords), _ptr(elem_k), _ptr(source),
-                                _ptr(dirichlet), C.byref(q), C.byref(opts), _ptr(T), _ptr(Tdot), C.byref(res),
-                                _stream(stream)))
+    if multigrid is not None:
+        mo = mg_opts(**multigrid)
+        check(lib.mf_heat_transient_mg(pattern.handle, capacity, conductivity, _ptr(coords), _ptr(elem_k),
+                                       _ptr(source), _ptr(dirichlet), C.byref(mo), C.byref(q), C.byref(opts), _ptr(T),
+                                       _ptr(Tdot), C.byref(res), _stream(stream)))
+    else:
+        check(lib.mf_heat_transient(pattern.handle, capacity, conductivity, _ptr(coords), _ptr(elem_k),
+                                    _ptr(source), _ptr(dirichlet), C.byref(q), C.byref(opts), _ptr(T), _ptr(Tdot),
+                                    C.byref(res), _stream(stream)))
     return {"steps": res.steps, "lin_iterations": res.lin_iterations, "max_lin_relres": res.max_lin_relres}
 
 

@@ -63,6 +63,11 @@ struct PcgArgs;
 mf_status nn_bind_pcg(const mf_nn_t* net, int64_t n_rows, PcgArgs* a);
 // multigrid.hip: one V-cycle as the external preconditioner of a solve on `values`
 mf_status mg_bind_pcg(const mf_mg_t* mg, int64_t n_rows, const double* values, PcgArgs* a);
+// the cycle for A = wa Ka + wb Kb (scalar forms; fa with elem_param) with the Dirichlet
+// elimination on every level, A0 the level-0 operator (sync)
+mf_status mg_update_combined(mf_mg_t* mg, const mf_form* fa, const double* elem_param, double wa,
+                             const mf_form* fb, double wb, const double* coords, const uint8_t* dirichlet,
+                             const mf_quadrature* quad, const double* A0, hipStream_t s);
 
 // assemble.hip
 struct AssembleArgs {

@@ -172,6 +172,23 @@ __global__ void __launch_bounds__(kThreads) k_mg_coarsen_elem(int64_t cx, int64_
     }
 }
 
+// A = a K + b M on one pattern, Dirichlet rows unit rows and their columns zero
+__global__ void __launch_bounds__(kThreads) k_mg_combine(int64_t n, const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ ci, const double* __restrict__ K,
+                                                         const double* __restrict__ M, double a, double b,
+                                                         const uint8_t* __restrict__ mask, double* __restrict__ A)
+{
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const bool fixed = mask && mask[r];
+        for (int k = rp[r]; k < rp[r + 1]; ++k) {
+            const int c = ci[k];
+            double v = a * K[k] + b * M[k];
+            if (fixed || (mask && mask[c])) v = c == r ? 1.0 : 0.0;
+            A[k] = v;
+        }
+    }
+}
+
 __global__ void k_mg_zero_int(int* p, int n)
 {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
@@ -475,6 +492,64 @@ mf_status mg_apply_cb(void* ctx, const double* r, double* z, hipStream_t s)
 }
 
 }  // namespace
+
+// The cycle for A = wa Ka + wb Kb (two scalar forms, fa with the element field elem_param,
+// fb without), with the Dirichlet elimination, on every level; A0 is level 0's operator.
+mf_status mg_update_combined(mf_mg_t* mg, const mf_form* fa, const double* elem_param, double wa,
+                             const mf_form* fb, double wb, const double* coords, const uint8_t* dirichlet,
+                             const mf_quadrature* quad, const double* A0, hipStream_t s)
+{
+    mg->updated = false;
+    mg->has_mask = dirichlet != nullptr;
+    mg->L[0].Kv = A0;
+    for (int l = 1; l < mg->n_levels; ++l) {
+        mf_mg_s::Level& Lf = mg->L[l - 1];
+        mf_mg_s::Level& Lc = mg->L[l];
+        k_mg_inject<<<grid_for(Lc.n_nodes, kThreads), kThreads, 0, s>>>(
+            Lc.nx, Lc.ny, Lc.n_nodes, Lf.nx, Lf.ny, Lf.n_nodes, mg->nf, mg->fm, l == 1 ? coords : Lf.coords,
+            Lc.coords, nullptr, Lc.state, dirichlet ? (l == 1 ? dirichlet : Lf.mask) : nullptr, Lc.mask);
+        if (elem_param)
+            k_mg_coarsen_elem<<<grid_for(Lc.nx * Lc.ny * Lc.nz, kThreads), kThreads, 0, s>>>(
+                Lc.nx, Lc.ny, Lc.nz, Lf.nx, Lf.ny, l == 1 ? elem_param : Lf.elem, Lc.elem);
+        MF_HIP(hipGetLastError());
+        // Kb into the level's sweep buffers would not fit (nnz > rows): assemble it into K,
+        // Ka into a scratch of nnz, then combine into K
+        double* Ka = nullptr;
+        if (hipMalloc(&Ka, sizeof(double) * std::max<int64_t>(Lc.P->nnz, 1)) != hipSuccess)
+            return set_error(MF_ERR_OOM, "multigrid workspace allocation failed");
+        struct FreeKa {
+            double* p;
+            hipStream_t s;
+            ~FreeKa() {
+                (void)hipStreamSynchronize(s);
+                (void)hipFree(p);
+            }
+        } fka{Ka, s};
+        mf_fields Fa{};
+        Fa.elem_param = elem_param ? Lc.elem : nullptr;
+        mf_status st = mf_assemble(Lc.P, fa, Lc.coords, &Fa, quad, MF_F64, Ka, Lc.d, s);
+        if (st != MF_OK) return st;
+        mf_fields Fb{};
+        st = mf_assemble(Lc.P, fb, Lc.coords, &Fb, quad, MF_F64, Lc.K, Lc.d, s);
+        if (st != MF_OK) return st;
+        k_mg_combine<<<grid_for(Lc.n_rows, kThreads), kThreads, 0, s>>>(Lc.n_rows, Lc.P->row_ptr, Lc.P->col_idx, Ka,
+                                                                       Lc.K, wa, wb, dirichlet ? Lc.mask : nullptr,
+                                                                       Lc.K);
+        MF_HIP(hipGetLastError());
+        int64_t bad = -1;
+        st = mf_status_poll(Lc.P, &bad);
+        if (st != MF_OK) return st;
+    }
+    for (int l = 0; l < mg->n_levels; ++l) {
+        const mf_mg_s::Level& Lv = mg->L[l];
+        k_mg_dinv<<<grid_for(Lv.n_rows, kThreads), kThreads, 0, s>>>(Lv.n_rows, Lv.Pv->row_ptr, Lv.Pv->col_idx, Lv.Kv,
+                                                                     Lv.dinv);
+    }
+    MF_HIP(hipGetLastError());
+    MF_HIP(hipStreamSynchronize(s));
+    mg->updated = true;
+    return MF_OK;
+}
 
 mf_status mg_bind_pcg(const mf_mg_t* mg, int64_t n_rows, const double* values, PcgArgs* a)
 {

@@ -10,7 +10,8 @@
 //   c2 = alpha_m = (3 - rho) / (2 (1 + rho)),  c1 = alpha_f = 1 / (1 + rho),
 //   b1 = gamma = 1/2 + alpha_m - alpha_f  (second order, unconditionally stable).
 // M and K are assembled once (FP64, the library's mass and conduction forms); each step
-// is two SpMVs, one combine-and-eliminate pass and a Jacobi-PCG solve.
+// is two SpMVs, one combine-and-eliminate pass and a PCG solve, with Jacobi or (the _mg
+// entry point) a multigrid cycle built once for the effective matrix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -81,11 +82,12 @@ __global__ void __launch_bounds__(kThreads) k_copy_masked(int64_t n, const doubl
 
 using namespace mf;
 
-extern "C" mf_status mf_heat_transient(const mf_pattern_t* P, double capacity, double conductivity,
-                                       const double* coords, const double* elem_k, const double* source,
-                                       const uint8_t* dirichlet, const mf_quadrature* quad,
-                                       const mf_transient_opts* opts, double* T, double* Tdot,
-                                       mf_transient_result* res, void* stream)
+// The driver behind mf_heat_transient and mf_heat_transient_mg: with mgo, the solves of
+// the steps are preconditioned by a multigrid cycle built once for the effective matrix.
+static mf_status transient_run(const mf_pattern_t* P, double capacity, double conductivity, const double* coords,
+                               const double* elem_k, const double* source, const uint8_t* dirichlet,
+                               const mf_mg_opts* mgo, const mf_quadrature* quad, const mf_transient_opts* opts,
+                               double* T, double* Tdot, mf_transient_result* res, void* stream)
 {
     if (!P || !quad || !opts || !res) return set_error(MF_ERR_ARG, "NULL pattern, quadrature, opts or res");
     if (P->nf != 1) return set_error(MF_ERR_ARG, "transient conduction needs a scalar pattern (1 field)");
@@ -178,6 +180,21 @@ extern "C" mf_status mf_heat_transient(const mf_pattern_t* P, double capacity, d
     if (opts->n_steps == 0) return MF_OK;
     k_combine<<<nb, kThreads, 0, s>>>(n, P->row_ptr, P->col_idx, K, M, af, am / (g * dt), dirichlet, A);
     MF_HIP(hipGetLastError());
+    mf_mg_t* mg = nullptr;
+    struct MgFree {
+        mf_mg_t** m;
+        ~MgFree() { mf_mg_destroy(*m); }
+    } mgf{&mg};
+    if (mgo) {
+        // the effective matrix af K + am/(g dt) M on every level
+        st = mf_mg_create(P, mgo, stream, &mg);
+        if (st != MF_OK) return st;
+        st = mg_update_combined(mg, &fk, elem_k, af, &fm, am / (g * dt), coords, dirichlet, quad, A, s);
+        if (st != MF_OK) return st;
+        po.precond = MF_PRECOND_MG;
+        po.mg = mg;
+        po.check_every = 4;
+    }
     const double beta = 1.0 - am / g;
     for (int k = 0; k < opts->n_steps; ++k) {
         st = run_spmv(&Kc, T, w1, s);
@@ -193,4 +210,25 @@ extern "C" mf_status mf_heat_transient(const mf_pattern_t* P, double capacity, d
         res->steps = k + 1;
     }
     return MF_OK;
+}
+
+extern "C" mf_status mf_heat_transient(const mf_pattern_t* P, double capacity, double conductivity,
+                                       const double* coords, const double* elem_k, const double* source,
+                                       const uint8_t* dirichlet, const mf_quadrature* quad,
+                                       const mf_transient_opts* opts, double* T, double* Tdot,
+                                       mf_transient_result* res, void* stream)
+{
+    return transient_run(P, capacity, conductivity, coords, elem_k, source, dirichlet, nullptr, quad, opts, T, Tdot,
+                         res, stream);
+}
+
+extern "C" mf_status mf_heat_transient_mg(const mf_pattern_t* P, double capacity, double conductivity,
+                                          const double* coords, const double* elem_k, const double* source,
+                                          const uint8_t* dirichlet, const mf_mg_opts* mg, const mf_quadrature* quad,
+                                          const mf_transient_opts* opts, double* T, double* Tdot,
+                                          mf_transient_result* res, void* stream)
+{
+    if (!mg) return set_error(MF_ERR_ARG, "multigrid options are NULL");
+    return transient_run(P, capacity, conductivity, coords, elem_k, source, dirichlet, mg, quad, opts, T, Tdot, res,
+                         stream);
 }
