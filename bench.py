@@ -133,8 +133,8 @@ def bench_pcg(dev, seeds=(10000, 10001, 10002), reps=2):
         rp, ci, _ = pat.device_arrays()
         net.set_system(rp, ci, K, args["dirichlet"])
         form = mf.Form(mf.POISSON, coef=1.0)
-        # V(1,1), omega 0.6: 10.8-10.9 ms on two of the systems, against 11.8 ms for V(2,2)
-        # at 0.6 and 11.8-14.8 ms for the flow solves' V(2,2) at 0.5
+        # V(1,1), omega 0.6: 9.7-9.8 ms on two of the systems, against 10.1-10.2 ms for V(2,2)
+        # at 0.6 and 10.2-12.6 ms for the flow solves' V(2,2) at 0.5
         mg = mf.Multigrid(pat, pre_sweeps=1, post_sweeps=1, omega=0.6)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -16,7 +16,9 @@
 // cleared with memset, so a cycle can be captured in a HIP graph):
 //   k_mg_sweep     one Jacobi sweep, out of place, with the SpMV fused (8 lanes per row for
 //                  the 4-field flow rows of up to 108 entries, 4 otherwise); the same kernel
-//                  forms the first sweep from x = 0 (no SpMV) and the residual b - A x
+//                  forms the first sweep from x = 0 (no SpMV) and the residual b - A x;
+//                  scalar patterns run it on a slot-major ELL copy, one row per thread
+//                  (k_mg_sweep_ell)
 //   k_mg_restrict  one thread per coarse node gathers its 27 fine neighbours, every field
 //   k_mg_prolong   one thread per fine node interpolates from its 1, 2, 4 or 8 parents
 //   k_mg_coarse    the coarsest level in one workgroup, the iterate in LDS, all sweeps in
@@ -49,6 +51,11 @@ struct mf_mg_s {
         double* x = nullptr;               // l >= 1: the cycle's output on this level
         double* b = nullptr;               // l >= 1: the restricted right side
         double* t = nullptr;               // second sweep buffer and residual
+        // scalar patterns: the operator in slot-major ELL form (slot k of row i at
+        // k * n_rows + i; padding has value 0 and column i), refreshed at every update
+        int width = 0;
+        int32_t* ecol = nullptr;
+        double* eval = nullptr;
     };
     int n_levels = 0;
     int nf = 0;
@@ -221,6 +228,45 @@ __global__ void __launch_bounds__(kThreads) k_mg_dinv(int64_t n, const int32_t* 
 }
 
 enum SweepMode { kSweep = 0, kFirst = 1, kResidual = 2 };
+
+// ELL columns of a CSR pattern (fixed with the pattern)
+__global__ void __launch_bounds__(kThreads) k_mg_ell_cols(int64_t n, int width, const int32_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ ci, int32_t* __restrict__ ecol)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int k0 = rp[i], len = rp[i + 1] - k0;
+        for (int k = 0; k < width; ++k) ecol[k * n + i] = k < len ? ci[k0 + k] : (int32_t)i;
+    }
+}
+
+// ELL values of the level's operator
+__global__ void __launch_bounds__(kThreads) k_mg_ell_vals(int64_t n, int width, const int32_t* __restrict__ rp,
+                                                          const double* __restrict__ A, double* __restrict__ eval)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int k0 = rp[i], len = rp[i + 1] - k0;
+        for (int k = 0; k < width; ++k) eval[k * n + i] = k < len ? A[k0 + k] : 0.0;
+    }
+}
+
+// The sweep of k_mg_sweep on the ELL copy, one row per thread: consecutive rows read
+// consecutive addresses of every slot.
+template <int MODE>
+__global__ void __launch_bounds__(kThreads) k_mg_sweep_ell(int64_t n, int width, const int32_t* __restrict__ ecol,
+                                                           const double* __restrict__ eval,
+                                                           const double* __restrict__ dinv,
+                                                           const double* __restrict__ b,
+                                                           const double* __restrict__ in, double* __restrict__ out,
+                                                           double omega)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+#pragma unroll 9
+        for (int k = 0; k < width; ++k) s = fma(eval[k * n + i], in[ecol[k * n + i]], s);
+        if (MODE == kSweep) out[i] = in[i] + omega * dinv[i] * (b[i] - s);
+        else out[i] = b[i] - s;
+    }
+}
 
 // kSweep:    out = in + omega dinv (b - A in)
 // kFirst:    out = omega dinv b            (the sweep from x = 0; A and in unused)
@@ -401,6 +447,14 @@ void launch_sweep(int mode, const mf_mg_s::Level& Lv, int nf, const double* b, c
     const int64_t n = Lv.n_rows;
     const int32_t* rp = Lv.Pv->row_ptr;
     const int32_t* ci = Lv.Pv->col_idx;
+    if (Lv.eval && mode != kFirst) {
+        const unsigned g = grid_for(n, kThreads);
+        if (mode == kSweep)
+            k_mg_sweep_ell<kSweep><<<g, kThreads, 0, s>>>(n, Lv.width, Lv.ecol, Lv.eval, Lv.dinv, b, in, out, omega);
+        else
+            k_mg_sweep_ell<kResidual><<<g, kThreads, 0, s>>>(n, Lv.width, Lv.ecol, Lv.eval, Lv.dinv, b, in, out, omega);
+        return;
+    }
     if (nf >= 4) {
         const unsigned g = grid_for(n * 8, kThreads);
         if (mode == kFirst) k_mg_sweep<8, kFirst><<<g, kThreads, 0, s>>>(n, rp, ci, Lv.Kv, Lv.dinv, b, in, out, omega);
@@ -544,6 +598,9 @@ mf_status mg_update_combined(mf_mg_t* mg, const mf_form* fa, const double* elem_
         const mf_mg_s::Level& Lv = mg->L[l];
         k_mg_dinv<<<grid_for(Lv.n_rows, kThreads), kThreads, 0, s>>>(Lv.n_rows, Lv.Pv->row_ptr, Lv.Pv->col_idx, Lv.Kv,
                                                                      Lv.dinv);
+        if (Lv.eval)
+            k_mg_ell_vals<<<grid_for(Lv.n_rows, kThreads), kThreads, 0, s>>>(Lv.n_rows, Lv.width, Lv.Pv->row_ptr,
+                                                                             Lv.Kv, Lv.eval);
     }
     MF_HIP(hipGetLastError());
     MF_HIP(hipStreamSynchronize(s));
@@ -674,6 +731,23 @@ extern "C" mf_status mf_mg_create(const mf_pattern_t* P, const mf_mg_opts* opts,
         Lv.K = (double*)dalloc(sizeof(double) * (size_t)Lv.P->nnz);
         Lv.Kv = Lv.K;
         if (!Lv.K) st = set_error(MF_ERR_OOM, "multigrid workspace allocation failed");
+    }
+    // scalar patterns: ELL copies of every level but the one-workgroup coarsest (rows of
+    // a hexahedral grid hold at most 27 entries)
+    for (int l = 0; l < n && st == MF_OK && P->nf == 1; ++l) {
+        mf_mg_s::Level& Lv = mg->L[l];
+        if (l == n - 1 && Lv.n_rows <= kCoarseMax) break;
+        Lv.width = 27;
+        Lv.ecol = (int32_t*)dalloc(sizeof(int32_t) * 27 * (size_t)Lv.n_rows);
+        Lv.eval = (double*)dalloc(sizeof(double) * 27 * (size_t)Lv.n_rows);
+        if (!Lv.ecol || !Lv.eval) {
+            st = set_error(MF_ERR_OOM, "multigrid workspace allocation failed");
+            break;
+        }
+        k_mg_ell_cols<<<grid_for(Lv.n_rows, kThreads), kThreads, 0, s>>>(Lv.n_rows, 27, Lv.Pv->row_ptr,
+                                                                         Lv.Pv->col_idx, Lv.ecol);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) st = hip_error(e, "k_mg_ell_cols");
     }
     if (st == MF_OK) {
         hipError_t e = hipStreamSynchronize(s);
@@ -829,6 +903,9 @@ extern "C" mf_status mf_mg_update_ex(mf_mg_t* mg, const mf_form* form, const dou
         const mf_mg_s::Level& Lv = mg->L[l];
         k_mg_dinv<<<grid_for(Lv.n_rows, kThreads), kThreads, 0, s>>>(Lv.n_rows, Lv.Pv->row_ptr, Lv.Pv->col_idx, Lv.Kv,
                                                                      Lv.dinv);
+        if (Lv.eval)
+            k_mg_ell_vals<<<grid_for(Lv.n_rows, kThreads), kThreads, 0, s>>>(Lv.n_rows, Lv.width, Lv.Pv->row_ptr,
+                                                                             Lv.Kv, Lv.eval);
     }
     MF_HIP(hipGetLastError());
     MF_HIP(hipStreamSynchronize(s));
