@@ -75,6 +75,11 @@ constexpr int kMaxBlocks = 8192;
 constexpr int kCoarseMax = 4096;      // rows of a coarsest level solved in one workgroup
 constexpr int kCoarseThreads = 1024;
 constexpr int kCoarseLanes = 4;       // lanes per row in the coarsest-level kernel
+// field counts whose levels sweep on an ELL copy (index: fields per node): scalar rows
+// (27 entries; 96^3 conduction 10.8 -> 9.7 ms per PCG solve).  The flow's 108-entry rows
+// stay on the 8-lane CSR sweep: with ELL, one thread per row, the 48^3 Newton solve took
+// 155-157 ms against 144 ms.
+constexpr bool kEllFields[5] = {false, true, false, false, false};
 
 __device__ __forceinline__ int64_t dof_of(int64_t node, int f, int64_t n_nodes, int nf, int fm)
 {
@@ -732,19 +737,20 @@ extern "C" mf_status mf_mg_create(const mf_pattern_t* P, const mf_mg_opts* opts,
         Lv.Kv = Lv.K;
         if (!Lv.K) st = set_error(MF_ERR_OOM, "multigrid workspace allocation failed");
     }
-    // scalar patterns: ELL copies of every level but the one-workgroup coarsest (rows of
-    // a hexahedral grid hold at most 27 entries)
-    for (int l = 0; l < n && st == MF_OK && P->nf == 1; ++l) {
+    // ELL copies of every level but the one-workgroup coarsest (rows of a hexahedral grid
+    // hold at most 27 nodes x nf entries)
+    const int ell_width = 27 * P->nf;
+    for (int l = 0; l < n && st == MF_OK && kEllFields[P->nf]; ++l) {
         mf_mg_s::Level& Lv = mg->L[l];
         if (l == n - 1 && Lv.n_rows <= kCoarseMax) break;
-        Lv.width = 27;
-        Lv.ecol = (int32_t*)dalloc(sizeof(int32_t) * 27 * (size_t)Lv.n_rows);
-        Lv.eval = (double*)dalloc(sizeof(double) * 27 * (size_t)Lv.n_rows);
+        Lv.width = ell_width;
+        Lv.ecol = (int32_t*)dalloc(sizeof(int32_t) * ell_width * (size_t)Lv.n_rows);
+        Lv.eval = (double*)dalloc(sizeof(double) * ell_width * (size_t)Lv.n_rows);
         if (!Lv.ecol || !Lv.eval) {
             st = set_error(MF_ERR_OOM, "multigrid workspace allocation failed");
             break;
         }
-        k_mg_ell_cols<<<grid_for(Lv.n_rows, kThreads), kThreads, 0, s>>>(Lv.n_rows, 27, Lv.Pv->row_ptr,
+        k_mg_ell_cols<<<grid_for(Lv.n_rows, kThreads), kThreads, 0, s>>>(Lv.n_rows, ell_width, Lv.Pv->row_ptr,
                                                                          Lv.Pv->col_idx, Lv.ecol);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) st = hip_error(e, "k_mg_ell_cols");
