@@ -322,11 +322,11 @@ def bench_newton(dev, n=24, cpu=True, n_cpu=16):
     return out
 
 
-def bench_newton_mg(dev, sizes=(24, 32, 48)):
+def bench_newton_mg(dev, sizes=(24, 32, 48, 64)):
     """The cavity of bench_newton with the multigrid-preconditioned BiCGStab
     (mf_ns_newton_mg: rediscretised coarse tangents down to at most 512 rows, damped Jacobi
-    V(2,2)), on bench_newton's 24^3 mesh, on 32^3 and on the flow Jacobian's 48^3 mesh, where
-    Jacobi-BiCGStab breaks down."""
+    V(2,2)), on bench_newton's 24^3 mesh, on 32^3, on the flow Jacobian's 48^3 mesh, where
+    Jacobi-BiCGStab breaks down, and on 64^3 (1.1 M unknowns)."""
     run_newton(dev, 8, multigrid=True)  # warm-up
     out = {}
     for n in sizes:
