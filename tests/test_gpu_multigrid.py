@@ -116,6 +116,9 @@ def test_flow_cycle_matches_oracle(mf, numbering, coarse_rows):
     (O.POISSON, 1, dict(coef=1.0), (18, 18, 18), dict(max_levels=1, coarse_sweeps=4), 1),
     (O.POISSON, 1, dict(coef=1.0), (8, 8, 8), dict(coarse_rows=1, pre_sweeps=0, post_sweeps=1,
                                                    coarse_sweeps=0), 4),
+    # the benchmark's V(1,1) at omega 0.6, and an odd total of sweeps per level
+    (O.POISSON, 1, dict(coef=1.0), (16, 16, 16), dict(pre_sweeps=1, post_sweeps=1, omega=0.6), 3),
+    (O.ELASTICITY, 3, dict(coef=1.0, nu=0.3), (8, 8, 8), dict(coarse_rows=1, pre_sweeps=2, post_sweeps=1), 4),
 ])
 def test_symmetric_form_cycle_matches_oracle(mf, kind, nf, prm, dims, opts, n_levels):
     say(f"cycle kind {kind} dims {dims} opts {opts}")
