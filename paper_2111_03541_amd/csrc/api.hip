@@ -332,6 +332,22 @@ int64_t mf_pcg_noalloc_max_rows(void) { return pcg_noalloc_max_rows(); }
 mf_status mf_bicgstab(const mf_csr* A, const double* b, double* x, const mf_pcg_opts* opts, mf_pcg_result* res,
                       void* stream)
 {
+    return bicgstab_on_pattern(A, nullptr, b, x, opts, res, stream);
+}
+
+mf_status mf_spmv(const mf_csr* A, const double* x, double* y, void* stream)
+{
+    if (!A) return set_error(MF_ERR_ARG, "A is NULL");
+    if (A->n_rows > 0 && (!A->row_ptr || !A->col_idx || !A->values || !x || !y))
+        return set_error(MF_ERR_ARG, "NULL matrix or vector");
+    return run_spmv(A, x, y, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+mf_status mf::bicgstab_on_pattern(const mf_csr* A, const mf_pattern_s* P, const double* b, double* x,
+                                  const mf_pcg_opts* opts, mf_pcg_result* res, void* stream)
+{
     g_err[0] = 0;
     if (!A || !opts || !res) return set_error(MF_ERR_ARG, "A, opts or res is NULL");
     if (A->n_rows < 0 || A->n_rows >= ((int64_t)1 << 31)) return set_error(MF_ERR_ARG, "n_rows out of range");
@@ -354,6 +370,13 @@ mf_status mf_bicgstab(const mf_csr* A, const double* b, double* x, const mf_pcg_
     a.use_graph = opts->use_graph && stream != nullptr;
     a.stream = (hipStream_t)stream;
     a.precond = opts->precond;
+    // A on P's CSR structure with node-major rows of four fully coupled fields (16 entries
+    // per node pair): the SpMV reads the columns from the node graph
+    if (P && A->row_ptr == P->row_ptr && A->col_idx == P->col_idx && A->n_rows == P->n_rows && P->nf == 4 &&
+        P->numbering == MF_NODE_MAJOR && P->nnz == 16 * P->n_pairs) {
+        a.node_ptr = P->nbr_ptr;
+        a.node_nbr = P->nbr;
+    }
     if (opts->precond == MF_PRECOND_MG) {
         if (!opts->mg) return set_error(MF_ERR_ARG, "MF_PRECOND_MG needs a multigrid cycle");
         mf_status st = mg_bind_pcg(opts->mg, A->n_rows, A->values, &a);
@@ -361,13 +384,3 @@ mf_status mf_bicgstab(const mf_csr* A, const double* b, double* x, const mf_pcg_
     }
     return run_bicgstab(a, res);
 }
-
-mf_status mf_spmv(const mf_csr* A, const double* x, double* y, void* stream)
-{
-    if (!A) return set_error(MF_ERR_ARG, "A is NULL");
-    if (A->n_rows > 0 && (!A->row_ptr || !A->col_idx || !A->values || !x || !y))
-        return set_error(MF_ERR_ARG, "NULL matrix or vector");
-    return run_spmv(A, x, y, (hipStream_t)stream);
-}
-
-}  // extern "C"

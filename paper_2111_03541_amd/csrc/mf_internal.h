@@ -60,6 +60,10 @@ mf_status build_pattern(mf_pattern_s* P, const int32_t* conn_in, hipStream_t s);
 mf_status ensure_coloring(const mf_pattern_s* P, hipStream_t s);
 
 struct PcgArgs;
+// mf_bicgstab; with P (the pattern whose CSR structure A uses) the SpMV of node-major
+// 4-field rows reads its columns from P's node graph
+mf_status bicgstab_on_pattern(const mf_csr* A, const mf_pattern_s* P, const double* b, double* x,
+                              const mf_pcg_opts* opts, mf_pcg_result* res, void* stream);
 mf_status nn_bind_pcg(const mf_nn_t* net, int64_t n_rows, PcgArgs* a);
 // multigrid.hip: one V-cycle as the external preconditioner of a solve on `values`
 mf_status mg_bind_pcg(const mf_mg_t* mg, int64_t n_rows, const double* values, PcgArgs* a);

@@ -201,7 +201,7 @@ static mf_status newton_run(const mf_pattern_t* P, const mf_form* form, const do
         const double target = std::max(opts->rtol * d0, opts->atol);
         lo.tol = std::max({opts->lin_tol, std::min(0.1, d0 > 0.0 ? norm / d0 : 0.1),
                            std::min(0.5, 0.5 * target / norm)});
-        st = mf_bicgstab(&A, d, du, &lo, &lr, stream);
+        st = bicgstab_on_pattern(&A, P, d, du, &lo, &lr, stream);
         res->lin_iterations += lr.iterations;
         const bool usable = (st == MF_ERR_NOT_CONVERGED || st == MF_ERR_NONFINITE) &&
                             std::isfinite(lr.true_relres) && lr.true_relres < 1.0;

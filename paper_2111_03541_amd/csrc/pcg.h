@@ -30,6 +30,10 @@ struct PcgArgs {
     PcgApply apply;
     void* apply_ctx;
     int apply_graph_safe;
+    // BiCGStab only: the node graph (offsets [n/4 + 1], neighbours) of node-major rows of
+    // four fully coupled fields, whose SpMV then reads the columns from it; null otherwise
+    const int32_t* node_ptr;
+    const int32_t* node_nbr;
     hipStream_t stream;
 };
 

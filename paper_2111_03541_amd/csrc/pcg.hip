@@ -191,6 +191,42 @@ __global__ void __launch_bounds__(kThreads) k_spmv_ell_dot(int n, int width, con
     }
 }
 
+// y = A x for node-major rows of four fully coupled fields, with the columns taken from
+// the node graph: row (v, f) starts at 16 P_v + 4 deg_v f (P_v, deg_v: node v's offset
+// and degree) and its entry o has column 4 w + o % 4, w the (o / 4)-th neighbour of v.
+// 8 lanes per row read 8 bytes per entry (12 for CSR or ELL) and K needs no copy.
+// partial[block] = sum of w[row] y[row], in a fixed order.
+__global__ void __launch_bounds__(kThreads) k_spmv_nodes_dot(int n, const int32_t* __restrict__ np,
+                                                             const int32_t* __restrict__ nb,
+                                                             const double* __restrict__ A,
+                                                             const double* __restrict__ x, double* __restrict__ y,
+                                                             const double* __restrict__ w, double* __restrict__ partial)
+{
+    __shared__ double sh[kThreads / 64];
+    constexpr int kLanes = 8;
+    const int lane = threadIdx.x % kLanes, g = lane % 4;
+    const int rows_per_pass = gridDim.x * (kThreads / kLanes);
+    double acc_dot = 0.0;
+    for (int row = (blockIdx.x * kThreads + threadIdx.x) / kLanes; row < n; row += rows_per_pass) {
+        const int p0 = np[row / 4], len = 4 * (np[row / 4 + 1] - p0);
+        const double* a = A + 16 * (int64_t)p0 + (int64_t)len * (row % 4);
+        const int32_t* nbr = nb + p0;
+        double s = 0.0;
+#pragma unroll 4
+        for (int o = lane; o < len; o += kLanes) s = fma(a[o], x[4 * nbr[o / 4] + g], s);
+#pragma unroll
+        for (int off = kLanes / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kLanes);
+        if (lane == 0) {
+            y[row] = s;
+            if (w) acc_dot = fma(w[row], s, acc_dot);
+        }
+    }
+    if (partial) {
+        const double t = block_sum_all(acc_dot, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = t;
+    }
+}
+
 // one block: alpha = (r.z) / (p.q) from the SpMV partials
 __global__ void k_reduce_alpha(const double* __restrict__ pq_part, int nb, double* s)
 {
@@ -996,7 +1032,8 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
     }
     int32_t* ecol = nullptr;
     double* eval = nullptr;
-    if (width > 0 && (int64_t)width * n <= (int64_t)nnz32 + nnz32 / 2) {
+    // with the node graph of 4-field rows the SpMV reads K in place (no ELL copy)
+    if (!a.node_ptr && width > 0 && (int64_t)width * n <= (int64_t)nnz32 + nnz32 / 2) {
         ecol = (int32_t*)dalloc(sizeof(int32_t) * (size_t)width * n);
         eval = (double*)dalloc(sizeof(double) * (size_t)width * n);
         if (ecol && eval) {
@@ -1008,7 +1045,9 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
         }
     }
     auto spmv = [&](const double* x_in, double* y, const double* w, double* part) {
-        if (ecol)
+        if (a.node_ptr)
+            k_spmv_nodes_dot<<<spmv_blocks, kThreads, 0, s>>>(n, a.node_ptr, a.node_nbr, a.values, x_in, y, w, part);
+        else if (ecol)
             k_spmv_ell_dot<<<spmv_blocks, kThreads, 0, s>>>(n, width, ecol, eval, x_in, y, w, part);
         else
             k_spmv_dot<<<spmv_blocks, kThreads, 0, s>>>(n, a.row_ptr, a.col_idx, a.values, x_in, y, w, part);
