@@ -11,6 +11,8 @@
 // K and d are cleared by fill kernels first, so the call overwrites them entirely.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "element.h"
 #include "mf_internal.h"
 
@@ -209,6 +211,44 @@ __global__ void k_dirichlet(const int32_t* __restrict__ row_ptr, const int32_t* 
     dirichlet_row(row_ptr, col_idx, mask, r, K, d);
 }
 
+// dirichlet_row with LANES lanes per row (consecutive lanes take consecutive entries, so
+// the column loads of a row group are one contiguous access); every entry gets the same
+// value as in dirichlet_row
+template <typename T, int LANES>
+__global__ void __launch_bounds__(kThreads) k_dirichlet_lanes(const int32_t* __restrict__ row_ptr,
+                                                              const int32_t* __restrict__ col_idx,
+                                                              const uint8_t* __restrict__ mask, int64_t n_rows,
+                                                              T* __restrict__ K, T* __restrict__ d)
+{
+    const int lane = threadIdx.x % LANES;
+    const int64_t rows_per_pass = (int64_t)gridDim.x * (kThreads / LANES);
+    for (int64_t r = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / LANES; r < n_rows; r += rows_per_pass) {
+        const int64_t k0 = row_ptr[r], k1 = row_ptr[r + 1];
+        if (mask[r]) {
+            for (int64_t k = k0 + lane; k < k1; k += LANES) K[k] = (col_idx[k] == r) ? T(1) : T(0);
+            if (lane == 0) d[r] = T(0);
+        } else {
+            for (int64_t k = k0 + lane; k < k1; k += LANES)
+                if (mask[col_idx[k]]) K[k] = T(0);
+        }
+    }
+}
+
+template <typename T>
+void launch_dirichlet(const mf_pattern_s* P, const uint8_t* mask, T* K, T* d, hipStream_t s)
+{
+    const int64_t n = P->n_rows;
+    const int64_t avg = P->nnz / n;
+    const int lanes = avg >= 48 ? 8 : avg >= 12 ? 4 : 1;
+    if (lanes == 1) {
+        k_dirichlet<T><<<blocks_for(n, kThreads), kThreads, 0, s>>>(P->row_ptr, P->col_idx, mask, n, K, d);
+        return;
+    }
+    const unsigned g = (unsigned)std::min<int64_t>(8192, (n * lanes + kThreads - 1) / kThreads);
+    if (lanes == 8) k_dirichlet_lanes<T, 8><<<g, kThreads, 0, s>>>(P->row_ptr, P->col_idx, mask, n, K, d);
+    else k_dirichlet_lanes<T, 4><<<g, kThreads, 0, s>>>(P->row_ptr, P->col_idx, mask, n, K, d);
+}
+
 __global__ void k_reset_status(unsigned long long* s)
 {
     s[0] = ~0ull;
@@ -342,12 +382,8 @@ mf_status apply_dirichlet(const AssembleArgs& A)
 {
     const mf_pattern_s* P = A.P;
     if (!A.dirichlet || P->n_rows == 0) return MF_OK;
-    if (A.prec == MF_F64)
-        k_dirichlet<double><<<blocks_for(P->n_rows, kThreads), kThreads, 0, A.stream>>>(
-            P->row_ptr, P->col_idx, A.dirichlet, P->n_rows, (double*)A.K, (double*)A.d);
-    else
-        k_dirichlet<float><<<blocks_for(P->n_rows, kThreads), kThreads, 0, A.stream>>>(
-            P->row_ptr, P->col_idx, A.dirichlet, P->n_rows, (float*)A.K, (float*)A.d);
+    if (A.prec == MF_F64) launch_dirichlet<double>(P, A.dirichlet, (double*)A.K, (double*)A.d, A.stream);
+    else launch_dirichlet<float>(P, A.dirichlet, (float*)A.K, (float*)A.d, A.stream);
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
