@@ -8,6 +8,8 @@
 //                  would be large.  Rows are split into one contiguous range per block,
 //                  laid out so that each XCD (workgroups go to the 8 XCDs round robin)
 //                  streams one contiguous eighth of K and gathers from one eighth of p.
+//                  BiCGStab on node-major 4-field rows (the Newton tangent) uses
+//                  k_spmv_nodes_dot instead: K in place, columns from the node graph.
 //   k_reduce_alpha one block: alpha = (r.z) / (p.q) from the partials in a fixed order
 //   k_update_dots  x += alpha p, r -= alpha q, z = D^-1 r, block partials of r.z and r.r
 //   k_reduce_beta  one block: beta = (r.z)_new / (r.z)
@@ -1019,9 +1021,9 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
         if (e != MF_OK && apply_status == MF_OK) apply_status = e;
     };
 
-    // ELL copy of K when the padding stays small (as in run_pcg)
+    // ELL copy of K when the padding stays small (as in run_pcg); none with the node graph
     int width = 0, nnz32 = 0;
-    {
+    if (!a.node_ptr) {
         int* dmax = (int*)dalloc(sizeof(int));
         if (!dmax) return set_error(MF_ERR_OOM, "BiCGStab workspace allocation failed");
         MF_HIP(hipMemsetAsync(dmax, 0, sizeof(int), s));
@@ -1032,8 +1034,7 @@ mf_status run_bicgstab(const PcgArgs& a, mf_pcg_result* res)
     }
     int32_t* ecol = nullptr;
     double* eval = nullptr;
-    // with the node graph of 4-field rows the SpMV reads K in place (no ELL copy)
-    if (!a.node_ptr && width > 0 && (int64_t)width * n <= (int64_t)nnz32 + nnz32 / 2) {
+    if (width > 0 && (int64_t)width * n <= (int64_t)nnz32 + nnz32 / 2) {
         ecol = (int32_t*)dalloc(sizeof(int32_t) * (size_t)width * n);
         eval = (double*)dalloc(sizeof(double) * (size_t)width * n);
         if (ecol && eval) {
