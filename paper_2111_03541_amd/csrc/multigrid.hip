@@ -20,7 +20,7 @@
 //                  scalar patterns run it on a slot-major ELL copy, one row per thread
 //                  (k_mg_sweep_ell), node-major flow rows with the columns taken from
 //                  the node graph (k_mg_sweep_nodes)
-//   k_mg_restrict  one thread per coarse node gathers its 27 fine neighbours, every field
+//   k_mg_restrict  one thread per coarse node and field gathers its 27 fine neighbours
 //   k_mg_prolong   one thread per fine node interpolates from its 1, 2, 4 or 8 parents
 //   k_mg_coarse    the coarsest level in one workgroup, the iterate in LDS, all sweeps in
 //                  one launch, rows cached in registers when there are at most 256 (levels
@@ -355,9 +355,12 @@ __global__ void __launch_bounds__(kThreads) k_mg_restrict(int64_t cx, int64_t cy
                                                           const uint8_t* __restrict__ cmask,
                                                           double* __restrict__ bc)
 {
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < cn; v += (int64_t)gridDim.x * blockDim.x) {
+    // one thread per (coarse node, field): the fields of a node are adjacent threads
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < cn * nf; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = t / nf;
+        const int f = (int)(t % nf);
         const int64_t i = v % (cx + 1), r = v / (cx + 1), j = r % (cy + 1), k = r / (cy + 1);
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        double acc = 0.0;
         for (int dk = -1; dk <= 1; ++dk) {
             const int64_t c = 2 * k + dk;
             if (c < 0 || c > fz) continue;
@@ -371,14 +374,12 @@ __global__ void __launch_bounds__(kThreads) k_mg_restrict(int64_t cx, int64_t cy
                     if (a < 0 || a > fx) continue;
                     const double w = di ? wy * 0.5 : wy;
                     const int64_t node = a + (fx + 1) * (bb + (fy + 1) * c);
-                    for (int f = 0; f < nf; ++f) acc[f] = fma(w, rf[dof_of(node, f, fn, nf, fm)], acc[f]);
+                    acc = fma(w, rf[dof_of(node, f, fn, nf, fm)], acc);
                 }
             }
         }
-        for (int f = 0; f < nf; ++f) {
-            const int64_t d = dof_of(v, f, cn, nf, fm);
-            bc[d] = (cmask && cmask[d]) ? 0.0 : acc[f];
-        }
+        const int64_t d = dof_of(v, f, cn, nf, fm);
+        bc[d] = (cmask && cmask[d]) ? 0.0 : acc;
     }
 }
 
@@ -573,7 +574,7 @@ void vcycle(const mf_mg_s* mg, int l, const double* b, double* out, hipStream_t 
         launch_sweep(kResidual, Lv, nf, b, cur, rbuf, omega, s);
         res = rbuf;
     }
-    k_mg_restrict<<<grid_for(Lc.n_nodes, kThreads), kThreads, 0, s>>>(Lc.nx, Lc.ny, Lc.n_nodes, Lv.nx, Lv.ny, Lv.nz,
+    k_mg_restrict<<<grid_for(Lc.n_nodes * nf, kThreads), kThreads, 0, s>>>(Lc.nx, Lc.ny, Lc.n_nodes, Lv.nx, Lv.ny, Lv.nz,
                                                                       Lv.n_nodes, nf, fm, res,
                                                                       mg->has_mask ? Lc.mask : nullptr, Lc.b);
     vcycle(mg, l + 1, Lc.b, Lc.x, s);
